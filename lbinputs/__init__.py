@@ -1,0 +1,196 @@
+"""Seeded synthetic inputs: analytic surface charts and right-hand sides.
+
+This module holds no arithmetic of the method: it only samples analytic charts
+X(u, v) and their exact derivatives at caller-supplied reference points, and
+evaluates analytic test functions.  Both the oracle-side tests and the HIP
+side (tests, bench) consume it; it imports neither.
+
+Surfaces (each patch is a chart T0 -> Gamma, T0 = {u, v >= 0, u + v <= 1}):
+* ``sphere_patches(nsub)``: icosahedron, ``nsub`` 4-way splits with midpoints
+  pushed to the sphere at each level, each flat triangle (A, B, C) radially
+  projected: X = P/|P|, P = A + u (B - A) + v (C - A).  80 patches at nsub=1,
+  5120 at nsub=4.
+* ``ellipsoid_patches(nsub, axes)``: the same charts scaled by diag(axes).
+* ``torus_patches(R, r, n_theta, n_phi)``: (theta, phi) grid, each cell split
+  along a fixed diagonal.
+* ``star_patches(coeffs, n_s)``: r(xi) = 1 + 0.25 sum a_lm Y_lm(xi) on the
+  sphere charts of an icosahedron whose faces are split n_s x n_s.
+"""
+import numpy as np
+from scipy.special import sph_harm_y
+
+
+# ----------------------------------------------------------------------
+# icosahedral triangulations of the unit sphere
+# ----------------------------------------------------------------------
+def icosahedron():
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+                  [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+                  [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], dtype=float)
+    V /= np.linalg.norm(V, axis=1)[:, None]
+    F = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]])
+    return V, F
+
+
+def icosphere(nsub):
+    """Vertices (on the unit sphere) and outward-oriented faces."""
+    V, F = icosahedron()
+    V = list(V)
+    for _ in range(nsub):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                cache[key] = len(V) - 1
+            return cache[key]
+        nf = []
+        for a, b, c in F:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, bc, ca]]
+        F = np.array(nf)
+    V = np.array(V)
+    # orient outward
+    A, B, C = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    flip = (np.cross(B - A, C - A) * (A + B + C)).sum(1) < 0
+    F[flip] = F[flip][:, [0, 2, 1]]
+    return V, F
+
+
+def icosphere_ns(n_s):
+    """Icosahedron with every face split into n_s^2 triangles (projected)."""
+    V0, F0 = icosahedron()
+    tris = []
+    for a, b, c in F0:
+        A, B, C = V0[a], V0[b], V0[c]
+        P = {}
+        for i in range(n_s + 1):
+            for j in range(n_s + 1 - i):
+                p = A + (B - A) * i / n_s + (C - A) * j / n_s
+                P[(i, j)] = p / np.linalg.norm(p)
+        for i in range(n_s):
+            for j in range(n_s - i):
+                tris.append((P[(i, j)], P[(i + 1, j)], P[(i, j + 1)]))
+                if i + j < n_s - 1:
+                    tris.append((P[(i + 1, j)], P[(i + 1, j + 1)], P[(i, j + 1)]))
+    T = np.array(tris)
+    flip = (np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]) * T.sum(1)).sum(1) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    return T
+
+
+def _radial_charts(T, uv):
+    """Radial projection of flat triangles T (NP,3,3) sampled at uv (n,2)."""
+    A, B, C = T[:, 0], T[:, 1], T[:, 2]
+    u = uv[None, :, 0:1]
+    v = uv[None, :, 1:2]
+    P = A[:, None, :] + u * (B - A)[:, None, :] + v * (C - A)[:, None, :]
+    nP = np.linalg.norm(P, axis=-1, keepdims=True)
+    X = P / nP
+
+    def d(Dv):
+        Dv = Dv[:, None, :]
+        return (Dv - X * (X * Dv).sum(-1, keepdims=True)) / nP
+    return X, d(B - A), d(C - A)
+
+
+def sphere_patches(nsub, uv, radius=1.0):
+    V, F = icosphere(nsub)
+    T = V[F]
+    X, Xu, Xv = _radial_charts(T, np.asarray(uv, dtype=float))
+    return radius * X, radius * Xu, radius * Xv
+
+
+def ellipsoid_patches(nsub, uv, axes=(1.0, 1.5, 2.0)):
+    X, Xu, Xv = sphere_patches(nsub, uv)
+    a = np.asarray(axes, dtype=float)
+    return X * a, Xu * a, Xv * a
+
+
+def sphere_preimage(X, axes):
+    """Unit-sphere point xi whose scaled image is X (for ellipsoid data)."""
+    return X / np.asarray(axes, dtype=float)
+
+
+def torus_patches(R, r, n_theta, n_phi, uv):
+    """Torus X = ((R + r cos th) cos ph, (R + r cos th) sin ph, r sin th).
+
+    The (ph, th) grid has n_phi x n_theta cells; each cell is split into the
+    triangles corner (0,0) + u e_ph + v e_th and corner (1,1) - u e_ph - v e_th,
+    so that X_u x X_v points outward.  Patch order: theta-major, phi, triangle.
+    """
+    uv = np.asarray(uv, dtype=float)
+    dth = 2 * np.pi / n_theta
+    dph = 2 * np.pi / n_phi
+    Xs, Us, Vs = [], [], []
+    for it in range(n_theta):
+        for ip in range(n_phi):
+            for corner, sgn in (((0, 0), 1.0), ((1, 1), -1.0)):
+                ph = (ip + corner[0]) * dph + sgn * dph * uv[:, 0]
+                th = (it + corner[1]) * dth + sgn * dth * uv[:, 1]
+                ct, st, cp, sp = np.cos(th), np.sin(th), np.cos(ph), np.sin(ph)
+                rho = R + r * ct
+                X = np.stack([rho * cp, rho * sp, r * st], -1)
+                Xth = np.stack([-r * st * cp, -r * st * sp, r * ct], -1)
+                Xph = np.stack([-rho * sp, rho * cp, 0 * ct], -1)
+                Xs.append(X)
+                Us.append(sgn * dph * Xph)
+                Vs.append(sgn * dth * Xth)
+    return np.array(Xs), np.array(Us), np.array(Vs)
+
+
+def torus_mean_curvature(X, R, r):
+    """H = (R + 2 r cos th) / (2 r (R + r cos th)) with the outward normal."""
+    rho = np.linalg.norm(X[..., :2], axis=-1)
+    ct = (rho - R) / r
+    return (R + 2 * r * ct) / (2 * r * (R + r * ct))
+
+
+# ----------------------------------------------------------------------
+# analytic functions
+# ----------------------------------------------------------------------
+def real_sph_harm(l, m, x):
+    """Real orthonormal spherical harmonic Y_lm at unit vectors x (..., 3)."""
+    x = np.asarray(x, dtype=float)
+    r = np.linalg.norm(x, axis=-1)
+    theta = np.arccos(np.clip(x[..., 2] / r, -1, 1))
+    phi = np.arctan2(x[..., 1], x[..., 0])
+    Y = sph_harm_y(l, abs(m), theta, phi)
+    if m > 0:
+        return np.sqrt(2.0) * (-1) ** m * Y.real
+    if m < 0:
+        return np.sqrt(2.0) * (-1) ** m * Y.imag
+    return Y.real
+
+
+def sh_gradient_on_sphere(l, m, x, h=1e-6):
+    """Surface gradient of Y_lm on the unit sphere (central differences of the
+    degree-0 homogeneous extension, projected on the tangent plane)."""
+    x = np.asarray(x, dtype=float)
+    g = np.zeros_like(x)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        g[..., c] = (real_sph_harm(l, m, x + e) - real_sph_harm(l, m, x - e)) / (2 * h)
+    n = x / np.linalg.norm(x, axis=-1, keepdims=True)
+    return g - n * (g * n).sum(-1, keepdims=True)
+
+
+def random_sh_coeffs(lmax, seed, decay=2.0, lmin=1):
+    """a_lm ~ N(0,1) (l+1)^-decay for lmin <= l <= lmax (seeded)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for l in range(lmin, lmax + 1):
+        for m in range(-l, l + 1):
+            out.append((l, m, rng.standard_normal() * (l + 1.0) ** (-decay)))
+    return out
+
+
+def sh_series(coeffs, x):
+    return sum(a * real_sph_harm(l, m, x) for l, m, a in coeffs)

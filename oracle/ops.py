@@ -1,0 +1,214 @@
+"""Discrete layer potentials, the A3 operator and GMRES (FP64, plain definitions).
+
+* Section 4, eq. (nys-lcq2): K[tau]_i = sum over ALL oversampled sources of
+  w^over_m K(x_i, s_m) tau~_m  +  sum over Near(i) of C_{i,lk} tau_lk.
+  The far sum is evaluated directly (no FMM): the FMM only replaces this sum.
+  The 1/(4 pi) of the Green's function (Section 3) is part of every kernel.
+* Section 4.1 (the gradient part of the A1 apply): grad S, and the surface
+  gradient grad_Gamma S = grad S - n (n . grad S), which equals the g^{ij}
+  form of that section.
+* Section 4.3 / eq. (ie-dis2): A3[tau] = -tau/4 + S'[S' tau]
+  - (S''+D')[S tau] - 2 H S'[S tau] + W S[S tau], applied right to left, with
+  W[phi] = sum_j w_j phi_j / sum_j w_j (the averaging operator of Section 3).
+* Section 6: GMRES, x0 = 0, no restart, at most 100 iterations, stop when
+  the relative Euclidean residual drops below tol.  Arnoldi by modified
+  Gram-Schmidt, Givens rotations.
+* Lemma 1 / Section 3: f is projected onto mean zero, u = S[S[sigma]].
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+import numpy as np
+
+from .quad import Corrections, FOUR_PI
+
+
+def direct(x, n, s, nu, c, chunk=None):
+    """Direct sums over all sources for targets x (T,3) with normals n (T,3).
+
+    c: strengths (No,) or (nd, No).  Returns pot (nd,T), grad (nd,T,3) and
+    sdd (nd,T) = sum c n.gradgrad G.(n - nu); every term includes 1/(4 pi).
+    """
+    c = np.atleast_2d(c)
+    nd = c.shape[0]
+    T = x.shape[0]
+    pot = np.zeros((nd, T))
+    grad = np.zeros((nd, T, 3))
+    sdd = np.zeros((nd, T))
+    if chunk is None:
+        chunk = max(1, int(4e6 // max(1, s.shape[0])))
+    for t0 in range(0, T, chunk):
+        xt = x[t0:t0 + chunk]
+        nt = n[t0:t0 + chunk]
+        d = xt[:, None, :] - s[None, :, :]                     # (t, No, 3)
+        r2 = (d * d).sum(-1)
+        inv_r = 1.0 / np.sqrt(r2)
+        inv_r3 = inv_r / r2
+        G = inv_r / FOUR_PI
+        Gd = -d * (inv_r3 / FOUR_PI)[..., None]
+        m = nt[:, None, :] - nu[None, :, :]
+        ndt = (nt[:, None, :] * d).sum(-1)
+        md = (m * d).sum(-1)
+        nm = (nt[:, None, :] * m).sum(-1)
+        H = (3.0 * ndt * md * inv_r3 / r2 - nm * inv_r3) / FOUR_PI
+        pot[:, t0:t0 + chunk] = c @ G.T
+        grad[:, t0:t0 + chunk, :] = np.einsum('dm,tmc->dtc', c, Gd)
+        sdd[:, t0:t0 + chunk] = c @ H.T
+    return pot, grad, sdd
+
+
+class Oracle:
+    """Discrete operators on one surface; ``targets`` restricts the rows.
+
+    For small problems (rows x oversampled sources <= dense_limit) the kernel
+    values of the far sum are tabulated once as dense matrices; the sums are
+    the same, only evaluated as matrix-vector products.
+    """
+
+    def __init__(self, geom, targets=None, corr=None, dense_limit=2e7, **quad_opts):
+        self.g = geom
+        self.corr = corr if corr is not None else Corrections(geom, targets, **quad_opts)
+        self.targets = self.corr.targets
+        self._K = None
+        if len(self.targets) * geom.No <= dense_limit:
+            t = self.targets
+            d = geom.x[t][:, None, :] - geom.s[None, :, :]
+            r2 = (d * d).sum(-1)
+            inv_r = 1.0 / np.sqrt(r2)
+            inv_r3 = inv_r / r2
+            n = geom.n[t][:, None, :]
+            m = n - geom.nu[None, :, :]
+            ndt = (n * d).sum(-1)
+            K = np.empty((6,) + r2.shape)
+            K[0] = inv_r / FOUR_PI
+            K[1:4] = np.moveaxis(-d * (inv_r3 / FOUR_PI)[..., None], -1, 0)
+            K[4] = -ndt * inv_r3 / FOUR_PI
+            K[5] = (3.0 * ndt * (m * d).sum(-1) * inv_r3 / r2 - (n * m).sum(-1) * inv_r3) / FOUR_PI
+            self._K = K
+
+    # -- pieces ---------------------------------------------------------
+    def oversample(self, tau):
+        """tau~ = P tau per patch, strengths w^over tau~ (Section 4, eq. nys-lcq)."""
+        g = self.g
+        tt = np.einsum('mb,pb->pm', g.re.P, np.asarray(tau).reshape(g.NP, g.n_p)).reshape(-1)
+        return g.wo * tt
+
+    def layer(self, tau):
+        """All six discrete kernels applied to tau at the target rows: (T, 6).
+
+        Columns: S, dS/dx1, dS/dx2, dS/dx3, S', S''+D'.
+        """
+        g = self.g
+        t = self.targets
+        c = self.oversample(tau)
+        if self._K is not None:
+            out = (self._K @ c).T
+        else:
+            pot, grad, sdd = direct(g.x[t], g.n[t], g.s, g.nu, c)
+            out = np.empty((len(t), 6))
+            out[:, 0] = pot[0]
+            out[:, 1:4] = grad[0]
+            out[:, 4] = (grad[0] * g.n[t]).sum(-1)
+            out[:, 5] = sdd[0]
+        return out + self.corr.apply(g, tau)
+
+    def operator_matrices(self):
+        """Dense matrices (6, rows, N) of the six discrete kernels (small N only)."""
+        g = self.g
+        assert self._K is not None
+        Pfull = np.zeros((g.No, g.N))
+        for p in range(g.NP):
+            Pfull[p * g.n_o:(p + 1) * g.n_o, p * g.n_p:(p + 1) * g.n_p] = g.re.P
+        Pw = g.wo[:, None] * Pfull
+        M = np.einsum('krs,sn->krn', self._K, Pw)
+        cr = self.corr
+        for j in range(len(cr.patch)):
+            r = cr.rows[j]
+            p = cr.patch[j]
+            M[:, r, p * g.n_p:(p + 1) * g.n_p] += cr.C[j].T
+        return M
+
+    # -- public applies ---------------------------------------------------
+    def apply_S(self, tau):
+        return self.layer(tau)[:, 0]
+
+    def apply_gradS(self, tau):
+        """Returns (S, grad S (T,3), S', grad_Gamma S (T,3))."""
+        L = self.layer(tau)
+        n = self.g.n[self.targets]
+        grad = L[:, 1:4]
+        sp = L[:, 4]
+        surf = grad - n * (grad * n).sum(-1, keepdims=True)
+        return L[:, 0], grad, sp, surf
+
+    def W(self, phi):
+        g = self.g
+        return (g.w * phi).sum() / g.w.sum()
+
+    def A3(self, tau):
+        """Section 4.3; needs all rows (targets == all nodes)."""
+        g = self.g
+        assert len(self.targets) == g.N
+        L1 = self.layer(tau)
+        mu1 = L1[:, 4]           # S' tau
+        mu2 = L1[:, 0]           # S tau
+        La = self.layer(mu1)
+        Lb = self.layer(mu2)
+        return (-0.25 * tau + La[:, 4] - Lb[:, 5] - 2.0 * g.H * Lb[:, 4]
+                + self.W(Lb[:, 0]))
+
+    def solve(self, f, tol=1e-12, max_iter=100):
+        """u solving Delta_Gamma u = f (mean-projected f), plus info dict."""
+        g = self.g
+        f = np.asarray(f, dtype=float)
+        mean = self.W(f)
+        fz = f - mean
+        sigma, info = gmres(self.A3, fz, tol=tol, max_iter=max_iter)
+        u = self.apply_S(self.apply_S(sigma))
+        info["removed_mean"] = mean
+        info["sigma"] = sigma
+        return u, info
+
+
+def gmres(A, b, tol=1e-12, max_iter=100):
+    """Un-restarted GMRES, x0 = 0, MGS Arnoldi, Givens rotations (Section 6)."""
+    b = np.asarray(b, dtype=float)
+    n = b.shape[0]
+    beta = np.linalg.norm(b)
+    if beta == 0.0:
+        return np.zeros(n), {"iters": 0, "rel_resid": 0.0, "history": []}
+    m = max_iter
+    V = np.zeros((m + 1, n))
+    Hs = np.zeros((m + 1, m))
+    cs = np.zeros(m)
+    sn = np.zeros(m)
+    gvec = np.zeros(m + 1)
+    gvec[0] = beta
+    V[0] = b / beta
+    hist = []
+    k_done = 0
+    for j in range(m):
+        w = A(V[j])
+        for i in range(j + 1):
+            Hs[i, j] = np.dot(V[i], w)
+            w = w - Hs[i, j] * V[i]
+        Hs[j + 1, j] = np.linalg.norm(w)
+        for i in range(j):
+            t = cs[i] * Hs[i, j] + sn[i] * Hs[i + 1, j]
+            Hs[i + 1, j] = -sn[i] * Hs[i, j] + cs[i] * Hs[i + 1, j]
+            Hs[i, j] = t
+        den = np.hypot(Hs[j, j], Hs[j + 1, j])
+        cs[j] = Hs[j, j] / den
+        sn[j] = Hs[j + 1, j] / den
+        hnext = Hs[j + 1, j]
+        Hs[j, j] = den
+        Hs[j + 1, j] = 0.0
+        gvec[j + 1] = -sn[j] * gvec[j]
+        gvec[j] = cs[j] * gvec[j]
+        k_done = j + 1
+        rel = abs(gvec[j + 1]) / beta
+        hist.append(rel)
+        if rel < tol or hnext == 0.0:
+            break
+        V[j + 1] = w / hnext
+    y = np.linalg.solve(np.triu(Hs[:k_done, :k_done]), gvec[:k_done])
+    x = V[:k_done].T @ y
+    return x, {"iters": k_done, "rel_resid": hist[-1], "history": hist}
