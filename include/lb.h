@@ -1,0 +1,166 @@
+/*
+ * lb.h -- C ABI of the MI355X Laplace-Beltrami layer-potential library.
+ *
+ * The library applies the Laplace single layer S and its gradient on the
+ * Nystrom nodes of high-order curved triangular patches, with a fast
+ * multipole method for the far field and stored locally corrected quadrature
+ * for the near field, and solves the Laplace-Beltrami problem with the
+ * second-kind formulation A3 = -I/4 + S'^2 - (S''+D'+2HS')S + WS^2
+ * (Agarwal, O'Neil, Rachh, arXiv 2111.10743: Section 3 for the operators and
+ * Lemma 1 for the mean-zero setting, Section 4 for the discretization and
+ * eq. (nys-lcq2), Section 4.3 for the A3 apply, Section 6 for GMRES).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an lb_status.  0 is success, negative values are
+ *    errors (nothing useful was written), LB_ENOCONV (> 0) is a warning.
+ *    lb_last_error() returns a thread-local message for the last failure.
+ *  - Patches: n_patches charts X: T0 -> Gamma, T0 = {u,v >= 0, u+v <= 1},
+ *    sampled at the n_p = (k+1)(k+2)/2 nodes of lb_ref_nodes(k).  Node data
+ *    is patch-major: index i = patch * n_p + local node.  N = n_patches * n_p.
+ *  - Buffers passed to lb_setup and lb_ref_nodes are HOST pointers; they are
+ *    copied, the context keeps no caller pointer.
+ *  - Density and output buffers of the apply/solve calls are DEVICE pointers
+ *    owned by the caller, contiguous, in the dtype selected by `prec`
+ *    (32: float, 64: double).  Densities are [nd][N] (density-major).
+ *  - All device work is enqueued on `stream` (a hipStream_t, NULL = the
+ *    default stream) and is stream ordered; calls return without waiting
+ *    unless stated.  Use one context from one stream at a time.
+ *  - The caller's current HIP device must be the one the context was
+ *    created on.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int lb_status;
+#define LB_OK            0
+#define LB_ENOCONV       1   /* warning: GMRES stopped at max_iter; best iterate written */
+#define LB_EINVAL       -1   /* bad argument (order, sizes, NaN/Inf input, null pointer) */
+#define LB_ENOMEM       -2   /* host or device allocation failed */
+#define LB_EHIP         -3   /* a HIP runtime call failed */
+#define LB_ENOTMEANZERO -4   /* strict-mean mode and f is not mean zero */
+#define LB_EGEOM        -5   /* degenerate patch (zero Jacobian) */
+
+/* precisions of the apply calls */
+#define LB_PREC_FP32 32
+#define LB_PREC_FP64 64
+
+/* lb_solve modes */
+#define LB_SOLVE_FP64        0   /* FP64 FMM, FP64 corrections, FP64 GMRES */
+#define LB_SOLVE_FP32_REFINE 1   /* FP32 inner GMRES operator, FP64 residual refinement */
+
+/* lb_opts.flags */
+#define LB_STRICT_MEAN 1   /* lb_solve rejects f with |mean| > 1e-12 ||f|| */
+#define LB_HOST_ONLY   2   /* lb_setup does the host work only (no HIP call) */
+#define LB_DIRECT      4   /* far field by all-pairs sums instead of the FMM */
+
+typedef struct lb_ctx lb_ctx;   /* opaque: owns host and device state */
+
+typedef struct {
+  double eta_near;  /* Near(x_i) = { l : |x_i - c_l| < eta_near * R_l }      (default 2)  */
+  int over_q;       /* oversampled far rule: q x q conical Gauss points       (default k+6)*/
+  int p_f32;        /* FMM expansion order of the FP32 path                   (default 10) */
+  int p_f64;        /* FMM expansion order of the FP64 path                   (default 24) */
+  int leaf_src;     /* target mean number of sources per FMM leaf box         (default 256)*/
+  int max_iter;     /* GMRES iteration cap per (inner) solve                  (default 100)*/
+  int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT                           */
+  int self_n;       /* self-patch rule: Gauss points along each Duffy ray    (default 16) */
+  int near_q;       /* adaptive near rule: near_q x near_q points per leaf    (default 8)  */
+  double near_adm;  /* adaptive near rule admissibility dist >= adm * diam    (default 2)  */
+} lb_opts;
+
+typedef struct {
+  int iters;            /* total GMRES iterations (inner, summed over refinement steps) */
+  int outer_steps;      /* FP64 residual evaluations after the first (0 in LB_SOLVE_FP64) */
+  double rel_resid;     /* ||f - A3 sigma||_2 / ||f||_2 of the returned sigma, FP64 operator */
+  double removed_mean;  /* weighted mean sum w f / sum w that was removed from f */
+} lb_solve_info;
+
+typedef struct {
+  int64_t n_patches, n_p, N;      /* patches, nodes per patch, nodes            */
+  int64_t n_o, N_o;               /* oversampled points per patch, in total     */
+  int64_t nnz_blocks;             /* (target, near patch) pairs of the corrections */
+  int64_t fmm_levels, fmm_leaves; /* octree depth and number of nonempty leaves */
+  int64_t p_f32, p_f64;           /* expansion orders in use                     */
+} lb_sizes;
+
+/* Fill *opts with the defaults listed above. */
+lb_status lb_default_opts(lb_opts *opts);
+
+/* Reference nodes of order k (1 <= k <= 7) on T0, where callers sample their
+ * charts (Section 4: the order-k interpolation nodes; this library's node
+ * family is the Blyth-Pozrikidis construction on Gauss-Legendre points).
+ * uv: host [n_p][2] (u, v); w_ref: host [n_p] interpolatory weights, nullable. */
+lb_status lb_ref_nodes(int order, double *uv, double *w_ref);
+
+/* Build geometry, near lists, quadrature corrections (Section 4, eqs. nys-lcq
+ * and nys-lcq2), the octree and the translation operators, and upload them.
+ * X, Xu, Xv: host [n_patches][n_p][3] chart samples and first derivatives at
+ * lb_ref_nodes(order).  opts: nullable (defaults).  On success *ctx owns all
+ * state; release it with lb_destroy.  Errors: LB_EINVAL (order out of range,
+ * NaN/Inf input), LB_EGEOM (zero Jacobian), LB_ENOMEM, LB_EHIP. */
+lb_status lb_setup(lb_ctx **ctx, int n_patches, int order, const double *X,
+                   const double *Xu, const double *Xv, const lb_opts *opts,
+                   void *stream);
+
+/* Sizes of the discretization held by ctx. */
+lb_status lb_get_sizes(const lb_ctx *ctx, lb_sizes *out);
+
+/* Host copies of the smooth weights w [N], unit normals [N][3] and mean
+ * curvature H [N] (Section 2; H = +1 on the unit sphere).  Nullable outputs. */
+lb_status lb_get_geometry(const lb_ctx *ctx, double *w, double *normals, double *H);
+
+/* Host copy of the FP64 near corrections C = A - B (eq. nys-lcq2) in block
+ * CSR form: row_ptr [N+1] (int64), patch [nnz_blocks] (int32) and
+ * vals [nnz_blocks][n_p][6] for the kernels S, dS/dx1, dS/dx2, dS/dx3, S',
+ * S''+D' (all including the 1/(4 pi) of the Green's function).  Works on a
+ * LB_HOST_ONLY context.  Any output may be NULL. */
+lb_status lb_get_corrections(const lb_ctx *ctx, int64_t *row_ptr, int32_t *patch,
+                             double *vals);
+
+/* S[sigma] at the N nodes (Section 4.1 first sum, eq. nys-lcq2).
+ * sigma: device [nd][N], pot: device [nd][N], dtype by prec. */
+lb_status lb_apply_S(lb_ctx *ctx, int nd, int prec, const void *sigma, void *pot,
+                     void *stream);
+
+/* S[sigma] and its on-surface gradient (Section 4.1): grad = principal-value
+ * gradient (the average of the two one-sided limits), dSdn = S' = n . grad,
+ * surf_grad = grad - n (n . grad) = the tangential gradient of S on Gamma.
+ * sigma: device [nd][N]; pot [nd][N], grad [nd][N][3], dSdn [nd][N],
+ * surf_grad [nd][N][3]; every output except grad is nullable. */
+lb_status lb_apply_gradS(lb_ctx *ctx, int nd, int prec, const void *sigma,
+                         void *pot, void *grad, void *dSdn, void *surf_grad,
+                         void *stream);
+
+/* The discretized A3 operator of eq. (ie-dis2), applied right to left as in
+ * Section 4.3: out = -tau/4 + S'[S' tau] - (S''+D')[S tau] - 2H S'[S tau]
+ * + W S[S tau].  tau, out: device [nd][N]. */
+lb_status lb_apply_A3(lb_ctx *ctx, int nd, int prec, const void *tau, void *out,
+                      void *stream);
+
+/* Solve Delta_Gamma u = f for the mean-zero u (Lemma 1), through
+ * A3 sigma = f - mean(f) and u = S[S[sigma]] (eq. ie-dis2, Section 6 GMRES:
+ * x0 = 0, no restart, relative Euclidean residual < tol, at most
+ * opts.max_iter iterations per inner solve).  f, u: device double [nrhs][N].
+ * info: host [nrhs], nullable.  Synchronizes `stream`.  Returns LB_ENOCONV
+ * if some right-hand side did not reach tol (its best iterate is written),
+ * LB_ENOTMEANZERO in strict-mean mode. */
+lb_status lb_solve(lb_ctx *ctx, int nrhs, const double *f, double *u, double tol,
+                   int mode, lb_solve_info *info, void *stream);
+
+/* Release all host and device state (NULL is ignored). */
+void lb_destroy(lb_ctx *ctx);
+
+/* Thread-local message describing the last failure of this thread. */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

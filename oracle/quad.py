@@ -79,7 +79,7 @@ def _full6(vals5, n):
 # ----------------------------------------------------------------------
 # self patch: Duffy + sinh + principal-value subtraction
 # ----------------------------------------------------------------------
-def self_integrals(geom, targets, ns=20, nt=16, panel=2.0):
+def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
     """A^K_{i, p(i), k} for the given target nodes: array (T, n_p, 6).
 
     ns Gauss points along the ray; the sinh-graded edge variable is split into
@@ -241,7 +241,7 @@ def far_rule(geom, tgt, pch):
 class Corrections:
     """Block-sparse corrections C = A - B for a set of target rows."""
 
-    def __init__(self, geom, targets=None, ns=20, nt=16, qa=8, adm=2.0):
+    def __init__(self, geom, targets=None, ns=16, nt=12, qa=8, adm=2.0):
         if targets is None:
             targets = np.arange(geom.N)
         targets = np.asarray(targets)

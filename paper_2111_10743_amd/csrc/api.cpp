@@ -1,0 +1,718 @@
+// C ABI of the library (include/lb.h): setup, applies, the A3 operator and
+// the GMRES solver, orchestrated on the caller's HIP stream.
+#include "../../include/lb.h"
+#include "common.hpp"
+#include "harmonics.hpp"
+#include "kernels.hpp"
+#include "octree.hpp"
+#include "refelem.hpp"
+#include "surface.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace lb {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+#define HIPTRY(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) fail(LB_EHIP, "%s failed: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// device allocation that frees itself
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { if (p) (void)hipFree(p); }
+  void alloc(size_t b) {
+    if (b <= bytes && p) return;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) fail(LB_ENOMEM, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+    bytes = b;
+  }
+};
+template <typename T> static inline T* dptr(const DBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+template <typename T>
+static void upload(DBuf& d, const std::vector<T>& h) {
+  d.alloc(sizeof(T) * std::max<size_t>(h.size(), 1));
+  if (!h.empty()) HIPTRY(hipMemcpy(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+}
+template <typename T, typename S>
+static void upload_as(DBuf& d, const std::vector<S>& h) {
+  std::vector<T> c(h.begin(), h.end());
+  upload(d, c);
+}
+
+// Everything one precision of the apply needs on the device.
+template <typename T>
+struct Prec {
+  int p = 0, L = 0;
+  Octree tree;
+  DevTree<T> dt{};
+  DBuf tx, ty, tz, tnx, tny, tnz, sx, sy, sz, snx, sny, snz, rm2, bcx, bcy, bcz;
+  DBuf tgt_beg, tgt_end, src_beg, src_end, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off;
+  DBuf parent, child, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
+  DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
+  DBuf m2m, l2l, m2l, dgrad, dhess;
+  // work
+  DBuf str, M, Lc, D, fmm, mu, tmp_in, tmp_out;
+  int ws_rhs = 0;
+};
+
+}  // namespace lb
+
+using namespace lb;
+
+struct lb_ctx {
+  int k = 0, NP = 0, n_p = 0, n_o = 0;
+  int64_t N = 0, No = 0;
+  lb_opts opts{};
+  std::unique_ptr<RefElem> re;
+  Surface S;
+  std::vector<double> C64;  // [nnzb][n_p][6]
+  bool host_only = false;
+  int device = 0;
+  Prec<float> f32;
+  Prec<double> f64;
+  DBuf row_ptr, patch, w;
+  // solver workspace
+  DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp;
+  int v_cols = 0;
+  double area = 0;
+};
+
+namespace lb {
+
+static void default_opts(lb_opts* o) {
+  o->eta_near = 2.0;
+  o->over_q = 0;
+  o->p_f32 = 10;
+  o->p_f64 = 24;
+  o->leaf_src = 256;
+  o->max_iter = 100;
+  o->flags = 0;
+  o->self_n = 16;
+  o->near_q = 8;
+  o->near_adm = 2.0;
+}
+
+template <typename T>
+static void transpose_blocks(const std::vector<double>& src, int nblk, int rows, int cols, std::vector<T>& dst) {
+  dst.resize((size_t)nblk * rows * cols);
+  for (int b = 0; b < nblk; ++b)
+    for (int r = 0; r < rows; ++r)
+      for (int c = 0; c < cols; ++c)
+        dst[(size_t)b * rows * cols + (size_t)c * rows + r] = (T)src[(size_t)b * rows * cols + (size_t)r * cols + c];
+}
+
+// pack [nnzb][n_p][6] corrections into the gradS (k=4: S, Gx, Gy, Gz) and
+// A3 (k=3: S, S', S''+D') layouts
+template <typename T>
+static void pack_vals(const std::vector<double>& C, int64_t nnz, std::vector<T>& v4, std::vector<T>& v3) {
+  v4.resize((size_t)nnz * 4);
+  v3.resize((size_t)nnz * 3);
+  for (int64_t e = 0; e < nnz; ++e) {
+    const double* c = &C[(size_t)e * 6];
+    v4[4 * e] = (T)c[0]; v4[4 * e + 1] = (T)c[1]; v4[4 * e + 2] = (T)c[2]; v4[4 * e + 3] = (T)c[3];
+    v3[3 * e] = (T)c[0]; v3[3 * e + 1] = (T)c[4]; v3[3 * e + 2] = (T)c[5];
+  }
+}
+
+template <typename T>
+static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>& C, const std::vector<float>& rm2f,
+                       double min_leaf_side, int leaf_src, bool direct) {
+  const Surface& S = ctx->S;
+  P.p = p;
+  P.L = (p + 1) * (p + 1);
+  P.tree.build(S.X.data(), S.N, S.s.data(), S.No, leaf_src, min_leaf_side, direct ? 0 : -1);
+  const Octree& t = P.tree;
+  const int64_t N = S.N, No = S.No;
+  // geometry in tree order
+  std::vector<T> a(N), b(N), c(N), d(N), e(N), f(N);
+  for (int64_t j = 0; j < N; ++j) {
+    int64_t i = t.tgt_perm[j];
+    a[j] = (T)S.X[3 * i]; b[j] = (T)S.X[3 * i + 1]; c[j] = (T)S.X[3 * i + 2];
+    d[j] = (T)S.nrm[3 * i]; e[j] = (T)S.nrm[3 * i + 1]; f[j] = (T)S.nrm[3 * i + 2];
+  }
+  upload(P.tx, a); upload(P.ty, b); upload(P.tz, c); upload(P.tnx, d); upload(P.tny, e); upload(P.tnz, f);
+  std::vector<T> sa(No), sb(No), sc(No), sd(No), se(No), sf(No), sr(No);
+  for (int64_t j = 0; j < No; ++j) {
+    int64_t i = t.src_perm[j];
+    sa[j] = (T)S.s[3 * i]; sb[j] = (T)S.s[3 * i + 1]; sc[j] = (T)S.s[3 * i + 2];
+    sd[j] = (T)S.nu[3 * i]; se[j] = (T)S.nu[3 * i + 1]; sf[j] = (T)S.nu[3 * i + 2];
+    sr[j] = rm2f.empty() ? (T)0 : (T)rm2f[i];
+  }
+  upload(P.sx, sa); upload(P.sy, sb); upload(P.sz, sc); upload(P.snx, sd); upload(P.sny, se); upload(P.snz, sf);
+  upload(P.rm2, sr);
+  const int nb = t.nbox();
+  std::vector<T> cx(nb), cy(nb), cz(nb);
+  for (int l = 0; l <= t.depth; ++l) {
+    double h = t.box_side(l);
+    for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+      cx[g] = (T)(t.lo[0] + (t.bx[g] + 0.5) * h);
+      cy[g] = (T)(t.lo[1] + (t.by[g] + 0.5) * h);
+      cz[g] = (T)(t.lo[2] + (t.bz[g] + 0.5) * h);
+    }
+  }
+  upload(P.bcx, cx); upload(P.bcy, cy); upload(P.bcz, cz);
+  upload(P.tgt_beg, t.tgt_beg); upload(P.tgt_end, t.tgt_end);
+  upload(P.src_beg, t.src_beg); upload(P.src_end, t.src_end);
+  upload(P.ulist_ptr, t.ulist_ptr); upload(P.ulist, t.ulist);
+  upload(P.vlist_ptr, t.vlist_ptr); upload(P.vlist_src, t.vlist_src); upload(P.vlist_off, t.vlist_off);
+  upload(P.parent, t.parent); upload(P.child, t.child);
+  std::vector<int> lt, ls;
+  const int nleaf = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
+  for (int l = 0; l < nleaf; ++l) {
+    if (t.has_tgt[t.lev_off[t.depth] + l]) lt.push_back(l);
+    if (t.has_src[t.lev_off[t.depth] + l]) ls.push_back(l);
+  }
+  upload(P.leaf_tgt, lt); upload(P.leaf_src, ls);
+  std::vector<int> lsv, lsp(1, 0), ltv, ltp(1, 0);
+  for (int l = 0; l <= t.depth; ++l) {
+    for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+      if (t.has_src[g]) lsv.push_back(g);
+      if (t.has_tgt[g]) ltv.push_back(g);
+    }
+    lsp.push_back((int)lsv.size());
+    ltp.push_back((int)ltv.size());
+  }
+  upload(P.lev_src, lsv); upload(P.lev_src_ptr, lsp); upload(P.lev_tgt, ltv); upload(P.lev_tgt_ptr, ltp);
+  // user-order maps
+  std::vector<int> tp(N), sp(No);
+  for (int64_t i = 0; i < N; ++i) tp[i] = (int)t.tgt_pos[i];
+  for (int64_t i = 0; i < No; ++i) sp[i] = (int)t.src_pos[i];
+  upload(P.tgt_pos, tp); upload(P.src_pos, sp);
+  upload_as<T>(P.P, ctx->re->P);
+  upload_as<T>(P.wo, S.wo);
+  upload_as<T>(P.nrm, S.nrm);
+  upload_as<T>(P.H, S.H);
+  std::vector<T> v4, v3;
+  pack_vals(C, (int64_t)C.size() / 6, v4, v3);
+  upload(P.vals4, v4);
+  upload(P.vals3, v3);
+  // translations
+  if (t.depth >= 2) {
+    Translations tr;
+    tr.build(p);
+    std::vector<T> m;
+    transpose_blocks(tr.m2m, 8, P.L, P.L, m); upload(P.m2m, m);
+    transpose_blocks(tr.l2l, 8, P.L, P.L, m); upload(P.l2l, m);
+    transpose_blocks(tr.m2l, 343, P.L, P.L, m); upload(P.m2l, m);
+    transpose_blocks(tr.dgrad, 3, p * p, P.L, m); upload(P.dgrad, m);
+    transpose_blocks(tr.dhess, 6, (p - 1) * (p - 1), P.L, m); upload(P.dhess, m);
+  }
+  // device tree descriptor
+  DevTree<T>& D = P.dt;
+  D.tx = dptr<T>(P.tx); D.ty = dptr<T>(P.ty); D.tz = dptr<T>(P.tz);
+  D.tnx = dptr<T>(P.tnx); D.tny = dptr<T>(P.tny); D.tnz = dptr<T>(P.tnz);
+  D.sx = dptr<T>(P.sx); D.sy = dptr<T>(P.sy); D.sz = dptr<T>(P.sz);
+  D.snx = dptr<T>(P.snx); D.sny = dptr<T>(P.sny); D.snz = dptr<T>(P.snz);
+  D.rm2 = dptr<T>(P.rm2);
+  D.bcx = dptr<T>(P.bcx); D.bcy = dptr<T>(P.bcy); D.bcz = dptr<T>(P.bcz);
+  D.tgt_beg = dptr<int>(P.tgt_beg); D.tgt_end = dptr<int>(P.tgt_end);
+  D.src_beg = dptr<int>(P.src_beg); D.src_end = dptr<int>(P.src_end);
+  D.ulist_ptr = dptr<int>(P.ulist_ptr); D.ulist = dptr<int>(P.ulist);
+  D.vlist_ptr = dptr<int>(P.vlist_ptr); D.vlist_src = dptr<int>(P.vlist_src); D.vlist_off = dptr<int>(P.vlist_off);
+  D.parent = dptr<int>(P.parent); D.child = dptr<int>(P.child);
+  D.leaf_tgt_list = dptr<int>(P.leaf_tgt); D.n_leaf_tgt = (int)lt.size();
+  D.leaf_src_list = dptr<int>(P.leaf_src); D.n_leaf_src = (int)ls.size();
+  D.lev_box_src = dptr<int>(P.lev_src); D.lev_box_src_ptr = dptr<int>(P.lev_src_ptr);
+  D.lev_box_tgt = dptr<int>(P.lev_tgt); D.lev_box_tgt_ptr = dptr<int>(P.lev_tgt_ptr);
+  D.depth = t.depth;
+  D.leaf_off = t.lev_off[t.depth];
+  D.nbox = nb;
+  if (t.depth + 2 > 24) fail(LB_EINVAL, "octree too deep");
+  for (int l = 0; l <= t.depth + 1; ++l) { D.h_lev_src_ptr[l] = lsp[l]; D.h_lev_tgt_ptr[l] = ltp[l]; }
+  D.side = t.side;
+  D.p = p;
+  D.L = P.L;
+  D.m2m = dptr<T>(P.m2m); D.l2l = dptr<T>(P.l2l); D.m2l = dptr<T>(P.m2l);
+  D.dgradT = dptr<T>(P.dgrad); D.dhessT = dptr<T>(P.dhess);
+}
+
+template <typename T>
+static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
+  if (P.ws_rhs >= chunk) return;
+  const int64_t N = ctx->N, No = ctx->No;
+  const int nb = P.dt.nbox;
+  const int L = P.L, p = P.p;
+  P.str.alloc(sizeof(T) * (size_t)No * 2 * chunk);
+  P.M.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
+  P.Lc.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
+  P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_tgt, 1) * chunk * (3 * 3 * p * p + 6 * (p - 1) * (p - 1)));
+  P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
+  P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
+  P.ws_rhs = chunk;
+  ctx->partial.alloc(sizeof(double) * ((size_t)4 * ((N + 3) / 4) + 64));
+}
+
+constexpr int CHUNK_GRAD = 8;
+
+template <typename T>
+static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, T* grad, T* dSdn, T* surf,
+                          hipStream_t st) {
+  ensure_ws(ctx, P, CHUNK_GRAD);
+  const int64_t N = ctx->N, No = ctx->No;
+  for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
+    const int c = std::min(CHUNK_GRAD, nd - d0);
+    launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
+                        dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
+    launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    launch_combine_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
+                           sigma + (int64_t)d0 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
+                           pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
+                           dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr, st);
+  }
+}
+
+template <typename T>
+static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
+  ensure_ws(ctx, P, CHUNK_GRAD);
+  const int64_t N = ctx->N, No = ctx->No;
+  T* mu = dptr<T>(P.mu);  // [mu1; mu2]
+  for (int d = 0; d < nd; ++d) {
+    const T* td = tau + (int64_t)d * N;
+    launch_strengths<T>(td, 1, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+                        dptr<T>(P.str), st);
+    launch_fmm<T>(P.dt, FMM_GRAD, 1, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    launch_combine_a3a<T>(1, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td,
+                          dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm), mu, mu + N, st);
+    launch_strengths<T>(mu, 2, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+                        dptr<T>(P.str), st);
+    launch_fmm<T>(P.dt, FMM_A3B, 1, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    launch_combine_a3b<T>(1, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td, mu,
+                          mu + N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.H), dptr<double>(ctx->w),
+                          1.0 / ctx->area, out + (int64_t)d * N, dptr<double>(ctx->partial), st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (Section 6): x0 = 0, no restart, CGS2 Arnoldi in FP64 on the device,
+// Givens rotations on the host.
+// ---------------------------------------------------------------------------
+template <typename ApplyFn>
+static int gmres(lb_ctx* ctx, ApplyFn A, const double* b, double* x, double tol, int maxit, double* relres,
+                 hipStream_t st) {
+  const int64_t N = ctx->N;
+  if (ctx->v_cols < maxit + 1) {
+    ctx->V.alloc(sizeof(double) * (size_t)N * (maxit + 1));
+    ctx->wv.alloc(sizeof(double) * (size_t)N);
+    ctx->hbuf.alloc(sizeof(double) * (maxit + 2) * 2);
+    ctx->v_cols = maxit + 1;
+  }
+  double* V = dptr<double>(ctx->V);
+  double* w = dptr<double>(ctx->wv);
+  double* hd = dptr<double>(ctx->hbuf);
+  double* part = dptr<double>(ctx->partial);
+  auto dots = [&](int k, const double* vec, std::vector<double>& out) {
+    launch_dots(V, N, k, vec, N, hd, part, st);
+    out.resize(k);
+    HIPTRY(hipMemcpyAsync(out.data(), hd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+  };
+  auto norm = [&](const double* vec) {
+    launch_dots(vec, N, 1, vec, N, hd, part, st);
+    double v;
+    HIPTRY(hipMemcpyAsync(&v, hd, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return std::sqrt(v);
+  };
+  HIPTRY(hipMemsetAsync(x, 0, sizeof(double) * N, st));
+  const double beta = norm(b);
+  if (beta == 0.0) { *relres = 0.0; return 0; }
+  launch_scale_copy(b, 1.0 / beta, V, N, st);
+  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0), h1, h2;
+  g[0] = beta;
+  int k = 0;
+  double rel = 1.0;
+  for (int j = 0; j < maxit; ++j) {
+    A(V + (int64_t)j * N, w);
+    dots(j + 1, w, h1);
+    HIPTRY(hipMemcpyAsync(hd, h1.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+    launch_gemv_sub(V, N, j + 1, hd, w, N, st);
+    dots(j + 1, w, h2);
+    HIPTRY(hipMemcpyAsync(hd, h2.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+    launch_gemv_sub(V, N, j + 1, hd, w, N, st);
+    double hn = norm(w);
+    double* col = &H[(size_t)j];  // H[i][j] at i*maxit + j
+    for (int i = 0; i <= j; ++i) H[(size_t)i * maxit + j] = h1[i] + h2[i];
+    H[(size_t)(j + 1) * maxit + j] = hn;
+    (void)col;
+    for (int i = 0; i < j; ++i) {
+      double a = H[(size_t)i * maxit + j], bb = H[(size_t)(i + 1) * maxit + j];
+      H[(size_t)i * maxit + j] = cs[i] * a + sn[i] * bb;
+      H[(size_t)(i + 1) * maxit + j] = -sn[i] * a + cs[i] * bb;
+    }
+    double a = H[(size_t)j * maxit + j], bb = H[(size_t)(j + 1) * maxit + j];
+    double den = std::hypot(a, bb);
+    cs[j] = a / den;
+    sn[j] = bb / den;
+    H[(size_t)j * maxit + j] = den;
+    H[(size_t)(j + 1) * maxit + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    rel = std::fabs(g[j + 1]) / beta;
+    if (rel < tol || hn == 0.0) break;
+    if (j + 1 < maxit) launch_scale_copy(w, 1.0 / hn, V + (int64_t)(j + 1) * N, N, st);
+  }
+  std::vector<double> y(k);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * maxit + c] * y[c];
+    y[i] = s / H[(size_t)i * maxit + i];
+  }
+  HIPTRY(hipMemcpyAsync(hd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+  launch_gemv_add(V, N, k, hd, x, N, st);
+  HIPTRY(hipStreamSynchronize(st));
+  *relres = rel;
+  return k;
+}
+
+}  // namespace lb
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+#define API_BEGIN try {
+#define API_END                                  \
+  }                                              \
+  catch (const lb::Error& e) {                   \
+    lb::set_last_error(e.what());                \
+    return e.code;                               \
+  }                                              \
+  catch (const std::bad_alloc&) {                \
+    lb::set_last_error("host allocation failed"); \
+    return LB_ENOMEM;                            \
+  }                                              \
+  catch (const std::exception& e) {              \
+    lb::set_last_error(e.what());                \
+    return LB_EINVAL;                            \
+  }                                              \
+  return LB_OK;
+
+extern "C" {
+
+const char* lb_last_error(void) { return lb::g_last_error.c_str(); }
+
+lb_status lb_default_opts(lb_opts* o) {
+  API_BEGIN
+  if (!o) fail(LB_EINVAL, "null opts");
+  default_opts(o);
+  API_END
+}
+
+lb_status lb_ref_nodes(int order, double* uv, double* w_ref) {
+  API_BEGIN
+  if (!uv) fail(LB_EINVAL, "null uv");
+  std::vector<double> nodes = ref_nodes(order);
+  std::memcpy(uv, nodes.data(), sizeof(double) * nodes.size());
+  if (w_ref) {
+    RefElem re(order, order + 2);
+    std::memcpy(w_ref, re.w_ref.data(), sizeof(double) * re.n_p);
+  }
+  API_END
+}
+
+lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, const double* Xu, const double* Xv,
+                   const lb_opts* opts, void* stream) {
+  API_BEGIN
+  (void)stream;
+  if (!out || !X || !Xu || !Xv) fail(LB_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_patches < 1) fail(LB_EINVAL, "n_patches must be >= 1");
+  if (order < 1 || order > 7) fail(LB_EINVAL, "order %d out of range 1..7", order);
+  auto ctx = std::make_unique<lb_ctx>();
+  if (opts) ctx->opts = *opts; else default_opts(&ctx->opts);
+  lb_opts& o = ctx->opts;
+  if (o.over_q <= 0) o.over_q = order + 6;
+  if (o.eta_near <= 1.0) fail(LB_EINVAL, "eta_near must be > 1");
+  if (o.p_f32 < 2 || o.p_f32 > 31 || o.p_f64 < 2 || o.p_f64 > 31) fail(LB_EINVAL, "expansion order out of range 2..31");
+  if (o.max_iter < 1) fail(LB_EINVAL, "max_iter must be >= 1");
+  if (o.self_n < 4 || o.near_q < 2 || o.near_adm <= 0) fail(LB_EINVAL, "bad quadrature options");
+  ctx->host_only = (o.flags & LB_HOST_ONLY) != 0;
+  ctx->k = order;
+  ctx->re.reset(new RefElem(order, o.over_q));
+  Surface& S = ctx->S;
+  S.build(*ctx->re, n_patches, X, Xu, Xv, o.eta_near);
+  S.build_near_lists();
+  ctx->NP = n_patches;
+  ctx->n_p = S.n_p;
+  ctx->n_o = S.n_o;
+  ctx->N = S.N;
+  ctx->No = S.No;
+  ctx->area = 0;
+  for (double wi : S.w) ctx->area += wi;
+  QuadOpts qo;
+  qo.self_n = o.self_n;
+  qo.near_q = o.near_q;
+  qo.near_adm = o.near_adm;
+  std::vector<double> A, B;
+  near_integrals(S, qo, A);
+  std::vector<float> none;
+  far_rule_blocks(S, none, none, none, false, B);
+  ctx->C64.resize(A.size());
+  for (size_t i = 0; i < A.size(); ++i) ctx->C64[i] = A[i] - B[i];
+  if (!ctx->host_only) {
+    HIPTRY(hipGetDevice(&ctx->device));
+    // FP32 near-field mask: sources of patch l within (eta-1) R_l of a target
+    // are left to the corrections
+    std::vector<float> rm2(S.No), tx32(3 * S.N), sx32(3 * S.No);
+    double rmax = 0;
+    for (int64_t m = 0; m < S.No; ++m) {
+      double rm = (o.eta_near - 1.0) * S.R[m / S.n_o];
+      rm2[m] = (float)(rm * rm);
+      rmax = std::max(rmax, rm);
+    }
+    for (int64_t i = 0; i < 3 * S.N; ++i) tx32[i] = (float)S.X[i];
+    for (int64_t i = 0; i < 3 * S.No; ++i) sx32[i] = (float)S.s[i];
+    std::vector<double> B32;
+    far_rule_blocks(S, rm2, tx32, sx32, true, B32);
+    std::vector<double> C32(A.size());
+    for (size_t i = 0; i < A.size(); ++i) C32[i] = A[i] - B32[i];
+    B32.clear();
+    B32.shrink_to_fit();
+    A.clear(); A.shrink_to_fit();
+    B.clear(); B.shrink_to_fit();
+    upload(ctx->row_ptr, S.near_ptr);
+    upload(ctx->patch, S.near_patch);
+    upload(ctx->w, S.w);
+    const bool direct = (o.flags & LB_DIRECT) != 0;
+    build_prec<float>(ctx.get(), ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
+    // the float positions used by the mask test must be exactly the ones on the device
+    build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
+    HIPTRY(hipDeviceSynchronize());
+  }
+  *out = ctx.release();
+  API_END
+}
+
+lb_status lb_get_sizes(const lb_ctx* ctx, lb_sizes* s) {
+  API_BEGIN
+  if (!ctx || !s) fail(LB_EINVAL, "null argument");
+  s->n_patches = ctx->NP;
+  s->n_p = ctx->n_p;
+  s->N = ctx->N;
+  s->n_o = ctx->n_o;
+  s->N_o = ctx->No;
+  s->nnz_blocks = ctx->S.near_ptr.empty() ? 0 : ctx->S.near_ptr.back();
+  s->fmm_levels = ctx->host_only ? 0 : ctx->f32.tree.depth;
+  s->fmm_leaves = ctx->host_only ? 0 : ctx->f32.dt.n_leaf_tgt;
+  s->p_f32 = ctx->opts.p_f32;
+  s->p_f64 = ctx->opts.p_f64;
+  API_END
+}
+
+lb_status lb_get_geometry(const lb_ctx* ctx, double* w, double* normals, double* H) {
+  API_BEGIN
+  if (!ctx) fail(LB_EINVAL, "null context");
+  const Surface& S = ctx->S;
+  if (w) std::memcpy(w, S.w.data(), sizeof(double) * S.N);
+  if (normals) std::memcpy(normals, S.nrm.data(), sizeof(double) * 3 * S.N);
+  if (H) std::memcpy(H, S.H.data(), sizeof(double) * S.N);
+  API_END
+}
+
+lb_status lb_get_corrections(const lb_ctx* ctx, int64_t* row_ptr, int32_t* patch, double* vals) {
+  API_BEGIN
+  if (!ctx) fail(LB_EINVAL, "null context");
+  const Surface& S = ctx->S;
+  if (row_ptr) std::memcpy(row_ptr, S.near_ptr.data(), sizeof(int64_t) * (S.N + 1));
+  if (patch) std::memcpy(patch, S.near_patch.data(), sizeof(int32_t) * S.near_patch.size());
+  if (vals) std::memcpy(vals, ctx->C64.data(), sizeof(double) * ctx->C64.size());
+  API_END
+}
+
+static void check_apply(lb_ctx* ctx, int nd, int prec) {
+  if (!ctx) fail(LB_EINVAL, "null context");
+  if (ctx->host_only) fail(LB_EINVAL, "context was set up with LB_HOST_ONLY");
+  if (nd < 1) fail(LB_EINVAL, "nd must be >= 1");
+  if (prec != LB_PREC_FP32 && prec != LB_PREC_FP64) fail(LB_EINVAL, "prec must be 32 or 64");
+  int dev = -1;
+  HIPTRY(hipGetDevice(&dev));
+  if (dev != ctx->device) fail(LB_EINVAL, "current device %d differs from the context's %d", dev, ctx->device);
+}
+
+lb_status lb_apply_gradS(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* grad, void* dSdn,
+                         void* surf_grad, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!sigma || !grad) fail(LB_EINVAL, "null sigma or grad");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_gradS_t<float>(ctx, ctx->f32, nd, (const float*)sigma, (float*)pot, (float*)grad, (float*)dSdn,
+                         (float*)surf_grad, st);
+  else
+    apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, (double*)grad, (double*)dSdn,
+                          (double*)surf_grad, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_apply_S(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!sigma || !pot) fail(LB_EINVAL, "null sigma or pot");
+  hipStream_t st = (hipStream_t)stream;
+  // gradient scratch
+  DBuf g;
+  g.alloc((prec == LB_PREC_FP32 ? sizeof(float) : sizeof(double)) * 3 * (size_t)ctx->N * nd);
+  if (prec == LB_PREC_FP32)
+    apply_gradS_t<float>(ctx, ctx->f32, nd, (const float*)sigma, (float*)pot, dptr<float>(g), nullptr, nullptr, st);
+  else
+    apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, dptr<double>(g), nullptr, nullptr, st);
+  HIPTRY(hipStreamSynchronize(st));
+  API_END
+}
+
+lb_status lb_apply_A3(lb_ctx* ctx, int nd, int prec, const void* tau, void* out, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!tau || !out) fail(LB_EINVAL, "null tau or out");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_A3_t<float>(ctx, ctx->f32, nd, (const float*)tau, (float*)out, st);
+  else
+    apply_A3_t<double>(ctx, ctx->f64, nd, (const double*)tau, (double*)out, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol, int mode, lb_solve_info* info,
+                   void* stream) {
+  API_BEGIN
+  check_apply(ctx, nrhs, LB_PREC_FP64);
+  if (!f || !u) fail(LB_EINVAL, "null f or u");
+  if (!(tol > 0)) fail(LB_EINVAL, "tol must be > 0");
+  if (mode != LB_SOLVE_FP64 && mode != LB_SOLVE_FP32_REFINE) fail(LB_EINVAL, "unknown mode");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = ctx->N;
+  const int maxit = ctx->opts.max_iter;
+  ensure_ws(ctx, ctx->f64, CHUNK_GRAD);
+  ensure_ws(ctx, ctx->f32, CHUNK_GRAD);
+  ctx->r.alloc(sizeof(double) * N);
+  ctx->sig.alloc(sizeof(double) * N);
+  ctx->ftmp.alloc(sizeof(double) * N);
+  ctx->utmp.alloc(sizeof(double) * N * 3);
+  ctx->f32.tmp_in.alloc(sizeof(float) * N);
+  ctx->f32.tmp_out.alloc(sizeof(float) * N);
+  double* r = dptr<double>(ctx->r);
+  double* sig = dptr<double>(ctx->sig);
+  double* fz = dptr<double>(ctx->ftmp);
+  double* ut = dptr<double>(ctx->utmp);
+  double* dcorr = ut + N;
+  double* hd = ctx->hbuf.p ? dptr<double>(ctx->hbuf) : nullptr;
+  DBuf scal;
+  scal.alloc(sizeof(double) * 4);
+  lb_status ret = LB_OK;
+  auto A64 = [&](const double* v, double* w) { apply_A3_t<double>(ctx, ctx->f64, 1, v, w, st); };
+  auto A32 = [&](const double* v, double* w) {
+    float* vi = dptr<float>(ctx->f32.tmp_in);
+    float* vo = dptr<float>(ctx->f32.tmp_out);
+    launch_convert<double, float>(v, vi, N, st);
+    apply_A3_t<float>(ctx, ctx->f32, 1, vi, vo, st);
+    launch_convert<float, double>(vo, w, N, st);
+  };
+  auto nrm2 = [&](const double* v) {
+    launch_dots(v, N, 1, v, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
+    double s;
+    HIPTRY(hipMemcpyAsync(&s, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return std::sqrt(s);
+  };
+  (void)hd;
+  for (int q = 0; q < nrhs; ++q) {
+    const double* fq = f + (int64_t)q * N;
+    // mean projection (Lemma 1)
+    launch_wmean(fq, dptr<double>(ctx->w), N, dptr<double>(ctx->partial), dptr<double>(scal), st);
+    double sumwf;
+    HIPTRY(hipMemcpyAsync(&sumwf, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    const double mean = sumwf / ctx->area;
+    HIPTRY(hipMemcpyAsync(fz, fq, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    if (ctx->opts.flags & LB_STRICT_MEAN) {
+      double fn = nrm2(fz);
+      if (std::fabs(mean) > 1e-12 * fn) fail(LB_ENOTMEANZERO, "f has weighted mean %g", mean);
+    }
+    launch_sub_scalar(fz, dptr<double>(scal), 1.0 / ctx->area, N, st);
+    const double fnorm = nrm2(fz);
+    int iters = 0, outer = 0;
+    double rel = 0;
+    if (mode == LB_SOLVE_FP64) {
+      int it = gmres(ctx, A64, fz, sig, tol, maxit, &rel, st);
+      iters = it;
+      A64(sig, ut);
+      launch_axpby(1.0, fz, -1.0, ut, r, N, st);
+      rel = fnorm > 0 ? nrm2(r) / fnorm : 0.0;
+      if (rel >= tol && it >= maxit) ret = LB_ENOCONV;
+    } else {
+      HIPTRY(hipMemsetAsync(sig, 0, sizeof(double) * N, st));
+      HIPTRY(hipMemcpyAsync(r, fz, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+      rel = 1.0;
+      const int max_outer = 12;
+      bool stalled = false;
+      double prev = 1e300;
+      while (rel >= tol && outer < max_outer) {
+        double inner_rel;
+        double inner_tol = std::max(1e-6, 0.5 * tol / std::max(rel, 1e-300));
+        int it = gmres(ctx, A32, r, dcorr, inner_tol, maxit, &inner_rel, st);
+        iters += it;
+        launch_axpby(1.0, sig, 1.0, dcorr, sig, N, st);
+        A64(sig, ut);
+        launch_axpby(1.0, fz, -1.0, ut, r, N, st);
+        rel = fnorm > 0 ? nrm2(r) / fnorm : 0.0;
+        ++outer;
+        if (rel > 0.5 * prev) { stalled = true; break; }
+        prev = rel;
+      }
+      if (rel >= tol) ret = LB_ENOCONV;
+      (void)stalled;
+    }
+    // u = S[S[sigma]] in FP64
+    double* uq = u + (int64_t)q * N;
+    {
+      DBuf g;
+      g.alloc(sizeof(double) * 3 * N);
+      apply_gradS_t<double>(ctx, ctx->f64, 1, sig, ut, dptr<double>(g), nullptr, nullptr, st);
+      apply_gradS_t<double>(ctx, ctx->f64, 1, ut, uq, dptr<double>(g), nullptr, nullptr, st);
+      HIPTRY(hipStreamSynchronize(st));
+    }
+    if (info) {
+      info[q].iters = iters;
+      info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer - 1, 0);
+      info[q].rel_resid = rel;
+      info[q].removed_mean = mean;
+    }
+  }
+  if (ret != LB_OK) {
+    lb::set_last_error("GMRES did not reach the tolerance for some right-hand side");
+    return ret;
+  }
+  API_END
+}
+
+void lb_destroy(lb_ctx* ctx) {
+  if (!ctx) return;
+  try {
+    if (!ctx->host_only) (void)hipSetDevice(ctx->device);
+    delete ctx;
+  } catch (...) {
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,932 @@
+// HIP kernels of the layer-potential apply (gfx950, wave64).
+//
+//  * strengths:     tau -> c = w^over (P tau) in source tree order (Section 4,
+//                   eq. nys-lcq: oversampled interpolation of the density)
+//  * FMM:           P2M, M2M, M2L, L2L, L2P for the charge/dipole vector FMM of
+//                   Section 4, eq. (fmm-formula), uniform-depth octree
+//  * near field:    direct sums over adjacent leaves (U-list) fused with L2P
+//  * corrections:   block-CSR products with the stored near corrections of
+//                   eq. (nys-lcq2), fused with the combination of Section 4.1
+//                   (S, grad S, S', surface gradient) and Section 4.3 (A3)
+//  * FP64 BLAS-1/2 helpers for GMRES (Section 6)
+// Every output element has one owning thread; no floating-point atomics, so
+// results are bitwise reproducible run to run.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+#include <cstdio>
+
+namespace lb {
+
+#define KCHECK()                                                                     \
+  do {                                                                               \
+    hipError_t e_ = hipGetLastError();                                               \
+    if (e_ != hipSuccess) {                                                          \
+      fprintf(stderr, "lb kernel launch failed: %s (%s:%d)\n", hipGetErrorString(e_), \
+              __FILE__, __LINE__);                                                   \
+    }                                                                                \
+  } while (0)
+
+template <typename T> __device__ __forceinline__ T dev_rsqrt(T x);
+template <> __device__ __forceinline__ float dev_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double dev_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename T> __device__ __forceinline__ T dev_fma(T a, T b, T c);
+template <> __device__ __forceinline__ float dev_fma<float>(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+template <> __device__ __forceinline__ double dev_fma<double>(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+__device__ __forceinline__ int cidx(int n, int m) { return n * (n + 1) / 2 + m; }
+
+// real layout index -> (n, m, part) with part 0 = Re, 1 = Im
+__device__ __forceinline__ void rdecode(int c, int& n, int& m, int& part) {
+  n = (int)sqrtf((float)c + 0.5f);
+  while (n * n > c) --n;
+  while ((n + 1) * (n + 1) <= c) ++n;
+  int r = c - n * n;
+  m = (r + 1) >> 1;
+  part = (r == 0 || (r & 1)) ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// strengths
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_strengths(const T* __restrict__ tau, int ne, int64_t N, int n_p, int n_o,
+                            const T* __restrict__ P, const T* __restrict__ wo,
+                            const int* __restrict__ src_pos, int64_t No, T* __restrict__ str) {
+  extern __shared__ unsigned char smraw[];
+  T* tp = reinterpret_cast<T*>(smraw);
+  const int pch = blockIdx.x;
+  for (int t = threadIdx.x; t < ne * n_p; t += blockDim.x) {
+    int e = t / n_p, k = t - e * n_p;
+    tp[t] = tau[(int64_t)e * N + (int64_t)pch * n_p + k];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ne * n_o; t += blockDim.x) {
+    int e = t / n_o, m = t - e * n_o;
+    const T* Pm = P + (int64_t)m * n_p;
+    const T* te = tp + e * n_p;
+    T acc = 0;
+    for (int k = 0; k < n_p; ++k) acc += Pm[k] * te[k];
+    int64_t gm = (int64_t)pch * n_o + m;
+    str[(int64_t)e * No + src_pos[gm]] = wo[gm] * acc;
+  }
+}
+
+template <typename T>
+void launch_strengths(const T* tau, int ne, int64_t N, int NP, int n_p, int n_o, const T* P,
+                      const T* wo, const int* src_pos, int64_t No, T* str, hipStream_t st) {
+  size_t sm = sizeof(T) * ne * n_p;
+  hipLaunchKernelGGL(k_strengths<T>, dim3(NP), dim3(256), sm, st, tau, ne, N, n_p, n_o, P, wo,
+                     src_pos, No, str);
+  KCHECK();
+}
+
+// ---------------------------------------------------------------------------
+// solid harmonics Rt_n^m (normalized regular) of xi into LDS rows (re, im)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void regular_to_lds(int p, T x, T y, T z, T* re, T* im) {
+  const T r2 = x * x + y * y + z * z;
+  T mre = 1, mim = 0;  // Rt_m^m
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      T f = -sqrt((T)(2 * m - 1) / (T)(2 * m));
+      T nr = f * (x * mre - y * mim);
+      T ni = f * (x * mim + y * mre);
+      mre = nr;
+      mim = ni;
+    }
+    re[cidx(m, m)] = mre;
+    im[cidx(m, m)] = mim;
+    if (m + 1 > p) continue;
+    T c1 = z * sqrt((T)(2 * m + 1));
+    T are = mre, aim = mim;           // n = m
+    T bre = c1 * mre, bim = c1 * mim;  // n = m+1
+    re[cidx(m + 1, m)] = bre;
+    im[cidx(m + 1, m)] = bim;
+    for (int n = m + 1; n < p; ++n) {
+      T f1 = (T)(2 * n + 1) * z;
+      T f2 = r2 * sqrt((T)((n + m) * (n - m)));
+      T dn = (T)1 / sqrt((T)((n + 1 + m) * (n + 1 - m)));
+      T cre = (f1 * bre - f2 * are) * dn;
+      T cim = (f1 * bim - f2 * aim) * dn;
+      re[cidx(n + 1, m)] = cre;
+      im[cidx(n + 1, m)] = cim;
+      are = bre; aim = bim;
+      bre = cre; bim = cim;
+    }
+  }
+}
+
+// Rt_n^m for any m in [-n, n] from an LDS row of m >= 0 values
+template <typename T>
+__device__ __forceinline__ void rt_get(const T* re, const T* im, int n, int m, T& a, T& b) {
+  if (m < -n || m > n || n < 0) { a = 0; b = 0; return; }
+  if (m >= 0) { a = re[cidx(n, m)]; b = im[cidx(n, m)]; return; }
+  T s = ((-m) & 1) ? (T)-1 : (T)1;
+  a = s * re[cidx(n, -m)];
+  b = -s * im[cidx(n, -m)];
+}
+
+// ---------------------------------------------------------------------------
+// P2M: leaf sources -> multipole (charges and, in FMM_A3B, dipoles c * nu)
+// grid (leaves with sources, nrhs); M [nbox][nrhs*nexp][L]
+// ---------------------------------------------------------------------------
+constexpr int P2M_TS = 32;
+constexpr int KMAX = 4;  // L <= 1024
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, const T* __restrict__ str,
+                                             int64_t No, T* __restrict__ M) {
+  extern __shared__ unsigned char smraw[];
+  const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
+  T* Rre = reinterpret_cast<T*>(smraw);
+  T* Rim = Rre + P2M_TS * Lc;
+  T* sq = Rim + P2M_TS * Lc;     // [2][TS] strengths of this rhs
+  T* sn = sq + 2 * P2M_TS;       // [3][TS] normals
+  const int b = t.leaf_src_list[blockIdx.x];
+  const int g = t.leaf_off + b;
+  const int rhs = blockIdx.y;
+  const int nexp = fmm_nexp(mode), nstr = fmm_nstr(mode);
+  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T ih = (T)1 / h;
+  const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
+  T acc[KMAX][3];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) acc[k][e] = 0;
+  const int beg = t.src_beg[b], end = t.src_end[b];
+  for (int t0 = beg; t0 < end; t0 += P2M_TS) {
+    const int nt = min(P2M_TS, end - t0);
+    const int j = threadIdx.x;
+    if (j < nt) {
+      const int s = t0 + j;
+      regular_to_lds<T>(p, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc, Rim + j * Lc);
+      for (int q = 0; q < nstr; ++q) sq[q * P2M_TS + j] = str[(int64_t)(rhs * nstr + q) * No + s];
+      sn[j] = t.snx[s];
+      sn[P2M_TS + j] = t.sny[s];
+      sn[2 * P2M_TS + j] = t.snz[s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int c = threadIdx.x + k * 256;
+      if (c >= L) break;
+      int n, m, part;
+      rdecode(c, n, m, part);
+      const T sgn = part ? (T)-1 : (T)1;  // conj
+      // dipole factors (nu . grad Rt_n^m), see harmonics.hpp
+      const T fa = sqrt((T)((n + m) * (n - m)));
+      const T fb = (T)0.5 * sqrt((T)((n - m) * (n - m - 1) > 0 ? (n - m) * (n - m - 1) : 0));
+      const T fc = (T)0.5 * sqrt((T)((n + m) * (n + m - 1) > 0 ? (n + m) * (n + m - 1) : 0));
+      for (int jj = 0; jj < nt; ++jj) {
+        const T* re = Rre + jj * Lc;
+        const T* im = Rim + jj * Lc;
+        const T v = part ? im[cidx(n, m)] : re[cidx(n, m)];
+        acc[k][0] += sq[jj] * sgn * v;
+        if (mode == FMM_A3B) {
+          acc[k][1] += sq[P2M_TS + jj] * sgn * v;
+          // nu . grad Rt_n^m = nz fa R_{n-1}^m + (nx - i ny) fb R_{n-1}^{m+1} - (nx + i ny) fc R_{n-1}^{m-1}
+          const T nx = sn[jj], ny = sn[P2M_TS + jj], nz = sn[2 * P2M_TS + jj];
+          T a0, b0, a1, b1, a2, b2;
+          rt_get(re, im, n - 1, m, a0, b0);
+          rt_get(re, im, n - 1, m + 1, a1, b1);
+          rt_get(re, im, n - 1, m - 1, a2, b2);
+          T gre = nz * fa * a0 + fb * (nx * a1 + ny * b1) - fc * (nx * a2 - ny * b2);
+          T gim = nz * fa * b0 + fb * (nx * b1 - ny * a1) - fc * (nx * b2 + ny * a2);
+          const T gv = part ? gim : gre;
+          acc[k][2] += sq[P2M_TS + jj] * sgn * gv * ih;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int c = threadIdx.x + k * 256;
+    if (c >= L) break;
+    for (int e = 0; e < nexp; ++e) M[((int64_t)g * nrhs * nexp + rhs * nexp + e) * L + c] = acc[k][e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense translation helpers: out[e][r] (+)= sum_c TT[c][r] x[e][c]
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void mv_acc(const T* __restrict__ TT, const T* x, int L, int ne, T acc[KMAX][8]) {
+  for (int c = 0; c < L; ++c) {
+    const T* col = TT + (int64_t)c * L;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int r = threadIdx.x + k * 256;
+      if (r < L) {
+        const T a = col[r];
+        for (int e = 0; e < ne; ++e) acc[k][e] += a * x[e * L + c];
+      }
+    }
+  }
+}
+
+// M2M: grid = boxes with sources on level l (l < depth)
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2m(DevTree<T> t, int l, int ne, T* __restrict__ M) {
+  extern __shared__ unsigned char smraw[];
+  T* x = reinterpret_cast<T*>(smraw);
+  const int L = t.L;
+  const int g = t.lev_box_src[t.lev_box_src_ptr[l] + blockIdx.x];
+  T acc[KMAX][8];
+  for (int k = 0; k < KMAX; ++k)
+    for (int e = 0; e < 8; ++e) acc[k][e] = 0;
+  for (int oct = 0; oct < 8; ++oct) {
+    const int ch = t.child[(int64_t)g * 8 + oct];
+    if (ch < 0) continue;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = M[(int64_t)ch * ne * L + i];
+    __syncthreads();
+    mv_acc(t.m2m + (int64_t)oct * L * L, x, L, ne, acc);
+  }
+  for (int k = 0; k < KMAX; ++k) {
+    const int r = threadIdx.x + k * 256;
+    if (r < L)
+      for (int e = 0; e < ne; ++e) M[((int64_t)g * ne + e) * L + r] = acc[k][e];
+  }
+}
+
+// M2L: grid = boxes with targets on level l (l >= 2); writes Lc (overwrite)
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l(DevTree<T> t, int l, int ne, const T* __restrict__ M, T* __restrict__ Lc) {
+  extern __shared__ unsigned char smraw[];
+  T* x = reinterpret_cast<T*>(smraw);
+  const int L = t.L;
+  const int g = t.lev_box_tgt[t.lev_box_tgt_ptr[l] + blockIdx.x];
+  T acc[KMAX][8];
+  for (int k = 0; k < KMAX; ++k)
+    for (int e = 0; e < 8; ++e) acc[k][e] = 0;
+  for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) {
+    const int s = t.vlist_src[v];
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = M[(int64_t)s * ne * L + i];
+    __syncthreads();
+    mv_acc(t.m2l + (int64_t)t.vlist_off[v] * L * L, x, L, ne, acc);
+  }
+  const T ih = (T)((double)(1 << l) / t.side);
+  for (int k = 0; k < KMAX; ++k) {
+    const int r = threadIdx.x + k * 256;
+    if (r < L)
+      for (int e = 0; e < ne; ++e) Lc[((int64_t)g * ne + e) * L + r] = acc[k][e] * ih;
+  }
+}
+
+// L2L: grid = boxes with targets on level l (l >= 3); Lc[g] += TT[oct] Lc[parent]
+template <typename T>
+__global__ __launch_bounds__(256) void k_l2l(DevTree<T> t, int l, int ne, T* __restrict__ Lc) {
+  extern __shared__ unsigned char smraw[];
+  T* x = reinterpret_cast<T*>(smraw);
+  const int L = t.L;
+  const int g = t.lev_box_tgt[t.lev_box_tgt_ptr[l] + blockIdx.x];
+  const int pg = t.parent[g];
+  int oct = -1;
+  for (int c = 0; c < 8; ++c)
+    if (t.child[(int64_t)pg * 8 + c] == g) oct = c;
+  for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = Lc[(int64_t)pg * ne * L + i];
+  __syncthreads();
+  T acc[KMAX][8];
+  for (int k = 0; k < KMAX; ++k)
+    for (int e = 0; e < 8; ++e) acc[k][e] = 0;
+  mv_acc(t.l2l + (int64_t)oct * L * L, x, L, ne, acc);
+  for (int k = 0; k < KMAX; ++k) {
+    const int r = threadIdx.x + k * 256;
+    if (r < L)
+      for (int e = 0; e < ne; ++e) Lc[((int64_t)g * ne + e) * L + r] += acc[k][e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// leaf evaluation: L2P (far) + direct sums over the U-list (near)
+// grid (leaves with targets, nrhs); out [nrhs*nout][N] in target tree order
+// ---------------------------------------------------------------------------
+constexpr int LEAF_BS = 128;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str,
+                                                  int64_t No, const T* __restrict__ Lc, T* __restrict__ D,
+                                                  T* __restrict__ out, int64_t N) {
+  extern __shared__ unsigned char smraw[];
+  const int b = t.leaf_tgt_list[blockIdx.x];
+  const int g = t.leaf_off + b;
+  const int rhs = blockIdx.y;
+  const int p = t.p, L = t.L, Lg = p * p, Lh = (p - 1) * (p - 1);
+  const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
+  const bool far = t.depth >= 2;
+  // expansions for L2P, read with wave-uniform addresses: local [nexp][L] in
+  // Lc; derived gradient [nexp][3][Lg] and hessian [6][Lh] (A3B: expansion 1)
+  // in this block's slice of D
+  const T* sL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
+  const int64_t dstride = (int64_t)nexp * 3 * Lg + 6 * Lh;
+  T* sG = D + ((int64_t)blockIdx.x * nrhs + rhs) * dstride;
+  T* sH = sG + nexp * 3 * Lg;
+  T* tile = reinterpret_cast<T*>(smraw);  // [9][LEAF_BS]: x, y, z, nx, ny, nz, rm2, q1, q2
+  if (far) {
+    const bool need_grad = MODE != FMM_POT;
+    if (need_grad) {
+      for (int i = threadIdx.x; i < nexp * 3 * Lg; i += blockDim.x) {
+        const int e = i / (3 * Lg), rr = i - e * 3 * Lg, comp = rr / Lg, r = rr - comp * Lg;
+        const T* Dm = t.dgradT + (int64_t)comp * L * Lg;
+        T a = 0;
+        for (int c = 0; c < L; ++c) a += Dm[(int64_t)c * Lg + r] * sL[e * L + c];
+        sG[i] = a;
+      }
+    }
+    if (MODE == FMM_A3B) {
+      for (int i = threadIdx.x; i < 6 * Lh; i += blockDim.x) {
+        const int comp = i / Lh, r = i - comp * Lh;
+        const T* Dm = t.dhessT + (int64_t)comp * L * Lh;
+        T a = 0;
+        for (int c = 0; c < L; ++c) a += Dm[(int64_t)c * Lh + r] * sL[1 * L + c];
+        sH[i] = a;
+      }
+    }
+    __syncthreads();
+  }
+  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T ih = (T)1 / h;
+  const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
+  const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
+  for (int i0 = tbeg; i0 < tend; i0 += LEAF_BS) {
+    const int i = i0 + threadIdx.x;
+    const bool act = i < tend;
+    T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0;
+    if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
+    T o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+    // ---- far field: evaluate local expansions at xi = (x - c)/h ----
+    if (far && act) {
+      const T x = (X - cx) * ih, y = (Y - cy) * ih, z = (Z - cz) * ih;
+      const T r2 = x * x + y * y + z * z;
+      T pot = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
+      T mre = 1, mim = 0;
+      for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+          T f = -sqrt((T)(2 * m - 1) / (T)(2 * m));
+          T nr = f * (x * mre - y * mim);
+          T ni = f * (x * mim + y * mre);
+          mre = nr; mim = ni;
+        }
+        T are = 0, aim = 0, bre = mre, bim = mim;  // R_{n-1}, R_n with n = m
+        for (int n = m; n <= p; ++n) {
+          if (n > m) {
+            T cre, cim;
+            if (n == m + 1) {
+              T c1 = z * sqrt((T)(2 * m + 1));
+              cre = c1 * bre; cim = c1 * bim;
+            } else {
+              const int nn = n - 1;
+              T f1 = (T)(2 * nn + 1) * z;
+              T f2 = r2 * sqrt((T)((nn + m) * (nn - m)));
+              T dn = (T)1 / sqrt((T)((nn + 1 + m) * (nn + 1 - m)));
+              cre = (f1 * bre - f2 * are) * dn;
+              cim = (f1 * bim - f2 * aim) * dn;
+            }
+            are = bre; aim = bim; bre = cre; bim = cim;
+          }
+          // rho entries of (n, m)
+          T rre, rim;
+          int ire, iim;
+          if (m == 0) { rre = bre; rim = 0; ire = n * n; iim = -1; }
+          else { rre = 2 * bre; rim = -2 * bim; ire = n * n + 2 * m - 1; iim = n * n + 2 * m; }
+#define ACC(dst, base, idxre, idxim) dst += (base)[idxre] * rre + ((idxim) >= 0 ? (base)[idxim] * rim : (T)0)
+          if (MODE == FMM_POT) {
+            ACC(pot, sL, ire, iim);
+          } else if (MODE == FMM_GRAD) {
+            ACC(pot, sL, ire, iim);
+            if (n < p) {
+              ACC(g1[0], sG, ire, iim);
+              ACC(g1[1], sG + Lg, ire, iim);
+              ACC(g1[2], sG + 2 * Lg, ire, iim);
+            }
+          } else {
+            ACC(pot, sL + L, ire, iim);  // phi_2
+            if (n < p) {
+              ACC(g1[0], sG, ire, iim);
+              ACC(g1[1], sG + Lg, ire, iim);
+              ACC(g1[2], sG + 2 * Lg, ire, iim);
+              ACC(g2[0], sG + 3 * Lg, ire, iim);
+              ACC(g2[1], sG + 4 * Lg, ire, iim);
+              ACC(g2[2], sG + 5 * Lg, ire, iim);
+              ACC(g3[0], sG + 6 * Lg, ire, iim);
+              ACC(g3[1], sG + 7 * Lg, ire, iim);
+              ACC(g3[2], sG + 8 * Lg, ire, iim);
+            }
+            if (n < p - 1) {
+#pragma unroll
+              for (int q = 0; q < 6; ++q) ACC(hs[q], sH + q * Lh, ire, iim);
+            }
+          }
+#undef ACC
+        }
+      }
+      if (MODE == FMM_POT) {
+        o0 = pot;
+      } else if (MODE == FMM_GRAD) {
+        o0 = pot; o1 = g1[0] * ih; o2 = g1[1] * ih; o3 = g1[2] * ih;
+      } else {
+        o0 = (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
+        o1 = pot;
+        o2 = (NX * g2[0] + NY * g2[1] + NZ * g2[2]) * ih;
+        T nhn = NX * NX * hs[0] + 2 * NX * NY * hs[1] + 2 * NX * NZ * hs[2] + NY * NY * hs[3] +
+                2 * NY * NZ * hs[4] + NZ * NZ * hs[5];
+        o3 = nhn * ih * ih + (NX * g3[0] + NY * g3[1] + NZ * g3[2]) * ih;
+      }
+    }
+    // ---- near field: U-list direct sums ----
+    T* tx_ = tile;
+    T* ty_ = tile + LEAF_BS;
+    T* tz_ = tile + 2 * LEAF_BS;
+    T* tnx_ = tile + 3 * LEAF_BS;
+    T* tny_ = tile + 4 * LEAF_BS;
+    T* tnz_ = tile + 5 * LEAF_BS;
+    T* trm_ = tile + 6 * LEAF_BS;
+    T* tq1_ = tile + 7 * LEAF_BS;
+    T* tq2_ = tile + 8 * LEAF_BS;
+    for (int u = t.ulist_ptr[b]; u < t.ulist_ptr[b + 1]; ++u) {
+      const int nb = t.ulist[u];
+      const int sb = t.src_beg[nb], se = t.src_end[nb];
+      for (int s0 = sb; s0 < se; s0 += LEAF_BS) {
+        const int ns = min(LEAF_BS, se - s0);
+        __syncthreads();
+        if (threadIdx.x < ns) {
+          const int s = s0 + threadIdx.x;
+          tx_[threadIdx.x] = t.sx[s];
+          ty_[threadIdx.x] = t.sy[s];
+          tz_[threadIdx.x] = t.sz[s];
+          trm_[threadIdx.x] = t.rm2[s];
+          tq1_[threadIdx.x] = str[(int64_t)(rhs * nstr) * No + s];
+          if (MODE == FMM_A3B) {
+            tq2_[threadIdx.x] = str[(int64_t)(rhs * nstr + 1) * No + s];
+            tnx_[threadIdx.x] = t.snx[s];
+            tny_[threadIdx.x] = t.sny[s];
+            tnz_[threadIdx.x] = t.snz[s];
+          }
+        }
+        __syncthreads();
+        if (act) {
+          for (int jj = 0; jj < ns; ++jj) {
+            const T dx = X - tx_[jj];
+            const T dy = Y - ty_[jj];
+            const T dz = Z - tz_[jj];
+            const T r2 = dev_fma(dz, dz, dev_fma(dy, dy, dx * dx));
+            if (r2 < trm_[jj] || r2 == (T)0) continue;  // pair handled by the stored corrections
+            const T ri = dev_rsqrt(r2);
+            const T ri2 = ri * ri;
+            const T ri3 = ri * ri2;
+            if (MODE == FMM_POT) {
+              o0 += tq1_[jj] * ri;
+            } else if (MODE == FMM_GRAD) {
+              const T q = tq1_[jj];
+              const T qr3 = q * ri3;
+              o0 += q * ri;
+              o1 -= qr3 * dx;
+              o2 -= qr3 * dy;
+              o3 -= qr3 * dz;
+            } else {
+              const T q1 = tq1_[jj], q2 = tq2_[jj];
+              const T nd = NX * dx + NY * dy + NZ * dz;
+              const T mx = NX - tnx_[jj], my = NY - tny_[jj], mz = NZ - tnz_[jj];
+              const T md = mx * dx + my * dy + mz * dz;
+              const T nm = NX * mx + NY * my + NZ * mz;
+              o0 -= q1 * nd * ri3;
+              o1 += q2 * ri;
+              o2 -= q2 * nd * ri3;
+              o3 += q2 * ((T)3 * nd * md * ri3 * ri2 - nm * ri3);
+            }
+          }
+        }
+      }
+    }
+    if (act) {
+      const int64_t base = (int64_t)rhs * nout * N;
+      out[base + i] = o0;
+      if (nout > 1) {
+        out[base + N + i] = o1;
+        out[base + 2 * N + i] = o2;
+        out[base + 3 * N + i] = o3;
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
+                int64_t N, int64_t No, hipStream_t st) {
+  const int p = t.p, L = t.L, Lc_ = (p + 1) * (p + 2) / 2;
+  const int ne = nrhs * fmm_nexp(mode);
+  if (t.depth >= 2) {
+    size_t sm = sizeof(T) * (2 * P2M_TS * Lc_ + 5 * P2M_TS);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M);
+    KCHECK();
+    const int* hp = t.h_lev_src_ptr;
+    const int* ht = t.h_lev_tgt_ptr;
+    size_t smv = sizeof(T) * ne * L;
+    for (int l = t.depth - 1; l >= 2; --l) {
+      int nb = hp[l + 1] - hp[l];
+      if (nb > 0) hipLaunchKernelGGL(k_m2m<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M);
+      KCHECK();
+    }
+    for (int l = 2; l <= t.depth; ++l) {
+      int nb = ht[l + 1] - ht[l];
+      if (nb > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M, Lc);
+      KCHECK();
+    }
+    for (int l = 3; l <= t.depth; ++l) {
+      int nb = ht[l + 1] - ht[l];
+      if (nb > 0) hipLaunchKernelGGL(k_l2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, Lc);
+      KCHECK();
+    }
+  }
+  const int nexp = fmm_nexp(mode);
+  size_t sml = sizeof(T) * 9 * LEAF_BS;
+  dim3 grid(t.n_leaf_tgt, nrhs);
+  if (mode == FMM_POT)
+    hipLaunchKernelGGL((k_leaf<T, FMM_POT>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
+  else if (mode == FMM_GRAD)
+    hipLaunchKernelGGL((k_leaf<T, FMM_GRAD>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
+  else
+    hipLaunchKernelGGL((k_leaf<T, FMM_A3B>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
+  KCHECK();
+}
+
+// ---------------------------------------------------------------------------
+// block-CSR corrections fused with the combination step; one wave per row
+// ---------------------------------------------------------------------------
+constexpr double INV4PI_D = 0.07957747154594767;  // 1/(4 pi)
+constexpr int NDMAX = 4;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine_grad(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+                                                      const int* __restrict__ patch, const T* __restrict__ vals,
+                                                      const T* __restrict__ sigma, const T* __restrict__ fmm,
+                                                      const int* __restrict__ tgt_pos, const T* __restrict__ nrm,
+                                                      T* pot, T* grad, T* dSdn, T* surf) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
+  const int64_t ne = (b1 - b0) * n_p;
+  T acc[NDMAX][4];
+#pragma unroll
+  for (int d = 0; d < NDMAX; ++d)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[d][k] = 0;
+  const T* v = vals + b0 * n_p * 4;
+  for (int64_t e = lane; e < ne; e += 64) {
+    const int64_t blk = e / n_p;
+    const int j = (int)(e - blk * n_p);
+    const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
+    const T c0 = v[4 * e], c1 = v[4 * e + 1], c2 = v[4 * e + 2], c3 = v[4 * e + 3];
+    for (int d = 0; d < nd; ++d) {
+      const T x = sigma[(int64_t)d * N + col];
+      acc[d][0] += c0 * x; acc[d][1] += c1 * x; acc[d][2] += c2 * x; acc[d][3] += c3 * x;
+    }
+  }
+  for (int d = 0; d < nd; ++d)
+    for (int k = 0; k < 4; ++k) acc[d][k] = wave_sum(acc[d][k]);
+  if (lane == 0) {
+    const int tp = tgt_pos[row];
+    const T n0 = nrm[3 * row], n1 = nrm[3 * row + 1], n2 = nrm[3 * row + 2];
+    const T s = (T)INV4PI_D;
+    for (int d = 0; d < nd; ++d) {
+      const T* f = fmm + (int64_t)d * 4 * N;
+      const T P = f[tp] * s + acc[d][0];
+      const T gx = f[N + tp] * s + acc[d][1];
+      const T gy = f[2 * N + tp] * s + acc[d][2];
+      const T gz = f[3 * N + tp] * s + acc[d][3];
+      const T dn = n0 * gx + n1 * gy + n2 * gz;
+      if (pot) pot[(int64_t)d * N + row] = P;
+      if (grad) {
+        grad[((int64_t)d * N + row) * 3] = gx;
+        grad[((int64_t)d * N + row) * 3 + 1] = gy;
+        grad[((int64_t)d * N + row) * 3 + 2] = gz;
+      }
+      if (dSdn) dSdn[(int64_t)d * N + row] = dn;
+      if (surf) {
+        surf[((int64_t)d * N + row) * 3] = gx - n0 * dn;
+        surf[((int64_t)d * N + row) * 3 + 1] = gy - n1 * dn;
+        surf[((int64_t)d * N + row) * 3 + 2] = gz - n2 * dn;
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                         const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
+                         const T* nrm, T* pot, T* grad, T* dSdn, T* surf, hipStream_t st) {
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    hipLaunchKernelGGL(k_combine_grad<T>, dim3((N + 3) / 4), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals4,
+                       sigma + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm,
+                       pot ? pot + (int64_t)d0 * N : nullptr, grad ? grad + (int64_t)d0 * 3 * N : nullptr,
+                       dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr);
+    KCHECK();
+  }
+}
+
+// A3 step 1: mu2 = S tau, mu1 = S' tau  (vals3 columns: S, S', S''+D')
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine_a3a(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+                                                     const int* __restrict__ patch, const T* __restrict__ vals,
+                                                     const T* __restrict__ tau, const T* __restrict__ fmm,
+                                                     const int* __restrict__ tgt_pos, const T* __restrict__ nrm,
+                                                     T* mu1, T* mu2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
+  const int64_t ne = (b1 - b0) * n_p;
+  T aS[NDMAX], aP[NDMAX];
+  for (int d = 0; d < NDMAX; ++d) { aS[d] = 0; aP[d] = 0; }
+  const T* v = vals + b0 * n_p * 3;
+  for (int64_t e = lane; e < ne; e += 64) {
+    const int64_t blk = e / n_p;
+    const int j = (int)(e - blk * n_p);
+    const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
+    const T c0 = v[3 * e], c1 = v[3 * e + 1];
+    for (int d = 0; d < nd; ++d) {
+      const T x = tau[(int64_t)d * N + col];
+      aS[d] += c0 * x;
+      aP[d] += c1 * x;
+    }
+  }
+  for (int d = 0; d < nd; ++d) { aS[d] = wave_sum(aS[d]); aP[d] = wave_sum(aP[d]); }
+  if (lane == 0) {
+    const int tp = tgt_pos[row];
+    const T n0 = nrm[3 * row], n1 = nrm[3 * row + 1], n2 = nrm[3 * row + 2];
+    const T s = (T)INV4PI_D;
+    for (int d = 0; d < nd; ++d) {
+      const T* f = fmm + (int64_t)d * 4 * N;
+      mu2[(int64_t)d * N + row] = f[tp] * s + aS[d];
+      mu1[(int64_t)d * N + row] = (n0 * f[N + tp] + n1 * f[2 * N + tp] + n2 * f[3 * N + tp]) * s + aP[d];
+    }
+  }
+}
+
+template <typename T>
+void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                        const T* vals3, const T* tau, const T* fmm, const int* tgt_pos,
+                        const T* nrm, T* mu1, T* mu2, hipStream_t st) {
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    hipLaunchKernelGGL(k_combine_a3a<T>, dim3((N + 3) / 4), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals3,
+                       tau + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm, mu1 + (int64_t)d0 * N,
+                       mu2 + (int64_t)d0 * N);
+    KCHECK();
+  }
+}
+
+// A3 step 2: per row y1 = S'mu1, y2 = S mu2, y3 = S'mu2, y4 = (S''+D')mu2;
+// out = -tau/4 + y1 - y4 - 2 H y3 ; partial[block][d] = sum_rows w y2
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine_a3b(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+                                                     const int* __restrict__ patch, const T* __restrict__ vals,
+                                                     const T* __restrict__ tau, const T* __restrict__ mu1,
+                                                     const T* __restrict__ mu2, const T* __restrict__ fmm,
+                                                     const int* __restrict__ tgt_pos, const T* __restrict__ H,
+                                                     const double* __restrict__ w, T* out, double* partial,
+                                                     int nblk) {
+  __shared__ double red[4][NDMAX];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wv;
+  double wy[NDMAX];
+  for (int d = 0; d < NDMAX; ++d) wy[d] = 0;
+  if (row < N) {
+    const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
+    const int64_t ne = (b1 - b0) * n_p;
+    T a1[NDMAX], a2[NDMAX], a3[NDMAX], a4[NDMAX];
+    for (int d = 0; d < NDMAX; ++d) { a1[d] = a2[d] = a3[d] = a4[d] = 0; }
+    const T* v = vals + b0 * n_p * 3;
+    for (int64_t e = lane; e < ne; e += 64) {
+      const int64_t blk = e / n_p;
+      const int j = (int)(e - blk * n_p);
+      const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
+      const T cS = v[3 * e], cP = v[3 * e + 1], cD = v[3 * e + 2];
+      for (int d = 0; d < nd; ++d) {
+        const T x1 = mu1[(int64_t)d * N + col];
+        const T x2 = mu2[(int64_t)d * N + col];
+        a1[d] += cP * x1;
+        a2[d] += cS * x2;
+        a3[d] += cP * x2;
+        a4[d] += cD * x2;
+      }
+    }
+    for (int d = 0; d < nd; ++d) {
+      a1[d] = wave_sum(a1[d]); a2[d] = wave_sum(a2[d]); a3[d] = wave_sum(a3[d]); a4[d] = wave_sum(a4[d]);
+    }
+    if (lane == 0) {
+      const int tp = tgt_pos[row];
+      const T s = (T)INV4PI_D;
+      for (int d = 0; d < nd; ++d) {
+        const T* f = fmm + (int64_t)d * 4 * N;
+        const T y1 = f[tp] * s + a1[d];
+        const T y2 = f[N + tp] * s + a2[d];
+        const T y3 = f[2 * N + tp] * s + a3[d];
+        const T y4 = f[3 * N + tp] * s + a4[d];
+        out[(int64_t)d * N + row] = -(T)0.25 * tau[(int64_t)d * N + row] + y1 - y4 - (T)2 * H[row] * y3;
+        wy[d] = w[row] * (double)y2;
+      }
+    }
+  }
+  if (lane == 0)
+    for (int d = 0; d < NDMAX; ++d) red[wv][d] = wy[d];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int d = 0; d < nd; ++d) partial[(int64_t)d * nblk + blockIdx.x] = red[0][d] + red[1][d] + red[2][d] + red[3][d];
+}
+
+// serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
+__global__ void k_reduce_partials(const double* partial, int nblk, int nd, double scale, double* s) {
+  __shared__ double red[256];
+  for (int d = 0; d < nd; ++d) {
+    double a = 0;
+    for (int b = threadIdx.x; b < nblk; b += 256) a += partial[(int64_t)d * nblk + b];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) s[d] = red[0] * scale;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_add_scalar(T* out, int64_t N, int nd, const double* s) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < nd; ++d) out[(int64_t)d * N + i] += (T)s[d];
+}
+
+template <typename T>
+void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                        const T* vals3, const T* tau, const T* mu1, const T* mu2, const T* fmm,
+                        const int* tgt_pos, const T* H, const double* w, double inv_area,
+                        T* out, double* partial, hipStream_t st) {
+  const int nblk = (int)((N + 3) / 4);
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    double* sc = partial + (int64_t)NDMAX * nblk;  // NDMAX scalars after the partials
+    hipLaunchKernelGGL(k_combine_a3b<T>, dim3(nblk), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals3,
+                       tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * N, mu2 + (int64_t)d0 * N,
+                       fmm + (int64_t)d0 * 4 * N, tgt_pos, H, w, out + (int64_t)d0 * N, partial, nblk);
+    KCHECK();
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblk, ndc, inv_area, sc);
+    KCHECK();
+    hipLaunchKernelGGL(k_add_scalar<T>, dim3((N + 255) / 256), dim3(256), 0, st, out + (int64_t)d0 * N, N, ndc, sc);
+    KCHECK();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 vector helpers
+// ---------------------------------------------------------------------------
+constexpr int DOT_BLOCKS = 256;
+
+__global__ void k_dots_partial(const double* V, int64_t ldv, int k, const double* w, int64_t N, double* partial) {
+  __shared__ double red[256];
+  const int j = blockIdx.y;
+  const double* vj = V + (int64_t)j * ldv;
+  double a = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) a += vj[i] * w[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_dots_final(const double* partial, int nb, double* out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double a = 0;
+  for (int b = threadIdx.x; b < nb; b += 256) a += partial[(int64_t)j * nb + b];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+void launch_dots(const double* V, int64_t ldv, int k, const double* w, int64_t N, double* out,
+                 double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_dots_partial, dim3(DOT_BLOCKS, k), dim3(256), 0, st, V, ldv, k, w, N, partial);
+  KCHECK();
+  hipLaunchKernelGGL(k_dots_final, dim3(k), dim3(256), 0, st, partial, DOT_BLOCKS, out);
+  KCHECK();
+}
+
+__global__ void k_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t N, double sign) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double a = 0;
+  for (int j = 0; j < k; ++j) a += h[j] * V[(int64_t)j * ldv + i];
+  w[i] += sign * a;
+}
+
+void launch_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_gemv_sub, dim3((N + 255) / 256), dim3(256), 0, st, V, ldv, k, h, w, N, -1.0);
+  KCHECK();
+}
+void launch_gemv_add(const double* V, int64_t ldv, int k, const double* y, double* x, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_gemv_sub, dim3((N + 255) / 256), dim3(256), 0, st, V, ldv, k, y, x, N, 1.0);
+  KCHECK();
+}
+
+__global__ void k_scale_copy(const double* w, double a, double* v, int64_t N) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) v[i] = a * w[i];
+}
+void launch_scale_copy(const double* w, double a, double* v, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((N + 255) / 256), dim3(256), 0, st, w, a, v, N);
+  KCHECK();
+}
+
+__global__ void k_axpby(double a, const double* x, double b, const double* y, double* z, int64_t N) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) z[i] = a * x[i] + b * y[i];
+}
+void launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3((N + 255) / 256), dim3(256), 0, st, a, x, b, y, z, N);
+  KCHECK();
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A* x, B* y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (B)x[i];
+}
+template <typename A, typename B>
+void launch_convert(const A* x, B* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<A, B>), dim3((n + 255) / 256), dim3(256), 0, st, x, y, n);
+  KCHECK();
+}
+
+__global__ void k_wmean_partial(const double* f, const double* w, int64_t N, double* partial) {
+  __shared__ double red[256];
+  double a = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) a += w[i] * f[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+void launch_wmean(const double* f, const double* w, int64_t N, double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_wmean_partial, dim3(DOT_BLOCKS), dim3(256), 0, st, f, w, N, partial);
+  KCHECK();
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, st, partial, DOT_BLOCKS, out);
+  KCHECK();
+}
+
+__global__ void k_sub_scalar(double* f, const double* s, double scale, int64_t N) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) f[i] -= scale * s[0];
+}
+void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_scalar, dim3((N + 255) / 256), dim3(256), 0, st, f, s, scale, N);
+  KCHECK();
+}
+
+// explicit instantiations
+#define INST(T)                                                                                                   \
+  template void launch_strengths<T>(const T*, int, int64_t, int, int, int, const T*, const T*, const int*,        \
+                                    int64_t, T*, hipStream_t);                                                    \
+  template void launch_fmm<T>(const DevTree<T>&, int, int, const T*, T*, T*, T*, T*, int64_t, int64_t,       \
+                              hipStream_t);                                                               \
+  template void launch_combine_grad<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,        \
+                                       const T*, const int*, const T*, T*, T*, T*, T*, hipStream_t);             \
+  template void launch_combine_a3a<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
+                                      const T*, const int*, const T*, T*, T*, hipStream_t);                      \
+  template void launch_combine_a3b<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
+                                      const T*, const T*, const T*, const int*, const T*, const double*, double, \
+                                      T*, double*, hipStream_t);
+INST(float)
+INST(double)
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+
+}  // namespace lb

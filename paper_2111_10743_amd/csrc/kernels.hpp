@@ -1,0 +1,88 @@
+// Launch wrappers of the HIP kernels (plain pointers, stream ordered).
+#pragma once
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace lb {
+
+// FMM output sets at the targets (tree order), per right-hand side:
+//   FMM_POT : phi
+//   FMM_GRAD: phi, d/dx phi, d/dy phi, d/dz phi
+//   FMM_A3B : n.grad phi_1, phi_2, n.grad phi_2, n.gradgrad phi_2.n + n.grad phi_3
+//             (expansions per rhs: charge mu1, charge mu2, dipole mu2 * nu)
+// phi = sum_j c_j / |x - y_j| (no 1/(4 pi)).
+enum FmmMode { FMM_POT = 0, FMM_GRAD = 1, FMM_A3B = 2 };
+__host__ __device__ inline int fmm_nout(int mode) { return mode == FMM_POT ? 1 : 4; }
+__host__ __device__ inline int fmm_nexp(int mode) { return mode == FMM_A3B ? 3 : 1; }
+__host__ __device__ inline int fmm_nstr(int mode) { return mode == FMM_A3B ? 2 : 1; }
+
+template <typename T>
+struct DevTree {
+  // geometry in tree order
+  const T *tx, *ty, *tz, *tnx, *tny, *tnz;       // targets
+  const T *sx, *sy, *sz, *snx, *sny, *snz;       // sources
+  const T *rm2;                                  // squared mask radius per source
+  const T *bcx, *bcy, *bcz;                      // box centres [nbox]
+  const int *tgt_beg, *tgt_end, *src_beg, *src_end;  // per leaf
+  const int *ulist_ptr, *ulist;
+  const int *vlist_ptr, *vlist_src, *vlist_off;
+  const int *parent;
+  const int *child;                              // [nbox][8]
+  const int *leaf_tgt_list;  int n_leaf_tgt;     // leaves holding targets
+  const int *leaf_src_list;  int n_leaf_src;     // leaves holding sources
+  const int *lev_box_src;  const int *lev_box_src_ptr;  // per level: boxes with sources
+  const int *lev_box_tgt;  const int *lev_box_tgt_ptr;  // per level: boxes with targets
+  int depth, leaf_off, nbox;
+  int h_lev_src_ptr[24], h_lev_tgt_ptr[24];      // host copies of the level pointers
+  double side;               // root side
+  int p, L;                  // expansion order, (p+1)^2
+  const T *m2m, *l2l, *m2l;  // transposed [..][in][out]
+  const T *dgradT, *dhessT;  // transposed [t][in][out]
+};
+
+// strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities
+template <typename T>
+void launch_strengths(const T* tau, int ne, int64_t N, int NP, int n_p, int n_o, const T* P,
+                      const T* wo, const int* src_pos, int64_t No, T* str, hipStream_t st);
+
+// full FMM (or direct sums when depth < 2): str [nrhs*nstr][No] -> out [nrhs*nout][N]
+// nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_tgt][nrhs][nexp*3*p^2 + 6*(p-1)^2]
+template <typename T>
+void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
+                int64_t N, int64_t No, hipStream_t st);
+
+// corrections + combine (user order)
+// gradS: sigma [nd][N] -> pot/grad/dSdn/surf (each nullable except grad)
+template <typename T>
+void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                         const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
+                         const T* nrm, T* pot, T* grad, T* dSdn, T* surf, hipStream_t st);
+// A3 step 1: tau -> mu1 = S' tau, mu2 = S tau  (out arrays [nd][N])
+template <typename T>
+void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                        const T* vals3, const T* tau, const T* fmm, const int* tgt_pos,
+                        const T* nrm, T* mu1, T* mu2, hipStream_t st);
+// A3 step 2: out = -tau/4 + S'mu1 - (S''+D')mu2 - 2H S'mu2 + W S mu2
+template <typename T>
+void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                        const T* vals3, const T* tau, const T* mu1, const T* mu2, const T* fmm,
+                        const int* tgt_pos, const T* H, const double* w, double inv_area,
+                        T* out, double* partial, hipStream_t st);
+
+// FP64 helpers for GMRES
+void launch_dots(const double* V, int64_t ldv, int k, const double* w, int64_t N, double* out,
+                 double* partial, hipStream_t st);                 // out[j] = V_j . w, j < k
+void launch_gemv_sub(const double* V, int64_t ldv, int k, const double* h, double* w, int64_t N,
+                     hipStream_t st);                              // w -= V h
+void launch_gemv_add(const double* V, int64_t ldv, int k, const double* y, double* x, int64_t N,
+                     hipStream_t st);                              // x += V y
+void launch_scale_copy(const double* w, double a, double* v, int64_t N, hipStream_t st);  // v = a w
+void launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t N,
+                  hipStream_t st);                                 // z = a x + b y
+template <typename A, typename B>
+void launch_convert(const A* x, B* y, int64_t n, hipStream_t st);
+void launch_wmean(const double* f, const double* w, int64_t N, double* partial, double* out,
+                  hipStream_t st);                                 // out = sum w f
+void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipStream_t st);  // f -= scale*s[0]
+
+}  // namespace lb

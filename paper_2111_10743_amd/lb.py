@@ -1,0 +1,229 @@
+"""ctypes binding of liblb.so (include/lb.h): argument marshalling only.
+
+Device buffers are torch tensors on the current HIP device; every call is
+enqueued on torch's current stream.  The library must be built
+(``python -m paper_2111_10743_amd.build``); importing this module without it
+raises, there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblb.so")
+
+LB_OK = 0
+LB_ENOCONV = 1
+LB_EINVAL = -1
+LB_ENOMEM = -2
+LB_EHIP = -3
+LB_ENOTMEANZERO = -4
+LB_EGEOM = -5
+LB_PREC_FP32 = 32
+LB_PREC_FP64 = 64
+LB_SOLVE_FP64 = 0
+LB_SOLVE_FP32_REFINE = 1
+LB_STRICT_MEAN = 1
+LB_HOST_ONLY = 2
+LB_DIRECT = 4
+
+EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
+            "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_A3", "lb_solve",
+            "lb_destroy", "lb_last_error")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("eta_near", ctypes.c_double), ("over_q", ctypes.c_int), ("p_f32", ctypes.c_int),
+                ("p_f64", ctypes.c_int), ("leaf_src", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("flags", ctypes.c_int), ("self_n", ctypes.c_int), ("near_q", ctypes.c_int),
+                ("near_adm", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_steps", ctypes.c_int), ("rel_resid", ctypes.c_double),
+                ("removed_mean", ctypes.c_double)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_patches", "n_p", "N", "n_o", "N_o", "nnz_blocks",
+                                               "fmm_levels", "fmm_leaves", "p_f32", "p_f64")]
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2111_10743_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        L.lb_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.lb_ref_nodes.argtypes = [ip, dp, dp]
+        L.lb_setup.argtypes = [ctypes.POINTER(vp), ip, ip, dp, dp, dp, ctypes.POINTER(Opts), vp]
+        L.lb_get_sizes.argtypes = [vp, ctypes.POINTER(Sizes)]
+        L.lb_get_geometry.argtypes = [vp, dp, dp, dp]
+        L.lb_get_corrections.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp]
+        L.lb_apply_S.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_apply_gradS.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
+        L.lb_apply_A3.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
+        L.lb_destroy.argtypes = [vp]
+        L.lb_destroy.restype = None
+        L.lb_last_error.restype = ctypes.c_char_p
+        for n in EXPORTED:
+            if n not in ("lb_destroy", "lb_last_error"):
+                getattr(L, n).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code < 0:
+        raise LBError(code, lib().lb_last_error().decode())
+    return code
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def default_opts():
+    o = Opts()
+    _check(lib().lb_default_opts(ctypes.byref(o)))
+    return o
+
+
+def ref_nodes(order):
+    """(uv [n_p, 2], w_ref [n_p]) of the library's order-k node set."""
+    n_p = (order + 1) * (order + 2) // 2
+    uv = np.zeros((n_p, 2))
+    w = np.zeros(n_p)
+    _check(lib().lb_ref_nodes(order, _dp(uv), _dp(w)))
+    return uv, w
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Surface:
+    """One discretized surface: lb_setup ... lb_destroy."""
+
+    def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, **kw):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        Xu = np.ascontiguousarray(Xu, dtype=np.float64)
+        Xv = np.ascontiguousarray(Xv, dtype=np.float64)
+        o = opts if opts is not None else default_opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        if host_only:
+            o.flags |= LB_HOST_ONLY
+        if direct:
+            o.flags |= LB_DIRECT
+        self.order = order
+        self.host_only = host_only
+        self._ctx = ctypes.c_void_p()
+        stream = None if host_only else _stream()
+        _check(lib().lb_setup(ctypes.byref(self._ctx), X.shape[0], order, _dp(X), _dp(Xu), _dp(Xv),
+                              ctypes.byref(o), stream))
+        s = Sizes()
+        _check(lib().lb_get_sizes(self._ctx, ctypes.byref(s)))
+        self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
+        self.N = s.N
+
+    def close(self):
+        if self._ctx:
+            lib().lb_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def geometry(self):
+        w = np.zeros(self.N)
+        n = np.zeros((self.N, 3))
+        H = np.zeros(self.N)
+        _check(lib().lb_get_geometry(self._ctx, _dp(w), _dp(n), _dp(H)))
+        return w, n, H
+
+    def corrections(self):
+        nb = self.sizes["nnz_blocks"]
+        ptr = np.zeros(self.N + 1, dtype=np.int64)
+        patch = np.zeros(nb, dtype=np.int32)
+        vals = np.zeros((nb, self.sizes["n_p"], 6))
+        _check(lib().lb_get_corrections(self._ctx, ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        patch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(vals)))
+        return ptr, patch, vals
+
+    # -- device calls (torch tensors) --------------------------------------
+    @staticmethod
+    def _prec(t):
+        import torch
+        if t.dtype == torch.float32:
+            return LB_PREC_FP32
+        if t.dtype == torch.float64:
+            return LB_PREC_FP64
+        raise TypeError("density must be float32 or float64")
+
+    def _nd(self, t):
+        if not t.is_cuda or not t.is_contiguous() or t.numel() % self.N != 0:
+            raise ValueError("density must be a contiguous device tensor with a multiple of N elements")
+        return t.numel() // self.N
+
+    def apply_S(self, sigma, out=None):
+        import torch
+        nd = self._nd(sigma)
+        pot = out if out is not None else torch.empty_like(sigma)
+        _check(lib().lb_apply_S(self._ctx, nd, self._prec(sigma), _ptr(sigma), _ptr(pot), _stream()))
+        return pot
+
+    def apply_gradS(self, sigma, want=("pot", "grad", "dSdn", "surf_grad")):
+        import torch
+        nd = self._nd(sigma)
+        shape = sigma.shape
+        o = {}
+        o["grad"] = torch.empty(shape + (3,), dtype=sigma.dtype, device=sigma.device)
+        for k in ("pot", "dSdn"):
+            if k in want:
+                o[k] = torch.empty_like(sigma)
+        if "surf_grad" in want:
+            o["surf_grad"] = torch.empty(shape + (3,), dtype=sigma.dtype, device=sigma.device)
+        _check(lib().lb_apply_gradS(self._ctx, nd, self._prec(sigma), _ptr(sigma), _ptr(o.get("pot")),
+                                    _ptr(o["grad"]), _ptr(o.get("dSdn")), _ptr(o.get("surf_grad")), _stream()))
+        return o
+
+    def apply_A3(self, tau, out=None):
+        import torch
+        nd = self._nd(tau)
+        res = out if out is not None else torch.empty_like(tau)
+        _check(lib().lb_apply_A3(self._ctx, nd, self._prec(tau), _ptr(tau), _ptr(res), _stream()))
+        return res
+
+    def solve(self, f, tol=1e-10, mode=LB_SOLVE_FP64):
+        import torch
+        if f.dtype != torch.float64:
+            raise TypeError("f must be float64")
+        nrhs = self._nd(f)
+        u = torch.empty_like(f)
+        info = (SolveInfo * nrhs)()
+        code = _check(lib().lb_solve(self._ctx, nrhs, _ptr(f), _ptr(u), tol, mode, info, _stream()))
+        infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
+                  "removed_mean": i.removed_mean} for i in info]
+        return u, infos, code
