@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the S / grad S apply and the Laplace-Beltrami solve on one GPU.
+
+Workload (default): ellipsoid with semi-axes (1, 1.5, 2), icosahedral mesh
+split 4 times (5120 curved triangles, radial charts scaled), order 6
+(28 nodes per patch, N = 143,360), density = random band-limited spherical
+harmonic series (l <= 8, coefficients N(0,1) (l+1)^-2, seed 1) of the unit
+sphere pre-image.  Synthetic inputs, resident in HBM before timing.
+
+One "step" is one lb_apply_gradS in FP32 (density oversampling, FMM, near
+field, corrections, combination): value = N / step time in Mpoints/s.
+The JSON line also carries the FP64 apply rate, the solve times (with
+--solve), the dominant kernel against its roofline (HIP events on the
+library's stream) and the FP64 oracle timed on a bounded sample on the
+host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FMM S/∇S apply Mpts/s + LB solve time at 1e-9 rel err, FP32+refine vs FP64"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def workload(name):
+    import lbinputs as I
+    import paper_2111_10743_amd as P
+    if name == "ellipsoid5120":
+        k, nsub, axes = 6, 4, (1.0, 1.5, 2.0)
+    elif name == "ellipsoid1280":
+        k, nsub, axes = 6, 3, (1.0, 1.5, 2.0)
+    elif name == "sphere80":
+        k, nsub, axes = 4, 1, (1.0, 1.0, 1.0)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    uv, _ = P.ref_nodes(k)
+    X, Xu, Xv = I.ellipsoid_patches(nsub, uv, axes)
+    xi = I.sphere_preimage(X.reshape(-1, 3), axes)
+    coef = I.random_sh_coeffs(8, seed=1, decay=2.0)
+    f = I.sh_series(coef, xi)
+    desc = {"workload": f"{name}: ellipsoid axes {axes}, {X.shape[0]} order-{k} patches, N={X.shape[0] * uv.shape[0]}",
+            "patches": int(X.shape[0]), "order": k, "N": int(X.shape[0] * uv.shape[0]),
+            "density": "band-limited SH series l<=8, seed 1"}
+    return X, Xu, Xv, k, f, desc
+
+
+def cpu_baseline(X, Xu, Xv, k, f, nrows):
+    """The FP64 oracle's apply (far sum over all oversampled sources + near
+    corrections) on `nrows` sampled target rows, single thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    with threadpool_limits(limits=1):
+        g = Geometry(X, Xu, Xv, k)
+        rows = np.linspace(0, g.N - 1, nrows).astype(np.int64)
+        o = Oracle(g, rows, dense_limit=0)
+        t0 = time.perf_counter()
+        o.layer(f)
+        dt = time.perf_counter() - t0
+    return {"value": nrows / dt / 1e6, "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nrows} of {g.N} target rows: direct far sum over all {g.No} oversampled sources "
+                      f"+ near corrections (correction generation excluded), {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ellipsoid5120")
+    ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+refine solves")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part "
+              "of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2111_10743_amd as P
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    X, Xu, Xv, k, f, desc = workload(args.workload)
+    t0 = time.perf_counter()
+    s = P.Surface(X, Xu, Xv, k)
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] setup {t_setup:.1f} s sizes {s.sizes}", file=sys.stderr, flush=True)
+    N = s.N
+    x32 = torch.tensor(f, dtype=torch.float32, device="cuda")
+    x64 = torch.tensor(f, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    for _ in range(args.warmup):
+        s.apply_gradS(x32)
+    ms32 = timed(lambda: s.apply_gradS(x32), args.steps)
+    print(f"[bench] fp32 apply {ms32:.3f} ms", file=sys.stderr, flush=True)
+    # per-phase HIP-event timing of the same apply
+    ph = {}
+    nph = max(3, args.steps // 2)
+    for _ in range(nph):
+        _, t = s.apply_gradS_timed(x32)
+        for key, v in t.items():
+            ph[key] = ph.get(key, 0.0) + v / nph
+    print(f"[bench] fp32 phases (ms) {ph}", file=sys.stderr, flush=True)
+    s.apply_gradS(x64)
+    st64 = max(2, args.steps // 4)
+    ms64 = timed(lambda: s.apply_gradS(x64), st64)
+    print(f"[bench] fp64 apply {ms64:.3f} ms", file=sys.stderr, flush=True)
+    # FP32 result against FP64 (the FP64 path matches the oracle to ~1e-10)
+    o32 = s.apply_gradS(x32)
+    o64 = s.apply_gradS(x64)
+    e_pot = float((o32["pot"].double() - o64["pot"]).norm() / o64["pot"].norm())
+    e_grad = float((o32["grad"].double() - o64["grad"]).norm() / o64["grad"].norm())
+
+    # roofline of the dominant phase
+    sz = s.sizes
+    L32 = (sz["p_f32"] + 1) ** 2
+    dom = max(("m2l", "leaf", "combine"), key=lambda q: ph.get(q, 0.0))
+    if dom == "m2l":
+        flops = 2.0 * L32 * L32 * sz["m2l_pairs32"]
+        ach = flops / (ph["m2l"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_m2l (M2L, FP32)",
+                "algorithmic": f"2 L^2 flops per V-list pair, L={L32}, {sz['m2l_pairs32']} pairs"}
+    elif dom == "leaf":
+        flops = 20.0 * sz["p2p_pairs32"]
+        ach = flops / (ph["leaf"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_leaf (L2P + near field, FP32)",
+                "algorithmic": f"20 flops per near-field pair, {sz['p2p_pairs32']} pairs"}
+    else:
+        nnz = sz["nnz_blocks"] * sz["n_p"]
+        byts = nnz * 4 * 4 + sz["nnz_blocks"] * 4 + (N + 1) * 8 + nnz * 4 + N * 4 * (1 + 3 + 4)
+        ach = byts / (ph["combine"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": "k_combine_grad (corrections, FP32)",
+                "algorithmic": f"block-CSR bytes, nnz={nnz}"}
+    out = {
+        "metric": METRIC, "value": N / (ms32 * 1e-3) / 1e6, "unit": "Mpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict(desc, setup_s=round(t_setup, 2), p_f32=sz["p_f32"], p_f64=sz["p_f64"],
+                       fmm_levels=sz["fmm_levels"]),
+        "fp64_apply": {"value": N / (ms64 * 1e-3) / 1e6, "unit": "Mpts/s", "ms": ms64},
+        "fp32_vs_fp64_rel_l2": {"pot": e_pot, "grad": e_grad},
+        "phases_ms_fp32": ph,
+        "roofline": roof,
+    }
+    if args.solve:
+        fz = torch.tensor(f, dtype=torch.float64, device="cuda")
+        res = {}
+        us = {}
+        for name, mode in (("fp64", P.LB_SOLVE_FP64), ("fp32_refine", P.LB_SOLVE_FP32_REFINE)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, info, code = s.solve(fz, tol=1e-9, mode=mode)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            us[name] = u
+            res[name] = {"s": dt, "iters": info[0]["iters"], "outer_steps": info[0]["outer_steps"],
+                         "rel_resid": info[0]["rel_resid"], "status": code}
+            print(f"[bench] solve {name} {res[name]}", file=sys.stderr, flush=True)
+        w, _, _ = s.geometry()
+        w = torch.tensor(w, device="cuda")
+        d = us["fp32_refine"] - us["fp64"]
+        res["fp32_refine_vs_fp64_rel_l2"] = float(torch.sqrt((w * d * d).sum() / (w * us["fp64"] ** 2).sum()))
+        out["solve"] = res
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(X, Xu, Xv, k, f, args.cpu_rows)
+    s.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -64,9 +64,9 @@ typedef struct lb_ctx lb_ctx;   /* opaque: owns host and device state */
 typedef struct {
   double eta_near;  /* Near(x_i) = { l : |x_i - c_l| < eta_near * R_l }      (default 2)  */
   int over_q;       /* oversampled far rule: q x q conical Gauss points       (default k+6)*/
-  int p_f32;        /* FMM expansion order of the FP32 path                   (default 10) */
-  int p_f64;        /* FMM expansion order of the FP64 path                   (default 24) */
-  int leaf_src;     /* target mean number of sources per FMM leaf box         (default 256)*/
+  int p_f32;        /* FMM expansion order of the FP32 path                   (default 14) */
+  int p_f64;        /* FMM expansion order of the FP64 path                   (default 28) */
+  int leaf_src;     /* target mean sources per FMM leaf box, FP32 path (FP64: 4x) (default 256)*/
   int max_iter;     /* GMRES iteration cap per (inner) solve                  (default 100)*/
   int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT                           */
   int self_n;       /* self-patch rule: Gauss points along each Duffy ray    (default 16) */
@@ -87,6 +87,9 @@ typedef struct {
   int64_t nnz_blocks;             /* (target, near patch) pairs of the corrections */
   int64_t fmm_levels, fmm_leaves; /* octree depth and number of nonempty leaves */
   int64_t p_f32, p_f64;           /* expansion orders in use                     */
+  int64_t p2p_pairs32, m2l_pairs32; /* near-field (target, source) pairs and V-list
+                                       (target box, source box) pairs, FP32 tree */
+  int64_t p2p_pairs64, m2l_pairs64; /* the same for the FP64 tree               */
 } lb_sizes;
 
 /* Fill *opts with the defaults listed above. */
@@ -136,6 +139,14 @@ lb_status lb_apply_S(lb_ctx *ctx, int nd, int prec, const void *sigma, void *pot
 lb_status lb_apply_gradS(lb_ctx *ctx, int nd, int prec, const void *sigma,
                          void *pot, void *grad, void *dSdn, void *surf_grad,
                          void *stream);
+
+/* lb_apply_gradS with per-phase timing (nd <= 8): HIP events recorded on
+ * `stream` around each phase of the apply; synchronizes `stream`.
+ * phase_ms: host [7], milliseconds of: density oversampling, P2M, M2M, M2L,
+ * L2L, leaf evaluation (L2P + near-field sums), corrections + combination. */
+lb_status lb_apply_gradS_timed(lb_ctx *ctx, int nd, int prec, const void *sigma,
+                               void *pot, void *grad, void *dSdn, void *surf_grad,
+                               double *phase_ms, void *stream);
 
 /* The discretized A3 operator of eq. (ie-dis2), applied right to left as in
  * Section 4.3: out = -tau/4 + S'[S' tau] - (S''+D')[S tau] - 2H S'[S tau]

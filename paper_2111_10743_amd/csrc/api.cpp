@@ -66,9 +66,13 @@ struct Prec {
   DevTree<T> dt{};
   DBuf tx, ty, tz, tnx, tny, tnz, sx, sy, sz, snx, sny, snz, rm2, bcx, bcy, bcz;
   DBuf tgt_beg, tgt_end, src_beg, src_end, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off;
-  DBuf parent, child, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
+  DBuf parent, child, child_src, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
   DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
   DBuf m2m, l2l, m2l, dgrad, dhess;
+  // M2L plan
+  M2LPlan plan;
+  DBuf pl_grp_off, pl_grp_beg, pl_pair_src, pl_boxes, pl_box_level, pl_tptr, pl_tpairs, pl_Y;
+  DBuf pl_work[9];
   // work
   DBuf str, M, Lc, D, fmm, mu, tmp_in, tmp_out;
   int ws_rhs = 0;
@@ -101,8 +105,8 @@ namespace lb {
 static void default_opts(lb_opts* o) {
   o->eta_near = 2.0;
   o->over_q = 0;
-  o->p_f32 = 10;
-  o->p_f64 = 24;
+  o->p_f32 = 14;
+  o->p_f64 = 28;
   o->leaf_src = 256;
   o->max_iter = 100;
   o->flags = 0;
@@ -175,6 +179,12 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   upload(P.ulist_ptr, t.ulist_ptr); upload(P.ulist, t.ulist);
   upload(P.vlist_ptr, t.vlist_ptr); upload(P.vlist_src, t.vlist_src); upload(P.vlist_off, t.vlist_off);
   upload(P.parent, t.parent); upload(P.child, t.child);
+  {
+    std::vector<int> cs(t.child);
+    for (size_t i = 0; i < cs.size(); ++i)
+      if (cs[i] >= 0 && !t.has_src[cs[i]]) cs[i] = -1;
+    upload(P.child_src, cs);
+  }
   std::vector<int> lt, ls;
   const int nleaf = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
   for (int l = 0; l < nleaf; ++l) {
@@ -216,6 +226,55 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     transpose_blocks(tr.dgrad, 3, p * p, P.L, m); upload(P.dgrad, m);
     transpose_blocks(tr.dhess, 6, (p - 1) * (p - 1), P.L, m); upload(P.dhess, m);
   }
+  // M2L plan: all V-list pairs sorted by (offset, target box)
+  if (t.depth >= 2) {
+    struct PairRec { int off, tgt, src; };
+    std::vector<PairRec> pr;
+    std::vector<int> boxes, blev;
+    for (int l = 2; l <= t.depth; ++l)
+      for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+        if (!t.has_tgt[g]) continue;
+        boxes.push_back(g);
+        blev.push_back(l);
+        for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) pr.push_back({t.vlist_off[v], g, t.vlist_src[v]});
+      }
+    std::stable_sort(pr.begin(), pr.end(), [](const PairRec& a, const PairRec& b) {
+      return a.off != b.off ? a.off < b.off : a.tgt < b.tgt;
+    });
+    std::vector<int> goff, gbeg, psrc(pr.size());
+    for (size_t i = 0; i < pr.size(); ++i) {
+      psrc[i] = pr[i].src;
+      if (i == 0 || pr[i].off != pr[i - 1].off) { goff.push_back(pr[i].off); gbeg.push_back((int)i); }
+    }
+    gbeg.push_back((int)pr.size());
+    std::vector<int> slot(t.nbox(), -1);
+    for (size_t b = 0; b < boxes.size(); ++b) slot[boxes[b]] = (int)b;
+    std::vector<int> tptr(boxes.size() + 1, 0), tpairs(pr.size());
+    for (const PairRec& q : pr) tptr[slot[q.tgt] + 1]++;
+    for (size_t b = 0; b < boxes.size(); ++b) tptr[b + 1] += tptr[b];
+    std::vector<int> fill(tptr.begin(), tptr.end() - 1);
+    for (size_t i = 0; i < pr.size(); ++i) tpairs[fill[slot[pr[i].tgt]]++] = (int)i;
+    upload(P.pl_grp_off, goff); upload(P.pl_grp_beg, gbeg); upload(P.pl_pair_src, psrc);
+    upload(P.pl_boxes, boxes); upload(P.pl_box_level, blev); upload(P.pl_tptr, tptr); upload(P.pl_tpairs, tpairs);
+    M2LPlan& pl = P.plan;
+    pl.ngrp = (int)goff.size();
+    pl.npair = (int)pr.size();
+    pl.nbox = (int)boxes.size();
+    pl.grp_off = dptr<int>(P.pl_grp_off); pl.grp_beg = dptr<int>(P.pl_grp_beg);
+    pl.pair_src = dptr<int>(P.pl_pair_src);
+    pl.boxes = dptr<int>(P.pl_boxes); pl.box_level = dptr<int>(P.pl_box_level);
+    pl.tptr = dptr<int>(P.pl_tptr); pl.tpairs = dptr<int>(P.pl_tpairs);
+    for (int ne = 1; ne <= 8; ++ne) {
+      std::vector<int> w;
+      for (int g2 = 0; g2 < pl.ngrp; ++g2)
+        for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += 64) { w.push_back(g2); w.push_back(c0); }
+      upload(P.pl_work[ne], w);
+      pl.work[ne] = dptr<int>(P.pl_work[ne]);
+      pl.nwork[ne] = (int)(w.size() / 2);
+    }
+    P.pl_Y.alloc(sizeof(T) * (size_t)std::max(pl.npair, 1) * 8 * P.L);
+    pl.Y = P.pl_Y.p;
+  }
   // device tree descriptor
   DevTree<T>& D = P.dt;
   D.tx = dptr<T>(P.tx); D.ty = dptr<T>(P.ty); D.tz = dptr<T>(P.tz);
@@ -228,7 +287,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.src_beg = dptr<int>(P.src_beg); D.src_end = dptr<int>(P.src_end);
   D.ulist_ptr = dptr<int>(P.ulist_ptr); D.ulist = dptr<int>(P.ulist);
   D.vlist_ptr = dptr<int>(P.vlist_ptr); D.vlist_src = dptr<int>(P.vlist_src); D.vlist_off = dptr<int>(P.vlist_off);
-  D.parent = dptr<int>(P.parent); D.child = dptr<int>(P.child);
+  D.parent = dptr<int>(P.parent); D.child = dptr<int>(P.child); D.child_src = dptr<int>(P.child_src);
   D.leaf_tgt_list = dptr<int>(P.leaf_tgt); D.n_leaf_tgt = (int)lt.size();
   D.leaf_src_list = dptr<int>(P.leaf_src); D.n_leaf_src = (int)ls.size();
   D.lev_box_src = dptr<int>(P.lev_src); D.lev_box_src_ptr = dptr<int>(P.lev_src_ptr);
@@ -243,6 +302,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.L = P.L;
   D.m2m = dptr<T>(P.m2m); D.l2l = dptr<T>(P.l2l); D.m2l = dptr<T>(P.m2l);
   D.dgradT = dptr<T>(P.dgrad); D.dhessT = dptr<T>(P.dhess);
+  D.m2l_plan = t.depth >= 2 ? &P.plan : nullptr;
 }
 
 template <typename T>
@@ -258,25 +318,32 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
   P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
   P.ws_rhs = chunk;
-  ctx->partial.alloc(sizeof(double) * ((size_t)4 * ((N + 3) / 4) + 64));
+  // per-block partial sums: the A3 combine (4 per row block) and the GMRES
+  // dot products (256 blocks per basis vector)
+  ctx->partial.alloc(sizeof(double) * std::max<size_t>((size_t)4 * ((N + 3) / 4) + 64,
+                                                       (size_t)256 * (ctx->opts.max_iter + 2)));
 }
 
 constexpr int CHUNK_GRAD = 8;
 
 template <typename T>
 static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, T* grad, T* dSdn, T* surf,
-                          hipStream_t st) {
+                          hipStream_t st, PhaseTimer* tm = nullptr) {
   ensure_ws(ctx, P, CHUNK_GRAD);
   const int64_t N = ctx->N, No = ctx->No;
   for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
     const int c = std::min(CHUNK_GRAD, nd - d0);
+    if (tm) tm->mark(PH_STR, st);
     launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
                         dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
-    launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    if (tm) tm->mark(PH_P2M, st);
+    launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st, tm);
+    if (tm) tm->mark(PH_COMB, st);
     launch_combine_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
                            sigma + (int64_t)d0 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
                            pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
                            dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr, st);
+    if (tm) tm->mark(PH_N, st);
   }
 }
 
@@ -470,12 +537,14 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
   for (size_t i = 0; i < A.size(); ++i) ctx->C64[i] = A[i] - B[i];
   if (!ctx->host_only) {
     HIPTRY(hipGetDevice(&ctx->device));
-    // FP32 near-field mask: sources of patch l within (eta-1) R_l of a target
-    // are left to the corrections
+    // FP32 near-field mask: sources of patch l within kMaskFrac (eta-1) R_l
+    // of a target are left to the corrections (such a patch is always in
+    // Near(target), since |x - c_l| < (1 + (eta-1)) R_l)
+    const double kMaskFrac = 0.5;
     std::vector<float> rm2(S.No), tx32(3 * S.N), sx32(3 * S.No);
     double rmax = 0;
     for (int64_t m = 0; m < S.No; ++m) {
-      double rm = (o.eta_near - 1.0) * S.R[m / S.n_o];
+      double rm = kMaskFrac * (o.eta_near - 1.0) * S.R[m / S.n_o];
       rm2[m] = (float)(rm * rm);
       rmax = std::max(rmax, rm);
     }
@@ -495,7 +564,9 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
     const bool direct = (o.flags & LB_DIRECT) != 0;
     build_prec<float>(ctx.get(), ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
     // the float positions used by the mask test must be exactly the ones on the device
-    build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
+    // the FP64 path uses 4x larger leaves: its translations (order p_f64) cost
+    // more relative to the near-field sums
+    build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, 4 * o.leaf_src, direct);
     HIPTRY(hipDeviceSynchronize());
   }
   *out = ctx.release();
@@ -515,6 +586,21 @@ lb_status lb_get_sizes(const lb_ctx* ctx, lb_sizes* s) {
   s->fmm_leaves = ctx->host_only ? 0 : ctx->f32.dt.n_leaf_tgt;
   s->p_f32 = ctx->opts.p_f32;
   s->p_f64 = ctx->opts.p_f64;
+  s->p2p_pairs32 = s->m2l_pairs32 = s->p2p_pairs64 = s->m2l_pairs64 = 0;
+  if (!ctx->host_only) {
+    auto count = [](const Octree& t, int64_t& pp, int64_t& mp) {
+      pp = 0;
+      const int nleaf = (int)t.tgt_beg.size();
+      for (int b = 0; b < nleaf; ++b) {
+        int64_t ns = 0;
+        for (int u = t.ulist_ptr[b]; u < t.ulist_ptr[b + 1]; ++u) ns += t.src_end[t.ulist[u]] - t.src_beg[t.ulist[u]];
+        pp += ns * (t.tgt_end[b] - t.tgt_beg[b]);
+      }
+      mp = t.vlist_ptr.empty() ? 0 : t.vlist_ptr.back();
+    };
+    count(ctx->f32.tree, s->p2p_pairs32, s->m2l_pairs32);
+    count(ctx->f64.tree, s->p2p_pairs64, s->m2l_pairs64);
+  }
   API_END
 }
 
@@ -561,6 +647,32 @@ lb_status lb_apply_gradS(lb_ctx* ctx, int nd, int prec, const void* sigma, void*
     apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, (double*)grad, (double*)dSdn,
                           (double*)surf_grad, st);
   HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_apply_gradS_timed(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* grad,
+                               void* dSdn, void* surf_grad, double* phase_ms, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!sigma || !grad || !phase_ms) fail(LB_EINVAL, "null sigma, grad or phase_ms");
+  if (nd > CHUNK_GRAD) fail(LB_EINVAL, "timed apply takes at most %d densities", CHUNK_GRAD);
+  hipStream_t st = (hipStream_t)stream;
+  PhaseTimer tm;
+  tm.on = true;
+  for (int i = 0; i <= PH_N; ++i) HIPTRY(hipEventCreate(&tm.ev[i]));
+  if (prec == LB_PREC_FP32)
+    apply_gradS_t<float>(ctx, ctx->f32, nd, (const float*)sigma, (float*)pot, (float*)grad, (float*)dSdn,
+                         (float*)surf_grad, st, &tm);
+  else
+    apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, (double*)grad, (double*)dSdn,
+                          (double*)surf_grad, st, &tm);
+  HIPTRY(hipEventSynchronize(tm.ev[PH_N]));
+  for (int i = 0; i < PH_N; ++i) {
+    float ms = 0;
+    HIPTRY(hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]));
+    phase_ms[i] = ms;
+  }
+  for (int i = 0; i <= PH_N; ++i) (void)hipEventDestroy(tm.ev[i]);
   API_END
 }
 

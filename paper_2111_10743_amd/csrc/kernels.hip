@@ -133,12 +133,12 @@ __device__ __forceinline__ void rt_get(const T* re, const T* im, int n, int m, T
 // P2M: leaf sources -> multipole (charges and, in FMM_A3B, dipoles c * nu)
 // grid (leaves with sources, nrhs); M [nbox][nrhs*nexp][L]
 // ---------------------------------------------------------------------------
-constexpr int P2M_TS = 32;
+constexpr int P2M_TSMAX = 32;
 constexpr int KMAX = 4;  // L <= 1024
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, const T* __restrict__ str,
-                                             int64_t No, T* __restrict__ M) {
+                                             int64_t No, T* __restrict__ M, int P2M_TS) {
   extern __shared__ unsigned char smraw[];
   const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
   T* Rre = reinterpret_cast<T*>(smraw);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_m2m(DevTree<T> t, int l, int ne, T* __r
   for (int k = 0; k < KMAX; ++k)
     for (int e = 0; e < 8; ++e) acc[k][e] = 0;
   for (int oct = 0; oct < 8; ++oct) {
-    const int ch = t.child[(int64_t)g * 8 + oct];
+    const int ch = t.child_src[(int64_t)g * 8 + oct];
     if (ch < 0) continue;
     __syncthreads();
     for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = M[(int64_t)ch * ne * L + i];
@@ -276,6 +276,111 @@ __global__ __launch_bounds__(256) void k_m2l(DevTree<T> t, int l, int ne, const 
     const int r = threadIdx.x + k * 256;
     if (r < L)
       for (int e = 0; e < ne; ++e) Lc[((int64_t)g * ne + e) * L + r] = acc[k][e] * ih;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2L as batched GEMMs on the matrix cores.  All V-list pairs of all levels
+// are grouped by offset (the translation matrix depends only on the offset
+// in units of the box size): Y[:, c] = T_o M[src(c)] for every column c of
+// the group (one column per (pair, expansion)), then a per-box reduction sums
+// the columns of each target box and applies the level scale 1/h.
+// v_mfma_*_16x16x4: lane l holds A[l%16][l/16] and B[l/16][l%16]; the
+// result register v of lane l is D[4*(l/16)+v][l%16] for f32 and
+// D[l/16+4v][l%16] for f64 (checked on gfx950).
+// ---------------------------------------------------------------------------
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  typedef mf4 acc;
+  static __device__ __forceinline__ acc op(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma<double> {
+  typedef md4 acc;
+  static __device__ __forceinline__ acc op(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+constexpr int GM_COLS = 64;   // columns per block (4 waves x 16)
+constexpr int GM_RB = 8;      // 16-row blocks per block (128 rows)
+constexpr int GM_KC = 16;     // k chunk staged in LDS
+
+// work item w: (group, first column); group: offset id and column range
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_gemm(const T* __restrict__ TT, int L, const int* __restrict__ work,
+                                                  const int* __restrict__ grp_off, const int* __restrict__ grp_beg,
+                                                  const int* __restrict__ pair_src, int ne, const T* __restrict__ M,
+                                                  T* __restrict__ Y) {
+  __shared__ T As[GM_KC][GM_RB * 16];
+  __shared__ T Bs[GM_KC][GM_COLS];
+  __shared__ int srcrow[GM_COLS];
+  const int grp = work[2 * blockIdx.x];
+  const int c0 = work[2 * blockIdx.x + 1];
+  const int cend = grp_beg[grp + 1] * ne;
+  const int r0 = blockIdx.y * GM_RB * 16;
+  const T* Tm = TT + (int64_t)grp_off[grp] * L * L;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x < GM_COLS) {
+    const int c = c0 + threadIdx.x;
+    srcrow[threadIdx.x] = c < cend ? pair_src[c / ne] * ne + (c % ne) : -1;
+  }
+  typename Mfma<T>::acc acc[GM_RB];
+#pragma unroll
+  for (int rb = 0; rb < GM_RB; ++rb) acc[rb] = (typename Mfma<T>::acc){0, 0, 0, 0};
+  for (int k0 = 0; k0 < L; k0 += GM_KC) {
+    __syncthreads();
+    // A tile: As[kk][r] = T_o[r0 + r][k0 + kk] = TT[k0 + kk][r0 + r]
+    for (int i = threadIdx.x; i < GM_KC * GM_RB * 16; i += 256) {
+      const int kk = i / (GM_RB * 16), r = i - kk * (GM_RB * 16);
+      const int k = k0 + kk, rr = r0 + r;
+      As[kk][r] = (k < L && rr < L) ? Tm[(int64_t)k * L + rr] : (T)0;
+    }
+    // B tile: Bs[kk][c] = M[srcrow[c]][k0 + kk]
+    for (int i = threadIdx.x; i < GM_KC * GM_COLS; i += 256) {
+      const int c = i / GM_KC, kk = i - c * GM_KC;
+      const int k = k0 + kk;
+      const int sr = srcrow[c];
+      Bs[kk][c] = (sr >= 0 && k < L) ? M[(int64_t)sr * L + k] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GM_KC; kk += 4) {
+      const T b = Bs[kk + (lane >> 4)][wv * 16 + (lane & 15)];
+#pragma unroll
+      for (int rb = 0; rb < GM_RB; ++rb) {
+        const T a = As[kk + (lane >> 4)][rb * 16 + (lane & 15)];
+        acc[rb] = Mfma<T>::op(a, b, acc[rb]);
+      }
+    }
+  }
+  const int c = c0 + wv * 16 + (lane & 15);
+  if (c < cend) {
+#pragma unroll
+    for (int rb = 0; rb < GM_RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + rb * 16 + Mfma<T>::row(lane, v);
+        if (r < L) Y[(int64_t)c * L + r] = acc[rb][v];
+      }
+  }
+}
+
+// Lc[g][e][r] = (2^level / side) * sum over the pairs p of box g of Y[p*ne + e][r]
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_reduce(const int* __restrict__ boxes, const int* __restrict__ box_level,
+                                                    const int* __restrict__ tptr, const int* __restrict__ tpairs,
+                                                    int ne, int L, double side, const T* __restrict__ Y,
+                                                    T* __restrict__ Lc) {
+  const int g = boxes[blockIdx.x];
+  const T ih = (T)((double)(1 << box_level[blockIdx.x]) / side);
+  const int pb = tptr[blockIdx.x], pe = tptr[blockIdx.x + 1];
+  for (int i = threadIdx.x; i < ne * L; i += blockDim.x) {
+    const int e = i / L, r = i - e * L;
+    T a = 0;
+    for (int q = pb; q < pe; ++q) a += Y[((int64_t)tpairs[q] * ne + e) * L + r];
+    Lc[((int64_t)g * ne + e) * L + r] = a * ih;
   }
 }
 
@@ -440,6 +545,8 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       }
     }
     // ---- near field: U-list direct sums ----
+    // pairs are summed in T per source tile and the tile sums in FP64
+    double a0 = o0, a1 = o1, a2 = o2, a3 = o3;
     T* tx_ = tile;
     T* ty_ = tile + LEAF_BS;
     T* tz_ = tile + 2 * LEAF_BS;
@@ -471,6 +578,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         }
         __syncthreads();
         if (act) {
+          T q0 = 0, q1 = 0, q2 = 0, q3 = 0;
           for (int jj = 0; jj < ns; ++jj) {
             const T dx = X - tx_[jj];
             const T dy = Y - ty_[jj];
@@ -481,29 +589,31 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
             const T ri2 = ri * ri;
             const T ri3 = ri * ri2;
             if (MODE == FMM_POT) {
-              o0 += tq1_[jj] * ri;
+              q0 += tq1_[jj] * ri;
             } else if (MODE == FMM_GRAD) {
               const T q = tq1_[jj];
               const T qr3 = q * ri3;
-              o0 += q * ri;
-              o1 -= qr3 * dx;
-              o2 -= qr3 * dy;
-              o3 -= qr3 * dz;
+              q0 += q * ri;
+              q1 -= qr3 * dx;
+              q2 -= qr3 * dy;
+              q3 -= qr3 * dz;
             } else {
-              const T q1 = tq1_[jj], q2 = tq2_[jj];
+              const T c1 = tq1_[jj], c2 = tq2_[jj];
               const T nd = NX * dx + NY * dy + NZ * dz;
               const T mx = NX - tnx_[jj], my = NY - tny_[jj], mz = NZ - tnz_[jj];
               const T md = mx * dx + my * dy + mz * dz;
               const T nm = NX * mx + NY * my + NZ * mz;
-              o0 -= q1 * nd * ri3;
-              o1 += q2 * ri;
-              o2 -= q2 * nd * ri3;
-              o3 += q2 * ((T)3 * nd * md * ri3 * ri2 - nm * ri3);
+              q0 -= c1 * nd * ri3;
+              q1 += c2 * ri;
+              q2 -= c2 * nd * ri3;
+              q3 += c2 * ((T)3 * nd * md * ri3 * ri2 - nm * ri3);
             }
           }
+          a0 += (double)q0; a1 += (double)q1; a2 += (double)q2; a3 += (double)q3;
         }
       }
     }
+    o0 = (T)a0; o1 = (T)a1; o2 = (T)a2; o3 = (T)a3;
     if (act) {
       const int64_t base = (int64_t)rhs * nout * N;
       out[base + i] = o0;
@@ -518,13 +628,23 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
 
 template <typename T>
 void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
-                int64_t N, int64_t No, hipStream_t st) {
+                int64_t N, int64_t No, hipStream_t st, PhaseTimer* tm) {
+  PhaseTimer dummy;
+  if (!tm) tm = &dummy;
   const int p = t.p, L = t.L, Lc_ = (p + 1) * (p + 2) / 2;
   const int ne = nrhs * fmm_nexp(mode);
+  if (ne > 8) {
+    fprintf(stderr, "lb: launch_fmm called with %d expansions (max 8)\n", ne);
+    return;
+  }
   if (t.depth >= 2) {
-    size_t sm = sizeof(T) * (2 * P2M_TS * Lc_ + 5 * P2M_TS);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M);
+    // source tile of P2M: harmonic tables of ts sources within 48 KiB of LDS
+    int ts = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (2 * Lc_));
+    ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
+    size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
     KCHECK();
+    tm->mark(PH_M2M, st);
     const int* hp = t.h_lev_src_ptr;
     const int* ht = t.h_lev_tgt_ptr;
     size_t smv = sizeof(T) * ne * L;
@@ -533,17 +653,35 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
       if (nb > 0) hipLaunchKernelGGL(k_m2m<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M);
       KCHECK();
     }
-    for (int l = 2; l <= t.depth; ++l) {
-      int nb = ht[l + 1] - ht[l];
-      if (nb > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M, Lc);
+    tm->mark(PH_M2L, st);
+    if (t.m2l_plan && t.m2l_plan->nwork[ne] > 0) {
+      const M2LPlan& pl = *t.m2l_plan;
+      dim3 grid(pl.nwork[ne], (L + GM_RB * 16 - 1) / (GM_RB * 16));
+      hipLaunchKernelGGL(k_m2l_gemm<T>, grid, dim3(256), 0, st, t.m2l, L, pl.work[ne], pl.grp_off, pl.grp_beg,
+                         pl.pair_src, ne, M, (T*)pl.Y);
       KCHECK();
+      hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.box_level, pl.tptr,
+                         pl.tpairs, ne, L, t.side, (const T*)pl.Y, Lc);
+      KCHECK();
+    } else {
+      for (int l = 2; l <= t.depth; ++l) {
+        int nb = ht[l + 1] - ht[l];
+        if (nb > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M, Lc);
+        KCHECK();
+      }
     }
+    tm->mark(PH_L2L, st);
     for (int l = 3; l <= t.depth; ++l) {
       int nb = ht[l + 1] - ht[l];
       if (nb > 0) hipLaunchKernelGGL(k_l2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, Lc);
       KCHECK();
     }
+  } else {
+    tm->mark(PH_M2M, st);
+    tm->mark(PH_M2L, st);
+    tm->mark(PH_L2L, st);
   }
+  tm->mark(PH_LEAF, st);
   const int nexp = fmm_nexp(mode);
   size_t sml = sizeof(T) * 9 * LEAF_BS;
   dim3 grid(t.n_leaf_tgt, nrhs);
@@ -916,7 +1054,7 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
   template void launch_strengths<T>(const T*, int, int64_t, int, int, int, const T*, const T*, const int*,        \
                                     int64_t, T*, hipStream_t);                                                    \
   template void launch_fmm<T>(const DevTree<T>&, int, int, const T*, T*, T*, T*, T*, int64_t, int64_t,       \
-                              hipStream_t);                                                               \
+                              hipStream_t, PhaseTimer*);                                                  \
   template void launch_combine_grad<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,        \
                                        const T*, const int*, const T*, T*, T*, T*, T*, hipStream_t);             \
   template void launch_combine_a3a<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \

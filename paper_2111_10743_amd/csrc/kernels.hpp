@@ -16,6 +16,20 @@ __host__ __device__ inline int fmm_nout(int mode) { return mode == FMM_POT ? 1 :
 __host__ __device__ inline int fmm_nexp(int mode) { return mode == FMM_A3B ? 3 : 1; }
 __host__ __device__ inline int fmm_nstr(int mode) { return mode == FMM_A3B ? 2 : 1; }
 
+// M2L work plan: V-list pairs of all levels sorted by offset.  Column
+// tiles are 64 wide; work[ne] lists (group, first column) for ne
+// expansions per box (columns = pairs * ne).
+struct M2LPlan {
+  int ngrp = 0, npair = 0, nbox = 0;
+  const int *grp_off = nullptr, *grp_beg = nullptr;  // [ngrp], [ngrp+1] (pair index)
+  const int *pair_src = nullptr;                      // [npair] source box
+  const int *boxes = nullptr, *box_level = nullptr;   // [nbox] target boxes
+  const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
+  const int* work[9] = {nullptr};
+  int nwork[9] = {0};
+  void* Y = nullptr;                                  // [npair * 8][L] scratch
+};
+
 template <typename T>
 struct DevTree {
   // geometry in tree order
@@ -28,6 +42,7 @@ struct DevTree {
   const int *vlist_ptr, *vlist_src, *vlist_off;
   const int *parent;
   const int *child;                              // [nbox][8]
+  const int *child_src;                          // [nbox][8], -1 unless the child holds sources
   const int *leaf_tgt_list;  int n_leaf_tgt;     // leaves holding targets
   const int *leaf_src_list;  int n_leaf_src;     // leaves holding sources
   const int *lev_box_src;  const int *lev_box_src_ptr;  // per level: boxes with sources
@@ -38,6 +53,7 @@ struct DevTree {
   int p, L;                  // expansion order, (p+1)^2
   const T *m2m, *l2l, *m2l;  // transposed [..][in][out]
   const T *dgradT, *dhessT;  // transposed [t][in][out]
+  M2LPlan* m2l_plan;          // host struct with device pointers (nullable)
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities
@@ -46,10 +62,19 @@ void launch_strengths(const T* tau, int ne, int64_t N, int NP, int n_p, int n_o,
                       const T* wo, const int* src_pos, int64_t No, T* str, hipStream_t st);
 
 // full FMM (or direct sums when depth < 2): str [nrhs*nstr][No] -> out [nrhs*nout][N]
+// Optional phase timer: events recorded on the launch stream at the phase
+// boundaries of one apply (strengths | P2M | M2M | M2L | L2L | leaf | combine).
+enum Phase { PH_STR = 0, PH_P2M, PH_M2M, PH_M2L, PH_L2L, PH_LEAF, PH_COMB, PH_N };
+struct PhaseTimer {
+  hipEvent_t ev[PH_N + 1];
+  bool on = false;
+  void mark(int i, hipStream_t st) { if (on) (void)hipEventRecord(ev[i], st); }
+};
+
 // nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_tgt][nrhs][nexp*3*p^2 + 6*(p-1)^2]
 template <typename T>
 void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
-                int64_t N, int64_t No, hipStream_t st);
+                int64_t N, int64_t No, hipStream_t st, PhaseTimer* tm = nullptr);
 
 // corrections + combine (user order)
 // gradS: sigma [nd][N] -> pot/grad/dSdn/surf (each nullable except grad)

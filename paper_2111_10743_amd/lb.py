@@ -29,8 +29,9 @@ LB_HOST_ONLY = 2
 LB_DIRECT = 4
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
-            "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_A3", "lb_solve",
-            "lb_destroy", "lb_last_error")
+            "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_timed", "lb_apply_A3",
+            "lb_solve", "lb_destroy", "lb_last_error")
+PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
 class Opts(ctypes.Structure):
@@ -47,7 +48,8 @@ class SolveInfo(ctypes.Structure):
 
 class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_patches", "n_p", "N", "n_o", "N_o", "nnz_blocks",
-                                               "fmm_levels", "fmm_leaves", "p_f32", "p_f64")]
+                                               "fmm_levels", "fmm_leaves", "p_f32", "p_f64",
+                                               "p2p_pairs32", "m2l_pairs32", "p2p_pairs64", "m2l_pairs64")]
 
 
 class LBError(RuntimeError):
@@ -74,6 +76,7 @@ def lib():
         L.lb_get_corrections.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp]
         L.lb_apply_S.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_gradS.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
+        L.lb_apply_gradS_timed.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, dp, vp]
         L.lb_apply_A3.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_destroy.argtypes = [vp]
@@ -208,6 +211,18 @@ class Surface:
         _check(lib().lb_apply_gradS(self._ctx, nd, self._prec(sigma), _ptr(sigma), _ptr(o.get("pot")),
                                     _ptr(o["grad"]), _ptr(o.get("dSdn")), _ptr(o.get("surf_grad")), _stream()))
         return o
+
+    def apply_gradS_timed(self, sigma):
+        """apply_gradS plus per-phase milliseconds (HIP events on the stream)."""
+        import torch
+        nd = self._nd(sigma)
+        shape = sigma.shape
+        grad = torch.empty(shape + (3,), dtype=sigma.dtype, device=sigma.device)
+        pot = torch.empty_like(sigma)
+        ms = np.zeros(len(PHASES))
+        _check(lib().lb_apply_gradS_timed(self._ctx, nd, self._prec(sigma), _ptr(sigma), _ptr(pot), _ptr(grad),
+                                          None, None, _dp(ms), _stream()))
+        return {"pot": pot, "grad": grad}, dict(zip(PHASES, ms))
 
     def apply_A3(self, tau, out=None):
         import torch

@@ -3,8 +3,10 @@
 Cases (printed before each GPU step): the c1 sphere (80 order-4 patches,
 N = 1200) all rows, direct far sums and FMM, FP64 and FP32; a mid-size sphere
 (1280 patches) and ellipsoid on sampled rows through the FMM.  Tolerances:
-FP64 1e-9 relative L2 (the two correction generators agree to ~1e-10),
-FP32 1e-6 relative L2.
+FP64 1e-9 relative L2 (the two correction generators agree to ~1e-10 and the
+FP64 expansions are accurate to ~1e-10), FP32 1e-6 relative L2 on S and
+grad S; derived quantities (S' = n . grad S, A3) get the bound of their
+composition.
 """
 import sys
 
@@ -85,7 +87,9 @@ def test_c1_apply_A3(torch_dev, c1_oracle, prec):
     ref = o.A3(tau)
     e = rel_l2(out, ref)
     note(f"A3 error {e:.2e}")
-    assert e < (1e-9 if prec == 64 else 2e-6)
+    # A3 composes three layer applies (S', S and S''+D' of S tau): the FP32
+    # errors of the pieces (~1e-6 each, S' up to ~2e-6) add
+    assert e < (1e-9 if prec == 64 else 5e-6)
     s.close()
 
 
