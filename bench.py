@@ -125,7 +125,12 @@ def main():
     s.apply_gradS(x64)
     st64 = max(2, args.steps // 4)
     ms64 = timed(lambda: s.apply_gradS(x64), st64)
-    print(f"[bench] fp64 apply {ms64:.3f} ms", file=sys.stderr, flush=True)
+    ph64 = {}
+    for _ in range(2):
+        _, t = s.apply_gradS_timed(x64)
+        for key, v in t.items():
+            ph64[key] = ph64.get(key, 0.0) + v / 2
+    print(f"[bench] fp64 apply {ms64:.3f} ms phases {ph64}", file=sys.stderr, flush=True)
     # FP32 result against FP64 (the FP64 path matches the oracle to ~1e-10)
     o32 = s.apply_gradS(x32)
     o64 = s.apply_gradS(x64)
@@ -161,7 +166,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, setup_s=round(t_setup, 2), p_f32=sz["p_f32"], p_f64=sz["p_f64"],
                        fmm_levels=sz["fmm_levels"]),
-        "fp64_apply": {"value": N / (ms64 * 1e-3) / 1e6, "unit": "Mpts/s", "ms": ms64},
+        "fp64_apply": {"value": N / (ms64 * 1e-3) / 1e6, "unit": "Mpts/s", "ms": ms64, "phases_ms": ph64},
         "fp32_vs_fp64_rel_l2": {"pot": e_pot, "grad": e_grad},
         "phases_ms_fp32": ph,
         "roofline": roof,

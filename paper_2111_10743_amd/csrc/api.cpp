@@ -47,6 +47,58 @@ struct DBuf {
 };
 template <typename T> static inline T* dptr(const DBuf& b) { return reinterpret_cast<T*>(b.p); }
 
+struct PlanBuf {
+  GemmPlan pl;
+  DBuf grp_mat, grp_beg, pair_src, boxes, box_level, tptr, tpairs, work[9];
+};
+
+template <typename T>
+static void upload(DBuf& d, const std::vector<T>& h);
+
+// Triples (matrix id, target box, source box) -> GemmPlan; `boxes` lists every
+// target box that gets an output (boxes without triples get zeros unless
+// the plan accumulates).
+struct Triple { int mat, tgt, src; };
+static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<int>& boxes,
+                         const std::vector<int>& levels, bool scaled, bool accumulate, int nbox_total) {
+  std::stable_sort(tr.begin(), tr.end(), [](const Triple& a, const Triple& b) {
+    return a.mat != b.mat ? a.mat < b.mat : a.tgt < b.tgt;
+  });
+  std::vector<int> gmat, gbeg, psrc(tr.size());
+  for (size_t i = 0; i < tr.size(); ++i) {
+    psrc[i] = tr[i].src;
+    if (i == 0 || tr[i].mat != tr[i - 1].mat) { gmat.push_back(tr[i].mat); gbeg.push_back((int)i); }
+  }
+  gbeg.push_back((int)tr.size());
+  std::vector<int> slot(nbox_total, -1);
+  for (size_t b = 0; b < boxes.size(); ++b) slot[boxes[b]] = (int)b;
+  std::vector<int> tptr(boxes.size() + 1, 0), tpairs(tr.size());
+  for (const Triple& q : tr) tptr[slot[q.tgt] + 1]++;
+  for (size_t b = 0; b < boxes.size(); ++b) tptr[b + 1] += tptr[b];
+  std::vector<int> fill(tptr.begin(), tptr.end() - 1);
+  for (size_t i = 0; i < tr.size(); ++i) tpairs[fill[slot[tr[i].tgt]]++] = (int)i;
+  upload(pb.grp_mat, gmat); upload(pb.grp_beg, gbeg); upload(pb.pair_src, psrc);
+  upload(pb.boxes, boxes); upload(pb.box_level, levels); upload(pb.tptr, tptr); upload(pb.tpairs, tpairs);
+  GemmPlan& pl = pb.pl;
+  pl.ngrp = (int)gmat.size();
+  pl.npair = (int)tr.size();
+  pl.nbox = (int)boxes.size();
+  pl.grp_mat = dptr<int>(pb.grp_mat); pl.grp_beg = dptr<int>(pb.grp_beg); pl.pair_src = dptr<int>(pb.pair_src);
+  pl.boxes = dptr<int>(pb.boxes); pl.box_level = dptr<int>(pb.box_level);
+  pl.tptr = dptr<int>(pb.tptr); pl.tpairs = dptr<int>(pb.tpairs);
+  pl.scaled = scaled;
+  pl.accumulate = accumulate;
+  for (int ne = 1; ne <= 8; ++ne) {
+    std::vector<int> w;
+    for (int g2 = 0; g2 < pl.ngrp; ++g2)
+      for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += 64) { w.push_back(g2); w.push_back(c0); }
+    upload(pb.work[ne], w);
+    pl.work[ne] = dptr<int>(pb.work[ne]);
+    pl.nwork[ne] = (int)(w.size() / 2);
+  }
+  return tr.size();
+}
+
 template <typename T>
 static void upload(DBuf& d, const std::vector<T>& h) {
   d.alloc(sizeof(T) * std::max<size_t>(h.size(), 1));
@@ -69,10 +121,11 @@ struct Prec {
   DBuf parent, child, child_src, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
   DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
   DBuf m2m, l2l, m2l, dgrad, dhess;
-  // M2L plan
-  M2LPlan plan;
-  DBuf pl_grp_off, pl_grp_beg, pl_pair_src, pl_boxes, pl_box_level, pl_tptr, pl_tpairs, pl_Y;
-  DBuf pl_work[9];
+  // batched translation plans (M2L over all levels; M2M, L2L per level)
+  std::unique_ptr<PlanBuf> m2l_pb;
+  std::vector<std::unique_ptr<PlanBuf>> m2m_pb, l2l_pb;
+  std::vector<GemmPlan> m2m_pl, l2l_pl;
+  DBuf Y;
   // work
   DBuf str, M, Lc, D, fmm, mu, tmp_in, tmp_out;
   int ws_rhs = 0;
@@ -107,7 +160,7 @@ static void default_opts(lb_opts* o) {
   o->over_q = 0;
   o->p_f32 = 14;
   o->p_f64 = 28;
-  o->leaf_src = 256;
+  o->leaf_src = 1024;
   o->max_iter = 100;
   o->flags = 0;
   o->self_n = 16;
@@ -226,54 +279,63 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     transpose_blocks(tr.dgrad, 3, p * p, P.L, m); upload(P.dgrad, m);
     transpose_blocks(tr.dhess, 6, (p - 1) * (p - 1), P.L, m); upload(P.dhess, m);
   }
-  // M2L plan: all V-list pairs sorted by (offset, target box)
+  // batched translation plans
   if (t.depth >= 2) {
-    struct PairRec { int off, tgt, src; };
-    std::vector<PairRec> pr;
-    std::vector<int> boxes, blev;
-    for (int l = 2; l <= t.depth; ++l)
+    size_t maxcols = 1;
+    {
+      std::vector<Triple> tr;
+      std::vector<int> boxes, blev;
+      for (int l = 2; l <= t.depth; ++l)
+        for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+          if (!t.has_tgt[g]) continue;
+          boxes.push_back(g);
+          blev.push_back(l);
+          for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) tr.push_back({t.vlist_off[v], g, t.vlist_src[v]});
+        }
+      P.m2l_pb.reset(new PlanBuf());
+      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, tr, boxes, blev, true, false, t.nbox()));
+    }
+    P.m2m_pb.clear();
+    P.l2l_pb.clear();
+    P.m2m_pl.assign(t.depth + 1, GemmPlan());
+    P.l2l_pl.assign(t.depth + 1, GemmPlan());
+    for (int l = 0; l <= t.depth; ++l) {
+      P.m2m_pb.emplace_back(new PlanBuf());
+      P.l2l_pb.emplace_back(new PlanBuf());
+    }
+    for (int l = 2; l < t.depth; ++l) {  // M2M into level l from level l+1
+      std::vector<Triple> tr;
+      std::vector<int> boxes, blev;
       for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
-        if (!t.has_tgt[g]) continue;
+        if (!t.has_src[g]) continue;
         boxes.push_back(g);
         blev.push_back(l);
-        for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) pr.push_back({t.vlist_off[v], g, t.vlist_src[v]});
+        for (int c = 0; c < 8; ++c) {
+          int ch = t.child[(size_t)g * 8 + c];
+          if (ch >= 0 && t.has_src[ch]) tr.push_back({c, g, ch});
+        }
       }
-    std::stable_sort(pr.begin(), pr.end(), [](const PairRec& a, const PairRec& b) {
-      return a.off != b.off ? a.off < b.off : a.tgt < b.tgt;
-    });
-    std::vector<int> goff, gbeg, psrc(pr.size());
-    for (size_t i = 0; i < pr.size(); ++i) {
-      psrc[i] = pr[i].src;
-      if (i == 0 || pr[i].off != pr[i - 1].off) { goff.push_back(pr[i].off); gbeg.push_back((int)i); }
+      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], tr, boxes, blev, false, false, t.nbox()));
+      P.m2m_pl[l] = P.m2m_pb[l]->pl;
     }
-    gbeg.push_back((int)pr.size());
-    std::vector<int> slot(t.nbox(), -1);
-    for (size_t b = 0; b < boxes.size(); ++b) slot[boxes[b]] = (int)b;
-    std::vector<int> tptr(boxes.size() + 1, 0), tpairs(pr.size());
-    for (const PairRec& q : pr) tptr[slot[q.tgt] + 1]++;
-    for (size_t b = 0; b < boxes.size(); ++b) tptr[b + 1] += tptr[b];
-    std::vector<int> fill(tptr.begin(), tptr.end() - 1);
-    for (size_t i = 0; i < pr.size(); ++i) tpairs[fill[slot[pr[i].tgt]]++] = (int)i;
-    upload(P.pl_grp_off, goff); upload(P.pl_grp_beg, gbeg); upload(P.pl_pair_src, psrc);
-    upload(P.pl_boxes, boxes); upload(P.pl_box_level, blev); upload(P.pl_tptr, tptr); upload(P.pl_tpairs, tpairs);
-    M2LPlan& pl = P.plan;
-    pl.ngrp = (int)goff.size();
-    pl.npair = (int)pr.size();
-    pl.nbox = (int)boxes.size();
-    pl.grp_off = dptr<int>(P.pl_grp_off); pl.grp_beg = dptr<int>(P.pl_grp_beg);
-    pl.pair_src = dptr<int>(P.pl_pair_src);
-    pl.boxes = dptr<int>(P.pl_boxes); pl.box_level = dptr<int>(P.pl_box_level);
-    pl.tptr = dptr<int>(P.pl_tptr); pl.tpairs = dptr<int>(P.pl_tpairs);
-    for (int ne = 1; ne <= 8; ++ne) {
-      std::vector<int> w;
-      for (int g2 = 0; g2 < pl.ngrp; ++g2)
-        for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += 64) { w.push_back(g2); w.push_back(c0); }
-      upload(P.pl_work[ne], w);
-      pl.work[ne] = dptr<int>(P.pl_work[ne]);
-      pl.nwork[ne] = (int)(w.size() / 2);
+    for (int l = 3; l <= t.depth; ++l) {  // L2L into level l from level l-1
+      std::vector<Triple> tr;
+      std::vector<int> boxes, blev;
+      for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+        if (!t.has_tgt[g]) continue;
+        const int pg = t.parent[g];
+        int oct = -1;
+        for (int c = 0; c < 8; ++c)
+          if (t.child[(size_t)pg * 8 + c] == g) oct = c;
+        if (oct < 0) fail(LB_EINVAL, "octree: box %d missing from its parent", g);
+        boxes.push_back(g);
+        blev.push_back(l);
+        tr.push_back({oct, g, pg});
+      }
+      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], tr, boxes, blev, false, true, t.nbox()));
+      P.l2l_pl[l] = P.l2l_pb[l]->pl;
     }
-    P.pl_Y.alloc(sizeof(T) * (size_t)std::max(pl.npair, 1) * 8 * P.L);
-    pl.Y = P.pl_Y.p;
+    P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);
   }
   // device tree descriptor
   DevTree<T>& D = P.dt;
@@ -302,7 +364,10 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.L = P.L;
   D.m2m = dptr<T>(P.m2m); D.l2l = dptr<T>(P.l2l); D.m2l = dptr<T>(P.m2l);
   D.dgradT = dptr<T>(P.dgrad); D.dhessT = dptr<T>(P.dhess);
-  D.m2l_plan = t.depth >= 2 ? &P.plan : nullptr;
+  D.m2l_plan = t.depth >= 2 ? &P.m2l_pb->pl : nullptr;
+  D.m2m_plan = t.depth >= 2 ? P.m2m_pl.data() : nullptr;
+  D.l2l_plan = t.depth >= 2 ? P.l2l_pl.data() : nullptr;
+  D.Y = P.Y.p;
 }
 
 template <typename T>
@@ -314,7 +379,7 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   P.str.alloc(sizeof(T) * (size_t)No * 2 * chunk);
   P.M.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
   P.Lc.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
-  P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_tgt, 1) * chunk * (3 * 3 * p * p + 6 * (p - 1) * (p - 1)));
+  P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_tgt, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1)));
   P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
   P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
   P.ws_rhs = chunk;

@@ -37,6 +37,10 @@ template <> __device__ __forceinline__ double dev_fma<double>(double a, double b
 
 __device__ __forceinline__ int cidx(int n, int m) { return n * (n + 1) / 2 + m; }
 
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
 // real layout index -> (n, m, part) with part 0 = Re, 1 = Im
 __device__ __forceinline__ void rdecode(int c, int& n, int& m, int& part) {
   n = (int)sqrtf((float)c + 0.5f);
@@ -119,6 +123,39 @@ __device__ void regular_to_lds(int p, T x, T y, T z, T* re, T* im) {
   }
 }
 
+// Column m of the normalized regular harmonics, Rt_n^m for n = m..p, into
+// LDS rows (re, im).  Rt_m^m = prod_{j<=m} (-(x+iy) sqrt((2j-1)/(2j))).
+template <typename T>
+__device__ void regular_column_to_lds(int p, int m, T x, T y, T z, T* re, T* im) {
+  const T r2 = x * x + y * y + z * z;
+  T mre = 1, mim = 0;
+  for (int j = 1; j <= m; ++j) {
+    const T f = -sqrt((T)(2 * j - 1) / (T)(2 * j));
+    const T nr = f * (x * mre - y * mim);
+    const T ni = f * (x * mim + y * mre);
+    mre = nr;
+    mim = ni;
+  }
+  re[cidx(m, m)] = mre;
+  im[cidx(m, m)] = mim;
+  if (m + 1 > p) return;
+  const T c1 = z * sqrt((T)(2 * m + 1));
+  T are = mre, aim = mim, bre = c1 * mre, bim = c1 * mim;
+  re[cidx(m + 1, m)] = bre;
+  im[cidx(m + 1, m)] = bim;
+  for (int n = m + 1; n < p; ++n) {
+    const T f1 = (T)(2 * n + 1) * z;
+    const T f2 = r2 * sqrt((T)((n + m) * (n - m)));
+    const T dn = (T)1 / sqrt((T)((n + 1 + m) * (n + 1 - m)));
+    const T cre = (f1 * bre - f2 * are) * dn;
+    const T cim = (f1 * bim - f2 * aim) * dn;
+    re[cidx(n + 1, m)] = cre;
+    im[cidx(n + 1, m)] = cim;
+    are = bre; aim = bim;
+    bre = cre; bim = cim;
+  }
+}
+
 // Rt_n^m for any m in [-n, n] from an LDS row of m >= 0 values
 template <typename T>
 __device__ __forceinline__ void rt_get(const T* re, const T* im, int n, int m, T& a, T& b) {
@@ -160,10 +197,16 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
   const int beg = t.src_beg[b], end = t.src_end[b];
   for (int t0 = beg; t0 < end; t0 += P2M_TS) {
     const int nt = min(P2M_TS, end - t0);
-    const int j = threadIdx.x;
-    if (j < nt) {
+    // harmonic tables of the tile: one thread per (source, column m)
+    for (int task = threadIdx.x; task < nt * (p + 1); task += blockDim.x) {
+      const int j = task / (p + 1), m = task - j * (p + 1);
       const int s = t0 + j;
-      regular_to_lds<T>(p, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc, Rim + j * Lc);
+      regular_column_to_lds<T>(p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
+                               Rim + j * Lc);
+    }
+    if (threadIdx.x < nt) {
+      const int j = threadIdx.x;
+      const int s = t0 + j;
       for (int q = 0; q < nstr; ++q) sq[q * P2M_TS + j] = str[(int64_t)(rhs * nstr + q) * No + s];
       sn[j] = t.snx[s];
       sn[P2M_TS + j] = t.sny[s];
@@ -309,10 +352,10 @@ constexpr int GM_KC = 16;     // k chunk staged in LDS
 
 // work item w: (group, first column); group: offset id and column range
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_gemm(const T* __restrict__ TT, int L, const int* __restrict__ work,
-                                                  const int* __restrict__ grp_off, const int* __restrict__ grp_beg,
-                                                  const int* __restrict__ pair_src, int ne, const T* __restrict__ M,
-                                                  T* __restrict__ Y) {
+__global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, int L, const int* __restrict__ work,
+                                                      const int* __restrict__ grp_off, const int* __restrict__ grp_beg,
+                                                      const int* __restrict__ pair_src, int ne, const T* __restrict__ M,
+                                                      T* __restrict__ Y) {
   __shared__ T As[GM_KC][GM_RB * 16];
   __shared__ T Bs[GM_KC][GM_COLS];
   __shared__ int srcrow[GM_COLS];
@@ -367,21 +410,38 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const T* __restrict__ TT, int 
   }
 }
 
-// Lc[g][e][r] = (2^level / side) * sum over the pairs p of box g of Y[p*ne + e][r]
+// out[g][e][r] (+)= f_g * sum over the triples p of box g of Y[p*ne + e][r],
+// f_g = 2^level / side when scaled, else 1
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_reduce(const int* __restrict__ boxes, const int* __restrict__ box_level,
+__global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxes, const int* __restrict__ box_level,
                                                     const int* __restrict__ tptr, const int* __restrict__ tpairs,
-                                                    int ne, int L, double side, const T* __restrict__ Y,
-                                                    T* __restrict__ Lc) {
+                                                    int ne, int L, double side, int scaled, int accumulate,
+                                                    const T* __restrict__ Y, T* __restrict__ out) {
   const int g = boxes[blockIdx.x];
-  const T ih = (T)((double)(1 << box_level[blockIdx.x]) / side);
+  const T f = scaled ? (T)((double)(1 << box_level[blockIdx.x]) / side) : (T)1;
   const int pb = tptr[blockIdx.x], pe = tptr[blockIdx.x + 1];
   for (int i = threadIdx.x; i < ne * L; i += blockDim.x) {
     const int e = i / L, r = i - e * L;
     T a = 0;
     for (int q = pb; q < pe; ++q) a += Y[((int64_t)tpairs[q] * ne + e) * L + r];
-    Lc[((int64_t)g * ne + e) * L + r] = a * ih;
+    const int64_t o = ((int64_t)g * ne + e) * L + r;
+    out[o] = accumulate ? out[o] + a * f : a * f;
   }
+}
+
+template <typename T>
+static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, double side, const T* X, T* Y, T* out,
+                     hipStream_t st) {
+  if (pl.nbox == 0) return;
+  if (pl.nwork[ne] > 0) {
+    dim3 grid(pl.nwork[ne], (L + GM_RB * 16 - 1) / (GM_RB * 16));
+    hipLaunchKernelGGL(k_gemm_grouped<T>, grid, dim3(256), 0, st, TT, L, pl.work[ne], pl.grp_mat, pl.grp_beg,
+                       pl.pair_src, ne, X, Y);
+    KCHECK();
+  }
+  hipLaunchKernelGGL(k_col_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.box_level, pl.tptr, pl.tpairs,
+                     ne, L, side, pl.scaled ? 1 : 0, pl.accumulate ? 1 : 0, (const T*)Y, out);
+  KCHECK();
 }
 
 // L2L: grid = boxes with targets on level l (l >= 3); Lc[g] += TT[oct] Lc[parent]
@@ -412,9 +472,58 @@ __global__ __launch_bounds__(256) void k_l2l(DevTree<T> t, int l, int ne, T* __r
 // leaf evaluation: L2P (far) + direct sums over the U-list (near)
 // grid (leaves with targets, nrhs); out [nrhs*nout][N] in target tree order
 // ---------------------------------------------------------------------------
-constexpr int LEAF_BS = 128;
+// Coefficient (n, m), any m in [-n, n], of a real-layout conjugate-symmetric
+// expansion (see harmonics.hpp).
+template <typename T>
+__device__ __forceinline__ void coef_get(const T* v, int n, int m, T& re, T& im) {
+  if (n < 0 || m < -n || m > n) { re = 0; im = 0; return; }
+  const int am = m < 0 ? -m : m;
+  re = am == 0 ? v[n * n] : v[n * n + 2 * am - 1];
+  im = am == 0 ? (T)0 : v[n * n + 2 * am];
+  if (m < 0) {
+    const T sg = (am & 1) ? (T)-1 : (T)1;
+    re = sg * re;
+    im = -sg * im;
+  }
+}
 
-template <typename T, int MODE>
+// d/dx, d/dy, d/dz of a local expansion of order pin (unit box), written as
+// expansions of order pin-1; the block's threads share the outputs.
+//   d/dz: Lz_n^m = L_{n+1}^m sqrt((n+1+m)(n+1-m))
+//   (d/dx + i d/dy): E_n^m = L_{n+1}^{m-1} sqrt((n-m+2)(n-m+1))
+//   (d/dx - i d/dy): F_n^m = -L_{n+1}^{m+1} sqrt((n+m+2)(n+m+1))
+template <typename T>
+__device__ void derive3(const T* src, int pin, T* dx, T* dy, T* dz) {
+  const int Lo = pin * pin;
+  for (int c = threadIdx.x; c < Lo; c += blockDim.x) {
+    int n, m, part;
+    rdecode(c, n, m, part);
+    T ar, ai, br, bi, cr, ci;
+    coef_get(src, n + 1, m, ar, ai);
+    coef_get(src, n + 1, m - 1, br, bi);
+    coef_get(src, n + 1, m + 1, cr, ci);
+    const T fz = sqrt((T)((n + 1 + m) * (n + 1 - m)));
+    const T fe = sqrt((T)((n - m + 2) * (n - m + 1)));
+    const T ff = -sqrt((T)((n + m + 2) * (n + m + 1)));
+    const T er = fe * br, ei = fe * bi, gr = ff * cr, gi = ff * ci;
+    // Gx = (E + F)/2, Gy = -i (E - F)/2
+    const T xr = (T)0.5 * (er + gr), xi = (T)0.5 * (ei + gi);
+    const T yr = (T)0.5 * (ei - gi), yi = -(T)0.5 * (er - gr);
+    dx[c] = part ? xi : xr;
+    dy[c] = part ? yi : yr;
+    dz[c] = part ? fz * ai : fz * ar;
+  }
+}
+
+constexpr int LEAF_BS = 256;
+constexpr int LEAF_FMAX = 8;                   // at most 8 threads per target
+
+// Each target of a leaf gets F = min(8, 256 / targets) threads (a power of
+// two): thread (slot, f) works for target slot `slot` of the current pass,
+// the far field over the harmonic orders m = f (mod F), the near field over
+// the source indices j = f (mod F) of each LDS chunk; the F partial sums of
+// a target (contiguous lanes) are then added by shuffles.
+template <typename T, int MODE, bool EXP_LDS>
 __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str,
                                                   int64_t No, const T* __restrict__ Lc, T* __restrict__ D,
                                                   T* __restrict__ out, int64_t N) {
@@ -425,47 +534,80 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   const int p = t.p, L = t.L, Lg = p * p, Lh = (p - 1) * (p - 1);
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
   const bool far = t.depth >= 2;
-  // expansions for L2P, read with wave-uniform addresses: local [nexp][L] in
-  // Lc; derived gradient [nexp][3][Lg] and hessian [6][Lh] (A3B: expansion 1)
-  // in this block's slice of D
-  const T* sL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
-  const int64_t dstride = (int64_t)nexp * 3 * Lg + 6 * Lh;
-  T* sG = D + ((int64_t)blockIdx.x * nrhs + rhs) * dstride;
+  const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
+  int F = LEAF_FMAX;
+  while (F > 1 && F * (tend - tbeg) > LEAF_BS) F >>= 1;
+  const int TPB = LEAF_BS / F;
+  const int slot = threadIdx.x / F, f = threadIdx.x % F;
+  // expansions for L2P: local [nexp][L], derived gradient [nexp][3][Lg] and
+  // hessian [6][Lh] (+ 3 [Lh] scratch; A3B: expansion 1), in LDS after the
+  // source chunk when EXP_LDS, else in this block's slice of D
+  constexpr int LEAF_CH = 512;                     // sources per LDS chunk
+  constexpr int REC = MODE == FMM_A3B ? 9 : 5;       // T values per source record
+  T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
+  const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
+  const int64_t dstride = (int64_t)nexp * 3 * Lg + 9 * Lh;
+  T* sL;
+  T* sG;
+  if (EXP_LDS) {
+    sL = tile + REC * LEAF_CH;
+    sG = sL + nexp * L;
+  } else {
+    sL = const_cast<T*>(gL);
+    sG = D + ((int64_t)blockIdx.x * nrhs + rhs) * dstride;
+  }
   T* sH = sG + nexp * 3 * Lg;
-  T* tile = reinterpret_cast<T*>(smraw);  // [9][LEAF_BS]: x, y, z, nx, ny, nz, rm2, q1, q2
   if (far) {
-    const bool need_grad = MODE != FMM_POT;
-    if (need_grad) {
-      for (int i = threadIdx.x; i < nexp * 3 * Lg; i += blockDim.x) {
-        const int e = i / (3 * Lg), rr = i - e * 3 * Lg, comp = rr / Lg, r = rr - comp * Lg;
-        const T* Dm = t.dgradT + (int64_t)comp * L * Lg;
-        T a = 0;
-        for (int c = 0; c < L; ++c) a += Dm[(int64_t)c * Lg + r] * sL[e * L + c];
-        sG[i] = a;
-      }
+    if (EXP_LDS) {
+      for (int i = threadIdx.x; i < nexp * L; i += blockDim.x) sL[i] = gL[i];
+      __syncthreads();
+    }
+    if (MODE != FMM_POT) {
+      for (int e = 0; e < nexp; ++e)
+        derive3(sL + e * L, p, sG + (e * 3 + 0) * Lg, sG + (e * 3 + 1) * Lg, sG + (e * 3 + 2) * Lg);
     }
     if (MODE == FMM_A3B) {
-      for (int i = threadIdx.x; i < 6 * Lh; i += blockDim.x) {
-        const int comp = i / Lh, r = i - comp * Lh;
-        const T* Dm = t.dhessT + (int64_t)comp * L * Lh;
-        T a = 0;
-        for (int c = 0; c < L; ++c) a += Dm[(int64_t)c * Lh + r] * sL[1 * L + c];
-        sH[i] = a;
-      }
+      // second derivatives of expansion 1 from its gradient expansions; the
+      // scratch after sH receives the unused d/dx of d/dy and d/dx, d/dy of d/dz
+      __syncthreads();
+      T* tmp = sH + 6 * Lh;
+      const T* gx = sG + 3 * Lg;
+      const T* gy = sG + 4 * Lg;
+      const T* gz = sG + 5 * Lg;
+      derive3(gx, p - 1, sH, sH + Lh, sH + 2 * Lh);          // xx, xy, xz
+      derive3(gy, p - 1, tmp, sH + 3 * Lh, sH + 4 * Lh);     // (yx), yy, yz
+      derive3(gz, p - 1, tmp + Lh, tmp + 2 * Lh, sH + 5 * Lh);  // (zx), (zy), zz
     }
     __syncthreads();
   }
   const T h = (T)(t.side / (double)(1 << t.depth));
   const T ih = (T)1 / h;
   const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
-  const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
-  for (int i0 = tbeg; i0 < tend; i0 += LEAF_BS) {
-    const int i = i0 + threadIdx.x;
+  // source records in LDS: (x, y, z, q1), (nx, ny, nz, q2) and rm2
+  typedef typename Vec4<T>::type T4;
+  T4* rec1 = reinterpret_cast<T4*>(tile);
+  T4* rec2 = rec1 + LEAF_CH;                                                   // A3B only
+  T* trm_ = reinterpret_cast<T*>(rec1 + (MODE == FMM_A3B ? 2 : 1) * LEAF_CH);
+  __shared__ int upref[28];
+  const int u0 = t.ulist_ptr[b], nU = t.ulist_ptr[b + 1] - u0;
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int k = 0; k < nU; ++k) {
+      upref[k] = acc;
+      const int nb = t.ulist[u0 + k];
+      acc += t.src_end[nb] - t.src_beg[nb];
+    }
+    upref[nU] = acc;
+  }
+  __syncthreads();
+  const int utot = upref[nU];
+  for (int i0 = tbeg; i0 < tend; i0 += TPB) {
+    const int i = i0 + slot;
     const bool act = i < tend;
     T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0;
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
-    T o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-    // ---- far field: evaluate local expansions at xi = (x - c)/h ----
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    // ---- far field: local expansions at xi = (x - c)/h, orders m = f mod F ----
     if (far && act) {
       const T x = (X - cx) * ih, y = (Y - cy) * ih, z = (Z - cz) * ih;
       const T r2 = x * x + y * y + z * z;
@@ -473,11 +615,12 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       T mre = 1, mim = 0;
       for (int m = 0; m <= p; ++m) {
         if (m > 0) {
-          T f = -sqrt((T)(2 * m - 1) / (T)(2 * m));
-          T nr = f * (x * mre - y * mim);
-          T ni = f * (x * mim + y * mre);
+          T fm = -sqrt((T)(2 * m - 1) / (T)(2 * m));
+          T nr = fm * (x * mre - y * mim);
+          T ni = fm * (x * mim + y * mre);
           mre = nr; mim = ni;
         }
+        if (m % F != f) continue;
         T are = 0, aim = 0, bre = mre, bim = mim;  // R_{n-1}, R_n with n = m
         for (int n = m; n <= p; ++n) {
           if (n > m) {
@@ -495,7 +638,6 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
             }
             are = bre; aim = bim; bre = cre; bim = cim;
           }
-          // rho entries of (n, m)
           T rre, rim;
           int ire, iim;
           if (m == 0) { rre = bre; rim = 0; ire = n * n; iim = -1; }
@@ -532,95 +674,103 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         }
       }
       if (MODE == FMM_POT) {
-        o0 = pot;
+        a0 = pot;
       } else if (MODE == FMM_GRAD) {
-        o0 = pot; o1 = g1[0] * ih; o2 = g1[1] * ih; o3 = g1[2] * ih;
+        a0 = pot; a1 = g1[0] * ih; a2 = g1[1] * ih; a3 = g1[2] * ih;
       } else {
-        o0 = (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
-        o1 = pot;
-        o2 = (NX * g2[0] + NY * g2[1] + NZ * g2[2]) * ih;
+        a0 = (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
+        a1 = pot;
+        a2 = (NX * g2[0] + NY * g2[1] + NZ * g2[2]) * ih;
         T nhn = NX * NX * hs[0] + 2 * NX * NY * hs[1] + 2 * NX * NZ * hs[2] + NY * NY * hs[3] +
                 2 * NY * NZ * hs[4] + NZ * NZ * hs[5];
-        o3 = nhn * ih * ih + (NX * g3[0] + NY * g3[1] + NZ * g3[2]) * ih;
+        a3 = nhn * ih * ih + (NX * g3[0] + NY * g3[1] + NZ * g3[2]) * ih;
       }
     }
-    // ---- near field: U-list direct sums ----
-    // pairs are summed in T per source tile and the tile sums in FP64
-    double a0 = o0, a1 = o1, a2 = o2, a3 = o3;
-    T* tx_ = tile;
-    T* ty_ = tile + LEAF_BS;
-    T* tz_ = tile + 2 * LEAF_BS;
-    T* tnx_ = tile + 3 * LEAF_BS;
-    T* tny_ = tile + 4 * LEAF_BS;
-    T* tnz_ = tile + 5 * LEAF_BS;
-    T* trm_ = tile + 6 * LEAF_BS;
-    T* tq1_ = tile + 7 * LEAF_BS;
-    T* tq2_ = tile + 8 * LEAF_BS;
-    for (int u = t.ulist_ptr[b]; u < t.ulist_ptr[b + 1]; ++u) {
-      const int nb = t.ulist[u];
-      const int sb = t.src_beg[nb], se = t.src_end[nb];
-      for (int s0 = sb; s0 < se; s0 += LEAF_BS) {
-        const int ns = min(LEAF_BS, se - s0);
-        __syncthreads();
-        if (threadIdx.x < ns) {
-          const int s = s0 + threadIdx.x;
-          tx_[threadIdx.x] = t.sx[s];
-          ty_[threadIdx.x] = t.sy[s];
-          tz_[threadIdx.x] = t.sz[s];
-          trm_[threadIdx.x] = t.rm2[s];
-          tq1_[threadIdx.x] = str[(int64_t)(rhs * nstr) * No + s];
-          if (MODE == FMM_A3B) {
-            tq2_[threadIdx.x] = str[(int64_t)(rhs * nstr + 1) * No + s];
-            tnx_[threadIdx.x] = t.snx[s];
-            tny_[threadIdx.x] = t.sny[s];
-            tnz_[threadIdx.x] = t.snz[s];
-          }
+    // ---- near field: U-list direct sums.  The U-list sources are gathered
+    // into LDS in chunks of LEAF_CH (several neighbour boxes per chunk);
+    // pairs are summed in T per chunk and the chunk sums in FP64 ----
+    for (int c0 = 0; c0 < utot; c0 += LEAF_CH) {
+      const int ns = min(LEAF_CH, utot - c0);
+      __syncthreads();
+      for (int k = 0; k < nU; ++k) {
+        const int lo = max(c0, upref[k]), hi = min(c0 + ns, upref[k + 1]);
+        if (lo >= hi) continue;
+        const int sbase = t.src_beg[t.ulist[u0 + k]] - upref[k];
+        for (int gj = lo + (int)threadIdx.x; gj < hi; gj += blockDim.x) {
+        const int j = gj - c0;
+        const int s = sbase + gj;
+        T4 r1;
+        r1.x = t.sx[s];
+        r1.y = t.sy[s];
+        r1.z = t.sz[s];
+        r1.w = str[(int64_t)(rhs * nstr) * No + s];
+        rec1[j] = r1;
+        trm_[j] = t.rm2[s];
+        if (MODE == FMM_A3B) {
+          T4 r2;
+          r2.x = t.snx[s];
+          r2.y = t.sny[s];
+          r2.z = t.snz[s];
+          r2.w = str[(int64_t)(rhs * nstr + 1) * No + s];
+          rec2[j] = r2;
         }
-        __syncthreads();
-        if (act) {
-          T q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-          for (int jj = 0; jj < ns; ++jj) {
-            const T dx = X - tx_[jj];
-            const T dy = Y - ty_[jj];
-            const T dz = Z - tz_[jj];
-            const T r2 = dev_fma(dz, dz, dev_fma(dy, dy, dx * dx));
-            if (r2 < trm_[jj] || r2 == (T)0) continue;  // pair handled by the stored corrections
-            const T ri = dev_rsqrt(r2);
-            const T ri2 = ri * ri;
-            const T ri3 = ri * ri2;
-            if (MODE == FMM_POT) {
-              q0 += tq1_[jj] * ri;
-            } else if (MODE == FMM_GRAD) {
-              const T q = tq1_[jj];
-              const T qr3 = q * ri3;
-              q0 += q * ri;
-              q1 -= qr3 * dx;
-              q2 -= qr3 * dy;
-              q3 -= qr3 * dz;
-            } else {
-              const T c1 = tq1_[jj], c2 = tq2_[jj];
-              const T nd = NX * dx + NY * dy + NZ * dz;
-              const T mx = NX - tnx_[jj], my = NY - tny_[jj], mz = NZ - tnz_[jj];
-              const T md = mx * dx + my * dy + mz * dz;
-              const T nm = NX * mx + NY * my + NZ * mz;
-              q0 -= c1 * nd * ri3;
-              q1 += c2 * ri;
-              q2 -= c2 * nd * ri3;
-              q3 += c2 * ((T)3 * nd * md * ri3 * ri2 - nm * ri3);
-            }
-          }
-          a0 += (double)q0; a1 += (double)q1; a2 += (double)q2; a3 += (double)q3;
         }
       }
+      __syncthreads();
+      if (act) {
+        T q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+#pragma unroll 4
+        for (int jj = f; jj < ns; jj += F) {
+          const T4 r1 = rec1[jj];
+          const T rm = trm_[jj];
+          const T dx = X - r1.x;
+          const T dy = Y - r1.y;
+          const T dz = Z - r1.z;
+          const T r2 = dev_fma(dz, dz, dev_fma(dy, dy, dx * dx));
+          // pairs inside the mask radius are handled by the stored corrections
+          const bool skip = r2 < rm || r2 == (T)0;
+          const T ri = skip ? (T)0 : dev_rsqrt(skip ? (T)1 : r2);
+          const T ri2 = ri * ri;
+          const T ri3 = ri * ri2;
+          if (MODE == FMM_POT) {
+            q0 += r1.w * ri;
+          } else if (MODE == FMM_GRAD) {
+            const T q = r1.w;
+            const T qr3 = q * ri3;
+            q0 += q * ri;
+            q1 -= qr3 * dx;
+            q2 -= qr3 * dy;
+            q3 -= qr3 * dz;
+          } else {
+            const T4 r2v = rec2[jj];
+            const T c1 = r1.w, c2 = r2v.w;
+            const T nd = NX * dx + NY * dy + NZ * dz;
+            const T mx = NX - r2v.x, my = NY - r2v.y, mz = NZ - r2v.z;
+            const T md = mx * dx + my * dy + mz * dz;
+            const T nm = NX * mx + NY * my + NZ * mz;
+            q0 -= c1 * nd * ri3;
+            q1 += c2 * ri;
+            q2 -= c2 * nd * ri3;
+            q3 += c2 * ((T)3 * nd * md * ri3 * ri2 - nm * ri3);
+          }
+        }
+        a0 += (double)q0; a1 += (double)q1; a2 += (double)q2; a3 += (double)q3;
+      }
     }
-    o0 = (T)a0; o1 = (T)a1; o2 = (T)a2; o3 = (T)a3;
-    if (act) {
+    // sum the F partials of each target (contiguous lanes)
+    for (int off = 1; off < F; off <<= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+      a2 += __shfl_xor(a2, off, 64);
+      a3 += __shfl_xor(a3, off, 64);
+    }
+    if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
-      out[base + i] = o0;
+      out[base + i] = (T)a0;
       if (nout > 1) {
-        out[base + N + i] = o1;
-        out[base + 2 * N + i] = o2;
-        out[base + 3 * N + i] = o3;
+        out[base + N + i] = (T)a1;
+        out[base + 2 * N + i] = (T)a2;
+        out[base + 3 * N + i] = (T)a3;
       }
     }
   }
@@ -648,21 +798,19 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     const int* hp = t.h_lev_src_ptr;
     const int* ht = t.h_lev_tgt_ptr;
     size_t smv = sizeof(T) * ne * L;
+    T* Y = (T*)t.Y;
     for (int l = t.depth - 1; l >= 2; --l) {
-      int nb = hp[l + 1] - hp[l];
-      if (nb > 0) hipLaunchKernelGGL(k_m2m<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M);
-      KCHECK();
+      if (t.m2m_plan) {
+        run_plan<T>(t.m2m_plan[l], t.m2m, L, ne, t.side, M, Y, M, st);
+      } else {
+        int nb = hp[l + 1] - hp[l];
+        if (nb > 0) hipLaunchKernelGGL(k_m2m<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M);
+        KCHECK();
+      }
     }
     tm->mark(PH_M2L, st);
-    if (t.m2l_plan && t.m2l_plan->nwork[ne] > 0) {
-      const M2LPlan& pl = *t.m2l_plan;
-      dim3 grid(pl.nwork[ne], (L + GM_RB * 16 - 1) / (GM_RB * 16));
-      hipLaunchKernelGGL(k_m2l_gemm<T>, grid, dim3(256), 0, st, t.m2l, L, pl.work[ne], pl.grp_off, pl.grp_beg,
-                         pl.pair_src, ne, M, (T*)pl.Y);
-      KCHECK();
-      hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.box_level, pl.tptr,
-                         pl.tpairs, ne, L, t.side, (const T*)pl.Y, Lc);
-      KCHECK();
+    if (t.m2l_plan) {
+      run_plan<T>(*t.m2l_plan, t.m2l, L, ne, t.side, M, Y, Lc, st);
     } else {
       for (int l = 2; l <= t.depth; ++l) {
         int nb = ht[l + 1] - ht[l];
@@ -672,9 +820,13 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     }
     tm->mark(PH_L2L, st);
     for (int l = 3; l <= t.depth; ++l) {
-      int nb = ht[l + 1] - ht[l];
-      if (nb > 0) hipLaunchKernelGGL(k_l2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, Lc);
-      KCHECK();
+      if (t.l2l_plan) {
+        run_plan<T>(t.l2l_plan[l], t.l2l, L, ne, t.side, Lc, Y, Lc, st);
+      } else {
+        int nb = ht[l + 1] - ht[l];
+        if (nb > 0) hipLaunchKernelGGL(k_l2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, Lc);
+        KCHECK();
+      }
     }
   } else {
     tm->mark(PH_M2M, st);
@@ -683,14 +835,24 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   }
   tm->mark(PH_LEAF, st);
   const int nexp = fmm_nexp(mode);
-  size_t sml = sizeof(T) * 9 * LEAF_BS;
+  const size_t chunk = sizeof(T) * (mode == FMM_A3B ? 9 : 5) * 512;
+  const size_t exps = sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
+  const bool lds = chunk + exps <= 64 * 1024;
+  const size_t sml = lds ? chunk + exps : chunk;
   dim3 grid(t.n_leaf_tgt, nrhs);
-  if (mode == FMM_POT)
-    hipLaunchKernelGGL((k_leaf<T, FMM_POT>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
-  else if (mode == FMM_GRAD)
-    hipLaunchKernelGGL((k_leaf<T, FMM_GRAD>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
-  else
-    hipLaunchKernelGGL((k_leaf<T, FMM_A3B>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
+#define LEAF_LAUNCH(MD)                                                                                   \
+  if (lds)                                                                                                \
+    hipLaunchKernelGGL((k_leaf<T, MD, true>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N); \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_leaf<T, MD, false>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
+  if (mode == FMM_POT) {
+    LEAF_LAUNCH(FMM_POT)
+  } else if (mode == FMM_GRAD) {
+    LEAF_LAUNCH(FMM_GRAD)
+  } else {
+    LEAF_LAUNCH(FMM_A3B)
+  }
+#undef LEAF_LAUNCH
   KCHECK();
 }
 

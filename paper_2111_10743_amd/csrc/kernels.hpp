@@ -16,18 +16,21 @@ __host__ __device__ inline int fmm_nout(int mode) { return mode == FMM_POT ? 1 :
 __host__ __device__ inline int fmm_nexp(int mode) { return mode == FMM_A3B ? 3 : 1; }
 __host__ __device__ inline int fmm_nstr(int mode) { return mode == FMM_A3B ? 2 : 1; }
 
-// M2L work plan: V-list pairs of all levels sorted by offset.  Column
-// tiles are 64 wide; work[ne] lists (group, first column) for ne
-// expansions per box (columns = pairs * ne).
-struct M2LPlan {
+// Batched translation plan: (matrix id, source box, target box) triples
+// sorted by (matrix, target).  Each matrix group is one GEMM
+// Y[:, c] = T_mat X[src(c)] over columns c = (triple, expansion); then every
+// target box sums its columns (scaled by its level factor when `scaled`)
+// into (or onto, when `accumulate`) its coefficient vector.  Column tiles are
+// 64 wide; work[ne] lists (group, first column) for ne expansions per box.
+struct GemmPlan {
   int ngrp = 0, npair = 0, nbox = 0;
-  const int *grp_off = nullptr, *grp_beg = nullptr;  // [ngrp], [ngrp+1] (pair index)
+  const int *grp_mat = nullptr, *grp_beg = nullptr;  // [ngrp], [ngrp+1] (triple index)
   const int *pair_src = nullptr;                      // [npair] source box
-  const int *boxes = nullptr, *box_level = nullptr;   // [nbox] target boxes
+  const int *boxes = nullptr, *box_level = nullptr;   // [nbox] target boxes and their levels
   const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
   const int* work[9] = {nullptr};
   int nwork[9] = {0};
-  void* Y = nullptr;                                  // [npair * 8][L] scratch
+  bool scaled = false, accumulate = false;
 };
 
 template <typename T>
@@ -53,7 +56,10 @@ struct DevTree {
   int p, L;                  // expansion order, (p+1)^2
   const T *m2m, *l2l, *m2l;  // transposed [..][in][out]
   const T *dgradT, *dhessT;  // transposed [t][in][out]
-  M2LPlan* m2l_plan;          // host struct with device pointers (nullable)
+  const GemmPlan* m2l_plan;   // host structs with device pointers (nullable):
+  const GemmPlan* m2m_plan;   //   M2L over all levels; M2M and L2L indexed by level
+  const GemmPlan* l2l_plan;
+  void* Y;                    // column scratch [max columns * 8][L]
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities
@@ -71,7 +77,7 @@ struct PhaseTimer {
   void mark(int i, hipStream_t st) { if (on) (void)hipEventRecord(ev[i], st); }
 };
 
-// nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_tgt][nrhs][nexp*3*p^2 + 6*(p-1)^2]
+// nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_tgt][nrhs][nexp*3*p^2 + 9*(p-1)^2]
 template <typename T>
 void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
                 int64_t N, int64_t No, hipStream_t st, PhaseTimer* tm = nullptr);
