@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+refine solves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part "
@@ -95,6 +97,11 @@ def main():
     t_setup = time.perf_counter() - t0
     print(f"[bench] setup {t_setup:.1f} s sizes {s.sizes}", file=sys.stderr, flush=True)
     N = s.N
+    if args.copy_calib_mb > 0:
+        a = torch.ones(args.copy_calib_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
     x32 = torch.tensor(f, dtype=torch.float32, device="cuda")
     x64 = torch.tensor(f, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
