@@ -66,7 +66,7 @@ typedef struct {
   int over_q;       /* oversampled far rule: q x q conical Gauss points       (default k+6)*/
   int p_f32;        /* FMM expansion order of the FP32 path                   (default 14) */
   int p_f64;        /* FMM expansion order of the FP64 path                   (default 28) */
-  int leaf_src;     /* target mean sources per FMM leaf box, FP32 path (FP64: 4x) (default 1024)*/
+  int leaf_src;     /* target mean number of sources per FMM leaf box         (default 1024)*/
   int max_iter;     /* GMRES iteration cap per (inner) solve                  (default 100)*/
   int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT                           */
   int self_n;       /* self-patch rule: Gauss points along each Duffy ray    (default 16) */

@@ -126,6 +126,7 @@ struct Prec {
   std::vector<std::unique_ptr<PlanBuf>> m2m_pb, l2l_pb;
   std::vector<GemmPlan> m2m_pl, l2l_pl;
   DBuf Y;
+  DBuf p2m_H, p2m_D;
   // work
   DBuf str, M, Lc, D, fmm, mu, tmp_in, tmp_out;
   int ws_rhs = 0;
@@ -337,6 +338,30 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     }
     P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);
   }
+  // FP32 P2M tables (the geometry is fixed; see p2m_tables), when they take
+  // less than 8 GiB
+  bool tables = false;
+  if (sizeof(T) == 4 && t.depth >= 2 && 2.0 * 4.0 * (double)No * P.L < 8.0 * (1 << 30)) {
+    tables = true;
+    const double h = t.box_side(t.depth);
+    std::vector<double> xi(3 * (size_t)No), nu(3 * (size_t)No);
+    const int nleaf = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
+    for (int b = 0; b < nleaf; ++b) {
+      const int g = t.lev_off[t.depth] + b;
+      const double c[3] = {t.lo[0] + (t.bx[g] + 0.5) * h, t.lo[1] + (t.by[g] + 0.5) * h, t.lo[2] + (t.bz[g] + 0.5) * h};
+      for (int j = t.src_beg[b]; j < t.src_end[b]; ++j) {
+        const int64_t i = t.src_perm[j];
+        for (int d = 0; d < 3; ++d) {
+          xi[3 * j + d] = (S.s[3 * i + d] - c[d]) / h;
+          nu[3 * j + d] = S.nu[3 * i + d];
+        }
+      }
+    }
+    std::vector<float> Ht((size_t)No * P.L), Dt((size_t)No * P.L);
+    p2m_tables(p, No, xi.data(), nu.data(), h, Ht.data(), Dt.data());
+    upload(P.p2m_H, Ht);
+    upload(P.p2m_D, Dt);
+  }
   // device tree descriptor
   DevTree<T>& D = P.dt;
   D.tx = dptr<T>(P.tx); D.ty = dptr<T>(P.ty); D.tz = dptr<T>(P.tz);
@@ -368,6 +393,8 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.m2m_plan = t.depth >= 2 ? P.m2m_pl.data() : nullptr;
   D.l2l_plan = t.depth >= 2 ? P.l2l_pl.data() : nullptr;
   D.Y = P.Y.p;
+  D.p2m_H = tables ? dptr<float>(P.p2m_H) : nullptr;
+  D.p2m_D = tables ? dptr<float>(P.p2m_D) : nullptr;
 }
 
 template <typename T>
@@ -629,9 +656,7 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
     const bool direct = (o.flags & LB_DIRECT) != 0;
     build_prec<float>(ctx.get(), ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
     // the float positions used by the mask test must be exactly the ones on the device
-    // the FP64 path uses 4x larger leaves: its translations (order p_f64) cost
-    // more relative to the near-field sums
-    build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, 4 * o.leaf_src, direct);
+    build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
     HIPTRY(hipDeviceSynchronize());
   }
   *out = ctx.release();

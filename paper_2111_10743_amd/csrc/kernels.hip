@@ -254,6 +254,40 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
   }
 }
 
+// P2M from precomputed per-source tables (FP32 path): thread per coefficient,
+// M[g][rhs*nexp + e][c] = sum_j q_e[j] H[j][c] (+ sum_j q2[j] Dp[j][c]).
+// grid (leaves with sources, nrhs)
+template <typename T>
+__global__ __launch_bounds__(256) void k_p2m_tab(DevTree<T> t, int mode, int nrhs, const T* __restrict__ str,
+                                                 int64_t No, const float* __restrict__ H,
+                                                 const float* __restrict__ Dp, T* __restrict__ M) {
+  const int b = t.leaf_src_list[blockIdx.x];
+  const int g = t.leaf_off + b;
+  const int rhs = blockIdx.y;
+  const int L = t.L;
+  const int nexp = fmm_nexp(mode), nstr = fmm_nstr(mode);
+  const int beg = t.src_beg[b], end = t.src_end[b];
+  const T* q1 = str + (int64_t)(rhs * nstr) * No;
+  const T* q2 = mode == FMM_A3B ? str + (int64_t)(rhs * nstr + 1) * No : q1;
+  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int j = beg; j < end; ++j) {
+      const T hv = (T)H[(int64_t)j * L + c];
+      a0 += q1[j] * hv;
+      if (mode == FMM_A3B) {
+        a1 += q2[j] * hv;
+        a2 += q2[j] * (T)Dp[(int64_t)j * L + c];
+      }
+    }
+    T* out = M + ((int64_t)g * nrhs * nexp + rhs * nexp) * L + c;
+    out[0] = a0;
+    if (mode == FMM_A3B) {
+      out[L] = a1;
+      out[2 * L] = a2;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // dense translation helpers: out[e][r] (+)= sum_c TT[c][r] x[e][c]
 // ---------------------------------------------------------------------------
@@ -792,7 +826,11 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     int ts = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
+    if (t.p2m_H)
+      hipLaunchKernelGGL(k_p2m_tab<T>, dim3(t.n_leaf_src, nrhs), dim3(256), 0, st, t, mode, nrhs, str, No, t.p2m_H,
+                         t.p2m_D, M);
+    else
+      hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
     KCHECK();
     tm->mark(PH_M2M, st);
     const int* hp = t.h_lev_src_ptr;

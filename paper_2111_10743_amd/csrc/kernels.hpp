@@ -60,6 +60,7 @@ struct DevTree {
   const GemmPlan* m2m_plan;   //   M2L over all levels; M2M and L2L indexed by level
   const GemmPlan* l2l_plan;
   void* Y;                    // column scratch [max columns * 8][L]
+  const float *p2m_H, *p2m_D; // per-source P2M tables [No][L] in tree order (nullable)
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities
