@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -213,7 +214,9 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     int64_t i = t.src_perm[j];
     sa[j] = (T)S.s[3 * i]; sb[j] = (T)S.s[3 * i + 1]; sc[j] = (T)S.s[3 * i + 2];
     sd[j] = (T)S.nu[3 * i]; se[j] = (T)S.nu[3 * i + 1]; sf[j] = (T)S.nu[3 * i + 2];
-    sr[j] = rm2f.empty() ? (T)0 : (T)rm2f[i];
+    // without a mask (FP64) the smallest positive normal value still excludes
+    // coincident points
+    sr[j] = rm2f.empty() ? std::numeric_limits<T>::min() : (T)rm2f[i];
   }
   upload(P.sx, sa); upload(P.sy, sb); upload(P.sz, sc); upload(P.snx, sd); upload(P.sny, se); upload(P.snz, sf);
   upload(P.rm2, sr);
@@ -439,108 +442,148 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
   }
 }
 
+// A3 (Section 4.3) for nd densities, two per traversal: the second FMM
+// carries three expansions per density (charges mu1, mu2 and dipole mu2 nu).
+constexpr int CHUNK_A3 = 2;
+
 template <typename T>
 static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
   ensure_ws(ctx, P, CHUNK_GRAD);
   const int64_t N = ctx->N, No = ctx->No;
-  T* mu = dptr<T>(P.mu);  // [mu1; mu2]
-  for (int d = 0; d < nd; ++d) {
-    const T* td = tau + (int64_t)d * N;
-    launch_strengths<T>(td, 1, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+  T* mu = dptr<T>(P.mu);  // [c][mu1; mu2]
+  for (int d0 = 0; d0 < nd; d0 += CHUNK_A3) {
+    const int c = std::min(CHUNK_A3, nd - d0);
+    const T* td = tau + (int64_t)d0 * N;
+    launch_strengths<T>(td, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
                         dptr<T>(P.str), st);
-    launch_fmm<T>(P.dt, FMM_GRAD, 1, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
-    launch_combine_a3a<T>(1, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td,
-                          dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm), mu, mu + N, st);
-    launch_strengths<T>(mu, 2, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
-                        dptr<T>(P.str), st);
-    launch_fmm<T>(P.dt, FMM_A3B, 1, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
-    launch_combine_a3b<T>(1, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td, mu,
-                          mu + N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.H), dptr<double>(ctx->w),
-                          1.0 / ctx->area, out + (int64_t)d * N, dptr<double>(ctx->partial), st);
+    launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    launch_combine_a3a<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td,
+                          dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm), mu, mu + N, 2 * N, st);
+    launch_strengths<T>(mu, 2 * c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos),
+                        No, dptr<T>(P.str), st);
+    launch_fmm<T>(P.dt, FMM_A3B, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    launch_combine_a3b<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td, mu,
+                          mu + N, 2 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.H), dptr<double>(ctx->w),
+                          1.0 / ctx->area, out + (int64_t)d0 * N, dptr<double>(ctx->partial), st);
   }
 }
 
 // ---------------------------------------------------------------------------
-// GMRES (Section 6): x0 = 0, no restart, CGS2 Arnoldi in FP64 on the device,
-// Givens rotations on the host.
+// GMRES (Section 6) for nb right-hand sides at once: x0 = 0, no restart,
+// each right-hand side has its own Arnoldi basis (CGS2, FP64 on the device)
+// and Givens rotations (host); the operator is applied to all active
+// right-hand sides in one batched call.  A(in [na][N], out [na][N], na).
 // ---------------------------------------------------------------------------
 template <typename ApplyFn>
-static int gmres(lb_ctx* ctx, ApplyFn A, const double* b, double* x, double tol, int maxit, double* relres,
-                 hipStream_t st) {
+static void gmres_multi(lb_ctx* ctx, ApplyFn A, int nb, const double* B, double* X, double tol, int maxit,
+                        const std::vector<char>& skip, std::vector<double>& relres, std::vector<int>& iters,
+                        hipStream_t st) {
   const int64_t N = ctx->N;
-  if (ctx->v_cols < maxit + 1) {
-    ctx->V.alloc(sizeof(double) * (size_t)N * (maxit + 1));
-    ctx->wv.alloc(sizeof(double) * (size_t)N);
-    ctx->hbuf.alloc(sizeof(double) * (maxit + 2) * 2);
-    ctx->v_cols = maxit + 1;
+  const size_t need = (size_t)nb * (maxit + 1);
+  if ((size_t)ctx->v_cols < need) {
+    ctx->V.alloc(sizeof(double) * (size_t)N * need);
+    ctx->v_cols = (int)need;
   }
-  double* V = dptr<double>(ctx->V);
-  double* w = dptr<double>(ctx->wv);
+  ctx->wv.alloc(sizeof(double) * (size_t)N * nb * 2);
+  ctx->hbuf.alloc(sizeof(double) * (maxit + 2) * 2);
+  double* Vall = dptr<double>(ctx->V);
+  double* win = dptr<double>(ctx->wv);
+  double* wout = win + (size_t)N * nb;
   double* hd = dptr<double>(ctx->hbuf);
   double* part = dptr<double>(ctx->partial);
-  auto dots = [&](int k, const double* vec, std::vector<double>& out) {
-    launch_dots(V, N, k, vec, N, hd, part, st);
+  auto V = [&](int r, int j) { return Vall + ((size_t)r * (maxit + 1) + j) * N; };
+  auto dots = [&](const double* Vb, int k, const double* vec, std::vector<double>& out) {
+    launch_dots(Vb, N, k, vec, N, hd, part, st);
     out.resize(k);
     HIPTRY(hipMemcpyAsync(out.data(), hd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
   };
   auto norm = [&](const double* vec) {
-    launch_dots(vec, N, 1, vec, N, hd, part, st);
-    double v;
-    HIPTRY(hipMemcpyAsync(&v, hd, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    return std::sqrt(v);
+    std::vector<double> v;
+    dots(vec, 1, vec, v);
+    return std::sqrt(v[0]);
   };
-  HIPTRY(hipMemsetAsync(x, 0, sizeof(double) * N, st));
-  const double beta = norm(b);
-  if (beta == 0.0) { *relres = 0.0; return 0; }
-  launch_scale_copy(b, 1.0 / beta, V, N, st);
-  std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0), h1, h2;
-  g[0] = beta;
-  int k = 0;
-  double rel = 1.0;
+  struct St {
+    std::vector<double> H, cs, sn, g;
+    double beta = 0;
+    int k = 0;
+    bool done = false;
+  };
+  std::vector<St> S(nb);
+  relres.assign(nb, 0.0);
+  iters.assign(nb, 0);
+  for (int r = 0; r < nb; ++r) {
+    double* x = X + (size_t)r * N;
+    HIPTRY(hipMemsetAsync(x, 0, sizeof(double) * N, st));
+    St& q = S[r];
+    q.H.assign((size_t)(maxit + 1) * maxit, 0.0);
+    q.cs.assign(maxit, 0.0);
+    q.sn.assign(maxit, 0.0);
+    q.g.assign(maxit + 1, 0.0);
+    if (skip[r]) { q.done = true; continue; }
+    q.beta = norm(B + (size_t)r * N);
+    if (q.beta == 0.0) { q.done = true; continue; }
+    q.g[0] = q.beta;
+    launch_scale_copy(B + (size_t)r * N, 1.0 / q.beta, V(r, 0), N, st);
+  }
+  std::vector<double> h1, h2;
   for (int j = 0; j < maxit; ++j) {
-    A(V + (int64_t)j * N, w);
-    dots(j + 1, w, h1);
-    HIPTRY(hipMemcpyAsync(hd, h1.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-    launch_gemv_sub(V, N, j + 1, hd, w, N, st);
-    dots(j + 1, w, h2);
-    HIPTRY(hipMemcpyAsync(hd, h2.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-    launch_gemv_sub(V, N, j + 1, hd, w, N, st);
-    double hn = norm(w);
-    double* col = &H[(size_t)j];  // H[i][j] at i*maxit + j
-    for (int i = 0; i <= j; ++i) H[(size_t)i * maxit + j] = h1[i] + h2[i];
-    H[(size_t)(j + 1) * maxit + j] = hn;
-    (void)col;
-    for (int i = 0; i < j; ++i) {
-      double a = H[(size_t)i * maxit + j], bb = H[(size_t)(i + 1) * maxit + j];
-      H[(size_t)i * maxit + j] = cs[i] * a + sn[i] * bb;
-      H[(size_t)(i + 1) * maxit + j] = -sn[i] * a + cs[i] * bb;
+    std::vector<int> act;
+    for (int r = 0; r < nb; ++r)
+      if (!S[r].done) act.push_back(r);
+    if (act.empty()) break;
+    for (size_t a = 0; a < act.size(); ++a)
+      HIPTRY(hipMemcpyAsync(win + a * N, V(act[a], j), sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    A(win, wout, (int)act.size());
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int r = act[a];
+      St& q = S[r];
+      double* w = wout + a * N;
+      dots(V(r, 0), j + 1, w, h1);
+      HIPTRY(hipMemcpyAsync(hd, h1.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+      launch_gemv_sub(V(r, 0), N, j + 1, hd, w, N, st);
+      dots(V(r, 0), j + 1, w, h2);
+      HIPTRY(hipMemcpyAsync(hd, h2.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+      launch_gemv_sub(V(r, 0), N, j + 1, hd, w, N, st);
+      const double hn = norm(w);
+      std::vector<double>& H = q.H;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * maxit + j] = h1[i] + h2[i];
+      H[(size_t)(j + 1) * maxit + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a1 = H[(size_t)i * maxit + j], b1 = H[(size_t)(i + 1) * maxit + j];
+        H[(size_t)i * maxit + j] = q.cs[i] * a1 + q.sn[i] * b1;
+        H[(size_t)(i + 1) * maxit + j] = -q.sn[i] * a1 + q.cs[i] * b1;
+      }
+      const double a1 = H[(size_t)j * maxit + j], b1 = H[(size_t)(j + 1) * maxit + j];
+      const double den = std::hypot(a1, b1);
+      q.cs[j] = a1 / den;
+      q.sn[j] = b1 / den;
+      H[(size_t)j * maxit + j] = den;
+      H[(size_t)(j + 1) * maxit + j] = 0.0;
+      q.g[j + 1] = -q.sn[j] * q.g[j];
+      q.g[j] = q.cs[j] * q.g[j];
+      q.k = j + 1;
+      relres[r] = std::fabs(q.g[j + 1]) / q.beta;
+      if (relres[r] < tol || hn == 0.0 || j + 1 == maxit)
+        q.done = true;
+      else
+        launch_scale_copy(w, 1.0 / hn, V(r, j + 1), N, st);
     }
-    double a = H[(size_t)j * maxit + j], bb = H[(size_t)(j + 1) * maxit + j];
-    double den = std::hypot(a, bb);
-    cs[j] = a / den;
-    sn[j] = bb / den;
-    H[(size_t)j * maxit + j] = den;
-    H[(size_t)(j + 1) * maxit + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    k = j + 1;
-    rel = std::fabs(g[j + 1]) / beta;
-    if (rel < tol || hn == 0.0) break;
-    if (j + 1 < maxit) launch_scale_copy(w, 1.0 / hn, V + (int64_t)(j + 1) * N, N, st);
   }
-  std::vector<double> y(k);
-  for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * maxit + c] * y[c];
-    y[i] = s / H[(size_t)i * maxit + i];
+  for (int r = 0; r < nb; ++r) {
+    St& q = S[r];
+    iters[r] = q.k;
+    if (q.k == 0) continue;
+    std::vector<double> y(q.k);
+    for (int i = q.k - 1; i >= 0; --i) {
+      double sacc = q.g[i];
+      for (int c = i + 1; c < q.k; ++c) sacc -= q.H[(size_t)i * maxit + c] * y[c];
+      y[i] = sacc / q.H[(size_t)i * maxit + i];
+    }
+    HIPTRY(hipMemcpyAsync(hd, y.data(), sizeof(double) * q.k, hipMemcpyHostToDevice, st));
+    launch_gemv_add(V(r, 0), N, q.k, hd, X + (size_t)r * N, N, st);
+    HIPTRY(hipStreamSynchronize(st));
   }
-  HIPTRY(hipMemcpyAsync(hd, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-  launch_gemv_add(V, N, k, hd, x, N, st);
-  HIPTRY(hipStreamSynchronize(st));
-  *relres = rel;
-  return k;
 }
 
 }  // namespace lb
@@ -807,98 +850,111 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   const int maxit = ctx->opts.max_iter;
   ensure_ws(ctx, ctx->f64, CHUNK_GRAD);
   ensure_ws(ctx, ctx->f32, CHUNK_GRAD);
-  ctx->r.alloc(sizeof(double) * N);
-  ctx->sig.alloc(sizeof(double) * N);
-  ctx->ftmp.alloc(sizeof(double) * N);
-  ctx->utmp.alloc(sizeof(double) * N * 3);
-  ctx->f32.tmp_in.alloc(sizeof(float) * N);
-  ctx->f32.tmp_out.alloc(sizeof(float) * N);
+  const size_t nN = (size_t)nrhs * N;
+  ctx->r.alloc(sizeof(double) * nN);
+  ctx->sig.alloc(sizeof(double) * nN);
+  ctx->ftmp.alloc(sizeof(double) * nN);
+  ctx->utmp.alloc(sizeof(double) * nN * 2);
+  ctx->f32.tmp_in.alloc(sizeof(float) * nN);
+  ctx->f32.tmp_out.alloc(sizeof(float) * nN);
   double* r = dptr<double>(ctx->r);
   double* sig = dptr<double>(ctx->sig);
   double* fz = dptr<double>(ctx->ftmp);
   double* ut = dptr<double>(ctx->utmp);
-  double* dcorr = ut + N;
-  double* hd = ctx->hbuf.p ? dptr<double>(ctx->hbuf) : nullptr;
+  double* dcorr = ut + nN;
   DBuf scal;
   scal.alloc(sizeof(double) * 4);
-  lb_status ret = LB_OK;
-  auto A64 = [&](const double* v, double* w) { apply_A3_t<double>(ctx, ctx->f64, 1, v, w, st); };
-  auto A32 = [&](const double* v, double* w) {
+  auto A64 = [&](const double* v, double* w, int na) { apply_A3_t<double>(ctx, ctx->f64, na, v, w, st); };
+  auto A32 = [&](const double* v, double* w, int na) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
     float* vo = dptr<float>(ctx->f32.tmp_out);
-    launch_convert<double, float>(v, vi, N, st);
-    apply_A3_t<float>(ctx, ctx->f32, 1, vi, vo, st);
-    launch_convert<float, double>(vo, w, N, st);
+    launch_convert<double, float>(v, vi, (int64_t)na * N, st);
+    apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, st);
+    launch_convert<float, double>(vo, w, (int64_t)na * N, st);
   };
   auto nrm2 = [&](const double* v) {
     launch_dots(v, N, 1, v, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
-    double s;
-    HIPTRY(hipMemcpyAsync(&s, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
+    double sv;
+    HIPTRY(hipMemcpyAsync(&sv, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
-    return std::sqrt(s);
+    return std::sqrt(sv);
   };
-  (void)hd;
+  // mean projection (Lemma 1)
+  std::vector<double> mean(nrhs), fnorm(nrhs);
   for (int q = 0; q < nrhs; ++q) {
-    const double* fq = f + (int64_t)q * N;
-    // mean projection (Lemma 1)
+    const double* fq = f + (size_t)q * N;
+    double* fzq = fz + (size_t)q * N;
     launch_wmean(fq, dptr<double>(ctx->w), N, dptr<double>(ctx->partial), dptr<double>(scal), st);
     double sumwf;
     HIPTRY(hipMemcpyAsync(&sumwf, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
-    const double mean = sumwf / ctx->area;
-    HIPTRY(hipMemcpyAsync(fz, fq, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    mean[q] = sumwf / ctx->area;
+    HIPTRY(hipMemcpyAsync(fzq, fq, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     if (ctx->opts.flags & LB_STRICT_MEAN) {
-      double fn = nrm2(fz);
-      if (std::fabs(mean) > 1e-12 * fn) fail(LB_ENOTMEANZERO, "f has weighted mean %g", mean);
+      const double fn = nrm2(fzq);
+      if (std::fabs(mean[q]) > 1e-12 * fn) fail(LB_ENOTMEANZERO, "right-hand side %d has weighted mean %g", q, mean[q]);
     }
-    launch_sub_scalar(fz, dptr<double>(scal), 1.0 / ctx->area, N, st);
-    const double fnorm = nrm2(fz);
-    int iters = 0, outer = 0;
-    double rel = 0;
-    if (mode == LB_SOLVE_FP64) {
-      int it = gmres(ctx, A64, fz, sig, tol, maxit, &rel, st);
-      iters = it;
-      A64(sig, ut);
-      launch_axpby(1.0, fz, -1.0, ut, r, N, st);
-      rel = fnorm > 0 ? nrm2(r) / fnorm : 0.0;
-      if (rel >= tol && it >= maxit) ret = LB_ENOCONV;
-    } else {
-      HIPTRY(hipMemsetAsync(sig, 0, sizeof(double) * N, st));
-      HIPTRY(hipMemcpyAsync(r, fz, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-      rel = 1.0;
-      const int max_outer = 12;
-      bool stalled = false;
-      double prev = 1e300;
-      while (rel >= tol && outer < max_outer) {
-        double inner_rel;
-        double inner_tol = std::max(1e-6, 0.5 * tol / std::max(rel, 1e-300));
-        int it = gmres(ctx, A32, r, dcorr, inner_tol, maxit, &inner_rel, st);
-        iters += it;
-        launch_axpby(1.0, sig, 1.0, dcorr, sig, N, st);
-        A64(sig, ut);
-        launch_axpby(1.0, fz, -1.0, ut, r, N, st);
-        rel = fnorm > 0 ? nrm2(r) / fnorm : 0.0;
-        ++outer;
-        if (rel > 0.5 * prev) { stalled = true; break; }
-        prev = rel;
+    launch_sub_scalar(fzq, dptr<double>(scal), 1.0 / ctx->area, N, st);
+    fnorm[q] = nrm2(fzq);
+  }
+  std::vector<double> rel(nrhs, 0.0), inner;
+  std::vector<int> iters(nrhs, 0), outer(nrhs, 0), it;
+  std::vector<char> skip(nrhs, 0);
+  auto residual = [&]() {  // r = fz - A3 sig (FP64), rel = |r| / |fz|
+    A64(sig, ut, nrhs);
+    launch_axpby(1.0, fz, -1.0, ut, r, (int64_t)nN, st);
+    for (int q = 0; q < nrhs; ++q) rel[q] = fnorm[q] > 0 ? nrm2(r + (size_t)q * N) / fnorm[q] : 0.0;
+  };
+  if (mode == LB_SOLVE_FP64) {
+    gmres_multi(ctx, A64, nrhs, fz, sig, tol, maxit, skip, inner, it, st);
+    for (int q = 0; q < nrhs; ++q) iters[q] = it[q];
+    residual();
+  } else {
+    HIPTRY(hipMemsetAsync(sig, 0, sizeof(double) * nN, st));
+    HIPTRY(hipMemcpyAsync(r, fz, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
+    for (int q = 0; q < nrhs; ++q) rel[q] = fnorm[q] > 0 ? 1.0 : 0.0;
+    std::vector<double> prev(nrhs, 1e300);
+    const int max_outer = 12;
+    for (int step = 0; step < max_outer; ++step) {
+      bool any = false;
+      for (int q = 0; q < nrhs; ++q) {
+        skip[q] = !(rel[q] >= tol) || rel[q] > 0.5 * prev[q];  // converged, or refinement stalled
+        any |= !skip[q];
       }
-      if (rel >= tol) ret = LB_ENOCONV;
-      (void)stalled;
+      if (!any) break;
+      // inner FP32 solves: the FP32 operator is accurate to ~1e-6, so each
+      // refinement step asks for no more than that
+      double worst = 0;
+      for (int q = 0; q < nrhs; ++q)
+        if (!skip[q]) worst = std::max(worst, rel[q]);
+      const double inner_tol = std::max(1e-6, 0.5 * tol / std::max(worst, 1e-300));
+      gmres_multi(ctx, A32, nrhs, r, dcorr, inner_tol, maxit, skip, inner, it, st);
+      for (int q = 0; q < nrhs; ++q) {
+        if (skip[q]) continue;
+        iters[q] += it[q];
+        outer[q] += 1;
+        launch_axpby(1.0, sig + (size_t)q * N, 1.0, dcorr + (size_t)q * N, sig + (size_t)q * N, N, st);
+      }
+      prev = rel;
+      residual();
     }
-    // u = S[S[sigma]] in FP64
-    double* uq = u + (int64_t)q * N;
-    {
-      DBuf g;
-      g.alloc(sizeof(double) * 3 * N);
-      apply_gradS_t<double>(ctx, ctx->f64, 1, sig, ut, dptr<double>(g), nullptr, nullptr, st);
-      apply_gradS_t<double>(ctx, ctx->f64, 1, ut, uq, dptr<double>(g), nullptr, nullptr, st);
-      HIPTRY(hipStreamSynchronize(st));
-    }
+  }
+  // u = S[S[sigma]] in FP64
+  {
+    DBuf g;
+    g.alloc(sizeof(double) * 3 * nN);
+    apply_gradS_t<double>(ctx, ctx->f64, nrhs, sig, ut, dptr<double>(g), nullptr, nullptr, st);
+    apply_gradS_t<double>(ctx, ctx->f64, nrhs, ut, u, dptr<double>(g), nullptr, nullptr, st);
+    HIPTRY(hipStreamSynchronize(st));
+  }
+  lb_status ret = LB_OK;
+  for (int q = 0; q < nrhs; ++q) {
+    if (!(rel[q] < tol)) ret = LB_ENOCONV;
     if (info) {
-      info[q].iters = iters;
-      info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer - 1, 0);
-      info[q].rel_resid = rel;
-      info[q].removed_mean = mean;
+      info[q].iters = iters[q];
+      info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[q] - 1, 0);
+      info[q].rel_resid = rel[q];
+      info[q].removed_mean = mean[q];
     }
   }
   if (ret != LB_OK) {

@@ -762,7 +762,8 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
           const T dz = Z - r1.z;
           const T r2 = dev_fma(dz, dz, dev_fma(dy, dy, dx * dx));
           // pairs inside the mask radius are handled by the stored corrections
-          const bool skip = r2 < rm || r2 == (T)0;
+          // (rm > 0 always, so coincident points are skipped too)
+          const bool skip = r2 < rm;
           const T ri = skip ? (T)0 : dev_rsqrt(skip ? (T)1 : r2);
           const T ri2 = ri * ri;
           const T ri3 = ri * ri2;
@@ -983,7 +984,7 @@ __global__ __launch_bounds__(256) void k_combine_a3a(int nd, int64_t N, int n_p,
                                                      const int* __restrict__ patch, const T* __restrict__ vals,
                                                      const T* __restrict__ tau, const T* __restrict__ fmm,
                                                      const int* __restrict__ tgt_pos, const T* __restrict__ nrm,
-                                                     T* mu1, T* mu2) {
+                                                     T* mu1, T* mu2, int64_t ldmu) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= N) return;
@@ -1010,8 +1011,8 @@ __global__ __launch_bounds__(256) void k_combine_a3a(int nd, int64_t N, int n_p,
     const T s = (T)INV4PI_D;
     for (int d = 0; d < nd; ++d) {
       const T* f = fmm + (int64_t)d * 4 * N;
-      mu2[(int64_t)d * N + row] = f[tp] * s + aS[d];
-      mu1[(int64_t)d * N + row] = (n0 * f[N + tp] + n1 * f[2 * N + tp] + n2 * f[3 * N + tp]) * s + aP[d];
+      mu2[(int64_t)d * ldmu + row] = f[tp] * s + aS[d];
+      mu1[(int64_t)d * ldmu + row] = (n0 * f[N + tp] + n1 * f[2 * N + tp] + n2 * f[3 * N + tp]) * s + aP[d];
     }
   }
 }
@@ -1019,12 +1020,12 @@ __global__ __launch_bounds__(256) void k_combine_a3a(int nd, int64_t N, int n_p,
 template <typename T>
 void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                         const T* vals3, const T* tau, const T* fmm, const int* tgt_pos,
-                        const T* nrm, T* mu1, T* mu2, hipStream_t st) {
+                        const T* nrm, T* mu1, T* mu2, int64_t ldmu, hipStream_t st) {
   for (int d0 = 0; d0 < nd; d0 += NDMAX) {
     int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
     hipLaunchKernelGGL(k_combine_a3a<T>, dim3((N + 3) / 4), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals3,
-                       tau + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm, mu1 + (int64_t)d0 * N,
-                       mu2 + (int64_t)d0 * N);
+                       tau + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm, mu1 + (int64_t)d0 * ldmu,
+                       mu2 + (int64_t)d0 * ldmu, ldmu);
     KCHECK();
   }
 }
@@ -1035,7 +1036,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_combine_a3b(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
                                                      const int* __restrict__ patch, const T* __restrict__ vals,
                                                      const T* __restrict__ tau, const T* __restrict__ mu1,
-                                                     const T* __restrict__ mu2, const T* __restrict__ fmm,
+                                                     const T* __restrict__ mu2, int64_t ldmu, const T* __restrict__ fmm,
                                                      const int* __restrict__ tgt_pos, const T* __restrict__ H,
                                                      const double* __restrict__ w, T* out, double* partial,
                                                      int nblk) {
@@ -1057,8 +1058,8 @@ __global__ __launch_bounds__(256) void k_combine_a3b(int nd, int64_t N, int n_p,
       const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
       const T cS = v[3 * e], cP = v[3 * e + 1], cD = v[3 * e + 2];
       for (int d = 0; d < nd; ++d) {
-        const T x1 = mu1[(int64_t)d * N + col];
-        const T x2 = mu2[(int64_t)d * N + col];
+        const T x1 = mu1[(int64_t)d * ldmu + col];
+        const T x2 = mu2[(int64_t)d * ldmu + col];
         a1[d] += cP * x1;
         a2[d] += cS * x2;
         a3[d] += cP * x2;
@@ -1115,7 +1116,7 @@ __global__ void k_add_scalar(T* out, int64_t N, int nd, const double* s) {
 
 template <typename T>
 void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
-                        const T* vals3, const T* tau, const T* mu1, const T* mu2, const T* fmm,
+                        const T* vals3, const T* tau, const T* mu1, const T* mu2, int64_t ldmu, const T* fmm,
                         const int* tgt_pos, const T* H, const double* w, double inv_area,
                         T* out, double* partial, hipStream_t st) {
   const int nblk = (int)((N + 3) / 4);
@@ -1123,7 +1124,7 @@ void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, cons
     int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
     double* sc = partial + (int64_t)NDMAX * nblk;  // NDMAX scalars after the partials
     hipLaunchKernelGGL(k_combine_a3b<T>, dim3(nblk), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals3,
-                       tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * N, mu2 + (int64_t)d0 * N,
+                       tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * ldmu, mu2 + (int64_t)d0 * ldmu, ldmu,
                        fmm + (int64_t)d0 * 4 * N, tgt_pos, H, w, out + (int64_t)d0 * N, partial, nblk);
     KCHECK();
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblk, ndc, inv_area, sc);
@@ -1258,10 +1259,10 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
   template void launch_combine_grad<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,        \
                                        const T*, const int*, const T*, T*, T*, T*, T*, hipStream_t);             \
   template void launch_combine_a3a<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
-                                      const T*, const int*, const T*, T*, T*, hipStream_t);                      \
+                                      const T*, const int*, const T*, T*, T*, int64_t, hipStream_t);             \
   template void launch_combine_a3b<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
-                                      const T*, const T*, const T*, const int*, const T*, const double*, double, \
-                                      T*, double*, hipStream_t);
+                                      const T*, const T*, int64_t, const T*, const int*, const T*, const double*, \
+                                      double, T*, double*, hipStream_t);
 INST(float)
 INST(double)
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);

@@ -89,15 +89,15 @@ template <typename T>
 void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                          const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
                          const T* nrm, T* pot, T* grad, T* dSdn, T* surf, hipStream_t st);
-// A3 step 1: tau -> mu1 = S' tau, mu2 = S tau  (out arrays [nd][N])
+// A3 step 1: tau -> mu1 = S' tau, mu2 = S tau  (density d of mu1/mu2 at offset d*ldmu)
 template <typename T>
 void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                         const T* vals3, const T* tau, const T* fmm, const int* tgt_pos,
-                        const T* nrm, T* mu1, T* mu2, hipStream_t st);
+                        const T* nrm, T* mu1, T* mu2, int64_t ldmu, hipStream_t st);
 // A3 step 2: out = -tau/4 + S'mu1 - (S''+D')mu2 - 2H S'mu2 + W S mu2
 template <typename T>
 void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
-                        const T* vals3, const T* tau, const T* mu1, const T* mu2, const T* fmm,
+                        const T* vals3, const T* tau, const T* mu1, const T* mu2, int64_t ldmu, const T* fmm,
                         const int* tgt_pos, const T* H, const double* w, double inv_area,
                         T* out, double* partial, hipStream_t st);
 

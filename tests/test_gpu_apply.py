@@ -142,3 +142,58 @@ def test_fmm_sampled_rows(torch_dev, kind, k, n):
         note(f"fmm {kind} prec={prec} errors pot {e1:.2e} grad {e2:.2e}")
         assert e1 < tol and e2 < tol
     s.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c1_batched_applies(torch_dev, c1_oracle, prec):
+    """Three densities in one call (a full chunk of the A3 traversal plus a
+    ragged one) against the oracle, density by density."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    o = c1_oracle
+    g = o.g
+    note(f"c1 batched applies prec={prec}")
+    s = P.Surface(g.Xp, g.Xup, g.Xvp, 4)
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(11)
+    sig = np.stack([I.real_sph_harm(2, 1, g.x), g.x[:, 0] * g.x[:, 1] + 0.1 * rng.standard_normal(g.N),
+                    np.ones(g.N)])
+    t = torch.tensor(sig, dtype=dt, device="cuda")
+    out = s.apply_gradS(t)
+    a3 = s.apply_A3(t).double().cpu().numpy()
+    torch.cuda.synchronize()
+    tol = 1e-9 if prec == 64 else 1e-6
+    for d in range(3):
+        L = o.layer(sig[d])
+        e1 = rel_l2(out["pot"][d].double().cpu().numpy(), L[:, 0])
+        e2 = rel_l2(out["grad"][d].double().cpu().numpy(), L[:, 1:4])
+        e3 = rel_l2(a3[d], o.A3(sig[d]))
+        note(f"density {d}: pot {e1:.2e} grad {e2:.2e} A3 {e3:.2e}")
+        assert e1 < tol and e2 < tol and e3 < 5 * tol
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c1_solve_multi_rhs(torch_dev, c1_oracle, mode):
+    """Four right-hand sides in one solve (one of them zero, one with a
+    nonzero mean) against the oracle's solves, one by one."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    o = c1_oracle
+    g = o.g
+    note(f"c1 multi-rhs solve mode={mode}")
+    s = P.Surface(g.Xp, g.Xup, g.Xvp, 4)
+    F = np.stack([g.x[:, 0] * g.x[:, 2], I.real_sph_harm(3, 1, g.x), np.zeros(g.N),
+                  g.x[:, 1] ** 2 + 0.2 * g.x[:, 0]])
+    u, info, code = s.solve(torch.tensor(F, dtype=torch.float64, device="cuda"), tol=1e-12, mode=mode)
+    u = u.cpu().numpy()
+    note(f"info {info}")
+    assert code == 0
+    assert np.all(u[2] == 0.0)
+    for r in (0, 1, 3):
+        uref, _ = o.solve(F[r], tol=1e-12)
+        e = rel_l2(u[r], uref, g.w)
+        note(f"rhs {r}: error vs oracle {e:.2e}")
+        assert e < 1e-9
+    assert abs(info[3]["removed_mean"]) > 0.1
+    s.close()
