@@ -192,6 +192,8 @@ static void pack_vals(const std::vector<double>& C, int64_t nnz, std::vector<T>&
   }
 }
 
+constexpr size_t P2M_TABLE_MAX = (size_t)64 << 30;
+
 template <typename T>
 static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>& C, const std::vector<float>& rm2f,
                        double min_leaf_side, int leaf_src, bool direct) {
@@ -247,6 +249,20 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   for (int l = 0; l < nleaf; ++l) {
     if (t.has_tgt[t.lev_off[t.depth] + l]) lt.push_back(l);
     if (t.has_src[t.lev_off[t.depth] + l]) ls.push_back(l);
+  }
+  // heaviest leaves first, so that the block-per-leaf kernels (P2M, leaf
+  // evaluation) do not end on a tail of large leaves
+  {
+    auto nsrc = [&](int l) { return t.src_end[l] - t.src_beg[l]; };
+    std::stable_sort(ls.begin(), ls.end(), [&](int a, int b) { return nsrc(a) > nsrc(b); });
+    std::vector<double> cost(nleaf, 0.0);
+    for (int l : lt) {
+      int64_t us = 0;
+      for (int k = t.ulist_ptr[l]; k < t.ulist_ptr[l + 1]; ++k) us += nsrc(t.ulist[k]);
+      const int nt = t.tgt_end[l] - t.tgt_beg[l];
+      cost[l] = (double)us * nt / std::min(256, 8 * nt);
+    }
+    std::stable_sort(lt.begin(), lt.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   }
   upload(P.leaf_tgt, lt); upload(P.leaf_src, ls);
   std::vector<int> lsv, lsp(1, 0), ltv, ltp(1, 0);
@@ -341,30 +357,6 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     }
     P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);
   }
-  // FP32 P2M tables (the geometry is fixed; see p2m_tables), when they take
-  // less than 8 GiB
-  bool tables = false;
-  if (sizeof(T) == 4 && t.depth >= 2 && 2.0 * 4.0 * (double)No * P.L < 8.0 * (1 << 30)) {
-    tables = true;
-    const double h = t.box_side(t.depth);
-    std::vector<double> xi(3 * (size_t)No), nu(3 * (size_t)No);
-    const int nleaf = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
-    for (int b = 0; b < nleaf; ++b) {
-      const int g = t.lev_off[t.depth] + b;
-      const double c[3] = {t.lo[0] + (t.bx[g] + 0.5) * h, t.lo[1] + (t.by[g] + 0.5) * h, t.lo[2] + (t.bz[g] + 0.5) * h};
-      for (int j = t.src_beg[b]; j < t.src_end[b]; ++j) {
-        const int64_t i = t.src_perm[j];
-        for (int d = 0; d < 3; ++d) {
-          xi[3 * j + d] = (S.s[3 * i + d] - c[d]) / h;
-          nu[3 * j + d] = S.nu[3 * i + d];
-        }
-      }
-    }
-    std::vector<float> Ht((size_t)No * P.L), Dt((size_t)No * P.L);
-    p2m_tables(p, No, xi.data(), nu.data(), h, Ht.data(), Dt.data());
-    upload(P.p2m_H, Ht);
-    upload(P.p2m_D, Dt);
-  }
   // device tree descriptor
   DevTree<T>& D = P.dt;
   D.tx = dptr<T>(P.tx); D.ty = dptr<T>(P.ty); D.tz = dptr<T>(P.tz);
@@ -396,8 +388,24 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.m2m_plan = t.depth >= 2 ? P.m2m_pl.data() : nullptr;
   D.l2l_plan = t.depth >= 2 ? P.l2l_pl.data() : nullptr;
   D.Y = P.Y.p;
-  D.p2m_H = tables ? dptr<float>(P.p2m_H) : nullptr;
-  D.p2m_D = tables ? dptr<float>(P.p2m_D) : nullptr;
+  D.p2m_H = nullptr;
+  D.p2m_D = nullptr;
+  // P2M tables (the geometry is fixed, so the leaf harmonics of every
+  // source can be kept): built on the device when both fit in a quarter of
+  // the free memory and under P2M_TABLE_MAX bytes
+  if (t.depth >= 2 && !(ctx->opts.flags & LB_NO_P2M_TABLES)) {
+    const size_t bytes = 2 * sizeof(T) * (size_t)No * P.L;
+    size_t fr = 0, tot = 0;
+    HIPTRY(hipMemGetInfo(&fr, &tot));
+    if (bytes <= P2M_TABLE_MAX && bytes <= fr / 4) {
+      P.p2m_H.alloc(bytes / 2);
+      P.p2m_D.alloc(bytes / 2);
+      launch_p2m_tables<T>(D, dptr<T>(P.p2m_H), dptr<T>(P.p2m_D), nullptr);
+      HIPTRY(hipDeviceSynchronize());
+      D.p2m_H = dptr<T>(P.p2m_H);
+      D.p2m_D = dptr<T>(P.p2m_D);
+    }
+  }
 }
 
 template <typename T>

@@ -201,39 +201,4 @@ void Translations::build(int p_) {
   }
 }
 
-void p2m_tables(int p, int64_t n, const double* xi, const double* nu, double h, float* H, float* Dp) {
-  const int L = (p + 1) * (p + 1);
-#pragma omp parallel for schedule(static)
-  for (int64_t j = 0; j < n; ++j) {
-    std::vector<cd> R;
-    regular(p, &xi[3 * j], R);
-    const double vx = nu[3 * j], vy = nu[3 * j + 1], vz = nu[3 * j + 2];
-    float* hj = H + (size_t)j * L;
-    float* dj = Dp + (size_t)j * L;
-    auto get = [&](int nn, int mm) -> cd {
-      if (nn < 0 || mm < -nn || mm > nn) return cd(0.0, 0.0);
-      return R[fidx(nn, mm)];
-    };
-    for (int nn = 0; nn <= p; ++nn)
-      for (int m = 0; m <= nn; ++m) {
-        const cd r = R[fidx(nn, m)];
-        // nu . grad Rt_n^m = nz a Rt_{n-1}^m + (nx - i ny) b Rt_{n-1}^{m+1} - (nx + i ny) c Rt_{n-1}^{m-1}
-        const double a = std::sqrt((double)(nn + m) * (nn - m));
-        const double b = 0.5 * std::sqrt((double)std::max((nn - m) * (nn - m - 1), 0));
-        const double c = 0.5 * std::sqrt((double)std::max((nn + m) * (nn + m - 1), 0));
-        const cd g = vz * a * get(nn - 1, m) + cd(vx, -vy) * b * get(nn - 1, m + 1) -
-                     cd(vx, vy) * c * get(nn - 1, m - 1);
-        if (m == 0) {
-          hj[nn * nn] = (float)r.real();
-          dj[nn * nn] = (float)(g.real() / h);
-        } else {
-          hj[nn * nn + 2 * m - 1] = (float)r.real();
-          hj[nn * nn + 2 * m] = (float)(-r.imag());
-          dj[nn * nn + 2 * m - 1] = (float)(g.real() / h);
-          dj[nn * nn + 2 * m] = (float)(-g.imag() / h);
-        }
-      }
-  }
-}
-
 }  // namespace lb

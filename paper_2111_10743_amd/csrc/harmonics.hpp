@@ -30,13 +30,6 @@ struct Translations {
   void build(int p);
 };
 
-// P2M tables of n sources about their leaf centres, scaled by the leaf side
-// h (real layout, L = (p+1)^2 per source):
-//   H[j] = conj(Rt((y_j - c)/h)),  Dp[j] = conj(nu_j . grad Rt((y_j - c)/h)) / h
-// so that a leaf multipole is sum_j q_j H[j] (+ sum_j c_j Dp[j] for dipoles
-// c_j nu_j).  xi: [n][3] scaled offsets, nu: [n][3] unit normals.
-void p2m_tables(int p, int64_t n, const double* xi, const double* nu, double h, float* H, float* Dp);
-
 inline int m2l_offset_id(int ox, int oy, int oz) { return ((ox + 3) * 7 + (oy + 3)) * 7 + (oz + 3); }
 inline int octant_id(int bx, int by, int bz) { return bx | (by << 1) | (bz << 2); }
 

@@ -254,37 +254,142 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
   }
 }
 
-// P2M from precomputed per-source tables (FP32 path): thread per coefficient,
-// M[g][rhs*nexp + e][c] = sum_j q_e[j] H[j][c] (+ sum_j q2[j] Dp[j][c]).
-// grid (leaves with sources, nrhs)
+// P2M tables of the sources of each leaf about the leaf centre (setup):
+//   H[j][c] = conj(Rt_c(xi_j)),  Dp[j][c] = conj(nu_j . grad Rt_c(xi_j)) / h,
+// xi_j = (y_j - centre) / h, real coefficient layout c < L.  A leaf multipole
+// is then sum_j q_j H[j] (+ sum_j q2_j Dp[j] for the dipoles q2_j nu_j).
+// grid: leaves with sources; tiles of ts sources through LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_p2m_tab(DevTree<T> t, int mode, int nrhs, const T* __restrict__ str,
-                                                 int64_t No, const float* __restrict__ H,
-                                                 const float* __restrict__ Dp, T* __restrict__ M) {
+__global__ __launch_bounds__(256) void k_p2m_build(DevTree<T> t, T* __restrict__ H, T* __restrict__ Dp, int ts) {
+  extern __shared__ unsigned char smraw[];
+  const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
+  T* Rre = reinterpret_cast<T*>(smraw);
+  T* Rim = Rre + ts * Lc;
+  T* sn = Rim + ts * Lc;  // [3][ts]
+  const int b = t.leaf_src_list[blockIdx.x];
+  const int g = t.leaf_off + b;
+  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T ih = (T)1 / h;
+  const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
+  const int beg = t.src_beg[b], end = t.src_end[b];
+  for (int t0 = beg; t0 < end; t0 += ts) {
+    const int nt = min(ts, end - t0);
+    for (int task = threadIdx.x; task < nt * (p + 1); task += blockDim.x) {
+      const int j = task / (p + 1), m = task - j * (p + 1);
+      const int s = t0 + j;
+      regular_column_to_lds<T>(p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
+                               Rim + j * Lc);
+    }
+    if (threadIdx.x < nt) {
+      const int s = t0 + threadIdx.x;
+      sn[threadIdx.x] = t.snx[s];
+      sn[ts + threadIdx.x] = t.sny[s];
+      sn[2 * ts + threadIdx.x] = t.snz[s];
+    }
+    __syncthreads();
+    for (int task = threadIdx.x; task < nt * L; task += blockDim.x) {
+      const int jj = task / L, c = task - jj * L;
+      int n, m, part;
+      rdecode(c, n, m, part);
+      const T sgn = part ? (T)-1 : (T)1;  // conj
+      const T* re = Rre + jj * Lc;
+      const T* im = Rim + jj * Lc;
+      const T v = part ? im[cidx(n, m)] : re[cidx(n, m)];
+      // nu . grad Rt_n^m = nz fa R_{n-1}^m + (nx - i ny) fb R_{n-1}^{m+1} - (nx + i ny) fc R_{n-1}^{m-1}
+      const T fa = sqrt((T)((n + m) * (n - m)));
+      const T fb = (T)0.5 * sqrt((T)((n - m) * (n - m - 1) > 0 ? (n - m) * (n - m - 1) : 0));
+      const T fc = (T)0.5 * sqrt((T)((n + m) * (n + m - 1) > 0 ? (n + m) * (n + m - 1) : 0));
+      const T nx = sn[jj], ny = sn[ts + jj], nz = sn[2 * ts + jj];
+      T a0, b0, a1, b1, a2, b2;
+      rt_get(re, im, n - 1, m, a0, b0);
+      rt_get(re, im, n - 1, m + 1, a1, b1);
+      rt_get(re, im, n - 1, m - 1, a2, b2);
+      const T gre = nz * fa * a0 + fb * (nx * a1 + ny * b1) - fc * (nx * a2 - ny * b2);
+      const T gim = nz * fa * b0 + fb * (nx * b1 - ny * a1) - fc * (nx * b2 + ny * a2);
+      const int64_t o = (int64_t)(t0 + jj) * L + c;
+      H[o] = sgn * v;
+      Dp[o] = sgn * (part ? gim : gre) * ih;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void launch_p2m_tables(const DevTree<T>& t, T* H, T* Dp, hipStream_t st) {
+  if (t.depth < 2 || t.n_leaf_src == 0) return;
+  const int Lc = (t.p + 1) * (t.p + 2) / 2;
+  int ts = (int)((48 * 1024 / sizeof(T)) / (2 * Lc + 3));
+  ts = ts < 1 ? 1 : (ts > 64 ? 64 : ts);
+  const size_t sm = sizeof(T) * (size_t)ts * (2 * Lc + 3);
+  hipLaunchKernelGGL(k_p2m_build<T>, dim3(t.n_leaf_src), dim3(256), sm, st, t, H, Dp, ts);
+  KCHECK();
+}
+
+// P2M from the tables: M[g][rhs*nexp + e] = sum_j q_e[j] H[j] (+ Dp for the
+// dipoles).  Each of the P2M_W waves of a block sums every P2M_W-th source
+// of the leaf over 256 coefficients (4 per lane); the wave partials meet in
+// LDS.  grid (leaves with sources, nrhs), block 64 * P2M_W
+constexpr int P2M_W = 8;
+
+template <typename T, bool A3B>
+__global__ __launch_bounds__(64 * P2M_W) void k_p2m_tab(DevTree<T> t, int nrhs, const T* __restrict__ str,
+                                                        int64_t No, const T* __restrict__ H,
+                                                        const T* __restrict__ Dp, T* __restrict__ M) {
+  constexpr int NE = A3B ? 3 : 1;
+  __shared__ T red[NE][P2M_W][256];
   const int b = t.leaf_src_list[blockIdx.x];
   const int g = t.leaf_off + b;
   const int rhs = blockIdx.y;
   const int L = t.L;
-  const int nexp = fmm_nexp(mode), nstr = fmm_nstr(mode);
+  const int nstr = A3B ? 2 : 1;
   const int beg = t.src_beg[b], end = t.src_end[b];
   const T* q1 = str + (int64_t)(rhs * nstr) * No;
-  const T* q2 = mode == FMM_A3B ? str + (int64_t)(rhs * nstr + 1) * No : q1;
-  for (int c = threadIdx.x; c < L; c += blockDim.x) {
-    T a0 = 0, a1 = 0, a2 = 0;
-    for (int j = beg; j < end; ++j) {
-      const T hv = (T)H[(int64_t)j * L + c];
-      a0 += q1[j] * hv;
-      if (mode == FMM_A3B) {
-        a1 += q2[j] * hv;
-        a2 += q2[j] * (T)Dp[(int64_t)j * L + c];
+  const T* q2 = A3B ? str + (int64_t)(rhs * nstr + 1) * No : q1;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T* out = M + ((int64_t)g * nrhs * NE + rhs * NE) * L;
+  for (int c0 = 0; c0 < L; c0 += 256) {
+    T a[NE][4];
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[e][k] = 0;
+    bool ok[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ok[k] = c0 + lane + 64 * k < L;
+#pragma unroll 2
+    for (int j = beg + w; j < end; j += P2M_W) {
+      const T s1 = q1[j];
+      const T s2 = q2[j];
+      const T* hr = H + (int64_t)j * L + c0 + lane;
+      const T* dr = Dp + (int64_t)j * L + c0 + lane;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (ok[k]) {
+          const T hv = hr[64 * k];
+          a[0][k] += s1 * hv;
+          if (A3B) {
+            a[1][k] += s2 * hv;
+            a[2][k] += s2 * dr[64 * k];
+          }
+        }
       }
     }
-    T* out = M + ((int64_t)g * nrhs * nexp + rhs * nexp) * L + c;
-    out[0] = a0;
-    if (mode == FMM_A3B) {
-      out[L] = a1;
-      out[2 * L] = a2;
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[e][w][lane + 64 * k] = a[e][k];
+    __syncthreads();
+    const int c = c0 + threadIdx.x;
+    if (threadIdx.x < 256 && c < L) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        T sum = 0;
+#pragma unroll
+        for (int v = 0; v < P2M_W; ++v) sum += red[e][v][threadIdx.x];
+        out[e * L + c] = sum;
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -550,9 +655,9 @@ __device__ void derive3(const T* src, int pin, T* dx, T* dy, T* dz) {
 }
 
 constexpr int LEAF_BS = 256;
-constexpr int LEAF_FMAX = 8;                   // at most 8 threads per target
+constexpr int LEAF_FMAX = 64;                  // at most one wave per target
 
-// Each target of a leaf gets F = min(8, 256 / targets) threads (a power of
+// Each target of a leaf gets F = min(64, 256 / targets) threads (a power of
 // two): thread (slot, f) works for target slot `slot` of the current pass,
 // the far field over the harmonic orders m = f (mod F), the near field over
 // the source indices j = f (mod F) of each LDS chunk; the F partial sums of
@@ -827,9 +932,12 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     int ts = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
-    if (t.p2m_H)
-      hipLaunchKernelGGL(k_p2m_tab<T>, dim3(t.n_leaf_src, nrhs), dim3(256), 0, st, t, mode, nrhs, str, No, t.p2m_H,
-                         t.p2m_D, M);
+    if (t.p2m_H && mode == FMM_A3B)
+      hipLaunchKernelGGL((k_p2m_tab<T, true>), dim3(t.n_leaf_src, nrhs), dim3(64 * P2M_W), 0, st, t, nrhs, str, No,
+                         t.p2m_H, t.p2m_D, M);
+    else if (t.p2m_H)
+      hipLaunchKernelGGL((k_p2m_tab<T, false>), dim3(t.n_leaf_src, nrhs), dim3(64 * P2M_W), 0, st, t, nrhs, str, No,
+                         t.p2m_H, t.p2m_D, M);
     else
       hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
     KCHECK();
@@ -1262,7 +1370,8 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
                                       const T*, const int*, const T*, T*, T*, int64_t, hipStream_t);             \
   template void launch_combine_a3b<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
                                       const T*, const T*, int64_t, const T*, const int*, const T*, const double*, \
-                                      double, T*, double*, hipStream_t);
+                                      double, T*, double*, hipStream_t);                                     \
+  template void launch_p2m_tables<T>(const DevTree<T>&, T*, T*, hipStream_t);
 INST(float)
 INST(double)
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);

@@ -60,13 +60,18 @@ struct DevTree {
   const GemmPlan* m2m_plan;   //   M2L over all levels; M2M and L2L indexed by level
   const GemmPlan* l2l_plan;
   void* Y;                    // column scratch [max columns * 8][L]
-  const float *p2m_H, *p2m_D; // per-source P2M tables [No][L] in tree order (nullable)
+  const T *p2m_H, *p2m_D;     // per-source P2M tables [No][L] in tree order (nullable)
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities
 template <typename T>
 void launch_strengths(const T* tau, int ne, int64_t N, int NP, int n_p, int n_o, const T* P,
                       const T* wo, const int* src_pos, int64_t No, T* str, hipStream_t st);
+
+// P2M tables of every source about its leaf centre (setup): H, Dp [No][L]
+// in tree order; see k_p2m_build
+template <typename T>
+void launch_p2m_tables(const DevTree<T>& t, T* H, T* Dp, hipStream_t st);
 
 // full FMM (or direct sums when depth < 2): str [nrhs*nstr][No] -> out [nrhs*nout][N]
 // Optional phase timer: events recorded on the launch stream at the phase

@@ -27,6 +27,7 @@ LB_SOLVE_FP32_REFINE = 1
 LB_STRICT_MEAN = 1
 LB_HOST_ONLY = 2
 LB_DIRECT = 4
+LB_NO_P2M_TABLES = 8
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_timed", "lb_apply_A3",
@@ -126,7 +127,7 @@ def _ptr(t):
 class Surface:
     """One discretized surface: lb_setup ... lb_destroy."""
 
-    def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, **kw):
+    def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, p2m_tables=True, **kw):
         X = np.ascontiguousarray(X, dtype=np.float64)
         Xu = np.ascontiguousarray(Xu, dtype=np.float64)
         Xv = np.ascontiguousarray(Xv, dtype=np.float64)
@@ -137,6 +138,8 @@ class Surface:
             o.flags |= LB_HOST_ONLY
         if direct:
             o.flags |= LB_DIRECT
+        if not p2m_tables:
+            o.flags |= LB_NO_P2M_TABLES
         self.order = order
         self.host_only = host_only
         self._ctx = ctypes.c_void_p()

@@ -113,16 +113,18 @@ def test_c1_solve(torch_dev, c1_oracle, mode):
     s.close()
 
 
-@pytest.mark.parametrize("kind,k,n", [("sphere", 4, 3), ("ellipsoid", 6, 2)])
-def test_fmm_sampled_rows(torch_dev, kind, k, n):
-    """FMM path (several levels, V-lists) against the oracle on sampled rows."""
+@pytest.mark.parametrize("kind,k,n,tables", [("sphere", 4, 3, True), ("sphere", 4, 3, False),
+                                              ("ellipsoid", 6, 2, True)])
+def test_fmm_sampled_rows(torch_dev, kind, k, n, tables):
+    """FMM path (several levels, V-lists) against the oracle on sampled rows,
+    with P2M from the per-source tables and from on-the-fly harmonics."""
     torch = torch_dev
     import paper_2111_10743_amd as P
     from oracle.geometry import Geometry
     from oracle.ops import Oracle
     X, Xu, Xv = make(kind, k, n)
-    note(f"fmm {kind} k={k} nsub={n} setup")
-    s = P.Surface(X, Xu, Xv, k)
+    note(f"fmm {kind} k={k} nsub={n} tables={tables} setup")
+    s = P.Surface(X, Xu, Xv, k, p2m_tables=tables)
     note(f"fmm {kind} sizes {s.sizes}")
     g = Geometry(X, Xu, Xv, k)
     rows = np.arange(0, g.N, max(1, g.N // 300))
