@@ -359,24 +359,25 @@ __global__ __launch_bounds__(64 * P2M_W) void k_p2m_tab(DevTree<T> t, int nrhs, 
     for (int e = 0; e < NE; ++e)
 #pragma unroll
       for (int k = 0; k < 4; ++k) a[e][k] = 0;
-    bool ok[4];
+    // coefficient of slot k of this lane, clamped into the row: lanes past
+    // L sum a copy of coefficient L-1 and are never stored (no predicated
+    // loads in the loop)
+    int cc[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ok[k] = c0 + lane + 64 * k < L;
-#pragma unroll 4
+    for (int k = 0; k < 4; ++k) cc[k] = min(c0 + lane + 64 * k, L - 1);
+#pragma unroll(A3B && sizeof(T) == 8 ? 2 : 4)
     for (int j = beg + w; j < end; j += P2M_W) {
       const T s1 = q1[j];
       const T s2 = q2[j];
-      const T* hr = H + (int64_t)j * L + c0 + lane;
-      const T* dr = Dp + (int64_t)j * L + c0 + lane;
+      const T* hr = H + (int64_t)j * L;
+      const T* dr = Dp + (int64_t)j * L;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (ok[k]) {
-          const T hv = hr[64 * k];
-          a[0][k] += s1 * hv;
-          if (A3B) {
-            a[1][k] += s2 * hv;
-            a[2][k] += s2 * dr[64 * k];
-          }
+        const T hv = hr[cc[k]];
+        a[0][k] += s1 * hv;
+        if (A3B) {
+          a[1][k] += s2 * hv;
+          a[2][k] += s2 * dr[cc[k]];
         }
       }
     }
@@ -521,25 +522,35 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
     srcrow[threadIdx.x] = c < cend ? pair_src[c / ne] * ne + (c % ne) : -1;
   }
   __syncthreads();
-  // this thread's tile elements: A (kk, r) = (i / 128, i % 128) and
-  // B (c, kk) = (i / KC, i % KC) for i = threadIdx.x + 256 u
+  // this thread's tile elements, i = threadIdx.x + 256 u: A (kk, r) =
+  // (i / 128, i % 128), B (c, kk) = (i / KC, i % KC).  Loads are unguarded
+  // (indices clamped into the matrix and the source rows) and zeroed by a
+  // select where k >= L or the column is empty.
+  static_assert(256 % (GM_RB * 16) == 0 && 256 % KC == 0, "tile shape");
+  const int ar = min(r0 + (int)(threadIdx.x % (GM_RB * 16)), L - 1);
+  const int akk = threadIdx.x / (GM_RB * 16);
+  const int bkk = threadIdx.x % KC;
+  const T* bp[NB];
+  T bv[NB];  // 1 for a column in use, else 0 (a factor, so that no load is predicated)
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int sr = srcrow[(threadIdx.x + 256 * u) / KC];
+    bv[u] = sr >= 0 ? (T)1 : (T)0;
+    bp[u] = M + (int64_t)(sr >= 0 ? sr : 0) * L;
+  }
   T ra[NA], rb_[NB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int i = threadIdx.x + 256 * u;
-      const int kk = i / (GM_RB * 16), r = i - kk * (GM_RB * 16);
-      const int k = k0 + kk, rr = r0 + r;
-      ra[u] = (k < L && rr < L) ? Tm[(int64_t)k * L + rr] : (T)0;
+      const int k = k0 + akk + u * (256 / (GM_RB * 16));
+      const T v = Tm[(int64_t)min(k, L - 1) * L + ar];
+      ra[u] = k < L ? v : (T)0;
     }
+    const int k = k0 + bkk;
+    const int kc = min(k, L - 1);
+    const T kv = k < L ? (T)1 : (T)0;
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int i = threadIdx.x + 256 * u;
-      const int c = i / KC, kk = i - c * KC;
-      const int k = k0 + kk;
-      const int sr = srcrow[c];
-      rb_[u] = (sr >= 0 && k < L) ? M[(int64_t)sr * L + k] : (T)0;
-    }
+    for (int u = 0; u < NB; ++u) rb_[u] = bp[u][kc] * (bv[u] * kv);
   };
   typename Mfma<T>::acc acc[GM_RB];
 #pragma unroll
@@ -1048,40 +1059,88 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_combine_grad(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+// Correction rows: one wave per target row.  The row's blocks of n_p
+// contiguous columns are spread over the wave as segments of SW lanes
+// (SW = 32 for n_p <= 32, else 64): f(entry, column, on) is called for
+// every (block, node) pair of the row, with indices clamped into the row so
+// that no load is predicated (on = false marks the clamped duplicates, whose
+// contribution the caller zeroes).  The patch numbers of up to 64 blocks are
+// loaded at once, one per lane, into this wave's 64-int LDS slice `pat`.
+template <typename F>
+__device__ __forceinline__ void row_blocks(int64_t b0, int64_t b1, int n_p, int lane, const int* __restrict__ patch,
+                                           int* pat, F&& f) {
+  const int SW = n_p <= 32 ? 32 : 64;
+  const int sub = lane / SW, j0 = lane - sub * SW, nsub = 64 / SW, NJ = (n_p + SW - 1) / SW;
+  // the row is the same for the whole wave: keep its bounds in scalar registers
+  b0 = (int64_t)__builtin_amdgcn_readfirstlane((int)b0) |
+       ((int64_t)__builtin_amdgcn_readfirstlane((int)(b0 >> 32)) << 32);
+  const int nb = __builtin_amdgcn_readfirstlane((int)(b1 - b0));
+  for (int base = 0; base < nb; base += 64) {
+    const int nbb = min(64, nb - base);
+    __builtin_amdgcn_wave_barrier();
+    pat[lane] = patch[b0 + base + min(lane, nbb - 1)];
+    __builtin_amdgcn_wave_barrier();
+    if (NJ == 1) {  // n_p <= 64: one node per lane and block
+      const int jc = min(j0, n_p - 1);
+      const bool okj = j0 < n_p;
+#pragma unroll 4
+      for (int q0 = 0; q0 < nbb; q0 += nsub) {
+        const int q = min(q0 + sub, nbb - 1);
+        const int64_t pc = (int64_t)pat[q] * n_p;
+        f((b0 + base + q) * n_p + jc, pc + jc, okj && q0 + sub < nbb);
+      }
+    } else {
+      for (int q0 = 0; q0 < nbb; q0 += nsub) {
+        const int q = min(q0 + sub, nbb - 1);
+        const bool okb = q0 + sub < nbb;
+        const int64_t pc = (int64_t)pat[q] * n_p;
+        const int64_t eb = (b0 + base + q) * n_p;
+        for (int jt = 0; jt < NJ; ++jt) {
+          const int j = j0 + jt * SW;
+          const int jc = min(j, n_p - 1);
+          f(eb + jc, pc + jc, okb && j < n_p);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void k_combine_grad(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
                                                       const int* __restrict__ patch, const T* __restrict__ vals,
                                                       const T* __restrict__ sigma, const T* __restrict__ fmm,
                                                       const int* __restrict__ tgt_pos, const T* __restrict__ nrm,
                                                       T* pot, T* grad, T* dSdn, T* surf) {
+  typedef typename Vec4<T>::type T4;
+  __shared__ int pat_s[4][64];
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= N) return;
-  const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
-  const int64_t ne = (b1 - b0) * n_p;
-  T acc[NDMAX][4];
+  T acc[ND][4];
 #pragma unroll
-  for (int d = 0; d < NDMAX; ++d)
+  for (int d = 0; d < ND; ++d)
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[d][k] = 0;
-  const T* v = vals + b0 * n_p * 4;
-  for (int64_t e = lane; e < ne; e += 64) {
-    const int64_t blk = e / n_p;
-    const int j = (int)(e - blk * n_p);
-    const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
-    const T c0 = v[4 * e], c1 = v[4 * e + 1], c2 = v[4 * e + 2], c3 = v[4 * e + 3];
-    for (int d = 0; d < nd; ++d) {
-      const T x = sigma[(int64_t)d * N + col];
-      acc[d][0] += c0 * x; acc[d][1] += c1 * x; acc[d][2] += c2 * x; acc[d][3] += c3 * x;
+  const T4* v4 = reinterpret_cast<const T4*>(vals);
+  row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[threadIdx.x >> 6], [&](int64_t e, int64_t col, bool on) {
+    const T4 c = v4[e];
+    const T m = on ? (T)1 : (T)0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const T x = sigma[(int64_t)d * N + col] * m;
+      acc[d][0] += c.x * x; acc[d][1] += c.y * x; acc[d][2] += c.z * x; acc[d][3] += c.w * x;
     }
-  }
-  for (int d = 0; d < nd; ++d)
+  });
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
     for (int k = 0; k < 4; ++k) acc[d][k] = wave_sum(acc[d][k]);
   if (lane == 0) {
     const int tp = tgt_pos[row];
     const T n0 = nrm[3 * row], n1 = nrm[3 * row + 1], n2 = nrm[3 * row + 2];
     const T s = (T)INV4PI_D;
-    for (int d = 0; d < nd; ++d) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
       const T* f = fmm + (int64_t)d * 4 * N;
       const T P = f[tp] * s + acc[d][0];
       const T gx = f[N + tp] * s + acc[d][1];
@@ -1104,52 +1163,62 @@ __global__ __launch_bounds__(256) void k_combine_grad(int nd, int64_t N, int n_p
   }
 }
 
+// launch a kernel templated on the number of densities ND = 1..NDMAX
+#define ND_DISPATCH(KERNEL, ND_, ...)                                                         \
+  switch (ND_) {                                                                              \
+    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), __VA_ARGS__); break;                          \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), __VA_ARGS__); break;                          \
+    case 3: hipLaunchKernelGGL((KERNEL<T, 3>), __VA_ARGS__); break;                          \
+    default: hipLaunchKernelGGL((KERNEL<T, 4>), __VA_ARGS__); break;                         \
+  }
+
 template <typename T>
 void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                          const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
                          const T* nrm, T* pot, T* grad, T* dSdn, T* surf, hipStream_t st) {
   for (int d0 = 0; d0 < nd; d0 += NDMAX) {
     int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
-    hipLaunchKernelGGL(k_combine_grad<T>, dim3((N + 3) / 4), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals4,
-                       sigma + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm,
-                       pot ? pot + (int64_t)d0 * N : nullptr, grad ? grad + (int64_t)d0 * 3 * N : nullptr,
-                       dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr);
+    ND_DISPATCH(k_combine_grad, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals4,
+                sigma + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm,
+                pot ? pot + (int64_t)d0 * N : nullptr, grad ? grad + (int64_t)d0 * 3 * N : nullptr,
+                dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr)
     KCHECK();
   }
 }
 
 // A3 step 1: mu2 = S tau, mu1 = S' tau  (vals3 columns: S, S', S''+D')
-template <typename T>
-__global__ __launch_bounds__(256) void k_combine_a3a(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void k_combine_a3a(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
                                                      const int* __restrict__ patch, const T* __restrict__ vals,
                                                      const T* __restrict__ tau, const T* __restrict__ fmm,
                                                      const int* __restrict__ tgt_pos, const T* __restrict__ nrm,
                                                      T* mu1, T* mu2, int64_t ldmu) {
+  __shared__ int pat_s[4][64];
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= N) return;
-  const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
-  const int64_t ne = (b1 - b0) * n_p;
-  T aS[NDMAX], aP[NDMAX];
-  for (int d = 0; d < NDMAX; ++d) { aS[d] = 0; aP[d] = 0; }
-  const T* v = vals + b0 * n_p * 3;
-  for (int64_t e = lane; e < ne; e += 64) {
-    const int64_t blk = e / n_p;
-    const int j = (int)(e - blk * n_p);
-    const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
-    const T c0 = v[3 * e], c1 = v[3 * e + 1];
-    for (int d = 0; d < nd; ++d) {
-      const T x = tau[(int64_t)d * N + col];
+  T aS[ND], aP[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) { aS[d] = 0; aP[d] = 0; }
+  row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[threadIdx.x >> 6], [&](int64_t e, int64_t col, bool on) {
+    const T* c = vals + e * 3;
+    const T c0 = c[0], c1 = c[1];
+    const T m = on ? (T)1 : (T)0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const T x = tau[(int64_t)d * N + col] * m;
       aS[d] += c0 * x;
       aP[d] += c1 * x;
     }
-  }
-  for (int d = 0; d < nd; ++d) { aS[d] = wave_sum(aS[d]); aP[d] = wave_sum(aP[d]); }
+  });
+#pragma unroll
+  for (int d = 0; d < ND; ++d) { aS[d] = wave_sum(aS[d]); aP[d] = wave_sum(aP[d]); }
   if (lane == 0) {
     const int tp = tgt_pos[row];
     const T n0 = nrm[3 * row], n1 = nrm[3 * row + 1], n2 = nrm[3 * row + 2];
     const T s = (T)INV4PI_D;
-    for (int d = 0; d < nd; ++d) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
       const T* f = fmm + (int64_t)d * 4 * N;
       mu2[(int64_t)d * ldmu + row] = f[tp] * s + aS[d];
       mu1[(int64_t)d * ldmu + row] = (n0 * f[N + tp] + n1 * f[2 * N + tp] + n2 * f[3 * N + tp]) * s + aP[d];
@@ -1163,17 +1232,17 @@ void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, cons
                         const T* nrm, T* mu1, T* mu2, int64_t ldmu, hipStream_t st) {
   for (int d0 = 0; d0 < nd; d0 += NDMAX) {
     int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
-    hipLaunchKernelGGL(k_combine_a3a<T>, dim3((N + 3) / 4), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals3,
-                       tau + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm, mu1 + (int64_t)d0 * ldmu,
-                       mu2 + (int64_t)d0 * ldmu, ldmu);
+    ND_DISPATCH(k_combine_a3a, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3,
+                tau + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm, mu1 + (int64_t)d0 * ldmu,
+                mu2 + (int64_t)d0 * ldmu, ldmu)
     KCHECK();
   }
 }
 
 // A3 step 2: per row y1 = S'mu1, y2 = S mu2, y3 = S'mu2, y4 = (S''+D')mu2;
 // out = -tau/4 + y1 - y4 - 2 H y3 ; partial[block][d] = sum_rows w y2
-template <typename T>
-__global__ __launch_bounds__(256) void k_combine_a3b(int nd, int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void k_combine_a3b(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
                                                      const int* __restrict__ patch, const T* __restrict__ vals,
                                                      const T* __restrict__ tau, const T* __restrict__ mu1,
                                                      const T* __restrict__ mu2, int64_t ldmu, const T* __restrict__ fmm,
@@ -1181,38 +1250,40 @@ __global__ __launch_bounds__(256) void k_combine_a3b(int nd, int64_t N, int n_p,
                                                      const double* __restrict__ w, T* out, double* partial,
                                                      int nblk) {
   __shared__ double red[4][NDMAX];
+  __shared__ int pat_s[4][64];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wv;
-  double wy[NDMAX];
-  for (int d = 0; d < NDMAX; ++d) wy[d] = 0;
+  double wy[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) wy[d] = 0;
   if (row < N) {
-    const int64_t b0 = row_ptr[row], b1 = row_ptr[row + 1];
-    const int64_t ne = (b1 - b0) * n_p;
-    T a1[NDMAX], a2[NDMAX], a3[NDMAX], a4[NDMAX];
-    for (int d = 0; d < NDMAX; ++d) { a1[d] = a2[d] = a3[d] = a4[d] = 0; }
-    const T* v = vals + b0 * n_p * 3;
-    for (int64_t e = lane; e < ne; e += 64) {
-      const int64_t blk = e / n_p;
-      const int j = (int)(e - blk * n_p);
-      const int64_t col = (int64_t)patch[b0 + blk] * n_p + j;
-      const T cS = v[3 * e], cP = v[3 * e + 1], cD = v[3 * e + 2];
-      for (int d = 0; d < nd; ++d) {
-        const T x1 = mu1[(int64_t)d * ldmu + col];
-        const T x2 = mu2[(int64_t)d * ldmu + col];
+    T a1[ND], a2[ND], a3[ND], a4[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) { a1[d] = a2[d] = a3[d] = a4[d] = 0; }
+    row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[threadIdx.x >> 6], [&](int64_t e, int64_t col, bool on) {
+      const T* c = vals + e * 3;
+      const T cS = c[0], cP = c[1], cD = c[2];
+      const T m = on ? (T)1 : (T)0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const T x1 = mu1[(int64_t)d * ldmu + col] * m;
+        const T x2 = mu2[(int64_t)d * ldmu + col] * m;
         a1[d] += cP * x1;
         a2[d] += cS * x2;
         a3[d] += cP * x2;
         a4[d] += cD * x2;
       }
-    }
-    for (int d = 0; d < nd; ++d) {
+    });
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
       a1[d] = wave_sum(a1[d]); a2[d] = wave_sum(a2[d]); a3[d] = wave_sum(a3[d]); a4[d] = wave_sum(a4[d]);
     }
     if (lane == 0) {
       const int tp = tgt_pos[row];
       const T s = (T)INV4PI_D;
-      for (int d = 0; d < nd; ++d) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
         const T* f = fmm + (int64_t)d * 4 * N;
         const T y1 = f[tp] * s + a1[d];
         const T y2 = f[N + tp] * s + a2[d];
@@ -1224,10 +1295,12 @@ __global__ __launch_bounds__(256) void k_combine_a3b(int nd, int64_t N, int n_p,
     }
   }
   if (lane == 0)
-    for (int d = 0; d < NDMAX; ++d) red[wv][d] = wy[d];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) red[wv][d] = wy[d];
   __syncthreads();
   if (threadIdx.x == 0)
-    for (int d = 0; d < nd; ++d) partial[(int64_t)d * nblk + blockIdx.x] = red[0][d] + red[1][d] + red[2][d] + red[3][d];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) partial[(int64_t)d * nblk + blockIdx.x] = red[0][d] + red[1][d] + red[2][d] + red[3][d];
 }
 
 // serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
@@ -1263,9 +1336,9 @@ void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, cons
   for (int d0 = 0; d0 < nd; d0 += NDMAX) {
     int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
     double* sc = partial + (int64_t)NDMAX * nblk;  // NDMAX scalars after the partials
-    hipLaunchKernelGGL(k_combine_a3b<T>, dim3(nblk), dim3(256), 0, st, ndc, N, n_p, row_ptr, patch, vals3,
-                       tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * ldmu, mu2 + (int64_t)d0 * ldmu, ldmu,
-                       fmm + (int64_t)d0 * 4 * N, tgt_pos, H, w, out + (int64_t)d0 * N, partial, nblk);
+    ND_DISPATCH(k_combine_a3b, ndc, dim3(nblk), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3,
+                tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * ldmu, mu2 + (int64_t)d0 * ldmu, ldmu,
+                fmm + (int64_t)d0 * 4 * N, tgt_pos, H, w, out + (int64_t)d0 * N, partial, nblk)
     KCHECK();
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblk, ndc, inv_area, sc);
     KCHECK();
