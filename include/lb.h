@@ -144,6 +144,28 @@ lb_status lb_apply_gradS(lb_ctx *ctx, int nd, int prec, const void *sigma,
                          void *pot, void *grad, void *dSdn, void *surf_grad,
                          void *stream);
 
+/* Adjoint of lb_apply_gradS with respect to the density: the exact transpose
+ * of the discrete operators of the same precision (far sum over the
+ * oversampled rule of Section 4 with its near mask, block corrections of
+ * eq. nys-lcq2, oversampling tau~ = P tau):
+ *   sigma_bar = S^T gpot + (grad S)^T ggrad + S'^T gdSdn + (grad_Gamma S)^T gsurf
+ * with S' = n . grad S and grad_Gamma S = grad S - n (n . grad S) as in
+ * lb_apply_gradS.  Cotangents: device gpot [nd][N], ggrad [nd][N][3],
+ * gdSdn [nd][N], gsurf [nd][N][3], each nullable (not all); sigma_bar:
+ * device [nd][N], overwritten.  The far part is an FMM with the N nodes as
+ * sources (charge gpot, dipole vector formed from the other cotangents) and
+ * the N_o oversampled points as targets.  The first call for a precision
+ * builds the transposed octree and correction index on the host and
+ * synchronizes the device; later calls are stream ordered on `stream`. */
+lb_status lb_apply_gradS_adj(lb_ctx *ctx, int nd, int prec, const void *gpot,
+                             const void *ggrad, const void *gdSdn, const void *gsurf,
+                             void *sigma_bar, void *stream);
+
+/* Adjoint of lb_apply_S: sigma_bar = S^T gbar (see lb_apply_gradS_adj).
+ * gbar, sigma_bar: device [nd][N]. */
+lb_status lb_apply_S_adj(lb_ctx *ctx, int nd, int prec, const void *gbar, void *sigma_bar,
+                         void *stream);
+
 /* lb_apply_gradS with per-phase timing (nd <= 8): HIP events recorded on
  * `stream` around each phase of the apply; synchronizes `stream`.
  * phase_ms: host [7], milliseconds of: density oversampling, P2M, M2M, M2L,

@@ -118,7 +118,7 @@ class Oracle:
         for p in range(g.NP):
             Pfull[p * g.n_o:(p + 1) * g.n_o, p * g.n_p:(p + 1) * g.n_p] = g.re.P
         Pw = g.wo[:, None] * Pfull
-        M = np.einsum('krs,sn->krn', self._K, Pw)
+        M = self._K @ Pw
         cr = self.corr
         for j in range(len(cr.patch)):
             r = cr.rows[j]
@@ -138,6 +138,32 @@ class Oracle:
         sp = L[:, 4]
         surf = grad - n * (grad * n).sum(-1, keepdims=True)
         return L[:, 0], grad, sp, surf
+
+    def adjoint_gradS(self, gpot=None, ggrad=None, gdSdn=None, gsurf=None):
+        """Transpose of the discrete apply_gradS operator (all rows, small N).
+
+        sigma_bar = S^T gpot + G^T gg with G = the three gradient rows
+        (dS/dx1..3) and gg = ggrad + n gdSdn + (gsurf - n (n . gsurf)): the
+        chain rule of S' = n . grad S and grad_Gamma S = grad S - n (n . grad S)
+        (Section 4.1).  Each cotangent is optional.
+        """
+        g = self.g
+        assert len(self.targets) == g.N
+        if getattr(self, "_M", None) is None:
+            self._M = self.operator_matrices()
+        M = self._M
+        n = g.n
+        gg = np.zeros((g.N, 3))
+        if ggrad is not None:
+            gg += ggrad
+        if gdSdn is not None:
+            gg += n * gdSdn[:, None]
+        if gsurf is not None:
+            gg += gsurf - n * (gsurf * n).sum(-1, keepdims=True)
+        out = np.einsum('kr,krn->n', gg.T, M[1:4])
+        if gpot is not None:
+            out += M[0].T @ gpot
+        return out
 
     def W(self, phi):
         g = self.g

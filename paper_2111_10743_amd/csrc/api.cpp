@@ -117,7 +117,7 @@ struct Prec {
   int p = 0, L = 0;
   Octree tree;
   DevTree<T> dt{};
-  DBuf tx, ty, tz, tnx, tny, tnz, sx, sy, sz, snx, sny, snz, rm2, bcx, bcy, bcz;
+  DBuf tx, ty, tz, tnx, tny, tnz, sx, sy, sz, snx, sny, snz, rm2, trm2, bcx, bcy, bcz;
   DBuf tgt_beg, tgt_end, src_beg, src_end, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off;
   DBuf parent, child, child_src, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
   DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
@@ -149,6 +149,15 @@ struct lb_ctx {
   Prec<float> f32;
   Prec<double> f64;
   DBuf row_ptr, patch, w;
+  // adjoint applies (built on first use): transposed trees, transposed
+  // block-CSR of the corrections (per patch: (row, block) entries), the FP32
+  // mask radii and the FP32 tree's minimum leaf side
+  Prec<float> a32;
+  Prec<double> a64;
+  bool adj_built32 = false, adj_built64 = false;
+  DBuf cptr, crow, cblk, g4;
+  bool csr_t_built = false;
+  std::vector<float> rm2f;
   // solver workspace
   DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp;
   int v_cols = 0;
@@ -194,31 +203,49 @@ static void pack_vals(const std::vector<double>& C, int64_t nnz, std::vector<T>&
 
 constexpr size_t P2M_TABLE_MAX = (size_t)64 << 30;
 
+// Device state of one precision.  With `fwd` set, the transposed problem of
+// the adjoint applies: the Nystrom nodes are the sources and the oversampled
+// points the targets (a tree of the same depth over the same points, so the
+// same boxes), the mask radius moves with the oversampled point to the
+// target side, and the reference matrices, corrections and translation
+// operators are those of `fwd`.
 template <typename T>
 static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>& C, const std::vector<float>& rm2f,
-                       double min_leaf_side, int leaf_src, bool direct) {
+                       double min_leaf_side, int leaf_src, bool direct, const Prec<T>* fwd = nullptr) {
   const Surface& S = ctx->S;
+  const bool adj = fwd != nullptr;
   P.p = p;
   P.L = (p + 1) * (p + 1);
-  P.tree.build(S.X.data(), S.N, S.s.data(), S.No, leaf_src, min_leaf_side, direct ? 0 : -1);
+  // tree order of targets and sources: (X, nrm) are the nodes, (s, nu) the
+  // oversampled points
+  const std::vector<double>& TX = adj ? S.s : S.X;
+  const std::vector<double>& TN = adj ? S.nu : S.nrm;
+  const std::vector<double>& SX = adj ? S.X : S.s;
+  const std::vector<double>& SN = adj ? S.nrm : S.nu;
+  const int64_t N = adj ? S.No : S.N, No = adj ? S.N : S.No;  // targets, sources of this tree
+  if (adj)
+    P.tree.build(TX.data(), N, SX.data(), No, leaf_src, 0.0, fwd->tree.depth);
+  else
+    P.tree.build(TX.data(), N, SX.data(), No, leaf_src, min_leaf_side, direct ? 0 : -1);
   const Octree& t = P.tree;
-  const int64_t N = S.N, No = S.No;
-  // geometry in tree order
-  std::vector<T> a(N), b(N), c(N), d(N), e(N), f(N);
+  // without a mask (FP64) the smallest positive normal value still excludes
+  // coincident points
+  auto rmask = [&](int64_t m) { return rm2f.empty() ? std::numeric_limits<T>::min() : (T)rm2f[m]; };
+  std::vector<T> a(N), b(N), c(N), d(N), e(N), f(N), tr(adj ? N : 0);
   for (int64_t j = 0; j < N; ++j) {
     int64_t i = t.tgt_perm[j];
-    a[j] = (T)S.X[3 * i]; b[j] = (T)S.X[3 * i + 1]; c[j] = (T)S.X[3 * i + 2];
-    d[j] = (T)S.nrm[3 * i]; e[j] = (T)S.nrm[3 * i + 1]; f[j] = (T)S.nrm[3 * i + 2];
+    a[j] = (T)TX[3 * i]; b[j] = (T)TX[3 * i + 1]; c[j] = (T)TX[3 * i + 2];
+    d[j] = (T)TN[3 * i]; e[j] = (T)TN[3 * i + 1]; f[j] = (T)TN[3 * i + 2];
+    if (adj) tr[j] = rmask(i);
   }
   upload(P.tx, a); upload(P.ty, b); upload(P.tz, c); upload(P.tnx, d); upload(P.tny, e); upload(P.tnz, f);
+  if (adj) upload(P.trm2, tr);
   std::vector<T> sa(No), sb(No), sc(No), sd(No), se(No), sf(No), sr(No);
   for (int64_t j = 0; j < No; ++j) {
     int64_t i = t.src_perm[j];
-    sa[j] = (T)S.s[3 * i]; sb[j] = (T)S.s[3 * i + 1]; sc[j] = (T)S.s[3 * i + 2];
-    sd[j] = (T)S.nu[3 * i]; se[j] = (T)S.nu[3 * i + 1]; sf[j] = (T)S.nu[3 * i + 2];
-    // without a mask (FP64) the smallest positive normal value still excludes
-    // coincident points
-    sr[j] = rm2f.empty() ? std::numeric_limits<T>::min() : (T)rm2f[i];
+    sa[j] = (T)SX[3 * i]; sb[j] = (T)SX[3 * i + 1]; sc[j] = (T)SX[3 * i + 2];
+    sd[j] = (T)SN[3 * i]; se[j] = (T)SN[3 * i + 1]; sf[j] = (T)SN[3 * i + 2];
+    sr[j] = adj ? std::numeric_limits<T>::min() : rmask(i);
   }
   upload(P.sx, sa); upload(P.sy, sb); upload(P.sz, sc); upload(P.snx, sd); upload(P.sny, se); upload(P.snz, sf);
   upload(P.rm2, sr);
@@ -280,16 +307,18 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   for (int64_t i = 0; i < N; ++i) tp[i] = (int)t.tgt_pos[i];
   for (int64_t i = 0; i < No; ++i) sp[i] = (int)t.src_pos[i];
   upload(P.tgt_pos, tp); upload(P.src_pos, sp);
-  upload_as<T>(P.P, ctx->re->P);
-  upload_as<T>(P.wo, S.wo);
-  upload_as<T>(P.nrm, S.nrm);
-  upload_as<T>(P.H, S.H);
-  std::vector<T> v4, v3;
-  pack_vals(C, (int64_t)C.size() / 6, v4, v3);
-  upload(P.vals4, v4);
-  upload(P.vals3, v3);
+  if (!adj) {
+    upload_as<T>(P.P, ctx->re->P);
+    upload_as<T>(P.wo, S.wo);
+    upload_as<T>(P.nrm, S.nrm);
+    upload_as<T>(P.H, S.H);
+    std::vector<T> v4, v3;
+    pack_vals(C, (int64_t)C.size() / 6, v4, v3);
+    upload(P.vals4, v4);
+    upload(P.vals3, v3);
+  }
   // translations
-  if (t.depth >= 2) {
+  if (t.depth >= 2 && !adj) {
     Translations tr;
     tr.build(p);
     std::vector<T> m;
@@ -364,6 +393,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.sx = dptr<T>(P.sx); D.sy = dptr<T>(P.sy); D.sz = dptr<T>(P.sz);
   D.snx = dptr<T>(P.snx); D.sny = dptr<T>(P.sny); D.snz = dptr<T>(P.snz);
   D.rm2 = dptr<T>(P.rm2);
+  D.trm2 = adj ? dptr<T>(P.trm2) : nullptr;
   D.bcx = dptr<T>(P.bcx); D.bcy = dptr<T>(P.bcy); D.bcz = dptr<T>(P.bcz);
   D.tgt_beg = dptr<int>(P.tgt_beg); D.tgt_end = dptr<int>(P.tgt_end);
   D.src_beg = dptr<int>(P.src_beg); D.src_end = dptr<int>(P.src_end);
@@ -382,8 +412,9 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.side = t.side;
   D.p = p;
   D.L = P.L;
-  D.m2m = dptr<T>(P.m2m); D.l2l = dptr<T>(P.l2l); D.m2l = dptr<T>(P.m2l);
-  D.dgradT = dptr<T>(P.dgrad); D.dhessT = dptr<T>(P.dhess);
+  const Prec<T>& TRs = adj ? *fwd : P;  // owner of the translation operators
+  D.m2m = dptr<T>(TRs.m2m); D.l2l = dptr<T>(TRs.l2l); D.m2l = dptr<T>(TRs.m2l);
+  D.dgradT = dptr<T>(TRs.dgrad); D.dhessT = dptr<T>(TRs.dhess);
   D.m2l_plan = t.depth >= 2 ? &P.m2l_pb->pl : nullptr;
   D.m2m_plan = t.depth >= 2 ? P.m2m_pl.data() : nullptr;
   D.l2l_plan = t.depth >= 2 ? P.l2l_pl.data() : nullptr;
@@ -393,7 +424,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   // P2M tables (the geometry is fixed, so the leaf harmonics of every
   // source can be kept): built on the device when both fit in a quarter of
   // the free memory and under P2M_TABLE_MAX bytes
-  if (t.depth >= 2 && !(ctx->opts.flags & LB_NO_P2M_TABLES)) {
+  if (t.depth >= 2 && !adj && !(ctx->opts.flags & LB_NO_P2M_TABLES)) {
     const size_t bytes = 2 * sizeof(T) * (size_t)No * P.L;
     size_t fr = 0, tot = 0;
     HIPTRY(hipMemGetInfo(&fr, &tot));
@@ -473,6 +504,68 @@ static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hi
     launch_combine_a3b<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td, mu,
                           mu + N, 2 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.H), dptr<double>(ctx->w),
                           1.0 / ctx->area, out + (int64_t)d0 * N, dptr<double>(ctx->partial), st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint applies: sigma_bar = S^T gpot + (grad S)^T ggrad + S'^T gdSdn +
+// (grad_Gamma S)^T gsurf, the exact transposes of the discrete operators of
+// lb_apply_gradS (far sum, mask and corrections of the same precision), the
+// far part through the FMM on the transposed tree.
+// ---------------------------------------------------------------------------
+template <typename T>
+static void ensure_adjoint(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built) {
+  if (!ctx->csr_t_built) {
+    const Surface& S = ctx->S;
+    std::vector<int64_t> cp(ctx->NP + 1, 0), cb;
+    std::vector<int> cr;
+    for (int32_t pt : S.near_patch) cp[pt + 1]++;
+    for (int l = 0; l < ctx->NP; ++l) cp[l + 1] += cp[l];
+    cr.resize(S.near_patch.size());
+    cb.resize(S.near_patch.size());
+    std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
+    for (int64_t i = 0; i < ctx->N; ++i)
+      for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b) {
+        const int64_t e = fill[S.near_patch[b]]++;
+        cr[e] = (int)i;
+        cb[e] = b;
+      }
+    upload(ctx->cptr, cp);
+    upload(ctx->crow, cr);
+    upload(ctx->cblk, cb);
+    ctx->csr_t_built = true;
+  }
+  if (built) return;
+  const bool fp32 = sizeof(T) == 4;
+  build_prec<T>(ctx, A, F.p, std::vector<double>(), fp32 ? ctx->rm2f : std::vector<float>(), 0.0,
+                ctx->opts.leaf_src, false, &F);
+  const int nb = A.dt.nbox, L = A.L, p = A.p, c = CHUNK_GRAD;
+  A.str.alloc(sizeof(T) * (size_t)ctx->N * 4 * c);
+  A.M.alloc(sizeof(T) * (size_t)nb * c * L);
+  A.Lc.alloc(sizeof(T) * (size_t)nb * c * L);
+  A.D.alloc(sizeof(T) * (size_t)std::max(A.dt.n_leaf_tgt, 1) * c * (3 * p * p + 9 * (p - 1) * (p - 1)));
+  A.fmm.alloc(sizeof(T) * (size_t)ctx->No * c);
+  HIPTRY(hipDeviceSynchronize());
+  built = true;
+}
+
+template <typename T>
+static void apply_adj_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int nd, const T* gpot, const T* ggrad,
+                        const T* gdSdn, const T* gsurf, T* sbar, hipStream_t st) {
+  ensure_adjoint<T>(ctx, F, A, built);
+  const int64_t N = ctx->N, No = ctx->No;
+  ctx->g4.alloc(sizeof(T) * (size_t)N * 4 * CHUNK_GRAD);
+  for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
+    const int c = std::min(CHUNK_GRAD, nd - d0);
+    launch_adj_strengths<T>(c, N, gpot ? gpot + (int64_t)d0 * N : nullptr, ggrad ? ggrad + (int64_t)d0 * 3 * N : nullptr,
+                            gdSdn ? gdSdn + (int64_t)d0 * N : nullptr, gsurf ? gsurf + (int64_t)d0 * 3 * N : nullptr,
+                            dptr<T>(F.nrm), dptr<int>(A.src_pos), dptr<T>(A.str), dptr<T>(ctx->g4), st);
+    // transposed tree: targets are the No oversampled points, sources the N nodes
+    launch_fmm<T>(A.dt, FMM_ADJ, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
+                  N, st);
+    launch_adj_combine<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
+                          dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
+                          dptr<int64_t>(ctx->cblk), dptr<T>(F.vals4), dptr<T>(ctx->g4), sbar + (int64_t)d0 * N, st);
   }
 }
 
@@ -706,6 +799,7 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
     upload(ctx->w, S.w);
     const bool direct = (o.flags & LB_DIRECT) != 0;
     build_prec<float>(ctx.get(), ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
+    ctx->rm2f = std::move(rm2);
     // the float positions used by the mask test must be exactly the ones on the device
     build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
     HIPTRY(hipDeviceSynchronize());
@@ -789,6 +883,31 @@ lb_status lb_apply_gradS(lb_ctx* ctx, int nd, int prec, const void* sigma, void*
                           (double*)surf_grad, st);
   HIPTRY(hipGetLastError());
   API_END
+}
+
+lb_status lb_apply_gradS_adj(lb_ctx* ctx, int nd, int prec, const void* gpot, const void* ggrad,
+                             const void* gdSdn, const void* gsurf, void* sigma_bar, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!sigma_bar) fail(LB_EINVAL, "null sigma_bar");
+  if (!gpot && !ggrad && !gdSdn && !gsurf) fail(LB_EINVAL, "all cotangents are null");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_adj_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, nd, (const float*)gpot, (const float*)ggrad,
+                       (const float*)gdSdn, (const float*)gsurf, (float*)sigma_bar, st);
+  else
+    apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nd, (const double*)gpot, (const double*)ggrad,
+                        (const double*)gdSdn, (const double*)gsurf, (double*)sigma_bar, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_apply_S_adj(lb_ctx* ctx, int nd, int prec, const void* gbar, void* sigma_bar, void* stream) {
+  if (!gbar) {
+    lb::set_last_error("null gbar");
+    return LB_EINVAL;
+  }
+  return lb_apply_gradS_adj(ctx, nd, prec, gbar, nullptr, nullptr, nullptr, sigma_bar, stream);
 }
 
 lb_status lb_apply_gradS_timed(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* grad,

@@ -213,10 +213,17 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
     if (threadIdx.x < nt) {
       const int j = threadIdx.x;
       const int s = t0 + j;
-      for (int q = 0; q < nstr; ++q) sq[q * P2M_TS + j] = str[(int64_t)(rhs * nstr + q) * No + s];
-      sn[j] = t.snx[s];
-      sn[P2M_TS + j] = t.sny[s];
-      sn[2 * P2M_TS + j] = t.snz[s];
+      if (mode == FMM_ADJ) {  // charge, and the dipole vector in place of the normal
+        sq[j] = str[(int64_t)(rhs * 4) * No + s];
+        sn[j] = str[(int64_t)(rhs * 4 + 1) * No + s];
+        sn[P2M_TS + j] = str[(int64_t)(rhs * 4 + 2) * No + s];
+        sn[2 * P2M_TS + j] = str[(int64_t)(rhs * 4 + 3) * No + s];
+      } else {
+        for (int q = 0; q < nstr; ++q) sq[q * P2M_TS + j] = str[(int64_t)(rhs * nstr + q) * No + s];
+        sn[j] = t.snx[s];
+        sn[P2M_TS + j] = t.sny[s];
+        sn[2 * P2M_TS + j] = t.snz[s];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -234,6 +241,18 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
         const T* re = Rre + jj * Lc;
         const T* im = Rim + jj * Lc;
         const T v = part ? im[cidx(n, m)] : re[cidx(n, m)];
+        if (mode == FMM_ADJ) {
+          // q Rt + d . grad Rt / h with the dipole vector d in sn
+          const T nx = sn[jj], ny = sn[P2M_TS + jj], nz = sn[2 * P2M_TS + jj];
+          T a0, b0, a1, b1, a2, b2;
+          rt_get(re, im, n - 1, m, a0, b0);
+          rt_get(re, im, n - 1, m + 1, a1, b1);
+          rt_get(re, im, n - 1, m - 1, a2, b2);
+          const T gre = nz * fa * a0 + fb * (nx * a1 + ny * b1) - fc * (nx * a2 - ny * b2);
+          const T gim = nz * fa * b0 + fb * (nx * b1 - ny * a1) - fc * (nx * b2 + ny * a2);
+          acc[k][0] += sgn * (sq[jj] * v + (part ? gim : gre) * ih);
+          continue;
+        }
         acc[k][0] += sq[jj] * sgn * v;
         if (mode == FMM_A3B) {
           acc[k][1] += sq[P2M_TS + jj] * sgn * v;
@@ -725,7 +744,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   // hessian [6][Lh] (+ 3 [Lh] scratch; A3B: expansion 1), in LDS after the
   // source chunk when EXP_LDS, else in this block's slice of D
   constexpr int LEAF_CH = 512;                     // sources per LDS chunk
-  constexpr int REC = MODE == FMM_A3B ? 9 : 5;       // T values per source record
+  constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ ? 9 : 5;  // T values per source record
   T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
   const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
   const int64_t dstride = (int64_t)nexp * 3 * Lg + 9 * Lh;
@@ -744,7 +763,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       for (int i = threadIdx.x; i < nexp * L; i += blockDim.x) sL[i] = gL[i];
       __syncthreads();
     }
-    if (MODE != FMM_POT) {
+    if (MODE == FMM_GRAD || MODE == FMM_A3B) {
       for (int e = 0; e < nexp; ++e)
         derive3(sL + e * L, p, sG + (e * 3 + 0) * Lg, sG + (e * 3 + 1) * Lg, sG + (e * 3 + 2) * Lg);
     }
@@ -769,7 +788,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   typedef typename Vec4<T>::type T4;
   T4* rec1 = reinterpret_cast<T4*>(tile);
   T4* rec2 = rec1 + LEAF_CH;                                                   // A3B only
-  T* trm_ = reinterpret_cast<T*>(rec1 + (MODE == FMM_A3B ? 2 : 1) * LEAF_CH);
+  T* trm_ = reinterpret_cast<T*>(rec1 + (MODE == FMM_A3B || MODE == FMM_ADJ ? 2 : 1) * LEAF_CH);
   __shared__ int upref[28];
   const int u0 = t.ulist_ptr[b], nU = t.ulist_ptr[b + 1] - u0;
   if (threadIdx.x == 0) {
@@ -786,8 +805,9 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   for (int i0 = tbeg; i0 < tend; i0 += TPB) {
     const int i = i0 + slot;
     const bool act = i < tend;
-    T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0;
+    T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0, TR = 0;
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
+    if (MODE == FMM_ADJ && act) TR = t.trm2[i];
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     // ---- far field: local expansions at xi = (x - c)/h, orders m = f mod F ----
     if (far && act) {
@@ -825,7 +845,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
           if (m == 0) { rre = bre; rim = 0; ire = n * n; iim = -1; }
           else { rre = 2 * bre; rim = -2 * bim; ire = n * n + 2 * m - 1; iim = n * n + 2 * m; }
 #define ACC(dst, base, idxre, idxim) dst += (base)[idxre] * rre + ((idxim) >= 0 ? (base)[idxim] * rim : (T)0)
-          if (MODE == FMM_POT) {
+          if (MODE == FMM_POT || MODE == FMM_ADJ) {
             ACC(pot, sL, ire, iim);
           } else if (MODE == FMM_GRAD) {
             ACC(pot, sL, ire, iim);
@@ -855,7 +875,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
 #undef ACC
         }
       }
-      if (MODE == FMM_POT) {
+      if (MODE == FMM_POT || MODE == FMM_ADJ) {
         a0 = pot;
       } else if (MODE == FMM_GRAD) {
         a0 = pot; a1 = g1[0] * ih; a2 = g1[1] * ih; a3 = g1[2] * ih;
@@ -887,13 +907,21 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         r1.z = t.sz[s];
         r1.w = str[(int64_t)(rhs * nstr) * No + s];
         rec1[j] = r1;
-        trm_[j] = t.rm2[s];
+        if (MODE != FMM_ADJ) trm_[j] = t.rm2[s];
         if (MODE == FMM_A3B) {
           T4 r2;
           r2.x = t.snx[s];
           r2.y = t.sny[s];
           r2.z = t.snz[s];
           r2.w = str[(int64_t)(rhs * nstr + 1) * No + s];
+          rec2[j] = r2;
+        }
+        if (MODE == FMM_ADJ) {  // dipole vector
+          T4 r2;
+          r2.x = str[(int64_t)(rhs * nstr + 1) * No + s];
+          r2.y = str[(int64_t)(rhs * nstr + 2) * No + s];
+          r2.z = str[(int64_t)(rhs * nstr + 3) * No + s];
+          r2.w = 0;
           rec2[j] = r2;
         }
         }
@@ -904,7 +932,8 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
 #pragma unroll 4
         for (int jj = f; jj < ns; jj += F) {
           const T4 r1 = rec1[jj];
-          const T rm = trm_[jj];
+          // the mask radius of the pair: the source's, or the target's in FMM_ADJ
+          const T rm = MODE == FMM_ADJ ? TR : trm_[jj];
           const T dx = X - r1.x;
           const T dy = Y - r1.y;
           const T dz = Z - r1.z;
@@ -917,6 +946,9 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
           const T ri3 = ri * ri2;
           if (MODE == FMM_POT) {
             q0 += r1.w * ri;
+          } else if (MODE == FMM_ADJ) {
+            const T4 dv = rec2[jj];
+            q0 += r1.w * ri + (dv.x * dx + dv.y * dy + dv.z * dz) * ri3;
           } else if (MODE == FMM_GRAD) {
             const T q = r1.w;
             const T qr3 = q * ri3;
@@ -975,6 +1007,10 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     int ts = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
+    if (t.p2m_H && mode == FMM_ADJ) {
+      fprintf(stderr, "lb: P2M tables are not built for the transposed tree\n");
+      return;
+    }
     if (t.p2m_H && mode == FMM_A3B)
       hipLaunchKernelGGL((k_p2m_tab<T, true>), dim3(t.n_leaf_src, nrhs), dim3(64 * P2M_W), 0, st, t, nrhs, str, No,
                          t.p2m_H, t.p2m_D, M);
@@ -1025,7 +1061,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   }
   tm->mark(PH_LEAF, st);
   const int nexp = fmm_nexp(mode);
-  const size_t chunk = sizeof(T) * (mode == FMM_A3B ? 9 : 5) * 512;
+  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ ? 9 : 5) * 512;
   const size_t exps = sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
   const bool lds = chunk + exps <= 64 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
@@ -1039,6 +1075,8 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     LEAF_LAUNCH(FMM_POT)
   } else if (mode == FMM_GRAD) {
     LEAF_LAUNCH(FMM_GRAD)
+  } else if (mode == FMM_ADJ) {
+    LEAF_LAUNCH(FMM_ADJ)
   } else {
     LEAF_LAUNCH(FMM_A3B)
   }
@@ -1303,6 +1341,89 @@ __global__ __launch_bounds__(256) void k_combine_a3b(int64_t N, int n_p, const i
     for (int d = 0; d < ND; ++d) partial[(int64_t)d * nblk + blockIdx.x] = red[0][d] + red[1][d] + red[2][d] + red[3][d];
 }
 
+// ---------------------------------------------------------------------------
+// adjoint applies (transposed far sum through the FMM on the transposed tree,
+// transposed corrections, transposed oversampling)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_adj_strengths(int nd, int64_t N, const T* __restrict__ gpot, const T* __restrict__ ggrad,
+                                const T* __restrict__ gdSdn, const T* __restrict__ gsurf, const T* __restrict__ nrm,
+                                const int* __restrict__ src_pos, T* __restrict__ str, T* __restrict__ g4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const T n0 = nrm[3 * i], n1 = nrm[3 * i + 1], n2 = nrm[3 * i + 2];
+  const int64_t pos = src_pos[i];
+  for (int d = 0; d < nd; ++d) {
+    const int64_t r = (int64_t)d * N + i;
+    const T q = gpot ? gpot[r] : (T)0;
+    T v0 = 0, v1 = 0, v2 = 0;
+    if (ggrad) { v0 += ggrad[3 * r]; v1 += ggrad[3 * r + 1]; v2 += ggrad[3 * r + 2]; }
+    if (gdSdn) { const T g = gdSdn[r]; v0 += n0 * g; v1 += n1 * g; v2 += n2 * g; }
+    if (gsurf) {
+      const T s0 = gsurf[3 * r], s1 = gsurf[3 * r + 1], s2 = gsurf[3 * r + 2];
+      const T ns = n0 * s0 + n1 * s1 + n2 * s2;
+      v0 += s0 - n0 * ns; v1 += s1 - n1 * ns; v2 += s2 - n2 * ns;
+    }
+    str[(int64_t)(4 * d) * N + pos] = q;
+    str[(int64_t)(4 * d + 1) * N + pos] = v0;
+    str[(int64_t)(4 * d + 2) * N + pos] = v1;
+    str[(int64_t)(4 * d + 3) * N + pos] = v2;
+    g4[4 * r] = q; g4[4 * r + 1] = v0; g4[4 * r + 2] = v1; g4[4 * r + 3] = v2;
+  }
+}
+
+template <typename T>
+void launch_adj_strengths(int nd, int64_t N, const T* gpot, const T* ggrad, const T* gdSdn, const T* gsurf,
+                          const T* nrm, const int* src_pos, T* str, T* g4, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_strengths<T>, dim3((N + 255) / 256), dim3(256), 0, st, nd, N, gpot, ggrad, gdSdn, gsurf,
+                     nrm, src_pos, str, g4);
+  KCHECK();
+}
+
+// One wave per (patch, density): node k of the patch is lane k % SW (SW = 32
+// for n_p <= 32, else 64); the two half-waves (n_p <= 32) split the
+// oversampled points and the correction entries and are added at the end.
+template <typename T>
+__global__ __launch_bounds__(64) void k_adj_combine(int NP, int n_p, int n_o, int64_t N, int64_t No,
+                                                    const T* __restrict__ P, const T* __restrict__ wo,
+                                                    const T* __restrict__ psi, const int* __restrict__ tgt_pos,
+                                                    const int64_t* __restrict__ cptr, const int* __restrict__ crow,
+                                                    const int64_t* __restrict__ cblk, const T* __restrict__ vals4,
+                                                    const T* __restrict__ g4, T* __restrict__ sbar) {
+  typedef typename Vec4<T>::type T4;
+  const int l = blockIdx.x, d = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int SW = n_p <= 32 ? 32 : 64, nsub = 64 / SW;
+  const int sub = lane / SW, k0 = lane - sub * SW;
+  const T4* v4 = reinterpret_cast<const T4*>(vals4);
+  const T4* gq = reinterpret_cast<const T4*>(g4) + (int64_t)d * N;
+  const T* ps = psi + (int64_t)d * No;
+  for (int k = k0; k < n_p; k += SW) {  // n_p > 64 needs several passes
+    T far = 0, corr = 0;
+    for (int m = sub; m < n_o; m += nsub) {
+      const int64_t om = (int64_t)l * n_o + m;
+      far += P[(int64_t)m * n_p + k] * wo[om] * ps[tgt_pos[om]];
+    }
+    for (int64_t e = cptr[l] + sub; e < cptr[l + 1]; e += nsub) {
+      const T4 c = v4[cblk[e] * n_p + k];
+      const T4 g = gq[crow[e]];
+      corr += c.x * g.x + c.y * g.y + c.z * g.z + c.w * g.w;
+    }
+    T tot = far * (T)INV4PI_D + corr;
+    if (nsub == 2) tot += __shfl_xor(tot, 32, 64);
+    if (sub == 0) sbar[(int64_t)d * N + (int64_t)l * n_p + k] = tot;
+  }
+}
+
+template <typename T>
+void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
+                        const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow,
+                        const int64_t* cblk, const T* vals4, const T* g4, T* sigma_bar, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_combine<T>, dim3(NP, nd), dim3(64), 0, st, NP, n_p, n_o, N, No, P, wo, psi, tgt_pos,
+                     cptr, crow, cblk, vals4, g4, sigma_bar);
+  KCHECK();
+}
+
 // serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
 __global__ void k_reduce_partials(const double* partial, int nblk, int nd, double scale, double* s) {
   __shared__ double red[256];
@@ -1476,7 +1597,12 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
   template void launch_combine_a3b<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
                                       const T*, const T*, int64_t, const T*, const int*, const T*, const double*, \
                                       double, T*, double*, hipStream_t);                                     \
-  template void launch_p2m_tables<T>(const DevTree<T>&, T*, T*, hipStream_t);
+  template void launch_p2m_tables<T>(const DevTree<T>&, T*, T*, hipStream_t);                                  \
+  template void launch_adj_strengths<T>(int, int64_t, const T*, const T*, const T*, const T*, const T*,          \
+                                        const int*, T*, T*, hipStream_t);                                       \
+  template void launch_adj_combine<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,       \
+                                      const int*, const int64_t*, const int*, const int64_t*, const T*, const T*, \
+                                      T*, hipStream_t);
 INST(float)
 INST(double)
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);

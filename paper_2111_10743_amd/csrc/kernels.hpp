@@ -10,11 +10,14 @@ namespace lb {
 //   FMM_GRAD: phi, d/dx phi, d/dy phi, d/dz phi
 //   FMM_A3B : n.grad phi_1, phi_2, n.grad phi_2, n.gradgrad phi_2.n + n.grad phi_3
 //             (expansions per rhs: charge mu1, charge mu2, dipole mu2 * nu)
+//   FMM_ADJ : psi = sum_j q_j / r + d_j . (x - y_j) / r^3 (sources with a
+//             charge q_j and a dipole vector d_j: strengths q, dx, dy, dz;
+//             the mask radius belongs to the target, see DevTree::trm2)
 // phi = sum_j c_j / |x - y_j| (no 1/(4 pi)).
-enum FmmMode { FMM_POT = 0, FMM_GRAD = 1, FMM_A3B = 2 };
-__host__ __device__ inline int fmm_nout(int mode) { return mode == FMM_POT ? 1 : 4; }
+enum FmmMode { FMM_POT = 0, FMM_GRAD = 1, FMM_A3B = 2, FMM_ADJ = 3 };
+__host__ __device__ inline int fmm_nout(int mode) { return mode == FMM_POT || mode == FMM_ADJ ? 1 : 4; }
 __host__ __device__ inline int fmm_nexp(int mode) { return mode == FMM_A3B ? 3 : 1; }
-__host__ __device__ inline int fmm_nstr(int mode) { return mode == FMM_A3B ? 2 : 1; }
+__host__ __device__ inline int fmm_nstr(int mode) { return mode == FMM_A3B ? 2 : (mode == FMM_ADJ ? 4 : 1); }
 
 // Batched translation plan: (matrix id, source box, target box) triples
 // sorted by (matrix, target).  Each matrix group is one GEMM
@@ -39,6 +42,7 @@ struct DevTree {
   const T *tx, *ty, *tz, *tnx, *tny, *tnz;       // targets
   const T *sx, *sy, *sz, *snx, *sny, *snz;       // sources
   const T *rm2;                                  // squared mask radius per source
+  const T *trm2;                                 // squared mask radius per target (FMM_ADJ)
   const T *bcx, *bcy, *bcz;                      // box centres [nbox]
   const int *tgt_beg, *tgt_end, *src_beg, *src_end;  // per leaf
   const int *ulist_ptr, *ulist;
@@ -67,6 +71,22 @@ struct DevTree {
 template <typename T>
 void launch_strengths(const T* tau, int ne, int64_t N, int NP, int n_p, int n_o, const T* P,
                       const T* wo, const int* src_pos, int64_t No, T* str, hipStream_t st);
+
+// Adjoint applies.  Node strengths of the transposed far sum from the
+// cotangents (each nullable, density-major, user order):
+//   q_i = gpot_i,  d_i = ggrad_i + n_i gdSdn_i + (gsurf_i - n_i (n_i . gsurf_i))
+// written as str [nd][4][N] at the tree positions src_pos of the transposed
+// tree, and in user order as g4 [nd][N][4] for the transposed corrections.
+template <typename T>
+void launch_adj_strengths(int nd, int64_t N, const T* gpot, const T* ggrad, const T* gdSdn, const T* gsurf,
+                          const T* nrm, const int* src_pos, T* str, T* g4, hipStream_t st);
+// sigma_bar [nd][N] = P^T (w^over psi / (4 pi)) per patch + C4^T g4, with psi
+// [nd][No] at the target positions tgt_pos of the transposed tree, and the
+// transposed block-CSR (per patch: entries (row, block), cptr [NP+1]).
+template <typename T>
+void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
+                        const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow,
+                        const int64_t* cblk, const T* vals4, const T* g4, T* sigma_bar, hipStream_t st);
 
 // P2M tables of every source about its leaf centre (setup): H, Dp [No][L]
 // in tree order; see k_p2m_build

@@ -6,6 +6,7 @@ enqueued on torch's current stream.  The library must be built
 raises, there is no fallback.
 """
 import ctypes
+import functools
 import os
 
 import numpy as np
@@ -30,8 +31,8 @@ LB_DIRECT = 4
 LB_NO_P2M_TABLES = 8
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
-            "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_timed", "lb_apply_A3",
-            "lb_solve", "lb_destroy", "lb_last_error")
+            "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj",
+            "lb_apply_gradS_timed", "lb_apply_A3", "lb_solve", "lb_destroy", "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -77,6 +78,8 @@ def lib():
         L.lb_get_corrections.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp]
         L.lb_apply_S.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_gradS.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
+        L.lb_apply_gradS_adj.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
+        L.lb_apply_S_adj.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_gradS_timed.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, dp, vp]
         L.lb_apply_A3.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
@@ -215,6 +218,32 @@ class Surface:
                                     _ptr(o["grad"]), _ptr(o.get("dSdn")), _ptr(o.get("surf_grad")), _stream()))
         return o
 
+    def apply_S_adj(self, gbar, out=None):
+        """sigma_bar = S^T gbar (the transpose of the discrete S of this precision)."""
+        import torch
+        nd = self._nd(gbar)
+        res = out if out is not None else torch.empty_like(gbar)
+        _check(lib().lb_apply_S_adj(self._ctx, nd, self._prec(gbar), _ptr(gbar), _ptr(res), _stream()))
+        return res
+
+    def apply_gradS_adj(self, gpot=None, ggrad=None, gdSdn=None, gsurf=None):
+        """sigma_bar = S^T gpot + (grad S)^T ggrad + S'^T gdSdn + (grad_Gamma S)^T gsurf."""
+        import torch
+        ref = next(t for t in (gpot, gdSdn, ggrad, gsurf) if t is not None)
+        if ref is gpot or ref is gdSdn:
+            nd = self._nd(ref)
+            shape = ref.shape
+        else:
+            nd = ref.numel() // (3 * self.N)
+            shape = ref.shape[:-1]
+        for t in (gpot, ggrad, gdSdn, gsurf):
+            if t is not None and (not t.is_cuda or not t.is_contiguous() or t.dtype != ref.dtype):
+                raise ValueError("cotangents must be contiguous device tensors of one dtype")
+        res = torch.empty(shape, dtype=ref.dtype, device=ref.device)
+        _check(lib().lb_apply_gradS_adj(self._ctx, nd, self._prec(ref), _ptr(gpot), _ptr(ggrad), _ptr(gdSdn),
+                                        _ptr(gsurf), _ptr(res), _stream()))
+        return res
+
     def apply_gradS_timed(self, sigma):
         """apply_gradS plus per-phase milliseconds (HIP events on the stream)."""
         import torch
@@ -245,3 +274,50 @@ class Surface:
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
                   "removed_mean": i.removed_mean} for i in info]
         return u, infos, code
+
+
+@functools.lru_cache(maxsize=None)
+def _autograd():
+    import torch
+
+    class ApplyS(torch.autograd.Function):
+        """pot = S[sigma]; backward: sigma_bar = S^T pot_bar (lb_apply_S_adj)."""
+
+        @staticmethod
+        def forward(ctx, surf, sigma):
+            ctx.surf = surf
+            return surf.apply_S(sigma.contiguous())
+
+        @staticmethod
+        def backward(ctx, gout):
+            return None, ctx.surf.apply_S_adj(gout.contiguous())
+
+    class ApplyGradS(torch.autograd.Function):
+        """(pot, grad, dSdn, surf_grad) = lb_apply_gradS(sigma); backward through
+        lb_apply_gradS_adj with the four cotangents."""
+
+        @staticmethod
+        def forward(ctx, surf, sigma):
+            ctx.surf = surf
+            o = surf.apply_gradS(sigma.contiguous())
+            return o["pot"], o["grad"], o["dSdn"], o["surf_grad"]
+
+        @staticmethod
+        def backward(ctx, gp, gg, gd, gs):
+            c = [t.contiguous() if t is not None else None for t in (gp, gg, gd, gs)]
+            if all(t is None for t in c):
+                return None, None
+            return None, ctx.surf.apply_gradS_adj(*c)
+
+    return ApplyS, ApplyGradS
+
+
+def apply_S(surf, sigma):
+    """Differentiable S[sigma] (torch.autograd): the backward pass is the
+    library's transposed apply."""
+    return _autograd()[0].apply(surf, sigma)
+
+
+def apply_gradS(surf, sigma):
+    """Differentiable (S, grad S, S', grad_Gamma S)[sigma] (torch.autograd)."""
+    return _autograd()[1].apply(surf, sigma)

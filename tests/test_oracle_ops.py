@@ -146,3 +146,28 @@ def test_table3_iteration_counts_range(c1_oracle):
     f = I.sh_series(coef, g.x)
     u, info = o.solve(f, tol=5e-7)
     assert lo - 2 <= info["iters"] <= hi + 2
+
+
+def test_adjoint_dot_product_identity(c1_oracle):
+    """Transposed apply (dense operator matrices, transposed) against the
+    forward apply (kernel table times strengths plus corrections): for any
+    cotangents g and density sigma, <g, A sigma> = <A^T g, sigma> with A the
+    map sigma -> (S, grad S, S' as n . grad S, grad_Gamma S)."""
+    o = c1_oracle
+    g = o.g
+    rng = np.random.default_rng(21)
+    sig = rng.standard_normal(g.N)
+    gp, gd = rng.standard_normal(g.N), rng.standard_normal(g.N)
+    gg, gs = rng.standard_normal((g.N, 3)), rng.standard_normal((g.N, 3))
+    L = o.layer(sig)
+    pot, grad = L[:, 0], L[:, 1:4]
+    dn = (grad * g.n).sum(-1)
+    surf = grad - g.n * dn[:, None]
+    lhs = gp @ pot + (gg * grad).sum() + gd @ dn + (gs * surf).sum()
+    rhs = o.adjoint_gradS(gp, gg, gd, gs) @ sig
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + np.abs(sig).sum())
+    # each cotangent alone
+    for kw in ({"gpot": gp}, {"ggrad": gg}, {"gdSdn": gd}, {"gsurf": gs}):
+        r = o.adjoint_gradS(**kw) @ sig
+        l = {"gpot": gp @ pot, "ggrad": (gg * grad).sum(), "gdSdn": gd @ dn, "gsurf": (gs * surf).sum()}[next(iter(kw))]
+        assert abs(l - r) < 1e-12 * (abs(l) + np.abs(sig).sum())
