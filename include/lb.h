@@ -58,6 +58,7 @@ typedef int lb_status;
 #define LB_STRICT_MEAN 1   /* lb_solve rejects f with |mean| > 1e-12 ||f|| */
 #define LB_HOST_ONLY   2   /* lb_setup does the host work only (no HIP call) */
 #define LB_DIRECT      4   /* far field by all-pairs sums instead of the FMM */
+#define LB_HOST_OCTREE 16  /* build the FMM octrees on the host instead of the device (same tree) */
 #define LB_NO_P2M_TABLES 8 /* compute the leaf harmonics of P2M on the fly instead of keeping
                               per-source tables (2 (p+1)^2 values per oversampled point and
                               precision, kept when they fit in a quarter of free device memory
@@ -72,7 +73,8 @@ typedef struct {
   int p_f64;        /* FMM expansion order of the FP64 path                   (default 28) */
   int leaf_src;     /* target mean number of sources per FMM leaf box         (default 1024)*/
   int max_iter;     /* GMRES iteration cap per (inner) solve                  (default 100)*/
-  int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT | LB_NO_P2M_TABLES        */
+  int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT | LB_NO_P2M_TABLES |
+                       LB_HOST_OCTREE                                                  */
   int self_n;       /* self-patch rule: Gauss points along each Duffy ray    (default 16) */
   int near_q;       /* adaptive near rule: near_q x near_q points per leaf    (default 8)  */
   double near_adm;  /* adaptive near rule admissibility dist >= adm * diam    (default 2)  */
@@ -129,6 +131,52 @@ lb_status lb_get_geometry(const lb_ctx *ctx, double *w, double *normals, double 
  * LB_HOST_ONLY context.  Any output may be NULL. */
 lb_status lb_get_corrections(const lb_ctx *ctx, int64_t *row_ptr, int32_t *patch,
                              double *vals);
+
+/* The FMM octree of one precision (transposed = 1: the tree of the adjoint
+ * applies, after the first one).  Uniform depth; boxes numbered level by
+ * level in Morton order (global id g); leaves = the boxes of level depth,
+ * numbered from 0.  Outputs (host, nullable; sizes from *info, so a first
+ * call may pass only info):
+ *   tgt_perm [targets], src_perm [sources]: tree position -> input index
+ *     (forward tree: targets = the N nodes, sources = the N_o oversampled
+ *     points; transposed tree: the other way round), stable in the input
+ *     order within a leaf;
+ *   leaf_ranges [nleaf][4]: target begin/end, source begin/end positions;
+ *   ulist_ptr [nleaf+1], ulist [nulist]: adjacent leaves holding sources of
+ *     each leaf holding targets (leaf numbers);
+ *   vlist_ptr [nbox+1], vlist_src [nvlist], vlist_off [nvlist]: for each box
+ *     holding targets on levels >= 2, the children of its parent's neighbours
+ *     that hold sources and are not adjacent (global ids), with the offset id
+ *     ((ox+3)*7 + (oy+3))*7 + (oz+3) of target minus source in box units;
+ *   boxes [nbox][5]: level, integer coordinates x, y, z on the level, and
+ *     flags (1: holds targets, 2: holds sources).
+ * The root cube is [lo, lo + side]^3. */
+typedef struct {
+  int32_t depth, nbox, nleaf, nulist, nvlist;
+  double lo[3], side;
+} lb_tree_info;
+lb_status lb_get_tree(const lb_ctx *ctx, int prec, int transposed, lb_tree_info *info,
+                      int64_t *tgt_perm, int64_t *src_perm, int32_t *leaf_ranges,
+                      int32_t *ulist_ptr, int32_t *ulist, int32_t *vlist_ptr,
+                      int32_t *vlist_src, int32_t *vlist_off, int32_t *boxes);
+
+/* The same octree for arbitrary point sets (the FMM of Section 4 runs on
+ * such a tree): tgt [nt][3], src [ns][3] host doubles; depth >= 0 fixes the
+ * leaf level, depth < 0 picks the first level >= 2 whose mean number of
+ * sources per non-empty leaf is <= leaf_src, coarsened while the leaf side is
+ * <= min_leaf_side.  on_device = 1 builds with the HIP kernels on the current
+ * device (synchronous), 0 on the host; both give the same tree.  Read it with
+ * lb_tree_get (outputs as lb_get_tree), release it with lb_tree_destroy.
+ * Errors: LB_EINVAL (empty or non-finite input, depth > 20), LB_EHIP. */
+typedef struct lb_tree lb_tree;
+lb_status lb_tree_build(lb_tree **tree, const double *tgt, int64_t nt, const double *src,
+                        int64_t ns, int leaf_src, double min_leaf_side, int depth,
+                        int on_device);
+lb_status lb_tree_get(const lb_tree *tree, lb_tree_info *info, int64_t *tgt_perm,
+                      int64_t *src_perm, int32_t *leaf_ranges, int32_t *ulist_ptr,
+                      int32_t *ulist, int32_t *vlist_ptr, int32_t *vlist_src,
+                      int32_t *vlist_off, int32_t *boxes);
+void lb_tree_destroy(lb_tree *tree);
 
 /* S[sigma] at the N nodes (Section 4.1 first sum, eq. nys-lcq2).
  * sigma: device [nd][N], pot: device [nd][N], dtype by prec. */

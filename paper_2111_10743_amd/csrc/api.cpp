@@ -223,10 +223,11 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   const std::vector<double>& SX = adj ? S.X : S.s;
   const std::vector<double>& SN = adj ? S.nrm : S.nu;
   const int64_t N = adj ? S.No : S.N, No = adj ? S.N : S.No;  // targets, sources of this tree
-  if (adj)
-    P.tree.build(TX.data(), N, SX.data(), No, leaf_src, 0.0, fwd->tree.depth);
+  const int depth_req = adj ? fwd->tree.depth : (direct ? 0 : -1);
+  if (ctx->opts.flags & LB_HOST_OCTREE)
+    P.tree.build(TX.data(), N, SX.data(), No, leaf_src, adj ? 0.0 : min_leaf_side, depth_req);
   else
-    P.tree.build(TX.data(), N, SX.data(), No, leaf_src, min_leaf_side, direct ? 0 : -1);
+    P.tree.build_device(TX.data(), N, SX.data(), No, leaf_src, adj ? 0.0 : min_leaf_side, depth_req);
   const Octree& t = P.tree;
   // without a mask (FP64) the smallest positive normal value still excludes
   // coincident points
@@ -933,6 +934,98 @@ lb_status lb_apply_gradS_timed(lb_ctx* ctx, int nd, int prec, const void* sigma,
     phase_ms[i] = ms;
   }
   for (int i = 0; i <= PH_N; ++i) (void)hipEventDestroy(tm.ev[i]);
+  API_END
+}
+
+namespace lb {
+static void export_tree(const Octree& t, lb_tree_info* info, int64_t* tgt_perm, int64_t* src_perm,
+                        int32_t* leaf_ranges, int32_t* ulist_ptr, int32_t* ulist, int32_t* vlist_ptr,
+                        int32_t* vlist_src, int32_t* vlist_off, int32_t* boxes) {
+  const int nb = t.nbox(), nleaf = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
+  if (info) {
+    info->depth = t.depth;
+    info->nbox = nb;
+    info->nleaf = nleaf;
+    info->nulist = (int32_t)t.ulist.size();
+    info->nvlist = (int32_t)t.vlist_src.size();
+    for (int d = 0; d < 3; ++d) info->lo[d] = t.lo[d];
+    info->side = t.side;
+  }
+  if (tgt_perm) std::copy(t.tgt_perm.begin(), t.tgt_perm.end(), tgt_perm);
+  if (src_perm) std::copy(t.src_perm.begin(), t.src_perm.end(), src_perm);
+  if (leaf_ranges)
+    for (int b = 0; b < nleaf; ++b) {
+      leaf_ranges[4 * b] = t.tgt_beg[b];
+      leaf_ranges[4 * b + 1] = t.tgt_end[b];
+      leaf_ranges[4 * b + 2] = t.src_beg[b];
+      leaf_ranges[4 * b + 3] = t.src_end[b];
+    }
+  if (ulist_ptr) std::copy(t.ulist_ptr.begin(), t.ulist_ptr.end(), ulist_ptr);
+  if (ulist) std::copy(t.ulist.begin(), t.ulist.end(), ulist);
+  if (vlist_ptr) std::copy(t.vlist_ptr.begin(), t.vlist_ptr.end(), vlist_ptr);
+  if (vlist_src) std::copy(t.vlist_src.begin(), t.vlist_src.end(), vlist_src);
+  if (vlist_off) std::copy(t.vlist_off.begin(), t.vlist_off.end(), vlist_off);
+  if (boxes)
+    for (int l = 0; l <= t.depth; ++l)
+      for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+        boxes[5 * g] = l;
+        boxes[5 * g + 1] = t.bx[g];
+        boxes[5 * g + 2] = t.by[g];
+        boxes[5 * g + 3] = t.bz[g];
+        boxes[5 * g + 4] = (t.has_tgt[g] ? 1 : 0) | (t.has_src[g] ? 2 : 0);
+      }
+}
+}  // namespace lb
+
+struct lb_tree {
+  Octree t;
+};
+
+lb_status lb_tree_build(lb_tree** out, const double* tgt, int64_t nt, const double* src, int64_t ns, int leaf_src,
+                        double min_leaf_side, int depth, int on_device) {
+  API_BEGIN
+  if (!out || !tgt || !src) fail(LB_EINVAL, "null argument");
+  *out = nullptr;
+  if (nt < 1 || ns < 1) fail(LB_EINVAL, "empty point set");
+  if (depth > 20) fail(LB_EINVAL, "depth must be <= 20");
+  if (depth < 0 && leaf_src < 1) fail(LB_EINVAL, "leaf_src must be >= 1");
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    if (!std::isfinite(tgt[i])) fail(LB_EINVAL, "non-finite target coordinate");
+  for (int64_t i = 0; i < 3 * ns; ++i)
+    if (!std::isfinite(src[i])) fail(LB_EINVAL, "non-finite source coordinate");
+  auto t = std::make_unique<lb_tree>();
+  if (on_device)
+    t->t.build_device(tgt, nt, src, ns, leaf_src, min_leaf_side, depth);
+  else
+    t->t.build(tgt, nt, src, ns, leaf_src, min_leaf_side, depth);
+  *out = t.release();
+  API_END
+}
+
+lb_status lb_tree_get(const lb_tree* tree, lb_tree_info* info, int64_t* tgt_perm, int64_t* src_perm,
+                      int32_t* leaf_ranges, int32_t* ulist_ptr, int32_t* ulist, int32_t* vlist_ptr,
+                      int32_t* vlist_src, int32_t* vlist_off, int32_t* boxes) {
+  API_BEGIN
+  if (!tree) fail(LB_EINVAL, "null tree");
+  export_tree(tree->t, info, tgt_perm, src_perm, leaf_ranges, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off,
+              boxes);
+  API_END
+}
+
+void lb_tree_destroy(lb_tree* tree) { delete tree; }
+
+lb_status lb_get_tree(const lb_ctx* ctx, int prec, int transposed, lb_tree_info* info, int64_t* tgt_perm,
+                      int64_t* src_perm, int32_t* leaf_ranges, int32_t* ulist_ptr, int32_t* ulist,
+                      int32_t* vlist_ptr, int32_t* vlist_src, int32_t* vlist_off, int32_t* boxes) {
+  API_BEGIN
+  if (!ctx) fail(LB_EINVAL, "null context");
+  if (ctx->host_only) fail(LB_EINVAL, "context was set up with LB_HOST_ONLY (no tree)");
+  if (prec != LB_PREC_FP32 && prec != LB_PREC_FP64) fail(LB_EINVAL, "prec must be 32 or 64");
+  const bool built = prec == LB_PREC_FP32 ? ctx->adj_built32 : ctx->adj_built64;
+  if (transposed && !built) fail(LB_EINVAL, "the transposed tree is built by the first adjoint apply");
+  const Octree& t = prec == LB_PREC_FP32 ? (transposed ? ctx->a32.tree : ctx->f32.tree)
+                                         : (transposed ? ctx->a64.tree : ctx->f64.tree);
+  export_tree(t, info, tgt_perm, src_perm, leaf_ranges, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off, boxes);
   API_END
 }
 

@@ -33,6 +33,23 @@ static inline uint32_t compact21(uint64_t x) {
   return (uint32_t)x;
 }
 
+void Octree::set_frame(const double mn[3], const double mx[3]) {
+  side = 0;
+  for (int d = 0; d < 3; ++d) side = std::max(side, mx[d] - mn[d]);
+  side = side * (1.0 + 1e-6) + 1e-12;
+  for (int d = 0; d < 3; ++d) lo[d] = 0.5 * (mn[d] + mx[d]) - 0.5 * side;
+}
+
+int Octree::choose_depth(const int64_t* cnt, int64_t ns, int leaf_src, double min_leaf_side) const {
+  int dep = 2;
+  for (int l = 2; l <= 20; ++l) {
+    dep = l;
+    if (cnt[l] > 0 && (double)ns / (double)cnt[l] <= (double)leaf_src) break;
+  }
+  while (dep > 1 && box_side(dep) <= min_leaf_side) --dep;
+  return dep;
+}
+
 void Octree::build(const double* tgt, int64_t nt, const double* src, int64_t ns, int leaf_src,
                    double min_leaf_side, int depth_req) {
   double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
@@ -42,10 +59,7 @@ void Octree::build(const double* tgt, int64_t nt, const double* src, int64_t ns,
   };
   upd(tgt, nt);
   upd(src, ns);
-  side = 0;
-  for (int d = 0; d < 3; ++d) side = std::max(side, mx[d] - mn[d]);
-  side = side * (1.0 + 1e-6) + 1e-12;
-  for (int d = 0; d < 3; ++d) lo[d] = 0.5 * (mn[d] + mx[d]) - 0.5 * side;
+  set_frame(mn, mx);
   const double scale = (double)(1 << 21) / side;
   auto key21 = [&](const double* p) {
     uint64_t c[3];
@@ -64,16 +78,13 @@ void Octree::build(const double* tgt, int64_t nt, const double* src, int64_t ns,
   } else {
     std::vector<uint64_t> sk = ks;
     std::sort(sk.begin(), sk.end());
-    depth = 2;
+    int64_t cnt[21] = {0};
     for (int l = 2; l <= 20; ++l) {
       int shift = 3 * (21 - l);
-      int64_t cnt = 0;
       for (int64_t i = 0; i < ns; ++i)
-        if (i == 0 || (sk[i] >> shift) != (sk[i - 1] >> shift)) ++cnt;
-      depth = l;
-      if ((double)ns / (double)cnt <= (double)leaf_src) break;
+        if (i == 0 || (sk[i] >> shift) != (sk[i - 1] >> shift)) ++cnt[l];
     }
-    while (depth > 1 && box_side(depth) <= min_leaf_side) --depth;
+    depth = choose_depth(cnt, ns, leaf_src, min_leaf_side);
   }
   const int shift = 3 * (21 - depth);
   // stable sort by leaf key

@@ -31,6 +31,17 @@ struct Octree {
   // side > min_leaf_side).  depth 0 gives a single box (all pairs direct).
   void build(const double* tgt, int64_t nt, const double* src, int64_t ns, int leaf_src,
              double min_leaf_side, int depth);
+  // The same tree built on the current HIP device (Morton keys, stable LSD
+  // radix sorts, unique boxes per level, links and lists in HIP kernels);
+  // the result is identical to build(): same frame, depth, orders and lists.
+  void build_device(const double* tgt, int64_t nt, const double* src, int64_t ns, int leaf_src,
+                    double min_leaf_side, int depth);
+  // root cube from the bounding box of all points (both builds)
+  void set_frame(const double mn[3], const double mx[3]);
+  // automatic depth: the first level >= 2 whose mean number of sources per
+  // non-empty leaf is <= leaf_src (cnt[l] = non-empty source boxes on level
+  // l, l = 2..20), then coarsened while the leaf side is <= min_leaf_side
+  int choose_depth(const int64_t* cnt, int64_t ns, int leaf_src, double min_leaf_side) const;
   double box_side(int level) const { return side / (double)(1 << level); }
   int nbox() const { return lev_off.back(); }
 };

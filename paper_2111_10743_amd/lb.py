@@ -29,9 +29,10 @@ LB_STRICT_MEAN = 1
 LB_HOST_ONLY = 2
 LB_DIRECT = 4
 LB_NO_P2M_TABLES = 8
+LB_HOST_OCTREE = 16
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
-            "lb_get_corrections", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj",
+            "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_solve", "lb_destroy", "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
@@ -52,6 +53,12 @@ class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_patches", "n_p", "N", "n_o", "N_o", "nnz_blocks",
                                                "fmm_levels", "fmm_leaves", "p_f32", "p_f64",
                                                "p2p_pairs32", "m2l_pairs32", "p2p_pairs64", "m2l_pairs64")]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("nbox", ctypes.c_int32), ("nleaf", ctypes.c_int32),
+                ("nulist", ctypes.c_int32), ("nvlist", ctypes.c_int32), ("lo", ctypes.c_double * 3),
+                ("side", ctypes.c_double)]
 
 
 class LBError(RuntimeError):
@@ -76,6 +83,11 @@ def lib():
         L.lb_get_sizes.argtypes = [vp, ctypes.POINTER(Sizes)]
         L.lb_get_geometry.argtypes = [vp, dp, dp, dp]
         L.lb_get_corrections.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp]
+        L.lb_get_tree.argtypes = [vp, ip, ip, ctypes.POINTER(TreeInfo)] + [vp] * 9
+        L.lb_tree_build.argtypes = [ctypes.POINTER(vp), dp, ctypes.c_int64, dp, ctypes.c_int64, ip,
+                                    ctypes.c_double, ip, ip]
+        L.lb_tree_get.argtypes = [vp, ctypes.POINTER(TreeInfo)] + [vp] * 9
+        L.lb_tree_destroy.argtypes = [vp]
         L.lb_apply_S.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_gradS.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.lb_apply_gradS_adj.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
@@ -85,9 +97,10 @@ def lib():
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_destroy.argtypes = [vp]
         L.lb_destroy.restype = None
+        L.lb_tree_destroy.restype = None
         L.lb_last_error.restype = ctypes.c_char_p
         for n in EXPORTED:
-            if n not in ("lb_destroy", "lb_last_error"):
+            if n not in ("lb_destroy", "lb_last_error", "lb_tree_destroy"):
                 getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -118,6 +131,34 @@ def ref_nodes(order):
     return uv, w
 
 
+def _tree_arrays(getter, nt, ns):
+    info = TreeInfo()
+    _check(getter(ctypes.byref(info), *([None] * 9)))
+    out = {"depth": info.depth, "lo": np.array(info.lo[:]), "side": info.side,
+           "tgt_perm": np.zeros(nt, np.int64), "src_perm": np.zeros(ns, np.int64),
+           "leaf_ranges": np.zeros((info.nleaf, 4), np.int32),
+           "ulist_ptr": np.zeros(info.nleaf + 1, np.int32), "ulist": np.zeros(info.nulist, np.int32),
+           "vlist_ptr": np.zeros(info.nbox + 1, np.int32), "vlist_src": np.zeros(info.nvlist, np.int32),
+           "vlist_off": np.zeros(info.nvlist, np.int32), "boxes": np.zeros((info.nbox, 5), np.int32)}
+    ptr = [out[k].ctypes.data_as(ctypes.c_void_p) for k in ("tgt_perm", "src_perm", "leaf_ranges", "ulist_ptr",
+                                                           "ulist", "vlist_ptr", "vlist_src", "vlist_off", "boxes")]
+    _check(getter(ctypes.byref(info), *ptr))
+    return out
+
+
+def build_tree(tgt, src, leaf_src=1024, min_leaf_side=0.0, depth=-1, device=True):
+    """The library's FMM octree of arbitrary points (lb_tree_build), as numpy arrays."""
+    tgt = np.ascontiguousarray(tgt, dtype=np.float64)
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().lb_tree_build(ctypes.byref(h), _dp(tgt), tgt.shape[0], _dp(src), src.shape[0], leaf_src,
+                               min_leaf_side, depth, int(device)))
+    try:
+        return _tree_arrays(lambda *a: lib().lb_tree_get(h, *a), tgt.shape[0], src.shape[0])
+    finally:
+        lib().lb_tree_destroy(h)
+
+
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -130,7 +171,8 @@ def _ptr(t):
 class Surface:
     """One discretized surface: lb_setup ... lb_destroy."""
 
-    def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, p2m_tables=True, **kw):
+    def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, p2m_tables=True,
+                 host_octree=False, **kw):
         X = np.ascontiguousarray(X, dtype=np.float64)
         Xu = np.ascontiguousarray(Xu, dtype=np.float64)
         Xv = np.ascontiguousarray(Xv, dtype=np.float64)
@@ -143,6 +185,8 @@ class Surface:
             o.flags |= LB_DIRECT
         if not p2m_tables:
             o.flags |= LB_NO_P2M_TABLES
+        if host_octree:
+            o.flags |= LB_HOST_OCTREE
         self.order = order
         self.host_only = host_only
         self._ctx = ctypes.c_void_p()
@@ -180,6 +224,11 @@ class Surface:
         _check(lib().lb_get_corrections(self._ctx, ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                         patch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(vals)))
         return ptr, patch, vals
+
+    def tree(self, prec=32, transposed=False):
+        """The FMM octree (see lb_get_tree in include/lb.h) as numpy arrays."""
+        nt, ns = (self.sizes["N_o"], self.N) if transposed else (self.N, self.sizes["N_o"])
+        return _tree_arrays(lambda *a: lib().lb_get_tree(self._ctx, prec, int(transposed), *a), nt, ns)
 
     # -- device calls (torch tensors) --------------------------------------
     @staticmethod
