@@ -228,6 +228,15 @@ lb_status lb_apply_gradS_timed(lb_ctx *ctx, int nd, int prec, const void *sigma,
 lb_status lb_apply_A3(lb_ctx *ctx, int nd, int prec, const void *tau, void *out,
                       void *stream);
 
+/* Transpose of lb_apply_A3 (the same discrete operator of the same
+ * precision): out = A3^T v = -v/4 + S'^T S'^T v - S^T (S''+D')^T v
+ * - S^T S'^T (2 H v) + (sum_i v_i / area) S^T S^T w, through two FMMs on the
+ * transposed tree (the first with dipole and quadrupole sources at the
+ * nodes).  v, out: device [nd][N].  The first call for a precision builds the
+ * transposed tree and S^T S^T w and synchronizes the device. */
+lb_status lb_apply_A3_adj(lb_ctx *ctx, int nd, int prec, const void *v, void *out,
+                          void *stream);
+
 /* Solve Delta_Gamma u = f for the mean-zero u (Lemma 1), through
  * A3 sigma = f - mean(f) and u = S[S[sigma]] (eq. ie-dis2, Section 6 GMRES:
  * x0 = 0, no restart, relative Euclidean residual < tol, at most
@@ -237,6 +246,15 @@ lb_status lb_apply_A3(lb_ctx *ctx, int nd, int prec, const void *tau, void *out,
  * LB_ENOTMEANZERO in strict-mean mode. */
 lb_status lb_solve(lb_ctx *ctx, int nrhs, const double *f, double *u, double tol,
                    int mode, lb_solve_info *info, void *stream);
+
+/* Adjoint of lb_solve with respect to f: with u = S S A3^{-1} (f - W f)
+ * (W f = sum_i w_i f_i / area), fbar = (I - w 1^T / area) A3^{-T} S^T S^T ubar,
+ * the A3^T system solved by GMRES (or FP32 inner / FP64 outer refinement) to
+ * tol as in lb_solve.  ubar, fbar: device double [nrhs][N]; info: host
+ * [nrhs], nullable (removed_mean reports sum_i y_i / area of the solution y).
+ * Synchronizes `stream`; LB_ENOCONV as lb_solve. */
+lb_status lb_solve_adj(lb_ctx *ctx, int nrhs, const double *ubar, double *fbar, double tol,
+                       int mode, lb_solve_info *info, void *stream);
 
 /* Release all host and device state (NULL is ignored). */
 void lb_destroy(lb_ctx *ctx);

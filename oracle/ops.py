@@ -165,6 +165,27 @@ class Oracle:
             out += M[0].T @ gpot
         return out
 
+    def A3_matrix(self):
+        """Dense A3 of Section 4.3 from the operator matrices (all rows, small N):
+        -I/4 + S' S' - (S''+D') S - 2 diag(H) S' S + (1/area) 1 w^T S S."""
+        g = self.g
+        if getattr(self, "_M", None) is None:
+            self._M = self.operator_matrices()
+        S, Sp, K = self._M[0], self._M[4], self._M[5]
+        SS = S @ S
+        return (-0.25 * np.eye(g.N) + Sp @ Sp - K @ S - 2.0 * g.H[:, None] * (Sp @ S)
+                + np.outer(np.ones(g.N), g.w @ SS) / g.w.sum())
+
+    def solve_adjoint(self, ubar):
+        """fbar = (I - w 1^T / area) A3^{-T} S^T S^T ubar: the transpose of the
+        linear map f -> u of solve() (mean projection, A3^{-1}, u = S S sigma)."""
+        g = self.g
+        if getattr(self, "_M", None) is None:
+            self._M = self.operator_matrices()
+        S = self._M[0]
+        y = np.linalg.solve(self.A3_matrix().T, S.T @ (S.T @ ubar))
+        return y - g.w * y.sum() / g.w.sum()
+
     def W(self, phi):
         g = self.g
         return (g.w * phi).sum() / g.w.sum()

@@ -157,6 +157,9 @@ struct lb_ctx {
   bool adj_built32 = false, adj_built64 = false;
   DBuf cptr, crow, cblk, g4;
   bool csr_t_built = false;
+  // transposed A3: z = S^T S^T w per precision, step workspace
+  DBuf z32, z64, a3t_a, a3t_b, a3t_scal;
+  bool z_built32 = false, z_built64 = false;
   std::vector<float> rm2f;
   // solver workspace
   DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp;
@@ -571,6 +574,61 @@ static void apply_adj_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int nd
 }
 
 // ---------------------------------------------------------------------------
+// Transposed A3 (adjoint of apply_A3_t, the same discrete operator):
+//   A3^T v = -v/4 + S'^T S'^T v - S^T (S''+D')^T v - S^T S'^T (2 H v)
+//            + (sum_i v_i / area) S^T S^T w
+// in two transposed FMMs: step 1 (FMM_ADJ3) a = S'^T v and
+// b = (S''+D')^T v + S'^T (2 H v); step 2 (FMM_ADJ) S'^T a - S^T b.
+// ---------------------------------------------------------------------------
+constexpr int CHUNK_A3T = 4;
+constexpr int NDMAX_HOST = 4;  // densities per reduction launch (k_reduce_partials takes up to 4 partial rows)
+
+template <typename T>
+static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& zb, bool& zbuilt, int nd,
+                        const T* v, T* out, hipStream_t st) {
+  ensure_ws(ctx, F, CHUNK_GRAD);  // allocates ctx->partial (column sums below)
+  ensure_adjoint<T>(ctx, F, A, built);
+  const int64_t N = ctx->N, No = ctx->No;
+  if (!zbuilt) {
+    DBuf wt, z1;
+    wt.alloc(sizeof(T) * N);
+    z1.alloc(sizeof(T) * N);
+    zb.alloc(sizeof(T) * N);
+    std::vector<T> wh(ctx->S.w.begin(), ctx->S.w.end());
+    HIPTRY(hipMemcpy(wt.p, wh.data(), sizeof(T) * N, hipMemcpyHostToDevice));
+    apply_adj_t<T>(ctx, F, A, built, 1, dptr<T>(wt), nullptr, nullptr, nullptr, dptr<T>(z1), st);
+    apply_adj_t<T>(ctx, F, A, built, 1, dptr<T>(z1), nullptr, nullptr, nullptr, dptr<T>(zb), st);
+    HIPTRY(hipStreamSynchronize(st));
+    zbuilt = true;
+  }
+  ctx->a3t_a.alloc(sizeof(double) * (size_t)N * CHUNK_A3T);
+  ctx->a3t_b.alloc(sizeof(double) * (size_t)N * CHUNK_A3T);
+  ctx->a3t_scal.alloc(sizeof(double) * CHUNK_A3T);
+  ctx->g4.alloc(sizeof(T) * (size_t)N * 4 * CHUNK_GRAD);
+  T* a = dptr<T>(ctx->a3t_a);
+  T* b = dptr<T>(ctx->a3t_b);
+  T* g2 = dptr<T>(ctx->g4);
+  for (int d0 = 0; d0 < nd; d0 += CHUNK_A3T) {
+    const int c = std::min(CHUNK_A3T, nd - d0);
+    const T* vd = v + (int64_t)d0 * N;
+    launch_adj3_str1<T>(c, N, vd, dptr<T>(F.H), dptr<int>(A.src_pos), dptr<T>(A.str), g2, st);
+    launch_fmm<T>(A.dt, FMM_ADJ3, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
+                  N, st);
+    launch_adj3_comb1<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
+                         dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
+                         dptr<int64_t>(ctx->cblk), dptr<T>(F.vals3), g2, a, b, st);
+    launch_colsum<T>(c, N, vd, 1.0 / ctx->area, dptr<double>(ctx->partial), dptr<double>(ctx->a3t_scal), st);
+    launch_adj3_str2<T>(c, N, a, b, dptr<T>(F.nrm), dptr<int>(A.src_pos), dptr<T>(A.str), g2, st);
+    launch_fmm<T>(A.dt, FMM_ADJ, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
+                  N, st);
+    launch_adj3_comb2<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
+                         dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
+                         dptr<int64_t>(ctx->cblk), dptr<T>(F.vals3), g2, vd, dptr<T>(zb),
+                         dptr<double>(ctx->a3t_scal), out + (int64_t)d0 * N, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // GMRES (Section 6) for nb right-hand sides at once: x0 = 0, no restart,
 // each right-hand side has its own Arnoldi basis (CGS2, FP64 on the device)
 // and Givens rotations (host); the operator is applied to all active
@@ -685,6 +743,77 @@ static void gmres_multi(lb_ctx* ctx, ApplyFn A, int nb, const double* B, double*
     HIPTRY(hipMemcpyAsync(hd, y.data(), sizeof(double) * q.k, hipMemcpyHostToDevice, st));
     launch_gemv_add(V(r, 0), N, q.k, hd, X + (size_t)r * N, N, st);
     HIPTRY(hipStreamSynchronize(st));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve A sig = b for nrhs right-hand sides (b [nrhs][N], norms bnorm):
+// LB_SOLVE_FP64: GMRES with the FP64 operator A64; LB_SOLVE_FP32_REFINE:
+// iterative refinement, each correction from GMRES with the FP32 operator
+// A32 on the FP64 residual.  rel = final FP64 relative residuals.
+// r, ut, dcorr: [nrhs][N] workspace.
+// ---------------------------------------------------------------------------
+template <typename Op64, typename Op32>
+static void solve_system(lb_ctx* ctx, int nrhs, Op64& A64, Op32& A32, const double* b,
+                         const std::vector<double>& bnorm, double* sig, double* r, double* ut, double* dcorr,
+                         double tol, int mode, std::vector<double>& rel, std::vector<int>& iters,
+                         std::vector<int>& outer, hipStream_t st) {
+  const int64_t N = ctx->N;
+  const size_t nN = (size_t)nrhs * N;
+  const int maxit = ctx->opts.max_iter;
+  DBuf scal;
+  scal.alloc(sizeof(double) * 4);
+  auto nrm2 = [&](const double* v) {
+    launch_dots(v, N, 1, v, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
+    double sv;
+    HIPTRY(hipMemcpyAsync(&sv, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return std::sqrt(sv);
+  };
+  rel.assign(nrhs, 0.0);
+  iters.assign(nrhs, 0);
+  outer.assign(nrhs, 0);
+  std::vector<double> inner;
+  std::vector<int> it;
+  std::vector<char> skip(nrhs, 0);
+  auto residual = [&]() {  // r = b - A sig (FP64), rel = |r| / |b|
+    A64(sig, ut, nrhs);
+    launch_axpby(1.0, b, -1.0, ut, r, (int64_t)nN, st);
+    for (int q = 0; q < nrhs; ++q) rel[q] = bnorm[q] > 0 ? nrm2(r + (size_t)q * N) / bnorm[q] : 0.0;
+  };
+  if (mode == LB_SOLVE_FP64) {
+    gmres_multi(ctx, A64, nrhs, b, sig, tol, maxit, skip, inner, it, st);
+    for (int q = 0; q < nrhs; ++q) iters[q] = it[q];
+    residual();
+    return;
+  }
+  HIPTRY(hipMemsetAsync(sig, 0, sizeof(double) * nN, st));
+  HIPTRY(hipMemcpyAsync(r, b, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
+  for (int q = 0; q < nrhs; ++q) rel[q] = bnorm[q] > 0 ? 1.0 : 0.0;
+  std::vector<double> prev(nrhs, 1e300);
+  const int max_outer = 12;
+  for (int step = 0; step < max_outer; ++step) {
+    bool any = false;
+    for (int q = 0; q < nrhs; ++q) {
+      skip[q] = !(rel[q] >= tol) || rel[q] > 0.5 * prev[q];  // converged, or refinement stalled
+      any |= !skip[q];
+    }
+    if (!any) break;
+    // inner FP32 solves: the FP32 operator is accurate to ~1e-6, so each
+    // refinement step asks for no more than that
+    double worst = 0;
+    for (int q = 0; q < nrhs; ++q)
+      if (!skip[q]) worst = std::max(worst, rel[q]);
+    const double inner_tol = std::max(1e-6, 0.5 * tol / std::max(worst, 1e-300));
+    gmres_multi(ctx, A32, nrhs, r, dcorr, inner_tol, maxit, skip, inner, it, st);
+    for (int q = 0; q < nrhs; ++q) {
+      if (skip[q]) continue;
+      iters[q] += it[q];
+      outer[q] += 1;
+      launch_axpby(1.0, sig + (size_t)q * N, 1.0, dcorr + (size_t)q * N, sig + (size_t)q * N, N, st);
+    }
+    prev = rel;
+    residual();
   }
 }
 
@@ -911,6 +1040,21 @@ lb_status lb_apply_S_adj(lb_ctx* ctx, int nd, int prec, const void* gbar, void* 
   return lb_apply_gradS_adj(ctx, nd, prec, gbar, nullptr, nullptr, nullptr, sigma_bar, stream);
 }
 
+lb_status lb_apply_A3_adj(lb_ctx* ctx, int nd, int prec, const void* v, void* out, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!v || !out) fail(LB_EINVAL, "null v or out");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_A3T_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, ctx->z32, ctx->z_built32, nd, (const float*)v,
+                       (float*)out, st);
+  else
+    apply_A3T_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, ctx->z64, ctx->z_built64, nd, (const double*)v,
+                        (double*)out, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
 lb_status lb_apply_gradS_timed(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* grad,
                                void* dSdn, void* surf_grad, double* phase_ms, void* stream) {
   API_BEGIN
@@ -1117,48 +1261,9 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
     launch_sub_scalar(fzq, dptr<double>(scal), 1.0 / ctx->area, N, st);
     fnorm[q] = nrm2(fzq);
   }
-  std::vector<double> rel(nrhs, 0.0), inner;
-  std::vector<int> iters(nrhs, 0), outer(nrhs, 0), it;
-  std::vector<char> skip(nrhs, 0);
-  auto residual = [&]() {  // r = fz - A3 sig (FP64), rel = |r| / |fz|
-    A64(sig, ut, nrhs);
-    launch_axpby(1.0, fz, -1.0, ut, r, (int64_t)nN, st);
-    for (int q = 0; q < nrhs; ++q) rel[q] = fnorm[q] > 0 ? nrm2(r + (size_t)q * N) / fnorm[q] : 0.0;
-  };
-  if (mode == LB_SOLVE_FP64) {
-    gmres_multi(ctx, A64, nrhs, fz, sig, tol, maxit, skip, inner, it, st);
-    for (int q = 0; q < nrhs; ++q) iters[q] = it[q];
-    residual();
-  } else {
-    HIPTRY(hipMemsetAsync(sig, 0, sizeof(double) * nN, st));
-    HIPTRY(hipMemcpyAsync(r, fz, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
-    for (int q = 0; q < nrhs; ++q) rel[q] = fnorm[q] > 0 ? 1.0 : 0.0;
-    std::vector<double> prev(nrhs, 1e300);
-    const int max_outer = 12;
-    for (int step = 0; step < max_outer; ++step) {
-      bool any = false;
-      for (int q = 0; q < nrhs; ++q) {
-        skip[q] = !(rel[q] >= tol) || rel[q] > 0.5 * prev[q];  // converged, or refinement stalled
-        any |= !skip[q];
-      }
-      if (!any) break;
-      // inner FP32 solves: the FP32 operator is accurate to ~1e-6, so each
-      // refinement step asks for no more than that
-      double worst = 0;
-      for (int q = 0; q < nrhs; ++q)
-        if (!skip[q]) worst = std::max(worst, rel[q]);
-      const double inner_tol = std::max(1e-6, 0.5 * tol / std::max(worst, 1e-300));
-      gmres_multi(ctx, A32, nrhs, r, dcorr, inner_tol, maxit, skip, inner, it, st);
-      for (int q = 0; q < nrhs; ++q) {
-        if (skip[q]) continue;
-        iters[q] += it[q];
-        outer[q] += 1;
-        launch_axpby(1.0, sig + (size_t)q * N, 1.0, dcorr + (size_t)q * N, sig + (size_t)q * N, N, st);
-      }
-      prev = rel;
-      residual();
-    }
-  }
+  std::vector<double> rel;
+  std::vector<int> iters, outer;
+  solve_system(ctx, nrhs, A64, A32, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel, iters, outer, st);
   // u = S[S[sigma]] in FP64
   {
     DBuf g;
@@ -1175,6 +1280,84 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
       info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[q] - 1, 0);
       info[q].rel_resid = rel[q];
       info[q].removed_mean = mean[q];
+    }
+  }
+  if (ret != LB_OK) {
+    lb::set_last_error("GMRES did not reach the tolerance for some right-hand side");
+    return ret;
+  }
+  API_END
+}
+
+lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, double tol, int mode,
+                       lb_solve_info* info, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nrhs, LB_PREC_FP64);
+  if (!ubar || !fbar) fail(LB_EINVAL, "null ubar or fbar");
+  if (!(tol > 0)) fail(LB_EINVAL, "tol must be > 0");
+  if (mode != LB_SOLVE_FP64 && mode != LB_SOLVE_FP32_REFINE) fail(LB_EINVAL, "unknown mode");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = ctx->N;
+  ensure_ws(ctx, ctx->f64, CHUNK_GRAD);
+  ensure_ws(ctx, ctx->f32, CHUNK_GRAD);
+  const size_t nN = (size_t)nrhs * N;
+  ctx->r.alloc(sizeof(double) * nN);
+  ctx->sig.alloc(sizeof(double) * nN);
+  ctx->ftmp.alloc(sizeof(double) * nN);
+  ctx->utmp.alloc(sizeof(double) * nN * 2);
+  ctx->f32.tmp_in.alloc(sizeof(float) * nN);
+  ctx->f32.tmp_out.alloc(sizeof(float) * nN);
+  double* r = dptr<double>(ctx->r);
+  double* y = dptr<double>(ctx->sig);
+  double* rhs = dptr<double>(ctx->ftmp);
+  double* ut = dptr<double>(ctx->utmp);
+  double* dcorr = ut + nN;
+  auto A64 = [&](const double* v, double* w, int na) {
+    apply_A3T_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, ctx->z64, ctx->z_built64, na, v, w, st);
+  };
+  auto A32 = [&](const double* v, double* w, int na) {
+    float* vi = dptr<float>(ctx->f32.tmp_in);
+    float* vo = dptr<float>(ctx->f32.tmp_out);
+    launch_convert<double, float>(v, vi, (int64_t)na * N, st);
+    apply_A3T_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, ctx->z32, ctx->z_built32, na, vi, vo, st);
+    launch_convert<float, double>(vo, w, (int64_t)na * N, st);
+  };
+  // rhs = S^T S^T ubar (adjoint of u = S[S[sigma]])
+  apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nrhs, ubar, nullptr, nullptr, nullptr, ut, st);
+  apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nrhs, ut, nullptr, nullptr, nullptr, rhs, st);
+  DBuf scal;
+  scal.alloc(sizeof(double) * 4);
+  std::vector<double> bnorm(nrhs);
+  for (int q = 0; q < nrhs; ++q) {
+    launch_dots(rhs + (size_t)q * N, N, 1, rhs + (size_t)q * N, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
+    double sv;
+    HIPTRY(hipMemcpyAsync(&sv, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    bnorm[q] = std::sqrt(sv);
+  }
+  std::vector<double> rel;
+  std::vector<int> iters, outer;
+  solve_system(ctx, nrhs, A64, A32, rhs, bnorm, y, r, ut, dcorr, tol, mode, rel, iters, outer, st);
+  // fbar = (I - w 1^T / area) y, the transpose of the mean projection
+  std::vector<double> removed(nrhs);
+  DBuf sc;
+  sc.alloc(sizeof(double) * nrhs);
+  for (int d0 = 0; d0 < nrhs; d0 += NDMAX_HOST) {
+    const int c = std::min(NDMAX_HOST, nrhs - d0);
+    launch_colsum<double>(c, N, y + (size_t)d0 * N, 1.0 / ctx->area, dptr<double>(ctx->partial),
+                          dptr<double>(sc) + d0, st);
+  }
+  launch_sub_wscal(nrhs, N, y, dptr<double>(ctx->w), dptr<double>(sc), fbar, st);
+  HIPTRY(hipMemcpyAsync(removed.data(), sc.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  lb_status ret = LB_OK;
+  for (int q = 0; q < nrhs; ++q) {
+    if (!(rel[q] < tol)) ret = LB_ENOCONV;
+    if (info) {
+      info[q].iters = iters[q];
+      info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[q] - 1, 0);
+      info[q].rel_resid = rel[q];
+      info[q].removed_mean = removed[q];
     }
   }
   if (ret != LB_OK) {

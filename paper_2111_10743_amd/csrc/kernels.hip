@@ -279,6 +279,106 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
   }
 }
 
+// P2M of the first transposed-A3 step (FMM_ADJ3): per source j with normal n,
+// strengths v, w: expansion 1 += v (n . grad) conj Rt / h, expansion 2 +=
+// v (n . grad)^2 conj Rt / h^2 + w (n . grad) conj Rt / h.  The directional
+// derivative of Rt_n^m is a combination of Rt_{n-1}^{m-1,m,m+1}; applying it
+// to that table again gives the second derivative.  Tiles of ts sources:
+// harmonic table R and derivative table D in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_p2m_adj3(DevTree<T> t, int nrhs, const T* __restrict__ str, int64_t No,
+                                                  T* __restrict__ M, int ts) {
+  extern __shared__ unsigned char smraw[];
+  const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
+  T* Rre = reinterpret_cast<T*>(smraw);
+  T* Rim = Rre + ts * Lc;
+  T* Dre = Rim + ts * Lc;
+  T* Dim = Dre + ts * Lc;
+  T* sq = Dim + ts * Lc;  // [2][ts] v, w
+  T* sn = sq + 2 * ts;    // [3][ts] normals
+  const int b = t.leaf_src_list[blockIdx.x];
+  const int g = t.leaf_off + b;
+  const int rhs = blockIdx.y;
+  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T ih = (T)1 / h;
+  const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
+  T acc[KMAX][2];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) acc[k][0] = acc[k][1] = 0;
+  const int beg = t.src_beg[b], end = t.src_end[b];
+  for (int t0 = beg; t0 < end; t0 += ts) {
+    const int nt = min(ts, end - t0);
+    for (int task = threadIdx.x; task < nt * (p + 1); task += blockDim.x) {
+      const int j = task / (p + 1), m = task - j * (p + 1);
+      const int s = t0 + j;
+      regular_column_to_lds<T>(p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
+                               Rim + j * Lc);
+    }
+    if (threadIdx.x < nt) {
+      const int s = t0 + threadIdx.x;
+      sq[threadIdx.x] = str[(int64_t)(rhs * 2) * No + s];
+      sq[ts + threadIdx.x] = str[(int64_t)(rhs * 2 + 1) * No + s];
+      sn[threadIdx.x] = t.snx[s];
+      sn[ts + threadIdx.x] = t.sny[s];
+      sn[2 * ts + threadIdx.x] = t.snz[s];
+    }
+    __syncthreads();
+    // D_n^m = (n . grad) Rt_n^m, m >= 0
+    for (int task = threadIdx.x; task < nt * Lc; task += blockDim.x) {
+      const int j = task / Lc, ci = task - j * Lc;
+      int n = (int)((sqrt(8.0 * ci + 1.0) - 1.0) * 0.5);
+      while (n * (n + 1) / 2 > ci) --n;
+      while ((n + 1) * (n + 2) / 2 <= ci) ++n;
+      const int m = ci - n * (n + 1) / 2;
+      const T fa = sqrt((T)((n + m) * (n - m)));
+      const T fb = (T)0.5 * sqrt((T)((n - m) * (n - m - 1) > 0 ? (n - m) * (n - m - 1) : 0));
+      const T fc = (T)0.5 * sqrt((T)((n + m) * (n + m - 1) > 0 ? (n + m) * (n + m - 1) : 0));
+      const T nx = sn[j], ny = sn[ts + j], nz = sn[2 * ts + j];
+      T a0, b0, a1, b1, a2, b2;
+      rt_get(Rre + j * Lc, Rim + j * Lc, n - 1, m, a0, b0);
+      rt_get(Rre + j * Lc, Rim + j * Lc, n - 1, m + 1, a1, b1);
+      rt_get(Rre + j * Lc, Rim + j * Lc, n - 1, m - 1, a2, b2);
+      Dre[j * Lc + ci] = nz * fa * a0 + fb * (nx * a1 + ny * b1) - fc * (nx * a2 - ny * b2);
+      Dim[j * Lc + ci] = nz * fa * b0 + fb * (nx * b1 - ny * a1) - fc * (nx * b2 + ny * a2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int c = threadIdx.x + k * 256;
+      if (c >= L) break;
+      int n, m, part;
+      rdecode(c, n, m, part);
+      const T sgn = part ? (T)-1 : (T)1;  // conj
+      const T fa = sqrt((T)((n + m) * (n - m)));
+      const T fb = (T)0.5 * sqrt((T)((n - m) * (n - m - 1) > 0 ? (n - m) * (n - m - 1) : 0));
+      const T fc = (T)0.5 * sqrt((T)((n + m) * (n + m - 1) > 0 ? (n + m) * (n + m - 1) : 0));
+      for (int jj = 0; jj < nt; ++jj) {
+        const T* dre = Dre + jj * Lc;
+        const T* dim = Dim + jj * Lc;
+        const T d1 = part ? dim[cidx(n, m)] : dre[cidx(n, m)];
+        const T nx = sn[jj], ny = sn[ts + jj], nz = sn[2 * ts + jj];
+        T a0, b0, a1, b1, a2, b2;
+        rt_get(dre, dim, n - 1, m, a0, b0);
+        rt_get(dre, dim, n - 1, m + 1, a1, b1);
+        rt_get(dre, dim, n - 1, m - 1, a2, b2);
+        const T gre = nz * fa * a0 + fb * (nx * a1 + ny * b1) - fc * (nx * a2 - ny * b2);
+        const T gim = nz * fa * b0 + fb * (nx * b1 - ny * a1) - fc * (nx * b2 + ny * a2);
+        const T d2 = part ? gim : gre;
+        const T v = sq[jj], w = sq[ts + jj];
+        acc[k][0] += sgn * v * d1 * ih;
+        acc[k][1] += sgn * (v * d2 * ih * ih + w * d1 * ih);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int c = threadIdx.x + k * 256;
+    if (c >= L) break;
+    for (int e = 0; e < 2; ++e) M[((int64_t)g * nrhs * 2 + rhs * 2 + e) * L + c] = acc[k][e];
+  }
+}
+
 // P2M tables of the sources of each leaf about the leaf centre (setup):
 //   H[j][c] = conj(Rt_c(xi_j)),  Dp[j][c] = conj(nu_j . grad Rt_c(xi_j)) / h,
 // xi_j = (y_j - centre) / h, real coefficient layout c < L.  A leaf multipole
@@ -744,7 +844,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   // hessian [6][Lh] (+ 3 [Lh] scratch; A3B: expansion 1), in LDS after the
   // source chunk when EXP_LDS, else in this block's slice of D
   constexpr int LEAF_CH = 512;                     // sources per LDS chunk
-  constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ ? 9 : 5;  // T values per source record
+  constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ || MODE == FMM_ADJ3 ? 9 : 5;  // T values per source record
   T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
   const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
   const int64_t dstride = (int64_t)nexp * 3 * Lg + 9 * Lh;
@@ -767,6 +867,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       for (int e = 0; e < nexp; ++e)
         derive3(sL + e * L, p, sG + (e * 3 + 0) * Lg, sG + (e * 3 + 1) * Lg, sG + (e * 3 + 2) * Lg);
     }
+    if (MODE == FMM_ADJ3) derive3(sL, p, sG, sG + Lg, sG + 2 * Lg);  // gradient of expansion 1
     if (MODE == FMM_A3B) {
       // second derivatives of expansion 1 from its gradient expansions; the
       // scratch after sH receives the unused d/dx of d/dy and d/dx, d/dy of d/dz
@@ -788,7 +889,8 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   typedef typename Vec4<T>::type T4;
   T4* rec1 = reinterpret_cast<T4*>(tile);
   T4* rec2 = rec1 + LEAF_CH;                                                   // A3B only
-  T* trm_ = reinterpret_cast<T*>(rec1 + (MODE == FMM_A3B || MODE == FMM_ADJ ? 2 : 1) * LEAF_CH);
+  constexpr bool TMASK = MODE == FMM_ADJ || MODE == FMM_ADJ3;  // the mask radius is the target's
+  T* trm_ = reinterpret_cast<T*>(rec1 + (MODE == FMM_A3B || TMASK ? 2 : 1) * LEAF_CH);
   __shared__ int upref[28];
   const int u0 = t.ulist_ptr[b], nU = t.ulist_ptr[b + 1] - u0;
   if (threadIdx.x == 0) {
@@ -807,13 +909,13 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     const bool act = i < tend;
     T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0, TR = 0;
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
-    if (MODE == FMM_ADJ && act) TR = t.trm2[i];
+    if (TMASK && act) TR = t.trm2[i];
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     // ---- far field: local expansions at xi = (x - c)/h, orders m = f mod F ----
     if (far && act) {
       const T x = (X - cx) * ih, y = (Y - cy) * ih, z = (Z - cz) * ih;
       const T r2 = x * x + y * y + z * z;
-      T pot = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
+      T pot = 0, pot2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
       T mre = 1, mim = 0;
       for (int m = 0; m <= p; ++m) {
         if (m > 0) {
@@ -847,6 +949,14 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
 #define ACC(dst, base, idxre, idxim) dst += (base)[idxre] * rre + ((idxim) >= 0 ? (base)[idxim] * rim : (T)0)
           if (MODE == FMM_POT || MODE == FMM_ADJ) {
             ACC(pot, sL, ire, iim);
+          } else if (MODE == FMM_ADJ3) {
+            ACC(pot, sL, ire, iim);
+            ACC(pot2, sL + L, ire, iim);
+            if (n < p) {
+              ACC(g1[0], sG, ire, iim);
+              ACC(g1[1], sG + Lg, ire, iim);
+              ACC(g1[2], sG + 2 * Lg, ire, iim);
+            }
           } else if (MODE == FMM_GRAD) {
             ACC(pot, sL, ire, iim);
             if (n < p) {
@@ -877,6 +987,9 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       }
       if (MODE == FMM_POT || MODE == FMM_ADJ) {
         a0 = pot;
+      } else if (MODE == FMM_ADJ3) {
+        a0 = pot;
+        a1 = pot2 + (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
       } else if (MODE == FMM_GRAD) {
         a0 = pot; a1 = g1[0] * ih; a2 = g1[1] * ih; a3 = g1[2] * ih;
       } else {
@@ -907,8 +1020,8 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         r1.z = t.sz[s];
         r1.w = str[(int64_t)(rhs * nstr) * No + s];
         rec1[j] = r1;
-        if (MODE != FMM_ADJ) trm_[j] = t.rm2[s];
-        if (MODE == FMM_A3B) {
+        if (!TMASK) trm_[j] = t.rm2[s];
+        if (MODE == FMM_A3B || MODE == FMM_ADJ3) {
           T4 r2;
           r2.x = t.snx[s];
           r2.y = t.sny[s];
@@ -933,7 +1046,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         for (int jj = f; jj < ns; jj += F) {
           const T4 r1 = rec1[jj];
           // the mask radius of the pair: the source's, or the target's in FMM_ADJ
-          const T rm = MODE == FMM_ADJ ? TR : trm_[jj];
+          const T rm = TMASK ? TR : trm_[jj];
           const T dx = X - r1.x;
           const T dy = Y - r1.y;
           const T dz = Z - r1.z;
@@ -949,6 +1062,15 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
           } else if (MODE == FMM_ADJ) {
             const T4 dv = rec2[jj];
             q0 += r1.w * ri + (dv.x * dx + dv.y * dy + dv.z * dz) * ri3;
+          } else if (MODE == FMM_ADJ3) {
+            // source normal in rec2, target normal (NX, NY, NZ)
+            const T4 nv = rec2[jj];
+            const T nd = nv.x * dx + nv.y * dy + nv.z * dz;
+            const T mx = nv.x - NX, my = nv.y - NY, mz = nv.z - NZ;
+            const T md = mx * dx + my * dy + mz * dz;
+            const T nm = nv.x * mx + nv.y * my + nv.z * mz;
+            q0 += r1.w * nd * ri3;
+            q1 += r1.w * ((T)3 * nd * md * ri3 * ri2 - nm * ri3) + nv.w * nd * ri3;
           } else if (MODE == FMM_GRAD) {
             const T q = r1.w;
             const T qr3 = q * ri3;
@@ -982,8 +1104,8 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
       out[base + i] = (T)a0;
-      if (nout > 1) {
-        out[base + N + i] = (T)a1;
+      if (nout > 1) out[base + N + i] = (T)a1;
+      if (nout > 2) {
         out[base + 2 * N + i] = (T)a2;
         out[base + 3 * N + i] = (T)a3;
       }
@@ -1007,11 +1129,16 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     int ts = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
-    if (t.p2m_H && mode == FMM_ADJ) {
+    if (t.p2m_H && (mode == FMM_ADJ || mode == FMM_ADJ3)) {
       fprintf(stderr, "lb: P2M tables are not built for the transposed tree\n");
       return;
     }
-    if (t.p2m_H && mode == FMM_A3B)
+    if (mode == FMM_ADJ3) {
+      int ts3 = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (4 * Lc_));
+      ts3 = ts3 < 1 ? 1 : (ts3 > P2M_TSMAX ? P2M_TSMAX : ts3);
+      const size_t sm3 = sizeof(T) * (4 * (size_t)ts3 * Lc_ + 5 * ts3);
+      hipLaunchKernelGGL(k_p2m_adj3<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm3, st, t, nrhs, str, No, M, ts3);
+    } else if (t.p2m_H && mode == FMM_A3B)
       hipLaunchKernelGGL((k_p2m_tab<T, true>), dim3(t.n_leaf_src, nrhs), dim3(64 * P2M_W), 0, st, t, nrhs, str, No,
                          t.p2m_H, t.p2m_D, M);
     else if (t.p2m_H)
@@ -1061,7 +1188,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   }
   tm->mark(PH_LEAF, st);
   const int nexp = fmm_nexp(mode);
-  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ ? 9 : 5) * 512;
+  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * 512;
   const size_t exps = sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
   const bool lds = chunk + exps <= 64 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
@@ -1077,6 +1204,8 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     LEAF_LAUNCH(FMM_GRAD)
   } else if (mode == FMM_ADJ) {
     LEAF_LAUNCH(FMM_ADJ)
+  } else if (mode == FMM_ADJ3) {
+    LEAF_LAUNCH(FMM_ADJ3)
   } else {
     LEAF_LAUNCH(FMM_A3B)
   }
@@ -1424,6 +1553,144 @@ void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No,
   KCHECK();
 }
 
+// ---- transposed A3 (see kernels.hpp) ----
+template <typename T>
+__global__ void k_adj3_str1(int nd, int64_t N, const T* __restrict__ v, const T* __restrict__ H,
+                            const int* __restrict__ src_pos, T* __restrict__ str, T* __restrict__ g2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t pos = src_pos[i];
+  for (int d = 0; d < nd; ++d) {
+    const T x = v[(int64_t)d * N + i];
+    const T w = (T)2 * H[i] * x;
+    str[(int64_t)(2 * d) * N + pos] = x;
+    str[(int64_t)(2 * d + 1) * N + pos] = w;
+    g2[2 * ((int64_t)d * N + i)] = x;
+    g2[2 * ((int64_t)d * N + i) + 1] = w;
+  }
+}
+
+template <typename T>
+__global__ void k_adj3_str2(int nd, int64_t N, const T* __restrict__ a, const T* __restrict__ b,
+                            const T* __restrict__ nrm, const int* __restrict__ src_pos, T* __restrict__ str,
+                            T* __restrict__ g2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t pos = src_pos[i];
+  for (int d = 0; d < nd; ++d) {
+    const T x = a[(int64_t)d * N + i], y = b[(int64_t)d * N + i];
+    str[(int64_t)(4 * d) * N + pos] = -y;
+    str[(int64_t)(4 * d + 1) * N + pos] = x * nrm[3 * i];
+    str[(int64_t)(4 * d + 2) * N + pos] = x * nrm[3 * i + 1];
+    str[(int64_t)(4 * d + 3) * N + pos] = x * nrm[3 * i + 2];
+    g2[2 * ((int64_t)d * N + i)] = x;
+    g2[2 * ((int64_t)d * N + i) + 1] = y;
+  }
+}
+
+// one wave per (patch, density), as k_adj_combine; STEP 1 writes a and b,
+// STEP 2 the transposed A3
+template <typename T, int STEP>
+__global__ __launch_bounds__(64) void k_adj3_comb(int NP, int n_p, int n_o, int64_t N, int64_t No,
+                                                  const T* __restrict__ P, const T* __restrict__ wo,
+                                                  const T* __restrict__ psi, const int* __restrict__ tgt_pos,
+                                                  const int64_t* __restrict__ cptr, const int* __restrict__ crow,
+                                                  const int64_t* __restrict__ cblk, const T* __restrict__ vals3,
+                                                  const T* __restrict__ g2, const T* __restrict__ v,
+                                                  const T* __restrict__ z, const double* __restrict__ scal,
+                                                  T* __restrict__ o1, T* __restrict__ o2) {
+  const int l = blockIdx.x, d = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int SW = n_p <= 32 ? 32 : 64, nsub = 64 / SW;
+  const int sub = lane / SW, k0 = lane - sub * SW;
+  const int nps = STEP == 1 ? 2 : 1;  // far outputs per density
+  const T* gq = g2 + (int64_t)d * N * 2;
+  for (int k = k0; k < n_p; k += SW) {
+    T f1 = 0, f2 = 0, c1 = 0, c2 = 0;
+    for (int m = sub; m < n_o; m += nsub) {
+      const int64_t om = (int64_t)l * n_o + m;
+      const T pw = P[(int64_t)m * n_p + k] * wo[om];
+      const int64_t tp = tgt_pos[om];
+      f1 += pw * psi[((int64_t)d * nps) * No + tp];
+      if (STEP == 1) f2 += pw * psi[((int64_t)d * nps + 1) * No + tp];
+    }
+    for (int64_t e = cptr[l] + sub; e < cptr[l + 1]; e += nsub) {
+      const T* c = vals3 + (cblk[e] * n_p + k) * 3;  // S, S', S''+D'
+      const T x = gq[2 * (int64_t)crow[e]], y = gq[2 * (int64_t)crow[e] + 1];
+      if (STEP == 1) {
+        c1 += c[1] * x;
+        c2 += c[2] * x + c[1] * y;
+      } else {
+        c1 += c[1] * x - c[0] * y;
+      }
+    }
+    T t1 = f1 * (T)INV4PI_D + c1, t2 = f2 * (T)INV4PI_D + c2;
+    if (nsub == 2) {
+      t1 += __shfl_xor(t1, 32, 64);
+      if (STEP == 1) t2 += __shfl_xor(t2, 32, 64);
+    }
+    if (sub == 0) {
+      const int64_t r = (int64_t)d * N + (int64_t)l * n_p + k;
+      if (STEP == 1) {
+        o1[r] = t1;
+        o2[r] = t2;
+      } else {
+        o1[r] = -(T)0.25 * v[r] + t1 + (T)scal[d] * z[(int64_t)l * n_p + k];
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_adj3_str1(int nd, int64_t N, const T* v, const T* H, const int* src_pos, T* str, T* g2,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_adj3_str1<T>, dim3((N + 255) / 256), dim3(256), 0, st, nd, N, v, H, src_pos, str, g2);
+  KCHECK();
+}
+template <typename T>
+void launch_adj3_str2(int nd, int64_t N, const T* a, const T* b, const T* nrm, const int* src_pos, T* str, T* g2,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_adj3_str2<T>, dim3((N + 255) / 256), dim3(256), 0, st, nd, N, a, b, nrm, src_pos, str, g2);
+  KCHECK();
+}
+template <typename T>
+void launch_adj3_comb1(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
+                       const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
+                       const T* vals3, const T* g2, T* a, T* b, hipStream_t st) {
+  hipLaunchKernelGGL((k_adj3_comb<T, 1>), dim3(NP, nd), dim3(64), 0, st, NP, n_p, n_o, N, No, P, wo, psi, tgt_pos,
+                     cptr, crow, cblk, vals3, g2, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, a,
+                     b);
+  KCHECK();
+}
+template <typename T>
+void launch_adj3_comb2(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
+                       const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
+                       const T* vals3, const T* g2, const T* v, const T* z, const double* scal, T* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((k_adj3_comb<T, 2>), dim3(NP, nd), dim3(64), 0, st, NP, n_p, n_o, N, No, P, wo, psi, tgt_pos,
+                     cptr, crow, cblk, vals3, g2, v, z, scal, out, (T*)nullptr);
+  KCHECK();
+}
+
+// per-block sums of v[d] (fixed order), then the serial-order reduction
+template <typename T>
+__global__ void k_colsum_part(int nd, int64_t N, const T* __restrict__ v, double* __restrict__ partial, int nblk) {
+  __shared__ double red[256];
+  for (int d = 0; d < nd; ++d) {
+    double a = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)nblk * 256)
+      a += (double)v[(int64_t)d * N + i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)d * nblk + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
 // serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
 __global__ void k_reduce_partials(const double* partial, int nblk, int nd, double scale, double* s) {
   __shared__ double red[256];
@@ -1446,6 +1713,28 @@ __global__ void k_add_scalar(T* out, int64_t N, int nd, const double* s) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   for (int d = 0; d < nd; ++d) out[(int64_t)d * N + i] += (T)s[d];
+}
+
+// out[d][i] = y[d][i] - w[i] * scal[d]   (FP64)
+__global__ void k_sub_wscal(int nd, int64_t N, const double* __restrict__ y, const double* __restrict__ w,
+                            const double* __restrict__ scal, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < nd; ++d) out[(int64_t)d * N + i] = y[(int64_t)d * N + i] - w[i] * scal[d];
+}
+void launch_sub_wscal(int nd, int64_t N, const double* y, const double* w, const double* scal, double* out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_wscal, dim3((N + 255) / 256), dim3(256), 0, st, nd, N, y, w, scal, out);
+  KCHECK();
+}
+
+template <typename T>
+void launch_colsum(int nd, int64_t N, const T* v, double scale, double* partial, double* scal, hipStream_t st) {
+  const int nblk = 256;
+  hipLaunchKernelGGL(k_colsum_part<T>, dim3(nblk), dim3(256), 0, st, nd, N, v, partial, nblk);
+  KCHECK();
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblk, nd, scale, scal);
+  KCHECK();
 }
 
 template <typename T>
@@ -1602,7 +1891,16 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
                                         const int*, T*, T*, hipStream_t);                                       \
   template void launch_adj_combine<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,       \
                                       const int*, const int64_t*, const int*, const int64_t*, const T*, const T*, \
-                                      T*, hipStream_t);
+                                      T*, hipStream_t);                                                           \
+  template void launch_adj3_str1<T>(int, int64_t, const T*, const T*, const int*, T*, T*, hipStream_t);          \
+  template void launch_adj3_str2<T>(int, int64_t, const T*, const T*, const T*, const int*, T*, T*, hipStream_t); \
+  template void launch_adj3_comb1<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,         \
+                                     const int*, const int64_t*, const int*, const int64_t*, const T*, const T*, \
+                                     T*, T*, hipStream_t);                                                        \
+  template void launch_adj3_comb2<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,         \
+                                     const int*, const int64_t*, const int*, const int64_t*, const T*, const T*, \
+                                     const T*, const T*, const double*, T*, hipStream_t);                         \
+  template void launch_colsum<T>(int, int64_t, const T*, double, double*, double*, hipStream_t);
 INST(float)
 INST(double)
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);

@@ -13,11 +13,24 @@ namespace lb {
 //   FMM_ADJ : psi = sum_j q_j / r + d_j . (x - y_j) / r^3 (sources with a
 //             charge q_j and a dipole vector d_j: strengths q, dx, dy, dz;
 //             the mask radius belongs to the target, see DevTree::trm2)
+//   FMM_ADJ3: the far part of the first step of the transposed A3, at
+//             targets x with normal nu from sources y_j with normal n_j and
+//             strengths v_j, w_j (d = x - y_j, m = n_j - nu):
+//               psi_a = sum_j v_j (n_j . d) / r^3                 (S'^T)
+//               psi_b = sum_j v_j (3 (n_j . d)(m . d) / r^5 - (n_j . m) / r^3)
+//                     + w_j (n_j . d) / r^3                       ((S''+D')^T, S'^T)
+//             through a dipole expansion (v n; potential and gradient) and
+//             a quadrupole + dipole expansion (v n n^T, w n; potential):
+//             psi_b = phi_2 + nu . grad phi_1
 // phi = sum_j c_j / |x - y_j| (no 1/(4 pi)).
-enum FmmMode { FMM_POT = 0, FMM_GRAD = 1, FMM_A3B = 2, FMM_ADJ = 3 };
-__host__ __device__ inline int fmm_nout(int mode) { return mode == FMM_POT || mode == FMM_ADJ ? 1 : 4; }
-__host__ __device__ inline int fmm_nexp(int mode) { return mode == FMM_A3B ? 3 : 1; }
-__host__ __device__ inline int fmm_nstr(int mode) { return mode == FMM_A3B ? 2 : (mode == FMM_ADJ ? 4 : 1); }
+enum FmmMode { FMM_POT = 0, FMM_GRAD = 1, FMM_A3B = 2, FMM_ADJ = 3, FMM_ADJ3 = 4 };
+__host__ __device__ inline int fmm_nout(int mode) {
+  return mode == FMM_POT || mode == FMM_ADJ ? 1 : (mode == FMM_ADJ3 ? 2 : 4);
+}
+__host__ __device__ inline int fmm_nexp(int mode) { return mode == FMM_A3B ? 3 : (mode == FMM_ADJ3 ? 2 : 1); }
+__host__ __device__ inline int fmm_nstr(int mode) {
+  return mode == FMM_A3B || mode == FMM_ADJ3 ? 2 : (mode == FMM_ADJ ? 4 : 1);
+}
 
 // Batched translation plan: (matrix id, source box, target box) triples
 // sorted by (matrix, target).  Each matrix group is one GEMM
@@ -87,6 +100,37 @@ template <typename T>
 void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
                         const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow,
                         const int64_t* cblk, const T* vals4, const T* g4, T* sigma_bar, hipStream_t st);
+
+// Transposed A3 (adjoint of lb_apply_A3), on the transposed tree:
+//   step 1 strengths from v [nd][N]: (v, 2 H v) -> str [nd][2][N] at src_pos
+//     and g2 [nd][N][2] (user order)
+//   step 1 combine: a = S'^T v, b = (S''+D')^T v + S'^T (2 H v) from psi
+//     [nd][2][No] (psi_a, psi_b) and the transposed corrections (vals3)
+//   step 2 strengths: charge -b, dipole a n -> str [nd][4][N] (FMM_ADJ),
+//     g2 = (a, b)
+//   step 2 combine: out = -v/4 + (far) + C_S'^T a - C_S^T b + cs_d z,
+//     cs_d = sum_i v_i / area (scal [nd]), z = S^T S^T w
+template <typename T>
+void launch_adj3_str1(int nd, int64_t N, const T* v, const T* H, const int* src_pos, T* str, T* g2,
+                      hipStream_t st);
+template <typename T>
+void launch_adj3_str2(int nd, int64_t N, const T* a, const T* b, const T* nrm, const int* src_pos, T* str, T* g2,
+                      hipStream_t st);
+template <typename T>
+void launch_adj3_comb1(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
+                       const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
+                       const T* vals3, const T* g2, T* a, T* b, hipStream_t st);
+template <typename T>
+void launch_adj3_comb2(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
+                       const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
+                       const T* vals3, const T* g2, const T* v, const T* z, const double* scal, T* out,
+                       hipStream_t st);
+// out[d][i] = y[d][i] - w[i] scal[d]  (FP64)
+void launch_sub_wscal(int nd, int64_t N, const double* y, const double* w, const double* scal, double* out,
+                      hipStream_t st);
+// scal[d] = scale * sum_i v[d][i] (deterministic two-level reduction)
+template <typename T>
+void launch_colsum(int nd, int64_t N, const T* v, double scale, double* partial, double* scal, hipStream_t st);
 
 // P2M tables of every source about its leaf centre (setup): H, Dp [No][L]
 // in tree order; see k_p2m_build

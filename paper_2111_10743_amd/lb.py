@@ -33,7 +33,8 @@ LB_HOST_OCTREE = 16
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj",
-            "lb_apply_gradS_timed", "lb_apply_A3", "lb_solve", "lb_destroy", "lb_last_error")
+            "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj", "lb_destroy",
+            "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -95,6 +96,8 @@ def lib():
         L.lb_apply_gradS_timed.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, dp, vp]
         L.lb_apply_A3.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
+        L.lb_solve_adj.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
+        L.lb_apply_A3_adj.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_destroy.argtypes = [vp]
         L.lb_destroy.restype = None
         L.lb_tree_destroy.restype = None
@@ -312,6 +315,27 @@ class Surface:
         _check(lib().lb_apply_A3(self._ctx, nd, self._prec(tau), _ptr(tau), _ptr(res), _stream()))
         return res
 
+    def apply_A3_adj(self, v, out=None):
+        """A3^T v (the transpose of the discrete A3 of this precision)."""
+        import torch
+        nd = self._nd(v)
+        res = out if out is not None else torch.empty_like(v)
+        _check(lib().lb_apply_A3_adj(self._ctx, nd, self._prec(v), _ptr(v), _ptr(res), _stream()))
+        return res
+
+    def solve_adj(self, ubar, tol=1e-10, mode=LB_SOLVE_FP64):
+        """fbar = (d u / d f)^T ubar for u = solve(f) (lb_solve_adj)."""
+        import torch
+        if ubar.dtype != torch.float64:
+            raise TypeError("ubar must be float64")
+        nrhs = self._nd(ubar)
+        fbar = torch.empty_like(ubar)
+        info = (SolveInfo * nrhs)()
+        code = _check(lib().lb_solve_adj(self._ctx, nrhs, _ptr(ubar), _ptr(fbar), tol, mode, info, _stream()))
+        infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
+                  "removed_mean": i.removed_mean} for i in info]
+        return fbar, infos, code
+
     def solve(self, f, tol=1e-10, mode=LB_SOLVE_FP64):
         import torch
         if f.dtype != torch.float64:
@@ -358,7 +382,30 @@ def _autograd():
                 return None, None
             return None, ctx.surf.apply_gradS_adj(*c)
 
-    return ApplyS, ApplyGradS
+    class Solve(torch.autograd.Function):
+        """u = lb_solve(f); backward: fbar = lb_solve_adj(ubar)."""
+
+        @staticmethod
+        def forward(ctx, surf, f, tol, mode):
+            ctx.surf, ctx.tol, ctx.mode = surf, tol, mode
+            u, info, code = surf.solve(f.contiguous(), tol=tol, mode=mode)
+            if code != LB_OK:
+                raise LBError(code, "solve did not converge")
+            return u
+
+        @staticmethod
+        def backward(ctx, ubar):
+            fbar, info, code = ctx.surf.solve_adj(ubar.contiguous(), tol=ctx.tol, mode=ctx.mode)
+            if code != LB_OK:
+                raise LBError(code, "adjoint solve did not converge")
+            return None, fbar, None, None
+
+    return ApplyS, ApplyGradS, Solve
+
+
+def solve(surf, f, tol=1e-10, mode=LB_SOLVE_FP64):
+    """Differentiable u = lb_solve(f) (torch.autograd; backward = lb_solve_adj)."""
+    return _autograd()[2].apply(surf, f, tol, mode)
 
 
 def apply_S(surf, sigma):

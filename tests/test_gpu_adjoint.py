@@ -136,3 +136,98 @@ def test_autograd_apply(torch_dev, c1_oracle):
     note(f"apply_gradS: directional derivative fd {fd:.12e} adjoint {an:.12e}")
     assert abs(fd - an) < 1e-8 * abs(an)
     s.close()
+
+
+@pytest.mark.parametrize("direct", [True, False])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c1_A3_adj_vs_oracle(torch_dev, c1_oracle, direct, prec):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    o = c1_oracle
+    g = o.g
+    note(f"c1 A3^T direct={direct} prec={prec}")
+    s = P.Surface(g.Xp, g.Xup, g.Xvp, 4, direct=direct)
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(61)
+    v = np.stack([rng.standard_normal(g.N), I.real_sph_harm(2, 1, g.x) + 0.2])
+    out = s.apply_A3_adj(torch.tensor(v, dtype=dt, device="cuda")).double().cpu().numpy()
+    AT = o.A3_matrix().T
+    for d in range(2):
+        e = rel_l2(out[d], AT @ v[d])
+        note(f"density {d}: A3^T error {e:.2e}")
+        assert e < (1e-9 if prec == 64 else 1e-5)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_fmm_A3_adj_dot_product(torch_dev, prec):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.ellipsoid_patches(2, nodes(6), (1.0, 1.5, 2.0))
+    note(f"fmm A3^T prec={prec} setup")
+    s = P.Surface(X, Xu, Xv, 6)
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(62)
+    x = torch.tensor(rng.standard_normal((3, s.N)), dtype=dt, device="cuda")
+    y = torch.tensor(rng.standard_normal((3, s.N)), dtype=dt, device="cuda")
+    Ax = s.apply_A3(x).double()
+    ATy = s.apply_A3_adj(y).double()
+    for d in range(3):
+        lhs = float((y[d].double() * Ax[d]).sum())
+        rhs = float((ATy[d] * x[d].double()).sum())
+        scale = float(y[d].double().norm() * Ax[d].norm())
+        note(f"density {d}: <y, A3 x> {lhs:.12e} <A3^T y, x> {rhs:.12e} rel {abs(lhs - rhs) / scale:.2e}")
+        assert abs(lhs - rhs) < (1e-9 if prec == 64 else 1e-5) * scale
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c1_solve_adj_vs_oracle(torch_dev, c1_oracle, mode):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    o = c1_oracle
+    g = o.g
+    note(f"c1 adjoint solve mode={mode}")
+    s = P.Surface(g.Xp, g.Xup, g.Xvp, 4)
+    rng = np.random.default_rng(63)
+    ub = np.stack([rng.standard_normal(g.N), g.w * I.real_sph_harm(3, 2, g.x)])
+    fb, info, code = s.solve_adj(torch.tensor(ub, dtype=torch.float64, device="cuda"), tol=1e-12, mode=mode)
+    note(f"info {info}")
+    assert code == 0
+    fb = fb.cpu().numpy()
+    for d in range(2):
+        e = rel_l2(fb[d], o.solve_adjoint(ub[d]))
+        note(f"rhs {d}: adjoint solve error vs oracle {e:.2e}")
+        assert e < 1e-9
+    s.close()
+
+
+def test_autograd_solve_fd(torch_dev):
+    """dJ/df through lb_solve_adj against central differences of the solve
+    (J = 1/2 sum w (u - u_t)^2 is quadratic in f), FMM path, FP32+refine."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.ellipsoid_patches(2, nodes(6), (1.0, 1.5, 2.0))
+    note("autograd solve setup")
+    s = P.Surface(X, Xu, Xv, 6)
+    w = torch.tensor(s.geometry()[0], device="cuda")
+    rng = np.random.default_rng(64)
+    xi = I.sphere_preimage(X.reshape(-1, 3), (1.0, 1.5, 2.0))
+    f = torch.tensor(I.sh_series(I.random_sh_coeffs(4, seed=2, decay=2.0), xi), device="cuda", requires_grad=True)
+    ut = torch.tensor(rng.standard_normal(s.N) * 0.01, device="cuda")
+    mode = P.LB_SOLVE_FP32_REFINE
+    u = P.solve(s, f, 1e-12, mode)
+    J = 0.5 * (w * (u - ut) ** 2).sum()
+    J.backward()
+    v = torch.tensor(I.sh_series(I.random_sh_coeffs(4, seed=3, decay=2.0), xi), device="cuda")
+    h = 1e-2
+    with torch.no_grad():
+        up, _, _ = s.solve(f + h * v, tol=1e-12, mode=mode)
+        um, _, _ = s.solve(f - h * v, tol=1e-12, mode=mode)
+        fd = float((0.5 * (w * (up - ut) ** 2).sum() - 0.5 * (w * (um - ut) ** 2).sum()) / (2 * h))
+    an = float((f.grad * v).sum())
+    note(f"directional derivative fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(an):.2e}")
+    assert abs(fd - an) < 1e-6 * abs(an)
+    s.close()

@@ -171,3 +171,25 @@ def test_adjoint_dot_product_identity(c1_oracle):
         r = o.adjoint_gradS(**kw) @ sig
         l = {"gpot": gp @ pot, "ggrad": (gg * grad).sum(), "gdSdn": gd @ dn, "gsurf": (gs * surf).sum()}[next(iter(kw))]
         assert abs(l - r) < 1e-12 * (abs(l) + np.abs(sig).sum())
+
+
+def test_A3_matrix_and_solve_adjoint(c1_oracle):
+    """Dense A3 against the layer-by-layer apply of Section 4.3, and the
+    transposed solve map against the forward solve by the dot-product
+    identity <ubar, u(f)> = <fbar(ubar), f> (u(f) by GMRES, fbar by a dense
+    solve with A3^T)."""
+    o = c1_oracle
+    g = o.g
+    rng = np.random.default_rng(23)
+    A = o.A3_matrix()
+    for _ in range(2):
+        v = rng.standard_normal(g.N)
+        assert np.linalg.norm(A @ v - o.A3(v)) < 1e-12 * np.linalg.norm(A @ v)
+    f = rng.standard_normal(g.N)
+    ub = rng.standard_normal(g.N)
+    u, info = o.solve(f, tol=1e-14)
+    fb = o.solve_adjoint(ub)
+    lhs, rhs = ub @ u, fb @ f
+    assert abs(lhs - rhs) < 1e-10 * np.linalg.norm(ub) * np.linalg.norm(u) * 10
+    # the transposed projection removes exactly the weighted constant direction
+    assert abs(np.ones(g.N) @ fb) < 1e-9 * np.abs(fb).sum()
