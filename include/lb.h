@@ -96,6 +96,7 @@ typedef struct {
   int64_t p2p_pairs32, m2l_pairs32; /* near-field (target, source) pairs and V-list
                                        (target box, source box) pairs, FP32 tree */
   int64_t p2p_pairs64, m2l_pairs64; /* the same for the FP64 tree               */
+  int64_t n_surf;                   /* surfaces of the context (lb_setup_batch)  */
 } lb_sizes;
 
 /* Fill *opts with the defaults listed above. */
@@ -117,6 +118,21 @@ lb_status lb_setup(lb_ctx **ctx, int n_patches, int order, const double *X,
                    const double *Xu, const double *Xv, const lb_opts *opts,
                    void *stream);
 
+/* Several independent surfaces in one context (for instance many small
+ * surfaces whose applies and solves are batched): surface q has
+ * patches_per_surf[q] patches, and X, Xu, Xv hold the patches of all surfaces
+ * one surface after the other.  Every apply, the A3 operator and the solves
+ * act on all surfaces at once (vectors [nd][N] with N the total number of
+ * nodes, surfaces in order), but the surfaces never interact: each has its
+ * own near lists, corrections, octree (one launch per FMM phase covers all
+ * trees), mean projection and W term of A3, and each (right-hand side,
+ * surface) pair is its own GMRES system with its own tolerance; info of
+ * lb_solve / lb_solve_adj then has nrhs * n_surf entries (index
+ * rhs * n_surf + surface).  Errors as lb_setup. */
+lb_status lb_setup_batch(lb_ctx **ctx, int n_surf, const int32_t *patches_per_surf, int order,
+                         const double *X, const double *Xu, const double *Xv,
+                         const lb_opts *opts, void *stream);
+
 /* Sizes of the discretization held by ctx. */
 lb_status lb_get_sizes(const lb_ctx *ctx, lb_sizes *out);
 
@@ -132,8 +148,8 @@ lb_status lb_get_geometry(const lb_ctx *ctx, double *w, double *normals, double 
 lb_status lb_get_corrections(const lb_ctx *ctx, int64_t *row_ptr, int32_t *patch,
                              double *vals);
 
-/* The FMM octree of one precision (transposed = 1: the tree of the adjoint
- * applies, after the first one).  Uniform depth; boxes numbered level by
+/* The FMM octree of surface `surf` in one precision (transposed = 1: the
+ * tree of the adjoint applies, after the first one).  Uniform depth; boxes numbered level by
  * level in Morton order (global id g); leaves = the boxes of level depth,
  * numbered from 0.  Outputs (host, nullable; sizes from *info, so a first
  * call may pass only info):
@@ -155,7 +171,7 @@ typedef struct {
   int32_t depth, nbox, nleaf, nulist, nvlist;
   double lo[3], side;
 } lb_tree_info;
-lb_status lb_get_tree(const lb_ctx *ctx, int prec, int transposed, lb_tree_info *info,
+lb_status lb_get_tree(const lb_ctx *ctx, int prec, int transposed, int surf, lb_tree_info *info,
                       int64_t *tgt_perm, int64_t *src_perm, int32_t *leaf_ranges,
                       int32_t *ulist_ptr, int32_t *ulist, int32_t *vlist_ptr,
                       int32_t *vlist_src, int32_t *vlist_off, int32_t *boxes);
@@ -241,7 +257,7 @@ lb_status lb_apply_A3_adj(lb_ctx *ctx, int nd, int prec, const void *v, void *ou
  * A3 sigma = f - mean(f) and u = S[S[sigma]] (eq. ie-dis2, Section 6 GMRES:
  * x0 = 0, no restart, relative Euclidean residual < tol, at most
  * opts.max_iter iterations per inner solve).  f, u: device double [nrhs][N].
- * info: host [nrhs], nullable.  Synchronizes `stream`.  Returns LB_ENOCONV
+ * info: host [nrhs * n_surf], nullable.  Synchronizes `stream`.  Returns LB_ENOCONV
  * if some right-hand side did not reach tol (its best iterate is written),
  * LB_ENOTMEANZERO in strict-mean mode. */
 lb_status lb_solve(lb_ctx *ctx, int nrhs, const double *f, double *u, double tol,
@@ -251,7 +267,7 @@ lb_status lb_solve(lb_ctx *ctx, int nrhs, const double *f, double *u, double tol
  * (W f = sum_i w_i f_i / area), fbar = (I - w 1^T / area) A3^{-T} S^T S^T ubar,
  * the A3^T system solved by GMRES (or FP32 inner / FP64 outer refinement) to
  * tol as in lb_solve.  ubar, fbar: device double [nrhs][N]; info: host
- * [nrhs], nullable (removed_mean reports sum_i y_i / area of the solution y).
+ * [nrhs * n_surf], nullable (removed_mean reports sum_i y_i / area of the solution y).
  * Synchronizes `stream`; LB_ENOCONV as lb_solve. */
 lb_status lb_solve_adj(lb_ctx *ctx, int nrhs, const double *ubar, double *fbar, double tol,
                        int mode, lb_solve_info *info, void *stream);

@@ -13,8 +13,9 @@ Surfaces (each patch is a chart T0 -> Gamma, T0 = {u, v >= 0, u + v <= 1}):
 * ``ellipsoid_patches(nsub, axes)``: the same charts scaled by diag(axes).
 * ``torus_patches(R, r, n_theta, n_phi)``: (theta, phi) grid, each cell split
   along a fixed diagonal.
-* ``star_patches(coeffs, n_s)``: r(xi) = 1 + 0.25 sum a_lm Y_lm(xi) on the
-  sphere charts of an icosahedron whose faces are split n_s x n_s.
+* ``star_patches(n_s, uv, coeffs)``: r(xi) = 1 + 0.25 sum a_lm Y_lm(xi) on
+  the sphere charts of an icosahedron whose faces are split n_s x n_s
+  (``star_coeffs(seed)`` draws the a_lm).
 """
 import numpy as np
 from scipy.special import sph_harm_y
@@ -194,3 +195,34 @@ def random_sh_coeffs(lmax, seed, decay=2.0, lmin=1):
 
 def sh_series(coeffs, x):
     return sum(a * real_sph_harm(l, m, x) for l, m, a in coeffs)
+
+
+# ----------------------------------------------------------------------
+# star-shaped surfaces r(xi) = 1 + amp * sum_{l <= lmax} a_lm Y_lm(xi)
+# ----------------------------------------------------------------------
+def star_coeffs(seed, lmax=4, amp=0.25, rmin=0.3):
+    """a_lm ~ U(-1, 1) / (l + 1), l = 0..lmax (seeded); redrawn until the
+    radius stays >= rmin on a fine sample of the sphere."""
+    rng = np.random.default_rng(seed)
+    probe = icosphere(4)[0]
+    while True:
+        c = [(l, m, rng.uniform(-1.0, 1.0) / (l + 1.0)) for l in range(lmax + 1) for m in range(-l, l + 1)]
+        if (1.0 + amp * sh_series(c, probe)).min() >= rmin:
+            return c
+
+
+def star_patches(n_s, uv, coeffs, amp=0.25, h=1e-3):
+    """Charts X = r(xi) xi over the icosahedron split into n_s^2 triangles per
+    face; X_u = r xi_u + (d r / d u) xi with the derivative of r along the
+    chart by 4th-order central differences of r(normalize(xi + t xi_u))."""
+    T = icosphere_ns(n_s)
+    xi, xu, xv = _radial_charts(T, np.asarray(uv, dtype=float))
+    r = lambda p: 1.0 + amp * sh_series(coeffs, p / np.linalg.norm(p, axis=-1, keepdims=True))
+
+    def dr(d):
+        return (-r(xi + 2 * h * d) + 8 * r(xi + h * d) - 8 * r(xi - h * d) + r(xi - 2 * h * d)) / (12 * h)
+    r0 = r(xi)[..., None]
+    X = r0 * xi
+    Xu = r0 * xu + dr(xu)[..., None] * xi
+    Xv = r0 * xv + dr(xv)[..., None] * xi
+    return X, Xu, Xv

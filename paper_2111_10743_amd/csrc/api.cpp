@@ -50,7 +50,7 @@ template <typename T> static inline T* dptr(const DBuf& b) { return reinterpret_
 
 struct PlanBuf {
   GemmPlan pl;
-  DBuf grp_mat, grp_beg, pair_src, boxes, box_level, tptr, tpairs, work[9];
+  DBuf grp_mat, grp_beg, pair_src, boxes, box_scale, tptr, tpairs, work[9];
 };
 
 template <typename T>
@@ -61,7 +61,7 @@ static void upload(DBuf& d, const std::vector<T>& h);
 // the plan accumulates).
 struct Triple { int mat, tgt, src; };
 static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<int>& boxes,
-                         const std::vector<int>& levels, bool scaled, bool accumulate, int nbox_total) {
+                         const std::vector<double>& scale, bool scaled, bool accumulate, int nbox_total) {
   std::stable_sort(tr.begin(), tr.end(), [](const Triple& a, const Triple& b) {
     return a.mat != b.mat ? a.mat < b.mat : a.tgt < b.tgt;
   });
@@ -79,13 +79,13 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
   std::vector<int> fill(tptr.begin(), tptr.end() - 1);
   for (size_t i = 0; i < tr.size(); ++i) tpairs[fill[slot[tr[i].tgt]]++] = (int)i;
   upload(pb.grp_mat, gmat); upload(pb.grp_beg, gbeg); upload(pb.pair_src, psrc);
-  upload(pb.boxes, boxes); upload(pb.box_level, levels); upload(pb.tptr, tptr); upload(pb.tpairs, tpairs);
+  upload(pb.boxes, boxes); upload(pb.box_scale, scale); upload(pb.tptr, tptr); upload(pb.tpairs, tpairs);
   GemmPlan& pl = pb.pl;
   pl.ngrp = (int)gmat.size();
   pl.npair = (int)tr.size();
   pl.nbox = (int)boxes.size();
   pl.grp_mat = dptr<int>(pb.grp_mat); pl.grp_beg = dptr<int>(pb.grp_beg); pl.pair_src = dptr<int>(pb.pair_src);
-  pl.boxes = dptr<int>(pb.boxes); pl.box_level = dptr<int>(pb.box_level);
+  pl.boxes = dptr<int>(pb.boxes); pl.box_scale = scaled ? dptr<double>(pb.box_scale) : nullptr;
   pl.tptr = dptr<int>(pb.tptr); pl.tpairs = dptr<int>(pb.tpairs);
   pl.scaled = scaled;
   pl.accumulate = accumulate;
@@ -115,11 +115,12 @@ static void upload_as(DBuf& d, const std::vector<S>& h) {
 template <typename T>
 struct Prec {
   int p = 0, L = 0;
-  Octree tree;
+  std::vector<Octree> trees;  // one per surface
   DevTree<T> dt{};
   DBuf tx, ty, tz, tnx, tny, tnz, sx, sy, sz, snx, sny, snz, rm2, trm2, bcx, bcy, bcz;
   DBuf tgt_beg, tgt_end, src_beg, src_end, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off;
   DBuf parent, child, child_src, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
+  DBuf leaf_box, leaf_lvl, leaf_h;
   DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
   DBuf m2m, l2l, m2l, dgrad, dhess;
   // batched translation plans (M2L over all levels; M2M, L2L per level)
@@ -129,7 +130,7 @@ struct Prec {
   DBuf Y;
   DBuf p2m_H, p2m_D;
   // work
-  DBuf str, M, Lc, D, fmm, mu, tmp_in, tmp_out;
+  DBuf str, M, Lc, D, fmm, mu, y2, tmp_in, tmp_out;
   int ws_rhs = 0;
 };
 
@@ -139,6 +140,11 @@ using namespace lb;
 
 struct lb_ctx {
   int k = 0, NP = 0, n_p = 0, n_o = 0;
+  // surfaces: surface q owns patches [surf_patch[q], surf_patch[q+1]) (its
+  // nodes and oversampled points follow in the same order)
+  int n_surf = 1;
+  std::vector<int> surf_patch;
+  std::vector<double> surf_area;
   int64_t N = 0, No = 0;
   lb_opts opts{};
   std::unique_ptr<RefElem> re;
@@ -162,9 +168,11 @@ struct lb_ctx {
   bool z_built32 = false, z_built64 = false;
   std::vector<float> rm2f;
   // solver workspace
-  DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp;
-  int v_cols = 0;
-  double area = 0;
+  DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp, msys, msys_part, msys2;
+  // per-surface row ranges: node_off [n_surf+1] (host and device), the
+  // surface of every node, 1/area per surface; scratch for per-surface sums
+  std::vector<int64_t> node_off_h;
+  DBuf node_off, node_surf, inv_area, seg_scal;
 };
 
 namespace lb {
@@ -206,12 +214,85 @@ static void pack_vals(const std::vector<double>& C, int64_t nnz, std::vector<T>&
 
 constexpr size_t P2M_TABLE_MAX = (size_t)64 << 30;
 
-// Device state of one precision.  With `fwd` set, the transposed problem of
-// the adjoint applies: the Nystrom nodes are the sources and the oversampled
-// points the targets (a tree of the same depth over the same points, so the
-// same boxes), the mask radius moves with the oversampled point to the
-// target side, and the reference matrices, corrections and translation
-// operators are those of `fwd`.
+// Several octrees (one per surface) numbered as one forest: the boxes,
+// leaves and tree positions of tree s follow those of trees 0..s-1; every
+// list holds global numbers.  Trees never interact: each surface's far
+// field is its own.
+struct Forest {
+  int depth = 0, nbox = 0, nleaf = 0;
+  std::vector<int> box_level, tree_depth, parent, child, child_src;
+  std::vector<double> box_cen, box_scale;      // [nbox][3], [nbox] 2^level / side of its tree
+  std::vector<uint8_t> has_src, has_tgt;
+  std::vector<int> leaf_box, leaf_lvl;
+  std::vector<double> leaf_h;
+  std::vector<int> tgt_beg, tgt_end, src_beg, src_end;  // per leaf, global tree positions
+  std::vector<int64_t> tgt_perm, src_perm, tgt_pos, src_pos;
+  std::vector<int> ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off;
+};
+
+static void merge_forest(const std::vector<Octree>& trees, const std::vector<int64_t>& toff,
+                         const std::vector<int64_t>& soff, Forest& F) {
+  F = Forest();
+  F.ulist_ptr.push_back(0);
+  F.vlist_ptr.push_back(0);
+  int boff = 0, loff = 0;
+  for (size_t s = 0; s < trees.size(); ++s) {
+    const Octree& t = trees[s];
+    const int nb = t.nbox(), nl = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
+    F.depth = std::max(F.depth, t.depth);
+    for (int l = 0; l <= t.depth; ++l) {
+      const double h = t.box_side(l);
+      for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
+        F.box_level.push_back(l);
+        F.tree_depth.push_back(t.depth);
+        F.box_cen.push_back(t.lo[0] + (t.bx[g] + 0.5) * h);
+        F.box_cen.push_back(t.lo[1] + (t.by[g] + 0.5) * h);
+        F.box_cen.push_back(t.lo[2] + (t.bz[g] + 0.5) * h);
+        F.box_scale.push_back((double)(1 << l) / t.side);
+        F.parent.push_back(t.parent[g] < 0 ? -1 : t.parent[g] + boff);
+        for (int c = 0; c < 8; ++c) {
+          const int ch = t.child[(size_t)g * 8 + c];
+          F.child.push_back(ch < 0 ? -1 : ch + boff);
+          F.child_src.push_back(ch < 0 || !t.has_src[ch] ? -1 : ch + boff);
+        }
+        F.has_src.push_back(t.has_src[g]);
+        F.has_tgt.push_back(t.has_tgt[g]);
+        for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) {
+          F.vlist_src.push_back(t.vlist_src[v] + boff);
+          F.vlist_off.push_back(t.vlist_off[v]);
+        }
+        F.vlist_ptr.push_back((int)F.vlist_src.size());
+      }
+    }
+    for (int b = 0; b < nl; ++b) {
+      F.leaf_box.push_back(t.lev_off[t.depth] + b + boff);
+      F.leaf_lvl.push_back(t.depth);
+      F.leaf_h.push_back(t.box_side(t.depth));
+      F.tgt_beg.push_back(t.tgt_beg[b] + (int)toff[s]);
+      F.tgt_end.push_back(t.tgt_end[b] + (int)toff[s]);
+      F.src_beg.push_back(t.src_beg[b] + (int)soff[s]);
+      F.src_end.push_back(t.src_end[b] + (int)soff[s]);
+      for (int k = t.ulist_ptr[b]; k < t.ulist_ptr[b + 1]; ++k) F.ulist.push_back(t.ulist[k] + loff);
+      F.ulist_ptr.push_back((int)F.ulist.size());
+    }
+    for (int64_t j : t.tgt_perm) F.tgt_perm.push_back(j + toff[s]);
+    for (int64_t j : t.src_perm) F.src_perm.push_back(j + soff[s]);
+    for (int64_t j : t.tgt_pos) F.tgt_pos.push_back(j + toff[s]);
+    for (int64_t j : t.src_pos) F.src_pos.push_back(j + soff[s]);
+    boff += nb;
+    loff += nl;
+  }
+  F.nbox = boff;
+  F.nleaf = loff;
+}
+
+// Device state of one precision: one octree per surface, merged into a
+// forest.  With `fwd` set, the transposed problem of the adjoint applies:
+// the Nystrom nodes are the sources and the oversampled points the targets
+// (trees of the same depths over the same points, so the same boxes), the
+// mask radius moves with the oversampled point to the target side, and the
+// reference matrices, corrections and translation operators are those of
+// `fwd`.
 template <typename T>
 static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>& C, const std::vector<float>& rm2f,
                        double min_leaf_side, int leaf_src, bool direct, const Prec<T>* fwd = nullptr) {
@@ -219,25 +300,38 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   const bool adj = fwd != nullptr;
   P.p = p;
   P.L = (p + 1) * (p + 1);
-  // tree order of targets and sources: (X, nrm) are the nodes, (s, nu) the
-  // oversampled points
+  // (X, nrm) are the nodes, (s, nu) the oversampled points
   const std::vector<double>& TX = adj ? S.s : S.X;
   const std::vector<double>& TN = adj ? S.nu : S.nrm;
   const std::vector<double>& SX = adj ? S.X : S.s;
   const std::vector<double>& SN = adj ? S.nrm : S.nu;
-  const int64_t N = adj ? S.No : S.N, No = adj ? S.N : S.No;  // targets, sources of this tree
-  const int depth_req = adj ? fwd->tree.depth : (direct ? 0 : -1);
-  if (ctx->opts.flags & LB_HOST_OCTREE)
-    P.tree.build(TX.data(), N, SX.data(), No, leaf_src, adj ? 0.0 : min_leaf_side, depth_req);
-  else
-    P.tree.build_device(TX.data(), N, SX.data(), No, leaf_src, adj ? 0.0 : min_leaf_side, depth_req);
-  const Octree& t = P.tree;
+  const int64_t N = adj ? S.No : S.N, No = adj ? S.N : S.No;  // targets, sources of these trees
+  const int ns = ctx->n_surf;
+  std::vector<int64_t> toff(ns + 1), soff(ns + 1);
+  for (int q = 0; q <= ns; ++q) {
+    const int64_t pn = (int64_t)ctx->surf_patch[q] * ctx->n_p, po = (int64_t)ctx->surf_patch[q] * ctx->n_o;
+    toff[q] = adj ? po : pn;
+    soff[q] = adj ? pn : po;
+  }
+  P.trees.assign(ns, Octree());
+  for (int q = 0; q < ns; ++q) {
+    const int depth_req = adj ? fwd->trees[q].depth : (direct ? 0 : -1);
+    const double* tq = TX.data() + 3 * toff[q];
+    const double* sq = SX.data() + 3 * soff[q];
+    const int64_t nt = toff[q + 1] - toff[q], nsr = soff[q + 1] - soff[q];
+    if (ctx->opts.flags & LB_HOST_OCTREE)
+      P.trees[q].build(tq, nt, sq, nsr, leaf_src, adj ? 0.0 : min_leaf_side, depth_req);
+    else
+      P.trees[q].build_device(tq, nt, sq, nsr, leaf_src, adj ? 0.0 : min_leaf_side, depth_req);
+  }
+  Forest F;
+  merge_forest(P.trees, toff, soff, F);
   // without a mask (FP64) the smallest positive normal value still excludes
   // coincident points
   auto rmask = [&](int64_t m) { return rm2f.empty() ? std::numeric_limits<T>::min() : (T)rm2f[m]; };
   std::vector<T> a(N), b(N), c(N), d(N), e(N), f(N), tr(adj ? N : 0);
   for (int64_t j = 0; j < N; ++j) {
-    int64_t i = t.tgt_perm[j];
+    int64_t i = F.tgt_perm[j];
     a[j] = (T)TX[3 * i]; b[j] = (T)TX[3 * i + 1]; c[j] = (T)TX[3 * i + 2];
     d[j] = (T)TN[3 * i]; e[j] = (T)TN[3 * i + 1]; f[j] = (T)TN[3 * i + 2];
     if (adj) tr[j] = rmask(i);
@@ -246,61 +340,51 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   if (adj) upload(P.trm2, tr);
   std::vector<T> sa(No), sb(No), sc(No), sd(No), se(No), sf(No), sr(No);
   for (int64_t j = 0; j < No; ++j) {
-    int64_t i = t.src_perm[j];
+    int64_t i = F.src_perm[j];
     sa[j] = (T)SX[3 * i]; sb[j] = (T)SX[3 * i + 1]; sc[j] = (T)SX[3 * i + 2];
     sd[j] = (T)SN[3 * i]; se[j] = (T)SN[3 * i + 1]; sf[j] = (T)SN[3 * i + 2];
     sr[j] = adj ? std::numeric_limits<T>::min() : rmask(i);
   }
   upload(P.sx, sa); upload(P.sy, sb); upload(P.sz, sc); upload(P.snx, sd); upload(P.sny, se); upload(P.snz, sf);
   upload(P.rm2, sr);
-  const int nb = t.nbox();
-  std::vector<T> cx(nb), cy(nb), cz(nb);
-  for (int l = 0; l <= t.depth; ++l) {
-    double h = t.box_side(l);
-    for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
-      cx[g] = (T)(t.lo[0] + (t.bx[g] + 0.5) * h);
-      cy[g] = (T)(t.lo[1] + (t.by[g] + 0.5) * h);
-      cz[g] = (T)(t.lo[2] + (t.bz[g] + 0.5) * h);
-    }
-  }
-  upload(P.bcx, cx); upload(P.bcy, cy); upload(P.bcz, cz);
-  upload(P.tgt_beg, t.tgt_beg); upload(P.tgt_end, t.tgt_end);
-  upload(P.src_beg, t.src_beg); upload(P.src_end, t.src_end);
-  upload(P.ulist_ptr, t.ulist_ptr); upload(P.ulist, t.ulist);
-  upload(P.vlist_ptr, t.vlist_ptr); upload(P.vlist_src, t.vlist_src); upload(P.vlist_off, t.vlist_off);
-  upload(P.parent, t.parent); upload(P.child, t.child);
+  const int nb = F.nbox;
   {
-    std::vector<int> cs(t.child);
-    for (size_t i = 0; i < cs.size(); ++i)
-      if (cs[i] >= 0 && !t.has_src[cs[i]]) cs[i] = -1;
-    upload(P.child_src, cs);
+    std::vector<T> cx(nb), cy(nb), cz(nb);
+    for (int g = 0; g < nb; ++g) { cx[g] = (T)F.box_cen[3 * g]; cy[g] = (T)F.box_cen[3 * g + 1]; cz[g] = (T)F.box_cen[3 * g + 2]; }
+    upload(P.bcx, cx); upload(P.bcy, cy); upload(P.bcz, cz);
   }
+  upload(P.tgt_beg, F.tgt_beg); upload(P.tgt_end, F.tgt_end);
+  upload(P.src_beg, F.src_beg); upload(P.src_end, F.src_end);
+  upload(P.ulist_ptr, F.ulist_ptr); upload(P.ulist, F.ulist);
+  upload(P.vlist_ptr, F.vlist_ptr); upload(P.vlist_src, F.vlist_src); upload(P.vlist_off, F.vlist_off);
+  upload(P.parent, F.parent); upload(P.child, F.child); upload(P.child_src, F.child_src);
+  upload(P.leaf_box, F.leaf_box); upload(P.leaf_lvl, F.leaf_lvl); upload_as<T>(P.leaf_h, F.leaf_h);
   std::vector<int> lt, ls;
-  const int nleaf = t.lev_off[t.depth + 1] - t.lev_off[t.depth];
-  for (int l = 0; l < nleaf; ++l) {
-    if (t.has_tgt[t.lev_off[t.depth] + l]) lt.push_back(l);
-    if (t.has_src[t.lev_off[t.depth] + l]) ls.push_back(l);
+  for (int l = 0; l < F.nleaf; ++l) {
+    if (F.has_tgt[F.leaf_box[l]]) lt.push_back(l);
+    if (F.has_src[F.leaf_box[l]]) ls.push_back(l);
   }
   // heaviest leaves first, so that the block-per-leaf kernels (P2M, leaf
   // evaluation) do not end on a tail of large leaves
   {
-    auto nsrc = [&](int l) { return t.src_end[l] - t.src_beg[l]; };
-    std::stable_sort(ls.begin(), ls.end(), [&](int a, int b) { return nsrc(a) > nsrc(b); });
-    std::vector<double> cost(nleaf, 0.0);
+    auto nsrc = [&](int l) { return F.src_end[l] - F.src_beg[l]; };
+    std::stable_sort(ls.begin(), ls.end(), [&](int x, int y) { return nsrc(x) > nsrc(y); });
+    std::vector<double> cost(F.nleaf, 0.0);
     for (int l : lt) {
       int64_t us = 0;
-      for (int k = t.ulist_ptr[l]; k < t.ulist_ptr[l + 1]; ++k) us += nsrc(t.ulist[k]);
-      const int nt = t.tgt_end[l] - t.tgt_beg[l];
+      for (int k = F.ulist_ptr[l]; k < F.ulist_ptr[l + 1]; ++k) us += nsrc(F.ulist[k]);
+      const int nt = F.tgt_end[l] - F.tgt_beg[l];
       cost[l] = (double)us * nt / std::min(256, 8 * nt);
     }
-    std::stable_sort(lt.begin(), lt.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::stable_sort(lt.begin(), lt.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   }
   upload(P.leaf_tgt, lt); upload(P.leaf_src, ls);
   std::vector<int> lsv, lsp(1, 0), ltv, ltp(1, 0);
-  for (int l = 0; l <= t.depth; ++l) {
-    for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
-      if (t.has_src[g]) lsv.push_back(g);
-      if (t.has_tgt[g]) ltv.push_back(g);
+  for (int l = 0; l <= F.depth; ++l) {
+    for (int g = 0; g < nb; ++g) {
+      if (F.box_level[g] != l) continue;
+      if (F.has_src[g]) lsv.push_back(g);
+      if (F.has_tgt[g]) ltv.push_back(g);
     }
     lsp.push_back((int)lsv.size());
     ltp.push_back((int)ltv.size());
@@ -308,8 +392,8 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   upload(P.lev_src, lsv); upload(P.lev_src_ptr, lsp); upload(P.lev_tgt, ltv); upload(P.lev_tgt_ptr, ltp);
   // user-order maps
   std::vector<int> tp(N), sp(No);
-  for (int64_t i = 0; i < N; ++i) tp[i] = (int)t.tgt_pos[i];
-  for (int64_t i = 0; i < No; ++i) sp[i] = (int)t.src_pos[i];
+  for (int64_t i = 0; i < N; ++i) tp[i] = (int)F.tgt_pos[i];
+  for (int64_t i = 0; i < No; ++i) sp[i] = (int)F.src_pos[i];
   upload(P.tgt_pos, tp); upload(P.src_pos, sp);
   if (!adj) {
     upload_as<T>(P.P, ctx->re->P);
@@ -322,70 +406,69 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     upload(P.vals3, v3);
   }
   // translations
-  if (t.depth >= 2 && !adj) {
-    Translations tr;
-    tr.build(p);
+  if (F.depth >= 2 && !adj) {
+    Translations trn;
+    trn.build(p);
     std::vector<T> m;
-    transpose_blocks(tr.m2m, 8, P.L, P.L, m); upload(P.m2m, m);
-    transpose_blocks(tr.l2l, 8, P.L, P.L, m); upload(P.l2l, m);
-    transpose_blocks(tr.m2l, 343, P.L, P.L, m); upload(P.m2l, m);
-    transpose_blocks(tr.dgrad, 3, p * p, P.L, m); upload(P.dgrad, m);
-    transpose_blocks(tr.dhess, 6, (p - 1) * (p - 1), P.L, m); upload(P.dhess, m);
+    transpose_blocks(trn.m2m, 8, P.L, P.L, m); upload(P.m2m, m);
+    transpose_blocks(trn.l2l, 8, P.L, P.L, m); upload(P.l2l, m);
+    transpose_blocks(trn.m2l, 343, P.L, P.L, m); upload(P.m2l, m);
+    transpose_blocks(trn.dgrad, 3, p * p, P.L, m); upload(P.dgrad, m);
+    transpose_blocks(trn.dhess, 6, (p - 1) * (p - 1), P.L, m); upload(P.dhess, m);
   }
-  // batched translation plans
-  if (t.depth >= 2) {
+  // batched translation plans over all trees
+  if (F.depth >= 2) {
     size_t maxcols = 1;
     {
-      std::vector<Triple> tr;
-      std::vector<int> boxes, blev;
-      for (int l = 2; l <= t.depth; ++l)
-        for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
-          if (!t.has_tgt[g]) continue;
-          boxes.push_back(g);
-          blev.push_back(l);
-          for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) tr.push_back({t.vlist_off[v], g, t.vlist_src[v]});
-        }
+      std::vector<Triple> trp;
+      std::vector<int> boxes;
+      std::vector<double> scale;
+      for (int g = 0; g < nb; ++g) {
+        if (F.box_level[g] < 2 || !F.has_tgt[g]) continue;
+        boxes.push_back(g);
+        scale.push_back(F.box_scale[g]);
+        for (int v = F.vlist_ptr[g]; v < F.vlist_ptr[g + 1]; ++v) trp.push_back({F.vlist_off[v], g, F.vlist_src[v]});
+      }
       P.m2l_pb.reset(new PlanBuf());
-      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, tr, boxes, blev, true, false, t.nbox()));
+      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb));
     }
     P.m2m_pb.clear();
     P.l2l_pb.clear();
-    P.m2m_pl.assign(t.depth + 1, GemmPlan());
-    P.l2l_pl.assign(t.depth + 1, GemmPlan());
-    for (int l = 0; l <= t.depth; ++l) {
+    P.m2m_pl.assign(F.depth + 1, GemmPlan());
+    P.l2l_pl.assign(F.depth + 1, GemmPlan());
+    for (int l = 0; l <= F.depth; ++l) {
       P.m2m_pb.emplace_back(new PlanBuf());
       P.l2l_pb.emplace_back(new PlanBuf());
     }
-    for (int l = 2; l < t.depth; ++l) {  // M2M into level l from level l+1
-      std::vector<Triple> tr;
-      std::vector<int> boxes, blev;
-      for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
-        if (!t.has_src[g]) continue;
+    for (int l = 2; l < F.depth; ++l) {  // M2M into level l from level l+1
+      std::vector<Triple> trp;
+      std::vector<int> boxes;
+      for (int g = 0; g < nb; ++g) {
+        // the leaves of shallower trees on this level keep their P2M multipoles
+        if (F.box_level[g] != l || !F.has_src[g] || F.box_level[g] == F.tree_depth[g]) continue;
         boxes.push_back(g);
-        blev.push_back(l);
         for (int c = 0; c < 8; ++c) {
-          int ch = t.child[(size_t)g * 8 + c];
-          if (ch >= 0 && t.has_src[ch]) tr.push_back({c, g, ch});
+          const int ch = F.child[(size_t)g * 8 + c];
+          if (ch >= 0 && F.has_src[ch]) trp.push_back({c, g, ch});
         }
       }
-      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], tr, boxes, blev, false, false, t.nbox()));
+      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb));
       P.m2m_pl[l] = P.m2m_pb[l]->pl;
     }
-    for (int l = 3; l <= t.depth; ++l) {  // L2L into level l from level l-1
-      std::vector<Triple> tr;
-      std::vector<int> boxes, blev;
-      for (int g = t.lev_off[l]; g < t.lev_off[l + 1]; ++g) {
-        if (!t.has_tgt[g]) continue;
-        const int pg = t.parent[g];
+    for (int l = 3; l <= F.depth; ++l) {  // L2L into level l from level l-1
+      std::vector<Triple> trp;
+      std::vector<int> boxes;
+      for (int g = 0; g < nb; ++g) {
+        if (F.box_level[g] != l || !F.has_tgt[g]) continue;
+        const int pg = F.parent[g];
         int oct = -1;
         for (int c = 0; c < 8; ++c)
-          if (t.child[(size_t)pg * 8 + c] == g) oct = c;
+          if (F.child[(size_t)pg * 8 + c] == g) oct = c;
         if (oct < 0) fail(LB_EINVAL, "octree: box %d missing from its parent", g);
         boxes.push_back(g);
-        blev.push_back(l);
-        tr.push_back({oct, g, pg});
+        trp.push_back({oct, g, pg});
       }
-      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], tr, boxes, blev, false, true, t.nbox()));
+      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb));
       P.l2l_pl[l] = P.l2l_pb[l]->pl;
     }
     P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);
@@ -408,27 +491,24 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.leaf_src_list = dptr<int>(P.leaf_src); D.n_leaf_src = (int)ls.size();
   D.lev_box_src = dptr<int>(P.lev_src); D.lev_box_src_ptr = dptr<int>(P.lev_src_ptr);
   D.lev_box_tgt = dptr<int>(P.lev_tgt); D.lev_box_tgt_ptr = dptr<int>(P.lev_tgt_ptr);
-  D.depth = t.depth;
-  D.leaf_off = t.lev_off[t.depth];
+  D.leaf_box = dptr<int>(P.leaf_box); D.leaf_lvl = dptr<int>(P.leaf_lvl); D.leaf_h = dptr<T>(P.leaf_h);
+  D.depth = F.depth;
   D.nbox = nb;
-  if (t.depth + 2 > 24) fail(LB_EINVAL, "octree too deep");
-  for (int l = 0; l <= t.depth + 1; ++l) { D.h_lev_src_ptr[l] = lsp[l]; D.h_lev_tgt_ptr[l] = ltp[l]; }
-  D.side = t.side;
   D.p = p;
   D.L = P.L;
   const Prec<T>& TRs = adj ? *fwd : P;  // owner of the translation operators
   D.m2m = dptr<T>(TRs.m2m); D.l2l = dptr<T>(TRs.l2l); D.m2l = dptr<T>(TRs.m2l);
   D.dgradT = dptr<T>(TRs.dgrad); D.dhessT = dptr<T>(TRs.dhess);
-  D.m2l_plan = t.depth >= 2 ? &P.m2l_pb->pl : nullptr;
-  D.m2m_plan = t.depth >= 2 ? P.m2m_pl.data() : nullptr;
-  D.l2l_plan = t.depth >= 2 ? P.l2l_pl.data() : nullptr;
+  D.m2l_plan = F.depth >= 2 ? &P.m2l_pb->pl : nullptr;
+  D.m2m_plan = F.depth >= 2 ? P.m2m_pl.data() : nullptr;
+  D.l2l_plan = F.depth >= 2 ? P.l2l_pl.data() : nullptr;
   D.Y = P.Y.p;
   D.p2m_H = nullptr;
   D.p2m_D = nullptr;
   // P2M tables (the geometry is fixed, so the leaf harmonics of every
   // source can be kept): built on the device when both fit in a quarter of
   // the free memory and under P2M_TABLE_MAX bytes
-  if (t.depth >= 2 && !adj && !(ctx->opts.flags & LB_NO_P2M_TABLES)) {
+  if (F.depth >= 2 && !adj && !(ctx->opts.flags & LB_NO_P2M_TABLES)) {
     const size_t bytes = 2 * sizeof(T) * (size_t)No * P.L;
     size_t fr = 0, tot = 0;
     HIPTRY(hipMemGetInfo(&fr, &tot));
@@ -455,6 +535,8 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_tgt, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1)));
   P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
   P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
+  P.y2.alloc(sizeof(T) * (size_t)N * chunk);
+  ctx->seg_scal.alloc(sizeof(double) * (size_t)chunk * ctx->n_surf + 8);
   P.ws_rhs = chunk;
   // per-block partial sums: the A3 combine (4 per row block) and the GMRES
   // dot products (256 blocks per basis vector)
@@ -485,6 +567,22 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
   }
 }
 
+// S alone (potential-only FMM), eight densities per traversal
+template <typename T>
+static void apply_S_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, hipStream_t st) {
+  ensure_ws(ctx, P, CHUNK_GRAD);
+  const int64_t N = ctx->N, No = ctx->No;
+  for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
+    const int c = std::min(CHUNK_GRAD, nd - d0);
+    launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
+                        dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
+    launch_fmm<T>(P.dt, FMM_POT, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No,
+                  st);
+    launch_combine_pot<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3),
+                          sigma + (int64_t)d0 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), pot + (int64_t)d0 * N, st);
+  }
+}
+
 // A3 (Section 4.3) for nd densities, two per traversal: the second FMM
 // carries three expansions per density (charges mu1, mu2 and dipole mu2 nu).
 constexpr int CHUNK_A3 = 2;
@@ -507,7 +605,9 @@ static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hi
     launch_fmm<T>(P.dt, FMM_A3B, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
     launch_combine_a3b<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td, mu,
                           mu + N, 2 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.H), dptr<double>(ctx->w),
-                          1.0 / ctx->area, out + (int64_t)d0 * N, dptr<double>(ctx->partial), st);
+                          ctx->n_surf, dptr<int64_t>(ctx->node_off), dptr<int>(ctx->node_surf),
+                          dptr<double>(ctx->inv_area), out + (int64_t)d0 * N, dptr<T>(P.y2),
+                          dptr<double>(ctx->seg_scal), st);
   }
 }
 
@@ -603,7 +703,7 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
   }
   ctx->a3t_a.alloc(sizeof(double) * (size_t)N * CHUNK_A3T);
   ctx->a3t_b.alloc(sizeof(double) * (size_t)N * CHUNK_A3T);
-  ctx->a3t_scal.alloc(sizeof(double) * CHUNK_A3T);
+  ctx->a3t_scal.alloc(sizeof(double) * CHUNK_A3T * ctx->n_surf);
   ctx->g4.alloc(sizeof(T) * (size_t)N * 4 * CHUNK_GRAD);
   T* a = dptr<T>(ctx->a3t_a);
   T* b = dptr<T>(ctx->a3t_b);
@@ -617,102 +717,161 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
     launch_adj3_comb1<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
                          dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
                          dptr<int64_t>(ctx->cblk), dptr<T>(F.vals3), g2, a, b, st);
-    launch_colsum<T>(c, N, vd, 1.0 / ctx->area, dptr<double>(ctx->partial), dptr<double>(ctx->a3t_scal), st);
+    launch_seg_dot<T>(c, ctx->n_surf, N, dptr<int64_t>(ctx->node_off), vd, nullptr, dptr<double>(ctx->inv_area),
+                      dptr<double>(ctx->a3t_scal), st);
     launch_adj3_str2<T>(c, N, a, b, dptr<T>(F.nrm), dptr<int>(A.src_pos), dptr<T>(A.str), g2, st);
     launch_fmm<T>(A.dt, FMM_ADJ, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
                   N, st);
     launch_adj3_comb2<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
                          dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
                          dptr<int64_t>(ctx->cblk), dptr<T>(F.vals3), g2, vd, dptr<T>(zb),
-                         dptr<double>(ctx->a3t_scal), out + (int64_t)d0 * N, st);
+                         dptr<double>(ctx->a3t_scal), ctx->n_surf, dptr<int>(ctx->node_surf), out + (int64_t)d0 * N,
+                         st);
   }
 }
 
 // ---------------------------------------------------------------------------
-// GMRES (Section 6) for nb right-hand sides at once: x0 = 0, no restart,
-// each right-hand side has its own Arnoldi basis (CGS2, FP64 on the device)
-// and Givens rotations (host); the operator is applied to all active
-// right-hand sides in one batched call.  A(in [na][N], out [na][N], na).
+// GMRES (Section 6) for several independent systems at once: x0 = 0, no
+// restart; system a is the segment [xoff[a], xoff[a] + len[a]) of the
+// operator's vectors [nrhs][N] (one (right-hand side, surface) pair), with
+// its own Arnoldi basis (CGS2, FP64 on the device) and Givens rotations
+// (host).  Each iteration applies the operator once to all systems (zero
+// segments for the finished ones) and needs one device-host round trip.
+// A(in [nrhs][N], out [nrhs][N], nrhs).
 // ---------------------------------------------------------------------------
+struct Systems {
+  std::vector<int64_t> xoff, len;
+};
+
+// Euclidean norms of every system's segment of v [nrhs][N]
+static std::vector<double> system_norms(lb_ctx* ctx, const Systems& sy, const double* v, hipStream_t st) {
+  const int ns = (int)sy.xoff.size();
+  ctx->msys2.alloc(sizeof(int64_t) * 2 * ns + sizeof(double) * (ns * 33 + 8));
+  int64_t* d = dptr<int64_t>(ctx->msys2);
+  double* part = reinterpret_cast<double*>(d + 2 * ns);
+  double* out = part + (size_t)ns * 32;
+  std::vector<int64_t> t(2 * ns);
+  for (int a = 0; a < ns; ++a) { t[a] = sy.xoff[a]; t[ns + a] = sy.len[a]; }
+  HIPTRY(hipMemcpyAsync(d, t.data(), sizeof(int64_t) * 2 * ns, hipMemcpyHostToDevice, st));
+  launch_msys_dots(ns, 1, d, d + ns, nullptr, nullptr, v, part, out, st);
+  std::vector<double> h(ns);
+  HIPTRY(hipMemcpyAsync(h.data(), out, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  for (double& x : h) x = std::sqrt(x);
+  return h;
+}
+
+// the (right-hand side, surface) systems of nrhs densities
+static Systems make_systems(const lb_ctx* ctx, int nrhs) {
+  Systems sy;
+  for (int q = 0; q < nrhs; ++q)
+    for (int s = 0; s < ctx->n_surf; ++s) {
+      sy.xoff.push_back((int64_t)q * ctx->N + ctx->node_off_h[s]);
+      sy.len.push_back(ctx->node_off_h[s + 1] - ctx->node_off_h[s]);
+    }
+  return sy;
+}
+
 template <typename ApplyFn>
-static void gmres_multi(lb_ctx* ctx, ApplyFn A, int nb, const double* B, double* X, double tol, int maxit,
-                        const std::vector<char>& skip, std::vector<double>& relres, std::vector<int>& iters,
-                        hipStream_t st) {
+static void gmres_sys(lb_ctx* ctx, ApplyFn A, int nrhs, const Systems& sy, const double* B, double* X, double tol,
+                      int maxit, const std::vector<char>& skip, std::vector<double>& relres, std::vector<int>& iters,
+                      hipStream_t st) {
   const int64_t N = ctx->N;
-  const size_t need = (size_t)nb * (maxit + 1);
-  if ((size_t)ctx->v_cols < need) {
-    ctx->V.alloc(sizeof(double) * (size_t)N * need);
-    ctx->v_cols = (int)need;
+  const int ns = (int)sy.xoff.size();
+  std::vector<int64_t> vbase(ns);
+  int64_t tot = 0, maxlen = 1;
+  for (int a = 0; a < ns; ++a) {
+    vbase[a] = tot;
+    tot += (int64_t)(maxit + 1) * sy.len[a];
+    maxlen = std::max(maxlen, sy.len[a]);
   }
-  ctx->wv.alloc(sizeof(double) * (size_t)N * nb * 2);
-  ctx->hbuf.alloc(sizeof(double) * (maxit + 2) * 2);
+  ctx->V.alloc(sizeof(double) * (size_t)std::max<int64_t>(tot, 1));
+  ctx->wv.alloc(sizeof(double) * (size_t)N * nrhs * 2);
+  ctx->msys.alloc(sizeof(int64_t) * 6 * ns + sizeof(int) * ns + 64);
+  ctx->msys_part.alloc(sizeof(double) * (size_t)ns * (maxit + 1) * 32 + 64);
+  ctx->hbuf.alloc(sizeof(double) * ((size_t)ns * (2 * (maxit + 1) + 2) + 8));
   double* Vall = dptr<double>(ctx->V);
   double* win = dptr<double>(ctx->wv);
-  double* wout = win + (size_t)N * nb;
-  double* hd = dptr<double>(ctx->hbuf);
-  double* part = dptr<double>(ctx->partial);
-  auto V = [&](int r, int j) { return Vall + ((size_t)r * (maxit + 1) + j) * N; };
-  auto dots = [&](const double* Vb, int k, const double* vec, std::vector<double>& out) {
-    launch_dots(Vb, N, k, vec, N, hd, part, st);
-    out.resize(k);
-    HIPTRY(hipMemcpyAsync(out.data(), hd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-  };
-  auto norm = [&](const double* vec) {
-    std::vector<double> v;
-    dots(vec, 1, vec, v);
-    return std::sqrt(v[0]);
-  };
+  double* wout = win + (size_t)N * nrhs;
+  int64_t* d_all = dptr<int64_t>(ctx->msys);       // all systems: xoff, len, vbase
+  int64_t* d_act = d_all + 3 * ns;                   // active systems: xoff, len, vbase
+  int* d_flag = reinterpret_cast<int*>(d_all + 6 * ns);
+  double* part = dptr<double>(ctx->msys_part);
+  double* h1 = dptr<double>(ctx->hbuf);
+  double* h2 = h1 + (size_t)ns * (maxit + 1);
+  double* nr = h2 + (size_t)ns * (maxit + 1);
+  double* sc = nr + ns;
+  {
+    std::vector<int64_t> t(3 * ns);
+    for (int a = 0; a < ns; ++a) { t[a] = sy.xoff[a]; t[ns + a] = sy.len[a]; t[2 * ns + a] = vbase[a]; }
+    HIPTRY(hipMemcpyAsync(d_all, t.data(), sizeof(int64_t) * 3 * ns, hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));  // t is a local host buffer
+  }
   struct St {
     std::vector<double> H, cs, sn, g;
     double beta = 0;
     int k = 0;
     bool done = false;
   };
-  std::vector<St> S(nb);
-  relres.assign(nb, 0.0);
-  iters.assign(nb, 0);
-  for (int r = 0; r < nb; ++r) {
-    double* x = X + (size_t)r * N;
-    HIPTRY(hipMemsetAsync(x, 0, sizeof(double) * N, st));
-    St& q = S[r];
+  std::vector<St> S(ns);
+  relres.assign(ns, 0.0);
+  iters.assign(ns, 0);
+  HIPTRY(hipMemsetAsync(X, 0, sizeof(double) * (size_t)N * nrhs, st));
+  // initial residuals b: norms and the first basis vectors
+  std::vector<double> hv((size_t)ns * (maxit + 1)), hw((size_t)ns * (maxit + 1)), hn(ns), scale(ns);
+  launch_msys_dots(ns, 1, d_all, d_all + ns, nullptr, nullptr, B, part, nr, st);
+  HIPTRY(hipMemcpyAsync(hn.data(), nr, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  for (int a = 0; a < ns; ++a) {
+    St& q = S[a];
     q.H.assign((size_t)(maxit + 1) * maxit, 0.0);
     q.cs.assign(maxit, 0.0);
     q.sn.assign(maxit, 0.0);
     q.g.assign(maxit + 1, 0.0);
-    if (skip[r]) { q.done = true; continue; }
-    q.beta = norm(B + (size_t)r * N);
-    if (q.beta == 0.0) { q.done = true; continue; }
+    q.beta = std::sqrt(hn[a]);
+    q.done = skip[a] || q.beta == 0.0;
     q.g[0] = q.beta;
-    launch_scale_copy(B + (size_t)r * N, 1.0 / q.beta, V(r, 0), N, st);
+    scale[a] = q.done ? 0.0 : 1.0 / q.beta;
   }
-  std::vector<double> h1, h2;
+  HIPTRY(hipMemcpyAsync(sc, scale.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
+  launch_msys_scale_copy(ns, maxlen, 0, d_all, d_all + ns, d_all + 2 * ns, sc, B, Vall, st);
+  std::vector<int> act, flag(ns);
+  std::vector<int64_t> at;
   for (int j = 0; j < maxit; ++j) {
-    std::vector<int> act;
-    for (int r = 0; r < nb; ++r)
-      if (!S[r].done) act.push_back(r);
+    act.clear();
+    for (int a = 0; a < ns; ++a) {
+      flag[a] = !S[a].done;
+      if (!S[a].done) act.push_back(a);
+    }
     if (act.empty()) break;
-    for (size_t a = 0; a < act.size(); ++a)
-      HIPTRY(hipMemcpyAsync(win + a * N, V(act[a], j), sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    A(win, wout, (int)act.size());
-    for (size_t a = 0; a < act.size(); ++a) {
-      const int r = act[a];
-      St& q = S[r];
-      double* w = wout + a * N;
-      dots(V(r, 0), j + 1, w, h1);
-      HIPTRY(hipMemcpyAsync(hd, h1.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-      launch_gemv_sub(V(r, 0), N, j + 1, hd, w, N, st);
-      dots(V(r, 0), j + 1, w, h2);
-      HIPTRY(hipMemcpyAsync(hd, h2.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-      launch_gemv_sub(V(r, 0), N, j + 1, hd, w, N, st);
-      const double hn = norm(w);
+    const int na = (int)act.size(), k = j + 1;
+    at.assign(3 * na, 0);
+    for (int i = 0; i < na; ++i) { at[i] = sy.xoff[act[i]]; at[na + i] = sy.len[act[i]]; at[2 * na + i] = vbase[act[i]]; }
+    HIPTRY(hipMemcpyAsync(d_act, at.data(), sizeof(int64_t) * 3 * na, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(d_flag, flag.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    launch_msys_gather(ns, maxlen, d_all, d_all + ns, d_all + 2 * ns, d_flag, j, Vall, win, st);
+    A(win, wout, nrhs);
+    // CGS2 on every active system, one round trip for h1, h2 and the norms
+    launch_msys_dots(na, k, d_act, d_act + na, d_act + 2 * na, Vall, wout, part, h1, st);
+    launch_msys_gemv(na, maxlen, k, d_act, d_act + na, d_act + 2 * na, Vall, h1, -1.0, wout, st);
+    launch_msys_dots(na, k, d_act, d_act + na, d_act + 2 * na, Vall, wout, part, h2, st);
+    launch_msys_gemv(na, maxlen, k, d_act, d_act + na, d_act + 2 * na, Vall, h2, -1.0, wout, st);
+    launch_msys_dots(na, 1, d_act, d_act + na, nullptr, nullptr, wout, part, nr, st);
+    HIPTRY(hipMemcpyAsync(hv.data(), h1, sizeof(double) * na * k, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(hw.data(), h2, sizeof(double) * na * k, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(hn.data(), nr, sizeof(double) * na, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    for (int i = 0; i < na; ++i) {
+      const int a = act[i];
+      St& q = S[a];
       std::vector<double>& H = q.H;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * maxit + j] = h1[i] + h2[i];
-      H[(size_t)(j + 1) * maxit + j] = hn;
-      for (int i = 0; i < j; ++i) {
-        const double a1 = H[(size_t)i * maxit + j], b1 = H[(size_t)(i + 1) * maxit + j];
-        H[(size_t)i * maxit + j] = q.cs[i] * a1 + q.sn[i] * b1;
-        H[(size_t)(i + 1) * maxit + j] = -q.sn[i] * a1 + q.cs[i] * b1;
+      const double hnrm = std::sqrt(hn[i]);
+      for (int r = 0; r <= j; ++r) H[(size_t)r * maxit + j] = hv[(size_t)i * k + r] + hw[(size_t)i * k + r];
+      H[(size_t)(j + 1) * maxit + j] = hnrm;
+      for (int r = 0; r < j; ++r) {
+        const double a1 = H[(size_t)r * maxit + j], b1 = H[(size_t)(r + 1) * maxit + j];
+        H[(size_t)r * maxit + j] = q.cs[r] * a1 + q.sn[r] * b1;
+        H[(size_t)(r + 1) * maxit + j] = -q.sn[r] * a1 + q.cs[r] * b1;
       }
       const double a1 = H[(size_t)j * maxit + j], b1 = H[(size_t)(j + 1) * maxit + j];
       const double den = std::hypot(a1, b1);
@@ -723,16 +882,18 @@ static void gmres_multi(lb_ctx* ctx, ApplyFn A, int nb, const double* B, double*
       q.g[j + 1] = -q.sn[j] * q.g[j];
       q.g[j] = q.cs[j] * q.g[j];
       q.k = j + 1;
-      relres[r] = std::fabs(q.g[j + 1]) / q.beta;
-      if (relres[r] < tol || hn == 0.0 || j + 1 == maxit)
-        q.done = true;
-      else
-        launch_scale_copy(w, 1.0 / hn, V(r, j + 1), N, st);
+      relres[a] = std::fabs(q.g[j + 1]) / q.beta;
+      if (relres[a] < tol || hnrm == 0.0 || j + 1 == maxit) q.done = true;
+      scale[i] = q.done ? 0.0 : 1.0 / hnrm;
     }
+    HIPTRY(hipMemcpyAsync(sc, scale.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
+    launch_msys_scale_copy(na, maxlen, j + 1, d_act, d_act + na, d_act + 2 * na, sc, wout, Vall, st);
   }
-  for (int r = 0; r < nb; ++r) {
-    St& q = S[r];
-    iters[r] = q.k;
+  // x = V y per system
+  std::vector<double> ys;
+  for (int a = 0; a < ns; ++a) {
+    St& q = S[a];
+    iters[a] = q.k;
     if (q.k == 0) continue;
     std::vector<double> y(q.k);
     for (int i = q.k - 1; i >= 0; --i) {
@@ -740,78 +901,72 @@ static void gmres_multi(lb_ctx* ctx, ApplyFn A, int nb, const double* B, double*
       for (int c = i + 1; c < q.k; ++c) sacc -= q.H[(size_t)i * maxit + c] * y[c];
       y[i] = sacc / q.H[(size_t)i * maxit + i];
     }
-    HIPTRY(hipMemcpyAsync(hd, y.data(), sizeof(double) * q.k, hipMemcpyHostToDevice, st));
-    launch_gemv_add(V(r, 0), N, q.k, hd, X + (size_t)r * N, N, st);
+    HIPTRY(hipMemcpyAsync(h1, y.data(), sizeof(double) * q.k, hipMemcpyHostToDevice, st));
+    launch_gemv_add(Vall + vbase[a], sy.len[a], q.k, h1, X + sy.xoff[a], sy.len[a], st);
     HIPTRY(hipStreamSynchronize(st));
   }
 }
 
 // ---------------------------------------------------------------------------
-// Solve A sig = b for nrhs right-hand sides (b [nrhs][N], norms bnorm):
+// Solve A sig = b for every system (b, sig [nrhs][N]; bnorm per system):
 // LB_SOLVE_FP64: GMRES with the FP64 operator A64; LB_SOLVE_FP32_REFINE:
 // iterative refinement, each correction from GMRES with the FP32 operator
-// A32 on the FP64 residual.  rel = final FP64 relative residuals.
+// A32 on the FP64 residual.  rel = final FP64 relative residuals per system.
 // r, ut, dcorr: [nrhs][N] workspace.
 // ---------------------------------------------------------------------------
 template <typename Op64, typename Op32>
-static void solve_system(lb_ctx* ctx, int nrhs, Op64& A64, Op32& A32, const double* b,
+static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op32& A32, const double* b,
                          const std::vector<double>& bnorm, double* sig, double* r, double* ut, double* dcorr,
                          double tol, int mode, std::vector<double>& rel, std::vector<int>& iters,
                          std::vector<int>& outer, hipStream_t st) {
   const int64_t N = ctx->N;
   const size_t nN = (size_t)nrhs * N;
   const int maxit = ctx->opts.max_iter;
-  DBuf scal;
-  scal.alloc(sizeof(double) * 4);
-  auto nrm2 = [&](const double* v) {
-    launch_dots(v, N, 1, v, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
-    double sv;
-    HIPTRY(hipMemcpyAsync(&sv, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    return std::sqrt(sv);
-  };
-  rel.assign(nrhs, 0.0);
-  iters.assign(nrhs, 0);
-  outer.assign(nrhs, 0);
+  const int ns = (int)sy.xoff.size();
+  rel.assign(ns, 0.0);
+  iters.assign(ns, 0);
+  outer.assign(ns, 0);
   std::vector<double> inner;
   std::vector<int> it;
-  std::vector<char> skip(nrhs, 0);
-  auto residual = [&]() {  // r = b - A sig (FP64), rel = |r| / |b|
+  std::vector<char> skip(ns, 0);
+  auto residual = [&]() {  // r = b - A sig (FP64), rel = |r| / |b| per system
     A64(sig, ut, nrhs);
     launch_axpby(1.0, b, -1.0, ut, r, (int64_t)nN, st);
-    for (int q = 0; q < nrhs; ++q) rel[q] = bnorm[q] > 0 ? nrm2(r + (size_t)q * N) / bnorm[q] : 0.0;
+    std::vector<double> rn = system_norms(ctx, sy, r, st);
+    for (int a = 0; a < ns; ++a) rel[a] = bnorm[a] > 0 ? rn[a] / bnorm[a] : 0.0;
   };
   if (mode == LB_SOLVE_FP64) {
-    gmres_multi(ctx, A64, nrhs, b, sig, tol, maxit, skip, inner, it, st);
-    for (int q = 0; q < nrhs; ++q) iters[q] = it[q];
+    gmres_sys(ctx, A64, nrhs, sy, b, sig, tol, maxit, skip, inner, it, st);
+    for (int a = 0; a < ns; ++a) iters[a] = it[a];
     residual();
     return;
   }
   HIPTRY(hipMemsetAsync(sig, 0, sizeof(double) * nN, st));
   HIPTRY(hipMemcpyAsync(r, b, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
-  for (int q = 0; q < nrhs; ++q) rel[q] = bnorm[q] > 0 ? 1.0 : 0.0;
-  std::vector<double> prev(nrhs, 1e300);
+  for (int a = 0; a < ns; ++a) rel[a] = bnorm[a] > 0 ? 1.0 : 0.0;
+  std::vector<double> prev(ns, 1e300);
   const int max_outer = 12;
   for (int step = 0; step < max_outer; ++step) {
     bool any = false;
-    for (int q = 0; q < nrhs; ++q) {
-      skip[q] = !(rel[q] >= tol) || rel[q] > 0.5 * prev[q];  // converged, or refinement stalled
-      any |= !skip[q];
+    for (int a = 0; a < ns; ++a) {
+      skip[a] = !(rel[a] >= tol) || rel[a] > 0.5 * prev[a];  // converged, or refinement stalled
+      any |= !skip[a];
     }
     if (!any) break;
     // inner FP32 solves: the FP32 operator is accurate to ~1e-6, so each
     // refinement step asks for no more than that
     double worst = 0;
-    for (int q = 0; q < nrhs; ++q)
-      if (!skip[q]) worst = std::max(worst, rel[q]);
+    for (int a = 0; a < ns; ++a)
+      if (!skip[a]) worst = std::max(worst, rel[a]);
     const double inner_tol = std::max(1e-6, 0.5 * tol / std::max(worst, 1e-300));
-    gmres_multi(ctx, A32, nrhs, r, dcorr, inner_tol, maxit, skip, inner, it, st);
-    for (int q = 0; q < nrhs; ++q) {
-      if (skip[q]) continue;
-      iters[q] += it[q];
-      outer[q] += 1;
-      launch_axpby(1.0, sig + (size_t)q * N, 1.0, dcorr + (size_t)q * N, sig + (size_t)q * N, N, st);
+    gmres_sys(ctx, A32, nrhs, sy, r, dcorr, inner_tol, maxit, skip, inner, it, st);
+    for (int a = 0; a < ns; ++a) {
+      if (skip[a]) continue;
+      iters[a] += it[a];
+      outer[a] += 1;
     }
+    // skipped systems have a zero correction (gmres_sys zeroes the output)
+    launch_axpby(1.0, sig, 1.0, dcorr, sig, (int64_t)nN, st);
     prev = rel;
     residual();
   }
@@ -862,15 +1017,19 @@ lb_status lb_ref_nodes(int order, double* uv, double* w_ref) {
   API_END
 }
 
-lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, const double* Xu, const double* Xv,
-                   const lb_opts* opts, void* stream) {
-  API_BEGIN
-  (void)stream;
-  if (!out || !X || !Xu || !Xv) fail(LB_EINVAL, "null argument");
-  *out = nullptr;
-  if (n_patches < 1) fail(LB_EINVAL, "n_patches must be >= 1");
+namespace lb {
+// Setup of n_surf surfaces (surface q: pps[q] patches, in order).
+static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, const double* X, const double* Xu,
+                       const double* Xv, const lb_opts* opts) {
+  if (!X || !Xu || !Xv || !pps) fail(LB_EINVAL, "null argument");
+  if (n_surf < 1) fail(LB_EINVAL, "n_surf must be >= 1");
+  ctx->surf_patch.assign(n_surf + 1, 0);
+  for (int q = 0; q < n_surf; ++q) {
+    if (pps[q] < 1) fail(LB_EINVAL, "surface %d has %d patches", q, pps[q]);
+    ctx->surf_patch[q + 1] = ctx->surf_patch[q] + pps[q];
+  }
+  const int n_patches = ctx->surf_patch[n_surf];
   if (order < 1 || order > 7) fail(LB_EINVAL, "order %d out of range 1..7", order);
-  auto ctx = std::make_unique<lb_ctx>();
   if (opts) ctx->opts = *opts; else default_opts(&ctx->opts);
   lb_opts& o = ctx->opts;
   if (o.over_q <= 0) o.over_q = order + 6;
@@ -880,17 +1039,31 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
   if (o.self_n < 4 || o.near_q < 2 || o.near_adm <= 0) fail(LB_EINVAL, "bad quadrature options");
   ctx->host_only = (o.flags & LB_HOST_ONLY) != 0;
   ctx->k = order;
+  ctx->n_surf = n_surf;
   ctx->re.reset(new RefElem(order, o.over_q));
   Surface& S = ctx->S;
   S.build(*ctx->re, n_patches, X, Xu, Xv, o.eta_near);
+  S.surf_of_patch.resize(n_patches);
+  for (int q = 0; q < n_surf; ++q)
+    for (int pt = ctx->surf_patch[q]; pt < ctx->surf_patch[q + 1]; ++pt) S.surf_of_patch[pt] = q;
   S.build_near_lists();
   ctx->NP = n_patches;
   ctx->n_p = S.n_p;
   ctx->n_o = S.n_o;
   ctx->N = S.N;
   ctx->No = S.No;
-  ctx->area = 0;
-  for (double wi : S.w) ctx->area += wi;
+  ctx->node_off_h.assign(n_surf + 1, 0);
+  ctx->surf_area.assign(n_surf, 0.0);
+  std::vector<int> nsurf_of(S.N);
+  std::vector<double> inv(n_surf);
+  for (int q = 0; q < n_surf; ++q) {
+    ctx->node_off_h[q + 1] = (int64_t)ctx->surf_patch[q + 1] * S.n_p;
+    for (int64_t i = ctx->node_off_h[q]; i < ctx->node_off_h[q + 1]; ++i) {
+      ctx->surf_area[q] += S.w[i];
+      nsurf_of[i] = q;
+    }
+    inv[q] = 1.0 / ctx->surf_area[q];
+  }
   QuadOpts qo;
   qo.self_n = o.self_n;
   qo.near_q = o.near_q;
@@ -927,13 +1100,41 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
     upload(ctx->row_ptr, S.near_ptr);
     upload(ctx->patch, S.near_patch);
     upload(ctx->w, S.w);
+    upload(ctx->node_off, ctx->node_off_h);
+    upload(ctx->node_surf, nsurf_of);
+    upload(ctx->inv_area, inv);
     const bool direct = (o.flags & LB_DIRECT) != 0;
-    build_prec<float>(ctx.get(), ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
+    build_prec<float>(ctx, ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
     ctx->rm2f = std::move(rm2);
     // the float positions used by the mask test must be exactly the ones on the device
-    build_prec<double>(ctx.get(), ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
+    build_prec<double>(ctx, ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
     HIPTRY(hipDeviceSynchronize());
   }
+}
+}  // namespace lb
+
+lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, const double* Xu, const double* Xv,
+                   const lb_opts* opts, void* stream) {
+  API_BEGIN
+  (void)stream;
+  if (!out) fail(LB_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_patches < 1) fail(LB_EINVAL, "n_patches must be >= 1");
+  auto ctx = std::make_unique<lb_ctx>();
+  const int32_t np = n_patches;
+  setup_impl(ctx.get(), 1, &np, order, X, Xu, Xv, opts);
+  *out = ctx.release();
+  API_END
+}
+
+lb_status lb_setup_batch(lb_ctx** out, int n_surf, const int32_t* patches_per_surf, int order, const double* X,
+                         const double* Xu, const double* Xv, const lb_opts* opts, void* stream) {
+  API_BEGIN
+  (void)stream;
+  if (!out) fail(LB_EINVAL, "null argument");
+  *out = nullptr;
+  auto ctx = std::make_unique<lb_ctx>();
+  setup_impl(ctx.get(), n_surf, patches_per_surf, order, X, Xu, Xv, opts);
   *out = ctx.release();
   API_END
 }
@@ -947,24 +1148,29 @@ lb_status lb_get_sizes(const lb_ctx* ctx, lb_sizes* s) {
   s->n_o = ctx->n_o;
   s->N_o = ctx->No;
   s->nnz_blocks = ctx->S.near_ptr.empty() ? 0 : ctx->S.near_ptr.back();
-  s->fmm_levels = ctx->host_only ? 0 : ctx->f32.tree.depth;
+  s->fmm_levels = 0;
+  if (!ctx->host_only)
+    for (const Octree& t : ctx->f32.trees) s->fmm_levels = std::max<int64_t>(s->fmm_levels, t.depth);
+  s->n_surf = ctx->n_surf;
   s->fmm_leaves = ctx->host_only ? 0 : ctx->f32.dt.n_leaf_tgt;
   s->p_f32 = ctx->opts.p_f32;
   s->p_f64 = ctx->opts.p_f64;
   s->p2p_pairs32 = s->m2l_pairs32 = s->p2p_pairs64 = s->m2l_pairs64 = 0;
   if (!ctx->host_only) {
-    auto count = [](const Octree& t, int64_t& pp, int64_t& mp) {
-      pp = 0;
-      const int nleaf = (int)t.tgt_beg.size();
-      for (int b = 0; b < nleaf; ++b) {
-        int64_t ns = 0;
-        for (int u = t.ulist_ptr[b]; u < t.ulist_ptr[b + 1]; ++u) ns += t.src_end[t.ulist[u]] - t.src_beg[t.ulist[u]];
-        pp += ns * (t.tgt_end[b] - t.tgt_beg[b]);
+    auto count = [](const std::vector<Octree>& trees, int64_t& pp, int64_t& mp) {
+      pp = mp = 0;
+      for (const Octree& t : trees) {
+        const int nleaf = (int)t.tgt_beg.size();
+        for (int b = 0; b < nleaf; ++b) {
+          int64_t ns = 0;
+          for (int u = t.ulist_ptr[b]; u < t.ulist_ptr[b + 1]; ++u) ns += t.src_end[t.ulist[u]] - t.src_beg[t.ulist[u]];
+          pp += ns * (t.tgt_end[b] - t.tgt_beg[b]);
+        }
+        mp += t.vlist_ptr.empty() ? 0 : t.vlist_ptr.back();
       }
-      mp = t.vlist_ptr.empty() ? 0 : t.vlist_ptr.back();
     };
-    count(ctx->f32.tree, s->p2p_pairs32, s->m2l_pairs32);
-    count(ctx->f64.tree, s->p2p_pairs64, s->m2l_pairs64);
+    count(ctx->f32.trees, s->p2p_pairs32, s->m2l_pairs32);
+    count(ctx->f64.trees, s->p2p_pairs64, s->m2l_pairs64);
   }
   API_END
 }
@@ -1158,7 +1364,7 @@ lb_status lb_tree_get(const lb_tree* tree, lb_tree_info* info, int64_t* tgt_perm
 
 void lb_tree_destroy(lb_tree* tree) { delete tree; }
 
-lb_status lb_get_tree(const lb_ctx* ctx, int prec, int transposed, lb_tree_info* info, int64_t* tgt_perm,
+lb_status lb_get_tree(const lb_ctx* ctx, int prec, int transposed, int surf, lb_tree_info* info, int64_t* tgt_perm,
                       int64_t* src_perm, int32_t* leaf_ranges, int32_t* ulist_ptr, int32_t* ulist,
                       int32_t* vlist_ptr, int32_t* vlist_src, int32_t* vlist_off, int32_t* boxes) {
   API_BEGIN
@@ -1167,8 +1373,9 @@ lb_status lb_get_tree(const lb_ctx* ctx, int prec, int transposed, lb_tree_info*
   if (prec != LB_PREC_FP32 && prec != LB_PREC_FP64) fail(LB_EINVAL, "prec must be 32 or 64");
   const bool built = prec == LB_PREC_FP32 ? ctx->adj_built32 : ctx->adj_built64;
   if (transposed && !built) fail(LB_EINVAL, "the transposed tree is built by the first adjoint apply");
-  const Octree& t = prec == LB_PREC_FP32 ? (transposed ? ctx->a32.tree : ctx->f32.tree)
-                                         : (transposed ? ctx->a64.tree : ctx->f64.tree);
+  if (surf < 0 || surf >= ctx->n_surf) fail(LB_EINVAL, "surface %d out of range", surf);
+  const Octree& t = prec == LB_PREC_FP32 ? (transposed ? ctx->a32.trees[surf] : ctx->f32.trees[surf])
+                                         : (transposed ? ctx->a64.trees[surf] : ctx->f64.trees[surf]);
   export_tree(t, info, tgt_perm, src_perm, leaf_ranges, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off, boxes);
   API_END
 }
@@ -1178,14 +1385,11 @@ lb_status lb_apply_S(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot
   check_apply(ctx, nd, prec);
   if (!sigma || !pot) fail(LB_EINVAL, "null sigma or pot");
   hipStream_t st = (hipStream_t)stream;
-  // gradient scratch
-  DBuf g;
-  g.alloc((prec == LB_PREC_FP32 ? sizeof(float) : sizeof(double)) * 3 * (size_t)ctx->N * nd);
   if (prec == LB_PREC_FP32)
-    apply_gradS_t<float>(ctx, ctx->f32, nd, (const float*)sigma, (float*)pot, dptr<float>(g), nullptr, nullptr, st);
+    apply_S_t<float>(ctx, ctx->f32, nd, (const float*)sigma, (float*)pot, st);
   else
-    apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, dptr<double>(g), nullptr, nullptr, st);
-  HIPTRY(hipStreamSynchronize(st));
+    apply_S_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, st);
+  HIPTRY(hipGetLastError());
   API_END
 }
 
@@ -1211,7 +1415,7 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   if (mode != LB_SOLVE_FP64 && mode != LB_SOLVE_FP32_REFINE) fail(LB_EINVAL, "unknown mode");
   hipStream_t st = (hipStream_t)stream;
   const int64_t N = ctx->N;
-  const int maxit = ctx->opts.max_iter;
+  const int nsf = ctx->n_surf;
   ensure_ws(ctx, ctx->f64, CHUNK_GRAD);
   ensure_ws(ctx, ctx->f32, CHUNK_GRAD);
   const size_t nN = (size_t)nrhs * N;
@@ -1226,8 +1430,6 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   double* fz = dptr<double>(ctx->ftmp);
   double* ut = dptr<double>(ctx->utmp);
   double* dcorr = ut + nN;
-  DBuf scal;
-  scal.alloc(sizeof(double) * 4);
   auto A64 = [&](const double* v, double* w, int na) { apply_A3_t<double>(ctx, ctx->f64, na, v, w, st); };
   auto A32 = [&](const double* v, double* w, int na) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
@@ -1236,50 +1438,38 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
     apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, st);
     launch_convert<float, double>(vo, w, (int64_t)na * N, st);
   };
-  auto nrm2 = [&](const double* v) {
-    launch_dots(v, N, 1, v, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
-    double sv;
-    HIPTRY(hipMemcpyAsync(&sv, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    return std::sqrt(sv);
-  };
-  // mean projection (Lemma 1)
-  std::vector<double> mean(nrhs), fnorm(nrhs);
-  for (int q = 0; q < nrhs; ++q) {
-    const double* fq = f + (size_t)q * N;
-    double* fzq = fz + (size_t)q * N;
-    launch_wmean(fq, dptr<double>(ctx->w), N, dptr<double>(ctx->partial), dptr<double>(scal), st);
-    double sumwf;
-    HIPTRY(hipMemcpyAsync(&sumwf, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    mean[q] = sumwf / ctx->area;
-    HIPTRY(hipMemcpyAsync(fzq, fq, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    if (ctx->opts.flags & LB_STRICT_MEAN) {
-      const double fn = nrm2(fzq);
-      if (std::fabs(mean[q]) > 1e-12 * fn) fail(LB_ENOTMEANZERO, "right-hand side %d has weighted mean %g", q, mean[q]);
-    }
-    launch_sub_scalar(fzq, dptr<double>(scal), 1.0 / ctx->area, N, st);
-    fnorm[q] = nrm2(fzq);
+  // mean projection per surface (Lemma 1): fz = f - (sum_q w f / area_q) on surface q
+  DBuf means;
+  means.alloc(sizeof(double) * (size_t)nrhs * nsf);
+  launch_seg_dot<double>(nrhs, nsf, N, dptr<int64_t>(ctx->node_off), f, dptr<double>(ctx->w),
+                         dptr<double>(ctx->inv_area), dptr<double>(means), st);
+  launch_seg_axpy<double>(nrhs, nsf, N, dptr<int>(ctx->node_surf), f, -1.0, nullptr, dptr<double>(means), fz, st);
+  std::vector<double> mean((size_t)nrhs * nsf);
+  HIPTRY(hipMemcpyAsync(mean.data(), means.p, sizeof(double) * mean.size(), hipMemcpyDeviceToHost, st));
+  const Systems sy = make_systems(ctx, nrhs);
+  if (ctx->opts.flags & LB_STRICT_MEAN) {
+    std::vector<double> fn = system_norms(ctx, sy, f, st);
+    for (size_t a = 0; a < fn.size(); ++a)
+      if (std::fabs(mean[a]) > 1e-12 * fn[a])
+        fail(LB_ENOTMEANZERO, "right-hand side %d (surface %d) has weighted mean %g", (int)(a / nsf), (int)(a % nsf),
+             mean[a]);
   }
+  const std::vector<double> fnorm = system_norms(ctx, sy, fz, st);
   std::vector<double> rel;
   std::vector<int> iters, outer;
-  solve_system(ctx, nrhs, A64, A32, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel, iters, outer, st);
+  solve_system(ctx, nrhs, sy, A64, A32, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel, iters, outer, st);
   // u = S[S[sigma]] in FP64
-  {
-    DBuf g;
-    g.alloc(sizeof(double) * 3 * nN);
-    apply_gradS_t<double>(ctx, ctx->f64, nrhs, sig, ut, dptr<double>(g), nullptr, nullptr, st);
-    apply_gradS_t<double>(ctx, ctx->f64, nrhs, ut, u, dptr<double>(g), nullptr, nullptr, st);
-    HIPTRY(hipStreamSynchronize(st));
-  }
+  apply_S_t<double>(ctx, ctx->f64, nrhs, sig, ut, st);
+  apply_S_t<double>(ctx, ctx->f64, nrhs, ut, u, st);
+  HIPTRY(hipStreamSynchronize(st));
   lb_status ret = LB_OK;
-  for (int q = 0; q < nrhs; ++q) {
-    if (!(rel[q] < tol)) ret = LB_ENOCONV;
+  for (size_t a = 0; a < rel.size(); ++a) {
+    if (!(rel[a] < tol)) ret = LB_ENOCONV;
     if (info) {
-      info[q].iters = iters[q];
-      info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[q] - 1, 0);
-      info[q].rel_resid = rel[q];
-      info[q].removed_mean = mean[q];
+      info[a].iters = iters[a];
+      info[a].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[a] - 1, 0);
+      info[a].rel_resid = rel[a];
+      info[a].removed_mean = mean[a];
     }
   }
   if (ret != LB_OK) {
@@ -1298,6 +1488,7 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
   if (mode != LB_SOLVE_FP64 && mode != LB_SOLVE_FP32_REFINE) fail(LB_EINVAL, "unknown mode");
   hipStream_t st = (hipStream_t)stream;
   const int64_t N = ctx->N;
+  const int nsf = ctx->n_surf;
   ensure_ws(ctx, ctx->f64, CHUNK_GRAD);
   ensure_ws(ctx, ctx->f32, CHUNK_GRAD);
   const size_t nN = (size_t)nrhs * N;
@@ -1325,39 +1516,29 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
   // rhs = S^T S^T ubar (adjoint of u = S[S[sigma]])
   apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nrhs, ubar, nullptr, nullptr, nullptr, ut, st);
   apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nrhs, ut, nullptr, nullptr, nullptr, rhs, st);
-  DBuf scal;
-  scal.alloc(sizeof(double) * 4);
-  std::vector<double> bnorm(nrhs);
-  for (int q = 0; q < nrhs; ++q) {
-    launch_dots(rhs + (size_t)q * N, N, 1, rhs + (size_t)q * N, N, dptr<double>(scal), dptr<double>(ctx->partial), st);
-    double sv;
-    HIPTRY(hipMemcpyAsync(&sv, dptr<double>(scal), sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    bnorm[q] = std::sqrt(sv);
-  }
+  const Systems sy = make_systems(ctx, nrhs);
+  const std::vector<double> bnorm = system_norms(ctx, sy, rhs, st);
   std::vector<double> rel;
   std::vector<int> iters, outer;
-  solve_system(ctx, nrhs, A64, A32, rhs, bnorm, y, r, ut, dcorr, tol, mode, rel, iters, outer, st);
-  // fbar = (I - w 1^T / area) y, the transpose of the mean projection
-  std::vector<double> removed(nrhs);
+  solve_system(ctx, nrhs, sy, A64, A32, rhs, bnorm, y, r, ut, dcorr, tol, mode, rel, iters, outer, st);
+  // fbar = (I - w 1^T / area_q) y on each surface q: the transposed mean projection
   DBuf sc;
-  sc.alloc(sizeof(double) * nrhs);
-  for (int d0 = 0; d0 < nrhs; d0 += NDMAX_HOST) {
-    const int c = std::min(NDMAX_HOST, nrhs - d0);
-    launch_colsum<double>(c, N, y + (size_t)d0 * N, 1.0 / ctx->area, dptr<double>(ctx->partial),
-                          dptr<double>(sc) + d0, st);
-  }
-  launch_sub_wscal(nrhs, N, y, dptr<double>(ctx->w), dptr<double>(sc), fbar, st);
-  HIPTRY(hipMemcpyAsync(removed.data(), sc.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  sc.alloc(sizeof(double) * (size_t)nrhs * nsf);
+  launch_seg_dot<double>(nrhs, nsf, N, dptr<int64_t>(ctx->node_off), y, nullptr, dptr<double>(ctx->inv_area),
+                         dptr<double>(sc), st);
+  launch_seg_axpy<double>(nrhs, nsf, N, dptr<int>(ctx->node_surf), y, -1.0, dptr<double>(ctx->w), dptr<double>(sc),
+                          fbar, st);
+  std::vector<double> removed((size_t)nrhs * nsf);
+  HIPTRY(hipMemcpyAsync(removed.data(), sc.p, sizeof(double) * removed.size(), hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
   lb_status ret = LB_OK;
-  for (int q = 0; q < nrhs; ++q) {
-    if (!(rel[q] < tol)) ret = LB_ENOCONV;
+  for (size_t a = 0; a < rel.size(); ++a) {
+    if (!(rel[a] < tol)) ret = LB_ENOCONV;
     if (info) {
-      info[q].iters = iters[q];
-      info[q].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[q] - 1, 0);
-      info[q].rel_resid = rel[q];
-      info[q].removed_mean = removed[q];
+      info[a].iters = iters[a];
+      info[a].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[a] - 1, 0);
+      info[a].rel_resid = rel[a];
+      info[a].removed_mean = removed[a];
     }
   }
   if (ret != LB_OK) {

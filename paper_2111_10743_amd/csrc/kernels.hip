@@ -189,10 +189,10 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
   T* sq = Rim + P2M_TS * Lc;     // [2][TS] strengths of this rhs
   T* sn = sq + 2 * P2M_TS;       // [3][TS] normals
   const int b = t.leaf_src_list[blockIdx.x];
-  const int g = t.leaf_off + b;
+  const int g = t.leaf_box[b];
   const int rhs = blockIdx.y;
   const int nexp = fmm_nexp(mode), nstr = fmm_nstr(mode);
-  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T h = t.leaf_h[b];
   const T ih = (T)1 / h;
   const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
   T acc[KMAX][3];
@@ -297,9 +297,9 @@ __global__ __launch_bounds__(256) void k_p2m_adj3(DevTree<T> t, int nrhs, const 
   T* sq = Dim + ts * Lc;  // [2][ts] v, w
   T* sn = sq + 2 * ts;    // [3][ts] normals
   const int b = t.leaf_src_list[blockIdx.x];
-  const int g = t.leaf_off + b;
+  const int g = t.leaf_box[b];
   const int rhs = blockIdx.y;
-  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T h = t.leaf_h[b];
   const T ih = (T)1 / h;
   const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
   T acc[KMAX][2];
@@ -392,8 +392,8 @@ __global__ __launch_bounds__(256) void k_p2m_build(DevTree<T> t, T* __restrict__
   T* Rim = Rre + ts * Lc;
   T* sn = Rim + ts * Lc;  // [3][ts]
   const int b = t.leaf_src_list[blockIdx.x];
-  const int g = t.leaf_off + b;
-  const T h = (T)(t.side / (double)(1 << t.depth));
+  const int g = t.leaf_box[b];
+  const T h = t.leaf_h[b];
   const T ih = (T)1 / h;
   const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
   const int beg = t.src_beg[b], end = t.src_end[b];
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(64 * P2M_W) void k_p2m_tab(DevTree<T> t, int nrhs, 
   constexpr int NE = A3B ? 3 : 1;
   __shared__ T red[NE][P2M_W][256];
   const int b = t.leaf_src_list[blockIdx.x];
-  const int g = t.leaf_off + b;
+  const int g = t.leaf_box[b];
   const int rhs = blockIdx.y;
   const int L = t.L;
   const int nstr = A3B ? 2 : 1;
@@ -516,74 +516,6 @@ __global__ __launch_bounds__(64 * P2M_W) void k_p2m_tab(DevTree<T> t, int nrhs, 
       }
     }
     __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// dense translation helpers: out[e][r] (+)= sum_c TT[c][r] x[e][c]
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void mv_acc(const T* __restrict__ TT, const T* x, int L, int ne, T acc[KMAX][8]) {
-  for (int c = 0; c < L; ++c) {
-    const T* col = TT + (int64_t)c * L;
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      const int r = threadIdx.x + k * 256;
-      if (r < L) {
-        const T a = col[r];
-        for (int e = 0; e < ne; ++e) acc[k][e] += a * x[e * L + c];
-      }
-    }
-  }
-}
-
-// M2M: grid = boxes with sources on level l (l < depth)
-template <typename T>
-__global__ __launch_bounds__(256) void k_m2m(DevTree<T> t, int l, int ne, T* __restrict__ M) {
-  extern __shared__ unsigned char smraw[];
-  T* x = reinterpret_cast<T*>(smraw);
-  const int L = t.L;
-  const int g = t.lev_box_src[t.lev_box_src_ptr[l] + blockIdx.x];
-  T acc[KMAX][8];
-  for (int k = 0; k < KMAX; ++k)
-    for (int e = 0; e < 8; ++e) acc[k][e] = 0;
-  for (int oct = 0; oct < 8; ++oct) {
-    const int ch = t.child_src[(int64_t)g * 8 + oct];
-    if (ch < 0) continue;
-    __syncthreads();
-    for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = M[(int64_t)ch * ne * L + i];
-    __syncthreads();
-    mv_acc(t.m2m + (int64_t)oct * L * L, x, L, ne, acc);
-  }
-  for (int k = 0; k < KMAX; ++k) {
-    const int r = threadIdx.x + k * 256;
-    if (r < L)
-      for (int e = 0; e < ne; ++e) M[((int64_t)g * ne + e) * L + r] = acc[k][e];
-  }
-}
-
-// M2L: grid = boxes with targets on level l (l >= 2); writes Lc (overwrite)
-template <typename T>
-__global__ __launch_bounds__(256) void k_m2l(DevTree<T> t, int l, int ne, const T* __restrict__ M, T* __restrict__ Lc) {
-  extern __shared__ unsigned char smraw[];
-  T* x = reinterpret_cast<T*>(smraw);
-  const int L = t.L;
-  const int g = t.lev_box_tgt[t.lev_box_tgt_ptr[l] + blockIdx.x];
-  T acc[KMAX][8];
-  for (int k = 0; k < KMAX; ++k)
-    for (int e = 0; e < 8; ++e) acc[k][e] = 0;
-  for (int v = t.vlist_ptr[g]; v < t.vlist_ptr[g + 1]; ++v) {
-    const int s = t.vlist_src[v];
-    __syncthreads();
-    for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = M[(int64_t)s * ne * L + i];
-    __syncthreads();
-    mv_acc(t.m2l + (int64_t)t.vlist_off[v] * L * L, x, L, ne, acc);
-  }
-  const T ih = (T)((double)(1 << l) / t.side);
-  for (int k = 0; k < KMAX; ++k) {
-    const int r = threadIdx.x + k * 256;
-    if (r < L)
-      for (int e = 0; e < ne; ++e) Lc[((int64_t)g * ne + e) * L + r] = acc[k][e] * ih;
   }
 }
 
@@ -712,14 +644,14 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
 }
 
 // out[g][e][r] (+)= f_g * sum over the triples p of box g of Y[p*ne + e][r],
-// f_g = 2^level / side when scaled, else 1
+// f_g = box_scale (2^level / side of the box's tree) when given, else 1
 template <typename T>
-__global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxes, const int* __restrict__ box_level,
+__global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxes, const double* __restrict__ box_scale,
                                                     const int* __restrict__ tptr, const int* __restrict__ tpairs,
-                                                    int ne, int L, double side, int scaled, int accumulate,
-                                                    const T* __restrict__ Y, T* __restrict__ out) {
+                                                    int ne, int L, int accumulate, const T* __restrict__ Y,
+                                                    T* __restrict__ out) {
   const int g = boxes[blockIdx.x];
-  const T f = scaled ? (T)((double)(1 << box_level[blockIdx.x]) / side) : (T)1;
+  const T f = box_scale ? (T)box_scale[blockIdx.x] : (T)1;
   const int pb = tptr[blockIdx.x], pe = tptr[blockIdx.x + 1];
   for (int i = threadIdx.x; i < ne * L; i += blockDim.x) {
     const int e = i / L, r = i - e * L;
@@ -731,8 +663,7 @@ __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxe
 }
 
 template <typename T>
-static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, double side, const T* X, T* Y, T* out,
-                     hipStream_t st) {
+static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, const T* X, T* Y, T* out, hipStream_t st) {
   if (pl.nbox == 0) return;
   if (pl.nwork[ne] > 0) {
     dim3 grid(pl.nwork[ne], (L + GM_RB * 16 - 1) / (GM_RB * 16));
@@ -740,33 +671,9 @@ static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, double side
                        pl.pair_src, ne, X, Y);
     KCHECK();
   }
-  hipLaunchKernelGGL(k_col_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.box_level, pl.tptr, pl.tpairs,
-                     ne, L, side, pl.scaled ? 1 : 0, pl.accumulate ? 1 : 0, (const T*)Y, out);
+  hipLaunchKernelGGL(k_col_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.scaled ? pl.box_scale : nullptr,
+                     pl.tptr, pl.tpairs, ne, L, pl.accumulate ? 1 : 0, (const T*)Y, out);
   KCHECK();
-}
-
-// L2L: grid = boxes with targets on level l (l >= 3); Lc[g] += TT[oct] Lc[parent]
-template <typename T>
-__global__ __launch_bounds__(256) void k_l2l(DevTree<T> t, int l, int ne, T* __restrict__ Lc) {
-  extern __shared__ unsigned char smraw[];
-  T* x = reinterpret_cast<T*>(smraw);
-  const int L = t.L;
-  const int g = t.lev_box_tgt[t.lev_box_tgt_ptr[l] + blockIdx.x];
-  const int pg = t.parent[g];
-  int oct = -1;
-  for (int c = 0; c < 8; ++c)
-    if (t.child[(int64_t)pg * 8 + c] == g) oct = c;
-  for (int i = threadIdx.x; i < ne * L; i += blockDim.x) x[i] = Lc[(int64_t)pg * ne * L + i];
-  __syncthreads();
-  T acc[KMAX][8];
-  for (int k = 0; k < KMAX; ++k)
-    for (int e = 0; e < 8; ++e) acc[k][e] = 0;
-  mv_acc(t.l2l + (int64_t)oct * L * L, x, L, ne, acc);
-  for (int k = 0; k < KMAX; ++k) {
-    const int r = threadIdx.x + k * 256;
-    if (r < L)
-      for (int e = 0; e < ne; ++e) Lc[((int64_t)g * ne + e) * L + r] += acc[k][e];
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -830,11 +737,11 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
                                                   T* __restrict__ out, int64_t N) {
   extern __shared__ unsigned char smraw[];
   const int b = t.leaf_tgt_list[blockIdx.x];
-  const int g = t.leaf_off + b;
+  const int g = t.leaf_box[b];
   const int rhs = blockIdx.y;
   const int p = t.p, L = t.L, Lg = p * p, Lh = (p - 1) * (p - 1);
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
-  const bool far = t.depth >= 2;
+  const bool far = t.leaf_lvl[b] >= 2;
   const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
   int F = LEAF_FMAX;
   while (F > 1 && F * (tend - tbeg) > LEAF_BS) F >>= 1;
@@ -882,7 +789,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     }
     __syncthreads();
   }
-  const T h = (T)(t.side / (double)(1 << t.depth));
+  const T h = t.leaf_h[b];
   const T ih = (T)1 / h;
   const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
   // source records in LDS: (x, y, z, q1), (nx, ny, nz, q2) and rm2
@@ -1148,39 +1055,12 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
       hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
     KCHECK();
     tm->mark(PH_M2M, st);
-    const int* hp = t.h_lev_src_ptr;
-    const int* ht = t.h_lev_tgt_ptr;
-    size_t smv = sizeof(T) * ne * L;
     T* Y = (T*)t.Y;
-    for (int l = t.depth - 1; l >= 2; --l) {
-      if (t.m2m_plan) {
-        run_plan<T>(t.m2m_plan[l], t.m2m, L, ne, t.side, M, Y, M, st);
-      } else {
-        int nb = hp[l + 1] - hp[l];
-        if (nb > 0) hipLaunchKernelGGL(k_m2m<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M);
-        KCHECK();
-      }
-    }
+    for (int l = t.depth - 1; l >= 2; --l) run_plan<T>(t.m2m_plan[l], t.m2m, L, ne, M, Y, M, st);
     tm->mark(PH_M2L, st);
-    if (t.m2l_plan) {
-      run_plan<T>(*t.m2l_plan, t.m2l, L, ne, t.side, M, Y, Lc, st);
-    } else {
-      for (int l = 2; l <= t.depth; ++l) {
-        int nb = ht[l + 1] - ht[l];
-        if (nb > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, M, Lc);
-        KCHECK();
-      }
-    }
+    run_plan<T>(*t.m2l_plan, t.m2l, L, ne, M, Y, Lc, st);
     tm->mark(PH_L2L, st);
-    for (int l = 3; l <= t.depth; ++l) {
-      if (t.l2l_plan) {
-        run_plan<T>(t.l2l_plan[l], t.l2l, L, ne, t.side, Lc, Y, Lc, st);
-      } else {
-        int nb = ht[l + 1] - ht[l];
-        if (nb > 0) hipLaunchKernelGGL(k_l2l<T>, dim3(nb), dim3(256), smv, st, t, l, ne, Lc);
-        KCHECK();
-      }
-    }
+    for (int l = 3; l <= t.depth; ++l) run_plan<T>(t.l2l_plan[l], t.l2l, L, ne, Lc, Y, Lc, st);
   } else {
     tm->mark(PH_M2M, st);
     tm->mark(PH_M2L, st);
@@ -1353,6 +1233,45 @@ void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, con
   }
 }
 
+// S only: pot = phi / (4 pi) + C_S sigma (vals3 column 0), FMM_POT output
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void k_combine_pot(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+                                                     const int* __restrict__ patch, const T* __restrict__ vals,
+                                                     const T* __restrict__ sigma, const T* __restrict__ fmm,
+                                                     const int* __restrict__ tgt_pos, T* pot) {
+  __shared__ int pat_s[4][64];
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  T acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = 0;
+  row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[threadIdx.x >> 6], [&](int64_t e, int64_t col, bool on) {
+    const T c0 = vals[e * 3];
+    const T m = on ? (T)1 : (T)0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] += c0 * sigma[(int64_t)d * N + col] * m;
+  });
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = wave_sum(acc[d]);
+  if (lane == 0) {
+    const int tp = tgt_pos[row];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) pot[(int64_t)d * N + row] = fmm[(int64_t)d * N + tp] * (T)INV4PI_D + acc[d];
+  }
+}
+
+template <typename T>
+void launch_combine_pot(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,
+                        const T* sigma, const T* fmm, const int* tgt_pos, T* pot, hipStream_t st) {
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    ND_DISPATCH(k_combine_pot, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3,
+                sigma + (int64_t)d0 * N, fmm + (int64_t)d0 * N, tgt_pos, pot + (int64_t)d0 * N)
+    KCHECK();
+  }
+}
+
 // A3 step 1: mu2 = S tau, mu1 = S' tau  (vals3 columns: S, S', S''+D')
 template <typename T, int ND>
 __global__ __launch_bounds__(256) void k_combine_a3a(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
@@ -1407,67 +1326,91 @@ void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, cons
 }
 
 // A3 step 2: per row y1 = S'mu1, y2 = S mu2, y3 = S'mu2, y4 = (S''+D')mu2;
-// out = -tau/4 + y1 - y4 - 2 H y3 ; partial[block][d] = sum_rows w y2
+// out = -tau/4 + y1 - y4 - 2 H y3 (the W S[S tau] term is added per surface
+// afterwards from y2, kept in y2buf)
 template <typename T, int ND>
 __global__ __launch_bounds__(256) void k_combine_a3b(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
                                                      const int* __restrict__ patch, const T* __restrict__ vals,
                                                      const T* __restrict__ tau, const T* __restrict__ mu1,
                                                      const T* __restrict__ mu2, int64_t ldmu, const T* __restrict__ fmm,
                                                      const int* __restrict__ tgt_pos, const T* __restrict__ H,
-                                                     const double* __restrict__ w, T* out, double* partial,
-                                                     int nblk) {
-  __shared__ double red[4][NDMAX];
+                                                     T* out, T* y2buf) {
   __shared__ int pat_s[4][64];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int64_t row = (int64_t)blockIdx.x * 4 + wv;
-  double wy[ND];
+  if (row >= N) return;
+  T a1[ND], a2[ND], a3[ND], a4[ND];
 #pragma unroll
-  for (int d = 0; d < ND; ++d) wy[d] = 0;
-  if (row < N) {
-    T a1[ND], a2[ND], a3[ND], a4[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) { a1[d] = a2[d] = a3[d] = a4[d] = 0; }
-    row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[threadIdx.x >> 6], [&](int64_t e, int64_t col, bool on) {
-      const T* c = vals + e * 3;
-      const T cS = c[0], cP = c[1], cD = c[2];
-      const T m = on ? (T)1 : (T)0;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        const T x1 = mu1[(int64_t)d * ldmu + col] * m;
-        const T x2 = mu2[(int64_t)d * ldmu + col] * m;
-        a1[d] += cP * x1;
-        a2[d] += cS * x2;
-        a3[d] += cP * x2;
-        a4[d] += cD * x2;
-      }
-    });
+  for (int d = 0; d < ND; ++d) { a1[d] = a2[d] = a3[d] = a4[d] = 0; }
+  row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[wv], [&](int64_t e, int64_t col, bool on) {
+    const T* c = vals + e * 3;
+    const T cS = c[0], cP = c[1], cD = c[2];
+    const T m = on ? (T)1 : (T)0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      a1[d] = wave_sum(a1[d]); a2[d] = wave_sum(a2[d]); a3[d] = wave_sum(a3[d]); a4[d] = wave_sum(a4[d]);
+      const T x1 = mu1[(int64_t)d * ldmu + col] * m;
+      const T x2 = mu2[(int64_t)d * ldmu + col] * m;
+      a1[d] += cP * x1;
+      a2[d] += cS * x2;
+      a3[d] += cP * x2;
+      a4[d] += cD * x2;
     }
-    if (lane == 0) {
-      const int tp = tgt_pos[row];
-      const T s = (T)INV4PI_D;
+  });
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        const T* f = fmm + (int64_t)d * 4 * N;
-        const T y1 = f[tp] * s + a1[d];
-        const T y2 = f[N + tp] * s + a2[d];
-        const T y3 = f[2 * N + tp] * s + a3[d];
-        const T y4 = f[3 * N + tp] * s + a4[d];
-        out[(int64_t)d * N + row] = -(T)0.25 * tau[(int64_t)d * N + row] + y1 - y4 - (T)2 * H[row] * y3;
-        wy[d] = w[row] * (double)y2;
-      }
+  for (int d = 0; d < ND; ++d) {
+    a1[d] = wave_sum(a1[d]); a2[d] = wave_sum(a2[d]); a3[d] = wave_sum(a3[d]); a4[d] = wave_sum(a4[d]);
+  }
+  if (lane == 0) {
+    const int tp = tgt_pos[row];
+    const T s = (T)INV4PI_D;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const T* f = fmm + (int64_t)d * 4 * N;
+      const T y1 = f[tp] * s + a1[d];
+      const T y2 = f[N + tp] * s + a2[d];
+      const T y3 = f[2 * N + tp] * s + a3[d];
+      const T y4 = f[3 * N + tp] * s + a4[d];
+      out[(int64_t)d * N + row] = -(T)0.25 * tau[(int64_t)d * N + row] + y1 - y4 - (T)2 * H[row] * y3;
+      y2buf[(int64_t)d * N + row] = y2;
     }
   }
-  if (lane == 0)
-#pragma unroll
-    for (int d = 0; d < ND; ++d) red[wv][d] = wy[d];
-  __syncthreads();
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int d = 0; d < ND; ++d) partial[(int64_t)d * nblk + blockIdx.x] = red[0][d] + red[1][d] + red[2][d] + red[3][d];
+}
+
+// serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
+__global__ void k_reduce_partials(const double* partial, int nblk, int nd, double scale, double* s) {
+  __shared__ double red[256];
+  for (int d = 0; d < nd; ++d) {
+    double a = 0;
+    for (int b = threadIdx.x; b < nblk; b += 256) a += partial[(int64_t)d * nblk + b];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) s[d] = red[0] * scale;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
+                        const T* vals3, const T* tau, const T* mu1, const T* mu2, int64_t ldmu, const T* fmm,
+                        const int* tgt_pos, const T* H, const double* w, int nsurf, const int64_t* node_off,
+                        const int* node_surf, const double* inv_area, T* out, T* y2buf, double* scal,
+                        hipStream_t st) {
+  const int nblk = (int)((N + 3) / 4);
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    ND_DISPATCH(k_combine_a3b, ndc, dim3(nblk), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3,
+                tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * ldmu, mu2 + (int64_t)d0 * ldmu, ldmu,
+                fmm + (int64_t)d0 * 4 * N, tgt_pos, H, out + (int64_t)d0 * N, y2buf + (int64_t)d0 * N)
+    KCHECK();
+  }
+  // W S[S tau] per surface: scal[d][q] = sum_{i in q} w_i y2_i / area_q
+  launch_seg_dot<T>(nd, nsurf, N, node_off, y2buf, w, inv_area, scal, st);
+  launch_seg_axpy<T>(nd, nsurf, N, node_surf, out, 1.0, nullptr, scal, out, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1598,6 +1541,7 @@ __global__ __launch_bounds__(64) void k_adj3_comb(int NP, int n_p, int n_o, int6
                                                   const int64_t* __restrict__ cblk, const T* __restrict__ vals3,
                                                   const T* __restrict__ g2, const T* __restrict__ v,
                                                   const T* __restrict__ z, const double* __restrict__ scal,
+                                                  int nsurf, const int* __restrict__ node_surf,
                                                   T* __restrict__ o1, T* __restrict__ o2) {
   const int l = blockIdx.x, d = blockIdx.y;
   const int lane = threadIdx.x;
@@ -1635,7 +1579,8 @@ __global__ __launch_bounds__(64) void k_adj3_comb(int NP, int n_p, int n_o, int6
         o1[r] = t1;
         o2[r] = t2;
       } else {
-        o1[r] = -(T)0.25 * v[r] + t1 + (T)scal[d] * z[(int64_t)l * n_p + k];
+        const int64_t i = (int64_t)l * n_p + k;
+        o1[r] = -(T)0.25 * v[r] + t1 + (T)scal[(int64_t)d * nsurf + node_surf[i]] * z[i];
       }
     }
   }
@@ -1658,103 +1603,18 @@ void launch_adj3_comb1(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, 
                        const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
                        const T* vals3, const T* g2, T* a, T* b, hipStream_t st) {
   hipLaunchKernelGGL((k_adj3_comb<T, 1>), dim3(NP, nd), dim3(64), 0, st, NP, n_p, n_o, N, No, P, wo, psi, tgt_pos,
-                     cptr, crow, cblk, vals3, g2, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, a,
-                     b);
+                     cptr, crow, cblk, vals3, g2, (const T*)nullptr, (const T*)nullptr, (const double*)nullptr, 0,
+                     (const int*)nullptr, a, b);
   KCHECK();
 }
 template <typename T>
 void launch_adj3_comb2(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
                        const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
-                       const T* vals3, const T* g2, const T* v, const T* z, const double* scal, T* out,
-                       hipStream_t st) {
+                       const T* vals3, const T* g2, const T* v, const T* z, const double* scal, int nsurf,
+                       const int* node_surf, T* out, hipStream_t st) {
   hipLaunchKernelGGL((k_adj3_comb<T, 2>), dim3(NP, nd), dim3(64), 0, st, NP, n_p, n_o, N, No, P, wo, psi, tgt_pos,
-                     cptr, crow, cblk, vals3, g2, v, z, scal, out, (T*)nullptr);
+                     cptr, crow, cblk, vals3, g2, v, z, scal, nsurf, node_surf, out, (T*)nullptr);
   KCHECK();
-}
-
-// per-block sums of v[d] (fixed order), then the serial-order reduction
-template <typename T>
-__global__ void k_colsum_part(int nd, int64_t N, const T* __restrict__ v, double* __restrict__ partial, int nblk) {
-  __shared__ double red[256];
-  for (int d = 0; d < nd; ++d) {
-    double a = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)nblk * 256)
-      a += (double)v[(int64_t)d * N + i];
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(int64_t)d * nblk + blockIdx.x] = red[0];
-    __syncthreads();
-  }
-}
-
-// serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
-__global__ void k_reduce_partials(const double* partial, int nblk, int nd, double scale, double* s) {
-  __shared__ double red[256];
-  for (int d = 0; d < nd; ++d) {
-    double a = 0;
-    for (int b = threadIdx.x; b < nblk; b += 256) a += partial[(int64_t)d * nblk + b];
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) s[d] = red[0] * scale;
-    __syncthreads();
-  }
-}
-
-template <typename T>
-__global__ void k_add_scalar(T* out, int64_t N, int nd, const double* s) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  for (int d = 0; d < nd; ++d) out[(int64_t)d * N + i] += (T)s[d];
-}
-
-// out[d][i] = y[d][i] - w[i] * scal[d]   (FP64)
-__global__ void k_sub_wscal(int nd, int64_t N, const double* __restrict__ y, const double* __restrict__ w,
-                            const double* __restrict__ scal, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  for (int d = 0; d < nd; ++d) out[(int64_t)d * N + i] = y[(int64_t)d * N + i] - w[i] * scal[d];
-}
-void launch_sub_wscal(int nd, int64_t N, const double* y, const double* w, const double* scal, double* out,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_sub_wscal, dim3((N + 255) / 256), dim3(256), 0, st, nd, N, y, w, scal, out);
-  KCHECK();
-}
-
-template <typename T>
-void launch_colsum(int nd, int64_t N, const T* v, double scale, double* partial, double* scal, hipStream_t st) {
-  const int nblk = 256;
-  hipLaunchKernelGGL(k_colsum_part<T>, dim3(nblk), dim3(256), 0, st, nd, N, v, partial, nblk);
-  KCHECK();
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblk, nd, scale, scal);
-  KCHECK();
-}
-
-template <typename T>
-void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
-                        const T* vals3, const T* tau, const T* mu1, const T* mu2, int64_t ldmu, const T* fmm,
-                        const int* tgt_pos, const T* H, const double* w, double inv_area,
-                        T* out, double* partial, hipStream_t st) {
-  const int nblk = (int)((N + 3) / 4);
-  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
-    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
-    double* sc = partial + (int64_t)NDMAX * nblk;  // NDMAX scalars after the partials
-    ND_DISPATCH(k_combine_a3b, ndc, dim3(nblk), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3,
-                tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * ldmu, mu2 + (int64_t)d0 * ldmu, ldmu,
-                fmm + (int64_t)d0 * 4 * N, tgt_pos, H, w, out + (int64_t)d0 * N, partial, nblk)
-    KCHECK();
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblk, ndc, inv_area, sc);
-    KCHECK();
-    hipLaunchKernelGGL(k_add_scalar<T>, dim3((N + 255) / 256), dim3(256), 0, st, out + (int64_t)d0 * N, N, ndc, sc);
-    KCHECK();
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1873,6 +1733,153 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
   KCHECK();
 }
 
+// ---- several GMRES systems at once (FP64).  System a owns the segment
+// [xoff[a], xoff[a] + len[a]) of the operator's vectors and the basis
+// vectors V + vbase[a] + j len[a], j = 0, 1, ...
+constexpr int MSYS_BLOCKS = 32;
+
+// win = basis vector j of every system in `act` order (all segments of win
+// belong to some system; those of inactive systems are zeroed)
+__global__ void k_msys_gather(int nsys, const int64_t* __restrict__ xoff, const int64_t* __restrict__ len,
+                              const int64_t* __restrict__ vbase, const int* __restrict__ active, int j,
+                              const double* __restrict__ V, double* __restrict__ win) {
+  const int a = blockIdx.y;
+  const int64_t n = len[a], o = xoff[a];
+  const double* v = V + vbase[a] + (int64_t)j * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    win[o + t] = active[a] ? v[t] : 0.0;
+}
+
+// partial[(a k + jj) MB + bx] = sum over this block's share of V_jj(a) . w(a)
+// (V_jj = w itself when vbase is null: the squared norm, k = 1)
+__global__ void k_msys_dots_partial(int k, const int64_t* __restrict__ xoff, const int64_t* __restrict__ len,
+                                    const int64_t* __restrict__ vbase, const double* __restrict__ V,
+                                    const double* __restrict__ W, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int jj = blockIdx.y, a = blockIdx.z;
+  const int64_t n = len[a];
+  const double* w = W + xoff[a];
+  const double* v = vbase ? V + vbase[a] + (int64_t)jj * n : w;
+  double acc = 0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)MSYS_BLOCKS * 256) acc += v[t] * w[t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[((int64_t)a * k + jj) * MSYS_BLOCKS + blockIdx.x] = red[0];
+}
+__global__ void k_msys_dots_final(const double* __restrict__ partial, int count, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double acc = 0;
+  for (int b = 0; b < MSYS_BLOCKS; ++b) acc += partial[(int64_t)i * MSYS_BLOCKS + b];
+  out[i] = acc;
+}
+
+// w(a) += sign sum_jj h[a k + jj] V_jj(a)
+__global__ void k_msys_gemv(int k, const int64_t* __restrict__ xoff, const int64_t* __restrict__ len,
+                            const int64_t* __restrict__ vbase, const double* __restrict__ V,
+                            const double* __restrict__ h, double sign, double* __restrict__ W) {
+  const int a = blockIdx.y;
+  const int64_t n = len[a];
+  const double* v = V + vbase[a];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int jj = 0; jj < k; ++jj) acc += h[(int64_t)a * k + jj] * v[(int64_t)jj * n + t];
+    W[xoff[a] + t] += sign * acc;
+  }
+}
+
+// V_j(a) = s[a] w(a)
+__global__ void k_msys_scale_copy(int j, const int64_t* __restrict__ xoff, const int64_t* __restrict__ len,
+                                  const int64_t* __restrict__ vbase, const double* __restrict__ sc,
+                                  const double* __restrict__ W, double* __restrict__ V) {
+  const int a = blockIdx.y;
+  const int64_t n = len[a];
+  double* v = V + vbase[a] + (int64_t)j * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    v[t] = sc[a] * W[xoff[a] + t];
+}
+
+static inline int msys_grid_x(int64_t maxlen) {
+  const int64_t b = (maxlen + 255) / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+}
+
+void launch_msys_gather(int nsys, int64_t maxlen, const int64_t* xoff, const int64_t* len, const int64_t* vbase,
+                        const int* active, int j, const double* V, double* win, hipStream_t st) {
+  hipLaunchKernelGGL(k_msys_gather, dim3(msys_grid_x(maxlen), nsys), dim3(256), 0, st, nsys, xoff, len, vbase, active,
+                     j, V, win);
+  KCHECK();
+}
+void launch_msys_dots(int nsys, int k, const int64_t* xoff, const int64_t* len, const int64_t* vbase,
+                      const double* V, const double* W, double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_msys_dots_partial, dim3(MSYS_BLOCKS, k, nsys), dim3(256), 0, st, k, xoff, len, vbase, V, W,
+                     partial);
+  KCHECK();
+  const int cnt = nsys * k;
+  hipLaunchKernelGGL(k_msys_dots_final, dim3((cnt + 255) / 256), dim3(256), 0, st, partial, cnt, out);
+  KCHECK();
+}
+void launch_msys_gemv(int nsys, int64_t maxlen, int k, const int64_t* xoff, const int64_t* len, const int64_t* vbase,
+                      const double* V, const double* h, double sign, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_msys_gemv, dim3(msys_grid_x(maxlen), nsys), dim3(256), 0, st, k, xoff, len, vbase, V, h, sign,
+                     W);
+  KCHECK();
+}
+void launch_msys_scale_copy(int nsys, int64_t maxlen, int j, const int64_t* xoff, const int64_t* len,
+                            const int64_t* vbase, const double* sc, const double* W, double* V, hipStream_t st) {
+  hipLaunchKernelGGL(k_msys_scale_copy, dim3(msys_grid_x(maxlen), nsys), dim3(256), 0, st, j, xoff, len, vbase, sc,
+                     W, V);
+  KCHECK();
+}
+
+// ---- per-surface reductions: surface q owns rows [off[q], off[q+1]) ----
+// out[d][q] = scale[q] * sum_{i in q} x[d][i] (w ? w[i] : 1), one block per
+// (surface, density), fixed summation order
+template <typename T>
+__global__ void k_seg_dot(int nsurf, int64_t N, const int64_t* __restrict__ off, const T* __restrict__ x,
+                          const double* __restrict__ w, const double* __restrict__ scale, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int q = blockIdx.x, d = blockIdx.y;
+  const T* xd = x + (int64_t)d * N;
+  double acc = 0;
+  for (int64_t i = off[q] + threadIdx.x; i < off[q + 1]; i += 256) acc += (double)xd[i] * (w ? w[i] : 1.0);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(int64_t)d * nsurf + q] = red[0] * scale[q];
+}
+// y[d][i] = x[d][i] + alpha (w ? w[i] : 1) c[d][surf[i]]
+template <typename T>
+__global__ void k_seg_axpy(int nd, int nsurf, int64_t N, const int* __restrict__ surf, const T* __restrict__ x,
+                           double alpha, const double* __restrict__ w, const double* __restrict__ c,
+                           T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int q = surf[i];
+  const double f = alpha * (w ? w[i] : 1.0);
+  for (int d = 0; d < nd; ++d)
+    y[(int64_t)d * N + i] = (T)((double)x[(int64_t)d * N + i] + f * c[(int64_t)d * nsurf + q]);
+}
+template <typename T>
+void launch_seg_dot(int nd, int nsurf, int64_t N, const int64_t* off, const T* x, const double* w,
+                    const double* scale, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_dot<T>, dim3(nsurf, nd), dim3(256), 0, st, nsurf, N, off, x, w, scale, out);
+  KCHECK();
+}
+template <typename T>
+void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, double alpha, const double* w,
+                     const double* c, T* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_axpy<T>, dim3((N + 255) / 256), dim3(256), 0, st, nd, nsurf, N, surf, x, alpha, w, c, y);
+  KCHECK();
+}
+
 // explicit instantiations
 #define INST(T)                                                                                                   \
   template void launch_strengths<T>(const T*, int, int64_t, int, int, int, const T*, const T*, const int*,        \
@@ -1885,8 +1892,10 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
                                       const T*, const int*, const T*, T*, T*, int64_t, hipStream_t);             \
   template void launch_combine_a3b<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \
                                       const T*, const T*, int64_t, const T*, const int*, const T*, const double*, \
-                                      double, T*, double*, hipStream_t);                                     \
+                                      int, const int64_t*, const int*, const double*, T*, T*, double*, hipStream_t);                                     \
   template void launch_p2m_tables<T>(const DevTree<T>&, T*, T*, hipStream_t);                                  \
+  template void launch_combine_pot<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*, const T*, \
+                                      const int*, T*, hipStream_t);                                             \
   template void launch_adj_strengths<T>(int, int64_t, const T*, const T*, const T*, const T*, const T*,          \
                                         const int*, T*, T*, hipStream_t);                                       \
   template void launch_adj_combine<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,       \
@@ -1899,8 +1908,11 @@ void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipS
                                      T*, T*, hipStream_t);                                                        \
   template void launch_adj3_comb2<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,         \
                                      const int*, const int64_t*, const int*, const int64_t*, const T*, const T*, \
-                                     const T*, const T*, const double*, T*, hipStream_t);                         \
-  template void launch_colsum<T>(int, int64_t, const T*, double, double*, double*, hipStream_t);
+                                     const T*, const T*, const double*, int, const int*, T*, hipStream_t);                         \
+  template void launch_seg_dot<T>(int, int, int64_t, const int64_t*, const T*, const double*, const double*,     \
+                                  double*, hipStream_t);                                                        \
+  template void launch_seg_axpy<T>(int, int, int64_t, const int*, const T*, double, const double*, const double*, \
+                                   T*, hipStream_t);
 INST(float)
 INST(double)
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);

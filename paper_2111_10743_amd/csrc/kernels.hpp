@@ -42,7 +42,8 @@ struct GemmPlan {
   int ngrp = 0, npair = 0, nbox = 0;
   const int *grp_mat = nullptr, *grp_beg = nullptr;  // [ngrp], [ngrp+1] (triple index)
   const int *pair_src = nullptr;                      // [npair] source box
-  const int *boxes = nullptr, *box_level = nullptr;   // [nbox] target boxes and their levels
+  const int* boxes = nullptr;                         // [nbox] target boxes
+  const double* box_scale = nullptr;                  // [nbox] factor of each target box (scaled plans)
   const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
   const int* work[9] = {nullptr};
   int nwork[9] = {0};
@@ -67,14 +68,16 @@ struct DevTree {
   const int *leaf_src_list;  int n_leaf_src;     // leaves holding sources
   const int *lev_box_src;  const int *lev_box_src_ptr;  // per level: boxes with sources
   const int *lev_box_tgt;  const int *lev_box_tgt_ptr;  // per level: boxes with targets
-  int depth, leaf_off, nbox;
-  int h_lev_src_ptr[24], h_lev_tgt_ptr[24];      // host copies of the level pointers
-  double side;               // root side
+  // leaves, numbered over all trees of the forest (one tree per surface)
+  const int *leaf_box;                           // [leaves] global box id
+  const int *leaf_lvl;                           // [leaves] level (= depth of its tree)
+  const T *leaf_h;                               // [leaves] side
+  int depth, nbox;                               // deepest level of any tree, boxes
   int p, L;                  // expansion order, (p+1)^2
   const T *m2m, *l2l, *m2l;  // transposed [..][in][out]
   const T *dgradT, *dhessT;  // transposed [t][in][out]
   const GemmPlan* m2l_plan;   // host structs with device pointers (nullable):
-  const GemmPlan* m2m_plan;   //   M2L over all levels; M2M and L2L indexed by level
+  const GemmPlan* m2m_plan;   //   M2L over all levels; M2M and L2L indexed by level (all trees)
   const GemmPlan* l2l_plan;
   void* Y;                    // column scratch [max columns * 8][L]
   const T *p2m_H, *p2m_D;     // per-source P2M tables [No][L] in tree order (nullable)
@@ -108,8 +111,9 @@ void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No,
 //     [nd][2][No] (psi_a, psi_b) and the transposed corrections (vals3)
 //   step 2 strengths: charge -b, dipole a n -> str [nd][4][N] (FMM_ADJ),
 //     g2 = (a, b)
-//   step 2 combine: out = -v/4 + (far) + C_S'^T a - C_S^T b + cs_d z,
-//     cs_d = sum_i v_i / area (scal [nd]), z = S^T S^T w
+//   step 2 combine: out = -v/4 + (far) + C_S'^T a - C_S^T b + cs z,
+//     cs = sum over the node's surface of v / its area (scal [nd][nsurf],
+//     node_surf [N]), z = S^T S^T w
 template <typename T>
 void launch_adj3_str1(int nd, int64_t N, const T* v, const T* H, const int* src_pos, T* str, T* g2,
                       hipStream_t st);
@@ -123,14 +127,31 @@ void launch_adj3_comb1(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, 
 template <typename T>
 void launch_adj3_comb2(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* wo,
                        const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow, const int64_t* cblk,
-                       const T* vals3, const T* g2, const T* v, const T* z, const double* scal, T* out,
-                       hipStream_t st);
-// out[d][i] = y[d][i] - w[i] scal[d]  (FP64)
-void launch_sub_wscal(int nd, int64_t N, const double* y, const double* w, const double* scal, double* out,
-                      hipStream_t st);
-// scal[d] = scale * sum_i v[d][i] (deterministic two-level reduction)
+                       const T* vals3, const T* g2, const T* v, const T* z, const double* scal, int nsurf,
+                       const int* node_surf, T* out, hipStream_t st);
+// Several GMRES systems at once (FP64): system a owns the segment
+// [xoff[a], xoff[a] + len[a]) of the operator's vectors and the basis
+// vectors V + vbase[a] + j len[a].  gather: win = V_j(a) (0 where active[a]
+// is 0); dots: out[a k + jj] = V_jj(a) . W(a) (vbase null: W(a) . W(a), k = 1;
+// partial: [nsys k 32]); gemv: W(a) += sign sum_jj h[a k + jj] V_jj(a);
+// scale_copy: V_j(a) = sc[a] W(a).  maxlen = max len (grid size).
+void launch_msys_gather(int nsys, int64_t maxlen, const int64_t* xoff, const int64_t* len, const int64_t* vbase,
+                        const int* active, int j, const double* V, double* win, hipStream_t st);
+void launch_msys_dots(int nsys, int k, const int64_t* xoff, const int64_t* len, const int64_t* vbase,
+                      const double* V, const double* W, double* partial, double* out, hipStream_t st);
+void launch_msys_gemv(int nsys, int64_t maxlen, int k, const int64_t* xoff, const int64_t* len, const int64_t* vbase,
+                      const double* V, const double* h, double sign, double* W, hipStream_t st);
+void launch_msys_scale_copy(int nsys, int64_t maxlen, int j, const int64_t* xoff, const int64_t* len,
+                            const int64_t* vbase, const double* sc, const double* W, double* V, hipStream_t st);
+// Per-surface reductions (surface q owns rows [off[q], off[q+1])):
+// seg_dot: out[d][q] = scale[q] sum_{i in q} x[d][i] (w ? w[i] : 1);
+// seg_axpy: y[d][i] = x[d][i] + alpha (w ? w[i] : 1) c[d][surf[i]].
 template <typename T>
-void launch_colsum(int nd, int64_t N, const T* v, double scale, double* partial, double* scal, hipStream_t st);
+void launch_seg_dot(int nd, int nsurf, int64_t N, const int64_t* off, const T* x, const double* w,
+                    const double* scale, double* out, hipStream_t st);
+template <typename T>
+void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, double alpha, const double* w,
+                     const double* c, T* y, hipStream_t st);
 
 // P2M tables of every source about its leaf centre (setup): H, Dp [No][L]
 // in tree order; see k_p2m_build
@@ -158,17 +179,24 @@ template <typename T>
 void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                          const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
                          const T* nrm, T* pot, T* grad, T* dSdn, T* surf, hipStream_t st);
+// S only: pot = S sigma from the FMM_POT output and the S corrections
+template <typename T>
+void launch_combine_pot(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,
+                        const T* sigma, const T* fmm, const int* tgt_pos, T* pot, hipStream_t st);
 // A3 step 1: tau -> mu1 = S' tau, mu2 = S tau  (density d of mu1/mu2 at offset d*ldmu)
 template <typename T>
 void launch_combine_a3a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                         const T* vals3, const T* tau, const T* fmm, const int* tgt_pos,
                         const T* nrm, T* mu1, T* mu2, int64_t ldmu, hipStream_t st);
-// A3 step 2: out = -tau/4 + S'mu1 - (S''+D')mu2 - 2H S'mu2 + W S mu2
+// A3 step 2: out = -tau/4 + S'mu1 - (S''+D')mu2 - 2H S'mu2 + W S mu2, the
+// last term per surface (surface q: rows [node_off[q], node_off[q+1]),
+// inv_area[q]; node_surf [N]); y2buf [nd][N] and scal [nd][nsurf] scratch
 template <typename T>
 void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                         const T* vals3, const T* tau, const T* mu1, const T* mu2, int64_t ldmu, const T* fmm,
-                        const int* tgt_pos, const T* H, const double* w, double inv_area,
-                        T* out, double* partial, hipStream_t st);
+                        const int* tgt_pos, const T* H, const double* w, int nsurf, const int64_t* node_off,
+                        const int* node_surf, const double* inv_area, T* out, T* y2buf, double* scal,
+                        hipStream_t st);
 
 // FP64 helpers for GMRES
 void launch_dots(const double* V, int64_t ldv, int k, const double* w, int64_t N, double* out,

@@ -197,6 +197,7 @@ void Surface::build_near_lists() {
           auto it = grid.find(key(a, b, c));
           if (it == grid.end()) continue;
           for (int p : it->second) {
+            if (!surf_of_patch.empty() && surf_of_patch[p] != surf_of_patch[self]) continue;
             const double* cc = &cen[3 * p];
             double dx = x[0] - cc[0], dy = x[1] - cc[1], dz = x[2] - cc[2];
             if (p == self || std::sqrt(dx * dx + dy * dy + dz * dz) < eta * R[p]) row.push_back(p);

@@ -34,7 +34,9 @@ struct Surface {
   // patches
   std::vector<double> cen, R;             // [NP][3], [NP]
   double eta = 2.0;
-  // near lists (block CSR rows = targets)
+  // surface of each patch (several independent surfaces; empty = one)
+  std::vector<int> surf_of_patch;
+  // near lists (block CSR rows = targets; only patches of the target's surface)
   std::vector<int64_t> near_ptr;          // [N+1]
   std::vector<int32_t> near_patch;        // [nnz_blocks]
 

@@ -31,7 +31,7 @@ LB_DIRECT = 4
 LB_NO_P2M_TABLES = 8
 LB_HOST_OCTREE = 16
 
-EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_get_sizes", "lb_get_geometry",
+EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj", "lb_destroy",
             "lb_last_error")
@@ -53,7 +53,8 @@ class SolveInfo(ctypes.Structure):
 class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_patches", "n_p", "N", "n_o", "N_o", "nnz_blocks",
                                                "fmm_levels", "fmm_leaves", "p_f32", "p_f64",
-                                               "p2p_pairs32", "m2l_pairs32", "p2p_pairs64", "m2l_pairs64")]
+                                               "p2p_pairs32", "m2l_pairs32", "p2p_pairs64", "m2l_pairs64",
+                                               "n_surf")]
 
 
 class TreeInfo(ctypes.Structure):
@@ -81,10 +82,12 @@ def lib():
         L.lb_default_opts.argtypes = [ctypes.POINTER(Opts)]
         L.lb_ref_nodes.argtypes = [ip, dp, dp]
         L.lb_setup.argtypes = [ctypes.POINTER(vp), ip, ip, dp, dp, dp, ctypes.POINTER(Opts), vp]
+        L.lb_setup_batch.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ctypes.c_int32), ip, dp, dp, dp,
+                                     ctypes.POINTER(Opts), vp]
         L.lb_get_sizes.argtypes = [vp, ctypes.POINTER(Sizes)]
         L.lb_get_geometry.argtypes = [vp, dp, dp, dp]
         L.lb_get_corrections.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp]
-        L.lb_get_tree.argtypes = [vp, ip, ip, ctypes.POINTER(TreeInfo)] + [vp] * 9
+        L.lb_get_tree.argtypes = [vp, ip, ip, ip, ctypes.POINTER(TreeInfo)] + [vp] * 9
         L.lb_tree_build.argtypes = [ctypes.POINTER(vp), dp, ctypes.c_int64, dp, ctypes.c_int64, ip,
                                     ctypes.c_double, ip, ip]
         L.lb_tree_get.argtypes = [vp, ctypes.POINTER(TreeInfo)] + [vp] * 9
@@ -175,7 +178,9 @@ class Surface:
     """One discretized surface: lb_setup ... lb_destroy."""
 
     def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, p2m_tables=True,
-                 host_octree=False, **kw):
+                 host_octree=False, patches_per_surf=None, **kw):
+        """One surface, or with patches_per_surf several independent surfaces
+        (their patches one after the other in X, Xu, Xv; lb_setup_batch)."""
         X = np.ascontiguousarray(X, dtype=np.float64)
         Xu = np.ascontiguousarray(Xu, dtype=np.float64)
         Xv = np.ascontiguousarray(Xv, dtype=np.float64)
@@ -194,12 +199,21 @@ class Surface:
         self.host_only = host_only
         self._ctx = ctypes.c_void_p()
         stream = None if host_only else _stream()
-        _check(lib().lb_setup(ctypes.byref(self._ctx), X.shape[0], order, _dp(X), _dp(Xu), _dp(Xv),
-                              ctypes.byref(o), stream))
+        if patches_per_surf is None:
+            _check(lib().lb_setup(ctypes.byref(self._ctx), X.shape[0], order, _dp(X), _dp(Xu), _dp(Xv),
+                                  ctypes.byref(o), stream))
+        else:
+            pps = np.ascontiguousarray(patches_per_surf, dtype=np.int32)
+            if int(pps.sum()) != X.shape[0]:
+                raise ValueError("patches_per_surf must add up to the number of patches")
+            _check(lib().lb_setup_batch(ctypes.byref(self._ctx), len(pps),
+                                        pps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), order, _dp(X), _dp(Xu),
+                                        _dp(Xv), ctypes.byref(o), stream))
         s = Sizes()
         _check(lib().lb_get_sizes(self._ctx, ctypes.byref(s)))
         self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
         self.N = s.N
+        self.n_surf = s.n_surf
 
     def close(self):
         if self._ctx:
@@ -228,10 +242,13 @@ class Surface:
                                         patch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(vals)))
         return ptr, patch, vals
 
-    def tree(self, prec=32, transposed=False):
-        """The FMM octree (see lb_get_tree in include/lb.h) as numpy arrays."""
-        nt, ns = (self.sizes["N_o"], self.N) if transposed else (self.N, self.sizes["N_o"])
-        return _tree_arrays(lambda *a: lib().lb_get_tree(self._ctx, prec, int(transposed), *a), nt, ns)
+    def tree(self, prec=32, transposed=False, surf=0, counts=None):
+        """The FMM octree of one surface (see lb_get_tree in include/lb.h) as
+        numpy arrays; counts = (nodes, oversampled points) of that surface
+        (default: the whole context, right for one surface)."""
+        nn, no = counts if counts is not None else (self.N, self.sizes["N_o"])
+        nt, ns = (no, nn) if transposed else (nn, no)
+        return _tree_arrays(lambda *a: lib().lb_get_tree(self._ctx, prec, int(transposed), surf, *a), nt, ns)
 
     # -- device calls (torch tensors) --------------------------------------
     @staticmethod
@@ -330,7 +347,7 @@ class Surface:
             raise TypeError("ubar must be float64")
         nrhs = self._nd(ubar)
         fbar = torch.empty_like(ubar)
-        info = (SolveInfo * nrhs)()
+        info = (SolveInfo * (nrhs * self.n_surf))()
         code = _check(lib().lb_solve_adj(self._ctx, nrhs, _ptr(ubar), _ptr(fbar), tol, mode, info, _stream()))
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
                   "removed_mean": i.removed_mean} for i in info]
@@ -342,7 +359,7 @@ class Surface:
             raise TypeError("f must be float64")
         nrhs = self._nd(f)
         u = torch.empty_like(f)
-        info = (SolveInfo * nrhs)()
+        info = (SolveInfo * (nrhs * self.n_surf))()
         code = _check(lib().lb_solve(self._ctx, nrhs, _ptr(f), _ptr(u), tol, mode, info, _stream()))
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
                   "removed_mean": i.removed_mean} for i in info]
