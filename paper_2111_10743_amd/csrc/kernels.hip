@@ -723,7 +723,18 @@ __device__ void derive3(const T* src, int pin, T* dx, T* dy, T* dz) {
   }
 }
 
-constexpr int LEAF_BS = 256;
+// leaf kernel shape (compile-time; -D overrides for tuning sweeps)
+#ifndef LB_LEAF_BS
+#define LB_LEAF_BS 256
+#endif
+#ifndef LB_LEAF_CH
+#define LB_LEAF_CH 512
+#endif
+#ifndef LB_LEAF_UNROLL
+#define LB_LEAF_UNROLL (sizeof(T) == 4 ? 8 : 4)
+#endif
+constexpr int LEAF_BS = LB_LEAF_BS;            // threads per block
+constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
 constexpr int LEAF_FMAX = 64;                  // at most one wave per target
 
 // Each target of a leaf gets F = min(64, 256 / targets) threads (a power of
@@ -750,7 +761,6 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   // expansions for L2P: local [nexp][L], derived gradient [nexp][3][Lg] and
   // hessian [6][Lh] (+ 3 [Lh] scratch; A3B: expansion 1), in LDS after the
   // source chunk when EXP_LDS, else in this block's slice of D
-  constexpr int LEAF_CH = 512;                     // sources per LDS chunk
   constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ || MODE == FMM_ADJ3 ? 9 : 5;  // T values per source record
   T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
   const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
@@ -949,7 +959,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       __syncthreads();
       if (act) {
         T q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-#pragma unroll 4
+#pragma unroll LB_LEAF_UNROLL
         for (int jj = f; jj < ns; jj += F) {
           const T4 r1 = rec1[jj];
           // the mask radius of the pair: the source's, or the target's in FMM_ADJ
@@ -1068,7 +1078,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   }
   tm->mark(PH_LEAF, st);
   const int nexp = fmm_nexp(mode);
-  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * 512;
+  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
   const size_t exps = sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
   const bool lds = chunk + exps <= 64 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
