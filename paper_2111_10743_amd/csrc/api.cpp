@@ -111,6 +111,24 @@ static void upload_as(DBuf& d, const std::vector<S>& h) {
   upload(d, c);
 }
 
+// An operator application v -> w captured once as a HIP graph and replayed
+// (valid for the captured buffers and density count).
+struct OpGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* in = nullptr;
+  const void* out = nullptr;
+  int n = 0;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    in = out = nullptr;
+    n = 0;
+  }
+};
+
 // Everything one precision of the apply needs on the device.
 template <typename T>
 struct Prec {
@@ -173,6 +191,14 @@ struct lb_ctx {
   // surface of every node, 1/area per surface; scratch for per-surface sums
   std::vector<int64_t> node_off_h;
   DBuf node_off, node_surf, inv_area, seg_scal;
+  // GMRES operators replayed from captured HIP graphs (A3 and A3^T, FP64
+  // and FP32), captured on the library's own stream
+  hipStream_t cap_stream = nullptr;
+  lb::OpGraph gA64, gA32, gT64, gT32;
+  ~lb_ctx() {
+    gA64.reset(); gA32.reset(); gT64.reset(); gT32.reset();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace lb {
@@ -728,6 +754,35 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
                          dptr<double>(ctx->a3t_scal), ctx->n_surf, dptr<int>(ctx->node_surf), out + (int64_t)d0 * N,
                          st);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Apply `body` (kernel launches only, on the stream it is given) to in -> out
+// through a captured HIP graph.  A call with new buffers or a new density
+// count runs the body eagerly on `st` (which also makes every allocation
+// the body needs), then captures it on the library's stream for the
+// following calls; LB_NO_GRAPH runs it eagerly always.
+// ---------------------------------------------------------------------------
+template <typename Body>
+static void graphed(lb_ctx* ctx, OpGraph& G, Body&& body, const void* in, const void* out, int n, hipStream_t st) {
+  if (ctx->opts.flags & LB_NO_GRAPH) {
+    body(st);
+    return;
+  }
+  if (G.exec && G.in == in && G.out == out && G.n == n) {
+    HIPTRY(hipGraphLaunch(G.exec, st));
+    return;
+  }
+  G.reset();
+  body(st);
+  if (!ctx->cap_stream) HIPTRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  HIPTRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  body(ctx->cap_stream);
+  HIPTRY(hipStreamEndCapture(ctx->cap_stream, &G.graph));
+  HIPTRY(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+  G.in = in;
+  G.out = out;
+  G.n = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -1430,13 +1485,17 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   double* fz = dptr<double>(ctx->ftmp);
   double* ut = dptr<double>(ctx->utmp);
   double* dcorr = ut + nN;
-  auto A64 = [&](const double* v, double* w, int na) { apply_A3_t<double>(ctx, ctx->f64, na, v, w, st); };
+  auto A64 = [&](const double* v, double* w, int na) {
+    graphed(ctx, ctx->gA64, [&](hipStream_t s2) { apply_A3_t<double>(ctx, ctx->f64, na, v, w, s2); }, v, w, na, st);
+  };
   auto A32 = [&](const double* v, double* w, int na) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
     float* vo = dptr<float>(ctx->f32.tmp_out);
-    launch_convert<double, float>(v, vi, (int64_t)na * N, st);
-    apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, st);
-    launch_convert<float, double>(vo, w, (int64_t)na * N, st);
+    graphed(ctx, ctx->gA32, [&](hipStream_t s2) {
+      launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
+      apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, s2);
+      launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
+    }, v, w, na, st);
   };
   // mean projection per surface (Lemma 1): fz = f - (sum_q w f / area_q) on surface q
   DBuf means;
@@ -1504,14 +1563,18 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
   double* ut = dptr<double>(ctx->utmp);
   double* dcorr = ut + nN;
   auto A64 = [&](const double* v, double* w, int na) {
-    apply_A3T_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, ctx->z64, ctx->z_built64, na, v, w, st);
+    graphed(ctx, ctx->gT64, [&](hipStream_t s2) {
+      apply_A3T_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, ctx->z64, ctx->z_built64, na, v, w, s2);
+    }, v, w, na, st);
   };
   auto A32 = [&](const double* v, double* w, int na) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
     float* vo = dptr<float>(ctx->f32.tmp_out);
-    launch_convert<double, float>(v, vi, (int64_t)na * N, st);
-    apply_A3T_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, ctx->z32, ctx->z_built32, na, vi, vo, st);
-    launch_convert<float, double>(vo, w, (int64_t)na * N, st);
+    graphed(ctx, ctx->gT32, [&](hipStream_t s2) {
+      launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
+      apply_A3T_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, ctx->z32, ctx->z_built32, na, vi, vo, s2);
+      launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
+    }, v, w, na, st);
   };
   // rhs = S^T S^T ubar (adjoint of u = S[S[sigma]])
   apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nrhs, ubar, nullptr, nullptr, nullptr, ut, st);

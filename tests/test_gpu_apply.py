@@ -199,3 +199,32 @@ def test_c1_solve_multi_rhs(torch_dev, c1_oracle, mode):
         assert e < 1e-9
     assert abs(info[3]["removed_mean"]) > 0.1
     s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_solve_graph_replay_matches_eager(torch_dev, mode):
+    """GMRES replays a captured HIP graph of the operator (A3, A3^T) between
+    its own eager dot products and host round trips; every replay must give
+    what plain launches give, so the solves agree bit for bit."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.ellipsoid_patches(2, nodes(6), (1.0, 1.5, 2.0))
+    note(f"graph replay mode={mode} setup")
+    a = P.Surface(X, Xu, Xv, 6)
+    b = P.Surface(X, Xu, Xv, 6, graphs=False)
+    xi = I.sphere_preimage(X.reshape(-1, 3), (1.0, 1.5, 2.0))
+    f = torch.tensor(np.stack([I.sh_series(I.random_sh_coeffs(5, seed=s, decay=2.0), xi) for s in (11, 12)]),
+                     device="cuda")
+    for rep in range(2):  # the second solve replays graphs captured by the first
+        ua, ia, ca = a.solve(f, tol=1e-10, mode=mode)
+        ub, ib, cb = b.solve(f, tol=1e-10, mode=mode)
+        note(f"rep {rep}: iters graph {[i['iters'] for i in ia]} eager {[i['iters'] for i in ib]}")
+        assert ca == cb == 0
+        assert [i["iters"] for i in ia] == [i["iters"] for i in ib]
+        assert torch.equal(ua, ub)
+        fa, _, _ = a.solve_adj(f, tol=1e-10, mode=mode)
+        fb, _, _ = b.solve_adj(f, tol=1e-10, mode=mode)
+        assert torch.equal(fa, fb)
+    a.close()
+    b.close()
