@@ -9,8 +9,9 @@ sphere pre-image.  Synthetic inputs, resident in HBM before timing.
 
 One "step" is one lb_apply_gradS in FP32 (density oversampling, FMM, near
 field, corrections, combination): value = N / step time in Mpoints/s.
-The JSON line also carries the FP64 apply rate, the solve times (with
---solve), the dominant kernel against its roofline (HIP events on the
+The JSON line also carries the FP64 apply rate, the solve times (unless
+--no-solve; each mode solved once untimed first, so that allocations and
+graph capture are not timed), the dominant kernel against its roofline (HIP events on the
 library's stream) and the FP64 oracle timed on a bounded sample on the
 host cores.
 """
@@ -71,13 +72,33 @@ def cpu_baseline(X, Xu, Xv, k, f, nrows):
                       f"+ near corrections (correction generation excluded), {dt:.2f} s"}
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter
+    summary (profiles/<kernel>_traffic.txt: FETCH_SIZE and WRITE_SIZE KiB per
+    dispatch and their copy-kernel scale factors), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = open(os.path.join(ROOT, "paper_2111_10743_amd", "csrc", "kernels.hip"), "rb").read()
+    if kv.get("kernels_hip_sha1") != hashlib.sha1(src).hexdigest():
+        return None
+    return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ellipsoid5120")
-    ap.add_argument("--solve", action="store_true", help="also time the FP64 and FP32+refine solves")
+    ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and FP32+refine solves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -158,8 +179,10 @@ def main():
         flops = 20.0 * sz["p2p_pairs32"]
         ach = flops / (ph["leaf"] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_leaf (L2P + near field, FP32)",
-                "algorithmic": f"20 flops per near-field pair, {sz['p2p_pairs32']} pairs"}
+                "frac": ach / PEAK_FP32_TFLOPS, "traffic": measured_traffic(f"leaf_fp32_{args.workload}"),
+                "kernel": "k_leaf<float, FMM_GRAD> (L2P + near field, FP32)",
+                "algorithmic": f"20 flops per near-field pair, {sz['p2p_pairs32']} pairs per launch",
+                "ms_per_launch": ph["leaf"]}
     else:
         nnz = sz["nnz_blocks"] * sz["n_p"]
         byts = nnz * 4 * 4 + sz["nnz_blocks"] * 4 + (N + 1) * 8 + nnz * 4 + N * 4 * (1 + 3 + 4)
@@ -178,11 +201,12 @@ def main():
         "phases_ms_fp32": ph,
         "roofline": roof,
     }
-    if args.solve:
+    if not args.no_solve:
         fz = torch.tensor(f, dtype=torch.float64, device="cuda")
         res = {}
         us = {}
         for name, mode in (("fp64", P.LB_SOLVE_FP64), ("fp32_refine", P.LB_SOLVE_FP32_REFINE)):
+            s.solve(fz, tol=1e-9, mode=mode)  # untimed: workspace allocation and graph capture
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             u, info, code = s.solve(fz, tol=1e-9, mode=mode)
