@@ -165,6 +165,37 @@ class Oracle:
             out += M[0].T @ gpot
         return out
 
+    def position_vjp_S(self, sigma, gbar, patches=None):
+        """Derivative of <gbar, S sigma> with respect to the node positions X.
+
+        Reading of the kernel-position derivative: in the discrete S of
+        eq. (nys-lcq2) the targets are the nodes x_i = X_i and the far-rule
+        points move with the chart, s_m = (P X)_m (Section 4); the weights
+        w^over, the oversampled density P sigma and the corrections are held
+        fixed.  With c = w^over P sigma, phi(x) = sum_m c_m G(x - s_m) and
+        psi(y) = sum_i gbar_i G(x_i - y):
+            X_bar_j = gbar_j grad phi(x_j) + sum_{m in patch(j)} P_{m,k(j)} c_m grad psi(s_m).
+        sigma, gbar: (N,) or (nd, N), summed over the densities.  Returns
+        (len(patches) * n_p, 3) for the nodes of `patches` (default: all).
+        """
+        g = self.g
+        sig = np.atleast_2d(np.asarray(sigma, dtype=float))
+        gb = np.atleast_2d(np.asarray(gbar, dtype=float))
+        pts = np.arange(g.NP) if patches is None else np.asarray(patches)
+        nodes = (pts[:, None] * g.n_p + np.arange(g.n_p)[None, :]).reshape(-1)
+        over = (pts[:, None] * g.n_o + np.arange(g.n_o)[None, :]).reshape(-1)
+        c = np.stack([self.oversample(t) for t in sig])
+        zn = np.zeros((len(nodes), 3))
+        zo = np.zeros((len(over), 3))
+        # grad phi at the nodes (far sum over every oversampled point)
+        _, gphi, _ = direct(g.x[nodes], zn, g.s, np.zeros_like(g.s), c)
+        # grad psi at the oversampled points (charges gbar on every node)
+        _, gpsi, _ = direct(g.s[over], zo, g.x, np.zeros_like(g.x), gb)
+        out = (gb[:, nodes, None] * gphi).sum(0)
+        sbar = (c[:, over, None] * gpsi).sum(0).reshape(len(pts), g.n_o, 3)
+        out += np.einsum('mk,pmc->pkc', g.re.P, sbar).reshape(-1, 3)
+        return out
+
     def A3_matrix(self):
         """Dense A3 of Section 4.3 from the operator matrices (all rows, small N):
         -I/4 + S' S' - (S''+D') S - 2 diag(H) S' S + (1/area) 1 w^T S S."""

@@ -193,3 +193,42 @@ def test_A3_matrix_and_solve_adjoint(c1_oracle):
     assert abs(lhs - rhs) < 1e-10 * np.linalg.norm(ub) * np.linalg.norm(u) * 10
     # the transposed projection removes exactly the weighted constant direction
     assert abs(np.ones(g.N) @ fb) < 1e-9 * np.abs(fb).sum()
+
+
+def test_position_vjp_S(c1_oracle):
+    """Kernel-position derivative of <gbar, S sigma> (nodes and far-rule points
+    moving with X, weights, oversampled density and corrections fixed):
+    central differences of the far sum written out here, invariance of that
+    sum under translations (sum_j X_bar_j = 0; the interpolation reproduces
+    constants, so s = P X translates with X) and rotations
+    (sum_j x_j x X_bar_j = 0), and the per-patch evaluation."""
+    o = c1_oracle
+    g = o.g
+    rng = np.random.default_rng(31)
+    sig = rng.standard_normal((2, g.N))
+    gb = rng.standard_normal((2, g.N))
+    Xb = o.position_vjp_S(sig, gb)
+    assert Xb.shape == (g.N, 3)
+    scale = np.abs(Xb).sum()
+    assert np.abs(Xb.sum(0)).max() < 1e-11 * scale
+    assert np.abs(np.cross(g.x, Xb).sum(0)).max() < 1e-11 * scale
+    c = np.stack([o.oversample(t) for t in sig])
+
+    def far(Xp):
+        x = Xp.reshape(-1, 3)
+        s = np.einsum('mb,pbc->pmc', g.re.P, Xp).reshape(-1, 3)
+        r = np.linalg.norm(x[:, None, :] - s[None, :, :], axis=-1)
+        return float((gb * (c @ (1.0 / (4.0 * np.pi * r)).T)).sum())
+    for sel in (None, 7):
+        dX = rng.standard_normal(g.Xp.shape)
+        if sel is not None:  # one patch moving alone
+            keep = np.zeros(g.NP, bool)
+            keep[sel] = True
+            dX[~keep] = 0.0
+        h = 1e-6
+        fd = (far(g.Xp + h * dX) - far(g.Xp - h * dX)) / (2 * h)
+        an = float((Xb * dX.reshape(-1, 3)).sum())
+        assert abs(fd - an) < 1e-6 * abs(an), (fd, an)
+    sub = o.position_vjp_S(sig, gb, patches=[3, 17])
+    rows = np.concatenate([np.arange(3 * g.n_p, 4 * g.n_p), np.arange(17 * g.n_p, 18 * g.n_p)])
+    assert np.allclose(sub, Xb[rows], rtol=0, atol=1e-13 * np.abs(Xb).max())
