@@ -232,6 +232,24 @@ lb_status lb_apply_gradS_adj(lb_ctx *ctx, int nd, int prec, const void *gpot,
 lb_status lb_apply_S_adj(lb_ctx *ctx, int nd, int prec, const void *gbar, void *sigma_bar,
                          void *stream);
 
+/* Derivative of lb_apply_S with respect to the node positions X (the
+ * gradient kernel): X_bar = d/dX sum_d <gbar_d, S sigma_d>, with the targets
+ * x_i = X_i and the oversampled points s = P X of Section 4 moving with the
+ * nodes, and the weights w^over, the oversampled density P sigma and the
+ * near corrections held at their setup values (the kernel-position
+ * derivative; a full shape derivative would also differentiate the
+ * corrections).  With c = w^over P sigma:
+ *   X_bar_j = sum_d [ gbar_dj grad phi_d(x_j)
+ *                     + sum_{m in patch(j)} P_{m,k(j)} c_dm grad psi_d(s_m) ],
+ *   phi_d(x) = sum_m c_dm G(x - s_m),  psi_d(y) = sum_i gbar_di G(x_i - y),
+ * both sums over every pair but coincident points (no near mask), through
+ * two gradient FMMs (forward and transposed trees).  sigma, gbar: device
+ * [nd][N]; X_bar: device [N][3], overwritten; dtype by prec.  The first call
+ * for a precision builds the transposed octree (as lb_apply_gradS_adj) and
+ * synchronizes the device. */
+lb_status lb_apply_S_adj_X(lb_ctx *ctx, int nd, int prec, const void *sigma, const void *gbar,
+                           void *X_bar, void *stream);
+
 /* lb_apply_gradS with per-phase timing (nd <= 8): HIP events recorded on
  * `stream` around each phase of the apply; synchronizes `stream`.
  * phase_ms: host [7], milliseconds of: density oversampling, P2M, M2M, M2L,

@@ -150,6 +150,9 @@ struct Prec {
   // work
   DBuf str, M, Lc, D, fmm, mu, y2, tmp_in, tmp_out;
   int ws_rhs = 0;
+  // position derivative: mask radii that exclude only coincident points
+  // (forward tree) and gradient outputs at the targets (transposed tree)
+  DBuf rm2_none, fmm4;
 };
 
 }  // namespace lb
@@ -696,6 +699,43 @@ static void apply_adj_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int nd
     launch_adj_combine<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
                           dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
                           dptr<int64_t>(ctx->cblk), dptr<T>(F.vals4), dptr<T>(ctx->g4), sbar + (int64_t)d0 * N, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-position derivative of S: X_bar = d<gbar, S sigma>/dX with the nodes
+// and the far-rule points s = P X moving, weights, oversampled density and
+// corrections fixed.  Two gradient FMMs without the near mask: grad phi at
+// the nodes (forward tree, strengths w^over P sigma) and grad psi at the
+// oversampled points (transposed tree, charges gbar at the nodes).
+// ---------------------------------------------------------------------------
+template <typename T>
+static void apply_S_xbar_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int nd, const T* sigma, const T* gbar,
+                           T* xbar, hipStream_t st) {
+  ensure_ws(ctx, F, CHUNK_GRAD);
+  ensure_adjoint<T>(ctx, F, A, built);
+  const int64_t N = ctx->N, No = ctx->No;
+  if (!F.rm2_none.p) {
+    upload(F.rm2_none, std::vector<T>((size_t)No, std::numeric_limits<T>::min()));
+    A.fmm4.alloc(sizeof(T) * (size_t)No * 4 * CHUNK_GRAD);
+  }
+  DevTree<T> Fu = F.dt;
+  Fu.rm2 = dptr<T>(F.rm2_none);
+  HIPTRY(hipMemsetAsync(xbar, 0, sizeof(T) * 3 * (size_t)N, st));
+  for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
+    const int c = std::min(CHUNK_GRAD, nd - d0);
+    const T* sd = sigma + (int64_t)d0 * N;
+    const T* gd = gbar + (int64_t)d0 * N;
+    launch_strengths<T>(sd, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(F.P), dptr<T>(F.wo), dptr<int>(F.src_pos), No,
+                        dptr<T>(F.str), st);
+    launch_fmm<T>(Fu, FMM_GRAD, c, dptr<T>(F.str), dptr<T>(F.M), dptr<T>(F.Lc), dptr<T>(F.D), dptr<T>(F.fmm), N, No,
+                  st);
+    // transposed tree: targets are the No oversampled points, sources the N nodes
+    launch_scatter_perm<T>(c, N, gd, dptr<int>(A.src_pos), dptr<T>(A.str), st);
+    launch_fmm<T>(A.dt, FMM_GRAD, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm4), No,
+                  N, st);
+    launch_xbar_S<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.str), dptr<int>(F.src_pos),
+                     dptr<T>(F.fmm), dptr<int>(F.tgt_pos), gd, dptr<T>(A.fmm4), dptr<int>(A.tgt_pos), xbar, st);
   }
 }
 
@@ -1299,6 +1339,22 @@ lb_status lb_apply_S_adj(lb_ctx* ctx, int nd, int prec, const void* gbar, void* 
     return LB_EINVAL;
   }
   return lb_apply_gradS_adj(ctx, nd, prec, gbar, nullptr, nullptr, nullptr, sigma_bar, stream);
+}
+
+lb_status lb_apply_S_adj_X(lb_ctx* ctx, int nd, int prec, const void* sigma, const void* gbar, void* X_bar,
+                          void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!sigma || !gbar || !X_bar) fail(LB_EINVAL, "null sigma, gbar or X_bar");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_S_xbar_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, nd, (const float*)sigma, (const float*)gbar,
+                          (float*)X_bar, st);
+  else
+    apply_S_xbar_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nd, (const double*)sigma,
+                           (const double*)gbar, (double*)X_bar, st);
+  HIPTRY(hipGetLastError());
+  API_END
 }
 
 lb_status lb_apply_A3_adj(lb_ctx* ctx, int nd, int prec, const void* v, void* out, void* stream) {

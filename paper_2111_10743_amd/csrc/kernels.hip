@@ -1506,6 +1506,83 @@ void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No,
   KCHECK();
 }
 
+// ---- kernel-position derivative of S (see kernels.hpp) ----
+template <typename T>
+__global__ void k_scatter_perm(int64_t n, const T* __restrict__ in, const int* __restrict__ pos,
+                               T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t d = blockIdx.y;
+  out[d * n + pos[i]] = in[d * n + i];
+}
+
+template <typename T>
+void launch_scatter_perm(int nd, int64_t n, const T* in, const int* pos, T* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_perm<T>, dim3((unsigned)((n + 255) / 256), nd), dim3(256), 0, st, n, in, pos, out);
+  KCHECK();
+}
+
+// One 64-thread block per patch: the source part c_m grad psi(s_m) of the
+// patch's oversampled points goes to LDS (summed over the densities), then
+// node k of the patch adds gbar grad phi at the node and sum_m P_mk of it.
+template <typename T>
+__global__ __launch_bounds__(64) void k_xbar_S(int nd, int n_p, int n_o, int64_t N, int64_t No,
+                                               const T* __restrict__ P, const T* __restrict__ str,
+                                               const int* __restrict__ src_pos, const T* __restrict__ gphi,
+                                               const int* __restrict__ tgt_pos, const T* __restrict__ gbar,
+                                               const T* __restrict__ gpsi, const int* __restrict__ atgt_pos,
+                                               T* __restrict__ xbar) {
+  extern __shared__ unsigned char smraw[];
+  double* sb = reinterpret_cast<double*>(smraw);  // [n_o][3]
+  const int64_t l = blockIdx.x;
+  for (int m = threadIdx.x; m < n_o; m += blockDim.x) {
+    const int64_t om = l * n_o + m;
+    const int64_t sp = src_pos[om], ap = atgt_pos[om];
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int d = 0; d < nd; ++d) {
+      const double c = (double)str[(int64_t)d * No + sp];
+      const T* g = gpsi + (int64_t)d * 4 * No;
+      a0 += c * (double)g[No + ap];
+      a1 += c * (double)g[2 * No + ap];
+      a2 += c * (double)g[3 * No + ap];
+    }
+    sb[3 * m] = a0;
+    sb[3 * m + 1] = a1;
+    sb[3 * m + 2] = a2;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_p; k += blockDim.x) {
+    const int64_t j = l * n_p + k;
+    const int64_t tp = tgt_pos[j];
+    double x0 = 0, x1 = 0, x2 = 0;
+    for (int d = 0; d < nd; ++d) {
+      const double gb = (double)gbar[(int64_t)d * N + j];
+      const T* g = gphi + (int64_t)d * 4 * N;
+      x0 += gb * (double)g[N + tp];
+      x1 += gb * (double)g[2 * N + tp];
+      x2 += gb * (double)g[3 * N + tp];
+    }
+    for (int m = 0; m < n_o; ++m) {
+      const double pm = (double)P[(int64_t)m * n_p + k];
+      x0 += pm * sb[3 * m];
+      x1 += pm * sb[3 * m + 1];
+      x2 += pm * sb[3 * m + 2];
+    }
+    xbar[3 * j] += (T)(x0 * INV4PI_D);
+    xbar[3 * j + 1] += (T)(x1 * INV4PI_D);
+    xbar[3 * j + 2] += (T)(x2 * INV4PI_D);
+  }
+}
+
+template <typename T>
+void launch_xbar_S(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* str,
+                   const int* src_pos, const T* gphi, const int* tgt_pos, const T* gbar, const T* gpsi,
+                   const int* atgt_pos, T* xbar, hipStream_t st) {
+  hipLaunchKernelGGL(k_xbar_S<T>, dim3(NP), dim3(64), sizeof(double) * 3 * n_o, st, nd, n_p, n_o, N, No, P, str,
+                     src_pos, gphi, tgt_pos, gbar, gpsi, atgt_pos, xbar);
+  KCHECK();
+}
+
 // ---- transposed A3 (see kernels.hpp) ----
 template <typename T>
 __global__ void k_adj3_str1(int nd, int64_t N, const T* __restrict__ v, const T* __restrict__ H,
@@ -1911,6 +1988,9 @@ void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, 
   template void launch_adj_combine<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,       \
                                       const int*, const int64_t*, const int*, const int64_t*, const T*, const T*, \
                                       T*, hipStream_t);                                                           \
+  template void launch_scatter_perm<T>(int, int64_t, const T*, const int*, T*, hipStream_t);                    \
+  template void launch_xbar_S<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const int*, const T*, \
+                                 const int*, const T*, const T*, const int*, T*, hipStream_t);                  \
   template void launch_adj3_str1<T>(int, int64_t, const T*, const T*, const int*, T*, T*, hipStream_t);          \
   template void launch_adj3_str2<T>(int, int64_t, const T*, const T*, const T*, const int*, T*, T*, hipStream_t); \
   template void launch_adj3_comb1<T>(int, int, int, int, int64_t, int64_t, const T*, const T*, const T*,         \

@@ -104,6 +104,20 @@ void launch_adj_combine(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No,
                         const T* psi, const int* tgt_pos, const int64_t* cptr, const int* crow,
                         const int64_t* cblk, const T* vals4, const T* g4, T* sigma_bar, hipStream_t st);
 
+// Kernel-position derivative of S (node positions X; the far-rule points
+// s = P X move with them; weights, oversampled density and corrections fixed):
+//   X_bar_j += sum_d [gbar_dj grad phi_d(x_j) + sum_{m in patch(j)} P_mk c_dm grad psi_d(s_m)] / (4 pi)
+// with grad phi [nd][4][N] (FMM_GRAD output of the forward tree, strengths
+// c = str [nd][No]) and grad psi [nd][4][No] (FMM_GRAD output of the
+// transposed tree for charges gbar at the nodes).
+// scatter: out[d][pos[i]] = in[d][i], d < nd, i < n.
+template <typename T>
+void launch_scatter_perm(int nd, int64_t n, const T* in, const int* pos, T* out, hipStream_t st);
+template <typename T>
+void launch_xbar_S(int nd, int NP, int n_p, int n_o, int64_t N, int64_t No, const T* P, const T* str,
+                   const int* src_pos, const T* gphi, const int* tgt_pos, const T* gbar, const T* gpsi,
+                   const int* atgt_pos, T* xbar, hipStream_t st);
+
 // Transposed A3 (adjoint of lb_apply_A3), on the transposed tree:
 //   step 1 strengths from v [nd][N]: (v, 2 H v) -> str [nd][2][N] at src_pos
 //     and g2 [nd][N][2] (user order)

@@ -33,7 +33,7 @@ LB_HOST_OCTREE = 16
 LB_NO_GRAPH = 32
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
-            "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj",
+            "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj", "lb_destroy",
             "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
@@ -97,6 +97,7 @@ def lib():
         L.lb_apply_gradS.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.lb_apply_gradS_adj.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.lb_apply_S_adj.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_apply_S_adj_X.argtypes = [vp, ip, ip, vp, vp, vp, vp]
         L.lb_apply_gradS_timed.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, dp, vp]
         L.lb_apply_A3.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
@@ -298,6 +299,19 @@ class Surface:
         _check(lib().lb_apply_S_adj(self._ctx, nd, self._prec(gbar), _ptr(gbar), _ptr(res), _stream()))
         return res
 
+    def apply_S_adj_X(self, sigma, gbar):
+        """X_bar [N, 3] = d/dX sum_d <gbar_d, S sigma_d>: the kernel-position
+        derivative (nodes and far-rule points move with X; weights, P sigma and
+        the near corrections fixed), summed over the densities."""
+        import torch
+        if sigma.shape != gbar.shape or sigma.dtype != gbar.dtype:
+            raise ValueError("sigma and gbar must have the same shape and dtype")
+        nd = self._nd(sigma)
+        xbar = torch.empty((self.N, 3), dtype=sigma.dtype, device=sigma.device)
+        _check(lib().lb_apply_S_adj_X(self._ctx, nd, self._prec(sigma), _ptr(sigma), _ptr(gbar), _ptr(xbar),
+                                      _stream()))
+        return xbar
+
     def apply_gradS_adj(self, gpot=None, ggrad=None, gdSdn=None, gsurf=None):
         """sigma_bar = S^T gpot + (grad S)^T ggrad + S'^T gdSdn + (grad_Gamma S)^T gsurf."""
         import torch
@@ -374,16 +388,29 @@ def _autograd():
     import torch
 
     class ApplyS(torch.autograd.Function):
-        """pot = S[sigma]; backward: sigma_bar = S^T pot_bar (lb_apply_S_adj)."""
+        """pot = S[sigma]; backward: sigma_bar = S^T pot_bar (lb_apply_S_adj)
+        and, when the node positions X are an input, X_bar from
+        lb_apply_S_adj_X (the kernel-position derivative)."""
 
         @staticmethod
-        def forward(ctx, surf, sigma):
+        def forward(ctx, surf, sigma, X):
             ctx.surf = surf
-            return surf.apply_S(sigma.contiguous())
+            ctx.has_x = X is not None
+            ctx.x_dtype = X.dtype if X is not None else None
+            sigma = sigma.contiguous()
+            if X is not None:
+                ctx.save_for_backward(sigma)
+            return surf.apply_S(sigma)
 
         @staticmethod
         def backward(ctx, gout):
-            return None, ctx.surf.apply_S_adj(gout.contiguous())
+            gout = gout.contiguous()
+            gs = ctx.surf.apply_S_adj(gout) if ctx.needs_input_grad[1] else None
+            gx = None
+            if ctx.has_x and ctx.needs_input_grad[2]:
+                (sigma,) = ctx.saved_tensors
+                gx = ctx.surf.apply_S_adj_X(sigma, gout).to(ctx.x_dtype)
+            return None, gs, gx
 
     class ApplyGradS(torch.autograd.Function):
         """(pot, grad, dSdn, surf_grad) = lb_apply_gradS(sigma); backward through
@@ -428,10 +455,15 @@ def solve(surf, f, tol=1e-10, mode=LB_SOLVE_FP64):
     return _autograd()[2].apply(surf, f, tol, mode)
 
 
-def apply_S(surf, sigma):
+def apply_S(surf, sigma, X=None):
     """Differentiable S[sigma] (torch.autograd): the backward pass is the
-    library's transposed apply."""
-    return _autograd()[0].apply(surf, sigma)
+    library's transposed apply.  X, optional: a [N, 3] tensor standing for
+    the node positions the surface was set up with (its values are not read);
+    when it requires grad, the backward pass returns the kernel-position
+    derivative for it."""
+    if X is not None and tuple(X.shape) != (surf.N, 3):
+        raise ValueError(f"X must have shape ({surf.N}, 3)")
+    return _autograd()[0].apply(surf, sigma, X)
 
 
 def apply_gradS(surf, sigma):

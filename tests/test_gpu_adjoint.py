@@ -231,3 +231,86 @@ def test_autograd_solve_fd(torch_dev):
     note(f"directional derivative fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(an):.2e}")
     assert abs(fd - an) < 1e-6 * abs(an)
     s.close()
+
+
+@pytest.mark.parametrize("direct", [True, False])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c1_position_vjp_vs_oracle(torch_dev, c1_oracle, direct, prec):
+    """Kernel-position derivative of S (lb_apply_S_adj_X) against the
+    oracle's, two densities summed.  FP32 sums every pair without the near
+    mask, so terms up to 1/r^2 of the closest node/point pairs enter the
+    FP32 sums: 1e-5 relative L2."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    o = c1_oracle
+    g = o.g
+    note(f"c1 position vjp direct={direct} prec={prec} setup")
+    s = P.Surface(g.Xp, g.Xup, g.Xvp, 4, direct=direct)
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(61)
+    sig, gb = rng.standard_normal((2, g.N)), rng.standard_normal((2, g.N))
+    note(f"c1 position vjp direct={direct} prec={prec} launch")
+    xb = s.apply_S_adj_X(torch.tensor(sig, dtype=dt, device="cuda"), torch.tensor(gb, dtype=dt, device="cuda"))
+    torch.cuda.synchronize()
+    ref = o.position_vjp_S(sig, gb)
+    e = rel_l2(xb.double().cpu().numpy(), ref)
+    note(f"c1 position vjp error {e:.2e}")
+    assert e < (1e-9 if prec == 64 else 1e-5)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_fmm_position_vjp_sampled(torch_dev, prec):
+    """Several FMM levels (sphere, 1280 order-4 patches, N = 19,200): the
+    position derivative on the nodes of 24 sampled patches against the
+    oracle's, which sums over every node and oversampled point."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.sphere_patches(3, nodes(4))
+    g = Geometry(X, Xu, Xv, 4)
+    note(f"fmm position vjp prec={prec} setup")
+    s = P.Surface(X, Xu, Xv, 4)
+    note(f"fmm position vjp sizes {s.sizes}")
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(62)
+    xi = g.x / np.linalg.norm(g.x, axis=1, keepdims=True)
+    sig = I.real_sph_harm(3, 2, xi) + 0.2 * rng.standard_normal(g.N)
+    gb = rng.standard_normal(g.N)
+    note(f"fmm position vjp prec={prec} launch")
+    xb = s.apply_S_adj_X(torch.tensor(sig, dtype=dt, device="cuda"), torch.tensor(gb, dtype=dt, device="cuda"))
+    torch.cuda.synchronize()
+    pts = np.arange(0, g.NP, g.NP // 24)[:24]
+    o = Oracle(g, np.arange(1))  # rows unused: the position derivative needs no corrections
+    ref = o.position_vjp_S(sig, gb, patches=pts)
+    rows = (pts[:, None] * g.n_p + np.arange(g.n_p)[None, :]).reshape(-1)
+    e = rel_l2(xb.double().cpu().numpy()[rows], ref)
+    note(f"fmm position vjp prec={prec} error {e:.2e}")
+    assert e < (1e-9 if prec == 64 else 1e-5)
+    s.close()
+
+
+def test_autograd_positions(torch_dev):
+    """torch.autograd through apply_S with the node positions as an input:
+    the gradients are the library's density and position derivatives."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    X, Xu, Xv = I.sphere_patches(1, __import__("oracle.refelem", fromlist=["nodes"]).nodes(4))
+    note("autograd positions setup")
+    s = P.Surface(X, Xu, Xv, 4)
+    rng = np.random.default_rng(63)
+    sig = torch.tensor(rng.standard_normal(s.N), dtype=torch.float64, device="cuda", requires_grad=True)
+    Xt = torch.tensor(X.reshape(-1, 3), dtype=torch.float64, device="cuda", requires_grad=True)
+    tgt = torch.tensor(rng.standard_normal(s.N), dtype=torch.float64, device="cuda")
+    u = P.apply_S(s, sig, Xt)
+    J = 0.5 * ((u - tgt) ** 2).sum()
+    J.backward()
+    gbar = (u.detach() - tgt).contiguous()
+    xb = s.apply_S_adj_X(sig.detach().contiguous(), gbar)
+    sb = s.apply_S_adj(gbar)
+    assert torch.equal(Xt.grad, xb) and torch.equal(sig.grad, sb)
+    with pytest.raises(ValueError):
+        P.apply_S(s, sig, Xt[:10])
+    s.close()
