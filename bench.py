@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--workload", default="ellipsoid5120")
     ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and FP32+refine solves")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default octree depth and leaf shape")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
@@ -117,6 +118,14 @@ def main():
     s = P.Surface(X, Xu, Xv, k)
     t_setup = time.perf_counter() - t0
     print(f"[bench] setup {t_setup:.1f} s sizes {s.sizes}", file=sys.stderr, flush=True)
+    tuning = None
+    if not args.no_tune:  # untimed: picks the octree depth and leaf-kernel shape of each precision
+        tuning = {}
+        for prec in (32, 64):
+            t = s.autotune(prec, 1)
+            tuning[f"fp{prec}"] = {k: t[k] for k in ("leaf_src", "leaf_fmax", "depth", "ms_best", "ms_default")}
+            print(f"[bench] autotune fp{prec} {t}", file=sys.stderr, flush=True)
+        print(f"[bench] sizes after tuning {s.sizes}", file=sys.stderr, flush=True)
     N = s.N
     if args.copy_calib_mb > 0:
         a = torch.ones(args.copy_calib_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
@@ -195,7 +204,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, setup_s=round(t_setup, 2), p_f32=sz["p_f32"], p_f64=sz["p_f64"],
-                       fmm_levels=sz["fmm_levels"]),
+                       fmm_levels=sz["fmm_levels"], tuning=tuning),
         "fp64_apply": {"value": N / (ms64 * 1e-3) / 1e6, "unit": "Mpts/s", "ms": ms64, "phases_ms": ph64},
         "fp32_vs_fp64_rel_l2": {"pot": e_pot, "grad": e_grad},
         "phases_ms_fp32": ph,

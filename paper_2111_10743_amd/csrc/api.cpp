@@ -153,6 +153,10 @@ struct Prec {
   // position derivative: mask radii that exclude only coincident points
   // (forward tree) and gradient outputs at the targets (transposed tree)
   DBuf rm2_none, fmm4;
+  // tree parameters of the last build (the autotuner rebuilds with others)
+  int build_leaf_src = 0, leaf_fmax = 64;
+  double min_leaf_side = 0.0;
+  bool direct = false;
 };
 
 }  // namespace lb
@@ -329,6 +333,9 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   const bool adj = fwd != nullptr;
   P.p = p;
   P.L = (p + 1) * (p + 1);
+  P.build_leaf_src = leaf_src;
+  P.min_leaf_side = min_leaf_side;
+  P.direct = direct;
   // (X, nrm) are the nodes, (s, nu) the oversampled points
   const std::vector<double>& TX = adj ? S.s : S.X;
   const std::vector<double>& TN = adj ? S.nu : S.nrm;
@@ -424,7 +431,9 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   for (int64_t i = 0; i < N; ++i) tp[i] = (int)F.tgt_pos[i];
   for (int64_t i = 0; i < No; ++i) sp[i] = (int)F.src_pos[i];
   upload(P.tgt_pos, tp); upload(P.src_pos, sp);
-  if (!adj) {
+  // node data and corrections do not depend on the tree: a rebuild (empty C)
+  // keeps them where they are
+  if (!adj && !C.empty()) {
     upload_as<T>(P.P, ctx->re->P);
     upload_as<T>(P.wo, S.wo);
     upload_as<T>(P.nrm, S.nrm);
@@ -434,8 +443,8 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     upload(P.vals4, v4);
     upload(P.vals3, v3);
   }
-  // translations
-  if (F.depth >= 2 && !adj) {
+  // translations (level independent: built once)
+  if (F.depth >= 2 && !adj && !P.m2l.p) {
     Translations trn;
     trn.build(p);
     std::vector<T> m;
@@ -534,6 +543,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.Y = P.Y.p;
   D.p2m_H = nullptr;
   D.p2m_D = nullptr;
+  D.leaf_fmax = P.leaf_fmax;
   // P2M tables (the geometry is fixed, so the leaf harmonics of every
   // source can be kept): built on the device when both fit in a quarter of
   // the free memory and under P2M_TABLE_MAX bytes
@@ -541,7 +551,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     const size_t bytes = 2 * sizeof(T) * (size_t)No * P.L;
     size_t fr = 0, tot = 0;
     HIPTRY(hipMemGetInfo(&fr, &tot));
-    if (bytes <= P2M_TABLE_MAX && bytes <= fr / 4) {
+    if (bytes <= P2M_TABLE_MAX && (bytes <= fr / 4 || P.p2m_H.bytes >= bytes / 2)) {
       P.p2m_H.alloc(bytes / 2);
       P.p2m_D.alloc(bytes / 2);
       launch_p2m_tables<T>(D, dptr<T>(P.p2m_H), dptr<T>(P.p2m_D), nullptr);
@@ -737,6 +747,103 @@ static void apply_S_xbar_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int
     launch_xbar_S<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.str), dptr<int>(F.src_pos),
                      dptr<T>(F.fmm), dptr<int>(F.tgt_pos), gd, dptr<T>(A.fmm4), dptr<int>(A.tgt_pos), xbar, st);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: the depth of every octree (through the mean number of
+// oversampled points per leaf, leaf_src) and the most lanes per target of
+// the leaf kernel (leaf_fmax), chosen by timing the gradient apply with HIP
+// events.  A rebuild keeps the corrections and node data, and drops what
+// depends on the trees: workspaces, captured graphs, transposed trees.
+// ---------------------------------------------------------------------------
+template <typename T>
+static void rebuild_trees(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, int leaf_src) {
+  HIPTRY(hipDeviceSynchronize());
+  ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
+  const bool fp32 = sizeof(T) == 4;
+  build_prec<T>(ctx, P, P.p, std::vector<double>(), fp32 ? ctx->rm2f : std::vector<float>(), P.min_leaf_side,
+                leaf_src, P.direct);
+  P.ws_rhs = 0;
+  adj_built = false;
+  z_built = false;
+  HIPTRY(hipDeviceSynchronize());
+}
+
+template <typename T>
+static double time_apply(lb_ctx* ctx, Prec<T>& P, int nd, const DBuf& in, DBuf& out, int reps, hipStream_t st) {
+  const int64_t N = ctx->N;
+  const T* x = dptr<T>(in);
+  T* o = dptr<T>(out);
+  auto run = [&]() {
+    apply_gradS_t<T>(ctx, P, nd, x, o, o + nd * N, o + 4 * nd * N, o + 5 * nd * N, st);
+  };
+  run();  // workspace allocation
+  hipEvent_t e0, e1;
+  HIPTRY(hipEventCreate(&e0));
+  HIPTRY(hipEventCreate(&e1));
+  HIPTRY(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) run();
+  HIPTRY(hipEventRecord(e1, st));
+  HIPTRY(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return (double)ms / reps;
+}
+
+template <typename T>
+static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, int nd, lb_tune_info& r,
+                       hipStream_t st) {
+  const int64_t N = ctx->N;
+  DBuf in, out;
+  in.alloc(sizeof(T) * (size_t)nd * N);
+  out.alloc(sizeof(T) * (size_t)8 * nd * N);
+  HIPTRY(hipMemsetAsync(in.p, 0, sizeof(T) * (size_t)nd * N, st));
+  const int reps = 3;
+  const int base_ls = P.build_leaf_src, base_fm = P.leaf_fmax;
+  std::vector<int> cand{base_ls};
+  if (!P.direct)
+    for (double f : {0.25, 0.5, 2.0, 4.0}) {
+      const int v = std::max(16, (int)(base_ls * f));
+      if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+    }
+  const int fms[3] = {64, 32, 16};
+  std::vector<std::vector<int>> seen;
+  int best_ls = base_ls, best_fm = base_fm;
+  double best = 1e300;
+  r = lb_tune_info{};
+  r.ms_default = -1.0;
+  for (size_t a = 0; a < cand.size(); ++a) {
+    if (a > 0) rebuild_trees<T>(ctx, P, adj_built, z_built, cand[a]);
+    std::vector<int> depths;
+    for (const Octree& t : P.trees) depths.push_back(t.depth);
+    if (std::find(seen.begin(), seen.end(), depths) != seen.end()) continue;
+    seen.push_back(depths);
+    for (int fm : fms) {
+      P.leaf_fmax = fm;
+      P.dt.leaf_fmax = fm;
+      const double ms = time_apply<T>(ctx, P, nd, in, out, reps, st);
+      if (a == 0 && fm == base_fm) r.ms_default = ms;
+      if (r.n_trials < LB_TUNE_MAX_TRIALS) {
+        r.trial_leaf_src[r.n_trials] = cand[a];
+        r.trial_fmax[r.n_trials] = fm;
+        r.trial_depth[r.n_trials] = *std::max_element(depths.begin(), depths.end());
+        r.trial_ms[r.n_trials] = ms;
+        r.n_trials++;
+      }
+      if (ms < best) { best = ms; best_ls = cand[a]; best_fm = fm; }
+    }
+  }
+  if (P.build_leaf_src != best_ls) rebuild_trees<T>(ctx, P, adj_built, z_built, best_ls);
+  P.leaf_fmax = best_fm;
+  P.dt.leaf_fmax = best_fm;
+  r.leaf_src = best_ls;
+  r.leaf_fmax = best_fm;
+  r.ms_best = best;
+  r.depth = 0;
+  for (const Octree& t : P.trees) r.depth = std::max(r.depth, t.depth);
+  HIPTRY(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------------------
@@ -1354,6 +1461,20 @@ lb_status lb_apply_S_adj_X(lb_ctx* ctx, int nd, int prec, const void* sigma, con
     apply_S_xbar_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nd, (const double*)sigma,
                            (const double*)gbar, (double*)X_bar, st);
   HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_autotune(lb_ctx* ctx, int prec, int nd, lb_tune_info* info, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (nd > 64) fail(LB_EINVAL, "autotune takes at most 64 densities");
+  hipStream_t st = (hipStream_t)stream;
+  lb_tune_info r{};
+  if (prec == LB_PREC_FP32)
+    autotune_t<float>(ctx, ctx->f32, ctx->adj_built32, ctx->z_built32, nd, r, st);
+  else
+    autotune_t<double>(ctx, ctx->f64, ctx->adj_built64, ctx->z_built64, nd, r, st);
+  if (info) *info = r;
   API_END
 }
 

@@ -735,10 +735,10 @@ __device__ void derive3(const T* src, int pin, T* dx, T* dy, T* dz) {
 #endif
 constexpr int LEAF_BS = LB_LEAF_BS;            // threads per block
 constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
-constexpr int LEAF_FMAX = 64;                  // at most one wave per target
 
-// Each target of a leaf gets F = min(64, 256 / targets) threads (a power of
-// two): thread (slot, f) works for target slot `slot` of the current pass,
+// Each target of a leaf gets F = min(leaf_fmax, 256 / targets) threads (a
+// power of two, at most one wave; leaf_fmax is set by the autotuner):
+// thread (slot, f) works for target slot `slot` of the current pass,
 // the far field over the harmonic orders m = f (mod F), the near field over
 // the source indices j = f (mod F) of each LDS chunk; the F partial sums of
 // a target (contiguous lanes) are then added by shuffles.
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
   const bool far = t.leaf_lvl[b] >= 2;
   const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
-  int F = LEAF_FMAX;
+  int F = t.leaf_fmax;
   while (F > 1 && F * (tend - tbeg) > LEAF_BS) F >>= 1;
   const int TPB = LEAF_BS / F;
   const int slot = threadIdx.x / F, f = threadIdx.x % F;

@@ -81,6 +81,7 @@ struct DevTree {
   const GemmPlan* l2l_plan;
   void* Y;                    // column scratch [max columns * 8][L]
   const T *p2m_H, *p2m_D;     // per-source P2M tables [No][L] in tree order (nullable)
+  int leaf_fmax;              // most lanes per target in the leaf kernel (power of two, 1..64)
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities

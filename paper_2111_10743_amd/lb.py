@@ -33,7 +33,7 @@ LB_HOST_OCTREE = 16
 LB_NO_GRAPH = 32
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
-            "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X",
+            "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj", "lb_destroy",
             "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
@@ -62,6 +62,16 @@ class TreeInfo(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("nbox", ctypes.c_int32), ("nleaf", ctypes.c_int32),
                 ("nulist", ctypes.c_int32), ("nvlist", ctypes.c_int32), ("lo", ctypes.c_double * 3),
                 ("side", ctypes.c_double)]
+
+
+TUNE_MAX = 32
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("leaf_src", ctypes.c_int32), ("leaf_fmax", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_trials", ctypes.c_int32), ("ms_best", ctypes.c_double), ("ms_default", ctypes.c_double),
+                ("trial_leaf_src", ctypes.c_int32 * TUNE_MAX), ("trial_fmax", ctypes.c_int32 * TUNE_MAX),
+                ("trial_depth", ctypes.c_int32 * TUNE_MAX), ("trial_ms", ctypes.c_double * TUNE_MAX)]
 
 
 class LBError(RuntimeError):
@@ -98,6 +108,7 @@ def lib():
         L.lb_apply_gradS_adj.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.lb_apply_S_adj.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_S_adj_X.argtypes = [vp, ip, ip, vp, vp, vp, vp]
+        L.lb_autotune.argtypes = [vp, ip, ip, ctypes.POINTER(TuneInfo), vp]
         L.lb_apply_gradS_timed.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, dp, vp]
         L.lb_apply_A3.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
@@ -329,6 +340,18 @@ class Surface:
         _check(lib().lb_apply_gradS_adj(self._ctx, nd, self._prec(ref), _ptr(gpot), _ptr(ggrad), _ptr(gdSdn),
                                         _ptr(gsurf), _ptr(res), _stream()))
         return res
+
+    def autotune(self, prec=32, nd=1):
+        """lb_autotune: time the gradient apply over octree depths (leaf_src)
+        and leaf-kernel shapes (leaf_fmax), keep the fastest.  Returns the
+        chosen configuration and every trial."""
+        info = TuneInfo()
+        _check(lib().lb_autotune(self._ctx, int(prec), int(nd), ctypes.byref(info), _stream()))
+        n = info.n_trials
+        return {"leaf_src": info.leaf_src, "leaf_fmax": info.leaf_fmax, "depth": info.depth,
+                "ms_best": info.ms_best, "ms_default": info.ms_default,
+                "trials": [{"leaf_src": info.trial_leaf_src[i], "leaf_fmax": info.trial_fmax[i],
+                            "depth": info.trial_depth[i], "ms": info.trial_ms[i]} for i in range(n)]}
 
     def apply_gradS_timed(self, sigma):
         """apply_gradS plus per-phase milliseconds (HIP events on the stream)."""

@@ -228,3 +228,59 @@ def test_solve_graph_replay_matches_eager(torch_dev, mode):
         assert torch.equal(fa, fb)
     a.close()
     b.close()
+
+
+def test_autotune_rebuilds_consistently(torch_dev):
+    """lb_autotune rebuilds the octrees of one precision (several depths) and
+    sets the leaf-kernel shape: afterwards the applies equal the oracle as
+    before, the forward/transposed dot-product identity holds, and the solves
+    (graphs recaptured on the new trees) agree with the ones before tuning."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.sphere_patches(3, nodes(4))
+    g = Geometry(X, Xu, Xv, 4)
+    note("autotune setup (sphere, 1280 order-4 patches)")
+    s = P.Surface(X, Xu, Xv, 4)
+    rows = np.arange(0, g.N, g.N // 200)
+    o = Oracle(g, rows)
+    rng = np.random.default_rng(71)
+    xi = g.x / np.linalg.norm(g.x, axis=1, keepdims=True)
+    sig = I.real_sph_harm(4, 1, xi) + 0.2 * rng.standard_normal(g.N)
+    L = o.layer(sig)
+    f = torch.tensor(I.real_sph_harm(3, -1, xi) + 0.1 * I.real_sph_harm(5, 2, xi), device="cuda")
+    note("autotune: solves before tuning")
+    u0 = {m: s.solve(f, tol=1e-11, mode=m)[0] for m in (P.LB_SOLVE_FP64, P.LB_SOLVE_FP32_REFINE)}
+    for prec, tol in ((32, 1e-6), (64, 1e-9)):
+        note(f"autotune prec={prec}")
+        t = s.autotune(prec, 1)
+        note(f"autotune prec={prec}: {t}")
+        assert len(t["trials"]) >= 3
+        ms = [q["ms"] for q in t["trials"]]
+        assert t["ms_best"] == min(ms) and t["ms_default"] in ms
+        assert any(q["leaf_src"] == t["leaf_src"] and q["leaf_fmax"] == t["leaf_fmax"] for q in t["trials"])
+        assert len({q["depth"] for q in t["trials"]}) >= 2
+        dt = torch.float64 if prec == 64 else torch.float32
+        out = s.apply_gradS(torch.tensor(sig, dtype=dt, device="cuda"))
+        torch.cuda.synchronize()
+        pot = out["pot"].double().cpu().numpy()[rows]
+        grad = out["grad"].double().cpu().numpy()[rows]
+        e1, e2 = rel_l2(pot, L[:, 0]), rel_l2(grad, L[:, 1:4])
+        note(f"autotune prec={prec}: errors after tuning pot {e1:.2e} grad {e2:.2e}")
+        assert e1 < tol and e2 < tol
+        # transposed apply on the rebuilt transposed tree
+        x = torch.tensor(rng.standard_normal(g.N), dtype=dt, device="cuda")
+        y = torch.tensor(rng.standard_normal(g.N), dtype=dt, device="cuda")
+        lhs = float((y.double() * s.apply_S(x).double()).sum())
+        rhs = float((s.apply_S_adj(y).double() * x.double()).sum())
+        note(f"autotune prec={prec}: <y, S x> {lhs:.12e} <S^T y, x> {rhs:.12e}")
+        assert abs(lhs - rhs) < (1e-10 if prec == 64 else 1e-5) * abs(lhs) + 1e-12
+    for m, u in u0.items():
+        note(f"autotune: solve mode={m} after tuning")
+        u1, info, code = s.solve(f, tol=1e-11, mode=m)
+        e = float((u1 - u).norm() / u.norm())
+        note(f"autotune: solve mode={m} change {e:.2e} info {info}")
+        assert code == 0 and e < 1e-9
+    s.close()
