@@ -226,3 +226,31 @@ def star_patches(n_s, uv, coeffs, amp=0.25, h=1e-3):
     Xu = r0 * xu + dr(xu)[..., None] * xi
     Xv = r0 * xv + dr(xv)[..., None] * xi
     return X, Xu, Xv
+
+
+# ----------------------------------------------------------------------
+# random smooth ambient vector fields (harmonic-field experiments)
+# ----------------------------------------------------------------------
+def legendre_field(x, seed, deg, L):
+    """V (n, 3): each component sum_{a,b,c <= deg} C_abc P_a(x/2L) P_b(y/2L) P_c(z/2L)
+    with C_abc ~ N(0, 1) (seeded), for points inside (-L, L)^3."""
+    from numpy.polynomial import legendre
+    x = np.asarray(x, dtype=float)
+    rng = np.random.default_rng(seed)
+    V = np.zeros_like(x)
+    for c in range(3):
+        C = rng.standard_normal((deg + 1, deg + 1, deg + 1))
+        V[:, c] = legendre.legval3d(x[:, 0] / (2 * L), x[:, 1] / (2 * L), x[:, 2] / (2 * L), C)
+    return V
+
+
+def torus_frame(X, R, r):
+    """Unit tangents e_phi, e_theta and rho = R + r cos(theta) of the torus of
+    torus_patches at the points X (n, 3)."""
+    X = np.asarray(X, dtype=float)
+    ph = np.arctan2(X[:, 1], X[:, 0])
+    rho = np.hypot(X[:, 0], X[:, 1])
+    th = np.arctan2(X[:, 2], rho - R)
+    e_ph = np.stack([-np.sin(ph), np.cos(ph), 0 * ph], 1)
+    e_th = np.stack([-np.sin(th) * np.cos(ph), -np.sin(th) * np.sin(ph), np.cos(th)], 1)
+    return e_ph, e_th, R + r * np.cos(th)
