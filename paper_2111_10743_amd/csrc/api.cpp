@@ -201,10 +201,17 @@ struct lb_ctx {
   // GMRES operators replayed from captured HIP graphs (A3 and A3^T, FP64
   // and FP32), captured on the library's own stream
   hipStream_t cap_stream = nullptr;
+  // near-field sums overlapped with the far-field passes: a non-blocking
+  // side stream (default priority) and its fork/join events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   lb::OpGraph gA64, gA32, gT64, gT32;
   ~lb_ctx() {
     gA64.reset(); gA32.reset(); gT64.reset(); gT32.reset();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -544,6 +551,15 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.p2m_H = nullptr;
   D.p2m_D = nullptr;
   D.leaf_fmax = P.leaf_fmax;
+  const bool overlap = !(ctx->opts.flags & LB_NO_OVERLAP);
+  if (overlap && !ctx->side_stream) {
+    HIPTRY(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking));
+    HIPTRY(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  }
+  D.side = overlap ? ctx->side_stream : nullptr;
+  D.fork_ev = ctx->ev_fork;
+  D.join_ev = ctx->ev_join;
   // P2M tables (the geometry is fixed, so the leaf harmonics of every
   // source can be kept): built on the device when both fit in a quarter of
   // the free memory and under P2M_TABLE_MAX bytes

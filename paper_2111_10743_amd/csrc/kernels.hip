@@ -742,7 +742,11 @@ constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
 // the far field over the harmonic orders m = f (mod F), the near field over
 // the source indices j = f (mod F) of each LDS chunk; the F partial sums of
 // a target (contiguous lanes) are then added by shuffles.
-template <typename T, int MODE, bool EXP_LDS>
+// PART: LEAF_BOTH (far and near, outputs written), LEAF_NEAR (near-field
+// sums only, outputs written), LEAF_FAR (L2P only, added to the outputs).
+enum { LEAF_BOTH = 0, LEAF_NEAR = 1, LEAF_FAR = 2 };
+
+template <typename T, int MODE, bool EXP_LDS, int PART>
 __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str,
                                                   int64_t No, const T* __restrict__ Lc, T* __restrict__ D,
                                                   T* __restrict__ out, int64_t N) {
@@ -752,7 +756,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   const int rhs = blockIdx.y;
   const int p = t.p, L = t.L, Lg = p * p, Lh = (p - 1) * (p - 1);
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
-  const bool far = t.leaf_lvl[b] >= 2;
+  const bool far = PART != LEAF_NEAR && t.leaf_lvl[b] >= 2;
   const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
   int F = t.leaf_fmax;
   while (F > 1 && F * (tend - tbeg) > LEAF_BS) F >>= 1;
@@ -768,7 +772,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   T* sL;
   T* sG;
   if (EXP_LDS) {
-    sL = tile + REC * LEAF_CH;
+    sL = tile + (PART == LEAF_FAR ? 0 : REC * LEAF_CH);  // the far-only kernel stages no sources
     sG = sL + nexp * L;
   } else {
     sL = const_cast<T*>(gL);
@@ -820,7 +824,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     upref[nU] = acc;
   }
   __syncthreads();
-  const int utot = upref[nU];
+  const int utot = PART == LEAF_FAR ? 0 : upref[nU];
   for (int i0 = tbeg; i0 < tend; i0 += TPB) {
     const int i = i0 + slot;
     const bool act = i < tend;
@@ -1020,14 +1024,64 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     }
     if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
-      out[base + i] = (T)a0;
-      if (nout > 1) out[base + N + i] = (T)a1;
-      if (nout > 2) {
-        out[base + 2 * N + i] = (T)a2;
-        out[base + 3 * N + i] = (T)a3;
+      if (PART == LEAF_FAR) {  // after the near-field kernel (stream ordered)
+        out[base + i] += (T)a0;
+        if (nout > 1) out[base + N + i] += (T)a1;
+        if (nout > 2) {
+          out[base + 2 * N + i] += (T)a2;
+          out[base + 3 * N + i] += (T)a3;
+        }
+      } else {
+        out[base + i] = (T)a0;
+        if (nout > 1) out[base + N + i] = (T)a1;
+        if (nout > 2) {
+          out[base + 2 * N + i] = (T)a2;
+          out[base + 3 * N + i] = (T)a3;
+        }
       }
     }
   }
+}
+
+template <typename T>
+static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const T* str, const T* Lc, T* D, T* out,
+                        int64_t N, int64_t No, hipStream_t st) {
+  const int p = t.p, L = t.L;
+  const int nexp = fmm_nexp(mode);
+  const size_t chunk = part == LEAF_FAR ? 0
+                       : sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
+  const size_t exps = part == LEAF_NEAR ? 0
+                      : sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
+  const bool lds = chunk + exps <= 64 * 1024;
+  const size_t sml = lds ? chunk + exps : chunk;
+  dim3 grid(t.n_leaf_tgt, nrhs);
+#define LEAF_LAUNCH(MD, PT)                                                                                    \
+  if (lds)                                                                                                     \
+    hipLaunchKernelGGL((k_leaf<T, MD, true, PT>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N); \
+  else                                                                                                         \
+    hipLaunchKernelGGL((k_leaf<T, MD, false, PT>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
+#define LEAF_PARTS(MD)                    \
+  if (part == LEAF_NEAR) {                \
+    LEAF_LAUNCH(MD, LEAF_NEAR)            \
+  } else if (part == LEAF_FAR) {          \
+    LEAF_LAUNCH(MD, LEAF_FAR)             \
+  } else {                                \
+    LEAF_LAUNCH(MD, LEAF_BOTH)            \
+  }
+  if (mode == FMM_POT) {
+    LEAF_PARTS(FMM_POT)
+  } else if (mode == FMM_GRAD) {
+    LEAF_PARTS(FMM_GRAD)
+  } else if (mode == FMM_ADJ) {
+    LEAF_PARTS(FMM_ADJ)
+  } else if (mode == FMM_ADJ3) {
+    LEAF_PARTS(FMM_ADJ3)
+  } else {
+    LEAF_PARTS(FMM_A3B)
+  }
+#undef LEAF_PARTS
+#undef LEAF_LAUNCH
+  KCHECK();
 }
 
 template <typename T>
@@ -1040,6 +1094,16 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   if (ne > 8) {
     fprintf(stderr, "lb: launch_fmm called with %d expansions (max 8)\n", ne);
     return;
+  }
+  // With a side stream, the near-field sums (which need only the strengths)
+  // run there while this stream does P2M, M2M, M2L and L2L; the L2P kernel
+  // then adds the far field.  Timed applies stay serial.
+  const bool ovl = t.side && t.depth >= 2 && !tm->on;
+  if (ovl) {  // fork
+    (void)hipEventRecord(t.fork_ev, st);
+    (void)hipStreamWaitEvent(t.side, t.fork_ev, 0);
+    launch_leaf<T>(t, mode, LEAF_NEAR, nrhs, str, Lc, D, out, N, No, t.side);
+    (void)hipEventRecord(t.join_ev, t.side);
   }
   if (t.depth >= 2) {
     // source tile of P2M: harmonic tables of ts sources within 48 KiB of LDS
@@ -1076,31 +1140,13 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     tm->mark(PH_M2L, st);
     tm->mark(PH_L2L, st);
   }
-  tm->mark(PH_LEAF, st);
-  const int nexp = fmm_nexp(mode);
-  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
-  const size_t exps = sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
-  const bool lds = chunk + exps <= 64 * 1024;
-  const size_t sml = lds ? chunk + exps : chunk;
-  dim3 grid(t.n_leaf_tgt, nrhs);
-#define LEAF_LAUNCH(MD)                                                                                   \
-  if (lds)                                                                                                \
-    hipLaunchKernelGGL((k_leaf<T, MD, true>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N); \
-  else                                                                                                    \
-    hipLaunchKernelGGL((k_leaf<T, MD, false>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N);
-  if (mode == FMM_POT) {
-    LEAF_LAUNCH(FMM_POT)
-  } else if (mode == FMM_GRAD) {
-    LEAF_LAUNCH(FMM_GRAD)
-  } else if (mode == FMM_ADJ) {
-    LEAF_LAUNCH(FMM_ADJ)
-  } else if (mode == FMM_ADJ3) {
-    LEAF_LAUNCH(FMM_ADJ3)
+  if (ovl) {  // join: the near-field sums are in `out`
+    (void)hipStreamWaitEvent(st, t.join_ev, 0);
+    launch_leaf<T>(t, mode, LEAF_FAR, nrhs, str, Lc, D, out, N, No, st);
   } else {
-    LEAF_LAUNCH(FMM_A3B)
+    tm->mark(PH_LEAF, st);
+    launch_leaf<T>(t, mode, LEAF_BOTH, nrhs, str, Lc, D, out, N, No, st);
   }
-#undef LEAF_LAUNCH
-  KCHECK();
 }
 
 // ---------------------------------------------------------------------------

@@ -82,6 +82,10 @@ struct DevTree {
   void* Y;                    // column scratch [max columns * 8][L]
   const T *p2m_H, *p2m_D;     // per-source P2M tables [No][L] in tree order (nullable)
   int leaf_fmax;              // most lanes per target in the leaf kernel (power of two, 1..64)
+  // host handles (nullable side): a non-blocking stream for the near-field
+  // sums and the events that fork it from and join it to the caller's stream
+  hipStream_t side;
+  hipEvent_t fork_ev, join_ev;
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities

@@ -31,6 +31,7 @@ LB_DIRECT = 4
 LB_NO_P2M_TABLES = 8
 LB_HOST_OCTREE = 16
 LB_NO_GRAPH = 32
+LB_NO_OVERLAP = 64
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
@@ -191,7 +192,7 @@ class Surface:
     """One discretized surface: lb_setup ... lb_destroy."""
 
     def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, p2m_tables=True,
-                 host_octree=False, patches_per_surf=None, graphs=True, **kw):
+                 host_octree=False, patches_per_surf=None, graphs=True, overlap=True, **kw):
         """One surface, or with patches_per_surf several independent surfaces
         (their patches one after the other in X, Xu, Xv; lb_setup_batch)."""
         X = np.ascontiguousarray(X, dtype=np.float64)
@@ -210,6 +211,8 @@ class Surface:
             o.flags |= LB_HOST_OCTREE
         if not graphs:
             o.flags |= LB_NO_GRAPH
+        if not overlap:
+            o.flags |= LB_NO_OVERLAP
         self.order = order
         self.host_only = host_only
         self._ctx = ctypes.c_void_p()
