@@ -269,19 +269,22 @@ lb_status lb_apply_gradS_timed(lb_ctx *ctx, int nd, int prec, const void *sigma,
  * leaf_src in {1/4, 1/2, 1, 2, 4} x its current value (each tree's depth:
  * the first level whose mean number of oversampled points per leaf is at
  * most leaf_src, coarsened in FP32 so that the leaf side stays above the
- * near-mask radius) and leaf_fmax in {64, 32, 16} (most lanes per target),
- * keeps the fastest pair and rebuilds the trees with it.  Corrections and
+ * near-mask radius) and leaf_fmax in {64, 32, 16} (most lanes per target,
+ * one block per leaf: leaf_split 0), then, at the fastest of those,
+ * leaf_split in {1, 2, 3} (a leaf cut into up to that many blocks, any
+ * number of lanes per target), and keeps the fastest configuration.  Corrections and
  * node data are kept; captured GMRES graphs and transposed trees are dropped
  * and rebuilt on next use.  Results are the same operator up to the FMM
  * truncation error.  A direct context (LB_DIRECT) tunes leaf_fmax only.
  * Synchronizes the device; nd <= 64; info: host, nullable. */
 #define LB_TUNE_MAX_TRIALS 32
 typedef struct {
-  int32_t leaf_src, leaf_fmax, depth; /* chosen configuration, deepest tree level */
+  int32_t leaf_src, leaf_fmax, leaf_split; /* chosen configuration */
+  int32_t depth;                      /* deepest tree level of the chosen forest */
   int32_t n_trials;                   /* entries used in the trial arrays */
   double ms_best, ms_default;         /* apply time chosen / of the configuration on entry */
   int32_t trial_leaf_src[LB_TUNE_MAX_TRIALS], trial_fmax[LB_TUNE_MAX_TRIALS],
-      trial_depth[LB_TUNE_MAX_TRIALS];
+      trial_split[LB_TUNE_MAX_TRIALS], trial_depth[LB_TUNE_MAX_TRIALS];
   double trial_ms[LB_TUNE_MAX_TRIALS];
 } lb_tune_info;
 lb_status lb_autotune(lb_ctx *ctx, int prec, int nd, lb_tune_info *info, void *stream);

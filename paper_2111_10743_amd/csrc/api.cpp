@@ -153,8 +153,13 @@ struct Prec {
   // position derivative: mask radii that exclude only coincident points
   // (forward tree) and gradient outputs at the targets (transposed tree)
   DBuf rm2_none, fmm4;
+  // leaf-kernel work items (leaf, target range, lanes per target), built
+  // from the per-target-leaf (leaf, tbeg, tend, U-list sources) of the trees
+  DBuf leaf_work;
+  std::vector<int> lw_leaf, lw_tbeg, lw_tend;
+  std::vector<int64_t> lw_usrc;
   // tree parameters of the last build (the autotuner rebuilds with others)
-  int build_leaf_src = 0, leaf_fmax = 64;
+  int build_leaf_src = 0, leaf_fmax = 64, leaf_split = 0;
   double min_leaf_side = 0.0;
   bool direct = false;
 };
@@ -326,6 +331,53 @@ static void merge_forest(const std::vector<Octree>& trees, const std::vector<int
   F.nleaf = loff;
 }
 
+// Work items of the leaf kernel: one block evaluates targets [tbeg, tend) of
+// one leaf with F lanes per target (256 / F target slots).  split = 0: one
+// block per leaf, F the largest power of two <= fmax with F a <= 256 for a
+// leaf of a targets.  split = s >= 1: a leaf whose U-list holds u sources is
+// cut into m <= s items of ceil(a / m) targets with any F =
+// min(fmax, 256 / ceil(a / m)), m minimizing m (u / F + 2 u / 256 + 8)
+// (near-field iterations per lane, staging of the sources, a fixed cost per
+// block).  Items are ordered heaviest first so that the grid does not end on
+// a tail of large blocks.
+template <typename T>
+static void make_leaf_work(Prec<T>& P, int fmax, int split) {
+  struct Item { int leaf, tbeg, tend, F; double cost; };
+  std::vector<Item> it;
+  for (size_t k = 0; k < P.lw_leaf.size(); ++k) {
+    const int a = P.lw_tend[k] - P.lw_tbeg[k];
+    const double u = (double)P.lw_usrc[k];
+    int bm = 1, bF = 1;
+    double bc = 1e300;
+    if (split == 0) {
+      bF = fmax;
+      while (bF > 1 && bF * a > 256) bF >>= 1;
+    }
+    for (int m = 1; m <= split; ++m) {
+      const int per = (a + m - 1) / m;
+      const int F = std::max(1, std::min(fmax, 256 / std::max(per, 1)));
+      const double c = m * (u / F + 2.0 * u / 256.0 + 8.0);
+      if (c < bc) { bc = c; bm = m; bF = F; }
+    }
+    const int per = (a + bm - 1) / bm;
+    for (int i = 0; i < bm; ++i) {
+      const int b0 = P.lw_tbeg[k] + i * per, b1 = std::min(P.lw_tend[k], b0 + per);
+      if (b0 < b1) it.push_back({P.lw_leaf[k], b0, b1, bF, u / bF + 2.0 * u / 256.0 + 8.0});
+    }
+  }
+  std::stable_sort(it.begin(), it.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+  std::vector<int> w(4 * std::max<size_t>(it.size(), 1), 0);
+  for (size_t i = 0; i < it.size(); ++i) {
+    w[4 * i] = it[i].leaf; w[4 * i + 1] = it[i].tbeg; w[4 * i + 2] = it[i].tend; w[4 * i + 3] = it[i].F;
+  }
+  upload(P.leaf_work, w);
+  P.dt.leaf_work = reinterpret_cast<const int4*>(P.leaf_work.p);
+  P.dt.n_leaf_work = (int)it.size();
+  P.leaf_fmax = fmax;
+  P.leaf_split = split;
+  P.dt.leaf_fmax = fmax;
+}
+
 // Device state of one precision: one octree per surface, merged into a
 // forest.  With `fwd` set, the transposed problem of the adjoint applies:
 // the Nystrom nodes are the sources and the oversampled points the targets
@@ -412,14 +464,15 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   {
     auto nsrc = [&](int l) { return F.src_end[l] - F.src_beg[l]; };
     std::stable_sort(ls.begin(), ls.end(), [&](int x, int y) { return nsrc(x) > nsrc(y); });
-    std::vector<double> cost(F.nleaf, 0.0);
+    P.lw_leaf.clear(); P.lw_tbeg.clear(); P.lw_tend.clear(); P.lw_usrc.clear();
     for (int l : lt) {
       int64_t us = 0;
       for (int k = F.ulist_ptr[l]; k < F.ulist_ptr[l + 1]; ++k) us += nsrc(F.ulist[k]);
-      const int nt = F.tgt_end[l] - F.tgt_beg[l];
-      cost[l] = (double)us * nt / std::min(256, 8 * nt);
+      P.lw_leaf.push_back(l);
+      P.lw_tbeg.push_back(F.tgt_beg[l]);
+      P.lw_tend.push_back(F.tgt_end[l]);
+      P.lw_usrc.push_back(us);
     }
-    std::stable_sort(lt.begin(), lt.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   }
   upload(P.leaf_tgt, lt); upload(P.leaf_src, ls);
   std::vector<int> lsv, lsp(1, 0), ltv, ltp(1, 0);
@@ -533,6 +586,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.vlist_ptr = dptr<int>(P.vlist_ptr); D.vlist_src = dptr<int>(P.vlist_src); D.vlist_off = dptr<int>(P.vlist_off);
   D.parent = dptr<int>(P.parent); D.child = dptr<int>(P.child); D.child_src = dptr<int>(P.child_src);
   D.leaf_tgt_list = dptr<int>(P.leaf_tgt); D.n_leaf_tgt = (int)lt.size();
+  make_leaf_work<T>(P, P.leaf_fmax, P.leaf_split);
   D.leaf_src_list = dptr<int>(P.leaf_src); D.n_leaf_src = (int)ls.size();
   D.lev_box_src = dptr<int>(P.lev_src); D.lev_box_src_ptr = dptr<int>(P.lev_src_ptr);
   D.lev_box_tgt = dptr<int>(P.lev_tgt); D.lev_box_tgt_ptr = dptr<int>(P.lev_tgt_ptr);
@@ -587,7 +641,7 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   P.str.alloc(sizeof(T) * (size_t)No * 2 * chunk);
   P.M.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
   P.Lc.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
-  P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_tgt, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1)));
+  P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_work, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1)));
   P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
   P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
   P.y2.alloc(sizeof(T) * (size_t)N * chunk);
@@ -702,7 +756,7 @@ static void ensure_adjoint(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built) {
   A.str.alloc(sizeof(T) * (size_t)ctx->N * 4 * c);
   A.M.alloc(sizeof(T) * (size_t)nb * c * L);
   A.Lc.alloc(sizeof(T) * (size_t)nb * c * L);
-  A.D.alloc(sizeof(T) * (size_t)std::max(A.dt.n_leaf_tgt, 1) * c * (3 * p * p + 9 * (p - 1) * (p - 1)));
+  A.D.alloc(sizeof(T) * (size_t)std::max(A.dt.n_leaf_work, 1) * c * (3 * p * p + 9 * (p - 1) * (p - 1)));
   A.fmm.alloc(sizeof(T) * (size_t)ctx->No * c);
   HIPTRY(hipDeviceSynchronize());
   built = true;
@@ -785,6 +839,17 @@ static void rebuild_trees(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_buil
   HIPTRY(hipDeviceSynchronize());
 }
 
+// new leaf-kernel work items (their count sizes the workspace; captured
+// graphs hold the old buffers)
+template <typename T>
+static void set_leaf_shape(lb_ctx* ctx, Prec<T>& P, int fmax, int split) {
+  HIPTRY(hipDeviceSynchronize());
+  ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
+  make_leaf_work<T>(P, fmax, split);
+  P.ws_rhs = 0;
+  HIPTRY(hipDeviceSynchronize());
+}
+
 template <typename T>
 static double time_apply(lb_ctx* ctx, Prec<T>& P, int nd, const DBuf& in, DBuf& out, int reps, hipStream_t st) {
   const int64_t N = ctx->N;
@@ -817,45 +882,55 @@ static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, 
   out.alloc(sizeof(T) * (size_t)8 * nd * N);
   HIPTRY(hipMemsetAsync(in.p, 0, sizeof(T) * (size_t)nd * N, st));
   const int reps = 3;
-  const int base_ls = P.build_leaf_src, base_fm = P.leaf_fmax;
+  const int base_ls = P.build_leaf_src, base_fm = P.leaf_fmax, base_sp = P.leaf_split;
   std::vector<int> cand{base_ls};
   if (!P.direct)
     for (double f : {0.25, 0.5, 2.0, 4.0}) {
       const int v = std::max(16, (int)(base_ls * f));
       if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
     }
-  const int fms[3] = {64, 32, 16};
   std::vector<std::vector<int>> seen;
-  int best_ls = base_ls, best_fm = base_fm;
+  int best_ls = base_ls, best_fm = base_fm, best_sp = base_sp;
   double best = 1e300;
   r = lb_tune_info{};
   r.ms_default = -1.0;
+  auto trial = [&](int ls, int fm, int sp, int depth) {
+    set_leaf_shape<T>(ctx, P, fm, sp);
+    const double ms = time_apply<T>(ctx, P, nd, in, out, reps, st);
+    if (ls == base_ls && fm == base_fm && sp == base_sp && r.ms_default < 0) r.ms_default = ms;
+    if (r.n_trials < LB_TUNE_MAX_TRIALS) {
+      const int k = r.n_trials++;
+      r.trial_leaf_src[k] = ls;
+      r.trial_fmax[k] = fm;
+      r.trial_split[k] = sp;
+      r.trial_depth[k] = depth;
+      r.trial_ms[k] = ms;
+    }
+    if (ms < best) { best = ms; best_ls = ls; best_fm = fm; best_sp = sp; }
+  };
+  // octree depth x lanes per target (one block per leaf), then the leaf
+  // splitting of the best of those
+  int best_depth = 0;
   for (size_t a = 0; a < cand.size(); ++a) {
     if (a > 0) rebuild_trees<T>(ctx, P, adj_built, z_built, cand[a]);
     std::vector<int> depths;
     for (const Octree& t : P.trees) depths.push_back(t.depth);
     if (std::find(seen.begin(), seen.end(), depths) != seen.end()) continue;
     seen.push_back(depths);
-    for (int fm : fms) {
-      P.leaf_fmax = fm;
-      P.dt.leaf_fmax = fm;
-      const double ms = time_apply<T>(ctx, P, nd, in, out, reps, st);
-      if (a == 0 && fm == base_fm) r.ms_default = ms;
-      if (r.n_trials < LB_TUNE_MAX_TRIALS) {
-        r.trial_leaf_src[r.n_trials] = cand[a];
-        r.trial_fmax[r.n_trials] = fm;
-        r.trial_depth[r.n_trials] = *std::max_element(depths.begin(), depths.end());
-        r.trial_ms[r.n_trials] = ms;
-        r.n_trials++;
-      }
-      if (ms < best) { best = ms; best_ls = cand[a]; best_fm = fm; }
+    const int dmax = *std::max_element(depths.begin(), depths.end());
+    for (int fm : {64, 32, 16}) {
+      const double b0 = best;
+      trial(cand[a], fm, 0, dmax);
+      if (best < b0) best_depth = dmax;
     }
   }
   if (P.build_leaf_src != best_ls) rebuild_trees<T>(ctx, P, adj_built, z_built, best_ls);
-  P.leaf_fmax = best_fm;
-  P.dt.leaf_fmax = best_fm;
+  const int fm0 = best_fm;
+  for (int sp : {1, 2, 3}) trial(best_ls, fm0, sp, best_depth);
+  set_leaf_shape<T>(ctx, P, best_fm, best_sp);
   r.leaf_src = best_ls;
   r.leaf_fmax = best_fm;
+  r.leaf_split = best_sp;
   r.ms_best = best;
   r.depth = 0;
   for (const Octree& t : P.trees) r.depth = std::max(r.depth, t.depth);

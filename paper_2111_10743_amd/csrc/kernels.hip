@@ -742,6 +742,16 @@ constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
 // the far field over the harmonic orders m = f (mod F), the near field over
 // the source indices j = f (mod F) of each LDS chunk; the F partial sums of
 // a target (contiguous lanes) are then added by shuffles.
+// LDS bytes of the L2P expansions of one block (local, gradient and Hessian
+// expansions), rounded up to 16; the far-only kernel's reduction area follows.
+template <typename T>
+__host__ __device__ inline size_t leaf_exp_bytes(int mode, int p) {
+  const size_t L = (size_t)(p + 1) * (p + 1), nexp = fmm_nexp(mode);
+  const size_t b = sizeof(T) * (nexp * L + nexp * 3 * (size_t)p * p + 9 * (size_t)(p - 1) * (p - 1));
+  return (b + 15) / 16 * 16;
+}
+constexpr size_t LEAF_RED_BYTES = sizeof(double) * 4 * LEAF_BS;  // reduction area of non-power-of-two F
+
 // PART: LEAF_BOTH (far and near, outputs written), LEAF_NEAR (near-field
 // sums only, outputs written), LEAF_FAR (L2P only, added to the outputs).
 enum { LEAF_BOTH = 0, LEAF_NEAR = 1, LEAF_FAR = 2 };
@@ -751,21 +761,23 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
                                                   int64_t No, const T* __restrict__ Lc, T* __restrict__ D,
                                                   T* __restrict__ out, int64_t N) {
   extern __shared__ unsigned char smraw[];
-  const int b = t.leaf_tgt_list[blockIdx.x];
+  const int4 wk = t.leaf_work[blockIdx.x];
+  const int b = wk.x;
   const int g = t.leaf_box[b];
   const int rhs = blockIdx.y;
   const int p = t.p, L = t.L, Lg = p * p, Lh = (p - 1) * (p - 1);
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
   const bool far = PART != LEAF_NEAR && t.leaf_lvl[b] >= 2;
-  const int tbeg = t.tgt_beg[b], tend = t.tgt_end[b];
-  int F = t.leaf_fmax;
-  while (F > 1 && F * (tend - tbeg) > LEAF_BS) F >>= 1;
-  const int TPB = LEAF_BS / F;
-  const int slot = threadIdx.x / F, f = threadIdx.x % F;
+  const int tbeg = wk.y, tend = wk.z;
+  const int F = wk.w;                            // 1 <= F <= 64
+  const bool pow2 = (F & (F - 1)) == 0;
+  const int TPB = LEAF_BS / F;                   // target slots; threads past TPB * F only help staging
+  const int slot = threadIdx.x / F, f = threadIdx.x - (threadIdx.x / F) * F;
   // expansions for L2P: local [nexp][L], derived gradient [nexp][3][Lg] and
   // hessian [6][Lh] (+ 3 [Lh] scratch; A3B: expansion 1), in LDS after the
   // source chunk when EXP_LDS, else in this block's slice of D
   constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ || MODE == FMM_ADJ3 ? 9 : 5;  // T values per source record
+  static_assert(REC * LEAF_CH * sizeof(T) >= LEAF_RED_BYTES, "the staging area doubles as the reduction area");
   T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
   const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
   const int64_t dstride = (int64_t)nexp * 3 * Lg + 9 * Lh;
@@ -827,7 +839,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   const int utot = PART == LEAF_FAR ? 0 : upref[nU];
   for (int i0 = tbeg; i0 < tend; i0 += TPB) {
     const int i = i0 + slot;
-    const bool act = i < tend;
+    const bool act = slot < TPB && i < tend;
     T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0, TR = 0;
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
     if (TMASK && act) TR = t.trm2[i];
@@ -1015,12 +1027,34 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         a0 += (double)q0; a1 += (double)q1; a2 += (double)q2; a3 += (double)q3;
       }
     }
-    // sum the F partials of each target (contiguous lanes)
-    for (int off = 1; off < F; off <<= 1) {
-      a0 += __shfl_xor(a0, off, 64);
-      a1 += __shfl_xor(a1, off, 64);
-      a2 += __shfl_xor(a2, off, 64);
-      a3 += __shfl_xor(a3, off, 64);
+    // sum the F partials of each target (contiguous lanes): by shuffles when
+    // F divides the wave, else through LDS (the source staging area, or the
+    // area after the expansions in the far-only kernel)
+    if (pow2) {
+      for (int off = 1; off < F; off <<= 1) {
+        a0 += __shfl_xor(a0, off, 64);
+        a1 += __shfl_xor(a1, off, 64);
+        a2 += __shfl_xor(a2, off, 64);
+        a3 += __shfl_xor(a3, off, 64);
+      }
+    } else {
+      double* red = reinterpret_cast<double*>(
+          PART == LEAF_FAR ? smraw + (EXP_LDS ? leaf_exp_bytes<T>(MODE, p) : 0) : smraw);
+      __syncthreads();  // the last chunk has been read by every thread
+      red[4 * threadIdx.x] = a0;
+      red[4 * threadIdx.x + 1] = a1;
+      red[4 * threadIdx.x + 2] = a2;
+      red[4 * threadIdx.x + 3] = a3;
+      __syncthreads();
+      if (act && f == 0) {
+        for (int k = 1; k < F; ++k) {
+          a0 += red[4 * (threadIdx.x + k)];
+          a1 += red[4 * (threadIdx.x + k) + 1];
+          a2 += red[4 * (threadIdx.x + k) + 2];
+          a3 += red[4 * (threadIdx.x + k) + 3];
+        }
+      }
+      __syncthreads();  // before the next pass stages sources or partials here
     }
     if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
@@ -1048,13 +1082,17 @@ static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const
                         int64_t N, int64_t No, hipStream_t st) {
   const int p = t.p, L = t.L;
   const int nexp = fmm_nexp(mode);
+  // LDS: staged sources (not in the far-only kernel; also the reduction
+  // area of non-power-of-two lanes per target, >= LEAF_RED_BYTES), then the
+  // expansions when they fit; the far-only kernel reduces after them
   const size_t chunk = part == LEAF_FAR ? 0
                        : sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
-  const size_t exps = part == LEAF_NEAR ? 0
-                      : sizeof(T) * ((size_t)nexp * L + (size_t)nexp * 3 * p * p + 9 * (size_t)(p - 1) * (p - 1));
-  const bool lds = chunk + exps <= 64 * 1024;
-  const size_t sml = lds ? chunk + exps : chunk;
-  dim3 grid(t.n_leaf_tgt, nrhs);
+  const size_t exps = part == LEAF_NEAR ? 0 : leaf_exp_bytes<T>(mode, p);
+  const size_t red = part == LEAF_FAR ? LEAF_RED_BYTES : 0;
+  const bool lds = chunk + exps + red <= 64 * 1024;
+  const size_t sml = (lds ? chunk + exps : chunk) + red;
+  (void)L; (void)nexp;
+  dim3 grid(t.n_leaf_work, nrhs);
 #define LEAF_LAUNCH(MD, PT)                                                                                    \
   if (lds)                                                                                                     \
     hipLaunchKernelGGL((k_leaf<T, MD, true, PT>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N); \

@@ -65,6 +65,7 @@ struct DevTree {
   const int *child;                              // [nbox][8]
   const int *child_src;                          // [nbox][8], -1 unless the child holds sources
   const int *leaf_tgt_list;  int n_leaf_tgt;     // leaves holding targets
+  const int4 *leaf_work;  int n_leaf_work;       // leaf-kernel blocks: (leaf, tbeg, tend, lanes per target)
   const int *leaf_src_list;  int n_leaf_src;     // leaves holding sources
   const int *lev_box_src;  const int *lev_box_src_ptr;  // per level: boxes with sources
   const int *lev_box_tgt;  const int *lev_box_tgt_ptr;  // per level: boxes with targets
@@ -187,7 +188,7 @@ struct PhaseTimer {
   void mark(int i, hipStream_t st) { if (on) (void)hipEventRecord(ev[i], st); }
 };
 
-// nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_tgt][nrhs][nexp*3*p^2 + 9*(p-1)^2]
+// nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_work][nrhs][nexp*3*p^2 + 9*(p-1)^2]
 template <typename T>
 void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
                 int64_t N, int64_t No, hipStream_t st, PhaseTimer* tm = nullptr);

@@ -69,10 +69,12 @@ TUNE_MAX = 32
 
 
 class TuneInfo(ctypes.Structure):
-    _fields_ = [("leaf_src", ctypes.c_int32), ("leaf_fmax", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("n_trials", ctypes.c_int32), ("ms_best", ctypes.c_double), ("ms_default", ctypes.c_double),
+    _fields_ = [("leaf_src", ctypes.c_int32), ("leaf_fmax", ctypes.c_int32), ("leaf_split", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("n_trials", ctypes.c_int32), ("ms_best", ctypes.c_double),
+                ("ms_default", ctypes.c_double),
                 ("trial_leaf_src", ctypes.c_int32 * TUNE_MAX), ("trial_fmax", ctypes.c_int32 * TUNE_MAX),
-                ("trial_depth", ctypes.c_int32 * TUNE_MAX), ("trial_ms", ctypes.c_double * TUNE_MAX)]
+                ("trial_split", ctypes.c_int32 * TUNE_MAX), ("trial_depth", ctypes.c_int32 * TUNE_MAX),
+                ("trial_ms", ctypes.c_double * TUNE_MAX)]
 
 
 class LBError(RuntimeError):
@@ -351,10 +353,11 @@ class Surface:
         info = TuneInfo()
         _check(lib().lb_autotune(self._ctx, int(prec), int(nd), ctypes.byref(info), _stream()))
         n = info.n_trials
-        return {"leaf_src": info.leaf_src, "leaf_fmax": info.leaf_fmax, "depth": info.depth,
-                "ms_best": info.ms_best, "ms_default": info.ms_default,
+        return {"leaf_src": info.leaf_src, "leaf_fmax": info.leaf_fmax, "leaf_split": info.leaf_split,
+                "depth": info.depth, "ms_best": info.ms_best, "ms_default": info.ms_default,
                 "trials": [{"leaf_src": info.trial_leaf_src[i], "leaf_fmax": info.trial_fmax[i],
-                            "depth": info.trial_depth[i], "ms": info.trial_ms[i]} for i in range(n)]}
+                            "leaf_split": info.trial_split[i], "depth": info.trial_depth[i],
+                            "ms": info.trial_ms[i]} for i in range(n)]}
 
     def apply_gradS_timed(self, sigma):
         """apply_gradS plus per-phase milliseconds (HIP events on the stream)."""

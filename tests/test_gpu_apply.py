@@ -260,7 +260,9 @@ def test_autotune_rebuilds_consistently(torch_dev):
         assert len(t["trials"]) >= 3
         ms = [q["ms"] for q in t["trials"]]
         assert t["ms_best"] == min(ms) and t["ms_default"] in ms
-        assert any(q["leaf_src"] == t["leaf_src"] and q["leaf_fmax"] == t["leaf_fmax"] for q in t["trials"])
+        assert any(q["leaf_src"] == t["leaf_src"] and q["leaf_fmax"] == t["leaf_fmax"] and
+                   q["leaf_split"] == t["leaf_split"] for q in t["trials"])
+        assert {q["leaf_split"] for q in t["trials"]} == {0, 1, 2, 3}
         assert len({q["depth"] for q in t["trials"]}) >= 2
         dt = torch.float64 if prec == 64 else torch.float32
         out = s.apply_gradS(torch.tensor(sig, dtype=dt, device="cuda"))
