@@ -271,8 +271,8 @@ lb_status lb_apply_gradS_timed(lb_ctx *ctx, int nd, int prec, const void *sigma,
  * most leaf_src, coarsened in FP32 so that the leaf side stays above the
  * near-mask radius) and leaf_fmax in {64, 32, 16} (most lanes per target,
  * one block per leaf: leaf_split 0), then, at the fastest of those,
- * leaf_split in {1, 2, 3} (a leaf cut into up to that many blocks, any
- * number of lanes per target), and keeps the fastest configuration.  Corrections and
+ * leaf_split in {1, 2, 3} (a leaf cut into up to that many blocks), and
+ * keeps the fastest configuration.  Corrections and
  * node data are kept; captured GMRES graphs and transposed trees are dropped
  * and rebuilt on next use.  Results are the same operator up to the FMM
  * truncation error.  A direct context (LB_DIRECT) tunes leaf_fmax only.

@@ -332,14 +332,14 @@ static void merge_forest(const std::vector<Octree>& trees, const std::vector<int
 }
 
 // Work items of the leaf kernel: one block evaluates targets [tbeg, tend) of
-// one leaf with F lanes per target (256 / F target slots).  split = 0: one
-// block per leaf, F the largest power of two <= fmax with F a <= 256 for a
-// leaf of a targets.  split = s >= 1: a leaf whose U-list holds u sources is
-// cut into m <= s items of ceil(a / m) targets with any F =
-// min(fmax, 256 / ceil(a / m)), m minimizing m (u / F + 2 u / 256 + 8)
-// (near-field iterations per lane, staging of the sources, a fixed cost per
-// block).  Items are ordered heaviest first so that the grid does not end on
-// a tail of large blocks.
+// one leaf with F lanes per target (F a power of two, 256 / F target slots).
+// split = 0: one block per leaf, F the largest power of two <= fmax with
+// F a <= 256 for a leaf of a targets.  split = s >= 1: a leaf whose U-list
+// holds u sources is cut into m <= s items of ceil(a / m) targets, F the
+// largest power of two <= min(fmax, 256 / ceil(a / m)), m minimizing
+// m (u / F + 2 u / 256 + 8) (near-field iterations per lane, staging of the
+// sources, a fixed cost per block).  Items are ordered heaviest first so
+// that the grid does not end on a tail of large blocks.
 template <typename T>
 static void make_leaf_work(Prec<T>& P, int fmax, int split) {
   struct Item { int leaf, tbeg, tend, F; double cost; };
@@ -355,7 +355,8 @@ static void make_leaf_work(Prec<T>& P, int fmax, int split) {
     }
     for (int m = 1; m <= split; ++m) {
       const int per = (a + m - 1) / m;
-      const int F = std::max(1, std::min(fmax, 256 / std::max(per, 1)));
+      int F = fmax;
+      while (F > 1 && F * per > 256) F >>= 1;
       const double c = m * (u / F + 2.0 * u / 256.0 + 8.0);
       if (c < bc) { bc = c; bm = m; bF = F; }
     }

@@ -743,14 +743,13 @@ constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
 // the source indices j = f (mod F) of each LDS chunk; the F partial sums of
 // a target (contiguous lanes) are then added by shuffles.
 // LDS bytes of the L2P expansions of one block (local, gradient and Hessian
-// expansions), rounded up to 16; the far-only kernel's reduction area follows.
+// expansions), rounded up to 16.
 template <typename T>
 __host__ __device__ inline size_t leaf_exp_bytes(int mode, int p) {
   const size_t L = (size_t)(p + 1) * (p + 1), nexp = fmm_nexp(mode);
   const size_t b = sizeof(T) * (nexp * L + nexp * 3 * (size_t)p * p + 9 * (size_t)(p - 1) * (p - 1));
   return (b + 15) / 16 * 16;
 }
-constexpr size_t LEAF_RED_BYTES = sizeof(double) * 4 * LEAF_BS;  // reduction area of non-power-of-two F
 
 // PART: LEAF_BOTH (far and near, outputs written), LEAF_NEAR (near-field
 // sums only, outputs written), LEAF_FAR (L2P only, added to the outputs).
@@ -769,15 +768,13 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
   const bool far = PART != LEAF_NEAR && t.leaf_lvl[b] >= 2;
   const int tbeg = wk.y, tend = wk.z;
-  const int F = wk.w;                            // 1 <= F <= 64
-  const bool pow2 = (F & (F - 1)) == 0;
-  const int TPB = LEAF_BS / F;                   // target slots; threads past TPB * F only help staging
+  const int F = wk.w;                            // lanes per target: a power of two <= 64
+  const int TPB = LEAF_BS / F;                   // target slots
   const int slot = threadIdx.x / F, f = threadIdx.x - (threadIdx.x / F) * F;
   // expansions for L2P: local [nexp][L], derived gradient [nexp][3][Lg] and
   // hessian [6][Lh] (+ 3 [Lh] scratch; A3B: expansion 1), in LDS after the
   // source chunk when EXP_LDS, else in this block's slice of D
   constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ || MODE == FMM_ADJ3 ? 9 : 5;  // T values per source record
-  static_assert(REC * LEAF_CH * sizeof(T) >= LEAF_RED_BYTES, "the staging area doubles as the reduction area");
   T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
   const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
   const int64_t dstride = (int64_t)nexp * 3 * Lg + 9 * Lh;
@@ -791,7 +788,27 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     sG = D + ((int64_t)blockIdx.x * nrhs + rhs) * dstride;
   }
   T* sH = sG + nexp * 3 * Lg;
+  // recurrence coefficients of the regular solid harmonics (p <= 31):
+  // R_m^m = sect[m] (x + i y) R_{m-1}^{m-1}, R_{m+1}^m = up[m] z R_m^m,
+  // R_{n+1}^m = a[n,m] z R_n^m - b[n,m] r^2 R_{n-1}^m
+  __shared__ T rtab[2 * 32 + 2 * 528];
+  T* rt_sect = rtab;
+  T* rt_up = rtab + 32;
+  T* rt_a = rtab + 64;
+  T* rt_b = rtab + 64 + 528;
   if (far) {
+    for (int c = threadIdx.x; c < (p + 1) * (p + 2) / 2; c += blockDim.x) {
+      int n = 0;
+      while ((n + 1) * (n + 2) / 2 <= c) ++n;
+      const int m = c - n * (n + 1) / 2;
+      const double dn = 1.0 / sqrt((double)((n + 1 + m) * (n + 1 - m)));
+      rt_a[c] = (T)((2 * n + 1) * dn);
+      rt_b[c] = (T)(sqrt((double)((n + m) * (n - m))) * dn);
+    }
+    for (int m = threadIdx.x; m <= p; m += blockDim.x) {
+      rt_sect[m] = m > 0 ? (T)(-sqrt((double)(2 * m - 1) / (double)(2 * m))) : (T)1;
+      rt_up[m] = (T)sqrt((double)(2 * m + 1));
+    }
     if (EXP_LDS) {
       for (int i = threadIdx.x; i < nexp * L; i += blockDim.x) sL[i] = gL[i];
       __syncthreads();
@@ -839,7 +856,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
   const int utot = PART == LEAF_FAR ? 0 : upref[nU];
   for (int i0 = tbeg; i0 < tend; i0 += TPB) {
     const int i = i0 + slot;
-    const bool act = slot < TPB && i < tend;
+    const bool act = i < tend;
     T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0, TR = 0;
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
     if (TMASK && act) TR = t.trm2[i];
@@ -850,28 +867,28 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       const T r2 = x * x + y * y + z * z;
       T pot = 0, pot2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
       T mre = 1, mim = 0;
-      for (int m = 0; m <= p; ++m) {
+      // orders m go to the F lanes back and forth (f, 2F-1-f, 2F+f, ...) so
+      // that the triangular n loops are balanced across the lanes
+      for (int m = 0, mq = 0, mr = 0; m <= p; ++m, mr = (mr + 1 == F ? 0 : mr + 1), mq += (mr == 0 && m > 0)) {
         if (m > 0) {
-          T fm = -sqrt((T)(2 * m - 1) / (T)(2 * m));
+          const T fm = rt_sect[m];
           T nr = fm * (x * mre - y * mim);
           T ni = fm * (x * mim + y * mre);
           mre = nr; mim = ni;
         }
-        if (m % F != f) continue;
+        if ((mq & 1 ? F - 1 - mr : mr) != f) continue;
         T are = 0, aim = 0, bre = mre, bim = mim;  // R_{n-1}, R_n with n = m
         for (int n = m; n <= p; ++n) {
           if (n > m) {
             T cre, cim;
             if (n == m + 1) {
-              T c1 = z * sqrt((T)(2 * m + 1));
+              T c1 = z * rt_up[m];
               cre = c1 * bre; cim = c1 * bim;
             } else {
-              const int nn = n - 1;
-              T f1 = (T)(2 * nn + 1) * z;
-              T f2 = r2 * sqrt((T)((nn + m) * (nn - m)));
-              T dn = (T)1 / sqrt((T)((nn + 1 + m) * (nn + 1 - m)));
-              cre = (f1 * bre - f2 * are) * dn;
-              cim = (f1 * bim - f2 * aim) * dn;
+              const int cc = cidx(n - 1, m);
+              const T f1 = rt_a[cc] * z, f2 = rt_b[cc] * r2;
+              cre = f1 * bre - f2 * are;
+              cim = f1 * bim - f2 * aim;
             }
             are = bre; aim = bim; bre = cre; bim = cim;
           }
@@ -1027,34 +1044,12 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
         a0 += (double)q0; a1 += (double)q1; a2 += (double)q2; a3 += (double)q3;
       }
     }
-    // sum the F partials of each target (contiguous lanes): by shuffles when
-    // F divides the wave, else through LDS (the source staging area, or the
-    // area after the expansions in the far-only kernel)
-    if (pow2) {
-      for (int off = 1; off < F; off <<= 1) {
-        a0 += __shfl_xor(a0, off, 64);
-        a1 += __shfl_xor(a1, off, 64);
-        a2 += __shfl_xor(a2, off, 64);
-        a3 += __shfl_xor(a3, off, 64);
-      }
-    } else {
-      double* red = reinterpret_cast<double*>(
-          PART == LEAF_FAR ? smraw + (EXP_LDS ? leaf_exp_bytes<T>(MODE, p) : 0) : smraw);
-      __syncthreads();  // the last chunk has been read by every thread
-      red[4 * threadIdx.x] = a0;
-      red[4 * threadIdx.x + 1] = a1;
-      red[4 * threadIdx.x + 2] = a2;
-      red[4 * threadIdx.x + 3] = a3;
-      __syncthreads();
-      if (act && f == 0) {
-        for (int k = 1; k < F; ++k) {
-          a0 += red[4 * (threadIdx.x + k)];
-          a1 += red[4 * (threadIdx.x + k) + 1];
-          a2 += red[4 * (threadIdx.x + k) + 2];
-          a3 += red[4 * (threadIdx.x + k) + 3];
-        }
-      }
-      __syncthreads();  // before the next pass stages sources or partials here
+    // sum the F partials of each target (contiguous lanes; F divides 64)
+    for (int off = 1; off < F; off <<= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+      a2 += __shfl_xor(a2, off, 64);
+      a3 += __shfl_xor(a3, off, 64);
     }
     if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
@@ -1082,15 +1077,13 @@ static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const
                         int64_t N, int64_t No, hipStream_t st) {
   const int p = t.p, L = t.L;
   const int nexp = fmm_nexp(mode);
-  // LDS: staged sources (not in the far-only kernel; also the reduction
-  // area of non-power-of-two lanes per target, >= LEAF_RED_BYTES), then the
-  // expansions when they fit; the far-only kernel reduces after them
+  // LDS: staged sources (not in the far-only kernel), then the expansions
+  // when they fit
   const size_t chunk = part == LEAF_FAR ? 0
                        : sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
   const size_t exps = part == LEAF_NEAR ? 0 : leaf_exp_bytes<T>(mode, p);
-  const size_t red = part == LEAF_FAR ? LEAF_RED_BYTES : 0;
-  const bool lds = chunk + exps + red <= 64 * 1024;
-  const size_t sml = (lds ? chunk + exps : chunk) + red;
+  const bool lds = chunk + exps <= 64 * 1024;
+  const size_t sml = lds ? chunk + exps : chunk;
   (void)L; (void)nexp;
   dim3 grid(t.n_leaf_work, nrhs);
 #define LEAF_LAUNCH(MD, PT)                                                                                    \
