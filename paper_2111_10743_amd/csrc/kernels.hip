@@ -95,6 +95,40 @@ void launch_strengths(const T* tau, int ne, int64_t N, int NP, int n_p, int n_o,
 // ---------------------------------------------------------------------------
 // solid harmonics Rt_n^m (normalized regular) of xi into LDS rows (re, im)
 // ---------------------------------------------------------------------------
+// Recurrence coefficients of the normalized regular solid harmonics
+// (p <= 31), kept in LDS by each block:
+//   Rt_m^m = sect[m] (x + i y) Rt_{m-1}^{m-1},  Rt_{m+1}^m = up[m] z Rt_m^m,
+//   Rt_{n+1}^m = a[n,m] z Rt_n^m - b[n,m] r^2 Rt_{n-1}^m   (index cidx(n, m)),
+// sect[m] = -sqrt((2m-1)/(2m)), up[m] = sqrt(2m+1),
+// a = (2n+1) / sqrt((n+1+m)(n+1-m)), b = sqrt((n+m)(n-m)) / sqrt((n+1+m)(n+1-m)),
+// evaluated in FP64 and rounded once.
+constexpr int RECTAB_N = 2 * 32 + 2 * 528;
+template <typename T>
+struct RecTab {
+  T* sect;
+  T* up;
+  T* a;
+  T* b;
+  __device__ explicit RecTab(T* base) : sect(base), up(base + 32), a(base + 64), b(base + 64 + 528) {}
+};
+
+// block-cooperative fill (the caller synchronizes before use)
+template <typename T>
+__device__ void fill_rectab(const RecTab<T>& rt, int p) {
+  for (int c = threadIdx.x; c < (p + 1) * (p + 2) / 2; c += blockDim.x) {
+    int n = 0;
+    while ((n + 1) * (n + 2) / 2 <= c) ++n;
+    const int m = c - n * (n + 1) / 2;
+    const double dn = 1.0 / sqrt((double)((n + 1 + m) * (n + 1 - m)));
+    rt.a[c] = (T)((2 * n + 1) * dn);
+    rt.b[c] = (T)(sqrt((double)((n + m) * (n - m))) * dn);
+  }
+  for (int m = threadIdx.x; m <= p; m += blockDim.x) {
+    rt.sect[m] = m > 0 ? (T)(-sqrt((double)(2 * m - 1) / (double)(2 * m))) : (T)1;
+    rt.up[m] = (T)sqrt((double)(2 * m + 1));
+  }
+}
+
 template <typename T>
 __device__ void regular_to_lds(int p, T x, T y, T z, T* re, T* im) {
   const T r2 = x * x + y * y + z * z;
@@ -132,11 +166,11 @@ __device__ void regular_to_lds(int p, T x, T y, T z, T* re, T* im) {
 // Column m of the normalized regular harmonics, Rt_n^m for n = m..p, into
 // LDS rows (re, im).  Rt_m^m = prod_{j<=m} (-(x+iy) sqrt((2j-1)/(2j))).
 template <typename T>
-__device__ void regular_column_to_lds(int p, int m, T x, T y, T z, T* re, T* im) {
+__device__ void regular_column_to_lds(const RecTab<T>& rt, int p, int m, T x, T y, T z, T* re, T* im) {
   const T r2 = x * x + y * y + z * z;
   T mre = 1, mim = 0;
   for (int j = 1; j <= m; ++j) {
-    const T f = -sqrt((T)(2 * j - 1) / (T)(2 * j));
+    const T f = rt.sect[j];
     const T nr = f * (x * mre - y * mim);
     const T ni = f * (x * mim + y * mre);
     mre = nr;
@@ -145,16 +179,15 @@ __device__ void regular_column_to_lds(int p, int m, T x, T y, T z, T* re, T* im)
   re[cidx(m, m)] = mre;
   im[cidx(m, m)] = mim;
   if (m + 1 > p) return;
-  const T c1 = z * sqrt((T)(2 * m + 1));
+  const T c1 = z * rt.up[m];
   T are = mre, aim = mim, bre = c1 * mre, bim = c1 * mim;
   re[cidx(m + 1, m)] = bre;
   im[cidx(m + 1, m)] = bim;
   for (int n = m + 1; n < p; ++n) {
-    const T f1 = (T)(2 * n + 1) * z;
-    const T f2 = r2 * sqrt((T)((n + m) * (n - m)));
-    const T dn = (T)1 / sqrt((T)((n + 1 + m) * (n + 1 - m)));
-    const T cre = (f1 * bre - f2 * are) * dn;
-    const T cim = (f1 * bim - f2 * aim) * dn;
+    const int c = cidx(n, m);
+    const T f1 = rt.a[c] * z, f2 = rt.b[c] * r2;
+    const T cre = f1 * bre - f2 * are;
+    const T cim = f1 * bim - f2 * aim;
     re[cidx(n + 1, m)] = cre;
     im[cidx(n + 1, m)] = cim;
     are = bre; aim = bim;
@@ -183,6 +216,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, const T* __restrict__ str,
                                              int64_t No, T* __restrict__ M, int P2M_TS) {
   extern __shared__ unsigned char smraw[];
+  __shared__ T rtab[RECTAB_N];
+  const RecTab<T> rt(rtab);
+  fill_rectab(rt, t.p);
+  __syncthreads();
   const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
   T* Rre = reinterpret_cast<T*>(smraw);
   T* Rim = Rre + P2M_TS * Lc;
@@ -207,7 +244,7 @@ __global__ __launch_bounds__(256) void k_p2m(DevTree<T> t, int mode, int nrhs, c
     for (int task = threadIdx.x; task < nt * (p + 1); task += blockDim.x) {
       const int j = task / (p + 1), m = task - j * (p + 1);
       const int s = t0 + j;
-      regular_column_to_lds<T>(p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
+      regular_column_to_lds<T>(rt, p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
                                Rim + j * Lc);
     }
     if (threadIdx.x < nt) {
@@ -289,6 +326,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_p2m_adj3(DevTree<T> t, int nrhs, const T* __restrict__ str, int64_t No,
                                                   T* __restrict__ M, int ts) {
   extern __shared__ unsigned char smraw[];
+  __shared__ T rtab[RECTAB_N];
+  const RecTab<T> rt(rtab);
+  fill_rectab(rt, t.p);
+  __syncthreads();
   const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
   T* Rre = reinterpret_cast<T*>(smraw);
   T* Rim = Rre + ts * Lc;
@@ -311,7 +352,7 @@ __global__ __launch_bounds__(256) void k_p2m_adj3(DevTree<T> t, int nrhs, const 
     for (int task = threadIdx.x; task < nt * (p + 1); task += blockDim.x) {
       const int j = task / (p + 1), m = task - j * (p + 1);
       const int s = t0 + j;
-      regular_column_to_lds<T>(p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
+      regular_column_to_lds<T>(rt, p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
                                Rim + j * Lc);
     }
     if (threadIdx.x < nt) {
@@ -387,6 +428,10 @@ __global__ __launch_bounds__(256) void k_p2m_adj3(DevTree<T> t, int nrhs, const 
 template <typename T>
 __global__ __launch_bounds__(256) void k_p2m_build(DevTree<T> t, T* __restrict__ H, T* __restrict__ Dp, int ts) {
   extern __shared__ unsigned char smraw[];
+  __shared__ T rtab[RECTAB_N];
+  const RecTab<T> rt(rtab);
+  fill_rectab(rt, t.p);
+  __syncthreads();
   const int p = t.p, L = t.L, Lc = (p + 1) * (p + 2) / 2;
   T* Rre = reinterpret_cast<T*>(smraw);
   T* Rim = Rre + ts * Lc;
@@ -402,7 +447,7 @@ __global__ __launch_bounds__(256) void k_p2m_build(DevTree<T> t, T* __restrict__
     for (int task = threadIdx.x; task < nt * (p + 1); task += blockDim.x) {
       const int j = task / (p + 1), m = task - j * (p + 1);
       const int s = t0 + j;
-      regular_column_to_lds<T>(p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
+      regular_column_to_lds<T>(rt, p, m, (t.sx[s] - cx) * ih, (t.sy[s] - cy) * ih, (t.sz[s] - cz) * ih, Rre + j * Lc,
                                Rim + j * Lc);
     }
     if (threadIdx.x < nt) {
@@ -443,7 +488,7 @@ template <typename T>
 void launch_p2m_tables(const DevTree<T>& t, T* H, T* Dp, hipStream_t st) {
   if (t.depth < 2 || t.n_leaf_src == 0) return;
   const int Lc = (t.p + 1) * (t.p + 2) / 2;
-  int ts = (int)((48 * 1024 / sizeof(T)) / (2 * Lc + 3));
+  int ts = (int)((48 * 1024 / sizeof(T) - RECTAB_N) / (2 * Lc + 3));
   ts = ts < 1 ? 1 : (ts > 64 ? 64 : ts);
   const size_t sm = sizeof(T) * (size_t)ts * (2 * Lc + 3);
   hipLaunchKernelGGL(k_p2m_build<T>, dim3(t.n_leaf_src), dim3(256), sm, st, t, H, Dp, ts);
@@ -788,27 +833,11 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
     sG = D + ((int64_t)blockIdx.x * nrhs + rhs) * dstride;
   }
   T* sH = sG + nexp * 3 * Lg;
-  // recurrence coefficients of the regular solid harmonics (p <= 31):
-  // R_m^m = sect[m] (x + i y) R_{m-1}^{m-1}, R_{m+1}^m = up[m] z R_m^m,
-  // R_{n+1}^m = a[n,m] z R_n^m - b[n,m] r^2 R_{n-1}^m
-  __shared__ T rtab[2 * 32 + 2 * 528];
-  T* rt_sect = rtab;
-  T* rt_up = rtab + 32;
-  T* rt_a = rtab + 64;
-  T* rt_b = rtab + 64 + 528;
+  // recurrence coefficients of the solid harmonics for L2P
+  __shared__ T rtab[RECTAB_N];
+  const RecTab<T> rt(rtab);
   if (far) {
-    for (int c = threadIdx.x; c < (p + 1) * (p + 2) / 2; c += blockDim.x) {
-      int n = 0;
-      while ((n + 1) * (n + 2) / 2 <= c) ++n;
-      const int m = c - n * (n + 1) / 2;
-      const double dn = 1.0 / sqrt((double)((n + 1 + m) * (n + 1 - m)));
-      rt_a[c] = (T)((2 * n + 1) * dn);
-      rt_b[c] = (T)(sqrt((double)((n + m) * (n - m))) * dn);
-    }
-    for (int m = threadIdx.x; m <= p; m += blockDim.x) {
-      rt_sect[m] = m > 0 ? (T)(-sqrt((double)(2 * m - 1) / (double)(2 * m))) : (T)1;
-      rt_up[m] = (T)sqrt((double)(2 * m + 1));
-    }
+    fill_rectab(rt, p);
     if (EXP_LDS) {
       for (int i = threadIdx.x; i < nexp * L; i += blockDim.x) sL[i] = gL[i];
       __syncthreads();
@@ -871,7 +900,7 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
       // that the triangular n loops are balanced across the lanes
       for (int m = 0, mq = 0, mr = 0; m <= p; ++m, mr = (mr + 1 == F ? 0 : mr + 1), mq += (mr == 0 && m > 0)) {
         if (m > 0) {
-          const T fm = rt_sect[m];
+          const T fm = rt.sect[m];
           T nr = fm * (x * mre - y * mim);
           T ni = fm * (x * mim + y * mre);
           mre = nr; mim = ni;
@@ -882,11 +911,11 @@ __global__ __launch_bounds__(LEAF_BS) void k_leaf(DevTree<T> t, int nrhs, const 
           if (n > m) {
             T cre, cim;
             if (n == m + 1) {
-              T c1 = z * rt_up[m];
+              T c1 = z * rt.up[m];
               cre = c1 * bre; cim = c1 * bim;
             } else {
               const int cc = cidx(n - 1, m);
-              const T f1 = rt_a[cc] * z, f2 = rt_b[cc] * r2;
+              const T f1 = rt.a[cc] * z, f2 = rt.b[cc] * r2;
               cre = f1 * bre - f2 * are;
               cim = f1 * bim - f2 * aim;
             }
@@ -1138,7 +1167,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   }
   if (t.depth >= 2) {
     // source tile of P2M: harmonic tables of ts sources within 48 KiB of LDS
-    int ts = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (2 * Lc_));
+    int ts = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
     if (t.p2m_H && (mode == FMM_ADJ || mode == FMM_ADJ3)) {
@@ -1146,7 +1175,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
       return;
     }
     if (mode == FMM_ADJ3) {
-      int ts3 = (int)((48 * 1024 / sizeof(T) - 5 * P2M_TSMAX) / (4 * Lc_));
+      int ts3 = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (4 * Lc_));
       ts3 = ts3 < 1 ? 1 : (ts3 > P2M_TSMAX ? P2M_TSMAX : ts3);
       const size_t sm3 = sizeof(T) * (4 * (size_t)ts3 * Lc_ + 5 * ts3);
       hipLaunchKernelGGL(k_p2m_adj3<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm3, st, t, nrhs, str, No, M, ts3);
