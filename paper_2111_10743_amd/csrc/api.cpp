@@ -1775,14 +1775,21 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   std::vector<double> mean((size_t)nrhs * nsf);
   HIPTRY(hipMemcpyAsync(mean.data(), means.p, sizeof(double) * mean.size(), hipMemcpyDeviceToHost, st));
   const Systems sy = make_systems(ctx, nrhs);
+  const std::vector<double> fn = system_norms(ctx, sy, f, st);
   if (ctx->opts.flags & LB_STRICT_MEAN) {
-    std::vector<double> fn = system_norms(ctx, sy, f, st);
     for (size_t a = 0; a < fn.size(); ++a)
       if (std::fabs(mean[a]) > 1e-12 * fn[a])
         fail(LB_ENOTMEANZERO, "right-hand side %d (surface %d) has weighted mean %g", (int)(a / nsf), (int)(a % nsf),
              mean[a]);
   }
-  const std::vector<double> fnorm = system_norms(ctx, sy, fz, st);
+  std::vector<double> fnorm = system_norms(ctx, sy, fz, st);
+  // a right-hand side that is constant up to rounding leaves only rounding
+  // noise after the projection: it is the zero right-hand side (u = 0)
+  for (size_t a = 0; a < fnorm.size(); ++a)
+    if (fnorm[a] > 0 && fnorm[a] <= 1e-13 * fn[a]) {
+      HIPTRY(hipMemsetAsync(fz + sy.xoff[a], 0, sizeof(double) * (size_t)sy.len[a], st));
+      fnorm[a] = 0.0;
+    }
   std::vector<double> rel;
   std::vector<int> iters, outer;
   solve_system(ctx, nrhs, sy, A64, A32, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel, iters, outer, st);

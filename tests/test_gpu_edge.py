@@ -1,0 +1,168 @@
+"""Edge and degenerate cases through the C ABI.
+
+* Right-hand sides that vanish after the mean projection (f = 0 and
+  f = constant: Lemma 1 needs mean-zero data, and the constant is exactly
+  what the projection removes): u = 0 with no iteration, next to a regular
+  right-hand side in the same batched solve, which must equal its solve
+  alone.
+* Density counts that are not multiples of the per-traversal chunks (8 for
+  the gradient apply and its transpose, 2 for A3, 4 for A3^T): every density
+  equals its own single-density apply bit for bit.
+* A surface of one patch (its own near list, a one-leaf tree), against the
+  oracle on every row.
+* The largest order (k = 7, 36 nodes per patch) against the oracle on
+  sampled rows.
+* LB_STRICT_MEAN: f with a mean is rejected (LB_ENOTMEANZERO), mean-zero f
+  solves; argument errors on a live context.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import lbinputs as I
+from conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def sphere80(torch_dev):
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.sphere_patches(1, nodes(4))
+    s = P.Surface(X, Xu, Xv, 4)
+    yield s, X
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_vanishing_right_hand_sides(torch_dev, sphere80, mode):
+    torch = torch_dev
+    s, X = sphere80
+    x = X.reshape(-1, 3)
+    f_reg = x[:, 0] * x[:, 2] + 0.3 * x[:, 1]
+    F = np.stack([np.zeros(s.N), np.full(s.N, 2.5), f_reg])
+    note(f"vanishing rhs mode={mode}: batch of 3")
+    u, info, code = s.solve(torch.tensor(F, device="cuda"), tol=1e-12, mode=mode)
+    note(f"vanishing rhs info {info}")
+    assert code == 0
+    u = u.cpu().numpy()
+    assert np.all(u[0] == 0.0) and np.all(u[1] == 0.0)
+    assert info[0]["iters"] == 0 and info[1]["iters"] == 0
+    assert abs(info[1]["removed_mean"] - 2.5) < 1e-12
+    u1, info1, code1 = s.solve(torch.tensor(F[2:], device="cuda"), tol=1e-12, mode=mode)
+    assert code1 == 0 and info1[0]["iters"] == info[2]["iters"]
+    e = float(np.abs(u1.cpu().numpy()[0] - u[2]).max() / np.abs(u[2]).max())
+    note(f"vanishing rhs: regular rhs batched vs alone {e:.1e}")
+    assert e < 1e-14
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_ragged_density_counts(torch_dev, sphere80, prec):
+    torch = torch_dev
+    s, _ = sphere80
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(91)
+    for name, nd, fn in (("gradS", 9, lambda x: s.apply_gradS(x)["grad"]),
+                         ("A3", 3, s.apply_A3),
+                         ("S^T", 9, s.apply_S_adj),
+                         ("A3^T", 5, s.apply_A3_adj)):
+        x = torch.tensor(rng.standard_normal((nd, s.N)), dtype=dt, device="cuda")
+        note(f"ragged {name} nd={nd} prec={prec}")
+        full = fn(x)
+        for d in range(nd):
+            one = fn(x[d:d + 1].contiguous())
+            assert torch.equal(full[d:d + 1], one), (name, d)
+
+
+def test_single_patch(torch_dev):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.sphere_patches(0, nodes(4))
+    X, Xu, Xv = X[:1], Xu[:1], Xv[:1]
+    g = Geometry(X, Xu, Xv, 4)
+    o = Oracle(g)
+    sig = np.cos(3 * g.x[:, 0]) + g.x[:, 1]
+    L = o.layer(sig)
+    for direct in (False, True):
+        note(f"single patch direct={direct}")
+        s = P.Surface(X, Xu, Xv, 4, direct=direct)
+        for prec, tol in ((64, 1e-9), (32, 1e-6)):
+            dt = torch.float64 if prec == 64 else torch.float32
+            out = s.apply_gradS(torch.tensor(sig, dtype=dt, device="cuda"))
+            e1 = rel_l2(out["pot"].double().cpu().numpy(), L[:, 0])
+            e2 = rel_l2(out["grad"].double().cpu().numpy(), L[:, 1:4])
+            note(f"single patch direct={direct} prec={prec}: pot {e1:.1e} grad {e2:.1e}")
+            assert e1 < tol and e2 < tol
+        s.close()
+
+
+def test_max_order(torch_dev):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.sphere_patches(1, nodes(7))
+    g = Geometry(X, Xu, Xv, 7)
+    rows = np.arange(0, g.N, 23)
+    o = Oracle(g, rows)
+    sig = I.real_sph_harm(5, 2, g.x) + 0.1 * g.x[:, 2]
+    L = o.layer(sig)
+    note(f"order 7 N={g.N}")
+    s = P.Surface(X, Xu, Xv, 7)
+    for prec, tol in ((64, 1e-9), (32, 1e-6)):
+        dt = torch.float64 if prec == 64 else torch.float32
+        out = s.apply_gradS(torch.tensor(sig, dtype=dt, device="cuda"))
+        e1 = rel_l2(out["pot"].double().cpu().numpy()[rows], L[:, 0])
+        e2 = rel_l2(out["grad"].double().cpu().numpy()[rows], L[:, 1:4])
+        note(f"order 7 prec={prec}: pot {e1:.1e} grad {e2:.1e}")
+        assert e1 < tol and e2 < tol
+    s.close()
+
+
+def test_strict_mean_and_argument_errors(torch_dev):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.sphere_patches(1, nodes(4))
+    s = P.Surface(X, Xu, Xv, 4, flags=P.LB_STRICT_MEAN)
+    x = X.reshape(-1, 3)
+    f = torch.tensor(x[:, 0] * x[:, 2] + 1.0, device="cuda")
+    note("strict mean: f with a mean")
+    with pytest.raises(P.LBError) as e:
+        s.solve(f, tol=1e-10)
+    assert e.value.code == P.LB_ENOTMEANZERO
+    fz = torch.tensor(x[:, 0] * x[:, 2], device="cuda")
+    u, info, code = s.solve(fz, tol=1e-10)
+    assert code == 0 and abs(info[0]["removed_mean"]) < 1e-12
+    lib = P.lib()
+    buf = torch.zeros(s.N, dtype=torch.float64, device="cuda")
+    ptr = ctypes.c_void_p(buf.data_ptr())
+    note("argument errors")
+    assert lib.lb_apply_S(s._ctx, 0, 64, ptr, ptr, None) == P.LB_EINVAL
+    assert lib.lb_apply_S(s._ctx, 1, 16, ptr, ptr, None) == P.LB_EINVAL
+    assert lib.lb_apply_gradS(s._ctx, 1, 64, ptr, ptr, None, None, None, None) == P.LB_EINVAL
+    assert lib.lb_apply_S_adj_X(s._ctx, 1, 64, ptr, ptr, None, None) == P.LB_EINVAL
+    assert lib.lb_autotune(s._ctx, 64, 65, None, None) == P.LB_EINVAL
+    with pytest.raises(ValueError):
+        s.apply_S_adj_X(buf, buf[:10])
+    s.close()
