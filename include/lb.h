@@ -82,6 +82,12 @@ typedef struct {
   int self_n;       /* self-patch rule: Gauss points along each Duffy ray    (default 16) */
   int near_q;       /* adaptive near rule: near_q x near_q points per leaf    (default 8)  */
   double near_adm;  /* adaptive near rule admissibility dist >= adm * diam    (default 2)  */
+  double m2l_trunc32; /* M2L order by offset, FP32 tree: an offset at centre distance d
+                         (box widths) translates the first (p_d+1)^2 coefficients,
+                         p_d = min(p, ceil(s p ln rho(2) / ln rho(d))), rho(d) = a/(d-a),
+                         a = sqrt(3)/2, s this factor; 0: order p for every offset
+                         (default 2.5) */
+  double m2l_trunc64; /* the same for the FP64 tree (default 2.0) */
 } lb_opts;
 
 typedef struct {

@@ -50,7 +50,7 @@ template <typename T> static inline T* dptr(const DBuf& b) { return reinterpret_
 
 struct PlanBuf {
   GemmPlan pl;
-  DBuf grp_mat, grp_beg, pair_src, boxes, box_scale, tptr, tpairs, work[9];
+  DBuf grp_mat, grp_beg, pair_src, boxes, box_scale, tptr, tpairs, grp_lo, pair_lo, work[9];
 };
 
 template <typename T>
@@ -60,8 +60,10 @@ static void upload(DBuf& d, const std::vector<T>& h);
 // target box that gets an output (boxes without triples get zeros unless
 // the plan accumulates).
 struct Triple { int mat, tgt, src; };
+// mat_lo (nullable: all L): active size of each matrix id's translation.
 static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<int>& boxes,
-                         const std::vector<double>& scale, bool scaled, bool accumulate, int nbox_total) {
+                         const std::vector<double>& scale, bool scaled, bool accumulate, int nbox_total, int L,
+                         const std::vector<int>& mat_lo = {}) {
   std::stable_sort(tr.begin(), tr.end(), [](const Triple& a, const Triple& b) {
     return a.mat != b.mat ? a.mat < b.mat : a.tgt < b.tgt;
   });
@@ -78,6 +80,13 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
   for (size_t b = 0; b < boxes.size(); ++b) tptr[b + 1] += tptr[b];
   std::vector<int> fill(tptr.begin(), tptr.end() - 1);
   for (size_t i = 0; i < tr.size(); ++i) tpairs[fill[slot[tr[i].tgt]]++] = (int)i;
+  std::vector<int> glo, plo;
+  if (!mat_lo.empty()) {
+    for (int m : gmat) glo.push_back(mat_lo[m]);
+    for (const Triple& q : tr) plo.push_back(mat_lo[q.mat]);
+    upload(pb.grp_lo, glo);
+    upload(pb.pair_lo, plo);
+  }
   upload(pb.grp_mat, gmat); upload(pb.grp_beg, gbeg); upload(pb.pair_src, psrc);
   upload(pb.boxes, boxes); upload(pb.box_scale, scale); upload(pb.tptr, tptr); upload(pb.tpairs, tpairs);
   GemmPlan& pl = pb.pl;
@@ -87,15 +96,22 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
   pl.grp_mat = dptr<int>(pb.grp_mat); pl.grp_beg = dptr<int>(pb.grp_beg); pl.pair_src = dptr<int>(pb.pair_src);
   pl.boxes = dptr<int>(pb.boxes); pl.box_scale = scaled ? dptr<double>(pb.box_scale) : nullptr;
   pl.tptr = dptr<int>(pb.tptr); pl.tpairs = dptr<int>(pb.tpairs);
+  pl.grp_lo = glo.empty() ? nullptr : dptr<int>(pb.grp_lo);
+  pl.pair_lo = plo.empty() ? nullptr : dptr<int>(pb.pair_lo);
   pl.scaled = scaled;
   pl.accumulate = accumulate;
   for (int ne = 1; ne <= 8; ++ne) {
     std::vector<int> w;
     for (int g2 = 0; g2 < pl.ngrp; ++g2)
-      for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += 64) { w.push_back(g2); w.push_back(c0); }
+      for (int r0 = 0; r0 < (glo.empty() ? L : glo[g2]); r0 += GEMM_TILE_ROWS)
+        for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += GEMM_TILE_COLS) {
+          w.push_back(g2);
+          w.push_back(c0);
+          w.push_back(r0);
+        }
     upload(pb.work[ne], w);
     pl.work[ne] = dptr<int>(pb.work[ne]);
-    pl.nwork[ne] = (int)(w.size() / 2);
+    pl.nwork[ne] = (int)(w.size() / 3);
   }
   return tr.size();
 }
@@ -233,6 +249,8 @@ static void default_opts(lb_opts* o) {
   o->self_n = 16;
   o->near_q = 8;
   o->near_adm = 2.0;
+  o->m2l_trunc32 = 2.5;
+  o->m2l_trunc64 = 2.0;
 }
 
 template <typename T>
@@ -329,6 +347,28 @@ static void merge_forest(const std::vector<Octree>& trees, const std::vector<int
   }
   F.nbox = boff;
   F.nleaf = loff;
+}
+
+// Active size (p_o + 1)^2 of the M2L translation of each offset o (in box
+// widths, id ((ox+3)*7 + (oy+3))*7 + (oz+3)): the multipole of a box of
+// half-diagonal a = sqrt(3)/2 seen from a box at centre distance d converges
+// like rho(d)^n with rho(d) = a / (d - a), so the order that matches the
+// error of the closest V-list offset (d = 2) at order p is
+// p ln rho(2) / ln rho(d); `safety` multiplies it (0: full order for all).
+static std::vector<int> m2l_orders(int p, double safety) {
+  if (!(safety > 0)) return {};
+  std::vector<int> lo(343);
+  const double a = 0.5 * std::sqrt(3.0);
+  const double l2 = std::log(a / (2.0 - a));
+  for (int o = 0; o < 343; ++o) {
+    const int ox = o / 49 - 3, oy = (o / 7) % 7 - 3, oz = o % 7 - 3;
+    const double d = std::sqrt((double)(ox * ox + oy * oy + oz * oz));
+    int po = p;
+    if (d > 2.0) po = std::min(p, (int)std::ceil(safety * p * l2 / std::log(a / (d - a))));
+    po = std::max(po, std::min(p, 4));
+    lo[o] = (po + 1) * (po + 1);
+  }
+  return lo;
 }
 
 // Work items of the leaf kernel: one block evaluates targets [tbeg, tend) of
@@ -529,7 +569,9 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         for (int v = F.vlist_ptr[g]; v < F.vlist_ptr[g + 1]; ++v) trp.push_back({F.vlist_off[v], g, F.vlist_src[v]});
       }
       P.m2l_pb.reset(new PlanBuf());
-      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb));
+      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb, P.L,
+                                             m2l_orders(p, sizeof(T) == 4 ? ctx->opts.m2l_trunc32
+                                                                          : ctx->opts.m2l_trunc64)));
     }
     P.m2m_pb.clear();
     P.l2l_pb.clear();
@@ -551,7 +593,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
           if (ch >= 0 && F.has_src[ch]) trp.push_back({c, g, ch});
         }
       }
-      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb));
+      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb, P.L));
       P.m2m_pl[l] = P.m2m_pb[l]->pl;
     }
     for (int l = 3; l <= F.depth; ++l) {  // L2L into level l from level l-1
@@ -567,7 +609,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         boxes.push_back(g);
         trp.push_back({oct, g, pg});
       }
-      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb));
+      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb, P.L));
       P.l2l_pl[l] = P.l2l_pb[l]->pl;
     }
     P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);
@@ -1331,6 +1373,8 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   if (o.p_f32 < 2 || o.p_f32 > 31 || o.p_f64 < 2 || o.p_f64 > 31) fail(LB_EINVAL, "expansion order out of range 2..31");
   if (o.max_iter < 1) fail(LB_EINVAL, "max_iter must be >= 1");
   if (o.self_n < 4 || o.near_q < 2 || o.near_adm <= 0) fail(LB_EINVAL, "bad quadrature options");
+  if (!(o.m2l_trunc32 >= 0 && o.m2l_trunc32 < 1e6) || !(o.m2l_trunc64 >= 0 && o.m2l_trunc64 < 1e6))
+    fail(LB_EINVAL, "m2l_trunc32 / m2l_trunc64 must be finite and >= 0");
   ctx->host_only = (o.flags & LB_HOST_ONLY) != 0;
   ctx->k = order;
   ctx->n_surf = n_surf;

@@ -592,6 +592,7 @@ template <> struct Mfma<double> {
 
 constexpr int GM_COLS = 64;   // columns per block (4 waves x 16)
 constexpr int GM_RB = 8;      // 16-row blocks per block (128 rows)
+static_assert(GM_COLS == GEMM_TILE_COLS && GM_RB * 16 == GEMM_TILE_ROWS, "tile shape shared with the plans");
 template <typename T> struct GmKc { static constexpr int v = 32; };   // k chunk staged in LDS
 template <> struct GmKc<double> { static constexpr int v = 16; };
 
@@ -601,18 +602,26 @@ template <> struct GmKc<double> { static constexpr int v = 16; };
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, int L, const int* __restrict__ work,
                                                       const int* __restrict__ grp_off, const int* __restrict__ grp_beg,
-                                                      const int* __restrict__ pair_src, int ne, const T* __restrict__ M,
-                                                      T* __restrict__ Y) {
+                                                      const int* __restrict__ pair_src, const int* __restrict__ grp_lo,
+                                                      int ne, const T* __restrict__ M, T* __restrict__ Y) {
   constexpr int KC = GmKc<T>::v;
   constexpr int NA = KC * GM_RB * 16 / 256;  // A values per thread per chunk
   constexpr int NB = KC * GM_COLS / 256;     // B values per thread per chunk
   __shared__ T As[KC][GM_RB * 16];
   __shared__ T Bs[GM_COLS][KC + 1];  // column-major, padded against bank conflicts
   __shared__ int srcrow[GM_COLS];
-  const int grp = work[2 * blockIdx.x];
-  const int c0 = work[2 * blockIdx.x + 1];
+  // XCD-aware order: block b runs on XCD b % 8; each XCD takes a contiguous
+  // range of the work list, so the column tiles that share a slab of a
+  // translation matrix (and the row tiles that share the columns) run on
+  // the same XCD and meet in its L2
+  const int total = gridDim.x, bq = total / GEMM_NXCD, br = total - bq * GEMM_NXCD;
+  const int xcd = blockIdx.x % GEMM_NXCD, loc = blockIdx.x / GEMM_NXCD;
+  const int w = xcd < br ? xcd * (bq + 1) + loc : br * (bq + 1) + (xcd - br) * bq + loc;
+  const int grp = work[3 * w];
+  const int c0 = work[3 * w + 1];
+  const int r0 = work[3 * w + 2];
   const int cend = grp_beg[grp + 1] * ne;
-  const int r0 = blockIdx.y * GM_RB * 16;
+  const int Lo = grp_lo ? grp_lo[grp] : L;  // coefficients in and out of this group's translation
   const T* Tm = TT + (int64_t)grp_off[grp] * L * L;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x < GM_COLS) {
@@ -642,11 +651,11 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
     for (int u = 0; u < NA; ++u) {
       const int k = k0 + akk + u * (256 / (GM_RB * 16));
       const T v = Tm[(int64_t)min(k, L - 1) * L + ar];
-      ra[u] = k < L ? v : (T)0;
+      ra[u] = k < Lo ? v : (T)0;
     }
     const int k = k0 + bkk;
     const int kc = min(k, L - 1);
-    const T kv = k < L ? (T)1 : (T)0;
+    const T kv = k < Lo ? (T)1 : (T)0;
 #pragma unroll
     for (int u = 0; u < NB; ++u) rb_[u] = bp[u][kc] * (bv[u] * kv);
   };
@@ -654,7 +663,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
 #pragma unroll
   for (int rb = 0; rb < GM_RB; ++rb) acc[rb] = (typename Mfma<T>::acc){0, 0, 0, 0};
   load(0);
-  for (int k0 = 0; k0 < L; k0 += KC) {
+  for (int k0 = 0; k0 < Lo; k0 += KC) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
@@ -667,7 +676,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
       Bs[i / KC][i % KC] = rb_[u];
     }
     __syncthreads();
-    if (k0 + KC < L) load(k0 + KC);
+    if (k0 + KC < Lo) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const T b = Bs[wv * 16 + (lane & 15)][kk + (lane >> 4)];
@@ -685,7 +694,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = r0 + rb * 16 + Mfma<T>::row(lane, v);
-        if (r < L) Y[(int64_t)c * L + r] = acc[rb][v];
+        if (r < Lo) Y[(int64_t)c * L + r] = acc[rb][v];
       }
   }
 }
@@ -695,15 +704,18 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxes, const double* __restrict__ box_scale,
                                                     const int* __restrict__ tptr, const int* __restrict__ tpairs,
-                                                    int ne, int L, int accumulate, const T* __restrict__ Y,
-                                                    T* __restrict__ out) {
+                                                    const int* __restrict__ pair_lo, int ne, int L, int accumulate,
+                                                    const T* __restrict__ Y, T* __restrict__ out) {
   const int g = boxes[blockIdx.x];
   const T f = box_scale ? (T)box_scale[blockIdx.x] : (T)1;
   const int pb = tptr[blockIdx.x], pe = tptr[blockIdx.x + 1];
   for (int i = threadIdx.x; i < ne * L; i += blockDim.x) {
     const int e = i / L, r = i - e * L;
     T a = 0;
-    for (int q = pb; q < pe; ++q) a += Y[((int64_t)tpairs[q] * ne + e) * L + r];
+    for (int q = pb; q < pe; ++q) {
+      const int pq = tpairs[q];
+      if (!pair_lo || r < pair_lo[pq]) a += Y[((int64_t)pq * ne + e) * L + r];
+    }
     const int64_t o = ((int64_t)g * ne + e) * L + r;
     out[o] = accumulate ? out[o] + a * f : a * f;
   }
@@ -713,13 +725,13 @@ template <typename T>
 static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, const T* X, T* Y, T* out, hipStream_t st) {
   if (pl.nbox == 0) return;
   if (pl.nwork[ne] > 0) {
-    dim3 grid(pl.nwork[ne], (L + GM_RB * 16 - 1) / (GM_RB * 16));
+    dim3 grid(pl.nwork[ne]);
     hipLaunchKernelGGL(k_gemm_grouped<T>, grid, dim3(256), 0, st, TT, L, pl.work[ne], pl.grp_mat, pl.grp_beg,
-                       pl.pair_src, ne, X, Y);
+                       pl.pair_src, pl.grp_lo, ne, X, Y);
     KCHECK();
   }
   hipLaunchKernelGGL(k_col_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.scaled ? pl.box_scale : nullptr,
-                     pl.tptr, pl.tpairs, ne, L, pl.accumulate ? 1 : 0, (const T*)Y, out);
+                     pl.tptr, pl.tpairs, pl.pair_lo, ne, L, pl.accumulate ? 1 : 0, (const T*)Y, out);
   KCHECK();
 }
 

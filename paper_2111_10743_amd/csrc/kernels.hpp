@@ -38,13 +38,25 @@ __host__ __device__ inline int fmm_nstr(int mode) {
 // target box sums its columns (scaled by its level factor when `scaled`)
 // into (or onto, when `accumulate`) its coefficient vector.  Column tiles are
 // 64 wide; work[ne] lists (group, first column) for ne expansions per box.
+// Output tile of the grouped translation GEMM: rows x columns per block.
+constexpr int GEMM_TILE_ROWS = 128, GEMM_TILE_COLS = 64;
+// Number of XCDs of the device: consecutive workgroups go to the XCDs in
+// turn, each XCD with its own L2.
+constexpr int GEMM_NXCD = 8;
+
 struct GemmPlan {
   int ngrp = 0, npair = 0, nbox = 0;
   const int *grp_mat = nullptr, *grp_beg = nullptr;  // [ngrp], [ngrp+1] (triple index)
   const int *pair_src = nullptr;                      // [npair] source box
+  // active size of each group's translation (nullable: L): the leading
+  // grp_lo[g] coefficients in and out (a lower expansion order); pair_lo
+  // [npair] the same per pair, for the column reduction
+  const int *grp_lo = nullptr, *pair_lo = nullptr;
   const int* boxes = nullptr;                         // [nbox] target boxes
   const double* box_scale = nullptr;                  // [nbox] factor of each target box (scaled plans)
   const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
+  // per density count ne (1..8): work items (group, first column, first
+  // row), ordered group -> row tile -> column tile
   const int* work[9] = {nullptr};
   int nwork[9] = {0};
   bool scaled = false, accumulate = false;

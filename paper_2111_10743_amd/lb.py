@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("eta_near", ctypes.c_double), ("over_q", ctypes.c_int), ("p_f32", ctypes.c_int),
                 ("p_f64", ctypes.c_int), ("leaf_src", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("flags", ctypes.c_int), ("self_n", ctypes.c_int), ("near_q", ctypes.c_int),
-                ("near_adm", ctypes.c_double)]
+                ("near_adm", ctypes.c_double), ("m2l_trunc32", ctypes.c_double), ("m2l_trunc64", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
