@@ -14,6 +14,8 @@
   sampled rows.
 * LB_STRICT_MEAN: f with a mean is rejected (LB_ENOTMEANZERO), mean-zero f
   solves; argument errors on a live context.
+* M2L orders by offset (the defaults) against the full order for every
+  offset, both against the oracle.
 """
 import ctypes
 import sys
@@ -166,3 +168,32 @@ def test_strict_mean_and_argument_errors(torch_dev):
     with pytest.raises(ValueError):
         s.apply_S_adj_X(buf, buf[:10])
     s.close()
+
+
+def test_m2l_order_by_offset(torch_dev):
+    """Offset-dependent M2L orders (the defaults) against the full order for
+    every offset (m2l_trunc32 = m2l_trunc64 = 0): both within the parity bar
+    of the oracle on sampled rows, and within FMM accuracy of each other."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.ellipsoid_patches(3, nodes(4), (1.0, 1.5, 2.0))
+    g = Geometry(X, Xu, Xv, 4)
+    rows = np.arange(0, g.N, g.N // 120)[:120]
+    o = Oracle(g, rows)
+    sig = I.real_sph_harm(4, -2, g.x / np.linalg.norm(g.x, axis=1, keepdims=True)) + 0.3 * g.x[:, 0]
+    L = o.layer(sig)
+    a = P.Surface(X, Xu, Xv, 4)
+    b = P.Surface(X, Xu, Xv, 4, m2l_trunc32=0.0, m2l_trunc64=0.0)
+    for prec, tol in ((64, 1e-9), (32, 1e-6)):
+        dt = torch.float64 if prec == 64 else torch.float32
+        x = torch.tensor(sig, dtype=dt, device="cuda")
+        ga, gb = a.apply_gradS(x)["grad"].double().cpu().numpy(), b.apply_gradS(x)["grad"].double().cpu().numpy()
+        ea, eb = rel_l2(ga[rows], L[:, 1:4]), rel_l2(gb[rows], L[:, 1:4])
+        d = rel_l2(ga, gb)
+        note(f"m2l orders prec={prec}: by offset {ea:.2e}, full {eb:.2e}, between {d:.2e}")
+        assert ea < tol and eb < tol and d < tol
+    a.close()
+    b.close()

@@ -55,6 +55,10 @@ def test_error_codes():
     with pytest.raises(lb.LBError) as e:
         lb.Surface(X, Xz, Xv, 4, host_only=True)
     assert e.value.code == lb.LB_EGEOM
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(lb.LBError) as e:
+            lb.Surface(X, Xu, Xv, 4, host_only=True, m2l_trunc64=bad)
+        assert e.value.code == lb.LB_EINVAL
     s = lb.Surface(X, Xu, Xv, 4, host_only=True)
     import ctypes
     code = lb.lib().lb_apply_S(s._ctx, 1, 32, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
