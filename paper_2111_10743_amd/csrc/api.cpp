@@ -988,7 +988,6 @@ static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, 
 // b = (S''+D')^T v + S'^T (2 H v); step 2 (FMM_ADJ) S'^T a - S^T b.
 // ---------------------------------------------------------------------------
 constexpr int CHUNK_A3T = 4;
-constexpr int NDMAX_HOST = 4;  // densities per reduction launch (k_reduce_partials takes up to 4 partial rows)
 
 template <typename T>
 static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& zb, bool& zbuilt, int nd,

@@ -131,40 +131,6 @@ __device__ void fill_rectab(const RecTab<T>& rt, int p) {
   }
 }
 
-template <typename T>
-__device__ void regular_to_lds(int p, T x, T y, T z, T* re, T* im) {
-  const T r2 = x * x + y * y + z * z;
-  T mre = 1, mim = 0;  // Rt_m^m
-  for (int m = 0; m <= p; ++m) {
-    if (m > 0) {
-      T f = -sqrt((T)(2 * m - 1) / (T)(2 * m));
-      T nr = f * (x * mre - y * mim);
-      T ni = f * (x * mim + y * mre);
-      mre = nr;
-      mim = ni;
-    }
-    re[cidx(m, m)] = mre;
-    im[cidx(m, m)] = mim;
-    if (m + 1 > p) continue;
-    T c1 = z * sqrt((T)(2 * m + 1));
-    T are = mre, aim = mim;           // n = m
-    T bre = c1 * mre, bim = c1 * mim;  // n = m+1
-    re[cidx(m + 1, m)] = bre;
-    im[cidx(m + 1, m)] = bim;
-    for (int n = m + 1; n < p; ++n) {
-      T f1 = (T)(2 * n + 1) * z;
-      T f2 = r2 * sqrt((T)((n + m) * (n - m)));
-      T dn = (T)1 / sqrt((T)((n + 1 + m) * (n + 1 - m)));
-      T cre = (f1 * bre - f2 * are) * dn;
-      T cim = (f1 * bim - f2 * aim) * dn;
-      re[cidx(n + 1, m)] = cre;
-      im[cidx(n + 1, m)] = cim;
-      are = bre; aim = bim;
-      bre = cre; bim = cim;
-    }
-  }
-}
-
 // Column m of the normalized regular harmonics, Rt_n^m for n = m..p, into
 // LDS rows (re, im).  Rt_m^m = prod_{j<=m} (-(x+iy) sqrt((2j-1)/(2j))).
 template <typename T>
@@ -1529,23 +1495,6 @@ __global__ __launch_bounds__(256) void k_combine_a3b(int64_t N, int n_p, const i
       out[(int64_t)d * N + row] = -(T)0.25 * tau[(int64_t)d * N + row] + y1 - y4 - (T)2 * H[row] * y3;
       y2buf[(int64_t)d * N + row] = y2;
     }
-  }
-}
-
-// serial-order reduction of per-block partials: s[d] = scale * sum_b partial[d][b]
-__global__ void k_reduce_partials(const double* partial, int nblk, int nd, double scale, double* s) {
-  __shared__ double red[256];
-  for (int d = 0; d < nd; ++d) {
-    double a = 0;
-    for (int b = threadIdx.x; b < nblk; b += 256) a += partial[(int64_t)d * nblk + b];
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) s[d] = red[0] * scale;
-    __syncthreads();
   }
 }
 
