@@ -63,7 +63,7 @@ struct Triple { int mat, tgt, src; };
 // mat_lo (nullable: all L): active size of each matrix id's translation.
 static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<int>& boxes,
                          const std::vector<double>& scale, bool scaled, bool accumulate, int nbox_total, int L,
-                         const std::vector<int>& mat_lo = {}) {
+                         const std::vector<int>& mat_lo = {}, bool ksplit = false) {
   std::stable_sort(tr.begin(), tr.end(), [](const Triple& a, const Triple& b) {
     return a.mat != b.mat ? a.mat < b.mat : a.tgt < b.tgt;
   });
@@ -100,20 +100,41 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
   pl.pair_lo = plo.empty() ? nullptr : dptr<int>(pb.pair_lo);
   pl.scaled = scaled;
   pl.accumulate = accumulate;
+  // k split (small plans): enough blocks to fill the device, slices of at
+  // least 64 coefficients, a multiple of 32 (the k chunks of both precisions)
+  pl.kslice = 0;
+  pl.nslice = 1;
+  if (ksplit && glo.empty()) {
+    int64_t nb1 = 0;
+    for (int g2 = 0; g2 < pl.ngrp; ++g2)
+      nb1 += (int64_t)((L + GEMM_TILE_ROWS - 1) / GEMM_TILE_ROWS) *
+             ((gbeg[g2 + 1] - gbeg[g2] + GEMM_TILE_COLS - 1) / GEMM_TILE_COLS);
+    const int ks = (int)std::min<int64_t>(8, std::max<int64_t>(1, (2048 + nb1 - 1) / std::max<int64_t>(nb1, 1)));
+    int kl = ((L + ks - 1) / ks + 31) / 32 * 32;
+    kl = std::max(kl, 64);
+    if (kl < L) {
+      pl.kslice = kl;
+      pl.nslice = (L + kl - 1) / kl;
+    }
+  }
   for (int ne = 1; ne <= 8; ++ne) {
     std::vector<int> w;
-    for (int g2 = 0; g2 < pl.ngrp; ++g2)
-      for (int r0 = 0; r0 < (glo.empty() ? L : glo[g2]); r0 += GEMM_TILE_ROWS)
-        for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += GEMM_TILE_COLS) {
-          w.push_back(g2);
-          w.push_back(c0);
-          w.push_back(r0);
-        }
+    for (int g2 = 0; g2 < pl.ngrp; ++g2) {
+      const int lo = glo.empty() ? L : glo[g2];
+      for (int r0 = 0; r0 < lo; r0 += GEMM_TILE_ROWS)
+        for (int c0 = gbeg[g2] * ne; c0 < gbeg[g2 + 1] * ne; c0 += GEMM_TILE_COLS)
+          for (int kb = 0; kb < lo; kb += pl.kslice ? pl.kslice : lo) {
+            w.push_back(g2);
+            w.push_back(c0);
+            w.push_back(r0);
+            w.push_back(kb);
+          }
+    }
     upload(pb.work[ne], w);
     pl.work[ne] = dptr<int>(pb.work[ne]);
-    pl.nwork[ne] = (int)(w.size() / 3);
+    pl.nwork[ne] = (int)(w.size() / 4);
   }
-  return tr.size();
+  return tr.size() * pl.nslice;
 }
 
 template <typename T>
@@ -593,7 +614,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
           if (ch >= 0 && F.has_src[ch]) trp.push_back({c, g, ch});
         }
       }
-      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb, P.L));
+      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb, P.L, {}, true));
       P.m2m_pl[l] = P.m2m_pb[l]->pl;
     }
     for (int l = 3; l <= F.depth; ++l) {  // L2L into level l from level l-1
@@ -609,7 +630,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         boxes.push_back(g);
         trp.push_back({oct, g, pg});
       }
-      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb, P.L));
+      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb, P.L, {}, true));
       P.l2l_pl[l] = P.l2l_pb[l]->pl;
     }
     P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);

@@ -562,14 +562,16 @@ static_assert(GM_COLS == GEMM_TILE_COLS && GM_RB * 16 == GEMM_TILE_ROWS, "tile s
 template <typename T> struct GmKc { static constexpr int v = 32; };   // k chunk staged in LDS
 template <> struct GmKc<double> { static constexpr int v = 16; };
 
-// work item w: (group, first column); group: offset id and column range.
+// work item w: (group, first column, first row, first k); group: offset id
+// and column range.
 // The tiles of k chunk i+1 are loaded into registers while the matrix cores
 // work on chunk i from LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, int L, const int* __restrict__ work,
                                                       const int* __restrict__ grp_off, const int* __restrict__ grp_beg,
                                                       const int* __restrict__ pair_src, const int* __restrict__ grp_lo,
-                                                      int ne, const T* __restrict__ M, T* __restrict__ Y) {
+                                                      int kslice, int64_t ystride, int ne, const T* __restrict__ M,
+                                                      T* __restrict__ Y) {
   constexpr int KC = GmKc<T>::v;
   constexpr int NA = KC * GM_RB * 16 / 256;  // A values per thread per chunk
   constexpr int NB = KC * GM_COLS / 256;     // B values per thread per chunk
@@ -583,11 +585,14 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
   const int total = gridDim.x, bq = total / GEMM_NXCD, br = total - bq * GEMM_NXCD;
   const int xcd = blockIdx.x % GEMM_NXCD, loc = blockIdx.x / GEMM_NXCD;
   const int w = xcd < br ? xcd * (bq + 1) + loc : br * (bq + 1) + (xcd - br) * bq + loc;
-  const int grp = work[3 * w];
-  const int c0 = work[3 * w + 1];
-  const int r0 = work[3 * w + 2];
+  const int grp = work[4 * w];
+  const int c0 = work[4 * w + 1];
+  const int r0 = work[4 * w + 2];
+  const int kb = work[4 * w + 3];
   const int cend = grp_beg[grp + 1] * ne;
   const int Lo = grp_lo ? grp_lo[grp] : L;  // coefficients in and out of this group's translation
+  const int ke = kslice ? min(Lo, kb + kslice) : Lo;  // this block's part of the sum over k
+  if (kslice) Y += (int64_t)(kb / kslice) * ystride;
   const T* Tm = TT + (int64_t)grp_off[grp] * L * L;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x < GM_COLS) {
@@ -617,19 +622,19 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
     for (int u = 0; u < NA; ++u) {
       const int k = k0 + akk + u * (256 / (GM_RB * 16));
       const T v = Tm[(int64_t)min(k, L - 1) * L + ar];
-      ra[u] = k < Lo ? v : (T)0;
+      ra[u] = k < ke ? v : (T)0;
     }
     const int k = k0 + bkk;
     const int kc = min(k, L - 1);
-    const T kv = k < Lo ? (T)1 : (T)0;
+    const T kv = k < ke ? (T)1 : (T)0;
 #pragma unroll
     for (int u = 0; u < NB; ++u) rb_[u] = bp[u][kc] * (bv[u] * kv);
   };
   typename Mfma<T>::acc acc[GM_RB];
 #pragma unroll
   for (int rb = 0; rb < GM_RB; ++rb) acc[rb] = (typename Mfma<T>::acc){0, 0, 0, 0};
-  load(0);
-  for (int k0 = 0; k0 < Lo; k0 += KC) {
+  load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KC) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
@@ -642,7 +647,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
       Bs[i / KC][i % KC] = rb_[u];
     }
     __syncthreads();
-    if (k0 + KC < Lo) load(k0 + KC);
+    if (k0 + KC < ke) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const T b = Bs[wv * 16 + (lane & 15)][kk + (lane >> 4)];
@@ -670,8 +675,9 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxes, const double* __restrict__ box_scale,
                                                     const int* __restrict__ tptr, const int* __restrict__ tpairs,
-                                                    const int* __restrict__ pair_lo, int ne, int L, int accumulate,
-                                                    const T* __restrict__ Y, T* __restrict__ out) {
+                                                    const int* __restrict__ pair_lo, int nslice, int64_t ystride,
+                                                    int ne, int L, int accumulate, const T* __restrict__ Y,
+                                                    T* __restrict__ out) {
   const int g = boxes[blockIdx.x];
   const T f = box_scale ? (T)box_scale[blockIdx.x] : (T)1;
   const int pb = tptr[blockIdx.x], pe = tptr[blockIdx.x + 1];
@@ -680,7 +686,8 @@ __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxe
     T a = 0;
     for (int q = pb; q < pe; ++q) {
       const int pq = tpairs[q];
-      if (!pair_lo || r < pair_lo[pq]) a += Y[((int64_t)pq * ne + e) * L + r];
+      if (!pair_lo || r < pair_lo[pq])
+        for (int sl = 0; sl < nslice; ++sl) a += Y[sl * ystride + ((int64_t)pq * ne + e) * L + r];
     }
     const int64_t o = ((int64_t)g * ne + e) * L + r;
     out[o] = accumulate ? out[o] + a * f : a * f;
@@ -690,14 +697,16 @@ __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxe
 template <typename T>
 static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, const T* X, T* Y, T* out, hipStream_t st) {
   if (pl.nbox == 0) return;
+  const int64_t ystride = (int64_t)pl.npair * ne * L;  // one k slice of Y
   if (pl.nwork[ne] > 0) {
     dim3 grid(pl.nwork[ne]);
     hipLaunchKernelGGL(k_gemm_grouped<T>, grid, dim3(256), 0, st, TT, L, pl.work[ne], pl.grp_mat, pl.grp_beg,
-                       pl.pair_src, pl.grp_lo, ne, X, Y);
+                       pl.pair_src, pl.grp_lo, pl.kslice, ystride, ne, X, Y);
     KCHECK();
   }
   hipLaunchKernelGGL(k_col_reduce<T>, dim3(pl.nbox), dim3(256), 0, st, pl.boxes, pl.scaled ? pl.box_scale : nullptr,
-                     pl.tptr, pl.tpairs, pl.pair_lo, ne, L, pl.accumulate ? 1 : 0, (const T*)Y, out);
+                     pl.tptr, pl.tpairs, pl.pair_lo, pl.nslice, ystride, ne, L, pl.accumulate ? 1 : 0, (const T*)Y,
+                     out);
   KCHECK();
 }
 

@@ -56,9 +56,13 @@ struct GemmPlan {
   const double* box_scale = nullptr;                  // [nbox] factor of each target box (scaled plans)
   const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
   // per density count ne (1..8): work items (group, first column, first
-  // row), ordered group -> row tile -> column tile
+  // row, first k), ordered group -> row tile -> column tile -> k slice
   const int* work[9] = {nullptr};
   int nwork[9] = {0};
+  // k split: slices of kslice coefficients (0: the whole sum in one block);
+  // slice s of column c goes to Y[s][c], and the column reduction adds the
+  // nslice slices
+  int kslice = 0, nslice = 1;
   bool scaled = false, accumulate = false;
 };
 
