@@ -776,13 +776,18 @@ constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
 // the far field over the harmonic orders m = f (mod F), the near field over
 // the source indices j = f (mod F) of each LDS chunk; the F partial sums of
 // a target (contiguous lanes) are then added by shuffles.
-// LDS bytes of the L2P expansions of one block (local, gradient and Hessian
-// expansions), rounded up to 16.
+// LDS bytes of the L2P expansions of one block, rounded up to 16: the local
+// expansions (nexp L), the gradient expansions the mode evaluates (3 p^2
+// per expansion: all three in A3B, the first in GRAD and ADJ3) and, in A3B
+// only, the Hessian expansions (6 (p-1)^2 and 3 (p-1)^2 scratch).
 template <typename T>
 __host__ __device__ inline size_t leaf_exp_bytes(int mode, int p) {
-  const size_t L = (size_t)(p + 1) * (p + 1), nexp = fmm_nexp(mode);
-  const size_t b = sizeof(T) * (nexp * L + nexp * 3 * (size_t)p * p + 9 * (size_t)(p - 1) * (p - 1));
-  return (b + 15) / 16 * 16;
+  const size_t L = (size_t)(p + 1) * (p + 1), Lg = (size_t)p * p, Lh = (size_t)(p - 1) * (p - 1);
+  const size_t nexp = fmm_nexp(mode);
+  size_t n = nexp * L;
+  if (mode == FMM_GRAD || mode == FMM_ADJ3) n += 3 * Lg;
+  if (mode == FMM_A3B) n += nexp * 3 * Lg + 9 * Lh;
+  return (sizeof(T) * n + 15) / 16 * 16;
 }
 
 // PART: LEAF_BOTH (far and near, outputs written), LEAF_NEAR (near-field
@@ -1121,11 +1126,13 @@ static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const
   const int p = t.p, L = t.L;
   const int nexp = fmm_nexp(mode);
   // LDS: staged sources (not in the far-only kernel), then the expansions
-  // when they fit
+  // when both stay within 40 KiB (at least 4 blocks per CU: more LDS per
+  // block costs more in occupancy than the global reads of the expansions,
+  // e.g. 1.42 ms -> 1.74 ms for the FP64 gradient kernel at 45 KiB)
   const size_t chunk = part == LEAF_FAR ? 0
                        : sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
   const size_t exps = part == LEAF_NEAR ? 0 : leaf_exp_bytes<T>(mode, p);
-  const bool lds = chunk + exps <= 64 * 1024;
+  const bool lds = chunk + exps <= 40 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
   (void)L; (void)nexp;
   dim3 grid(t.n_leaf_work, nrhs);
