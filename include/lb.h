@@ -63,6 +63,8 @@ typedef int lb_status;
                               a captured HIP graph of one application */
 #define LB_NO_OVERLAP  64  /* run the near-field sums after the far-field passes on the caller's
                               stream instead of concurrently on a second (non-blocking) stream */
+#define LB_HOST_QUAD   128 /* lb_setup computes every near-patch correction integral on the host
+                              (OpenMP) instead of those of non-self patches on the device */
 #define LB_NO_P2M_TABLES 8 /* compute the leaf harmonics of P2M on the fly instead of keeping
                               per-source tables (2 (p+1)^2 values per oversampled point and
                               precision, kept when they fit in a quarter of free device memory
@@ -78,7 +80,7 @@ typedef struct {
   int leaf_src;     /* target mean number of sources per FMM leaf box         (default 1024)*/
   int max_iter;     /* GMRES iteration cap per (inner) solve                  (default 100)*/
   int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT | LB_NO_P2M_TABLES |
-                       LB_HOST_OCTREE | LB_NO_GRAPH | LB_NO_OVERLAP                    */
+                       LB_HOST_OCTREE | LB_NO_GRAPH | LB_NO_OVERLAP | LB_HOST_QUAD     */
   int self_n;       /* self-patch rule: Gauss points along each Duffy ray    (default 16) */
   int near_q;       /* adaptive near rule: near_q x near_q points per leaf    (default 8)  */
   double near_adm;  /* adaptive near rule admissibility dist >= adm * diam    (default 2)  */

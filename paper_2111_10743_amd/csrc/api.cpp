@@ -1374,6 +1374,73 @@ lb_status lb_ref_nodes(int order, double* uv, double* w_ref) {
 }
 
 namespace lb {
+// Accurate near integrals A of every (target, near patch) block: the blocks
+// of patches other than the target's own by the device's adaptive rule, the
+// self blocks by the host rule while the device works.
+static void near_integrals_device(const Surface& S, const RefElem& re, const QuadOpts& qo, std::vector<double>& A) {
+  const int n_p = S.n_p;
+  const int64_t nb = S.near_ptr[S.N];
+  std::vector<int64_t> row, blk;
+  std::vector<int32_t> pat;
+  for (int64_t i = 0; i < S.N; ++i)
+    for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b)
+      if (S.near_patch[b] != (int32_t)(i / n_p)) {
+        row.push_back(i);
+        blk.push_back(b);
+        pat.push_back(S.near_patch[b]);
+      }
+  std::vector<double> ru, rw;
+  near_leaf_rule(qo.near_q, ru, rw);
+  DBuf dX, dn, dcX, dcXu, dcXv, dja, djb, djc, dVinv, dru, drw, drow, dblk, dpat, dA;
+  upload(dX, S.X);
+  upload(dn, S.nrm);
+  upload(dcX, S.cX);
+  upload(dcXu, S.cXu);
+  upload(dcXv, S.cXv);
+  upload(dja, re.ja);
+  upload(djb, re.jb);
+  upload(djc, re.jc);
+  upload(dVinv, re.Vinv);
+  upload(dru, ru);
+  upload(drw, rw);
+  upload(drow, row);
+  upload(dblk, blk);
+  upload(dpat, pat);
+  dA.alloc(sizeof(double) * (size_t)nb * n_p * 6);
+  NearQuadArgs a;
+  a.X = dptr<double>(dX);
+  a.nrm = dptr<double>(dn);
+  a.cX = dptr<double>(dcX);
+  a.cXu = dptr<double>(dcXu);
+  a.cXv = dptr<double>(dcXv);
+  a.ja = dptr<double>(dja);
+  a.jb = dptr<double>(djb);
+  a.jc = dptr<double>(djc);
+  a.Vinv = dptr<double>(dVinv);
+  a.ru = dptr<double>(dru);
+  a.rw = dptr<double>(drw);
+  a.row = dptr<int64_t>(drow);
+  a.blk = dptr<int64_t>(dblk);
+  a.patch = dptr<int32_t>(dpat);
+  a.A = dptr<double>(dA);
+  a.nwork = (int64_t)row.size();
+  a.k = re.k;
+  a.nq = qo.near_q * qo.near_q;
+  a.max_depth = qo.max_depth;
+  a.adm = qo.near_adm;
+  HIPTRY(launch_near_quad(a, nullptr));
+  // self blocks on the host meanwhile, into a copy that the download below
+  // does not overwrite
+  std::vector<double> As((size_t)nb * n_p * 6, 0.0);
+  near_integrals(S, qo, As, true);
+  A.assign((size_t)nb * n_p * 6, 0.0);
+  HIPTRY(hipMemcpy(A.data(), dA.p, sizeof(double) * A.size(), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < S.N; ++i)
+    for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b)
+      if (S.near_patch[b] == (int32_t)(i / n_p))
+        std::memcpy(&A[(size_t)b * n_p * 6], &As[(size_t)b * n_p * 6], sizeof(double) * n_p * 6);
+}
+
 // Setup of n_surf surfaces (surface q: pps[q] patches, in order).
 static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, const double* X, const double* Xu,
                        const double* Xv, const lb_opts* opts) {
@@ -1427,7 +1494,13 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   qo.near_q = o.near_q;
   qo.near_adm = o.near_adm;
   std::vector<double> A, B;
-  near_integrals(S, qo, A);
+  // the device rule keeps at most 3 max_depth + 1 triangles on its stack
+  if (!ctx->host_only && !(o.flags & LB_HOST_QUAD) && 3 * qo.max_depth + 1 <= 72) {
+    HIPTRY(hipGetDevice(&ctx->device));
+    near_integrals_device(S, *ctx->re, qo, A);
+  } else {
+    near_integrals(S, qo, A);
+  }
   std::vector<float> none;
   far_rule_blocks(S, none, none, none, false, B);
   ctx->C64.resize(A.size());

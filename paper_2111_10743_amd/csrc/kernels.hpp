@@ -250,4 +250,31 @@ void launch_wmean(const double* f, const double* w, int64_t N, double* partial, 
                   hipStream_t st);                                 // out = sum w f
 void launch_sub_scalar(double* f, const double* s, double scale, int64_t N, hipStream_t st);  // f -= scale*s[0]
 
+// Accurate integrals A of the corrections for (target, near patch) pairs
+// with the patch not the target's own (Section 4, eq. nys-lcq2), by the
+// adaptive subdivision rule: work item w is target row[w] against patch
+// patch[w], written to block blk[w] of A: A[blk][b][t] (n_p values b,
+// kernels t = S, Gx, Gy, Gz, S', S''+D').
+struct NearQuadArgs {
+  const double* X = nullptr;    // [N][3] targets
+  const double* nrm = nullptr;  // [N][3] target normals
+  const double* cX = nullptr;   // [NP][n_p][3] modal coefficients of X, X_u, X_v
+  const double* cXu = nullptr;
+  const double* cXv = nullptr;
+  const double* ja = nullptr;   // [(k+1)^2] Jacobi recurrence of the modal basis
+  const double* jb = nullptr;
+  const double* jc = nullptr;
+  const double* Vinv = nullptr; // [n_p][n_p]
+  const double* ru = nullptr;   // [nq][2] leaf rule on the unit triangle
+  const double* rw = nullptr;   // [nq]
+  const int64_t* row = nullptr; // [nwork]
+  const int64_t* blk = nullptr; // [nwork]
+  const int32_t* patch = nullptr;
+  double* A = nullptr;          // [nnz_blocks][n_p][6]
+  int64_t nwork = 0;
+  int k = 0, nq = 0, max_depth = 0;
+  double adm = 2.0;
+};
+hipError_t launch_near_quad(const NearQuadArgs& q, hipStream_t st);
+
 }  // namespace lb

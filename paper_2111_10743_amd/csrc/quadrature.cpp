@@ -194,17 +194,11 @@ static void near_integral(const Surface& S, int64_t i, int p, const QuadOpts& qo
   moments_to_nodal(S, mom, out);
 }
 
-void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A) {
-  const int n_p = S.n_p;
-  const int64_t nb = S.near_ptr[S.N];
-  A.assign((size_t)nb * n_p * 6, 0.0);
-  std::vector<double> g, gw, tg, tw;
-  gauss_legendre01(qo.self_n, g, gw);
-  gauss_legendre01(qo.self_nt, tg, tw);
+void near_leaf_rule(int q, std::vector<double>& ru, std::vector<double>& rw) {
   std::vector<double> a, aw;
-  gauss_legendre01(qo.near_q, a, aw);
-  const int q = qo.near_q;
-  std::vector<double> ru(2 * q * q), rw(q * q);
+  gauss_legendre01(q, a, aw);
+  ru.assign(2 * q * q, 0.0);
+  rw.assign(q * q, 0.0);
   for (int jb = 0; jb < q; ++jb)
     for (int ia = 0; ia < q; ++ia) {
       int m = jb * q + ia;
@@ -212,6 +206,17 @@ void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A
       ru[2 * m + 1] = a[jb];
       rw[m] = aw[ia] * aw[jb] * (1.0 - a[jb]);
     }
+}
+
+void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A, bool self_only) {
+  const int n_p = S.n_p;
+  const int64_t nb = S.near_ptr[S.N];
+  if (!self_only) A.assign((size_t)nb * n_p * 6, 0.0);
+  std::vector<double> g, gw, tg, tw;
+  gauss_legendre01(qo.self_n, g, gw);
+  gauss_legendre01(qo.self_nt, tg, tw);
+  std::vector<double> ru, rw;
+  near_leaf_rule(qo.near_q, ru, rw);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t i = 0; i < S.N; ++i) {
     const int self = (int)(i / n_p);
@@ -220,7 +225,7 @@ void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A
       int p = S.near_patch[b];
       if (p == self)
         self_integral(S, i, qo, g, gw, tg, tw, out);
-      else
+      else if (!self_only)
         near_integral(S, i, p, qo, ru, rw, out);
     }
   }

@@ -50,7 +50,13 @@ struct Surface {
 
 // Accurate near integrals A (eq. nys-lcq2) for every (target, near patch)
 // block: vals [nnz_blocks][n_p][6], kernels S, Gx, Gy, Gz, S', S''+D'.
-void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A);
+// With self_only, A must already hold nnz_blocks * n_p * 6 values and only
+// the blocks of each target's own patch are written.
+void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A, bool self_only = false);
+
+// Leaf rule of the adaptive near quadrature: the q x q conical Gauss rule on
+// T0 (points ru [q*q][2], weights rw [q*q]).
+void near_leaf_rule(int q, std::vector<double>& ru, std::vector<double>& rw);
 
 // Far-rule contributions B of the near patches.  When fp32_mask is set, the
 // oversampled sources whose float32 squared distance to the target is below

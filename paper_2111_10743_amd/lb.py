@@ -30,6 +30,7 @@ LB_HOST_ONLY = 2
 LB_DIRECT = 4
 LB_NO_P2M_TABLES = 8
 LB_HOST_OCTREE = 16
+LB_HOST_QUAD = 128
 LB_NO_GRAPH = 32
 LB_NO_OVERLAP = 64
 
@@ -194,7 +195,7 @@ class Surface:
     """One discretized surface: lb_setup ... lb_destroy."""
 
     def __init__(self, X, Xu, Xv, order, opts=None, host_only=False, direct=False, p2m_tables=True,
-                 host_octree=False, patches_per_surf=None, graphs=True, overlap=True, **kw):
+                 host_octree=False, patches_per_surf=None, graphs=True, overlap=True, host_quad=False, **kw):
         """One surface, or with patches_per_surf several independent surfaces
         (their patches one after the other in X, Xu, Xv; lb_setup_batch)."""
         X = np.ascontiguousarray(X, dtype=np.float64)
@@ -215,6 +216,8 @@ class Surface:
             o.flags |= LB_NO_GRAPH
         if not overlap:
             o.flags |= LB_NO_OVERLAP
+        if host_quad:
+            o.flags |= LB_HOST_QUAD
         self.order = order
         self.host_only = host_only
         self._ctx = ctypes.c_void_p()
