@@ -63,8 +63,8 @@ typedef int lb_status;
                               a captured HIP graph of one application */
 #define LB_NO_OVERLAP  64  /* run the near-field sums after the far-field passes on the caller's
                               stream instead of concurrently on a second (non-blocking) stream */
-#define LB_HOST_QUAD   128 /* lb_setup computes every near-patch correction integral on the host
-                              (OpenMP) instead of those of non-self patches on the device */
+#define LB_HOST_QUAD   128 /* lb_setup computes the quadrature corrections on the host (OpenMP)
+                              instead of on the device */
 #define LB_NO_P2M_TABLES 8 /* compute the leaf harmonics of P2M on the fly instead of keeping
                               per-source tables (2 (p+1)^2 values per oversampled point and
                               precision, kept when they fit in a quarter of free device memory
@@ -123,7 +123,11 @@ lb_status lb_ref_nodes(int order, double *uv, double *w_ref);
 /* Build geometry, near lists, quadrature corrections (Section 4, eqs. nys-lcq
  * and nys-lcq2), the octree and the translation operators, and upload them.
  * X, Xu, Xv: host [n_patches][n_p][3] chart samples and first derivatives at
- * lb_ref_nodes(order).  opts: nullable (defaults).  On success *ctx owns all
+ * lb_ref_nodes(order).  opts: nullable (defaults).  The corrections are
+ * computed on the current device (one wavefront per target for the self
+ * blocks, per (target, patch) pair for the others and the far rule), on the
+ * host with LB_HOST_QUAD or LB_HOST_ONLY: the same rules, equal up to
+ * rounding order.  On success *ctx owns all
  * state; release it with lb_destroy.  Errors: LB_EINVAL (order out of range,
  * NaN/Inf input), LB_EGEOM (zero Jacobian), LB_ENOMEM, LB_EHIP. */
 lb_status lb_setup(lb_ctx **ctx, int n_patches, int order, const double *X,

@@ -449,7 +449,8 @@ static void make_leaf_work(Prec<T>& P, int fmax, int split) {
 // `fwd`.
 template <typename T>
 static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>& C, const std::vector<float>& rm2f,
-                       double min_leaf_side, int leaf_src, bool direct, const Prec<T>* fwd = nullptr) {
+                       double min_leaf_side, int leaf_src, bool direct, const Prec<T>* fwd = nullptr,
+                       DBuf* dev_v4 = nullptr, DBuf* dev_v3 = nullptr) {
   const Surface& S = ctx->S;
   const bool adj = fwd != nullptr;
   P.p = p;
@@ -555,15 +556,22 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   upload(P.tgt_pos, tp); upload(P.src_pos, sp);
   // node data and corrections do not depend on the tree: a rebuild (empty C)
   // keeps them where they are
-  if (!adj && !C.empty()) {
+  // (dev_v4, dev_v3: corrections already on the device in the packed
+  // layouts, taken over)
+  if (!adj && (!C.empty() || dev_v4)) {
     upload_as<T>(P.P, ctx->re->P);
     upload_as<T>(P.wo, S.wo);
     upload_as<T>(P.nrm, S.nrm);
     upload_as<T>(P.H, S.H);
-    std::vector<T> v4, v3;
-    pack_vals(C, (int64_t)C.size() / 6, v4, v3);
-    upload(P.vals4, v4);
-    upload(P.vals3, v3);
+    if (dev_v4) {
+      std::swap(P.vals4.p, dev_v4->p); std::swap(P.vals4.bytes, dev_v4->bytes);
+      std::swap(P.vals3.p, dev_v3->p); std::swap(P.vals3.bytes, dev_v3->bytes);
+    } else {
+      std::vector<T> v4, v3;
+      pack_vals(C, (int64_t)C.size() / 6, v4, v3);
+      upload(P.vals4, v4);
+      upload(P.vals3, v3);
+    }
   }
   // translations (level independent: built once)
   if (F.depth >= 2 && !adj && !P.m2l.p) {
@@ -1374,71 +1382,77 @@ lb_status lb_ref_nodes(int order, double* uv, double* w_ref) {
 }
 
 namespace lb {
-// Accurate near integrals A of every (target, near patch) block: the blocks
-// of patches other than the target's own by the device's adaptive rule, the
-// self blocks by the host rule while the device works.
-static void near_integrals_device(const Surface& S, const RefElem& re, const QuadOpts& qo, std::vector<double>& A) {
+// Corrections C = A - B of every (target, near patch) block on the device
+// (self rule, adaptive near rule, far rule with and without the FP32 mask),
+// left in the packed layouts of the combine kernels: v4 (S, Gx, Gy, Gz) and
+// v3 (S, S', S''+D') per (block, node), FP64 and FP32.
+struct DevCorrections {
+  DBuf v4_64, v3_64, v4_32, v3_32;
+};
+
+static void corrections_device(const Surface& S, const RefElem& re, const QuadOpts& qo, const std::vector<float>& rm2,
+                               DevCorrections& out) {
   const int n_p = S.n_p;
   const int64_t nb = S.near_ptr[S.N];
-  std::vector<int64_t> row, blk;
+  std::vector<int64_t> row, blk, brow(nb), sblk(S.N, -1);
   std::vector<int32_t> pat;
   for (int64_t i = 0; i < S.N; ++i)
-    for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b)
-      if (S.near_patch[b] != (int32_t)(i / n_p)) {
+    for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b) {
+      brow[b] = i;
+      if (S.near_patch[b] == (int32_t)(i / n_p)) {
+        sblk[i] = b;
+      } else {
         row.push_back(i);
         blk.push_back(b);
         pat.push_back(S.near_patch[b]);
       }
-  std::vector<double> ru, rw;
+    }
+  std::vector<double> ru, rw, g, gw, tg, tw;
   near_leaf_rule(qo.near_q, ru, rw);
-  DBuf dX, dn, dcX, dcXu, dcXv, dja, djb, djc, dVinv, dru, drw, drow, dblk, dpat, dA;
-  upload(dX, S.X);
-  upload(dn, S.nrm);
-  upload(dcX, S.cX);
-  upload(dcXu, S.cXu);
-  upload(dcXv, S.cXv);
-  upload(dja, re.ja);
-  upload(djb, re.jb);
-  upload(djc, re.jc);
-  upload(dVinv, re.Vinv);
-  upload(dru, ru);
-  upload(drw, rw);
-  upload(drow, row);
-  upload(dblk, blk);
-  upload(dpat, pat);
+  gauss_legendre01(qo.self_n, g, gw);
+  gauss_legendre01(qo.self_nt, tg, tw);
+  DBuf dX, dn, ddXu, ddXv, dJ, dcX, dcXu, dcXv, dja, djb, djc, dVinv, duv, dg, dgw, dtg, dtw, dru, drw;
+  DBuf drow, dblk, dpat, dsblk, dbrow, dnp, ds, dnu, dwo, drm2, dP, dA;
+  upload(dX, S.X); upload(dn, S.nrm); upload(ddXu, S.dXu); upload(ddXv, S.dXv); upload(dJ, S.J);
+  upload(dcX, S.cX); upload(dcXu, S.cXu); upload(dcXv, S.cXv);
+  upload(dja, re.ja); upload(djb, re.jb); upload(djc, re.jc); upload(dVinv, re.Vinv); upload(duv, re.uv);
+  upload(dg, g); upload(dgw, gw); upload(dtg, tg); upload(dtw, tw); upload(dru, ru); upload(drw, rw);
+  upload(drow, row); upload(dblk, blk); upload(dpat, pat); upload(dsblk, sblk); upload(dbrow, brow);
+  upload(dnp, S.near_patch);
+  upload(ds, S.s); upload(dnu, S.nu); upload(dwo, S.wo); upload(drm2, rm2); upload(dP, re.P);
   dA.alloc(sizeof(double) * (size_t)nb * n_p * 6);
-  NearQuadArgs a;
-  a.X = dptr<double>(dX);
-  a.nrm = dptr<double>(dn);
-  a.cX = dptr<double>(dcX);
-  a.cXu = dptr<double>(dcXu);
-  a.cXv = dptr<double>(dcXv);
-  a.ja = dptr<double>(dja);
-  a.jb = dptr<double>(djb);
-  a.jc = dptr<double>(djc);
-  a.Vinv = dptr<double>(dVinv);
-  a.ru = dptr<double>(dru);
-  a.rw = dptr<double>(drw);
-  a.row = dptr<int64_t>(drow);
-  a.blk = dptr<int64_t>(dblk);
-  a.patch = dptr<int32_t>(dpat);
-  a.A = dptr<double>(dA);
-  a.nwork = (int64_t)row.size();
-  a.k = re.k;
-  a.nq = qo.near_q * qo.near_q;
-  a.max_depth = qo.max_depth;
-  a.adm = qo.near_adm;
-  HIPTRY(launch_near_quad(a, nullptr));
-  // self blocks on the host meanwhile, into a copy that the download below
-  // does not overwrite
-  std::vector<double> As((size_t)nb * n_p * 6, 0.0);
-  near_integrals(S, qo, As, true);
-  A.assign((size_t)nb * n_p * 6, 0.0);
-  HIPTRY(hipMemcpy(A.data(), dA.p, sizeof(double) * A.size(), hipMemcpyDeviceToHost));
-  for (int64_t i = 0; i < S.N; ++i)
-    for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b)
-      if (S.near_patch[b] == (int32_t)(i / n_p))
-        std::memcpy(&A[(size_t)b * n_p * 6], &As[(size_t)b * n_p * 6], sizeof(double) * n_p * 6);
+  SelfQuadArgs sq;
+  sq.X = dptr<double>(dX); sq.nrm = dptr<double>(dn); sq.dXu = dptr<double>(ddXu); sq.dXv = dptr<double>(ddXv);
+  sq.J = dptr<double>(dJ);
+  sq.cX = dptr<double>(dcX); sq.cXu = dptr<double>(dcXu); sq.cXv = dptr<double>(dcXv);
+  sq.ja = dptr<double>(dja); sq.jb = dptr<double>(djb); sq.jc = dptr<double>(djc);
+  sq.Vinv = dptr<double>(dVinv); sq.uv = dptr<double>(duv);
+  sq.g = dptr<double>(dg); sq.gw = dptr<double>(dgw); sq.tg = dptr<double>(dtg); sq.tw = dptr<double>(dtw);
+  sq.sblk = dptr<int64_t>(dsblk); sq.A = dptr<double>(dA);
+  sq.N = S.N; sq.k = re.k; sq.ns = qo.self_n; sq.nt = qo.self_nt; sq.panel = qo.self_panel;
+  HIPTRY(launch_self_quad(sq, nullptr));
+  NearQuadArgs nq;
+  nq.X = sq.X; nq.nrm = sq.nrm; nq.cX = sq.cX; nq.cXu = sq.cXu; nq.cXv = sq.cXv;
+  nq.ja = sq.ja; nq.jb = sq.jb; nq.jc = sq.jc; nq.Vinv = sq.Vinv;
+  nq.ru = dptr<double>(dru); nq.rw = dptr<double>(drw);
+  nq.row = dptr<int64_t>(drow); nq.blk = dptr<int64_t>(dblk); nq.patch = dptr<int32_t>(dpat);
+  nq.A = sq.A; nq.nwork = (int64_t)row.size(); nq.k = re.k; nq.nq = qo.near_q * qo.near_q;
+  nq.max_depth = qo.max_depth; nq.adm = qo.near_adm;
+  HIPTRY(launch_near_quad(nq, nullptr));
+  const size_t ne = (size_t)nb * n_p;
+  out.v4_64.alloc(sizeof(double) * ne * 4);
+  out.v3_64.alloc(sizeof(double) * ne * 3);
+  out.v4_32.alloc(sizeof(float) * ne * 4);
+  out.v3_32.alloc(sizeof(float) * ne * 3);
+  FarRuleArgs fr;
+  fr.X = sq.X; fr.nrm = sq.nrm; fr.s = dptr<double>(ds); fr.nu = dptr<double>(dnu); fr.wo = dptr<double>(dwo);
+  fr.rm2 = dptr<float>(drm2); fr.P = dptr<double>(dP);
+  fr.brow = dptr<int64_t>(dbrow); fr.patch = dptr<int32_t>(dnp); fr.A = sq.A;
+  fr.v4_64 = dptr<double>(out.v4_64); fr.v3_64 = dptr<double>(out.v3_64);
+  fr.v4_32 = dptr<float>(out.v4_32); fr.v3_32 = dptr<float>(out.v3_32);
+  fr.nb = nb; fr.n_p = n_p; fr.n_o = S.n_o;
+  HIPTRY(launch_far_rule(fr, nullptr));
+  HIPTRY(hipDeviceSynchronize());
 }
 
 // Setup of n_surf surfaces (surface q: pps[q] patches, in order).
@@ -1493,39 +1507,44 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   qo.self_n = o.self_n;
   qo.near_q = o.near_q;
   qo.near_adm = o.near_adm;
+  // the device rules: at most 3 max_depth + 1 triangles on the near rule's
+  // stack, at most 256 (node, kernel) outputs per block
+  const bool dev_quad = !ctx->host_only && !(o.flags & LB_HOST_QUAD) && 3 * qo.max_depth + 1 <= 72 &&
+                        6 * S.n_p <= 256;
   std::vector<double> A, B;
-  // the device rule keeps at most 3 max_depth + 1 triangles on its stack
-  if (!ctx->host_only && !(o.flags & LB_HOST_QUAD) && 3 * qo.max_depth + 1 <= 72) {
-    HIPTRY(hipGetDevice(&ctx->device));
-    near_integrals_device(S, *ctx->re, qo, A);
-  } else {
+  if (!dev_quad) {
     near_integrals(S, qo, A);
+    std::vector<float> none;
+    far_rule_blocks(S, none, none, none, false, B);
+    ctx->C64.resize(A.size());
+    for (size_t i = 0; i < A.size(); ++i) ctx->C64[i] = A[i] - B[i];
   }
-  std::vector<float> none;
-  far_rule_blocks(S, none, none, none, false, B);
-  ctx->C64.resize(A.size());
-  for (size_t i = 0; i < A.size(); ++i) ctx->C64[i] = A[i] - B[i];
   if (!ctx->host_only) {
     HIPTRY(hipGetDevice(&ctx->device));
     // FP32 near-field mask: sources of patch l within kMaskFrac (eta-1) R_l
     // of a target are left to the corrections (such a patch is always in
     // Near(target), since |x - c_l| < (1 + (eta-1)) R_l)
     const double kMaskFrac = 0.5;
-    std::vector<float> rm2(S.No), tx32(3 * S.N), sx32(3 * S.No);
+    std::vector<float> rm2(S.No);
     double rmax = 0;
     for (int64_t m = 0; m < S.No; ++m) {
       double rm = kMaskFrac * (o.eta_near - 1.0) * S.R[m / S.n_o];
       rm2[m] = (float)(rm * rm);
       rmax = std::max(rmax, rm);
     }
-    for (int64_t i = 0; i < 3 * S.N; ++i) tx32[i] = (float)S.X[i];
-    for (int64_t i = 0; i < 3 * S.No; ++i) sx32[i] = (float)S.s[i];
-    std::vector<double> B32;
-    far_rule_blocks(S, rm2, tx32, sx32, true, B32);
-    std::vector<double> C32(A.size());
-    for (size_t i = 0; i < A.size(); ++i) C32[i] = A[i] - B32[i];
-    B32.clear();
-    B32.shrink_to_fit();
+    std::vector<double> C32;
+    DevCorrections dc;
+    if (dev_quad) {
+      corrections_device(S, *ctx->re, qo, rm2, dc);
+    } else {
+      std::vector<float> tx32(3 * S.N), sx32(3 * S.No);
+      for (int64_t i = 0; i < 3 * S.N; ++i) tx32[i] = (float)S.X[i];
+      for (int64_t i = 0; i < 3 * S.No; ++i) sx32[i] = (float)S.s[i];
+      std::vector<double> B32;
+      far_rule_blocks(S, rm2, tx32, sx32, true, B32);
+      C32.resize(A.size());
+      for (size_t i = 0; i < A.size(); ++i) C32[i] = A[i] - B32[i];
+    }
     A.clear(); A.shrink_to_fit();
     B.clear(); B.shrink_to_fit();
     upload(ctx->row_ptr, S.near_ptr);
@@ -1535,10 +1554,13 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
     upload(ctx->node_surf, nsurf_of);
     upload(ctx->inv_area, inv);
     const bool direct = (o.flags & LB_DIRECT) != 0;
-    build_prec<float>(ctx, ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct);
+    build_prec<float>(ctx, ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct, nullptr,
+                      dev_quad ? &dc.v4_32 : nullptr, dev_quad ? &dc.v3_32 : nullptr);
+    C32.clear(); C32.shrink_to_fit();
     ctx->rm2f = std::move(rm2);
     // the float positions used by the mask test must be exactly the ones on the device
-    build_prec<double>(ctx, ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct);
+    build_prec<double>(ctx, ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct, nullptr,
+                       dev_quad ? &dc.v4_64 : nullptr, dev_quad ? &dc.v3_64 : nullptr);
     HIPTRY(hipDeviceSynchronize());
   }
 }
@@ -1622,7 +1644,20 @@ lb_status lb_get_corrections(const lb_ctx* ctx, int64_t* row_ptr, int32_t* patch
   const Surface& S = ctx->S;
   if (row_ptr) std::memcpy(row_ptr, S.near_ptr.data(), sizeof(int64_t) * (S.N + 1));
   if (patch) std::memcpy(patch, S.near_patch.data(), sizeof(int32_t) * S.near_patch.size());
-  if (vals) std::memcpy(vals, ctx->C64.data(), sizeof(double) * ctx->C64.size());
+  if (vals && !ctx->C64.empty()) {
+    std::memcpy(vals, ctx->C64.data(), sizeof(double) * ctx->C64.size());
+  } else if (vals) {
+    // generated on the device: unpack the FP64 combine layouts
+    const size_t ne = (size_t)S.near_ptr[S.N] * S.n_p;
+    std::vector<double> v4(ne * 4), v3(ne * 3);
+    HIPTRY(hipMemcpy(v4.data(), ctx->f64.vals4.p, sizeof(double) * v4.size(), hipMemcpyDeviceToHost));
+    HIPTRY(hipMemcpy(v3.data(), ctx->f64.vals3.p, sizeof(double) * v3.size(), hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < ne; ++e) {
+      for (int t = 0; t < 4; ++t) vals[6 * e + t] = v4[4 * e + t];
+      vals[6 * e + 4] = v3[3 * e + 1];
+      vals[6 * e + 5] = v3[3 * e + 2];
+    }
+  }
   API_END
 }
 

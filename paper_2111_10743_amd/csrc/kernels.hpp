@@ -277,4 +277,57 @@ struct NearQuadArgs {
 };
 hipError_t launch_near_quad(const NearQuadArgs& q, hipStream_t st);
 
+// Accurate integrals A of the self blocks (Section 4: Duffy triangles at the
+// node, sinh-graded edge variable, principal value of the gradient kernels):
+// target i writes block sblk[i] of A (no block when sblk[i] < 0).
+struct SelfQuadArgs {
+  const double* X = nullptr;    // [N][3]
+  const double* nrm = nullptr;  // [N][3]
+  const double* dXu = nullptr;  // [N][3] derivatives of the interpolated chart at the nodes
+  const double* dXv = nullptr;
+  const double* J = nullptr;    // [N]
+  const double* cX = nullptr;   // [NP][n_p][3]
+  const double* cXu = nullptr;
+  const double* cXv = nullptr;
+  const double* ja = nullptr;   // [(k+1)^2]
+  const double* jb = nullptr;
+  const double* jc = nullptr;
+  const double* Vinv = nullptr; // [n_p][n_p]
+  const double* uv = nullptr;   // [n_p][2] reference nodes
+  const double* g = nullptr;    // [ns] Gauss-Legendre rule on [0, 1] along the rays
+  const double* gw = nullptr;
+  const double* tg = nullptr;   // [nt] the same per panel of the edge variable
+  const double* tw = nullptr;
+  const int64_t* sblk = nullptr;  // [N]
+  double* A = nullptr;          // [nnz_blocks][n_p][6]
+  int64_t N = 0;
+  int k = 0, ns = 0, nt = 0;
+  double panel = 2.0;
+};
+hipError_t launch_self_quad(const SelfQuadArgs& q, hipStream_t st);
+
+// C = A - B of every block (eq. nys-lcq) in the packed layouts of the
+// combine kernels, for FP64 (B over every oversampled point of the patch)
+// and FP32 (B without the points that the float32 near-field kernel skips:
+// float r^2 below rm2 of the point).
+struct FarRuleArgs {
+  const double* X = nullptr;    // [N][3]
+  const double* nrm = nullptr;  // [N][3]
+  const double* s = nullptr;    // [No][3] oversampled points
+  const double* nu = nullptr;   // [No][3]
+  const double* wo = nullptr;   // [No]
+  const float* rm2 = nullptr;   // [No]
+  const double* P = nullptr;    // [n_o][n_p]
+  const int64_t* brow = nullptr;  // [nb] target of each block
+  const int32_t* patch = nullptr; // [nb]
+  const double* A = nullptr;    // [nb][n_p][6]
+  double* v4_64 = nullptr;      // [nb * n_p][4]
+  double* v3_64 = nullptr;      // [nb * n_p][3]
+  float* v4_32 = nullptr;
+  float* v3_32 = nullptr;
+  int64_t nb = 0;
+  int n_p = 0, n_o = 0;
+};
+hipError_t launch_far_rule(const FarRuleArgs& q, hipStream_t st);
+
 }  // namespace lb

@@ -1,18 +1,22 @@
-"""Device generation of the near-patch correction integrals (Section 4,
-eq. nys-lcq2: the accurate integrals A of every (target, near patch) pair
-whose patch is not the target's own; the self blocks stay on the host).
+"""Device generation of the quadrature corrections (Section 4, eqs. nys-lcq
+and nys-lcq2: C = A - B for every (target, near patch) pair; the self rule
+with its principal value, the adaptive near rule and the far rule with and
+without the FP32 mask, all on the device).
 
-* Against the oracle's corrections C = A - B on sampled rows, at the bar of
-  the host rule (2e-10 of the largest entry), for a sphere (k = 4) and an
-  ellipsoid (k = 6).
-* Against the host rule (LB_HOST_QUAD) on every block: the self blocks are
-  the host's in both contexts (bit-identical), the others differ by rounding
-  order only unless a leaf test lands on the other side of its threshold,
-  where both are within the rule's accuracy (2e-10 of the largest entry).
-  Every order 1..7 (each its own kernel instantiation), leaves of 25 points
-  (near_q = 5: lanes left idle) and of 81 points (near_q = 9: two passes of
-  the wavefront).
-* Applies of the two contexts agree to 1e-12.
+* Against the oracle's corrections on sampled rows, at the bar of the host
+  rule (2e-10 of the largest entry), for a sphere (k = 4) and an ellipsoid
+  (k = 6).
+* Against the host rules (LB_HOST_QUAD) on every block: the same rules, so
+  the two differ by rounding order unless a leaf test of the near rule lands
+  on the other side of its threshold, where both are within the rule's
+  accuracy (2e-10 of the largest entry).  Every order 1..7 (each its own
+  kernel instantiation), leaves of 25 points (near_q = 5: lanes left idle)
+  and of 81 points (near_q = 9: two passes of the wavefront).
+* FP64 applies of the two contexts agree to 1e-12 and FP32 applies to 1e-7:
+  the FP32 corrections leave out exactly the far-rule points that the
+  float32 near-field kernel skips, decided by the same float test on both
+  sides (one point decided differently would show as an error of the order
+  of its kernel value, far above float rounding).
 """
 import sys
 import time
@@ -55,11 +59,13 @@ def _compare_to_host(P, X, Xu, Xv, k, label, **kw):
     ph, ch, vh = h.corrections()
     assert np.array_equal(pd, ph) and np.array_equal(cd, ch)
     selfb = _self_mask(pd, cd, d.sizes["n_p"])
-    assert np.array_equal(vd[selfb], vh[selfb])
+    assert selfb.sum() == d.N
     scale = np.abs(vh).max()
-    diff = np.abs(vd[~selfb] - vh[~selfb]).max(axis=(1, 2)) / scale
-    note(f"{label}: setup device rule {t1 - t0:.2f} s, host rule {t2 - t1:.2f} s; "
-         f"{(~selfb).sum()} blocks, max diff {diff.max():.1e}, median {np.median(diff):.1e}")
+    diff = np.abs(vd - vh).max(axis=(1, 2)) / scale
+    ds, dn = diff[selfb], diff[~selfb]
+    note(f"{label}: setup device rules {t1 - t0:.2f} s, host rules {t2 - t1:.2f} s; "
+         f"self blocks {len(ds)}: max diff {ds.max():.1e}, median {np.median(ds):.1e}; "
+         f"other blocks {len(dn)}: max {dn.max() if len(dn) else 0:.1e}, median {np.median(dn) if len(dn) else 0:.1e}")
     assert diff.max() < 2e-10
     return d, h
 
@@ -105,11 +111,12 @@ def test_leaf_rule_sizes_and_applies(torch_dev, near_q):
     X, Xu, Xv = I.star_patches(2, nodes(5), I.star_coeffs(7))
     d, h = _compare_to_host(P, X, Xu, Xv, 5, f"star order 5 near_q={near_q}", near_q=near_q)
     x = torch.tensor(np.random.default_rng(5).standard_normal((2, d.N)), device="cuda")
-    a, b = d.apply_gradS(x), h.apply_gradS(x)
-    e = max(rel_l2(a[key].cpu().numpy(), b[key].cpu().numpy()) for key in ("pot", "grad"))
-    ta = torch.randn(2, d.N, dtype=torch.float64, device="cuda")
-    e3 = rel_l2(d.apply_A3(ta).cpu().numpy(), h.apply_A3(ta).cpu().numpy())
-    note(f"star near_q={near_q}: gradS applies differ {e:.1e}, A3 {e3:.1e}")
-    assert e < 1e-12 and e3 < 1e-12
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-7)):
+        xd = x.to(dt)
+        a, b = d.apply_gradS(xd), h.apply_gradS(xd)
+        e = max(rel_l2(a[key].double().cpu().numpy(), b[key].double().cpu().numpy()) for key in ("pot", "grad"))
+        e3 = rel_l2(d.apply_A3(xd).double().cpu().numpy(), h.apply_A3(xd).double().cpu().numpy())
+        note(f"star near_q={near_q} {dt}: gradS applies differ {e:.1e}, A3 {e3:.1e}")
+        assert e < tol and e3 < tol
     d.close()
     h.close()
