@@ -53,8 +53,8 @@ struct PlanBuf {
   DBuf grp_mat, grp_beg, pair_src, boxes, box_scale, tptr, tpairs, grp_lo, pair_lo, work[9];
 };
 
-template <typename T>
-static void upload(DBuf& d, const std::vector<T>& h);
+template <typename T, class A>
+static void upload(DBuf& d, const std::vector<T, A>& h);
 
 // Triples (matrix id, target box, source box) -> GemmPlan; `boxes` lists every
 // target box that gets an output (boxes without triples get zeros unless
@@ -137,8 +137,8 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
   return tr.size() * pl.nslice;
 }
 
-template <typename T>
-static void upload(DBuf& d, const std::vector<T>& h) {
+template <typename T, class A>
+static void upload(DBuf& d, const std::vector<T, A>& h) {
   d.alloc(sizeof(T) * std::max<size_t>(h.size(), 1));
   if (!h.empty()) HIPTRY(hipMemcpy(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
 }
@@ -274,12 +274,13 @@ static void default_opts(lb_opts* o) {
   o->m2l_trunc64 = 2.0;
 }
 
-template <typename T>
-static void transpose_blocks(const std::vector<double>& src, int nblk, int rows, int cols, std::vector<T>& dst) {
+template <typename T, class V>
+static void transpose_blocks(const V& src, int nblk, int rows, int cols, big_vector<T>& dst) {
   dst.resize((size_t)nblk * rows * cols);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int b = 0; b < nblk; ++b)
-    for (int r = 0; r < rows; ++r)
-      for (int c = 0; c < cols; ++c)
+    for (int c = 0; c < cols; ++c)
+      for (int r = 0; r < rows; ++r)
         dst[(size_t)b * rows * cols + (size_t)c * rows + r] = (T)src[(size_t)b * rows * cols + (size_t)r * cols + c];
 }
 
@@ -577,7 +578,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   if (F.depth >= 2 && !adj && !P.m2l.p) {
     Translations trn;
     trn.build(p);
-    std::vector<T> m;
+    big_vector<T> m;
     transpose_blocks(trn.m2m, 8, P.L, P.L, m); upload(P.m2m, m);
     transpose_blocks(trn.l2l, 8, P.L, P.L, m); upload(P.l2l, m);
     transpose_blocks(trn.m2l, 343, P.L, P.L, m); upload(P.m2l, m);

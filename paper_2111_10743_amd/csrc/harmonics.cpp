@@ -134,7 +134,7 @@ void Translations::build(int p_) {
   const int F = L;
   m2m.assign((size_t)8 * L * L, 0.0);
   l2l.assign((size_t)8 * L * L, 0.0);
-  m2l.assign((size_t)343 * L * L, 0.0);
+  m2l.resize((size_t)343 * L * L);
   std::vector<cd> Tc((size_t)F * F), Rb;
   for (int oct = 0; oct < 8; ++oct) {
     double beta[3] = {(oct & 1) - 0.5, ((oct >> 1) & 1) - 0.5, ((oct >> 2) & 1) - 0.5};
@@ -164,25 +164,40 @@ void Translations::build(int p_) {
           }
     to_real(Tc, p, p, &l2l[(size_t)oct * L * L]);
   }
+  // M2L: T[(k,l)][(n,m)] = (-1)^{k+l} c_{n+k}^{m-l} / (c_k^l c_n^m) St_{n+k}^{m-l}(A);
+  // the factor does not depend on the offset A: tabulated once
+  std::vector<double> fac((size_t)F * F, 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k <= p; ++k)
+    for (int l = -k; l <= k; ++l)
+      for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) {
+          const int nn = n + k, mm = m - l;
+          if (mm < -nn || mm > nn) continue;
+          const double sg = ((k + l) & 1) ? -1.0 : 1.0;
+          fac[(size_t)fidx(k, l) * F + fidx(n, m)] = sg * std::exp(lc(nn, mm) - lc(k, l) - lc(n, m));
+        }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int id = 0; id < 343; ++id) {
-        const int ox = id / 49 - 3, oy = (id / 7) % 7 - 3, oz = id % 7 - 3;
-        if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) continue;
-        std::vector<cd> SA, Tc((size_t)F * F, 0.0);
-        double A[3] = {(double)ox, (double)oy, (double)oz};
-        irregular(2 * p, A, SA);
-        for (int k = 0; k <= p; ++k)
-          for (int l = -k; l <= k; ++l)
-            for (int n = 0; n <= p; ++n)
-              for (int m = -n; m <= n; ++m) {
-                int nn = n + k, mm = m - l;
-                if (mm < -nn || mm > nn) continue;
-                double f = std::exp(lc(nn, mm) - lc(k, l) - lc(n, m));
-                double sg = ((k + l) & 1) ? -1.0 : 1.0;
-                Tc[(size_t)fidx(k, l) * F + fidx(n, m)] = sg * f * SA[fidx(nn, mm)];
-              }
-        to_real(Tc, p, p, &m2l[(size_t)m2l_offset_id(ox, oy, oz) * L * L]);
-      }
+    const int ox = id / 49 - 3, oy = (id / 7) % 7 - 3, oz = id % 7 - 3;
+    double* out = &m2l[(size_t)m2l_offset_id(ox, oy, oz) * L * L];
+    if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) {
+      for (size_t e = 0; e < (size_t)L * L; ++e) out[e] = 0.0;
+      continue;
+    }
+    std::vector<cd> SA, Tc((size_t)F * F, 0.0);
+    double A[3] = {(double)ox, (double)oy, (double)oz};
+    irregular(2 * p, A, SA);
+    for (int k = 0; k <= p; ++k)
+      for (int l = -k; l <= k; ++l)
+        for (int n = 0; n <= p; ++n)
+          for (int m = -n; m <= n; ++m) {
+            const int nn = n + k, mm = m - l;
+            if (mm < -nn || mm > nn) continue;
+            Tc[(size_t)fidx(k, l) * F + fidx(n, m)] = fac[(size_t)fidx(k, l) * F + fidx(n, m)] * SA[fidx(nn, mm)];
+          }
+    to_real(Tc, p, p, out);
+  }
   // derivative maps
   std::vector<cd> Gx, Gy, Gz, Gx2, Gy2, Gz2;
   deriv_maps(p, Gx, Gy, Gz);

@@ -16,15 +16,32 @@
 //   (m = 1..n), L = (p+1)^2 reals.
 #pragma once
 #include <cstdint>
+#include <memory>
+#include <new>
+#include <utility>
 #include <vector>
 
 namespace lb {
+
+// Allocator that leaves value-initialized elements of trivially
+// constructible type uninitialized: large host tables that are filled
+// (in parallel) right after the allocation skip a serial zero-fill.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U> struct rebind { using other = NoInitAlloc<U>; };
+  NoInitAlloc() = default;
+  template <class U> NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U> void construct(U* p) noexcept { ::new (static_cast<void*>(p)) U; }
+  template <class U, class... A> void construct(U* p, A&&... a) { ::new (static_cast<void*>(p)) U(std::forward<A>(a)...); }
+};
+template <class T> using big_vector = std::vector<T, NoInitAlloc<T>>;
 
 struct Translations {
   int p = 0, L = 0;
   std::vector<double> m2m;   // [8][L][L]   child octant -> parent
   std::vector<double> l2l;   // [8][L][L]   parent -> child octant
-  std::vector<double> m2l;   // [343][L][L] offset (target - source) in {-3..3}^3, unit box
+  big_vector<double> m2l;    // [343][L][L] offset (target - source) in {-3..3}^3, unit box
+                             // (zero for the 27 offsets in {-1..1}^3)
   std::vector<double> dgrad; // [3][p^2][L]       d/dx, d/dy, d/dz (unit box)
   std::vector<double> dhess; // [6][(p-1)^2][L]   xx, xy, xz, yy, yz, zz (unit box)
   void build(int p);
