@@ -335,6 +335,32 @@ lb_status lb_solve(lb_ctx *ctx, int nrhs, const double *f, double *u, double tol
 lb_status lb_solve_adj(lb_ctx *ctx, int nrhs, const double *ubar, double *fbar, double tol,
                        int mode, lb_solve_info *info, void *stream);
 
+/* Surface gradient of node values (Section 2): on each patch the order-k
+ * interpolant of psi differentiated along the chart, with the metric of the
+ * chart derivatives X_u, X_v given at the nodes: grad psi = g^{ij} (d_i psi) X_j.  psi: device double [nd][N]; grad:
+ * device double [nd][N][3].  Stream-ordered on `stream`.  Errors: LB_EINVAL
+ * (null pointer, nd < 1, host-only context), LB_EHIP. */
+lb_status lb_surface_grad(lb_ctx *ctx, int nd, const double *psi, double *grad, void *stream);
+
+/* Surface divergence (Section 2) of the tangential part of V (cross_n = 0)
+ * or of n x V (cross_n = 1): |g|^{-1/2} d_i (|g|^{1/2} V^i) with V^i the
+ * contravariant components, the derivatives as in lb_surface_grad.
+ * V: device double [nd][N][3]; div: device double [nd][N].  Stream-ordered. */
+lb_status lb_surface_div(lb_ctx *ctx, int nd, const double *V, int cross_n, double *div,
+                         void *stream);
+
+/* Hodge decomposition of nf tangential fields (harmonic vector field
+ * section): F = grad alpha + n x grad beta + H with Delta alpha = div F,
+ * Delta beta = -div(n x F) (both mean zero; one batched lb_solve of 2 nf
+ * right-hand sides, alpha's first) and H = F - grad alpha - n x grad beta,
+ * divergence free and with n x H divergence free (a harmonic field).
+ * F: device double [nf][N][3] (its tangential part is used); H: device
+ * double [nf][N][3]; alpha, beta: device double [nf][N], nullable.  tol,
+ * mode and info [2 nf n_surf] as lb_solve.  Synchronizes `stream`; returns
+ * LB_ENOCONV as lb_solve (H is still written). */
+lb_status lb_hodge(lb_ctx *ctx, int nf, const double *F, double *alpha, double *beta, double *H,
+                   double tol, int mode, lb_solve_info *info, void *stream);
+
 /* Release all host and device state (NULL is ignored). */
 void lb_destroy(lb_ctx *ctx);
 

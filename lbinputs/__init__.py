@@ -146,6 +146,57 @@ def torus_patches(R, r, n_theta, n_phi, uv):
     return np.array(Xs), np.array(Us), np.array(Vs)
 
 
+# twisted torus: X(u, v) = sum_{i,j} d_ij (cos v cos t, sin v cos t, sin t),
+# t = (1 - i) u + j v, with the nonzero d_ij below (harmonic-fields section)
+TWISTED_TORUS_COEFFS = {(-1, -1): 0.17, (-1, 0): 0.11, (0, 0): 1.0, (1, 0): 4.5, (2, 0): -0.25,
+                        (0, 1): 0.01, (2, 1): -0.45}
+
+
+def twisted_torus_point(u, v):
+    """X, X_u, X_v of the twisted torus at parameters (u, v) (arrays)."""
+    u = np.asarray(u, dtype=float)
+    v = np.asarray(v, dtype=float)
+    X = np.zeros(u.shape + (3,))
+    Xu = np.zeros_like(X)
+    Xv = np.zeros_like(X)
+    cv, sv = np.cos(v), np.sin(v)
+    for (i, j), d in TWISTED_TORUS_COEFFS.items():
+        t = (1 - i) * u + j * v
+        ct, st = np.cos(t), np.sin(t)
+        X += d * np.stack([cv * ct, sv * ct, st], -1)
+        dt = np.stack([-cv * st, -sv * st, ct], -1)        # d/dt
+        Xu += d * (1 - i) * dt
+        Xv += d * (np.stack([-sv * ct, cv * ct, 0 * ct], -1) + j * dt)
+    return X, Xu, Xv
+
+
+def twisted_torus_patches(n_u, n_v, uv):
+    """The twisted torus on an n_v x n_u grid of (v, u) cells (v the long way
+    round), each cell split into the triangles corner (0,0) + a e_v + b e_u
+    and corner (1,1) - a e_v - b e_u, so that X_a x X_b points outward."""
+    uv = np.asarray(uv, dtype=float)
+    du = 2 * np.pi / n_u
+    dv = 2 * np.pi / n_v
+    Xs, As, Bs = [], [], []
+    for iu in range(n_u):
+        for iv in range(n_v):
+            for corner, sgn in (((0, 0), 1.0), ((1, 1), -1.0)):
+                v = (iv + corner[0]) * dv + sgn * dv * uv[:, 0]
+                u = (iu + corner[1]) * du + sgn * du * uv[:, 1]
+                X, Xu, Xv = twisted_torus_point(u, v)
+                Xs.append(X)
+                As.append(sgn * dv * Xv)
+                Bs.append(sgn * du * Xu)
+    return np.array(Xs), np.array(As), np.array(Bs)
+
+
+def current_source_field(x, x0=(0.2, 0.2, 0.2), ell=(0.0, 1.0, 1.0)):
+    """V = ell x (x - x0) / |x - x0|^3 (a line current element at x0)."""
+    d = np.asarray(x, dtype=float) - np.asarray(x0, dtype=float)
+    r3 = np.linalg.norm(d, axis=-1, keepdims=True) ** 3
+    return np.cross(np.asarray(ell, dtype=float), d) / r3
+
+
 def torus_mean_curvature(X, R, r):
     """H = (R + 2 r cos th) / (2 r (R + r cos th)) with the outward normal."""
     rho = np.linalg.norm(X[..., :2], axis=-1)

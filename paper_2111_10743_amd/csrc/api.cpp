@@ -234,6 +234,10 @@ struct lb_ctx {
   DBuf z32, z64, a3t_a, a3t_b, a3t_scal;
   bool z_built32 = false, z_built64 = false;
   std::vector<float> rm2f;
+  // surface calculus (built on first use): nodal differentiation matrices,
+  // the chart derivatives given at the nodes and the normals, FP64
+  DBuf c_Du, c_Dv, c_Xu, c_Xv, c_nrm;
+  bool calc_built = false;
   // solver workspace
   DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp, msys, msys_part, msys2;
   // per-surface row ranges: node_off [n_surf+1] (host and device), the
@@ -1984,6 +1988,71 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
     lb::set_last_error("GMRES did not reach the tolerance for some right-hand side");
     return ret;
   }
+  API_END
+}
+
+namespace lb {
+static SurfCalcArgs calc_args(lb_ctx* ctx) {
+  if (!ctx->calc_built) {
+    upload(ctx->c_Du, ctx->re->Du);
+    upload(ctx->c_Dv, ctx->re->Dv);
+    upload(ctx->c_Xu, ctx->S.Xu);
+    upload(ctx->c_Xv, ctx->S.Xv);
+    upload(ctx->c_nrm, ctx->S.nrm);
+    ctx->calc_built = true;
+  }
+  SurfCalcArgs q;
+  q.Du = dptr<double>(ctx->c_Du);
+  q.Dv = dptr<double>(ctx->c_Dv);
+  q.Xu = dptr<double>(ctx->c_Xu);
+  q.Xv = dptr<double>(ctx->c_Xv);
+  q.nrm = dptr<double>(ctx->c_nrm);
+  q.N = ctx->N;
+  q.n_p = ctx->n_p;
+  return q;
+}
+}  // namespace lb
+
+lb_status lb_surface_grad(lb_ctx* ctx, int nd, const double* psi, double* grad, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, LB_PREC_FP64);
+  if (!psi || !grad) fail(LB_EINVAL, "null psi or grad");
+  HIPTRY(launch_surf_grad(calc_args(ctx), nd, psi, grad, (hipStream_t)stream));
+  API_END
+}
+
+lb_status lb_surface_div(lb_ctx* ctx, int nd, const double* V, int cross_n, double* div, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, LB_PREC_FP64);
+  if (!V || !div) fail(LB_EINVAL, "null V or div");
+  if (cross_n != 0 && cross_n != 1) fail(LB_EINVAL, "cross_n must be 0 or 1");
+  HIPTRY(launch_surf_div(calc_args(ctx), nd, V, cross_n, 1.0, div, (hipStream_t)stream));
+  API_END
+}
+
+lb_status lb_hodge(lb_ctx* ctx, int nf, const double* F, double* alpha, double* beta, double* H, double tol,
+                   int mode, lb_solve_info* info, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nf, LB_PREC_FP64);
+  if (!F || !H) fail(LB_EINVAL, "null F or H");
+  hipStream_t st = (hipStream_t)stream;
+  const SurfCalcArgs q = calc_args(ctx);
+  const size_t nN = (size_t)nf * ctx->N;
+  DBuf rhs, u;
+  rhs.alloc(sizeof(double) * nN * 2);
+  u.alloc(sizeof(double) * nN * 2);
+  double* r = dptr<double>(rhs);
+  double* uu = dptr<double>(u);
+  // Delta alpha = div F (rows 0..nf-1), Delta beta = -div(n x F) (rows nf..2nf-1)
+  HIPTRY(launch_surf_div(q, nf, F, 0, 1.0, r, st));
+  HIPTRY(launch_surf_div(q, nf, F, 1, -1.0, r + nN, st));
+  const lb_status status = lb_solve(ctx, 2 * nf, r, uu, tol, mode, info, stream);
+  if (status < 0) return status;
+  HIPTRY(launch_hodge_h(q, nf, F, uu, uu + nN, H, st));
+  if (alpha) HIPTRY(hipMemcpyAsync(alpha, uu, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
+  if (beta) HIPTRY(hipMemcpyAsync(beta, uu + nN, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
+  HIPTRY(hipStreamSynchronize(st));
+  if (status != LB_OK) return status;
   API_END
 }
 

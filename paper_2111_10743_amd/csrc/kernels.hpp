@@ -330,4 +330,26 @@ struct FarRuleArgs {
 };
 hipError_t launch_far_rule(const FarRuleArgs& q, hipStream_t st);
 
+// Surface calculus of node values (Section 2): the order-k interpolant on
+// each patch differentiated in the chart (Du, Dv [n_p][n_p] nodal
+// differentiation, Xu, Xv [N][3] the chart derivatives given at the nodes).
+struct SurfCalcArgs {
+  const double* Du = nullptr;
+  const double* Dv = nullptr;
+  const double* Xu = nullptr;
+  const double* Xv = nullptr;
+  const double* nrm = nullptr;  // [N][3]
+  int64_t N = 0;
+  int n_p = 0;
+};
+// grad [nd][N][3] = surface gradient of psi [nd][N]
+hipError_t launch_surf_grad(const SurfCalcArgs& q, int nd, const double* psi, double* grad, hipStream_t st);
+// div [nd][N] = sign * surface divergence of the tangential part of V (or of
+// n x V when cross_n), V [nd][N][3]
+hipError_t launch_surf_div(const SurfCalcArgs& q, int nd, const double* V, int cross_n, double sign, double* div,
+                           hipStream_t st);
+// H [nf][N][3] = F - grad alpha - n x grad beta (alpha, beta [nf][N])
+hipError_t launch_hodge_h(const SurfCalcArgs& q, int nf, const double* F, const double* alpha, const double* beta,
+                          double* H, hipStream_t st);
+
 }  // namespace lb

@@ -36,8 +36,8 @@ LB_NO_OVERLAP = 64
 
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
-            "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj", "lb_destroy",
-            "lb_last_error")
+            "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj",
+            "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_destroy", "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -118,6 +118,9 @@ def lib():
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_solve_adj.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_apply_A3_adj.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_surface_grad.argtypes = [vp, ip, vp, vp, vp]
+        L.lb_surface_div.argtypes = [vp, ip, vp, ip, vp, vp]
+        L.lb_hodge.argtypes = [vp, ip, vp, vp, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_destroy.argtypes = [vp]
         L.lb_destroy.restype = None
         L.lb_tree_destroy.restype = None
@@ -413,6 +416,48 @@ class Surface:
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
                   "removed_mean": i.removed_mean} for i in info]
         return u, infos, code
+
+    def _field(self, V):
+        import torch
+        if V.dtype != torch.float64 or not V.is_cuda or not V.is_contiguous() or V.shape[-1] != 3 \
+                or V.numel() % (3 * self.N) != 0:
+            raise ValueError("field must be a contiguous float64 device tensor [..., N, 3]")
+        return V.numel() // (3 * self.N)
+
+    def surface_grad(self, psi):
+        """lb_surface_grad: surface gradient of node values psi [..., N] -> [..., N, 3] (FP64)."""
+        import torch
+        if psi.dtype != torch.float64:
+            raise TypeError("psi must be float64")
+        nd = self._nd(psi)
+        g = torch.empty(psi.shape + (3,), dtype=psi.dtype, device=psi.device)
+        _check(lib().lb_surface_grad(self._ctx, nd, _ptr(psi), _ptr(g), _stream()))
+        return g
+
+    def surface_div(self, V, cross_n=False):
+        """lb_surface_div: surface divergence of the tangential part of V
+        [..., N, 3] (of n x V with cross_n) -> [..., N] (FP64)."""
+        import torch
+        nd = self._field(V)
+        d = torch.empty(V.shape[:-1], dtype=V.dtype, device=V.device)
+        _check(lib().lb_surface_div(self._ctx, nd, _ptr(V), int(bool(cross_n)), _ptr(d), _stream()))
+        return d
+
+    def hodge(self, F, tol=1e-10, mode=LB_SOLVE_FP64):
+        """lb_hodge: F = grad alpha + n x grad beta + H for fields F
+        [..., N, 3]; returns (alpha, beta, H, info, code), info per solve
+        (alpha's systems first)."""
+        import torch
+        nf = self._field(F)
+        alpha = torch.empty(F.shape[:-1], dtype=F.dtype, device=F.device)
+        beta = torch.empty_like(alpha)
+        H = torch.empty_like(F)
+        info = (SolveInfo * (2 * nf * self.n_surf))()
+        code = _check(lib().lb_hodge(self._ctx, nf, _ptr(F), _ptr(alpha), _ptr(beta), _ptr(H), tol, mode, info,
+                                     _stream()))
+        infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
+                  "removed_mean": i.removed_mean} for i in info]
+        return alpha, beta, H, infos, code
 
 
 @functools.lru_cache(maxsize=None)

@@ -117,3 +117,27 @@ def test_harmonic_parts_vanish_sphere(c1_oracle):
         F = tangential(g, I.legendre_field(g.x, 50 + s, 2, 1.1))
         _, _, H = hodge(g, lambda f: o.solve(f, tol=1e-11)[0], F)
         assert wnorm(g, H) < 1e-2 * wnorm(g, F)
+
+
+def test_twisted_torus_charts():
+    """The twisted torus of the harmonic-fields section: chart derivatives
+    against central differences, a closed surface (sum of w n = 0), normals
+    outward (enclosed volume (1/3) sum w x.n > 0), and the current element
+    at (0.2, 0.2, 0.2) outside the solid (in the hole)."""
+    u = np.array([0.3, 1.7, 4.0])
+    v = np.array([2.1, 5.0, 0.4])
+    h = 1e-6
+    X, Xu, Xv = I.twisted_torus_point(u, v)
+    fu = (I.twisted_torus_point(u + h, v)[0] - I.twisted_torus_point(u - h, v)[0]) / (2 * h)
+    fv = (I.twisted_torus_point(u, v + h)[0] - I.twisted_torus_point(u, v - h)[0]) / (2 * h)
+    assert np.abs(fu - Xu).max() < 1e-8 and np.abs(fv - Xv).max() < 1e-8
+    Xp, Xa, Xb = I.twisted_torus_patches(4, 16, nodes(5))
+    g = Geometry(Xp, Xa, Xb, 5)
+    # (the quadrature error of this coarse mesh: 1.3e-5 of the area)
+    assert np.abs((g.w[:, None] * g.n).sum(0)).max() < 1e-4 * g.w.sum()
+    vol = (g.w * (g.x * g.n).sum(1)).sum() / 3
+    assert vol > 0
+    # solid angle of the surface seen from x0: 0 outside the solid
+    d = g.x - 0.2
+    omega = (g.w * (d * g.n).sum(1) / np.linalg.norm(d, axis=1) ** 3).sum()
+    assert abs(omega) < 1e-3 * 4 * np.pi
