@@ -15,6 +15,11 @@ and six more band-limited data.  Checks:
 * every solution agrees with the plain FP64 solve to 1e-9.
 Surface gradients and divergences of node values come from the order-6
 interpolant on each patch (oracle.hodge), applied to the library's solves.
+
+The entry points lb_surface_grad / lb_surface_div (against the oracle's
+calculus) and lb_hodge (the exact torus field; a random field against the
+library's solve plus the oracle's calculus), and the twisted torus of the
+harmonic-fields section with the field of a current element.
 """
 import sys
 import time
