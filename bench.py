@@ -12,8 +12,9 @@ field, corrections, combination): value = N / step time in Mpoints/s.
 The JSON line also carries the FP64 apply rate, the solve times (unless
 --no-solve; each mode solved once untimed first, so that allocations and
 graph capture are not timed), the dominant kernel against its roofline (HIP events on the
-library's stream) and the FP64 oracle timed on a bounded sample on the
-host cores.
+library's stream), the Hodge decomposition of the twisted torus of the
+harmonic-fields section at N = 108,000 (unless --no-hodge) and the FP64
+oracle timed on a bounded sample on the host cores.
 """
 import argparse
 import json
@@ -104,6 +105,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and FP32+refine solves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default octree depth and leaf shape")
+    ap.add_argument("--no-hodge", action="store_true", help="skip the twisted-torus Hodge decomposition")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
@@ -235,10 +237,44 @@ def main():
         d = us["fp32_refine"] - us["fp64"]
         res["fp32_refine_vs_fp64_rel_l2"] = float(torch.sqrt((w * d * d).sum() / (w * us["fp64"] ** 2).sum()))
         out["solve"] = res
+    s.close()
+    if not args.no_hodge:
+        out["hodge_twisted_torus"] = hodge_run(P, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(X, Xu, Xv, k, f, args.cpu_rows)
-    s.close()
     print(json.dumps(out))
+
+
+def hodge_run(P, torch, n_u=20, n_v=75, k=7):
+    """Harmonic part of the current-element field on the twisted torus
+    (order 7, 20 x 75 cells split in two: N = 108,000 nodes, the paper's
+    finer size): lb_hodge time t_s (two batched FP32 + refinement solves at
+    GMRES tolerance 5e-10 and the surface calculus; setup excluded, as the
+    paper reuses its corrections), iterations, |H| and the divergence proxies."""
+    import lbinputs as I
+    uv = P.ref_nodes(k)[0]
+    X, Xu, Xv = I.twisted_torus_patches(n_u, n_v, uv)
+    t0 = time.perf_counter()
+    s = P.Surface(X, Xu, Xv, k)
+    t_setup = time.perf_counter() - t0
+    w, nrm, _ = s.geometry()
+    x = X.reshape(-1, 3)
+    V = I.current_source_field(x)
+    F = torch.tensor(V - nrm * (nrm * V).sum(1, keepdims=True), device="cuda")
+    s.hodge(F, tol=5e-10, mode=P.LB_SOLVE_FP32_REFINE)  # untimed: workspaces and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, H, info, code = s.hodge(F, tol=5e-10, mode=P.LB_SOLVE_FP32_REFINE)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    wt = torch.tensor(w, device="cuda")
+    wn = lambda v: float(torch.sqrt((wt * (v * v).reshape(len(w), -1).sum(1)).sum()))
+    res = {"N": s.N, "order": k, "cells": [n_u, n_v], "setup_s": round(t_setup, 2), "t_s": t_s,
+           "iters": [i["iters"] for i in info], "status": code, "H_norm": wn(H),
+           "div_H": wn(s.surface_div(H)), "div_nxH": wn(s.surface_div(H, cross_n=True))}
+    print(f"[bench] hodge twisted torus {res}", file=sys.stderr, flush=True)
+    s.close()
+    return res
 
 
 if __name__ == "__main__":
