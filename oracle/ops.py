@@ -7,6 +7,10 @@
 * Section 4.1 (the gradient part of the A1 apply): grad S, and the surface
   gradient grad_Gamma S = grad S - n (n . grad S), which equals the g^{ij}
   form of that section.
+* Section 4.1 / eq. (ie-dis0): A1[tau] = div S[mu] + W(S tau) S[1] with
+  mu = grad_Gamma S tau, div S[mu] = sum_l d_l S[mu_l] (each Cartesian
+  component of mu a density of the single layer, its x_l derivative taken),
+  applied right to left.
 * Section 4.3 / eq. (ie-dis2): A3[tau] = -tau/4 + S'[S' tau]
   - (S''+D')[S tau] - 2 H S'[S tau] + W S[S tau], applied right to left, with
   W[phi] = sum_j w_j phi_j / sum_j w_j (the averaging operator of Section 3).
@@ -206,6 +210,33 @@ class Oracle:
         SS = S @ S
         return (-0.25 * np.eye(g.N) + Sp @ Sp - K @ S - 2.0 * g.H[:, None] * (Sp @ S)
                 + np.outer(np.ones(g.N), g.w @ SS) / g.w.sum())
+
+    def A1_matrix(self):
+        """Dense A1 of Section 4.1 from the operator matrices (all rows, small N):
+        sum_l G_l T_l G + (1/area) S 1 w^T S, with G = (G_1, G_2, G_3) the
+        gradient matrices and T_l the l-th row of the tangential projector
+        I - n n^T at each node."""
+        g = self.g
+        if getattr(self, "_M", None) is None:
+            self._M = self.operator_matrices()
+        S = self._M[0]
+        G = self._M[1:4]
+        A = np.outer(S @ np.ones(g.N), g.w @ S) / g.w.sum()
+        for l in range(3):
+            Mu = G[l] - g.n[:, l, None] * sum(g.n[:, m, None] * G[m] for m in range(3))
+            A += G[l] @ Mu
+        return A
+
+    def A1(self, tau):
+        """Section 4.1; needs all rows (targets == all nodes)."""
+        g = self.g
+        assert len(self.targets) == g.N
+        L = self.layer(tau)
+        grad = L[:, 1:4]
+        mu = grad - g.n * (grad * g.n).sum(-1, keepdims=True)
+        div = sum(self.layer(mu[:, l])[:, 1 + l] for l in range(3))
+        phi0 = self.layer(np.ones(g.N))[:, 0]
+        return div + self.W(L[:, 0]) * phi0
 
     def solve_adjoint(self, ubar):
         """fbar = (I - w 1^T / area) A3^{-T} S^T S^T ubar: the transpose of the

@@ -232,3 +232,45 @@ def test_position_vjp_S(c1_oracle):
     sub = o.position_vjp_S(sig, gb, patches=[3, 17])
     rows = np.concatenate([np.arange(3 * g.n_p, 4 * g.n_p), np.arange(17 * g.n_p, 18 * g.n_p)])
     assert np.allclose(sub, Xb[rows], rtol=0, atol=1e-13 * np.abs(Xb).max())
+
+
+def test_sphere_A1_eigenvalues(c1_oracle):
+    """A1 = S (Delta + W) S (Section 4.1) on the unit sphere: S Y_l = Y_l /
+    (2l+1) and Delta Y_l = -l(l+1) Y_l give A1 Y_l = -l(l+1)/(2l+1)^2 Y_l,
+    the eigenvalue of A3 as well; S[1] = 1 and W[1] = 1 give A1[1] = 1.  The
+    dense assembly equals the apply."""
+    o = c1_oracle
+    g = o.g
+    assert np.abs(o.A1(np.ones(g.N)) - 1.0).max() < 1e-3
+    for l, m in [(1, 0), (2, 1), (3, -2)]:
+        Y = I.real_sph_harm(l, m, g.x)
+        lam = -l * (l + 1) / (2 * l + 1) ** 2
+        assert rel_l2(o.A1(Y), lam * Y, g.w) < 3e-3
+    tau = np.cos(2 * g.x[:, 0]) + g.x[:, 1] * g.x[:, 2]
+    assert rel_l2(o.A1_matrix() @ tau, o.A1(tau)) < 1e-13
+
+
+def test_numerical_second_kindness(c1_oracle):
+    """Section 5 (numerical second-kindness): on the sphere with order-4
+    patches, the smallest singular value of A1 (no explicit identity term)
+    falls under refinement while that of A3 stays put, and GMRES on A1 needs
+    many more iterations, reaching the cap at the finer mesh, while A3
+    converges in a handful (data: random degree <= 4 harmonics, coefficients
+    U(-0.5, 0.5))."""
+    from oracle.ops import gmres
+    res = []
+    for nsub in (0, 1):
+        g, o = sphere(4, 0) if nsub == 0 else (c1_oracle.g, c1_oracle)
+        A1, A3 = o.A1_matrix(), o.A3_matrix()
+        s1 = np.linalg.svd(A1, compute_uv=False)
+        s3 = np.linalg.svd(A3, compute_uv=False)
+        rng = np.random.default_rng(3)
+        f = sum(rng.uniform(-0.5, 0.5) * I.real_sph_harm(l, m, g.x) for l in range(1, 5) for m in range(-l, l + 1))
+        f = f - o.W(f)
+        _, i1 = gmres(lambda v: A1 @ v, o._M[0] @ f, tol=1e-14, max_iter=100)
+        _, i3 = gmres(lambda v: A3 @ v, f, tol=1e-14, max_iter=100)
+        res.append((s1[-1], s3[-1], i1["iters"], i3["iters"]))
+    (a0, b0, n10, n30), (a1, b1, n11, n31) = res
+    assert a1 < a0 / 2 and abs(b1 - b0) < 0.05 * b0
+    assert a1 < 1e-2 * b1
+    assert n30 <= 12 and n31 <= 12 and n10 > 3 * n30 and n11 == 100
