@@ -335,6 +335,15 @@ lb_status lb_solve(lb_ctx *ctx, int nrhs, const double *f, double *u, double tol
 lb_status lb_solve_adj(lb_ctx *ctx, int nrhs, const double *ubar, double *fbar, double tol,
                        int mode, lb_solve_info *info, void *stream);
 
+/* A1 (Section 4.1, eq. ie-dis0): A1[tau] = div S[grad_Gamma S tau] + S W S tau,
+ * the non-second-kind discretization of S (Delta + W) S, applied right to
+ * left: S tau and mu = grad_Gamma S tau by one gradient apply, the three
+ * Cartesian components of mu as densities of a second gradient apply,
+ * div S[mu] = sum_l (d_l S)[mu_l], plus W(S tau) S[1] per surface (S[1]
+ * computed on first use).  tau, out: device [nd][N] in the precision `prec`
+ * (32 or 64).  Stream-ordered.  Errors as lb_apply_S. */
+lb_status lb_apply_A1(lb_ctx *ctx, int nd, int prec, const void *tau, void *out, void *stream);
+
 /* Surface gradient of node values (Section 2): on each patch the order-k
  * interpolant of psi differentiated along the chart, with the metric of the
  * chart derivatives X_u, X_v given at the nodes: grad psi = g^{ij} (d_i psi) X_j.  psi: device double [nd][N]; grad:

@@ -238,6 +238,8 @@ struct lb_ctx {
   // the chart derivatives given at the nodes and the normals, FP64
   DBuf c_Du, c_Dv, c_Xu, c_Xv, c_nrm;
   bool calc_built = false;
+  // A1 workspace per precision: S[1], and the intermediate applies
+  DBuf a1_phi0_32, a1_phi0_64, a1_pot, a1_g1, a1_surf, a1_mu, a1_g2, a1_eta;
   // solver workspace
   DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp, msys, msys_part, msys2;
   // per-surface row ranges: node_off [n_surf+1] (host and device), the
@@ -795,6 +797,38 @@ static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hi
                           dptr<double>(ctx->inv_area), out + (int64_t)d0 * N, dptr<T>(P.y2),
                           dptr<double>(ctx->seg_scal), st);
   }
+}
+
+// A1 (Section 4.1, eq. ie-dis0) for nd densities: S tau and grad_Gamma S tau
+// (one gradient apply), mu = grad_Gamma S tau as three densities, the
+// gradient apply of mu, and div S[mu] = sum_l (d_l S)[mu_l] plus
+// W(S tau) S[1] (S[1] computed once per precision).
+template <typename T>
+static void apply_A1_t(lb_ctx* ctx, Prec<T>& P, DBuf& phi0, int nd, const T* tau, T* out, hipStream_t st) {
+  const int64_t N = ctx->N;
+  const int nsf = ctx->n_surf;
+  if (!phi0.p) {
+    std::vector<T> one((size_t)N, (T)1);
+    DBuf d1;
+    upload(d1, one);
+    phi0.alloc(sizeof(T) * N);
+    apply_S_t<T>(ctx, P, 1, dptr<T>(d1), dptr<T>(phi0), st);
+    HIPTRY(hipStreamSynchronize(st));
+  }
+  ctx->a1_pot.alloc(sizeof(T) * (size_t)nd * N);
+  ctx->a1_g1.alloc(sizeof(T) * (size_t)nd * N * 3);
+  ctx->a1_surf.alloc(sizeof(T) * (size_t)nd * N * 3);
+  ctx->a1_mu.alloc(sizeof(T) * (size_t)nd * N * 3);
+  ctx->a1_g2.alloc(sizeof(T) * (size_t)nd * N * 9);
+  ctx->a1_eta.alloc(sizeof(double) * (size_t)nd * nsf);
+  T* pot = dptr<T>(ctx->a1_pot);
+  apply_gradS_t<T>(ctx, P, nd, tau, pot, dptr<T>(ctx->a1_g1), nullptr, dptr<T>(ctx->a1_surf), st);
+  HIPTRY(launch_a1_split<T>(N, nd, dptr<T>(ctx->a1_surf), dptr<T>(ctx->a1_mu), st));
+  apply_gradS_t<T>(ctx, P, 3 * nd, dptr<T>(ctx->a1_mu), nullptr, dptr<T>(ctx->a1_g2), nullptr, nullptr, st);
+  launch_seg_dot<T>(nd, nsf, N, dptr<int64_t>(ctx->node_off), pot, dptr<double>(ctx->w), dptr<double>(ctx->inv_area),
+                    dptr<double>(ctx->a1_eta), st);
+  HIPTRY(launch_a1_finish<T>(N, nd, nsf, dptr<int>(ctx->node_surf), dptr<T>(ctx->a1_g2), dptr<double>(ctx->a1_eta),
+                             dptr<T>(phi0), out, st));
 }
 
 // ---------------------------------------------------------------------------
@@ -1688,6 +1722,19 @@ lb_status lb_apply_gradS(lb_ctx* ctx, int nd, int prec, const void* sigma, void*
   else
     apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, (double*)grad, (double*)dSdn,
                           (double*)surf_grad, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_apply_A1(lb_ctx* ctx, int nd, int prec, const void* tau, void* out, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!tau || !out) fail(LB_EINVAL, "null tau or out");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_A1_t<float>(ctx, ctx->f32, ctx->a1_phi0_32, nd, (const float*)tau, (float*)out, st);
+  else
+    apply_A1_t<double>(ctx, ctx->f64, ctx->a1_phi0_64, nd, (const double*)tau, (double*)out, st);
   HIPTRY(hipGetLastError());
   API_END
 }

@@ -136,3 +136,62 @@ hipError_t launch_hodge_h(const SurfCalcArgs& q, int nf, const double* F, const 
 }
 
 }  // namespace lb
+
+// ---------------------------------------------------------------------------
+// A1 (Section 4.1, eq. ie-dis0): A1[tau] = div S[mu] + W(S tau) S[1] with
+// mu = grad_Gamma S tau; the two elementwise steps between the applies.
+// ---------------------------------------------------------------------------
+namespace lb {
+namespace {
+
+// mu[3 d + l][i] = surf[d][i][l]
+template <typename T>
+__global__ void k_a1_split(int64_t N, int nd, const T* surf, T* mu) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nd * N) return;
+  const int64_t d = t / N, i = t - d * N;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) mu[(3 * d + l) * N + i] = surf[3 * t + l];
+}
+
+// out[d][i] = sum_l g[3 d + l][i][l] + eta[d][surface of i] phi0[i]
+template <typename T>
+__global__ void k_a1_finish(int64_t N, int nd, int nsurf, const int* surf_of, const T* g, const double* eta,
+                            const T* phi0, T* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nd * N) return;
+  const int64_t d = t / N, i = t - d * N;
+  double s = 0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) s += (double)g[((3 * d + l) * N + i) * 3 + l];
+  out[t] = (T)(s + eta[d * nsurf + surf_of[i]] * (double)phi0[i]);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_a1_split(int64_t N, int nd, const T* surf, T* mu, hipStream_t st) {
+  const int64_t n = (int64_t)nd * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_a1_split<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, nd, surf, mu);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_a1_finish(int64_t N, int nd, int nsurf, const int* surf_of, const T* g, const double* eta,
+                            const T* phi0, T* out, hipStream_t st) {
+  const int64_t n = (int64_t)nd * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_a1_finish<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, nd, nsurf, surf_of, g,
+                     eta, phi0, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_a1_split<float>(int64_t, int, const float*, float*, hipStream_t);
+template hipError_t launch_a1_split<double>(int64_t, int, const double*, double*, hipStream_t);
+template hipError_t launch_a1_finish<float>(int64_t, int, int, const int*, const float*, const double*, const float*,
+                                            float*, hipStream_t);
+template hipError_t launch_a1_finish<double>(int64_t, int, int, const int*, const double*, const double*,
+                                             const double*, double*, hipStream_t);
+
+}  // namespace lb

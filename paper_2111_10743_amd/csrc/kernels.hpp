@@ -352,4 +352,13 @@ hipError_t launch_surf_div(const SurfCalcArgs& q, int nd, const double* V, int c
 hipError_t launch_hodge_h(const SurfCalcArgs& q, int nf, const double* F, const double* alpha, const double* beta,
                           double* H, hipStream_t st);
 
+// A1 (Section 4.1): mu [3 nd][N] from grad_Gamma S tau [nd][N][3], and
+// out [nd][N] = sum_l (d_l S)[mu_l] + eta[d][surface] S[1] from the gradient
+// apply of mu (g [3 nd][N][3]), eta [nd][nsurf] and phi0 = S[1] [N]
+template <typename T>
+hipError_t launch_a1_split(int64_t N, int nd, const T* surf, T* mu, hipStream_t st);
+template <typename T>
+hipError_t launch_a1_finish(int64_t N, int nd, int nsurf, const int* surf_of, const T* g, const double* eta,
+                            const T* phi0, T* out, hipStream_t st);
+
 }  // namespace lb

@@ -37,7 +37,7 @@ LB_NO_OVERLAP = 64
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj",
-            "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_destroy", "lb_last_error")
+            "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_apply_A1", "lb_destroy", "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -118,6 +118,7 @@ def lib():
         L.lb_solve.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_solve_adj.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_apply_A3_adj.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_apply_A1.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_surface_grad.argtypes = [vp, ip, vp, vp, vp]
         L.lb_surface_div.argtypes = [vp, ip, vp, ip, vp, vp]
         L.lb_hodge.argtypes = [vp, ip, vp, vp, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
@@ -382,6 +383,14 @@ class Surface:
         nd = self._nd(tau)
         res = out if out is not None else torch.empty_like(tau)
         _check(lib().lb_apply_A3(self._ctx, nd, self._prec(tau), _ptr(tau), _ptr(res), _stream()))
+        return res
+
+    def apply_A1(self, tau, out=None):
+        """lb_apply_A1: div S[grad_Gamma S tau] + S W S tau (Section 4.1)."""
+        import torch
+        nd = self._nd(tau)
+        res = out if out is not None else torch.empty_like(tau)
+        _check(lib().lb_apply_A1(self._ctx, nd, self._prec(tau), _ptr(tau), _ptr(res), _stream()))
         return res
 
     def apply_A3_adj(self, v, out=None):
