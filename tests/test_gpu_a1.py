@@ -1,0 +1,108 @@
+"""A1 (Section 4.1, eq. ie-dis0) through the C ABI, and the numerical
+second-kindness section with the library's operators.
+
+* lb_apply_A1 against the oracle's A1 on every row (sphere and ellipsoid,
+  20 order-4 patches, N = 300): FP64 <= 1e-9, FP32 <= 2e-5 (two gradient
+  applies in sequence, the second on tangential components of the first).
+* A batch of densities equals the densities applied one at a time.
+* Dense A1 and A3 assembled from the library's FP64 applies (the paper uses
+  dense matrices to keep FMM errors out; the FP64 FMM's 1e-11 are far below
+  the singular values in question) on the sphere with order-4 patches, N = 1200 and 4800 (the paper: 1920 and
+  7680): the smallest singular value of A1 falls under refinement while
+  A3's stays put, and GMRES (tol 1e-14, at most 100 iterations; data:
+  random degree <= 4 harmonics with U(-0.5, 0.5) coefficients) converges on
+  A3 in a handful of iterations and stalls at the cap on A1.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lbinputs as I
+from conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("shape", ["sphere", "ellipsoid"])
+def test_A1_against_oracle(torch_dev, shape):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.geometry import Geometry
+    from oracle.ops import Oracle
+    from oracle.refelem import nodes
+    if shape == "sphere":
+        X, Xu, Xv = I.sphere_patches(0, nodes(4))
+    else:
+        X, Xu, Xv = I.ellipsoid_patches(0, nodes(4), (1.0, 1.5, 2.0))
+    g = Geometry(X, Xu, Xv, 4)
+    o = Oracle(g)
+    rng = np.random.default_rng(17)
+    taus = np.stack([np.cos(2 * g.x[:, 0]) + g.x[:, 1] * g.x[:, 2], rng.standard_normal(g.N)])
+    ref = np.stack([o.A1(t) for t in taus])
+    s = P.Surface(X, Xu, Xv, 4)
+    for prec, tol in ((64, 1e-9), (32, 2e-5)):
+        dt = torch.float64 if prec == 64 else torch.float32
+        x = torch.tensor(taus, dtype=dt, device="cuda")
+        out = s.apply_A1(x)
+        errs = [rel_l2(out[d].double().cpu().numpy(), ref[d]) for d in range(2)]
+        note(f"A1 {shape} N={g.N} prec={prec}: {errs[0]:.1e} (smooth), {errs[1]:.1e} (random)")
+        assert max(errs) < tol
+        for d in range(2):
+            assert torch.equal(out[d:d + 1], s.apply_A1(x[d:d + 1].contiguous()))
+    s.close()
+
+
+def _dense(torch, apply, N):
+    eye = torch.eye(N, dtype=torch.float64, device="cuda")
+    cols = []
+    for c0 in range(0, N, 512):
+        cols.append(apply(eye[c0:c0 + 512].contiguous()))
+    return torch.cat(cols).T.contiguous()   # row d of the batch is A e_d
+
+
+def test_numerical_second_kindness(torch_dev):
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.ops import gmres
+    from oracle.refelem import nodes
+    res = []
+    for nsub in (1, 2):
+        X, Xu, Xv = I.sphere_patches(nsub, nodes(4))
+        s = P.Surface(X, Xu, Xv, 4)
+        N = s.N
+        note(f"second kindness N={N}: dense A1, A3")
+        A1 = _dense(torch, s.apply_A1, N)
+        A3 = _dense(torch, s.apply_A3, N)
+        Sm = _dense(torch, s.apply_S, N)
+        s1 = torch.linalg.svdvals(A1).cpu().numpy()
+        s3 = torch.linalg.svdvals(A3).cpu().numpy()
+        x = X.reshape(-1, 3)
+        w = s.geometry()[0]
+        rng = np.random.default_rng(3)
+        f = sum(rng.uniform(-0.5, 0.5) * I.real_sph_harm(l, m, x) for l in range(1, 5) for m in range(-l, l + 1))
+        f = f - (w * f).sum() / w.sum()
+        A1h, A3h, Sh = A1.cpu().numpy(), A3.cpu().numpy(), Sm.cpu().numpy()
+        _, i1 = gmres(lambda v: A1h @ v, Sh @ f, tol=1e-14, max_iter=100)
+        _, i3 = gmres(lambda v: A3h @ v, f, tol=1e-14, max_iter=100)
+        note(f"second kindness N={N}: A1 sigma max {s1[0]:.3f} min {s1[-1]:.2e}; A3 sigma max {s3[0]:.3f} "
+             f"min {s3[-1]:.3f}; GMRES A1 {i1['iters']} its (resid {i1['rel_resid']:.1e}), "
+             f"A3 {i3['iters']} its (resid {i3['rel_resid']:.1e})")
+        res.append((s1[-1], s3[-1], i1["iters"], i3["iters"]))
+        s.close()
+    (a0, b0, n10, n30), (a1, b1, n11, n31) = res
+    assert a1 < a0 / 2 and abs(b1 - b0) < 0.05 * b0 and a1 < 1e-2 * b1
+    assert n30 <= 12 and n31 <= 12 and n10 == 100 and n11 == 100
