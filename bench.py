@@ -174,6 +174,13 @@ def main():
         for key, v in t.items():
             ph64[key] = ph64.get(key, 0.0) + v / 2
     print(f"[bench] fp64 apply {ms64:.3f} ms phases {ph64}", file=sys.stderr, flush=True)
+    # operator applies per GMRES iteration (t_mv): A3 and the non-second-kind A1
+    t_mv = {}
+    for name, fn in (("A3", s.apply_A3), ("A1", s.apply_A1)):
+        for tag, xx in (("fp32", x32), ("fp64", x64)):
+            fn(xx)
+            t_mv[f"{name}_{tag}_ms"] = timed(lambda: fn(xx), st64)
+    print(f"[bench] operator applies {t_mv}", file=sys.stderr, flush=True)
     # FP32 result against FP64 (the FP64 path matches the oracle to ~1e-10)
     o32 = s.apply_gradS(x32)
     o64 = s.apply_gradS(x64)
@@ -215,6 +222,7 @@ def main():
         "fp64_apply": {"value": N / (ms64 * 1e-3) / 1e6, "unit": "Mpts/s", "ms": ms64, "phases_ms": ph64},
         "fp32_vs_fp64_rel_l2": {"pot": e_pot, "grad": e_grad},
         "phases_ms_fp32": ph,
+        "operator_apply_ms": t_mv,
         "roofline": roof,
     }
     if not args.no_solve:
