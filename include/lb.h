@@ -8,7 +8,9 @@
  * second-kind formulation A3 = -I/4 + S'^2 - (S''+D'+2HS')S + WS^2
  * (Agarwal, O'Neil, Rachh, arXiv 2111.10743: Section 3 for the operators and
  * Lemma 1 for the mean-zero setting, Section 4 for the discretization and
- * eq. (nys-lcq2), Section 4.3 for the A3 apply, Section 6 for GMRES).
+ * eq. (nys-lcq2), Section 4.3 for the A3 apply, Section 6 for GMRES).  It
+ * also applies the non-second-kind A1 (Section 4.1) and computes Hodge
+ * decompositions of tangential fields (the harmonic-vector-field section).
  *
  * Conventions shared by every entry point:
  *  - Every function returns an lb_status.  0 is success, negative values are
