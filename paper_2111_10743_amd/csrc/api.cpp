@@ -197,6 +197,7 @@ struct Prec {
   std::vector<int64_t> lw_usrc;
   // tree parameters of the last build (the autotuner rebuilds with others)
   int build_leaf_src = 0, leaf_fmax = 64, leaf_split = 0;
+  int fork_late = 0, near_grid = 0;  // overlapped-apply schedule (see DevTree)
   double min_leaf_side = 0.0;
   bool direct = false;
 };
@@ -693,6 +694,8 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.side = overlap ? ctx->side_stream : nullptr;
   D.fork_ev = ctx->ev_fork;
   D.join_ev = ctx->ev_join;
+  D.fork_late = P.fork_late;
+  D.near_grid = P.near_grid;
   // P2M tables (the geometry is fixed, so the leaf harmonics of every
   // source can be kept): built on the device when both fit in a quarter of
   // the free memory and under P2M_TABLE_MAX bytes
@@ -961,6 +964,18 @@ static void set_leaf_shape(lb_ctx* ctx, Prec<T>& P, int fmax, int split) {
   HIPTRY(hipDeviceSynchronize());
 }
 
+// overlapped-apply schedule (fork point, near-field grid); graphs captured
+// with the old one are dropped
+template <typename T>
+static void set_schedule(lb_ctx* ctx, Prec<T>& P, int fork_late, int near_grid) {
+  HIPTRY(hipDeviceSynchronize());
+  ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
+  P.fork_late = fork_late;
+  P.near_grid = near_grid;
+  P.dt.fork_late = fork_late;
+  P.dt.near_grid = near_grid;
+}
+
 template <typename T>
 static double time_apply(lb_ctx* ctx, Prec<T>& P, int nd, const DBuf& in, DBuf& out, int reps, hipStream_t st) {
   const int64_t N = ctx->N;
@@ -1016,6 +1031,8 @@ static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, 
       r.trial_split[k] = sp;
       r.trial_depth[k] = depth;
       r.trial_ms[k] = ms;
+      r.trial_fork_late[k] = P.fork_late;
+      r.trial_near_grid[k] = P.near_grid;
     }
     if (ms < best) { best = ms; best_ls = ls; best_fm = fm; best_sp = sp; }
   };
@@ -1039,13 +1056,50 @@ static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, 
   const int fm0 = best_fm;
   for (int sp : {1, 2, 3}) trial(best_ls, fm0, sp, best_depth);
   set_leaf_shape<T>(ctx, P, best_fm, best_sp);
+  // schedule of the overlapped apply at the best shape: the near-field
+  // kernel forked after the strengths or after P2M, on every work item or
+  // on 4 or 6 blocks per compute unit (leaving wave slots to the far field)
+  int best_fl = P.fork_late, best_ng = P.near_grid;
+  if (ctx->side_stream && !P.direct) {
+    int dev = 0, ncu = 0;
+    HIPTRY(hipGetDevice(&dev));
+    HIPTRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int fl : {0, 1})
+      for (int ng : {0, 4 * ncu, 6 * ncu}) {
+        if (fl == P.fork_late && ng == P.near_grid) continue;  // timed above
+        set_schedule<T>(ctx, P, fl, ng);
+        const double ms = time_apply<T>(ctx, P, nd, in, out, reps, st);
+        if (r.n_trials < LB_TUNE_MAX_TRIALS) {
+          const int k = r.n_trials++;
+          r.trial_leaf_src[k] = best_ls;
+          r.trial_fmax[k] = best_fm;
+          r.trial_split[k] = best_sp;
+          r.trial_depth[k] = best_depth;
+          r.trial_ms[k] = ms;
+          r.trial_fork_late[k] = fl;
+          r.trial_near_grid[k] = ng;
+        }
+        if (ms < best) { best = ms; best_fl = fl; best_ng = ng; }
+      }
+    set_schedule<T>(ctx, P, best_fl, best_ng);
+  }
   r.leaf_src = best_ls;
   r.leaf_fmax = best_fm;
   r.leaf_split = best_sp;
+  r.fork_late = best_fl;
+  r.near_grid = best_ng;
   r.ms_best = best;
   r.depth = 0;
   for (const Octree& t : P.trees) r.depth = std::max(r.depth, t.depth);
   HIPTRY(hipStreamSynchronize(st));
+}
+
+template <typename T>
+static void set_tuning_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, const lb_tune_info& c) {
+  if (P.direct && c.leaf_src != P.build_leaf_src) fail(LB_EINVAL, "a direct context keeps its one-leaf tree");
+  if (c.leaf_src != P.build_leaf_src) rebuild_trees<T>(ctx, P, adj_built, z_built, c.leaf_src);
+  set_leaf_shape<T>(ctx, P, c.leaf_fmax, c.leaf_split);
+  set_schedule<T>(ctx, P, c.fork_late, c.near_grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -1791,6 +1845,23 @@ lb_status lb_autotune(lb_ctx* ctx, int prec, int nd, lb_tune_info* info, void* s
   else
     autotune_t<double>(ctx, ctx->f64, ctx->adj_built64, ctx->z_built64, nd, r, st);
   if (info) *info = r;
+  API_END
+}
+
+lb_status lb_set_tuning(lb_ctx* ctx, int prec, const lb_tune_info* config) {
+  API_BEGIN
+  check_apply(ctx, 1, prec);
+  if (!config) fail(LB_EINVAL, "null config");
+  const lb_tune_info& c = *config;
+  if (c.leaf_src < 16 || c.leaf_src > (1 << 20)) fail(LB_EINVAL, "leaf_src %d out of range 16..2^20", c.leaf_src);
+  if (c.leaf_fmax < 1 || c.leaf_fmax > 64 || (c.leaf_fmax & (c.leaf_fmax - 1)))
+    fail(LB_EINVAL, "leaf_fmax must be a power of two in 1..64");
+  if (c.leaf_split < 0 || c.leaf_split > 3) fail(LB_EINVAL, "leaf_split must be 0..3");
+  if ((c.fork_late != 0 && c.fork_late != 1) || c.near_grid < 0) fail(LB_EINVAL, "bad schedule");
+  if (prec == LB_PREC_FP32)
+    set_tuning_t<float>(ctx, ctx->f32, ctx->adj_built32, ctx->z_built32, c);
+  else
+    set_tuning_t<double>(ctx, ctx->f64, ctx->adj_built64, ctx->z_built64, c);
   API_END
 }
 

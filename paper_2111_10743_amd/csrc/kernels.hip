@@ -802,13 +802,13 @@ constexpr int leaf_waves() {
   return sizeof(T) == 4 ? (MODE == FMM_ADJ ? 1 : 6) : (MODE == FMM_A3B || MODE == FMM_ADJ3 ? 1 : 6);
 }
 
+// one work item (leaf, target range, lanes per target) of the leaf kernel
 template <typename T, int MODE, bool EXP_LDS, int PART>
-__global__ __launch_bounds__(LEAF_BS) __attribute__((amdgpu_waves_per_eu(leaf_waves<T, MODE>())))
-void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str,
-                                                  int64_t No, const T* __restrict__ Lc, T* __restrict__ D,
-                                                  T* __restrict__ out, int64_t N) {
+__device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T* __restrict__ str, int64_t No,
+                                          const T* __restrict__ Lc, T* __restrict__ D, T* __restrict__ out, int64_t N,
+                                          int widx) {
   extern __shared__ unsigned char smraw[];
-  const int4 wk = t.leaf_work[blockIdx.x];
+  const int4 wk = t.leaf_work[widx];
   const int b = wk.x;
   const int g = t.leaf_box[b];
   const int rhs = blockIdx.y;
@@ -833,7 +833,7 @@ void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str,
     sG = sL + nexp * L;
   } else {
     sL = const_cast<T*>(gL);
-    sG = D + ((int64_t)blockIdx.x * nrhs + rhs) * dstride;
+    sG = D + ((int64_t)widx * nrhs + rhs) * dstride;
   }
   T* sH = sG + nexp * 3 * Lg;
   // recurrence coefficients of the solid harmonics for L2P
@@ -1120,6 +1120,24 @@ void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str,
   }
 }
 
+// One work item per block; the near-field part of the overlapped apply
+// takes the items b, b + gridDim.x, ... (heaviest first), so that a grid
+// smaller than the item count leaves wave slots to the far-field kernels
+// running at the same time on the other stream.
+template <typename T, int MODE, bool EXP_LDS, int PART>
+__global__ __launch_bounds__(LEAF_BS) __attribute__((amdgpu_waves_per_eu(leaf_waves<T, MODE>())))
+void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str, int64_t No, const T* __restrict__ Lc,
+            T* __restrict__ D, T* __restrict__ out, int64_t N) {
+  if (PART == LEAF_NEAR) {
+    for (int w = blockIdx.x; w < t.n_leaf_work; w += gridDim.x) {
+      leaf_item<T, MODE, EXP_LDS, PART>(t, nrhs, str, No, Lc, D, out, N, w);
+      __syncthreads();  // the next item restages LDS
+    }
+  } else {
+    leaf_item<T, MODE, EXP_LDS, PART>(t, nrhs, str, No, Lc, D, out, N, blockIdx.x);
+  }
+}
+
 template <typename T>
 static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const T* str, const T* Lc, T* D, T* out,
                         int64_t N, int64_t No, hipStream_t st) {
@@ -1135,7 +1153,8 @@ static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const
   const bool lds = chunk + exps <= 40 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
   (void)L; (void)nexp;
-  dim3 grid(t.n_leaf_work, nrhs);
+  const int gx = part == LEAF_NEAR && t.near_grid > 0 ? std::min(t.n_leaf_work, t.near_grid) : t.n_leaf_work;
+  dim3 grid(gx, nrhs);
 #define LEAF_LAUNCH(MD, PT)                                                                                    \
   if (lds)                                                                                                     \
     hipLaunchKernelGGL((k_leaf<T, MD, true, PT>), grid, dim3(LEAF_BS), sml, st, t, nrhs, str, No, Lc, D, out, N); \
@@ -1177,15 +1196,16 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     return;
   }
   // With a side stream, the near-field sums (which need only the strengths)
-  // run there while this stream does P2M, M2M, M2L and L2L; the L2P kernel
-  // then adds the far field.  Timed applies stay serial.
+  // run there while this stream does P2M (unless fork_late), M2M, M2L and
+  // L2L; the L2P kernel then adds the far field.  Timed applies stay serial.
   const bool ovl = t.side && t.depth >= 2 && !tm->on;
-  if (ovl) {  // fork
+  auto fork = [&]() {
     (void)hipEventRecord(t.fork_ev, st);
     (void)hipStreamWaitEvent(t.side, t.fork_ev, 0);
     launch_leaf<T>(t, mode, LEAF_NEAR, nrhs, str, Lc, D, out, N, No, t.side);
     (void)hipEventRecord(t.join_ev, t.side);
-  }
+  };
+  if (ovl && !t.fork_late) fork();
   if (t.depth >= 2) {
     // source tile of P2M: harmonic tables of ts sources within 48 KiB of LDS
     int ts = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (2 * Lc_));
@@ -1209,6 +1229,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     else
       hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
     KCHECK();
+    if (ovl && t.fork_late) fork();
     tm->mark(PH_M2M, st);
     T* Y = (T*)t.Y;
     for (int l = t.depth - 1; l >= 2; --l) run_plan<T>(t.m2m_plan[l], t.m2m, L, ne, M, Y, M, st);

@@ -103,6 +103,10 @@ struct DevTree {
   // sums and the events that fork it from and join it to the caller's stream
   hipStream_t side;
   hipEvent_t fork_ev, join_ev;
+  // schedule of the overlapped apply: the near-field kernel forked after
+  // the strengths (fork_late = 0) or after P2M (1), with at most near_grid
+  // blocks (0: one per work item)
+  int fork_late, near_grid;
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities

@@ -37,7 +37,8 @@ LB_NO_OVERLAP = 64
 EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb_get_sizes", "lb_get_geometry",
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj",
-            "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_apply_A1", "lb_destroy", "lb_last_error")
+            "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_apply_A1", "lb_set_tuning", "lb_destroy",
+            "lb_last_error")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -75,7 +76,9 @@ class TuneInfo(ctypes.Structure):
                 ("ms_default", ctypes.c_double),
                 ("trial_leaf_src", ctypes.c_int32 * TUNE_MAX), ("trial_fmax", ctypes.c_int32 * TUNE_MAX),
                 ("trial_split", ctypes.c_int32 * TUNE_MAX), ("trial_depth", ctypes.c_int32 * TUNE_MAX),
-                ("trial_ms", ctypes.c_double * TUNE_MAX)]
+                ("trial_ms", ctypes.c_double * TUNE_MAX),
+                ("fork_late", ctypes.c_int32), ("near_grid", ctypes.c_int32),
+                ("trial_fork_late", ctypes.c_int32 * TUNE_MAX), ("trial_near_grid", ctypes.c_int32 * TUNE_MAX)]
 
 
 class LBError(RuntimeError):
@@ -119,6 +122,7 @@ def lib():
         L.lb_solve_adj.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_apply_A3_adj.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_A1.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_set_tuning.argtypes = [vp, ip, ctypes.POINTER(TuneInfo)]
         L.lb_surface_grad.argtypes = [vp, ip, vp, vp, vp]
         L.lb_surface_div.argtypes = [vp, ip, vp, ip, vp, vp]
         L.lb_hodge.argtypes = [vp, ip, vp, vp, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
@@ -361,10 +365,20 @@ class Surface:
         _check(lib().lb_autotune(self._ctx, int(prec), int(nd), ctypes.byref(info), _stream()))
         n = info.n_trials
         return {"leaf_src": info.leaf_src, "leaf_fmax": info.leaf_fmax, "leaf_split": info.leaf_split,
-                "depth": info.depth, "ms_best": info.ms_best, "ms_default": info.ms_default,
+                "depth": info.depth, "fork_late": info.fork_late, "near_grid": info.near_grid,
+                "ms_best": info.ms_best, "ms_default": info.ms_default,
                 "trials": [{"leaf_src": info.trial_leaf_src[i], "leaf_fmax": info.trial_fmax[i],
                             "leaf_split": info.trial_split[i], "depth": info.trial_depth[i],
+                            "fork_late": info.trial_fork_late[i], "near_grid": info.trial_near_grid[i],
                             "ms": info.trial_ms[i]} for i in range(n)]}
+
+    def set_tuning(self, prec, leaf_src, leaf_fmax, leaf_split=0, fork_late=0, near_grid=0):
+        """lb_set_tuning: apply a configuration (as returned by autotune)
+        without timing."""
+        c = TuneInfo()
+        c.leaf_src, c.leaf_fmax, c.leaf_split = int(leaf_src), int(leaf_fmax), int(leaf_split)
+        c.fork_late, c.near_grid = int(fork_late), int(near_grid)
+        _check(lib().lb_set_tuning(self._ctx, int(prec), ctypes.byref(c)))
 
     def apply_gradS_timed(self, sigma):
         """apply_gradS plus per-phase milliseconds (HIP events on the stream)."""

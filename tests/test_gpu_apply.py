@@ -264,6 +264,11 @@ def test_autotune_rebuilds_consistently(torch_dev):
                    q["leaf_split"] == t["leaf_split"] for q in t["trials"])
         assert {q["leaf_split"] for q in t["trials"]} == {0, 1, 2, 3}
         assert len({q["depth"] for q in t["trials"]}) >= 2
+        # the overlapped-apply schedules: fork point x near-field grid
+        assert {(q["fork_late"], q["near_grid"] > 0) for q in t["trials"]} == {(0, False), (1, False), (0, True),
+                                                                              (1, True)}
+        assert any(q["ms"] == t["ms_best"] and q["fork_late"] == t["fork_late"] and
+                   q["near_grid"] == t["near_grid"] for q in t["trials"])
         dt = torch.float64 if prec == 64 else torch.float32
         out = s.apply_gradS(torch.tensor(sig, dtype=dt, device="cuda"))
         torch.cuda.synchronize()
@@ -324,3 +329,34 @@ def test_overlap_matches_serial(torch_dev):
         assert ca == cb == 0 and e < 1e-9
     a.close()
     b.close()
+
+
+def test_overlap_schedules_bit_identical(torch_dev):
+    """lb_set_tuning with every schedule of the overlapped apply (near-field
+    kernel forked after the strengths or after P2M; one block per work item
+    or a grid of 300 / 1024 blocks taking the items in turn): the same sums
+    in the same order, so the gradient apply and A3 are bit-identical to the
+    default schedule.  Bad configurations are rejected."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.ellipsoid_patches(3, nodes(4), (1.0, 1.5, 2.0))
+    s = P.Surface(X, Xu, Xv, 4)
+    x = np.random.default_rng(83).standard_normal((2, s.N))
+    for prec, dt in ((32, torch.float32), (64, torch.float64)):
+        xs = torch.tensor(x, dtype=dt, device="cuda")
+        s.set_tuning(prec, 1024, 64, 0, 0, 0)
+        g0, a0 = s.apply_gradS(xs), s.apply_A3(xs)
+        for fl in (0, 1):
+            for ng in (0, 300, 1024):
+                s.set_tuning(prec, 1024, 64, 0, fl, ng)
+                g1, a1 = s.apply_gradS(xs), s.apply_A3(xs)
+                same = all(torch.equal(g0[k], g1[k]) for k in g0) and torch.equal(a0, a1)
+                note(f"schedule prec={prec} fork_late={fl} near_grid={ng}: bit-identical {same}")
+                assert same
+        for bad in ((1024, 48, 0, 0, 0), (1024, 64, 4, 0, 0), (1024, 64, 0, 2, 0), (1024, 64, 0, 0, -1),
+                    (8, 64, 0, 0, 0)):
+            with pytest.raises(P.LBError) as e:
+                s.set_tuning(prec, *bad)
+            assert e.value.code == P.LB_EINVAL
+    s.close()
