@@ -129,7 +129,7 @@ def main():
         for prec in (32, 64):
             t = s.autotune(prec, 1)
             tuning[f"fp{prec}"] = {k: t[k] for k in ("leaf_src", "leaf_fmax", "leaf_split", "depth", "fork_late",
-                                                      "near_grid", "ms_best", "ms_default")}
+                                                      "near_grid", "corr_early", "ms_best", "ms_default")}
             print(f"[bench] autotune fp{prec} {t}", file=sys.stderr, flush=True)
         print(f"[bench] sizes after tuning {s.sizes}", file=sys.stderr, flush=True)
     N = s.N

@@ -288,8 +288,9 @@ lb_status lb_apply_gradS_timed(lb_ctx *ctx, int nd, int prec, const void *sigma,
  * leaf_split in {1, 2, 3} (a leaf cut into up to that many blocks), then
  * the schedule of the overlapped apply (near-field kernel forked after the
  * strengths or after P2M; on every work item or on 4 or 6 blocks per
- * compute unit: fork_late, near_grid = 0 or the block count), and
- * keeps the fastest configuration.  Corrections and
+ * compute unit: fork_late, near_grid = 0 or the block count; the gradient
+ * apply's correction sums fused with the final combination or run first on
+ * the side stream: corr_early), and keeps the fastest configuration.  Corrections and
  * node data are kept; captured GMRES graphs and transposed trees are dropped
  * and rebuilt on next use.  Results are the same operator up to the FMM
  * truncation error.  A direct context (LB_DIRECT) tunes leaf_fmax only.
@@ -305,14 +306,16 @@ typedef struct {
   double trial_ms[LB_TUNE_MAX_TRIALS];
   int32_t fork_late, near_grid;       /* chosen schedule of the overlapped apply */
   int32_t trial_fork_late[LB_TUNE_MAX_TRIALS], trial_near_grid[LB_TUNE_MAX_TRIALS];
+  int32_t corr_early;                 /* gradient apply: correction sums first on the side stream */
+  int32_t trial_corr_early[LB_TUNE_MAX_TRIALS];
 } lb_tune_info;
 lb_status lb_autotune(lb_ctx *ctx, int prec, int nd, lb_tune_info *info, void *stream);
 
 /* Apply a configuration of one precision without timing (for instance one
  * that lb_autotune chose earlier for the same geometry): config->leaf_src
  * (16 .. 2^20; a direct context keeps its own), leaf_fmax (power of two,
- * 1..64), leaf_split (0..3), fork_late (0 or 1) and near_grid (>= 0); the
- * other fields are ignored.  Rebuilds the octrees when leaf_src differs;
+ * 1..64), leaf_split (0..3), fork_late (0 or 1), near_grid (>= 0) and
+ * corr_early (0 or 1); the other fields are ignored.  Rebuilds the octrees when leaf_src differs;
  * captured graphs and transposed trees are dropped as by lb_autotune.
  * Synchronizes the device.  Errors: LB_EINVAL. */
 lb_status lb_set_tuning(lb_ctx *ctx, int prec, const lb_tune_info *config);

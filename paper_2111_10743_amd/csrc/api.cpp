@@ -197,7 +197,8 @@ struct Prec {
   std::vector<int64_t> lw_usrc;
   // tree parameters of the last build (the autotuner rebuilds with others)
   int build_leaf_src = 0, leaf_fmax = 64, leaf_split = 0;
-  int fork_late = 0, near_grid = 0;  // overlapped-apply schedule (see DevTree)
+  int fork_late = 0, near_grid = 0, corr_early = 0;  // overlapped-apply schedule (see DevTree)
+  DBuf corr;  // early correction sums of the gradient apply [chunk][N][4]
   double min_leaf_side = 0.0;
   bool direct = false;
 };
@@ -696,6 +697,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   D.join_ev = ctx->ev_join;
   D.fork_late = P.fork_late;
   D.near_grid = P.near_grid;
+  D.corr_early = P.corr_early;
   // P2M tables (the geometry is fixed, so the leaf harmonics of every
   // source can be kept): built on the device when both fit in a quarter of
   // the free memory and under P2M_TABLE_MAX bytes
@@ -725,6 +727,7 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   P.Lc.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
   P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_work, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1)));
   P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
+  P.corr.alloc(sizeof(T) * (size_t)N * 4 * chunk);
   P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
   P.y2.alloc(sizeof(T) * (size_t)N * chunk);
   ctx->seg_scal.alloc(sizeof(double) * (size_t)chunk * ctx->n_surf + 8);
@@ -742,18 +745,34 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
                           hipStream_t st, PhaseTimer* tm = nullptr) {
   ensure_ws(ctx, P, CHUNK_GRAD);
   const int64_t N = ctx->N, No = ctx->No;
+  // corr_early: the correction sums need only sigma, so they run first on
+  // the side stream (ahead of the near field, which launch_fmm forks there
+  // and joins back), and a light final step adds the far sums
+  const bool early = P.corr_early && P.dt.side && P.dt.depth >= 2 && !tm;
   for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
     const int c = std::min(CHUNK_GRAD, nd - d0);
+    if (early) {
+      HIPTRY(hipEventRecord(P.dt.fork_ev, st));
+      HIPTRY(hipStreamWaitEvent(P.dt.side, P.dt.fork_ev, 0));
+      launch_corr_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
+                          sigma + (int64_t)d0 * N, dptr<T>(P.corr), P.dt.side);
+    }
     if (tm) tm->mark(PH_STR, st);
     launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
                         dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
     if (tm) tm->mark(PH_P2M, st);
     launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st, tm);
     if (tm) tm->mark(PH_COMB, st);
-    launch_combine_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
-                           sigma + (int64_t)d0 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
-                           pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
-                           dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr, st);
+    if (early)
+      launch_combine_grad_fin<T>(c, N, dptr<T>(P.fmm), dptr<T>(P.corr), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
+                                 pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
+                                 dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr,
+                                 st);
+    else
+      launch_combine_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
+                             sigma + (int64_t)d0 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
+                             pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
+                             dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr, st);
     if (tm) tm->mark(PH_N, st);
   }
 }
@@ -967,13 +986,15 @@ static void set_leaf_shape(lb_ctx* ctx, Prec<T>& P, int fmax, int split) {
 // overlapped-apply schedule (fork point, near-field grid); graphs captured
 // with the old one are dropped
 template <typename T>
-static void set_schedule(lb_ctx* ctx, Prec<T>& P, int fork_late, int near_grid) {
+static void set_schedule(lb_ctx* ctx, Prec<T>& P, int fork_late, int near_grid, int corr_early) {
   HIPTRY(hipDeviceSynchronize());
   ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
   P.fork_late = fork_late;
   P.near_grid = near_grid;
+  P.corr_early = corr_early;
   P.dt.fork_late = fork_late;
   P.dt.near_grid = near_grid;
+  P.dt.corr_early = corr_early;
 }
 
 template <typename T>
@@ -1033,6 +1054,7 @@ static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, 
       r.trial_ms[k] = ms;
       r.trial_fork_late[k] = P.fork_late;
       r.trial_near_grid[k] = P.near_grid;
+      r.trial_corr_early[k] = P.corr_early;
     }
     if (ms < best) { best = ms; best_ls = ls; best_fm = fm; best_sp = sp; }
   };
@@ -1059,35 +1081,39 @@ static void autotune_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, 
   // schedule of the overlapped apply at the best shape: the near-field
   // kernel forked after the strengths or after P2M, on every work item or
   // on 4 or 6 blocks per compute unit (leaving wave slots to the far field)
-  int best_fl = P.fork_late, best_ng = P.near_grid;
+  int best_fl = P.fork_late, best_ng = P.near_grid, best_ce = P.corr_early;
   if (ctx->side_stream && !P.direct) {
     int dev = 0, ncu = 0;
     HIPTRY(hipGetDevice(&dev));
     HIPTRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    for (int fl : {0, 1})
-      for (int ng : {0, 4 * ncu, 6 * ncu}) {
-        if (fl == P.fork_late && ng == P.near_grid) continue;  // timed above
-        set_schedule<T>(ctx, P, fl, ng);
-        const double ms = time_apply<T>(ctx, P, nd, in, out, reps, st);
-        if (r.n_trials < LB_TUNE_MAX_TRIALS) {
-          const int k = r.n_trials++;
-          r.trial_leaf_src[k] = best_ls;
-          r.trial_fmax[k] = best_fm;
-          r.trial_split[k] = best_sp;
-          r.trial_depth[k] = best_depth;
-          r.trial_ms[k] = ms;
-          r.trial_fork_late[k] = fl;
-          r.trial_near_grid[k] = ng;
+    const int fl0 = P.fork_late, ng0 = P.near_grid, ce0 = P.corr_early;
+    for (int ce : {0, 1})
+      for (int fl : {0, 1})
+        for (int ng : {0, 4 * ncu, 6 * ncu}) {
+          if (fl == fl0 && ng == ng0 && ce == ce0) continue;  // timed above
+          set_schedule<T>(ctx, P, fl, ng, ce);
+          const double ms = time_apply<T>(ctx, P, nd, in, out, reps, st);
+          if (r.n_trials < LB_TUNE_MAX_TRIALS) {
+            const int k = r.n_trials++;
+            r.trial_leaf_src[k] = best_ls;
+            r.trial_fmax[k] = best_fm;
+            r.trial_split[k] = best_sp;
+            r.trial_depth[k] = best_depth;
+            r.trial_ms[k] = ms;
+            r.trial_fork_late[k] = fl;
+            r.trial_near_grid[k] = ng;
+            r.trial_corr_early[k] = ce;
+          }
+          if (ms < best) { best = ms; best_fl = fl; best_ng = ng; best_ce = ce; }
         }
-        if (ms < best) { best = ms; best_fl = fl; best_ng = ng; }
-      }
-    set_schedule<T>(ctx, P, best_fl, best_ng);
+    set_schedule<T>(ctx, P, best_fl, best_ng, best_ce);
   }
   r.leaf_src = best_ls;
   r.leaf_fmax = best_fm;
   r.leaf_split = best_sp;
   r.fork_late = best_fl;
   r.near_grid = best_ng;
+  r.corr_early = best_ce;
   r.ms_best = best;
   r.depth = 0;
   for (const Octree& t : P.trees) r.depth = std::max(r.depth, t.depth);
@@ -1099,7 +1125,7 @@ static void set_tuning_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built
   if (P.direct && c.leaf_src != P.build_leaf_src) fail(LB_EINVAL, "a direct context keeps its one-leaf tree");
   if (c.leaf_src != P.build_leaf_src) rebuild_trees<T>(ctx, P, adj_built, z_built, c.leaf_src);
   set_leaf_shape<T>(ctx, P, c.leaf_fmax, c.leaf_split);
-  set_schedule<T>(ctx, P, c.fork_late, c.near_grid);
+  set_schedule<T>(ctx, P, c.fork_late, c.near_grid, c.corr_early);
 }
 
 // ---------------------------------------------------------------------------
@@ -1857,7 +1883,8 @@ lb_status lb_set_tuning(lb_ctx* ctx, int prec, const lb_tune_info* config) {
   if (c.leaf_fmax < 1 || c.leaf_fmax > 64 || (c.leaf_fmax & (c.leaf_fmax - 1)))
     fail(LB_EINVAL, "leaf_fmax must be a power of two in 1..64");
   if (c.leaf_split < 0 || c.leaf_split > 3) fail(LB_EINVAL, "leaf_split must be 0..3");
-  if ((c.fork_late != 0 && c.fork_late != 1) || c.near_grid < 0) fail(LB_EINVAL, "bad schedule");
+  if ((c.fork_late != 0 && c.fork_late != 1) || c.near_grid < 0 || (c.corr_early != 0 && c.corr_early != 1))
+    fail(LB_EINVAL, "bad schedule");
   if (prec == LB_PREC_FP32)
     set_tuning_t<float>(ctx, ctx->f32, ctx->adj_built32, ctx->z_built32, c);
   else

@@ -1315,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_combine_grad(int64_t N, int n_p, const 
                                                       const int* __restrict__ patch, const T* __restrict__ vals,
                                                       const T* __restrict__ sigma, const T* __restrict__ fmm,
                                                       const int* __restrict__ tgt_pos, const T* __restrict__ nrm,
-                                                      T* pot, T* grad, T* dSdn, T* surf) {
+                                                      T* pot, T* grad, T* dSdn, T* surf, T* corr) {
   typedef typename Vec4<T>::type T4;
   __shared__ int pat_s[4][64];
   const int lane = threadIdx.x & 63;
@@ -1340,6 +1340,14 @@ __global__ __launch_bounds__(256) void k_combine_grad(int64_t N, int n_p, const 
   for (int d = 0; d < ND; ++d)
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[d][k] = wave_sum(acc[d][k]);
+  if (corr) {  // corrections only: the final step adds the far sums later
+    if (lane == 0)
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) corr[((int64_t)d * N + row) * 4 + k] = acc[d][k];
+    return;
+  }
   if (lane == 0) {
     const int tp = tgt_pos[row];
     const T n0 = nrm[3 * row], n1 = nrm[3 * row + 1], n2 = nrm[3 * row + 2];
@@ -1377,6 +1385,32 @@ __global__ __launch_bounds__(256) void k_combine_grad(int64_t N, int n_p, const 
     default: hipLaunchKernelGGL((KERNEL<T, 4>), __VA_ARGS__); break;                         \
   }
 
+// the far sums (FMM outputs in tree order) plus the corrections computed
+// before by k_combine_grad into corr [d][row][4]: the same values as the
+// fused kernel (the same sums, added in the same order)
+template <typename T>
+__global__ void k_combine_grad_fin(int64_t N, int nd, const T* __restrict__ fmm, const T* __restrict__ corr,
+                                   const int* __restrict__ tgt_pos, const T* __restrict__ nrm, T* pot, T* grad,
+                                   T* dSdn, T* surf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nd * N) return;
+  const int64_t d = t / N, row = t - d * N;
+  const int tp = tgt_pos[row];
+  const T n0 = nrm[3 * row], n1 = nrm[3 * row + 1], n2 = nrm[3 * row + 2];
+  const T s = (T)INV4PI_D;
+  const T* f = fmm + d * 4 * N;
+  const T* c = corr + t * 4;
+  const T P = f[tp] * s + c[0];
+  const T gx = f[N + tp] * s + c[1];
+  const T gy = f[2 * N + tp] * s + c[2];
+  const T gz = f[3 * N + tp] * s + c[3];
+  const T dn = n0 * gx + n1 * gy + n2 * gz;
+  if (pot) pot[t] = P;
+  if (grad) { grad[3 * t] = gx; grad[3 * t + 1] = gy; grad[3 * t + 2] = gz; }
+  if (dSdn) dSdn[t] = dn;
+  if (surf) { surf[3 * t] = gx - n0 * dn; surf[3 * t + 1] = gy - n1 * dn; surf[3 * t + 2] = gz - n2 * dn; }
+}
+
 template <typename T>
 void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                          const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
@@ -1386,10 +1420,34 @@ void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, con
     ND_DISPATCH(k_combine_grad, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals4,
                 sigma + (int64_t)d0 * N, fmm + (int64_t)d0 * 4 * N, tgt_pos, nrm,
                 pot ? pot + (int64_t)d0 * N : nullptr, grad ? grad + (int64_t)d0 * 3 * N : nullptr,
-                dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr)
-    KCHECK();
+                dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr,
+                (T*)nullptr)
   }
+  KCHECK();
 }
+
+template <typename T>
+void launch_corr_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals4,
+                      const T* sigma, T* corr, hipStream_t st) {
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    ND_DISPATCH(k_combine_grad, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals4,
+                sigma + (int64_t)d0 * N, (const T*)nullptr, (const int*)nullptr, (const T*)nullptr, (T*)nullptr,
+                (T*)nullptr, (T*)nullptr, (T*)nullptr, corr + (int64_t)d0 * 4 * N)
+  }
+  KCHECK();
+}
+
+template <typename T>
+void launch_combine_grad_fin(int nd, int64_t N, const T* fmm, const T* corr, const int* tgt_pos, const T* nrm,
+                             T* pot, T* grad, T* dSdn, T* surf, hipStream_t st) {
+  const int64_t n = (int64_t)nd * N;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_combine_grad_fin<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, nd, fmm, corr,
+                     tgt_pos, nrm, pot, grad, dSdn, surf);
+  KCHECK();
+}
+
 
 // S only: pot = phi / (4 pi) + C_S sigma (vals3 column 0), FMM_POT output
 template <typename T, int ND>
@@ -2104,6 +2162,10 @@ void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, 
                                     int64_t, T*, hipStream_t);                                                    \
   template void launch_fmm<T>(const DevTree<T>&, int, int, const T*, T*, T*, T*, T*, int64_t, int64_t,       \
                               hipStream_t, PhaseTimer*);                                                  \
+  template void launch_corr_grad<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*, T*,        \
+                                    hipStream_t);                                                                 \
+  template void launch_combine_grad_fin<T>(int, int64_t, const T*, const T*, const int*, const T*, T*, T*, T*, T*, \
+                                           hipStream_t);                                                          \
   template void launch_combine_grad<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,        \
                                        const T*, const int*, const T*, T*, T*, T*, T*, hipStream_t);             \
   template void launch_combine_a3a<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,         \

@@ -105,8 +105,9 @@ struct DevTree {
   hipEvent_t fork_ev, join_ev;
   // schedule of the overlapped apply: the near-field kernel forked after
   // the strengths (fork_late = 0) or after P2M (1), with at most near_grid
-  // blocks (0: one per work item)
-  int fork_late, near_grid;
+  // blocks (0: one per work item); corr_early: the gradient apply's
+  // correction sums run on the side stream before the near field
+  int fork_late, near_grid, corr_early;
 };
 
 // strengths c[e][tree pos of m] = wo[m] * (P tau_e)[m] for ne densities
@@ -219,6 +220,14 @@ template <typename T>
 void launch_combine_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch,
                          const T* vals4, const T* sigma, const T* fmm, const int* tgt_pos,
                          const T* nrm, T* pot, T* grad, T* dSdn, T* surf, hipStream_t st);
+// the same in two steps: the corrections alone (corr [nd][N][4], no FMM
+// output needed, so they can run beside the FMM), then the final sums
+template <typename T>
+void launch_corr_grad(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals4,
+                      const T* sigma, T* corr, hipStream_t st);
+template <typename T>
+void launch_combine_grad_fin(int nd, int64_t N, const T* fmm, const T* corr, const int* tgt_pos, const T* nrm,
+                             T* pot, T* grad, T* dSdn, T* surf, hipStream_t st);
 // S only: pot = S sigma from the FMM_POT output and the S corrections
 template <typename T>
 void launch_combine_pot(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,

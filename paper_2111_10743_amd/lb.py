@@ -78,7 +78,8 @@ class TuneInfo(ctypes.Structure):
                 ("trial_split", ctypes.c_int32 * TUNE_MAX), ("trial_depth", ctypes.c_int32 * TUNE_MAX),
                 ("trial_ms", ctypes.c_double * TUNE_MAX),
                 ("fork_late", ctypes.c_int32), ("near_grid", ctypes.c_int32),
-                ("trial_fork_late", ctypes.c_int32 * TUNE_MAX), ("trial_near_grid", ctypes.c_int32 * TUNE_MAX)]
+                ("trial_fork_late", ctypes.c_int32 * TUNE_MAX), ("trial_near_grid", ctypes.c_int32 * TUNE_MAX),
+                ("corr_early", ctypes.c_int32), ("trial_corr_early", ctypes.c_int32 * TUNE_MAX)]
 
 
 class LBError(RuntimeError):
@@ -366,18 +367,20 @@ class Surface:
         n = info.n_trials
         return {"leaf_src": info.leaf_src, "leaf_fmax": info.leaf_fmax, "leaf_split": info.leaf_split,
                 "depth": info.depth, "fork_late": info.fork_late, "near_grid": info.near_grid,
+                "corr_early": info.corr_early,
                 "ms_best": info.ms_best, "ms_default": info.ms_default,
                 "trials": [{"leaf_src": info.trial_leaf_src[i], "leaf_fmax": info.trial_fmax[i],
                             "leaf_split": info.trial_split[i], "depth": info.trial_depth[i],
                             "fork_late": info.trial_fork_late[i], "near_grid": info.trial_near_grid[i],
+                            "corr_early": info.trial_corr_early[i],
                             "ms": info.trial_ms[i]} for i in range(n)]}
 
-    def set_tuning(self, prec, leaf_src, leaf_fmax, leaf_split=0, fork_late=0, near_grid=0):
+    def set_tuning(self, prec, leaf_src, leaf_fmax, leaf_split=0, fork_late=0, near_grid=0, corr_early=0):
         """lb_set_tuning: apply a configuration (as returned by autotune)
         without timing."""
         c = TuneInfo()
         c.leaf_src, c.leaf_fmax, c.leaf_split = int(leaf_src), int(leaf_fmax), int(leaf_split)
-        c.fork_late, c.near_grid = int(fork_late), int(near_grid)
+        c.fork_late, c.near_grid, c.corr_early = int(fork_late), int(near_grid), int(corr_early)
         _check(lib().lb_set_tuning(self._ctx, int(prec), ctypes.byref(c)))
 
     def apply_gradS_timed(self, sigma):

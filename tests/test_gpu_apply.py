@@ -334,7 +334,8 @@ def test_overlap_matches_serial(torch_dev):
 def test_overlap_schedules_bit_identical(torch_dev):
     """lb_set_tuning with every schedule of the overlapped apply (near-field
     kernel forked after the strengths or after P2M; one block per work item
-    or a grid of 300 / 1024 blocks taking the items in turn): the same sums
+    or a grid of 300 / 1024 blocks taking the items in turn; the gradient
+    apply's corrections fused or first on the side stream): the same sums
     in the same order, so the gradient apply and A3 are bit-identical to the
     default schedule.  Bad configurations are rejected."""
     torch = torch_dev
@@ -347,15 +348,16 @@ def test_overlap_schedules_bit_identical(torch_dev):
         xs = torch.tensor(x, dtype=dt, device="cuda")
         s.set_tuning(prec, 1024, 64, 0, 0, 0)
         g0, a0 = s.apply_gradS(xs), s.apply_A3(xs)
-        for fl in (0, 1):
-            for ng in (0, 300, 1024):
-                s.set_tuning(prec, 1024, 64, 0, fl, ng)
-                g1, a1 = s.apply_gradS(xs), s.apply_A3(xs)
-                same = all(torch.equal(g0[k], g1[k]) for k in g0) and torch.equal(a0, a1)
-                note(f"schedule prec={prec} fork_late={fl} near_grid={ng}: bit-identical {same}")
-                assert same
+        for ce in (0, 1):
+            for fl in (0, 1):
+                for ng in (0, 300, 1024):
+                    s.set_tuning(prec, 1024, 64, 0, fl, ng, ce)
+                    g1, a1 = s.apply_gradS(xs), s.apply_A3(xs)
+                    same = all(torch.equal(g0[k], g1[k]) for k in g0) and torch.equal(a0, a1)
+                    note(f"schedule prec={prec} corr_early={ce} fork_late={fl} near_grid={ng}: bit-identical {same}")
+                    assert same
         for bad in ((1024, 48, 0, 0, 0), (1024, 64, 4, 0, 0), (1024, 64, 0, 2, 0), (1024, 64, 0, 0, -1),
-                    (8, 64, 0, 0, 0)):
+                    (8, 64, 0, 0, 0), (1024, 64, 0, 0, 0, 2)):
             with pytest.raises(P.LBError) as e:
                 s.set_tuning(prec, *bad)
             assert e.value.code == P.LB_EINVAL
