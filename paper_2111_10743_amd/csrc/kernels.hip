@@ -791,8 +791,17 @@ __host__ __device__ inline size_t leaf_exp_bytes(int mode, int p) {
 }
 
 // PART: LEAF_BOTH (far and near, outputs written), LEAF_NEAR (near-field
-// sums only, outputs written), LEAF_FAR (L2P only, added to the outputs).
-enum { LEAF_BOTH = 0, LEAF_NEAR = 1, LEAF_FAR = 2 };
+// sums only, outputs written), LEAF_FAR (L2P only, added to the outputs);
+// in A3B, when its expansions do not fit in LDS, the far part in two
+// passes whose expansions do: LEAF_FAR1 (outputs 0-2: the gradient of
+// expansion 0, expansion 1 and its gradient) and LEAF_FAR2 (output 3: the
+// Hessian of expansion 1 and the gradient of expansion 2).
+enum { LEAF_BOTH = 0, LEAF_NEAR = 1, LEAF_FAR = 2, LEAF_FAR1 = 3, LEAF_FAR2 = 4 };
+template <typename T>
+__host__ __device__ inline size_t leaf_far_split_bytes(int part, int p) {
+  const size_t L = (size_t)(p + 1) * (p + 1), Lg = (size_t)p * p, Lh = (size_t)(p - 1) * (p - 1);
+  return sizeof(T) * (part == LEAF_FAR1 ? L + 6 * Lg : 6 * Lh + 3 * Lg);
+}
 
 // Waves per SIMD the compiler must leave room for (caps the registers):
 // 6 where that fits without spilling (measured: the FP32 gradient leaf
@@ -814,6 +823,7 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   const int rhs = blockIdx.y;
   const int p = t.p, L = t.L, Lg = p * p, Lh = (p - 1) * (p - 1);
   const int nexp = fmm_nexp(MODE), nstr = fmm_nstr(MODE), nout = fmm_nout(MODE);
+  constexpr bool FARONLY = PART == LEAF_FAR || PART == LEAF_FAR1 || PART == LEAF_FAR2;
   const bool far = PART != LEAF_NEAR && t.leaf_lvl[b] >= 2;
   const int tbeg = wk.y, tend = wk.z;
   const int F = wk.w;                            // lanes per target: a power of two <= 64
@@ -829,17 +839,53 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   T* sL;
   T* sG;
   if (EXP_LDS) {
-    sL = tile + (PART == LEAF_FAR ? 0 : REC * LEAF_CH);  // the far-only kernel stages no sources
+    sL = tile + (FARONLY ? 0 : REC * LEAF_CH);  // the far-only kernels stage no sources
     sG = sL + nexp * L;
   } else {
     sL = const_cast<T*>(gL);
     sG = D + ((int64_t)widx * nrhs + rhs) * dstride;
   }
   T* sH = sG + nexp * 3 * Lg;
+  // A3B: the expansion values the L2P sums read (expansion 1, gradients of
+  // 0, 1, 2, Hessian of 1); the split passes keep theirs in LDS
+  const T* xP = sL + L;
+  const T* xG1 = sG;
+  const T* xG2 = sG + 3 * Lg;
+  const T* xG3 = sG + 6 * Lg;
+  const T* xH = sH;
+  if (PART == LEAF_FAR1) {
+    xP = tile;
+    xG1 = tile + L;
+    xG2 = tile + L + 3 * Lg;
+  } else if (PART == LEAF_FAR2) {
+    xH = tile;
+    xG3 = tile + 6 * Lh;
+  }
   // recurrence coefficients of the solid harmonics for L2P
   __shared__ T rtab[RECTAB_N];
   const RecTab<T> rt(rtab);
-  if (far) {
+  if (far && MODE == FMM_A3B && PART == LEAF_FAR1) {
+    fill_rectab(rt, p);
+    T* lp = tile;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) lp[i] = gL[L + i];
+    derive3(gL, p, lp + L, lp + L + Lg, lp + L + 2 * Lg);
+    derive3(gL + L, p, lp + L + 3 * Lg, lp + L + 4 * Lg, lp + L + 5 * Lg);
+    __syncthreads();
+  } else if (far && MODE == FMM_A3B && PART == LEAF_FAR2) {
+    // gradient of expansion 1 and scratch in this block's slice of D, the
+    // Hessian and the gradient of expansion 2 in LDS
+    fill_rectab(rt, p);
+    T* dg = D + ((int64_t)widx * nrhs + rhs) * dstride;
+    T* tmp = dg + 3 * Lg;
+    T* lh = tile;
+    derive3(gL + L, p, dg, dg + Lg, dg + 2 * Lg);
+    derive3(gL + 2 * L, p, lh + 6 * Lh, lh + 6 * Lh + Lg, lh + 6 * Lh + 2 * Lg);
+    __syncthreads();
+    derive3(dg, p - 1, lh, lh + Lh, lh + 2 * Lh);                // xx, xy, xz
+    derive3(dg + Lg, p - 1, tmp, lh + 3 * Lh, lh + 4 * Lh);      // (yx), yy, yz
+    derive3(dg + 2 * Lg, p - 1, tmp + Lh, tmp + 2 * Lh, lh + 5 * Lh);  // (zx), (zy), zz
+    __syncthreads();
+  } else if (far) {
     fill_rectab(rt, p);
     if (EXP_LDS) {
       for (int i = threadIdx.x; i < nexp * L; i += blockDim.x) sL[i] = gL[i];
@@ -885,7 +931,7 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     upref[nU] = acc;
   }
   __syncthreads();
-  const int utot = PART == LEAF_FAR ? 0 : upref[nU];
+  const int utot = FARONLY ? 0 : upref[nU];
   for (int i0 = tbeg; i0 < tend; i0 += TPB) {
     const int i = i0 + slot;
     const bool act = i < tend;
@@ -947,21 +993,27 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
               ACC(g1[2], sG + 2 * Lg, ire, iim);
             }
           } else {
-            ACC(pot, sL + L, ire, iim);  // phi_2
-            if (n < p) {
-              ACC(g1[0], sG, ire, iim);
-              ACC(g1[1], sG + Lg, ire, iim);
-              ACC(g1[2], sG + 2 * Lg, ire, iim);
-              ACC(g2[0], sG + 3 * Lg, ire, iim);
-              ACC(g2[1], sG + 4 * Lg, ire, iim);
-              ACC(g2[2], sG + 5 * Lg, ire, iim);
-              ACC(g3[0], sG + 6 * Lg, ire, iim);
-              ACC(g3[1], sG + 7 * Lg, ire, iim);
-              ACC(g3[2], sG + 8 * Lg, ire, iim);
+            if (PART != LEAF_FAR2) {
+              ACC(pot, xP, ire, iim);  // phi_2
+              if (n < p) {
+                ACC(g1[0], xG1, ire, iim);
+                ACC(g1[1], xG1 + Lg, ire, iim);
+                ACC(g1[2], xG1 + 2 * Lg, ire, iim);
+                ACC(g2[0], xG2, ire, iim);
+                ACC(g2[1], xG2 + Lg, ire, iim);
+                ACC(g2[2], xG2 + 2 * Lg, ire, iim);
+              }
             }
-            if (n < p - 1) {
+            if (PART != LEAF_FAR1) {
+              if (n < p) {
+                ACC(g3[0], xG3, ire, iim);
+                ACC(g3[1], xG3 + Lg, ire, iim);
+                ACC(g3[2], xG3 + 2 * Lg, ire, iim);
+              }
+              if (n < p - 1) {
 #pragma unroll
-              for (int q = 0; q < 6; ++q) ACC(hs[q], sH + q * Lh, ire, iim);
+                for (int q = 0; q < 6; ++q) ACC(hs[q], xH + q * Lh, ire, iim);
+              }
             }
           }
 #undef ACC
@@ -1101,7 +1153,13 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     }
     if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
-      if (PART == LEAF_FAR) {  // after the near-field kernel (stream ordered)
+      if (PART == LEAF_FAR1) {
+        out[base + i] += (T)a0;
+        out[base + N + i] += (T)a1;
+        out[base + 2 * N + i] += (T)a2;
+      } else if (PART == LEAF_FAR2) {
+        out[base + 3 * N + i] += (T)a3;
+      } else if (PART == LEAF_FAR) {  // after the near-field kernel (stream ordered)
         out[base + i] += (T)a0;
         if (nout > 1) out[base + N + i] += (T)a1;
         if (nout > 2) {
@@ -1153,6 +1211,21 @@ static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const
   const bool lds = chunk + exps <= 40 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
   (void)L; (void)nexp;
+  // A3B whose expansions do not fit: the far part in two passes that keep
+  // theirs in LDS (within 64 KiB per block with the static tables)
+  const size_t stat = sizeof(T) * RECTAB_N + 512;
+  if (mode == FMM_A3B && !lds && part != LEAF_NEAR &&
+      leaf_far_split_bytes<T>(LEAF_FAR1, p) + stat <= 64 * 1024 &&
+      leaf_far_split_bytes<T>(LEAF_FAR2, p) + stat <= 64 * 1024) {
+    if (part == LEAF_BOTH) launch_leaf<T>(t, mode, LEAF_NEAR, nrhs, str, Lc, D, out, N, No, st);
+    const dim3 gf(t.n_leaf_work, nrhs);
+    hipLaunchKernelGGL((k_leaf<T, FMM_A3B, true, LEAF_FAR1>), gf, dim3(LEAF_BS), leaf_far_split_bytes<T>(LEAF_FAR1, p),
+                       st, t, nrhs, str, No, Lc, D, out, N);
+    hipLaunchKernelGGL((k_leaf<T, FMM_A3B, true, LEAF_FAR2>), gf, dim3(LEAF_BS), leaf_far_split_bytes<T>(LEAF_FAR2, p),
+                       st, t, nrhs, str, No, Lc, D, out, N);
+    KCHECK();
+    return;
+  }
   const int gx = part == LEAF_NEAR && t.near_grid > 0 ? std::min(t.n_leaf_work, t.near_grid) : t.n_leaf_work;
   dim3 grid(gx, nrhs);
 #define LEAF_LAUNCH(MD, PT)                                                                                    \
