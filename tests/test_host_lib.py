@@ -88,3 +88,26 @@ def test_host_corrections_match_oracle(case):
         assert np.array_equal(patch[ptr[i]:ptr[i + 1]], c.patch[c.ptr[r]:c.ptr[r + 1]])
         d = np.abs(vals[ptr[i]:ptr[i + 1]] - c.C[c.ptr[r]:c.ptr[r + 1]]).max()
         assert d < 2e-10 * scale, (i, d)
+
+
+def test_host_only_rejects_device_entry_points():
+    """A LB_HOST_ONLY context has no device state: every entry point that
+    needs it returns LB_EINVAL without touching the (bogus) pointers, and
+    lb_get_corrections still returns the host-rule corrections."""
+    import ctypes
+    lb = _lib()
+    uv, _ = lb.ref_nodes(3)
+    X, Xu, Xv = I.sphere_patches(0, uv)
+    s = lb.Surface(X, Xu, Xv, 3, host_only=True)
+    L = lb.lib()
+    p = ctypes.c_void_p(16)
+    info = lb.SolveInfo()
+    cfg = lb.TuneInfo()
+    cfg.leaf_src, cfg.leaf_fmax = 1024, 64
+    assert L.lb_apply_A1(s._ctx, 1, 64, p, p, None) == lb.LB_EINVAL
+    assert L.lb_surface_grad(s._ctx, 1, p, p, None) == lb.LB_EINVAL
+    assert L.lb_surface_div(s._ctx, 1, p, 0, p, None) == lb.LB_EINVAL
+    assert L.lb_hodge(s._ctx, 1, p, None, None, p, 1e-10, 0, ctypes.byref(info), None) == lb.LB_EINVAL
+    assert L.lb_set_tuning(s._ctx, 32, ctypes.byref(cfg)) == lb.LB_EINVAL
+    ptr, patch, vals = s.corrections()
+    assert ptr[-1] == len(patch) and np.isfinite(vals).all() and np.abs(vals).max() > 0
