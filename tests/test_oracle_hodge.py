@@ -141,3 +141,22 @@ def test_twisted_torus_charts():
     d = g.x - 0.2
     omega = (g.w * (d * g.n).sum(1) / np.linalg.norm(d, axis=1) ** 3).sum()
     assert abs(omega) < 1e-3 * 4 * np.pi
+
+
+def test_current_source_field():
+    """V = l x (x - x0)/|x - x0|^3 (the field of a current element): divergence
+    free away from x0 (div(l x r/r^3) = -l . curl(r/r^3) = 0; central
+    differences), and orthogonal to l and to x - x0."""
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-3, 3, (20, 3)) + np.array([4.0, 0.0, 0.0])
+    h = 1e-5
+    V = I.current_source_field(x)
+    J = np.zeros((20, 3, 3))   # J[:, i, j] = d V_i / d x_j
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        J[:, :, j] = (I.current_source_field(x + e) - I.current_source_field(x - e)) / (2 * h)
+    scale = np.abs(J).max()
+    assert np.abs(np.trace(J, axis1=1, axis2=2)).max() < 1e-7 * scale
+    assert np.abs(V @ np.array([0.0, 1.0, 1.0])).max() < 1e-14
+    assert np.abs((V * (x - 0.2)).sum(1)).max() < 1e-14
