@@ -35,3 +35,13 @@ def rel_l2(a, b, w=None):
     d = ((a - b) ** 2).reshape(len(w), -1).sum(1)
     r = (b ** 2).reshape(len(w), -1).sum(1)
     return float(np.sqrt((w * d).sum() / (w * r).sum()))
+
+
+def max_row(a, b):
+    """Largest row error relative to the largest row of b: max_i |a_i - b_i| / max_i |b_i|
+    (rows: the first axis; a row's norm is the Euclidean norm of its entries)."""
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    d = np.linalg.norm((a - b).reshape(len(b), -1), axis=1)
+    r = np.linalg.norm(b.reshape(len(b), -1), axis=1)
+    return float(d.max() / r.max())
