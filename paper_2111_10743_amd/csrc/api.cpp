@@ -1205,7 +1205,15 @@ static void graphed(lb_ctx* ctx, OpGraph& G, Body&& body, const void* in, const 
   body(st);
   if (!ctx->cap_stream) HIPTRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   HIPTRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-  body(ctx->cap_stream);
+  try {
+    body(ctx->cap_stream);
+  } catch (...) {
+    // close the capture so the stream stays usable, then report the failure
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(ctx->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
   HIPTRY(hipStreamEndCapture(ctx->cap_stream, &G.graph));
   HIPTRY(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
   G.in = in;

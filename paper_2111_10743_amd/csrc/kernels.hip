@@ -12,6 +12,7 @@
 // Every output element has one owning thread; no floating-point atomics, so
 // results are bitwise reproducible run to run.
 #include "kernels.hpp"
+#include "common.hpp"
 
 #include <type_traits>
 
@@ -20,13 +21,14 @@
 
 namespace lb {
 
-#define KCHECK()                                                                     \
-  do {                                                                               \
-    hipError_t e_ = hipGetLastError();                                               \
-    if (e_ != hipSuccess) {                                                          \
-      fprintf(stderr, "lb kernel launch failed: %s (%s:%d)\n", hipGetErrorString(e_), \
-              __FILE__, __LINE__);                                                   \
-    }                                                                                \
+// A failed launch (bad grid, LDS size or argument) throws, so the C entry
+// point returns LB_EHIP instead of reporting success with unwritten outputs
+// (hipGetLastError clears the error, so it must be acted on here).
+#define KCHECK()                                                                          \
+  do {                                                                                    \
+    hipError_t e_ = hipGetLastError();                                                    \
+    if (e_ != hipSuccess)                                                                 \
+      fail(LB_EHIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
   } while (0)
 
 template <typename T> __device__ __forceinline__ T dev_rsqrt(T x);
@@ -1264,10 +1266,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   if (!tm) tm = &dummy;
   const int p = t.p, L = t.L, Lc_ = (p + 1) * (p + 2) / 2;
   const int ne = nrhs * fmm_nexp(mode);
-  if (ne > 8) {
-    fprintf(stderr, "lb: launch_fmm called with %d expansions (max 8)\n", ne);
-    return;
-  }
+  if (ne > 8) fail(LB_EINVAL, "launch_fmm called with %d expansions (max 8)", ne);
   // With a side stream, the near-field sums (which need only the strengths)
   // run there while this stream does P2M (unless fork_late), M2M, M2L and
   // L2L; the L2P kernel then adds the far field.  Timed applies stay serial.
@@ -1284,10 +1283,8 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     int ts = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
-    if (t.p2m_H && (mode == FMM_ADJ || mode == FMM_ADJ3)) {
-      fprintf(stderr, "lb: P2M tables are not built for the transposed tree\n");
-      return;
-    }
+    if (t.p2m_H && (mode == FMM_ADJ || mode == FMM_ADJ3))
+      fail(LB_EINVAL, "P2M tables are not built for the transposed tree");
     if (mode == FMM_ADJ3) {
       int ts3 = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (4 * Lc_));
       ts3 = ts3 < 1 ? 1 : (ts3 > P2M_TSMAX ? P2M_TSMAX : ts3);
