@@ -1,0 +1,37 @@
+"""The stored oracle outputs (tests/golden/oracle_*.npz, written by
+make_oracle_golden.py) are the oracle's: the six layer columns on sampled
+rows of the ellipsoid recomputed here by a row-restricted oracle with its own
+corrections (the same arithmetic per row), and the stored solutions are mean
+zero in the smooth weights (Lemma 1) and their count of GMRES iterations is
+in the range the paper's Table 3 reports for A3 (a handful)."""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_oracle_golden as G  # noqa: E402
+from oracle.geometry import Geometry  # noqa: E402
+from oracle.ops import Oracle  # noqa: E402
+
+
+def test_golden_layer_rows_match_oracle():
+    X, Xu, Xv, k = G.surface("ellipsoid320_k6")
+    g = Geometry(X, Xu, Xv, k)
+    ref = np.load(os.path.join(HERE, "golden", "oracle_ellipsoid320_k6.npz"))
+    rows = np.arange(7, g.N, g.N // 24)
+    o = Oracle(g, rows)
+    L = o.layer(G.inputs("ellipsoid320_k6", X)["sigma"])
+    e = np.abs(L - ref["layer"][rows]).max() / np.abs(ref["layer"]).max()
+    assert e < 1e-13
+
+
+def test_golden_solutions_mean_zero():
+    for name in ("ellipsoid320_k6", "star320_k4"):
+        X, Xu, Xv, k = G.surface(name)
+        g = Geometry(X, Xu, Xv, k)
+        ref = np.load(os.path.join(HERE, "golden", f"oracle_{name}.npz"))
+        for u in ref["u"]:
+            assert abs((g.w * u).sum()) < 1e-4 * np.sqrt((g.w * u * u).sum() * g.w.sum())
+        assert np.all((ref["iters"] >= 3) & (ref["iters"] <= 15))
