@@ -16,7 +16,13 @@ third-party package that is not reproduced; this module computes A with
   from [0,1]^2 by the Duffy map (radial variable s, edge variable along the
   opposite edge); the edge variable is graded with the sinh map about the foot
   of the perpendicular, measured in the chart's metric at the node, so that
-  nodes close to an edge cost no more than central ones.  The gradient kernel is a Cauchy principal value with a ball of R^3
+  nodes close to an edge cost no more than central ones.  The displacement
+  from the node to a point of the ray is formed without cancellation: the
+  chart is a polynomial of degree k, so X(u0 + s e) - X(u0) =
+  s int_0^1 X'(u0 + t s e) e dt exactly, with X' the derivative of the
+  interpolated chart (degree k - 1) and ceil(k/2) Gauss points in t; the
+  difference of two nearly equal positions would carry a rounding error
+  proportional to |X| / |x - y| into the 1/r^2 kernels.  The gradient kernel is a Cauchy principal value with a ball of R^3
   as exclusion set: its 1/s part is subtracted and integrated analytically
   (Guiggiani-Gigante singularity subtraction), which adds f_{-1} ln|B| with
   B the chart's tangent along the ray.
@@ -42,7 +48,11 @@ KNAMES = ("S", "Gx", "Gy", "Gz", "Sp", "SDD")
 
 def kernels(x, n, y, nu):
     """Pointwise kernel values, shape (..., 5): S, Gx, Gy, Gz, SDD."""
-    d = x - y
+    return kernels_d(x - y, n, nu)
+
+
+def kernels_d(d, n, nu):
+    """The same from the displacement d = x - y."""
     r2 = (d * d).sum(-1)
     r = np.sqrt(r2)
     inv_r = 1.0 / r
@@ -90,6 +100,7 @@ def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
     n_p = geom.n_p
     sg, sw = gauss01(ns)
     tg, tw = gauss01(nt)
+    mg, mw = gauss01((geom.k + 1) // 2)      # exact for the degree k - 1 of X'
     verts = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
     out = np.zeros((len(targets), n_p, 6))
     for ti, i in enumerate(targets):
@@ -130,7 +141,15 @@ def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
             cr = np.cross(Xu, Xv)
             J = np.linalg.norm(cr, axis=-1)
             nu = cr / J[:, None]
-            kv = _full6(kernels(xi[None, :], ni[None, :], X, nu), ni[None, :])   # (nt*ns, 6)
+            # d = x_i - X(u0 + s e) = -s sum_j mw_j X'(u0 + mg_j s e) e,  e = dvec
+            um = (x0[None, None, None, :] + (sg[None, :, None] * mg[None, None, :])[..., None]
+                  * dvec[:, None, None, :])                                    # (nt, ns, m, 2)
+            Lm = basis(geom.k, um[..., 0].ravel(), um[..., 1].ravel()) @ re.Vinv
+            Lm = Lm.reshape(um.shape[:-1] + (n_p,))
+            Xd = (np.einsum('tsmb,bc->tsmc', Lm, geom.dXu[pch]) * dvec[:, None, None, 0:1]
+                  + np.einsum('tsmb,bc->tsmc', Lm, geom.dXv[pch]) * dvec[:, None, None, 1:2])
+            d = -(sg[None, :, None] * np.einsum('m,tsmc->tsc', mw, Xd)).reshape(-1, 3)
+            kv = _full6(kernels_d(d, ni[None, :], nu), ni[None, :])             # (nt*ns, 6)
             wgt = (jac_t[:, None] * sg[None, :] * wtau[:, None] * sw[None, :]).reshape(-1)
             f = kv * (J * wgt)[:, None]                                     # (M, 6)
             acc += L.T @ f

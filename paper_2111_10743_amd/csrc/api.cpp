@@ -1534,11 +1534,14 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
         pat.push_back(S.near_patch[b]);
       }
     }
-  std::vector<double> ru, rw, g, gw, tg, tw;
+  std::vector<double> ru, rw, g, gw, tg, tw, mg, mw;
   near_leaf_rule(qo.near_q, ru, rw);
   gauss_legendre01(qo.self_n, g, gw);
   gauss_legendre01(qo.self_nt, tg, tw);
+  gauss_legendre01((re.k + 1) / 2, mg, mw);
   DBuf dX, dn, ddXu, ddXv, dJ, dcX, dcXu, dcXv, dja, djb, djc, dVinv, duv, dg, dgw, dtg, dtw, dru, drw;
+  DBuf dcDu, dcDv, dmg, dmw;
+  upload(dcDu, S.cDu); upload(dcDv, S.cDv); upload(dmg, mg); upload(dmw, mw);
   DBuf drow, dblk, dpat, dsblk, dbrow, dnp, ds, dnu, dwo, drm2, dP, dA;
   upload(dX, S.X); upload(dn, S.nrm); upload(ddXu, S.dXu); upload(ddXv, S.dXv); upload(dJ, S.J);
   upload(dcX, S.cX); upload(dcXu, S.cXu); upload(dcXv, S.cXv);
@@ -1556,6 +1559,8 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
   sq.Vinv = dptr<double>(dVinv); sq.uv = dptr<double>(duv);
   sq.g = dptr<double>(dg); sq.gw = dptr<double>(dgw); sq.tg = dptr<double>(dtg); sq.tw = dptr<double>(dtw);
   sq.sblk = dptr<int64_t>(dsblk); sq.A = dptr<double>(dA);
+  sq.cDu = dptr<double>(dcDu); sq.cDv = dptr<double>(dcDv);
+  sq.mg = dptr<double>(dmg); sq.mw = dptr<double>(dmw); sq.nm = (int)mg.size();
   sq.N = S.N; sq.k = re.k; sq.ns = qo.self_n; sq.nt = qo.self_nt; sq.panel = qo.self_panel;
   HIPTRY(launch_self_quad(sq, nullptr));
   NearQuadArgs nq;

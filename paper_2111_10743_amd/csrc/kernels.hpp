@@ -313,6 +313,14 @@ struct SelfQuadArgs {
   const double* tw = nullptr;
   const int64_t* sblk = nullptr;  // [N]
   double* A = nullptr;          // [nnz_blocks][n_p][6]
+  // the displacement x_i - X(u0 + s e) as -s sum_j mw_j X'(u0 + mg_j s e) e:
+  // modal coefficients of the derivatives of the interpolated X
+  // [NP][n_p][3] and an nm-point Gauss rule on [0, 1] (nm = ceil(k / 2))
+  const double* cDu = nullptr;
+  const double* cDv = nullptr;
+  const double* mg = nullptr;
+  const double* mw = nullptr;
+  int nm = 0;
   int64_t N = 0;
   int k = 0, ns = 0, nt = 0;
   double panel = 2.0;

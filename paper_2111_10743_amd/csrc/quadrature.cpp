@@ -17,6 +17,12 @@
 //    integral from the ball radius to 1 is added analytically; the ln(eps)
 //    parts cancel over the full angle, leaving f_{-1} ln|B| with B the tangent
 //    of the interpolated chart along the ray (Guiggiani-Gigante subtraction).
+//    The displacement from the node to a point s e of a ray is formed without
+//    cancellation: the interpolated chart is a polynomial of degree k, so
+//    X(u0 + s e) - X(u0) = s int_0^1 X'(u0 + t s e) e dt exactly with
+//    ceil(k/2) Gauss points in t (X' the derivative of the interpolant, of
+//    degree k - 1); subtracting two nearly equal positions instead would put
+//    a rounding error of order |X| eps / |x - y| into the 1/r^2 kernels.
 //  * other near patches: recursive 4-way subdivision of T0 with a conical
 //    Gauss rule per leaf, leaf accepted when its distance to the target is at
 //    least near_adm times its diameter.
@@ -33,9 +39,8 @@ namespace lb {
 static const double INV4PI = 0.25 / M_PI;
 
 // S, Gx, Gy, Gz, S', S''+D' at target x (normal n) from source y (normal nu).
-static inline void kernel6(const double* x, const double* n, const double* y, const double* nu,
-                           double* k) {
-  double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+static inline void kernel6_d(const double* d, const double* n, const double* nu, double* k) {
+  const double d0 = d[0], d1 = d[1], d2 = d[2];
   double r2 = d0 * d0 + d1 * d1 + d2 * d2;
   double ir = 1.0 / std::sqrt(r2);
   double ir3 = ir / r2;
@@ -52,18 +57,27 @@ static inline void kernel6(const double* x, const double* n, const double* y, co
   k[5] = (3.0 * nd * md * ir5 - nm * ir3) * INV4PI;
 }
 
-// Accumulate weight * kernel(x, chart(p, u, v)) * psi_c(u, v) into mom[c][6].
+static inline void kernel6(const double* x, const double* n, const double* y, const double* nu, double* k) {
+  const double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+  kernel6_d(d, n, nu, k);
+}
+
+// Accumulate weight * kernel(x, chart(p, u, v)) * psi_c(u, v) into mom[c][6];
+// dsp (nullable) is the displacement x - chart(p, u, v) when the caller has
+// formed it without cancellation (self rule).
 static inline void accum_point(const Surface& S, int p, double u, double v, double wgt,
-                               const double* x, const double* n, double* mom, double* kv_out) {
+                               const double* x, const double* n, double* mom, double* kv_out,
+                               const double* dsp = nullptr) {
   double K[64], y[3], yu[3], yv[3], c[3];
   S.chart(p, u, v, K, y, yu, yv);
+  const double dxy[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
   c[0] = yu[1] * yv[2] - yu[2] * yv[1];
   c[1] = yu[2] * yv[0] - yu[0] * yv[2];
   c[2] = yu[0] * yv[1] - yu[1] * yv[0];
   double J = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
   double nu[3] = {c[0] / J, c[1] / J, c[2] / J};
   double kv[6];
-  kernel6(x, n, y, nu, kv);
+  kernel6_d(dsp ? dsp : dxy, n, nu, kv);
   double f = wgt * J;
   for (int t = 0; t < 6; ++t) kv[t] *= f;
   for (int m = 0; m < S.n_p; ++m)
@@ -96,6 +110,11 @@ static void self_integral(const Surface& S, int64_t i, const QuadOpts& qo,
   const double* bv = &S.dXv[3 * i];
   const double Ji = S.J[i];
   const int ns = qo.self_n, nt = (int)tg.size();
+  // Gauss rule in the ray variable of the displacement integral (exact for
+  // the degree k - 1 of the chart's derivative)
+  std::vector<double> mg, mw;
+  gauss_legendre01((S.re->k + 1) / 2, mg, mw);
+  const int nm = (int)mg.size();
   double mom[6 * 64];
   std::memset(mom, 0, sizeof(double) * 6 * n_p);
   double pv[4] = {0, 0, 0, 0};
@@ -129,7 +148,14 @@ static void self_integral(const Surface& S, int64_t i, const QuadOpts& qo,
         const double jac = c0 * h * ch / eG;
         for (int js = 0; js < ns; ++js) {
           const double sv = g[js];
-          accum_point(S, p, u0 + sv * du, v0 + sv * dv, wt * gw[js] * jac * sv, x, n, mom, nullptr);
+          // x - X(u0 + s e) = -s sum_j mw_j X'(u0 + mg_j s e) e without cancellation
+          double dsp[3] = {0, 0, 0}, K[64], pu[3], pv3[3];
+          for (int jm = 0; jm < nm; ++jm) {
+            S.dchart(p, u0 + mg[jm] * sv * du, v0 + mg[jm] * sv * dv, K, pu, pv3);
+            for (int c = 0; c < 3; ++c) dsp[c] += mw[jm] * (pu[c] * du + pv3[c] * dv);
+          }
+          for (int c = 0; c < 3; ++c) dsp[c] *= -sv;
+          accum_point(S, p, u0 + sv * du, v0 + sv * dv, wt * gw[js] * jac * sv, x, n, mom, nullptr, dsp);
         }
         // principal-value term of the gradient kernels at column a
         double B[3] = {du * bu[0] + dv * bv[0], du * bu[1] + dv * bv[1], du * bu[2] + dv * bv[2]};

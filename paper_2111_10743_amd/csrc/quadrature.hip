@@ -8,7 +8,10 @@
 //    Duffy triangles; along each edge the sinh-graded arclength variable in
 //    the metric of the chart at the node, panels of self_panel, nt x ns
 //    Gauss points; the principal value of the gradient kernels by
-//    subtracting the 1/s part and adding f_{-1} ln|B| (Guiggiani-Gigante).
+//    subtracting the 1/s part and adding f_{-1} ln|B| (Guiggiani-Gigante);
+//    the displacement from the node to a point of a ray as the integral of
+//    the chart's derivative along the ray (no cancellation of nearly equal
+//    positions).
 //  * other near patches: recursive 4-way subdivision of the reference
 //    triangle, a triangle accepted as a leaf when its distance to the target
 //    is at least `adm` times its diameter (or at depth max_depth), and the
@@ -109,10 +112,12 @@ __device__ inline void chart_pos(const QuadLds<KO>& L, double u, double v, doubl
 // One batch of 64 quadrature points (lane l: point (u, v) with weight wgt
 // when `active`): acc[j] += sum_points wgt J psi_c kernel_t for the lane's
 // moments (c, t).  Every lane of the wavefront calls it (two barriers).
+// dsp (nullable): the displacement x - X(u, v) of the lane's point when the
+// caller formed it without cancellation (self rule).
 template <int KO>
 __device__ inline void quad_batch(QuadLds<KO>& L, int lane, bool active, double u, double v, double wgt,
                                   double x0, double x1, double x2, double n0, double n1, double n2,
-                                  double* acc) {
+                                  double* acc, const double* dsp = nullptr) {
   constexpr int NPP = QuadLds<KO>::NPP;
   double K[NPP];
   double kv[6] = {0, 0, 0, 0, 0, 0};
@@ -133,7 +138,7 @@ __device__ inline void quad_batch(QuadLds<KO>& L, int lane, bool active, double 
     const double c2 = yu[0] * yv[1] - yu[1] * yv[0];
     const double J = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
     const double nu0 = c0 / J, nu1 = c1 / J, nu2 = c2 / J;
-    const double d0 = x0 - y[0], d1 = x1 - y[1], d2 = x2 - y[2];
+    const double d0 = dsp ? dsp[0] : x0 - y[0], d1 = dsp ? dsp[1] : x1 - y[1], d2 = dsp ? dsp[2] : x2 - y[2];
     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
     const double ir = 1.0 / sqrt(r2);
     const double ir3 = ir / r2;
@@ -283,6 +288,8 @@ __global__ __launch_bounds__(64) void k_self_quad(SelfQuadArgs q) {
   __shared__ QuadLds<KO> L;
   __shared__ double spv[64][4];
   __shared__ double spvs[4];
+  __shared__ double sdc[2][NPP * 3];  // modal coefficients of the chart's derivatives
+  __shared__ double smr[2][4];        // Gauss rule of the displacement integral
   const int lane = threadIdx.x;
   const int64_t i = blockIdx.x;
   if (i >= q.N) return;
@@ -291,6 +298,15 @@ __global__ __launch_bounds__(64) void k_self_quad(SelfQuadArgs q) {
   const int64_t p = i / NPP;
   const int a = (int)(i % NPP);
   load_patch<KO>(L, q.cX, q.cXu, q.cXv, q.ja, q.jb, q.jc, p, lane);
+  for (int e = lane; e < 3 * NPP; e += 64) {
+    sdc[0][e] = q.cDu[p * NPP * 3 + e];
+    sdc[1][e] = q.cDv[p * NPP * 3 + e];
+  }
+  const int nm = q.nm;
+  if (lane < nm) {
+    smr[0][lane] = q.mg[lane];
+    smr[1][lane] = q.mw[lane];
+  }
   __syncthreads();
   const double u0 = q.uv[2 * a], v0 = q.uv[2 * a + 1];
   const double x0 = q.X[3 * i], x1 = q.X[3 * i + 1], x2 = q.X[3 * i + 2];
@@ -331,6 +347,7 @@ __global__ __launch_bounds__(64) void k_self_quad(SelfQuadArgs q) {
       const int qq = q0 + lane;
       const bool act = qq < npts;
       double u = 0, v = 0, wgt = 0;
+      double dsp[3] = {0, 0, 0};
       if (act) {
         const int js = qq % ns, jt = (qq / ns) % nt, ip = qq / (ns * nt);
         const double t = ta + dl * (ip + q.tg[jt]);
@@ -342,6 +359,25 @@ __global__ __launch_bounds__(64) void k_self_quad(SelfQuadArgs q) {
         u = u0 + s * du;
         v = v0 + s * dv;
         wgt = wt * q.gw[js] * jac * s;
+        // x_i - X(u, v) = -s sum_j mw_j X'(u0 + mg_j s e) e, e = (du, dv)
+        for (int jm = 0; jm < nm; ++jm) {
+          double K[NPP];
+          const double sj = smr[0][jm] * s;
+          nq_basis<KO>(L.sj[0], L.sj[1], L.sj[2], u0 + sj * du, v0 + sj * dv, K);
+          double t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+          for (int m = 0; m < NPP; ++m) {
+            t0 += K[m] * (sdc[0][3 * m] * du + sdc[1][3 * m] * dv);
+            t1 += K[m] * (sdc[0][3 * m + 1] * du + sdc[1][3 * m + 1] * dv);
+            t2 += K[m] * (sdc[0][3 * m + 2] * du + sdc[1][3 * m + 2] * dv);
+          }
+          dsp[0] += smr[1][jm] * t0;
+          dsp[1] += smr[1][jm] * t1;
+          dsp[2] += smr[1][jm] * t2;
+        }
+        dsp[0] *= -s;
+        dsp[1] *= -s;
+        dsp[2] *= -s;
         if (js == 0) {
           // principal-value term of the gradient kernels at column a
           const double B0 = du * bu0 + dv * bv0, B1 = du * bu1 + dv * bv1, B2 = du * bu2 + dv * bv2;
@@ -355,7 +391,7 @@ __global__ __launch_bounds__(64) void k_self_quad(SelfQuadArgs q) {
           pv[3] += wt * (fm0 * n0 + fm1 * n1 + fm2 * n2) * lg;
         }
       }
-      quad_batch<KO>(L, lane, act, u, v, wgt, x0, x1, x2, n0, n1, n2, acc);
+      quad_batch<KO>(L, lane, act, u, v, wgt, x0, x1, x2, n0, n1, n2, acc, dsp);
     }
   }
 #pragma unroll
@@ -483,7 +519,8 @@ hipError_t launch_near_quad(const NearQuadArgs& q, hipStream_t st) {
 
 hipError_t launch_self_quad(const SelfQuadArgs& q, hipStream_t st) {
   if (q.N <= 0) return hipSuccess;
-  if (q.N > 0x7fffffff || q.ns < 1 || q.nt < 1 || !(q.panel > 0)) return hipErrorInvalidValue;
+  if (q.N > 0x7fffffff || q.ns < 1 || q.nt < 1 || !(q.panel > 0) || q.nm < 1 || q.nm > 4 || !q.cDu || !q.cDv)
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)q.N), blk(64);
   switch (q.k) {
     case 1: hipLaunchKernelGGL(k_self_quad<1>, grid, blk, 0, st, q); break;

@@ -43,6 +43,20 @@ void Surface::chart(int p, double u, double v, double* K, double* x, double* xu,
   xv[0] = v0; xv[1] = v1; xv[2] = v2;
 }
 
+void Surface::dchart(int p, double u, double v, double* K, double* du, double* dv) const {
+  re->basis(u, v, K);
+  const double* a = &cDu[(size_t)p * n_p * 3];
+  const double* b = &cDv[(size_t)p * n_p * 3];
+  double u0 = 0, u1 = 0, u2 = 0, v0 = 0, v1 = 0, v2 = 0;
+  for (int m = 0; m < n_p; ++m) {
+    const double k = K[m];
+    u0 += k * a[3 * m]; u1 += k * a[3 * m + 1]; u2 += k * a[3 * m + 2];
+    v0 += k * b[3 * m]; v1 += k * b[3 * m + 1]; v2 += k * b[3 * m + 2];
+  }
+  du[0] = u0; du[1] = u1; du[2] = u2;
+  dv[0] = v0; dv[1] = v1; dv[2] = v2;
+}
+
 void Surface::build(const RefElem& re_, int NP_, const double* X_, const double* Xu_,
                     const double* Xv_, double eta_) {
   re = &re_;
@@ -61,6 +75,7 @@ void Surface::build(const RefElem& re_, int NP_, const double* X_, const double*
   nrm.resize(3 * N); w.resize(N); J.resize(N); H.resize(N);
   dXu.resize(3 * N); dXv.resize(3 * N);
   cX.resize(3 * N); cXu.resize(3 * N); cXv.resize(3 * N);
+  cDu.resize(3 * N); cDv.resize(3 * N);
   s.resize(3 * No); nu.resize(3 * No); wo.resize(No);
   cen.resize(3 * NP); R.resize(NP);
   const std::vector<double>& Du = re->Du;
@@ -108,16 +123,20 @@ void Surface::build(const RefElem& re_, int NP_, const double* X_, const double*
     // modal coefficients: c[m] = sum_b Vinv[m][b] X[b]
     for (int m = 0; m < n_p; ++m)
       for (int d = 0; d < 3; ++d) {
-        double sx = 0, su = 0, sv = 0;
+        double sx = 0, su = 0, sv = 0, sdu = 0, sdv = 0;
         for (int b = 0; b < n_p; ++b) {
           double vi = re->Vinv[m * n_p + b];
           sx += vi * X[3 * (o + b) + d];
           su += vi * Xu[3 * (o + b) + d];
           sv += vi * Xv[3 * (o + b) + d];
+          sdu += vi * dXu[3 * (o + b) + d];
+          sdv += vi * dXv[3 * (o + b) + d];
         }
         cX[3 * (o + m) + d] = sx;
         cXu[3 * (o + m) + d] = su;
         cXv[3 * (o + m) + d] = sv;
+        cDu[3 * (o + m) + d] = sdu;
+        cDv[3 * (o + m) + d] = sdv;
       }
     // oversampled points
     const int64_t oo = (int64_t)p * n_o;

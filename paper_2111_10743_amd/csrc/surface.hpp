@@ -29,6 +29,9 @@ struct Surface {
   std::vector<double> dXu, dXv;           // derivative of the interpolated X at nodes [N][3]
   // modal coefficients of X, Xu, Xv per patch: [NP][n_p][3]
   std::vector<double> cX, cXu, cXv;
+  // modal coefficients of the derivatives of the interpolated X (the
+  // polynomials dXu, dXv of degree k - 1): [NP][n_p][3]
+  std::vector<double> cDu, cDv;
   // oversampled far rule
   std::vector<double> s, nu, wo;          // [No][3], [No][3], [No]
   // patches
@@ -46,6 +49,9 @@ struct Surface {
   // Chart at param (u, v) of patch p: position, interpolated X_u, X_v and the
   // basis values K (modal), n_p of them.
   void chart(int p, double u, double v, double* K, double* x, double* xu, double* xv) const;
+  // Derivatives of the interpolated X (not the interpolated X_u, X_v) at
+  // param (u, v) of patch p; K is basis scratch of n_p values.
+  void dchart(int p, double u, double v, double* K, double* du, double* dv) const;
 };
 
 // Accurate near integrals A (eq. nys-lcq2) for every (target, near patch)

@@ -12,15 +12,18 @@ split exists for, every point of a far patch at distance >= (eta - 1) R_l,
 is checked by brute force over the dense samples.
 
 Self rule (Duffy triangles, sinh-graded edge variable, principal value of
-the gradient): the default 16 radial x 12 edge points against 24 x 20.  The
-S column agrees to 3e-13 (sphere, order 4) .. 3e-11 (ellipsoid, order 6) of
-its largest entry and the gradient columns to 1e-11 .. 5e-11; S' and S''+D'
-only to 2e-10 .. 1.6e-9, because on the interpolated
-chart the target's given normal is not exactly orthogonal to the chart's
-tangents, so n . (x - y) / r^3 keeps a 1/r^2 part whose coefficient is the
-chart's interpolation error (odd in direction, a principal value that Gauss
-rules resolve only algebraically).  That floor is far below the
-discretization error of these surfaces (1e-5 .. 1e-7).
+the gradient, the displacement from the node formed as the integral of the
+chart's derivative along the ray): the default 16 radial x 12 edge points
+against 24 x 20.  The S column agrees to 3e-13 (sphere, order 4) .. 3e-11
+(ellipsoid, order 6) of its largest entry, the gradient and S' columns to
+5e-12 .. 6e-11, S''+D' to 5e-11 .. 1e-9: on the interpolated chart the
+target's given normal is not exactly orthogonal to the chart's tangents, so
+the S''+D' kernel keeps a 1/r^2 part whose coefficient is the chart's
+interpolation error (odd in direction, a principal value that Gauss rules
+resolve only algebraically), far below the discretization error of these
+surfaces (1e-5 .. 1e-7).  Translating the surface leaves the self integrals
+unchanged up to rounding (translation by 10 moves them by < 1e-11 of each
+column's largest entry): no cancellation of nearly equal positions.
 """
 import numpy as np
 import pytest
@@ -120,4 +123,21 @@ def test_self_rule_converged(name):
     if name == "flat":
         assert np.all(d[4:] < 1e-11)
     else:
-        assert np.all(d[4:] < 3e-9 * sc[4:])
+        assert d[4] < 2e-10 * sc[4]
+        assert d[5] < 3e-9 * sc[5]
+
+
+@pytest.mark.parametrize("name", ["sphere", "ellipsoid"])
+def test_self_rule_translation_invariant(name):
+    """The self integrals of a surface and of its translate by (10, 10, 10)
+    agree to rounding: the displacement from the node to a quadrature point
+    is not the difference of two positions of size |X|."""
+    chart, k = _surface(name)
+    X, Xu, Xv = chart(nodes(k))
+    t = np.arange(0, 240, 7)
+    a = self_integrals(Geometry(X, Xu, Xv, k), t)
+    b = self_integrals(Geometry(X + 10.0, Xu, Xv, k), t)
+    sc = np.abs(a).max(axis=(0, 1))
+    d = np.abs(a - b).max(axis=(0, 1)) / sc
+    print(name, " ".join(f"{x:.1e}" for x in d))
+    assert np.all(d[:5] < 2e-11) and d[5] < 1e-10
