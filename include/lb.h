@@ -226,6 +226,25 @@ lb_status lb_apply_gradS(lb_ctx *ctx, int nd, int prec, const void *sigma,
                          void *pot, void *grad, void *dSdn, void *surf_grad,
                          void *stream);
 
+/* lb_apply_gradS for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as lb_apply_gradS (bit for bit), but
+ * the per-call workspace (strengths, multipole and local expansions, the
+ * leaf kernel's derived expansions, FMM outputs, early correction sums) lives
+ * in a static device array of 128 MiB that each device holds from library
+ * load until the process ends; the call makes no hipMalloc or hipFree.  Every
+ * call on a device shares that device's array, so calls that overlap in time
+ * on one device (two streams, two contexts, two threads) race and must be
+ * serialized by the caller; nothing in it needs to start at zero.  Limit:
+ * the workspace of min(nd, 8) densities must fit in the 128 MiB (the FP32
+ * apply of one density on a 5120-patch order-6 surface does); larger
+ * requests return LB_ENOMEM without launching anything.  The context must
+ * come from lb_setup / lb_setup_batch on the current device (which looked
+ * up the array's device address). */
+lb_status lb_apply_gradS_noalloc(lb_ctx *ctx, int nd, int prec, const void *sigma,
+                                 void *pot, void *grad, void *dSdn, void *surf_grad,
+                                 void *stream);
+
 /* Adjoint of lb_apply_gradS with respect to the density: the exact transpose
  * of the discrete operators of the same precision (far sum over the
  * oversampled rule of Section 4 with its near mask, block corrections of

@@ -17,7 +17,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SRC = ["refelem.cpp", "surface.cpp", "quadrature.cpp", "octree.cpp", "harmonics.cpp"]
 HIP_HOST_SRC = ["api.cpp"]
-HIP_SRC = ["kernels.hip", "octree.hip", "quadrature.hip", "calculus.hip"]
+HIP_SRC = ["kernels.hip", "octree.hip", "quadrature.hip", "calculus.hip", "noalloc.hip"]
 
 CXXFLAGS = ["-O3", "-fPIC", "-std=c++17", "-fopenmp", "-Wall", "-Wno-unused-function"]
 HIPFLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

@@ -4,6 +4,7 @@
 #include "common.hpp"
 #include "harmonics.hpp"
 #include "kernels.hpp"
+#include "noalloc.hpp"
 #include "octree.hpp"
 #include "refelem.hpp"
 #include "surface.hpp"
@@ -740,10 +741,44 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
 
 constexpr int CHUNK_GRAD = 8;
 
+// Per-call workspace of the gradient apply for `chunk` densities per
+// traversal: strengths, multipole and local expansions, derived leaf
+// expansions, FMM outputs and the early correction sums.
+template <typename T>
+struct ApplyWs {
+  T *str = nullptr, *M = nullptr, *Lc = nullptr, *D = nullptr, *fmm = nullptr, *corr = nullptr;
+};
+
+// element counts of the ApplyWs buffers (the sizes ensure_ws allocates)
+template <typename T>
+static void ws_counts(const lb_ctx* ctx, const Prec<T>& P, int chunk, size_t cnt[6]) {
+  const int p = P.p;
+  cnt[0] = (size_t)ctx->No * 2 * chunk;
+  cnt[1] = (size_t)P.dt.nbox * 3 * chunk * P.L;
+  cnt[2] = cnt[1];
+  cnt[3] = (size_t)std::max(P.dt.n_leaf_work, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1));
+  cnt[4] = (size_t)ctx->N * 4 * chunk;
+  cnt[5] = (size_t)ctx->N * 4 * chunk;
+}
+
+template <typename T>
+static ApplyWs<T> ctx_ws(Prec<T>& P) {
+  ApplyWs<T> w;
+  w.str = dptr<T>(P.str); w.M = dptr<T>(P.M); w.Lc = dptr<T>(P.Lc);
+  w.D = dptr<T>(P.D); w.fmm = dptr<T>(P.fmm); w.corr = dptr<T>(P.corr);
+  return w;
+}
+
 template <typename T>
 static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, T* grad, T* dSdn, T* surf,
-                          hipStream_t st, PhaseTimer* tm = nullptr) {
-  ensure_ws(ctx, P, CHUNK_GRAD);
+                          hipStream_t st, PhaseTimer* tm = nullptr, const ApplyWs<T>* ws = nullptr) {
+  ApplyWs<T> W;
+  if (ws) {
+    W = *ws;
+  } else {
+    ensure_ws(ctx, P, CHUNK_GRAD);
+    W = ctx_ws(P);
+  }
   const int64_t N = ctx->N, No = ctx->No;
   // corr_early: the correction sums need only sigma, so they run first on
   // the side stream (ahead of the near field, which launch_fmm forks there
@@ -755,22 +790,22 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
       HIPTRY(hipEventRecord(P.dt.fork_ev, st));
       HIPTRY(hipStreamWaitEvent(P.dt.side, P.dt.fork_ev, 0));
       launch_corr_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
-                          sigma + (int64_t)d0 * N, dptr<T>(P.corr), P.dt.side);
+                          sigma + (int64_t)d0 * N, W.corr, P.dt.side);
     }
     if (tm) tm->mark(PH_STR, st);
     launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
-                        dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
+                        dptr<int>(P.src_pos), No, W.str, st);
     if (tm) tm->mark(PH_P2M, st);
-    launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st, tm);
+    launch_fmm<T>(P.dt, FMM_GRAD, c, W.str, W.M, W.Lc, W.D, W.fmm, N, No, st, tm);
     if (tm) tm->mark(PH_COMB, st);
     if (early)
-      launch_combine_grad_fin<T>(c, N, dptr<T>(P.fmm), dptr<T>(P.corr), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
+      launch_combine_grad_fin<T>(c, N, W.fmm, W.corr, dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
                                  pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
                                  dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr,
                                  st);
     else
       launch_combine_grad<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals4),
-                             sigma + (int64_t)d0 * N, dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
+                             sigma + (int64_t)d0 * N, W.fmm, dptr<int>(P.tgt_pos), dptr<T>(P.nrm),
                              pot ? pot + (int64_t)d0 * N : nullptr, grad + (int64_t)d0 * 3 * N,
                              dSdn ? dSdn + (int64_t)d0 * N : nullptr, surf ? surf + (int64_t)d0 * 3 * N : nullptr, st);
     if (tm) tm->mark(PH_N, st);
@@ -1465,6 +1500,30 @@ static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op
 
 }  // namespace lb
 
+namespace lb {
+// Carve the gradient apply's workspace out of the static scratch (256-byte
+// aligned pieces); throws LB_ENOMEM when it does not fit.
+template <typename T>
+static ApplyWs<T> scratch_ws(lb_ctx* ctx, Prec<T>& P, int nd) {
+  size_t cnt[6];
+  ws_counts<T>(ctx, P, std::min(nd, CHUNK_GRAD), cnt);
+  size_t off[7] = {0};
+  for (int i = 0; i < 6; ++i) off[i + 1] = off[i] + (sizeof(T) * cnt[i] + 255) / 256 * 256;
+  if (off[6] > NOALLOC_SCRATCH_BYTES)
+    fail(LB_ENOMEM, "lb_apply_gradS_noalloc needs %zu bytes of scratch for %d densities, the static scratch holds %zu",
+         off[6], nd, NOALLOC_SCRATCH_BYTES);
+  unsigned char* base = static_cast<unsigned char*>(noalloc_scratch(ctx->device));
+  ApplyWs<T> w;
+  w.str = reinterpret_cast<T*>(base + off[0]);
+  w.M = reinterpret_cast<T*>(base + off[1]);
+  w.Lc = reinterpret_cast<T*>(base + off[2]);
+  w.D = reinterpret_cast<T*>(base + off[3]);
+  w.fmm = reinterpret_cast<T*>(base + off[4]);
+  w.corr = reinterpret_cast<T*>(base + off[5]);
+  return w;
+}
+}  // namespace lb
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1653,6 +1712,9 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   }
   if (!ctx->host_only) {
     HIPTRY(hipGetDevice(&ctx->device));
+    // device address of the static scratch of lb_apply_gradS_noalloc on
+    // this device (looked up once per device, with the device current)
+    (void)noalloc_scratch(ctx->device);
     // FP32 near-field mask: sources of patch l within kMaskFrac (eta-1) R_l
     // of a target are left to the corrections (such a patch is always in
     // Near(target), since |x - c_l| < (1 + (eta-1)) R_l)
@@ -1815,6 +1877,25 @@ lb_status lb_apply_gradS(lb_ctx* ctx, int nd, int prec, const void* sigma, void*
   else
     apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, (double*)grad, (double*)dSdn,
                           (double*)surf_grad, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_apply_gradS_noalloc(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* grad,
+                                 void* dSdn, void* surf_grad, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!sigma || !grad) fail(LB_EINVAL, "null sigma or grad");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32) {
+    const ApplyWs<float> w = scratch_ws<float>(ctx, ctx->f32, nd);
+    apply_gradS_t<float>(ctx, ctx->f32, nd, (const float*)sigma, (float*)pot, (float*)grad, (float*)dSdn,
+                         (float*)surf_grad, st, nullptr, &w);
+  } else {
+    const ApplyWs<double> w = scratch_ws<double>(ctx, ctx->f64, nd);
+    apply_gradS_t<double>(ctx, ctx->f64, nd, (const double*)sigma, (double*)pot, (double*)grad, (double*)dSdn,
+                          (double*)surf_grad, st, nullptr, &w);
+  }
   HIPTRY(hipGetLastError());
   API_END
 }

@@ -38,7 +38,7 @@ EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj",
             "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_apply_A1", "lb_set_tuning", "lb_destroy",
-            "lb_last_error")
+            "lb_last_error", "lb_apply_gradS_noalloc")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -113,6 +113,7 @@ def lib():
         L.lb_tree_destroy.argtypes = [vp]
         L.lb_apply_S.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_gradS.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
+        L.lb_apply_gradS_noalloc.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.lb_apply_gradS_adj.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.lb_apply_S_adj.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_S_adj_X.argtypes = [vp, ip, ip, vp, vp, vp, vp]
@@ -318,6 +319,15 @@ class Surface:
         _check(lib().lb_apply_gradS(self._ctx, nd, self._prec(sigma), _ptr(sigma), _ptr(o.get("pot")),
                                     _ptr(o["grad"]), _ptr(o.get("dSdn")), _ptr(o.get("surf_grad")), _stream()))
         return o
+
+    def apply_gradS_noalloc(self, sigma, out):
+        """lb_apply_gradS_noalloc into caller-allocated outputs: out holds
+        "grad" (shape sigma.shape + (3,)) and optionally "pot", "dSdn",
+        "surf_grad"; the library allocates nothing."""
+        _check(lib().lb_apply_gradS_noalloc(self._ctx, self._nd(sigma), self._prec(sigma), _ptr(sigma),
+                                            _ptr(out.get("pot")), _ptr(out["grad"]), _ptr(out.get("dSdn")),
+                                            _ptr(out.get("surf_grad")), _stream()))
+        return out
 
     def apply_S_adj(self, gbar, out=None):
         """sigma_bar = S^T gbar (the transpose of the discrete S of this precision)."""
