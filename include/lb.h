@@ -99,6 +99,11 @@ typedef struct {
   int outer_steps;      /* FP64 residual evaluations after the first (0 in LB_SOLVE_FP64) */
   double rel_resid;     /* ||f - A3 sigma||_2 / ||f||_2 of the returned sigma, FP64 operator */
   double removed_mean;  /* weighted mean sum w f / sum w that was removed from f */
+  double t_setup;       /* wall-clock seconds the context's setup took (lb_setup, lb_setup_batch
+                           or lb_import_setup): the paper's quadrature time t_q plus the tree
+                           and translation setup */
+  double t_solve;       /* wall-clock seconds of this lb_solve / lb_solve_adj call, from entry
+                           to the synchronized result (the paper's t_s without t_q) */
 } lb_solve_info;
 
 typedef struct {

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <limits>
 #include <cstring>
@@ -22,6 +23,10 @@
 namespace lb {
 
 static thread_local std::string g_last_error;
+
+static double wall_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 #define HIPTRY(x)                                                                     \
@@ -157,6 +162,11 @@ struct OpGraph {
   const void* in = nullptr;
   const void* out = nullptr;
   int n = 0;
+  // further buffers and sizes the captured launches depend on (GMRES
+  // iteration graphs: basis, state, system count, iteration cap)
+  const void* aux0 = nullptr;
+  const void* aux1 = nullptr;
+  int64_t aux2 = 0;
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -164,6 +174,8 @@ struct OpGraph {
     graph = nullptr;
     in = out = nullptr;
     n = 0;
+    aux0 = aux1 = nullptr;
+    aux2 = 0;
   }
 };
 
@@ -210,6 +222,7 @@ using namespace lb;
 
 struct lb_ctx {
   int k = 0, NP = 0, n_p = 0, n_o = 0;
+  double t_setup = 0.0;  // wall-clock seconds of lb_setup / lb_setup_batch (or of the import)
   // surfaces: surface q owns patches [surf_patch[q], surf_patch[q+1]) (its
   // nodes and oversampled points follow in the same order)
   int n_surf = 1;
@@ -244,7 +257,11 @@ struct lb_ctx {
   // A1 workspace per precision: S[1], and the intermediate applies
   DBuf a1_phi0_32, a1_phi0_64, a1_pot, a1_g1, a1_surf, a1_mu, a1_g2, a1_eta;
   // solver workspace
-  DBuf V, wv, hbuf, partial, r, sig, ftmp, utmp, msys, msys_part, msys2;
+  DBuf V, wv, partial, r, sig, ftmp, utmp, msys2;
+  // device GMRES state (GmresDev), skip flags, pinned host word for the
+  // per-iteration count of active systems
+  DBuf gm_state, gm_skip;
+  int* gm_host = nullptr;
   // per-surface row ranges: node_off [n_surf+1] (host and device), the
   // surface of every node, 1/area per surface; scratch for per-surface sums
   std::vector<int64_t> node_off_h;
@@ -256,9 +273,15 @@ struct lb_ctx {
   // side stream (default priority) and its fork/join events
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  lb::OpGraph gA64, gA32, gT64, gT32;
+  // GMRES iteration graphs (A3 and A3^T, FP64 and FP32) and the FP64
+  // residual applies of the solves
+  lb::OpGraph gI64, gI32, gIT64, gIT32, gR64, gRT64;
+  void reset_graphs() {
+    gI64.reset(); gI32.reset(); gIT64.reset(); gIT32.reset(); gR64.reset(); gRT64.reset();
+  }
   ~lb_ctx() {
-    gA64.reset(); gA32.reset(); gT64.reset(); gT32.reset();
+    reset_graphs();
+    if (gm_host) (void)hipHostFree(gm_host);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (side_stream) (void)hipStreamDestroy(side_stream);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -997,7 +1020,7 @@ static void apply_S_xbar_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int
 template <typename T>
 static void rebuild_trees(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, int leaf_src) {
   HIPTRY(hipDeviceSynchronize());
-  ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
+  ctx->reset_graphs();
   const bool fp32 = sizeof(T) == 4;
   build_prec<T>(ctx, P, P.p, std::vector<double>(), fp32 ? ctx->rm2f : std::vector<float>(), P.min_leaf_side,
                 leaf_src, P.direct);
@@ -1012,7 +1035,7 @@ static void rebuild_trees(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_buil
 template <typename T>
 static void set_leaf_shape(lb_ctx* ctx, Prec<T>& P, int fmax, int split) {
   HIPTRY(hipDeviceSynchronize());
-  ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
+  ctx->reset_graphs();
   make_leaf_work<T>(P, fmax, split);
   P.ws_rhs = 0;
   HIPTRY(hipDeviceSynchronize());
@@ -1023,7 +1046,7 @@ static void set_leaf_shape(lb_ctx* ctx, Prec<T>& P, int fmax, int split) {
 template <typename T>
 static void set_schedule(lb_ctx* ctx, Prec<T>& P, int fork_late, int near_grid, int corr_early) {
   HIPTRY(hipDeviceSynchronize());
-  ctx->gA64.reset(); ctx->gA32.reset(); ctx->gT64.reset(); ctx->gT32.reset();
+  ctx->reset_graphs();
   P.fork_late = fork_late;
   P.near_grid = near_grid;
   P.corr_early = corr_early;
@@ -1226,18 +1249,10 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
 // the body needs), then captures it on the library's stream for the
 // following calls; LB_NO_GRAPH runs it eagerly always.
 // ---------------------------------------------------------------------------
+// capture `body` (kernel launches only) on the library's capture stream
+// into G and instantiate it
 template <typename Body>
-static void graphed(lb_ctx* ctx, OpGraph& G, Body&& body, const void* in, const void* out, int n, hipStream_t st) {
-  if (ctx->opts.flags & LB_NO_GRAPH) {
-    body(st);
-    return;
-  }
-  if (G.exec && G.in == in && G.out == out && G.n == n) {
-    HIPTRY(hipGraphLaunch(G.exec, st));
-    return;
-  }
-  G.reset();
-  body(st);
+static void capture(lb_ctx* ctx, OpGraph& G, Body&& body) {
   if (!ctx->cap_stream) HIPTRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   HIPTRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
   try {
@@ -1251,6 +1266,21 @@ static void graphed(lb_ctx* ctx, OpGraph& G, Body&& body, const void* in, const 
   }
   HIPTRY(hipStreamEndCapture(ctx->cap_stream, &G.graph));
   HIPTRY(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+}
+
+template <typename Body>
+static void graphed(lb_ctx* ctx, OpGraph& G, Body&& body, const void* in, const void* out, int n, hipStream_t st) {
+  if (ctx->opts.flags & LB_NO_GRAPH) {
+    body(st);
+    return;
+  }
+  if (G.exec && G.in == in && G.out == out && G.n == n) {
+    HIPTRY(hipGraphLaunch(G.exec, st));
+    return;
+  }
+  G.reset();
+  body(st);
+  capture(ctx, G, body);
   G.in = in;
   G.out = out;
   G.n = n;
@@ -1260,10 +1290,13 @@ static void graphed(lb_ctx* ctx, OpGraph& G, Body&& body, const void* in, const 
 // GMRES (Section 6) for several independent systems at once: x0 = 0, no
 // restart; system a is the segment [xoff[a], xoff[a] + len[a]) of the
 // operator's vectors [nrhs][N] (one (right-hand side, surface) pair), with
-// its own Arnoldi basis (CGS2, FP64 on the device) and Givens rotations
-// (host).  Each iteration applies the operator once to all systems (zero
-// segments for the finished ones) and needs one device-host round trip.
-// A(in [nrhs][N], out [nrhs][N], nrhs).
+// its own Arnoldi basis (CGS2) and Givens rotations, all FP64 on the device
+// (launch_gm_*).  One iteration (gather of the current basis vectors, the
+// operator on all systems at once (zero segments for the stopped ones),
+// CGS2, the Givens step, the next basis vector) is captured once as a HIP
+// graph and replayed; the host reads one integer per iteration, the number
+// of systems still iterating.
+// A(in [nrhs][N], out [nrhs][N], nrhs, stream): kernel launches only.
 // ---------------------------------------------------------------------------
 struct Systems {
   std::vector<int64_t> xoff, len;
@@ -1298,153 +1331,123 @@ static Systems make_systems(const lb_ctx* ctx, int nrhs) {
   return sy;
 }
 
+// device state of gmres_sys for ns systems and maxit iterations (one
+// allocation, carved in 256-byte aligned pieces)
+static GmresDev gmres_state(lb_ctx* ctx, const Systems& sy, int maxit, int64_t& vtot) {
+  const int ns = (int)sy.xoff.size();
+  const int km = maxit + 1;
+  const size_t sz[] = {sizeof(int64_t) * ns * 3, sizeof(int) * ((size_t)ns * 2 + 2),
+                       sizeof(double) * (size_t)ns * maxit * maxit, sizeof(double) * (size_t)ns * maxit * 2,
+                       sizeof(double) * (size_t)ns * km * 3, sizeof(double) * (size_t)ns * 5,
+                       sizeof(double) * (size_t)ns * km * 32, sizeof(double)};
+  size_t off[9] = {0};
+  for (int q = 0; q < 8; ++q) off[q + 1] = off[q] + (sz[q] + 255) / 256 * 256;
+  ctx->gm_state.alloc(off[8]);
+  ctx->gm_skip.alloc(sizeof(int) * (size_t)ns);
+  if (!ctx->gm_host) HIPTRY(hipHostMalloc((void**)&ctx->gm_host, sizeof(int) * 4, hipHostMallocDefault));
+  char* b = static_cast<char*>(ctx->gm_state.p);
+  GmresDev gm;
+  int64_t* i64 = reinterpret_cast<int64_t*>(b + off[0]);
+  gm.xoff = i64; gm.len = i64 + ns; gm.vbase = i64 + 2 * ns;
+  int* i32 = reinterpret_cast<int*>(b + off[1]);
+  gm.active = i32; gm.kdone = i32 + ns; gm.iter = i32 + 2 * ns; gm.nactive = i32 + 2 * ns + 1;
+  gm.R = reinterpret_cast<double*>(b + off[2]);
+  gm.cs = reinterpret_cast<double*>(b + off[3]); gm.sn = gm.cs + (size_t)ns * maxit;
+  gm.g = reinterpret_cast<double*>(b + off[4]); gm.h1 = gm.g + (size_t)ns * km; gm.h2 = gm.h1 + (size_t)ns * km;
+  double* s5 = reinterpret_cast<double*>(b + off[5]);
+  gm.beta = s5; gm.relres = s5 + ns; gm.sc = s5 + 2 * ns; gm.nr = s5 + 3 * ns;
+  gm.part = reinterpret_cast<double*>(b + off[6]);
+  gm.tol = reinterpret_cast<double*>(b + off[7]);
+  gm.ns = ns; gm.maxit = maxit; gm.km = km;
+  std::vector<int64_t> t(3 * (size_t)ns);
+  vtot = 0;
+  gm.maxlen = 1;
+  for (int a = 0; a < ns; ++a) {
+    t[a] = sy.xoff[a];
+    t[ns + a] = sy.len[a];
+    t[2 * ns + a] = vtot;
+    vtot += (int64_t)km * sy.len[a];
+    gm.maxlen = std::max(gm.maxlen, sy.len[a]);
+  }
+  HIPTRY(hipMemcpy(const_cast<int64_t*>(gm.xoff), t.data(), sizeof(int64_t) * t.size(), hipMemcpyHostToDevice));
+  return gm;
+}
+
 template <typename ApplyFn>
-static void gmres_sys(lb_ctx* ctx, ApplyFn A, int nrhs, const Systems& sy, const double* B, double* X, double tol,
-                      int maxit, const std::vector<char>& skip, std::vector<double>& relres, std::vector<int>& iters,
-                      hipStream_t st) {
+static void gmres_sys(lb_ctx* ctx, ApplyFn A, OpGraph& G, int nrhs, const Systems& sy, const double* B, double* X,
+                      double tol, int maxit, const std::vector<char>& skip, std::vector<double>& relres,
+                      std::vector<int>& iters, hipStream_t st) {
   const int64_t N = ctx->N;
   const int ns = (int)sy.xoff.size();
-  std::vector<int64_t> vbase(ns);
-  int64_t tot = 0, maxlen = 1;
-  for (int a = 0; a < ns; ++a) {
-    vbase[a] = tot;
-    tot += (int64_t)(maxit + 1) * sy.len[a];
-    maxlen = std::max(maxlen, sy.len[a]);
-  }
-  ctx->V.alloc(sizeof(double) * (size_t)std::max<int64_t>(tot, 1));
+  int64_t vtot = 0;
+  const GmresDev gm = gmres_state(ctx, sy, maxit, vtot);
+  ctx->V.alloc(sizeof(double) * (size_t)std::max<int64_t>(vtot, 1));
   ctx->wv.alloc(sizeof(double) * (size_t)N * nrhs * 2);
-  ctx->msys.alloc(sizeof(int64_t) * 6 * ns + sizeof(int) * ns + 64);
-  ctx->msys_part.alloc(sizeof(double) * (size_t)ns * (maxit + 1) * 32 + 64);
-  ctx->hbuf.alloc(sizeof(double) * ((size_t)ns * (2 * (maxit + 1) + 2) + 8));
   double* Vall = dptr<double>(ctx->V);
   double* win = dptr<double>(ctx->wv);
   double* wout = win + (size_t)N * nrhs;
-  int64_t* d_all = dptr<int64_t>(ctx->msys);       // all systems: xoff, len, vbase
-  int64_t* d_act = d_all + 3 * ns;                   // active systems: xoff, len, vbase
-  int* d_flag = reinterpret_cast<int*>(d_all + 6 * ns);
-  double* part = dptr<double>(ctx->msys_part);
-  double* h1 = dptr<double>(ctx->hbuf);
-  double* h2 = h1 + (size_t)ns * (maxit + 1);
-  double* nr = h2 + (size_t)ns * (maxit + 1);
-  double* sc = nr + ns;
   {
-    std::vector<int64_t> t(3 * ns);
-    for (int a = 0; a < ns; ++a) { t[a] = sy.xoff[a]; t[ns + a] = sy.len[a]; t[2 * ns + a] = vbase[a]; }
-    HIPTRY(hipMemcpyAsync(d_all, t.data(), sizeof(int64_t) * 3 * ns, hipMemcpyHostToDevice, st));
-    HIPTRY(hipStreamSynchronize(st));  // t is a local host buffer
+    std::vector<int> sk(ns);
+    for (int a = 0; a < ns; ++a) sk[a] = skip[a] ? 1 : 0;
+    HIPTRY(hipMemcpyAsync(dptr<int>(ctx->gm_skip), sk.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(const_cast<double*>(gm.tol), &tol, sizeof(double), hipMemcpyHostToDevice, st));
+    launch_gm_start(gm, B, dptr<int>(ctx->gm_skip), Vall, st);
+    HIPTRY(hipMemcpyAsync(ctx->gm_host, gm.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));  // sk and tol are host locals; nactive read
   }
-  struct St {
-    std::vector<double> H, cs, sn, g;
-    double beta = 0;
-    int k = 0;
-    bool done = false;
+  auto body = [&](hipStream_t s) {
+    launch_gm_gather(gm, Vall, win, s);
+    A(win, wout, nrhs, s);
+    launch_gm_arnoldi(gm, Vall, wout, s);
   };
-  std::vector<St> S(ns);
+  const bool use_graph = !(ctx->opts.flags & LB_NO_GRAPH);
+  bool have = G.exec && G.in == win && G.out == wout && G.n == nrhs && G.aux0 == Vall && G.aux1 == ctx->gm_state.p &&
+              G.aux2 == ((int64_t)ns << 32 | maxit);
+  for (int j = 0; j < maxit && *ctx->gm_host > 0; ++j) {
+    if (!use_graph) {
+      body(st);
+    } else if (have) {
+      HIPTRY(hipGraphLaunch(G.exec, st));
+    } else {
+      // the first iteration runs eagerly (it makes the allocations the
+      // operator needs); the following ones replay its graph
+      G.reset();
+      body(st);
+      capture(ctx, G, body);
+      G.in = win; G.out = wout; G.n = nrhs;
+      G.aux0 = Vall; G.aux1 = ctx->gm_state.p; G.aux2 = (int64_t)ns << 32 | maxit;
+      have = true;
+    }
+    HIPTRY(hipMemcpyAsync(ctx->gm_host, gm.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+  }
+  launch_gm_finish(gm, Vall, X, st);
+  std::vector<int> kd(ns);
   relres.assign(ns, 0.0);
-  iters.assign(ns, 0);
-  HIPTRY(hipMemsetAsync(X, 0, sizeof(double) * (size_t)N * nrhs, st));
-  // initial residuals b: norms and the first basis vectors
-  std::vector<double> hv((size_t)ns * (maxit + 1)), hw((size_t)ns * (maxit + 1)), hn(ns), scale(ns);
-  launch_msys_dots(ns, 1, d_all, d_all + ns, nullptr, nullptr, B, part, nr, st);
-  HIPTRY(hipMemcpyAsync(hn.data(), nr, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipMemcpyAsync(kd.data(), gm.kdone, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipMemcpyAsync(relres.data(), gm.relres, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
-  for (int a = 0; a < ns; ++a) {
-    St& q = S[a];
-    q.H.assign((size_t)(maxit + 1) * maxit, 0.0);
-    q.cs.assign(maxit, 0.0);
-    q.sn.assign(maxit, 0.0);
-    q.g.assign(maxit + 1, 0.0);
-    q.beta = std::sqrt(hn[a]);
-    q.done = skip[a] || q.beta == 0.0;
-    q.g[0] = q.beta;
-    scale[a] = q.done ? 0.0 : 1.0 / q.beta;
-  }
-  HIPTRY(hipMemcpyAsync(sc, scale.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
-  launch_msys_scale_copy(ns, maxlen, 0, d_all, d_all + ns, d_all + 2 * ns, sc, B, Vall, st);
-  std::vector<int> act, flag(ns);
-  std::vector<int64_t> at;
-  for (int j = 0; j < maxit; ++j) {
-    act.clear();
-    for (int a = 0; a < ns; ++a) {
-      flag[a] = !S[a].done;
-      if (!S[a].done) act.push_back(a);
-    }
-    if (act.empty()) break;
-    const int na = (int)act.size(), k = j + 1;
-    at.assign(3 * na, 0);
-    for (int i = 0; i < na; ++i) { at[i] = sy.xoff[act[i]]; at[na + i] = sy.len[act[i]]; at[2 * na + i] = vbase[act[i]]; }
-    HIPTRY(hipMemcpyAsync(d_act, at.data(), sizeof(int64_t) * 3 * na, hipMemcpyHostToDevice, st));
-    HIPTRY(hipMemcpyAsync(d_flag, flag.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
-    launch_msys_gather(ns, maxlen, d_all, d_all + ns, d_all + 2 * ns, d_flag, j, Vall, win, st);
-    A(win, wout, nrhs);
-    // CGS2 on every active system, one round trip for h1, h2 and the norms
-    launch_msys_dots(na, k, d_act, d_act + na, d_act + 2 * na, Vall, wout, part, h1, st);
-    launch_msys_gemv(na, maxlen, k, d_act, d_act + na, d_act + 2 * na, Vall, h1, -1.0, wout, st);
-    launch_msys_dots(na, k, d_act, d_act + na, d_act + 2 * na, Vall, wout, part, h2, st);
-    launch_msys_gemv(na, maxlen, k, d_act, d_act + na, d_act + 2 * na, Vall, h2, -1.0, wout, st);
-    launch_msys_dots(na, 1, d_act, d_act + na, nullptr, nullptr, wout, part, nr, st);
-    HIPTRY(hipMemcpyAsync(hv.data(), h1, sizeof(double) * na * k, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(hw.data(), h2, sizeof(double) * na * k, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(hn.data(), nr, sizeof(double) * na, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    for (int i = 0; i < na; ++i) {
-      const int a = act[i];
-      St& q = S[a];
-      std::vector<double>& H = q.H;
-      const double hnrm = std::sqrt(hn[i]);
-      for (int r = 0; r <= j; ++r) H[(size_t)r * maxit + j] = hv[(size_t)i * k + r] + hw[(size_t)i * k + r];
-      H[(size_t)(j + 1) * maxit + j] = hnrm;
-      for (int r = 0; r < j; ++r) {
-        const double a1 = H[(size_t)r * maxit + j], b1 = H[(size_t)(r + 1) * maxit + j];
-        H[(size_t)r * maxit + j] = q.cs[r] * a1 + q.sn[r] * b1;
-        H[(size_t)(r + 1) * maxit + j] = -q.sn[r] * a1 + q.cs[r] * b1;
-      }
-      const double a1 = H[(size_t)j * maxit + j], b1 = H[(size_t)(j + 1) * maxit + j];
-      const double den = std::hypot(a1, b1);
-      q.cs[j] = a1 / den;
-      q.sn[j] = b1 / den;
-      H[(size_t)j * maxit + j] = den;
-      H[(size_t)(j + 1) * maxit + j] = 0.0;
-      q.g[j + 1] = -q.sn[j] * q.g[j];
-      q.g[j] = q.cs[j] * q.g[j];
-      q.k = j + 1;
-      relres[a] = std::fabs(q.g[j + 1]) / q.beta;
-      if (relres[a] < tol || hnrm == 0.0 || j + 1 == maxit) q.done = true;
-      scale[i] = q.done ? 0.0 : 1.0 / hnrm;
-    }
-    HIPTRY(hipMemcpyAsync(sc, scale.data(), sizeof(double) * na, hipMemcpyHostToDevice, st));
-    launch_msys_scale_copy(na, maxlen, j + 1, d_act, d_act + na, d_act + 2 * na, sc, wout, Vall, st);
-  }
-  // x = V y per system
-  std::vector<double> ys;
-  for (int a = 0; a < ns; ++a) {
-    St& q = S[a];
-    iters[a] = q.k;
-    if (q.k == 0) continue;
-    std::vector<double> y(q.k);
-    for (int i = q.k - 1; i >= 0; --i) {
-      double sacc = q.g[i];
-      for (int c = i + 1; c < q.k; ++c) sacc -= q.H[(size_t)i * maxit + c] * y[c];
-      y[i] = sacc / q.H[(size_t)i * maxit + i];
-    }
-    HIPTRY(hipMemcpyAsync(h1, y.data(), sizeof(double) * q.k, hipMemcpyHostToDevice, st));
-    launch_gemv_add(Vall + vbase[a], sy.len[a], q.k, h1, X + sy.xoff[a], sy.len[a], st);
-    HIPTRY(hipStreamSynchronize(st));
-  }
+  iters.assign(kd.begin(), kd.end());
 }
 
 // ---------------------------------------------------------------------------
 // Solve A sig = b for every system (b, sig [nrhs][N]; bnorm per system):
 // LB_SOLVE_FP64: GMRES with the FP64 operator A64; LB_SOLVE_FP32_REFINE:
 // iterative refinement, each correction from GMRES with the FP32 operator
-// A32 on the FP64 residual.  rel = final FP64 relative residuals per system.
-// r, ut, dcorr: [nrhs][N] workspace.
+// A32 on the FP64 residual.  A refinement step that leaves a system's FP64
+// residual larger than before is taken back for that system; a system whose
+// refinement stops contracting (residual above half the previous one) before
+// reaching tol gets a last correction from GMRES with the FP64 operator.
+// rel = final FP64 relative residuals per system.  A64 / A32: kernel
+// launches only (in, out, nrhs, stream); G64 / G32 hold their GMRES
+// iteration graphs, GR the residual apply's graph.  r, ut, dcorr: [nrhs][N]
+// workspace.
 // ---------------------------------------------------------------------------
 template <typename Op64, typename Op32>
-static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op32& A32, const double* b,
-                         const std::vector<double>& bnorm, double* sig, double* r, double* ut, double* dcorr,
-                         double tol, int mode, std::vector<double>& rel, std::vector<int>& iters,
-                         std::vector<int>& outer, hipStream_t st) {
+static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op32& A32, OpGraph& G64,
+                         OpGraph& G32, OpGraph& GR, const double* b, const std::vector<double>& bnorm, double* sig,
+                         double* r, double* ut, double* dcorr, double tol, int mode, std::vector<double>& rel,
+                         std::vector<int>& iters, std::vector<int>& outer, hipStream_t st) {
   const int64_t N = ctx->N;
   const size_t nN = (size_t)nrhs * N;
   const int maxit = ctx->opts.max_iter;
@@ -1456,13 +1459,13 @@ static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op
   std::vector<int> it;
   std::vector<char> skip(ns, 0);
   auto residual = [&]() {  // r = b - A sig (FP64), rel = |r| / |b| per system
-    A64(sig, ut, nrhs);
+    graphed(ctx, GR, [&](hipStream_t s2) { A64(sig, ut, nrhs, s2); }, sig, ut, nrhs, st);
     launch_axpby(1.0, b, -1.0, ut, r, (int64_t)nN, st);
     std::vector<double> rn = system_norms(ctx, sy, r, st);
     for (int a = 0; a < ns; ++a) rel[a] = bnorm[a] > 0 ? rn[a] / bnorm[a] : 0.0;
   };
   if (mode == LB_SOLVE_FP64) {
-    gmres_sys(ctx, A64, nrhs, sy, b, sig, tol, maxit, skip, inner, it, st);
+    gmres_sys(ctx, A64, G64, nrhs, sy, b, sig, tol, maxit, skip, inner, it, st);
     for (int a = 0; a < ns; ++a) iters[a] = it[a];
     residual();
     return;
@@ -1471,11 +1474,13 @@ static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op
   HIPTRY(hipMemcpyAsync(r, b, sizeof(double) * nN, hipMemcpyDeviceToDevice, st));
   for (int a = 0; a < ns; ++a) rel[a] = bnorm[a] > 0 ? 1.0 : 0.0;
   std::vector<double> prev(ns, 1e300);
+  std::vector<char> stalled(ns, 0);
   const int max_outer = 12;
   for (int step = 0; step < max_outer; ++step) {
     bool any = false;
     for (int a = 0; a < ns; ++a) {
-      skip[a] = !(rel[a] >= tol) || rel[a] > 0.5 * prev[a];  // converged, or refinement stalled
+      if (rel[a] >= tol && rel[a] > 0.5 * prev[a]) stalled[a] = 1;  // refinement stopped contracting
+      skip[a] = !(rel[a] >= tol) || stalled[a];
       any |= !skip[a];
     }
     if (!any) break;
@@ -1485,15 +1490,44 @@ static void solve_system(lb_ctx* ctx, int nrhs, const Systems& sy, Op64& A64, Op
     for (int a = 0; a < ns; ++a)
       if (!skip[a]) worst = std::max(worst, rel[a]);
     const double inner_tol = std::max(1e-6, 0.5 * tol / std::max(worst, 1e-300));
-    gmres_sys(ctx, A32, nrhs, sy, r, dcorr, inner_tol, maxit, skip, inner, it, st);
+    gmres_sys(ctx, A32, G32, nrhs, sy, r, dcorr, inner_tol, maxit, skip, inner, it, st);
     for (int a = 0; a < ns; ++a) {
       if (skip[a]) continue;
       iters[a] += it[a];
       outer[a] += 1;
     }
-    // skipped systems have a zero correction (gmres_sys zeroes the output)
+    // skipped systems have a zero correction (gmres_sys writes zeros there)
     launch_axpby(1.0, sig, 1.0, dcorr, sig, (int64_t)nN, st);
     prev = rel;
+    residual();
+    bool undo = false;
+    for (int a = 0; a < ns; ++a)
+      if (!skip[a] && rel[a] > prev[a]) {  // the step made this system worse: take it back
+        launch_axpby(1.0, sig + sy.xoff[a], -1.0, dcorr + sy.xoff[a], sig + sy.xoff[a], sy.len[a], st);
+        stalled[a] = 1;
+        undo = true;
+      }
+    if (undo) residual();
+  }
+  // FP64 correction for the systems whose refinement stalled above tol
+  bool any = false;
+  double worst = 0;
+  for (int a = 0; a < ns; ++a) {
+    skip[a] = !(stalled[a] && rel[a] >= tol);
+    if (!skip[a]) {
+      any = true;
+      worst = std::max(worst, rel[a]);
+    }
+  }
+  if (any) {
+    gmres_sys(ctx, A64, G64, nrhs, sy, r, dcorr, std::min(0.5, 0.5 * tol / std::max(worst, 1e-300)), maxit, skip,
+              inner, it, st);
+    for (int a = 0; a < ns; ++a)
+      if (!skip[a]) {
+        iters[a] += it[a];
+        outer[a] += 1;
+      }
+    launch_axpby(1.0, sig, 1.0, dcorr, sig, (int64_t)nN, st);
     residual();
   }
 }
@@ -1767,9 +1801,11 @@ lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, cons
   if (!out) fail(LB_EINVAL, "null argument");
   *out = nullptr;
   if (n_patches < 1) fail(LB_EINVAL, "n_patches must be >= 1");
+  const double t0 = wall_seconds();
   auto ctx = std::make_unique<lb_ctx>();
   const int32_t np = n_patches;
   setup_impl(ctx.get(), 1, &np, order, X, Xu, Xv, opts);
+  ctx->t_setup = wall_seconds() - t0;
   *out = ctx.release();
   API_END
 }
@@ -1780,8 +1816,10 @@ lb_status lb_setup_batch(lb_ctx** out, int n_surf, const int32_t* patches_per_su
   (void)stream;
   if (!out) fail(LB_EINVAL, "null argument");
   *out = nullptr;
+  const double t0 = wall_seconds();
   auto ctx = std::make_unique<lb_ctx>();
   setup_impl(ctx.get(), n_surf, patches_per_surf, order, X, Xu, Xv, opts);
+  ctx->t_setup = wall_seconds() - t0;
   *out = ctx.release();
   API_END
 }
@@ -1880,6 +1918,7 @@ lb_status lb_apply_gradS(lb_ctx* ctx, int nd, int prec, const void* sigma, void*
   HIPTRY(hipGetLastError());
   API_END
 }
+
 
 lb_status lb_apply_gradS_noalloc(lb_ctx* ctx, int nd, int prec, const void* sigma, void* pot, void* grad,
                                  void* dSdn, void* surf_grad, void* stream) {
@@ -2149,6 +2188,7 @@ lb_status lb_apply_A3(lb_ctx* ctx, int nd, int prec, const void* tau, void* out,
 lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol, int mode, lb_solve_info* info,
                    void* stream) {
   API_BEGIN
+  const double t_start = wall_seconds();
   check_apply(ctx, nrhs, LB_PREC_FP64);
   if (!f || !u) fail(LB_EINVAL, "null f or u");
   if (!(tol > 0)) fail(LB_EINVAL, "tol must be > 0");
@@ -2170,17 +2210,15 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   double* fz = dptr<double>(ctx->ftmp);
   double* ut = dptr<double>(ctx->utmp);
   double* dcorr = ut + nN;
-  auto A64 = [&](const double* v, double* w, int na) {
-    graphed(ctx, ctx->gA64, [&](hipStream_t s2) { apply_A3_t<double>(ctx, ctx->f64, na, v, w, s2); }, v, w, na, st);
+  auto A64 = [&](const double* v, double* w, int na, hipStream_t s2) {
+    apply_A3_t<double>(ctx, ctx->f64, na, v, w, s2);
   };
-  auto A32 = [&](const double* v, double* w, int na) {
+  auto A32 = [&](const double* v, double* w, int na, hipStream_t s2) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
     float* vo = dptr<float>(ctx->f32.tmp_out);
-    graphed(ctx, ctx->gA32, [&](hipStream_t s2) {
-      launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
-      apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, s2);
-      launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
-    }, v, w, na, st);
+    launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
+    apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, s2);
+    launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
   };
   // mean projection per surface (Lemma 1): fz = f - (sum_q w f / area_q) on surface q
   DBuf means;
@@ -2208,11 +2246,13 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
     }
   std::vector<double> rel;
   std::vector<int> iters, outer;
-  solve_system(ctx, nrhs, sy, A64, A32, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel, iters, outer, st);
+  solve_system(ctx, nrhs, sy, A64, A32, ctx->gI64, ctx->gI32, ctx->gR64, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel,
+               iters, outer, st);
   // u = S[S[sigma]] in FP64
   apply_S_t<double>(ctx, ctx->f64, nrhs, sig, ut, st);
   apply_S_t<double>(ctx, ctx->f64, nrhs, ut, u, st);
   HIPTRY(hipStreamSynchronize(st));
+  const double t_solve = wall_seconds() - t_start;
   lb_status ret = LB_OK;
   for (size_t a = 0; a < rel.size(); ++a) {
     if (!(rel[a] < tol)) ret = LB_ENOCONV;
@@ -2221,6 +2261,8 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
       info[a].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[a] - 1, 0);
       info[a].rel_resid = rel[a];
       info[a].removed_mean = mean[a];
+      info[a].t_setup = ctx->t_setup;
+      info[a].t_solve = t_solve;
     }
   }
   if (ret != LB_OK) {
@@ -2298,6 +2340,7 @@ lb_status lb_hodge(lb_ctx* ctx, int nf, const double* F, double* alpha, double* 
 lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, double tol, int mode,
                        lb_solve_info* info, void* stream) {
   API_BEGIN
+  const double t_start = wall_seconds();
   check_apply(ctx, nrhs, LB_PREC_FP64);
   if (!ubar || !fbar) fail(LB_EINVAL, "null ubar or fbar");
   if (!(tol > 0)) fail(LB_EINVAL, "tol must be > 0");
@@ -2319,19 +2362,15 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
   double* rhs = dptr<double>(ctx->ftmp);
   double* ut = dptr<double>(ctx->utmp);
   double* dcorr = ut + nN;
-  auto A64 = [&](const double* v, double* w, int na) {
-    graphed(ctx, ctx->gT64, [&](hipStream_t s2) {
-      apply_A3T_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, ctx->z64, ctx->z_built64, na, v, w, s2);
-    }, v, w, na, st);
+  auto A64 = [&](const double* v, double* w, int na, hipStream_t s2) {
+    apply_A3T_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, ctx->z64, ctx->z_built64, na, v, w, s2);
   };
-  auto A32 = [&](const double* v, double* w, int na) {
+  auto A32 = [&](const double* v, double* w, int na, hipStream_t s2) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
     float* vo = dptr<float>(ctx->f32.tmp_out);
-    graphed(ctx, ctx->gT32, [&](hipStream_t s2) {
-      launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
-      apply_A3T_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, ctx->z32, ctx->z_built32, na, vi, vo, s2);
-      launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
-    }, v, w, na, st);
+    launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
+    apply_A3T_t<float>(ctx, ctx->f32, ctx->a32, ctx->adj_built32, ctx->z32, ctx->z_built32, na, vi, vo, s2);
+    launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
   };
   // rhs = S^T S^T ubar (adjoint of u = S[S[sigma]])
   apply_adj_t<double>(ctx, ctx->f64, ctx->a64, ctx->adj_built64, nrhs, ubar, nullptr, nullptr, nullptr, ut, st);
@@ -2340,7 +2379,8 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
   const std::vector<double> bnorm = system_norms(ctx, sy, rhs, st);
   std::vector<double> rel;
   std::vector<int> iters, outer;
-  solve_system(ctx, nrhs, sy, A64, A32, rhs, bnorm, y, r, ut, dcorr, tol, mode, rel, iters, outer, st);
+  solve_system(ctx, nrhs, sy, A64, A32, ctx->gIT64, ctx->gIT32, ctx->gRT64, rhs, bnorm, y, r, ut, dcorr, tol, mode,
+               rel, iters, outer, st);
   // fbar = (I - w 1^T / area_q) y on each surface q: the transposed mean projection
   DBuf sc;
   sc.alloc(sizeof(double) * (size_t)nrhs * nsf);
@@ -2351,6 +2391,7 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
   std::vector<double> removed((size_t)nrhs * nsf);
   HIPTRY(hipMemcpyAsync(removed.data(), sc.p, sizeof(double) * removed.size(), hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
+  const double t_solve = wall_seconds() - t_start;
   lb_status ret = LB_OK;
   for (size_t a = 0; a < rel.size(); ++a) {
     if (!(rel[a] < tol)) ret = LB_ENOCONV;
@@ -2359,6 +2400,8 @@ lb_status lb_solve_adj(lb_ctx* ctx, int nrhs, const double* ubar, double* fbar, 
       info[a].outer_steps = mode == LB_SOLVE_FP64 ? 0 : std::max(outer[a] - 1, 0);
       info[a].rel_resid = rel[a];
       info[a].removed_mean = removed[a];
+      info[a].t_setup = ctx->t_setup;
+      info[a].t_solve = t_solve;
     }
   }
   if (ret != LB_OK) {

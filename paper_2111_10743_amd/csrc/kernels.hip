@@ -2182,6 +2182,250 @@ void launch_msys_scale_copy(int nsys, int64_t maxlen, int j, const int64_t* xoff
   KCHECK();
 }
 
+// ---- GMRES iterations driven on the device (Section 6) -------------------
+// Every kernel reads the iteration number j from gm.iter, so one captured
+// graph of an iteration (gather, operator, CGS2, Givens, next basis vector)
+// is replayed for every j.  Systems that have stopped (gm.active[a] = 0)
+// are skipped by every kernel; their segments of the operator input are 0.
+
+// win(a) = V_j(a) for active systems, 0 otherwise
+__global__ void k_gm_gather(GmresDev gm, const double* __restrict__ V, double* __restrict__ win) {
+  const int a = blockIdx.y;
+  const int j = *gm.iter;
+  const int64_t n = gm.len[a], o = gm.xoff[a];
+  const bool act = gm.active[a] != 0;
+  const double* v = V + gm.vbase[a] + (int64_t)j * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    win[o + t] = act ? v[t] : 0.0;
+}
+
+// part[(a KM + jj) MB + bx] = this block's share of V_jj(a) . w(a) for
+// jj <= j (basis), or of w(a) . w(a) (norm, jj = 0); active systems only
+// unless `all`
+__global__ void k_gm_dots_partial(GmresDev gm, int basis, int all, const double* __restrict__ V,
+                                  const double* __restrict__ W, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int a = blockIdx.y;
+  if (!all && !gm.active[a]) return;
+  const int k = basis ? *gm.iter + 1 : 1;
+  const int64_t n = gm.len[a];
+  const double* w = W + gm.xoff[a];
+  for (int jj = 0; jj < k; ++jj) {
+    const double* v = basis ? V + gm.vbase[a] + (int64_t)jj * n : w;
+    double acc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)MSYS_BLOCKS * 256)
+      acc += v[t] * w[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((int64_t)a * gm.km + jj) * MSYS_BLOCKS + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+// sum of the partial sums (fixed order): out[a KM + jj] (basis) or out[a]
+// (norm)
+__global__ void k_gm_dots_final(GmresDev gm, int basis, int all, const double* __restrict__ part,
+                                double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)gm.ns * gm.km) return;
+  const int a = (int)(i / gm.km), jj = (int)(i % gm.km);
+  const int k = basis ? *gm.iter + 1 : 1;
+  if ((!all && !gm.active[a]) || jj >= k) return;
+  double acc = 0;
+  for (int b = 0; b < MSYS_BLOCKS; ++b) acc += part[i * MSYS_BLOCKS + b];
+  out[basis ? i : a] = acc;
+}
+
+// w(a) -= sum_{jj <= j} h[a KM + jj] V_jj(a), active systems
+__global__ void k_gm_gemv_sub(GmresDev gm, const double* __restrict__ V, const double* __restrict__ h,
+                              double* __restrict__ W) {
+  const int a = blockIdx.y;
+  if (!gm.active[a]) return;
+  const int k = *gm.iter + 1;
+  const int64_t n = gm.len[a];
+  const double* v = V + gm.vbase[a];
+  const double* ha = h + (int64_t)a * gm.km;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int jj = 0; jj < k; ++jj) acc += ha[jj] * v[(int64_t)jj * n + t];
+    W[gm.xoff[a] + t] -= acc;
+  }
+}
+
+// start: beta = |b(a)|, g_0 = beta, the first basis vector's scale, the
+// iteration counter and the number of active systems (one block)
+__global__ void k_gm_init(GmresDev gm, const int* __restrict__ skip) {
+  __shared__ int cnt[256];
+  int c = 0;
+  for (int a = threadIdx.x; a < gm.ns; a += blockDim.x) {
+    const double beta = sqrt(gm.nr[a]);
+    const bool act = !skip[a] && beta > 0.0;
+    gm.beta[a] = beta;
+    gm.g[(int64_t)a * gm.km] = beta;
+    gm.sc[a] = act ? 1.0 / beta : 0.0;
+    gm.active[a] = act ? 1 : 0;
+    gm.kdone[a] = 0;
+    gm.relres[a] = act ? 1.0 : 0.0;
+    c += act ? 1 : 0;
+  }
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *gm.iter = 0;
+    *gm.nactive = cnt[0];
+  }
+}
+
+// Givens step of iteration j for every active system (one block): the new
+// Hessenberg column h1 + h2 (two Gram-Schmidt passes) and |w|, the earlier
+// rotations applied to it, a new rotation, the residual estimate |g_{j+1}| /
+// beta, the stopping test (below tol, breakdown or the last iteration), the
+// scale of the next basis vector; then j + 1 and the active count.
+__global__ void k_gm_givens(GmresDev gm) {
+  __shared__ int cnt[256];
+  const int j = *gm.iter;
+  const int km = gm.km, mi = gm.maxit;
+  const double tol = *gm.tol;
+  int c = 0;
+  for (int a = threadIdx.x; a < gm.ns; a += blockDim.x) {
+    if (!gm.active[a]) continue;
+    const double* h1 = gm.h1 + (int64_t)a * km;
+    const double* h2 = gm.h2 + (int64_t)a * km;
+    double* R = gm.R + (int64_t)a * mi * mi;  // R[r * mi + col]
+    double* cs = gm.cs + (int64_t)a * mi;
+    double* sn = gm.sn + (int64_t)a * mi;
+    double* g = gm.g + (int64_t)a * km;
+    const double hnrm = sqrt(gm.nr[a]);
+    for (int r = 0; r <= j; ++r) R[r * mi + j] = h1[r] + h2[r];
+    double below = hnrm;  // entry j + 1 of the column
+    for (int r = 0; r < j; ++r) {
+      const double x = R[r * mi + j], y = R[(r + 1) * mi + j];
+      R[r * mi + j] = cs[r] * x + sn[r] * y;
+      R[(r + 1) * mi + j] = -sn[r] * x + cs[r] * y;
+    }
+    const double x = R[j * mi + j];
+    const double den = hypot(x, below);
+    cs[j] = x / den;
+    sn[j] = below / den;
+    R[j * mi + j] = den;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    const double rel = fabs(g[j + 1]) / gm.beta[a];
+    gm.relres[a] = rel;
+    gm.kdone[a] = j + 1;
+    const bool done = rel < tol || hnrm == 0.0 || j + 1 >= mi;
+    gm.sc[a] = done ? 0.0 : 1.0 / hnrm;
+    gm.active[a] = done ? 0 : 1;
+    c += done ? 0 : 1;
+  }
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *gm.nactive = cnt[0];
+    *gm.iter = j + 1;
+  }
+}
+
+// V_j(a) = sc[a] w(a) with j = the current counter (after the Givens step:
+// the next basis vector), systems with sc[a] != 0
+__global__ void k_gm_scale_copy(GmresDev gm, const double* __restrict__ W, double* __restrict__ V) {
+  const int a = blockIdx.y;
+  const double s = gm.sc[a];
+  if (s == 0.0) return;
+  const int j = *gm.iter;
+  const int64_t n = gm.len[a];
+  double* v = V + gm.vbase[a] + (int64_t)j * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    v[t] = s * W[gm.xoff[a] + t];
+}
+
+// y = R^{-1} g over the kdone[a] iterations of each system (one thread per
+// system), written to h1[a KM + .]
+__global__ void k_gm_backsolve(GmresDev gm) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= gm.ns) return;
+  const int k = gm.kdone[a], mi = gm.maxit;
+  const double* R = gm.R + (int64_t)a * mi * mi;
+  const double* g = gm.g + (int64_t)a * gm.km;
+  double* y = gm.h1 + (int64_t)a * gm.km;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int c = i + 1; c < k; ++c) s -= R[i * mi + c] * y[c];
+    y[i] = s / R[i * mi + i];
+  }
+}
+
+// x(a) = sum_{jj < kdone[a]} y_jj V_jj(a) (x(a) = 0 when kdone[a] = 0)
+__global__ void k_gm_solution(GmresDev gm, const double* __restrict__ V, double* __restrict__ X) {
+  const int a = blockIdx.y;
+  const int k = gm.kdone[a];
+  const int64_t n = gm.len[a];
+  const double* v = V + gm.vbase[a];
+  const double* y = gm.h1 + (int64_t)a * gm.km;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int jj = 0; jj < k; ++jj) acc += y[jj] * v[(int64_t)jj * n + t];
+    X[gm.xoff[a] + t] = acc;
+  }
+}
+
+void launch_gm_start(const GmresDev& gm, const double* B, const int* skip, double* V, hipStream_t st) {
+  const int nf = (int)(((int64_t)gm.ns * gm.km + 255) / 256);
+  hipLaunchKernelGGL(k_gm_dots_partial, dim3(MSYS_BLOCKS, gm.ns), dim3(256), 0, st, gm, 0, 1, V, B, gm.part);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_dots_final, dim3(nf), dim3(256), 0, st, gm, 0, 1, gm.part, gm.nr);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(256), 0, st, gm, skip);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_scale_copy, dim3(msys_grid_x(gm.maxlen), gm.ns), dim3(256), 0, st, gm, B, V);
+  KCHECK();
+}
+
+void launch_gm_gather(const GmresDev& gm, const double* V, double* win, hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_gather, dim3(msys_grid_x(gm.maxlen), gm.ns), dim3(256), 0, st, gm, V, win);
+  KCHECK();
+}
+
+void launch_gm_arnoldi(const GmresDev& gm, double* V, double* W, hipStream_t st) {
+  const dim3 gx(msys_grid_x(gm.maxlen), gm.ns), gd(MSYS_BLOCKS, gm.ns);
+  const int nf = (int)(((int64_t)gm.ns * gm.km + 255) / 256);
+  for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+    double* h = pass == 0 ? gm.h1 : gm.h2;
+    hipLaunchKernelGGL(k_gm_dots_partial, gd, dim3(256), 0, st, gm, 1, 0, V, W, gm.part);
+    KCHECK();
+    hipLaunchKernelGGL(k_gm_dots_final, dim3(nf), dim3(256), 0, st, gm, 1, 0, gm.part, h);
+    KCHECK();
+    hipLaunchKernelGGL(k_gm_gemv_sub, gx, dim3(256), 0, st, gm, V, h, W);
+    KCHECK();
+  }
+  hipLaunchKernelGGL(k_gm_dots_partial, gd, dim3(256), 0, st, gm, 0, 0, V, W, gm.part);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_dots_final, dim3(nf), dim3(256), 0, st, gm, 0, 0, gm.part, gm.nr);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(256), 0, st, gm);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_scale_copy, gx, dim3(256), 0, st, gm, W, V);
+  KCHECK();
+}
+
+void launch_gm_finish(const GmresDev& gm, const double* V, double* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_backsolve, dim3((gm.ns + 63) / 64), dim3(64), 0, st, gm);
+  KCHECK();
+  hipLaunchKernelGGL(k_gm_solution, dim3(msys_grid_x(gm.maxlen), gm.ns), dim3(256), 0, st, gm, V, X);
+  KCHECK();
+}
+
 // ---- per-surface reductions: surface q owns rows [off[q], off[q+1]) ----
 // out[d][q] = scale[q] * sum_{i in q} x[d][i] (w ? w[i] : 1), one block per
 // (surface, density), fixed summation order

@@ -184,6 +184,35 @@ void launch_msys_gemv(int nsys, int64_t maxlen, int k, const int64_t* xoff, cons
                       const double* V, const double* h, double sign, double* W, hipStream_t st);
 void launch_msys_scale_copy(int nsys, int64_t maxlen, int j, const int64_t* xoff, const int64_t* len,
                             const int64_t* vbase, const double* sc, const double* W, double* V, hipStream_t st);
+// GMRES (Section 6) driven on the device for ns independent systems (FP64):
+// system a owns the segment [xoff[a], xoff[a] + len[a]) of the operator's
+// vectors and the basis vectors V + vbase[a] + j len[a], j = 0..maxit.  The
+// iteration number lives in *iter, so the launches of one iteration are the
+// same for every j (one captured graph replays them all).  R [ns][maxit]
+// [maxit] holds the rotated Hessenberg matrix (R[r][c]), cs, sn [ns][maxit]
+// the rotations, g [ns][km] the rotated right-hand side (km = maxit + 1),
+// h1, h2 [ns][km] the two Gram-Schmidt passes' coefficients (h1 later y),
+// nr [ns] squared norms, part [ns][km][32] partial sums.
+struct GmresDev {
+  const int64_t *xoff = nullptr, *len = nullptr, *vbase = nullptr;
+  int *active = nullptr, *kdone = nullptr, *iter = nullptr, *nactive = nullptr;
+  double *R = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *beta = nullptr, *relres = nullptr;
+  double *sc = nullptr, *h1 = nullptr, *h2 = nullptr, *nr = nullptr, *part = nullptr;
+  const double* tol = nullptr;  // [1] relative residual target
+  int ns = 0, maxit = 0, km = 0;
+  int64_t maxlen = 1;           // largest segment (grid size)
+};
+// norms of b, beta, g_0, the active flags (skip[a] = 1: not solved), the
+// first basis vectors V_0 = b / beta, iter = 0, nactive
+void launch_gm_start(const GmresDev& gm, const double* B, const int* skip, double* V, hipStream_t st);
+// win = V_j of the active systems (0 elsewhere)
+void launch_gm_gather(const GmresDev& gm, const double* V, double* win, hipStream_t st);
+// after the operator has written W = A V_j: CGS2 against V_0..V_j, the
+// Givens step, V_{j+1} = W / |W|, iter = j + 1, nactive
+void launch_gm_arnoldi(const GmresDev& gm, double* V, double* W, hipStream_t st);
+// x(a) = V y(a) with R y = g over the iterations each system ran
+void launch_gm_finish(const GmresDev& gm, const double* V, double* X, hipStream_t st);
+
 // Per-surface reductions (surface q owns rows [off[q], off[q+1])):
 // seg_dot: out[d][q] = scale[q] sum_{i in q} x[d][i] (w ? w[i] : 1);
 // seg_axpy: y[d][i] = x[d][i] + alpha (w ? w[i] : 1) c[d][surf[i]].

@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_steps", ctypes.c_int), ("rel_resid", ctypes.c_double),
-                ("removed_mean", ctypes.c_double)]
+                ("removed_mean", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double)]
 
 
 class Sizes(ctypes.Structure):
@@ -438,7 +438,7 @@ class Surface:
         info = (SolveInfo * (nrhs * self.n_surf))()
         code = _check(lib().lb_solve_adj(self._ctx, nrhs, _ptr(ubar), _ptr(fbar), tol, mode, info, _stream()))
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
-                  "removed_mean": i.removed_mean} for i in info]
+                  "removed_mean": i.removed_mean, "t_setup": i.t_setup, "t_solve": i.t_solve} for i in info]
         return fbar, infos, code
 
     def solve(self, f, tol=1e-10, mode=LB_SOLVE_FP64):
@@ -450,7 +450,7 @@ class Surface:
         info = (SolveInfo * (nrhs * self.n_surf))()
         code = _check(lib().lb_solve(self._ctx, nrhs, _ptr(f), _ptr(u), tol, mode, info, _stream()))
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
-                  "removed_mean": i.removed_mean} for i in info]
+                  "removed_mean": i.removed_mean, "t_setup": i.t_setup, "t_solve": i.t_solve} for i in info]
         return u, infos, code
 
     def _field(self, V):
@@ -492,7 +492,7 @@ class Surface:
         code = _check(lib().lb_hodge(self._ctx, nf, _ptr(F), _ptr(alpha), _ptr(beta), _ptr(H), tol, mode, info,
                                      _stream()))
         infos = [{"iters": i.iters, "outer_steps": i.outer_steps, "rel_resid": i.rel_resid,
-                  "removed_mean": i.removed_mean} for i in info]
+                  "removed_mean": i.removed_mean, "t_setup": i.t_setup, "t_solve": i.t_solve} for i in info]
         return alpha, beta, H, infos, code
 
 
