@@ -34,11 +34,14 @@ PEAK_FP32_TFLOPS = 157.3        # FP32 vector (packed) and FP32 MFMA
 PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+CPU_POOL_MAX = 16               # worker processes of the CPU baseline (the host share of one GPU)
 
 
-def workload(name):
+def workload(name, host_nodes=False):
+    """Charts, density and description of a workload; host_nodes takes the
+    reference nodes from the oracle's node construction (equal bit for bit
+    to the library's) so that the CPU-only baseline never loads the library."""
     import lbinputs as I
-    import paper_2111_10743_amd as P
     if name == "ellipsoid5120":
         k, nsub, axes = 6, 4, (1.0, 1.5, 2.0)
     elif name == "ellipsoid1280":
@@ -47,7 +50,12 @@ def workload(name):
         k, nsub, axes = 4, 1, (1.0, 1.0, 1.0)
     else:
         raise SystemExit(f"unknown workload {name}")
-    uv, _ = P.ref_nodes(k)
+    if host_nodes:
+        from oracle.refelem import nodes
+        uv = nodes(k)
+    else:
+        import paper_2111_10743_amd as P
+        uv, _ = P.ref_nodes(k)
     X, Xu, Xv = I.ellipsoid_patches(nsub, uv, axes)
     xi = I.sphere_preimage(X.reshape(-1, 3), axes)
     coef = I.random_sh_coeffs(8, seed=1, decay=2.0)
@@ -58,31 +66,57 @@ def workload(name):
     return X, Xu, Xv, k, f, desc
 
 
+_ORC = None
+
+
+def _orc_layer(args):
+    c, f = args
+    t0 = time.perf_counter()
+    _ORC[c].layer(f)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(X, Xu, Xv, k, f, nrows):
     """The FP64 oracle's apply (far sum over all oversampled sources + near
-    corrections) on `nrows` sampled target rows, single thread."""
+    corrections, correction generation excluded) on sampled target rows:
+    `nrows` rows on one thread, then `nrows` rows per core on every host core
+    this process may use (one process per core, BLAS single-threaded)."""
+    global _ORC
+    from multiprocessing import get_context
     from threadpoolctl import threadpool_limits
     from oracle.geometry import Geometry
     from oracle.ops import Oracle
+    cores = min(len(os.sched_getaffinity(0)), CPU_POOL_MAX)
     with threadpool_limits(limits=1):
         g = Geometry(X, Xu, Xv, k)
         rows = np.linspace(0, g.N - 1, nrows).astype(np.int64)
         o = Oracle(g, rows, dense_limit=0)
         t0 = time.perf_counter()
         o.layer(f)
-        dt = time.perf_counter() - t0
-    return {"value": nrows / dt / 1e6, "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nrows} of {g.N} target rows: direct far sum over all {g.No} oversampled sources "
-                      f"+ near corrections (correction generation excluded), {dt:.2f} s"}
+        dt1 = time.perf_counter() - t0
+        allrows = np.array_split(np.linspace(0, g.N - 1, nrows * cores).astype(np.int64), cores)
+        _ORC = [Oracle(g, r, dense_limit=0) for r in allrows]   # corrections (untimed)
+    with get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        per = pool.map(_orc_layer, [(c, f) for c in range(cores)])
+        dtn = time.perf_counter() - t0
+        pool.close()
+        pool.join()
+    _ORC = None
+    return {"value": nrows * cores / dtn / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nrows} target rows per core ({nrows * cores} of {g.N}) on {cores} cores, one process "
+                      f"each: direct far sum over all {g.No} oversampled sources + near corrections (correction "
+                      f"generation excluded), {dtn:.2f} s wall (slowest core {max(per):.2f} s)",
+            "single_core": {"value": nrows / dt1 / 1e6, "unit": "Mpts/s", "cores": 1,
+                            "sample": f"{nrows} target rows, {dt1:.2f} s"},
+            "host_cores": cores}
 
 
-def measured_traffic(kernel_key):
-    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter
-    summary (profiles/<kernel>_traffic.txt: FETCH_SIZE and WRITE_SIZE KiB per
-    dispatch and their copy-kernel scale factors), or None when the kernel
-    source has changed since the counters were taken."""
+def counter_summary(name):
+    """key = value lines of a committed rocprofv3 summary (profiles/<name>.txt),
+    or None when missing or when kernels.hip changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel_key}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{name}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -92,6 +126,17 @@ def measured_traffic(kernel_key):
             kv[k.strip()] = v.strip()
     src = open(os.path.join(ROOT, "paper_2111_10743_amd", "csrc", "kernels.hip"), "rb").read()
     if kv.get("kernels_hip_sha1") != hashlib.sha1(src).hexdigest():
+        return None
+    return kv
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter
+    summary (profiles/<kernel>_traffic.txt: FETCH_SIZE and WRITE_SIZE KiB per
+    dispatch and their copy-kernel scale factors), or None when the kernel
+    source has changed since the counters were taken."""
+    kv = counter_summary(f"{kernel_key}_traffic")
+    if kv is None:
         return None
     return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"]))
 
@@ -106,10 +151,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default octree depth and leaf shape")
     ap.add_argument("--no-hodge", action="store_true", help="skip the twisted-torus Hodge decomposition")
-    ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--cpu-rows", type=int, default=24, help="oracle rows per host core in the cpu baseline")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="print the CPU baseline of the workload as JSON and exit (no GPU use); the full run "
+                         "starts itself with this flag as a child process")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.cpu_only:
+        X, Xu, Xv, k, f, _ = workload(args.workload, host_nodes=True)
+        print(json.dumps(cpu_baseline(X, Xu, Xv, k, f, args.cpu_rows)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part "
               "of this build", file=sys.stderr)
@@ -187,32 +239,42 @@ def main():
     e_pot = float((o32["pot"].double() - o64["pot"]).norm() / o64["pot"].norm())
     e_grad = float((o32["grad"].double() - o64["grad"]).norm() / o64["grad"].norm())
 
-    # roofline of the dominant phase
+    # rooflines: the dominant phase, M2L and the correction SpMV
     sz = s.sizes
-    L32 = (sz["p_f32"] + 1) ** 2
+    rf = {}
+    flops = 20.0 * sz["p2p_pairs32"]
+    ach = flops / (ph["leaf"] * 1e-3) / 1e12
+    rf["leaf"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                  "frac": ach / PEAK_FP32_TFLOPS, "traffic": measured_traffic(f"leaf_fp32_{args.workload}"),
+                  "peak_nonpacked_issue": PEAK_FP32_VALU_TFLOPS, "frac_of_nonpacked_issue": ach / PEAK_FP32_VALU_TFLOPS,
+                  "kernel": "k_leaf<float, 1, true, 0> (L2P + near field, FP32)",
+                  "algorithmic": f"20 flops per near-field pair, {sz['p2p_pairs32']} pairs per launch",
+                  "ms_per_launch": ph["leaf"]}
+    mfl = float(sz["m2l_flops32"])
+    ach = mfl / (ph["m2l"] * 1e-3) / 1e12
+    busy = counter_summary(f"m2l_fp32_{args.workload}_mfma")
+    rf["m2l"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                 "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                 "kernel": "k_gemm_grouped<float> + k_col_reduce<float> (M2L phase, FP32)",
+                 "algorithmic": f"2 L_o^2 flops per V-list pair (L_o by offset), {sz['m2l_pairs32']} pairs, "
+                                f"{mfl / 1e9:.2f} GFLOP per density",
+                 "ms_per_launch": ph["m2l"],
+                 "mfma_busy_frac": float(busy["mfma_busy_frac"]) if busy else None}
+    nnz = sz["nnz_blocks"] * sz["n_p"]
+    byts = nnz * 4 * 4 + sz["nnz_blocks"] * 4 + (N + 1) * 4 + N * 4 + N * 4 * 4
+    ach = byts / (ph["combine"] * 1e-3) / 1e9
+    rf["spmv"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(f"combine_fp32_{args.workload}"),
+                  "kernel": "k_combine_grad<float> (correction block-CSR SpMV + combine, FP32)",
+                  "algorithmic": f"nnz k b_val + blocks 4 + (N+1) 4 + N b_x + N k b_y with k=4, 4-byte values: "
+                                 f"nnz={nnz}, {byts / 1e6:.1f} MB",
+                  "ms_per_launch": ph["combine"]}
     dom = max(("m2l", "leaf", "combine"), key=lambda q: ph.get(q, 0.0))
-    if dom == "m2l":
-        flops = 2.0 * L32 * L32 * sz["m2l_pairs32"]
-        ach = flops / (ph["m2l"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_m2l (M2L, FP32)",
-                "algorithmic": f"2 L^2 flops per V-list pair, L={L32}, {sz['m2l_pairs32']} pairs"}
-    elif dom == "leaf":
-        flops = 20.0 * sz["p2p_pairs32"]
-        ach = flops / (ph["leaf"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": measured_traffic(f"leaf_fp32_{args.workload}"),
-                "peak_packed_fp32": PEAK_FP32_TFLOPS, "frac_of_packed_peak": ach / PEAK_FP32_TFLOPS,
-                "kernel": "k_leaf<float, 1, true, 0> (L2P + near field, FP32)",
-                "algorithmic": f"20 flops per near-field pair, {sz['p2p_pairs32']} pairs per launch",
-                "ms_per_launch": ph["leaf"]}
-    else:
-        nnz = sz["nnz_blocks"] * sz["n_p"]
-        byts = nnz * 4 * 4 + sz["nnz_blocks"] * 4 + (N + 1) * 8 + nnz * 4 + N * 4 * (1 + 3 + 4)
-        ach = byts / (ph["combine"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": "k_combine_grad (corrections, FP32)",
-                "algorithmic": f"block-CSR bytes, nnz={nnz}"}
+    roof = dict(rf[{"combine": "spmv"}.get(dom, dom)])
+    roof["m2l"] = rf["m2l"]
+    roof["spmv"] = rf["spmv"]
+    if dom != "leaf":
+        roof["leaf"] = rf["leaf"]
     out = {
         "metric": METRIC, "value": N / (ms32 * 1e-3) / 1e6, "unit": "Mpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True,
@@ -249,8 +311,15 @@ def main():
     if not args.no_hodge:
         out["hodge_twisted_torus"] = hodge_run(P, torch)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(X, Xu, Xv, k, f, args.cpu_rows)
-    print(json.dumps(out))
+        # in a child process that never touches the GPU (its worker pool
+        # then holds no device handles)
+        import subprocess
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only", "--workload", args.workload,
+                            "--cpu-rows", str(args.cpu_rows)], capture_output=True, text=True, timeout=600)
+        if r.returncode != 0:
+            raise SystemExit(f"cpu baseline failed:\n{r.stderr}")
+        out["cpu_baseline"] = json.loads(r.stdout.strip().splitlines()[-1])
+    print(json.dumps(out), flush=True)
 
 
 def hodge_run(P, torch, n_u=20, n_v=75, k=7):

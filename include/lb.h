@@ -116,6 +116,8 @@ typedef struct {
                                        (target box, source box) pairs, FP32 tree */
   int64_t p2p_pairs64, m2l_pairs64; /* the same for the FP64 tree               */
   int64_t n_surf;                   /* surfaces of the context (lb_setup_batch)  */
+  int64_t m2l_flops32, m2l_flops64; /* algorithmic M2L flops per density: 2 L_o^2 per
+                                       V-list pair, L_o the active size of its offset */
 } lb_sizes;
 
 /* Fill *opts with the defaults listed above. */

@@ -212,6 +212,7 @@ struct Prec {
   int build_leaf_src = 0, leaf_fmax = 64, leaf_split = 0;
   int fork_late = 0, near_grid = 0, corr_early = 0;  // overlapped-apply schedule (see DevTree)
   DBuf corr;  // early correction sums of the gradient apply [chunk][N][4]
+  double m2l_flops = 0;  // algorithmic M2L flops per density (all V-list pairs, orders by offset)
   double min_leaf_side = 0.0;
   bool direct = false;
 };
@@ -631,9 +632,15 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         for (int v = F.vlist_ptr[g]; v < F.vlist_ptr[g + 1]; ++v) trp.push_back({F.vlist_off[v], g, F.vlist_src[v]});
       }
       P.m2l_pb.reset(new PlanBuf());
-      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb, P.L,
-                                             m2l_orders(p, sizeof(T) == 4 ? ctx->opts.m2l_trunc32
-                                                                          : ctx->opts.m2l_trunc64)));
+      const std::vector<int> lo = m2l_orders(p, sizeof(T) == 4 ? ctx->opts.m2l_trunc32 : ctx->opts.m2l_trunc64);
+      // algorithmic M2L work per density: a pair at offset o multiplies its
+      // leading lo[o] coefficients by the leading lo[o] x lo[o] block
+      P.m2l_flops = 0;
+      for (const Triple& q : trp) {
+        const double l = lo.empty() ? P.L : lo[q.mat];
+        P.m2l_flops += 2.0 * l * l;
+      }
+      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb, P.L, lo));
     }
     P.m2m_pb.clear();
     P.l2l_pb.clear();
@@ -1857,6 +1864,8 @@ lb_status lb_get_sizes(const lb_ctx* ctx, lb_sizes* s) {
     count(ctx->f32.trees, s->p2p_pairs32, s->m2l_pairs32);
     count(ctx->f64.trees, s->p2p_pairs64, s->m2l_pairs64);
   }
+  s->m2l_flops32 = (int64_t)ctx->f32.m2l_flops;
+  s->m2l_flops64 = (int64_t)ctx->f64.m2l_flops;
   API_END
 }
 

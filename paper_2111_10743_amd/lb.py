@@ -58,7 +58,7 @@ class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_patches", "n_p", "N", "n_o", "N_o", "nnz_blocks",
                                                "fmm_levels", "fmm_leaves", "p_f32", "p_f64",
                                                "p2p_pairs32", "m2l_pairs32", "p2p_pairs64", "m2l_pairs64",
-                                               "n_surf")]
+                                               "n_surf", "m2l_flops32", "m2l_flops64")]
 
 
 class TreeInfo(ctypes.Structure):
