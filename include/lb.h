@@ -76,7 +76,8 @@ typedef struct lb_ctx lb_ctx;   /* opaque: owns host and device state */
 
 typedef struct {
   double eta_near;  /* Near(x_i) = { l : |x_i - c_l| < eta_near * R_l }      (default 2)  */
-  int over_q;       /* oversampled far rule: q x q conical Gauss points       (default k+6)*/
+  int over_q;       /* oversampled far rule of the FP64 path: q x q conical Gauss points
+                       (default k+6)                                                   */
   int p_f32;        /* FMM expansion order of the FP32 path                   (default 14) */
   int p_f64;        /* FMM expansion order of the FP64 path                   (default 28) */
   int leaf_src;     /* target mean number of sources per FMM leaf box         (default 1024)*/
@@ -92,6 +93,9 @@ typedef struct {
                          a = sqrt(3)/2, s this factor; 0: order p for every offset
                          (default 2.5) */
   double m2l_trunc64; /* the same for the FP64 tree (default 2.0) */
+  int over_q32;     /* far rule of the FP32 path: q x q conical Gauss points (default
+                       max(k+2, 6): it changes the operator by 7.5e-9 (k = 6) .. 1.4e-7
+                       (k = 4) against the k+6 rule, at or below FP32 rounding) */
 } lb_opts;
 
 typedef struct {
@@ -118,6 +122,8 @@ typedef struct {
   int64_t n_surf;                   /* surfaces of the context (lb_setup_batch)  */
   int64_t m2l_flops32, m2l_flops64; /* algorithmic M2L flops per density: 2 L_o^2 per
                                        V-list pair, L_o the active size of its offset */
+  int64_t n_o32, N_o32;             /* oversampled points per patch, in total, of the
+                                       FP32 far rule (n_o, N_o: the FP64 one)      */
 } lb_sizes;
 
 /* Fill *opts with the defaults listed above. */

@@ -183,6 +183,8 @@ struct OpGraph {
 template <typename T>
 struct Prec {
   int p = 0, L = 0;
+  int n_o = 0;      // oversampled points per patch of this precision's far rule
+  int64_t No = 0;   // oversampled points in total
   std::vector<Octree> trees;  // one per surface
   DevTree<T> dt{};
   DBuf tx, ty, tz, tnx, tny, tnz, sx, sy, sz, snx, sny, snz, rm2, trm2, bcx, bcy, bcz;
@@ -231,7 +233,8 @@ struct lb_ctx {
   std::vector<double> surf_area;
   int64_t N = 0, No = 0;
   lb_opts opts{};
-  std::unique_ptr<RefElem> re;
+  std::unique_ptr<RefElem> re;    // order k, the FP64 far rule (q = over_q)
+  std::unique_ptr<RefElem> re32;  // order k, the FP32 far rule (q = over_q32)
   Surface S;
   std::vector<double> C64;  // [nnzb][n_p][6]
   bool host_only = false;
@@ -295,6 +298,7 @@ namespace lb {
 static void default_opts(lb_opts* o) {
   o->eta_near = 2.0;
   o->over_q = 0;
+  o->over_q32 = 0;
   o->p_f32 = 14;
   o->p_f64 = 28;
   o->leaf_src = 1024;
@@ -474,6 +478,24 @@ static void make_leaf_work(Prec<T>& P, int fmax, int split) {
   P.dt.leaf_fmax = fmax;
 }
 
+// The far rule of a precision: FP64 the surface's primary rule, FP32 its own
+// (coarser) one; the transposed trees use their forward precision's.
+struct OverView {
+  int n_o;
+  int64_t No;
+  const std::vector<double>* s;
+  const std::vector<double>* nu;
+  const std::vector<double>* wo;
+  const std::vector<double>* P;
+};
+template <typename T>
+static OverView over_view(const lb_ctx* ctx) {
+  const Surface& S = ctx->S;
+  if (sizeof(T) == 4)
+    return {S.o32.n_o, S.o32.No, &S.o32.s, &S.o32.nu, &S.o32.wo, &S.o32.re->P};
+  return {S.n_o, S.No, &S.s, &S.nu, &S.wo, &ctx->re->P};
+}
+
 // Device state of one precision: one octree per surface, merged into a
 // forest.  With `fwd` set, the transposed problem of the adjoint applies:
 // the Nystrom nodes are the sources and the oversampled points the targets
@@ -487,21 +509,24 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
                        DBuf* dev_v4 = nullptr, DBuf* dev_v3 = nullptr) {
   const Surface& S = ctx->S;
   const bool adj = fwd != nullptr;
+  const OverView ov = over_view<T>(ctx);
   P.p = p;
   P.L = (p + 1) * (p + 1);
+  P.n_o = ov.n_o;
+  P.No = ov.No;
   P.build_leaf_src = leaf_src;
   P.min_leaf_side = min_leaf_side;
   P.direct = direct;
   // (X, nrm) are the nodes, (s, nu) the oversampled points
-  const std::vector<double>& TX = adj ? S.s : S.X;
-  const std::vector<double>& TN = adj ? S.nu : S.nrm;
-  const std::vector<double>& SX = adj ? S.X : S.s;
-  const std::vector<double>& SN = adj ? S.nrm : S.nu;
-  const int64_t N = adj ? S.No : S.N, No = adj ? S.N : S.No;  // targets, sources of these trees
+  const std::vector<double>& TX = adj ? *ov.s : S.X;
+  const std::vector<double>& TN = adj ? *ov.nu : S.nrm;
+  const std::vector<double>& SX = adj ? S.X : *ov.s;
+  const std::vector<double>& SN = adj ? S.nrm : *ov.nu;
+  const int64_t N = adj ? ov.No : S.N, No = adj ? S.N : ov.No;  // targets, sources of these trees
   const int ns = ctx->n_surf;
   std::vector<int64_t> toff(ns + 1), soff(ns + 1);
   for (int q = 0; q <= ns; ++q) {
-    const int64_t pn = (int64_t)ctx->surf_patch[q] * ctx->n_p, po = (int64_t)ctx->surf_patch[q] * ctx->n_o;
+    const int64_t pn = (int64_t)ctx->surf_patch[q] * ctx->n_p, po = (int64_t)ctx->surf_patch[q] * ov.n_o;
     toff[q] = adj ? po : pn;
     soff[q] = adj ? pn : po;
   }
@@ -593,8 +618,8 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   // (dev_v4, dev_v3: corrections already on the device in the packed
   // layouts, taken over)
   if (!adj && (!C.empty() || dev_v4)) {
-    upload_as<T>(P.P, ctx->re->P);
-    upload_as<T>(P.wo, S.wo);
+    upload_as<T>(P.P, *ov.P);
+    upload_as<T>(P.wo, *ov.wo);
     upload_as<T>(P.nrm, S.nrm);
     upload_as<T>(P.H, S.H);
     if (dev_v4) {
@@ -750,7 +775,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
 template <typename T>
 static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   if (P.ws_rhs >= chunk) return;
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = P.No;
   const int nb = P.dt.nbox;
   const int L = P.L, p = P.p;
   P.str.alloc(sizeof(T) * (size_t)No * 2 * chunk);
@@ -783,7 +808,7 @@ struct ApplyWs {
 template <typename T>
 static void ws_counts(const lb_ctx* ctx, const Prec<T>& P, int chunk, size_t cnt[6]) {
   const int p = P.p;
-  cnt[0] = (size_t)ctx->No * 2 * chunk;
+  cnt[0] = (size_t)P.No * 2 * chunk;
   cnt[1] = (size_t)P.dt.nbox * 3 * chunk * P.L;
   cnt[2] = cnt[1];
   cnt[3] = (size_t)std::max(P.dt.n_leaf_work, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1));
@@ -809,7 +834,7 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
     ensure_ws(ctx, P, CHUNK_GRAD);
     W = ctx_ws(P);
   }
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = P.No;
   // corr_early: the correction sums need only sigma, so they run first on
   // the side stream (ahead of the near field, which launch_fmm forks there
   // and joins back), and a light final step adds the far sums
@@ -823,7 +848,7 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
                           sigma + (int64_t)d0 * N, W.corr, P.dt.side);
     }
     if (tm) tm->mark(PH_STR, st);
-    launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
+    launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo),
                         dptr<int>(P.src_pos), No, W.str, st);
     if (tm) tm->mark(PH_P2M, st);
     launch_fmm<T>(P.dt, FMM_GRAD, c, W.str, W.M, W.Lc, W.D, W.fmm, N, No, st, tm);
@@ -846,10 +871,10 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
 template <typename T>
 static void apply_S_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, hipStream_t st) {
   ensure_ws(ctx, P, CHUNK_GRAD);
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = P.No;
   for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
     const int c = std::min(CHUNK_GRAD, nd - d0);
-    launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo),
+    launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo),
                         dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
     launch_fmm<T>(P.dt, FMM_POT, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No,
                   st);
@@ -865,17 +890,17 @@ constexpr int CHUNK_A3 = 2;
 template <typename T>
 static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
   ensure_ws(ctx, P, CHUNK_GRAD);
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = P.No;
   T* mu = dptr<T>(P.mu);  // [c][mu1; mu2]
   for (int d0 = 0; d0 < nd; d0 += CHUNK_A3) {
     const int c = std::min(CHUNK_A3, nd - d0);
     const T* td = tau + (int64_t)d0 * N;
-    launch_strengths<T>(td, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+    launch_strengths<T>(td, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
                         dptr<T>(P.str), st);
     launch_fmm<T>(P.dt, FMM_GRAD, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
     launch_combine_a3a<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td,
                           dptr<T>(P.fmm), dptr<int>(P.tgt_pos), dptr<T>(P.nrm), mu, mu + N, 2 * N, st);
-    launch_strengths<T>(mu, 2 * c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos),
+    launch_strengths<T>(mu, 2 * c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos),
                         No, dptr<T>(P.str), st);
     launch_fmm<T>(P.dt, FMM_A3B, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
     launch_combine_a3b<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3), td, mu,
@@ -955,7 +980,7 @@ static void ensure_adjoint(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built) {
   A.M.alloc(sizeof(T) * (size_t)nb * c * L);
   A.Lc.alloc(sizeof(T) * (size_t)nb * c * L);
   A.D.alloc(sizeof(T) * (size_t)std::max(A.dt.n_leaf_work, 1) * c * (3 * p * p + 9 * (p - 1) * (p - 1)));
-  A.fmm.alloc(sizeof(T) * (size_t)ctx->No * c);
+  A.fmm.alloc(sizeof(T) * (size_t)F.No * c);
   HIPTRY(hipDeviceSynchronize());
   built = true;
 }
@@ -964,7 +989,7 @@ template <typename T>
 static void apply_adj_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int nd, const T* gpot, const T* ggrad,
                         const T* gdSdn, const T* gsurf, T* sbar, hipStream_t st) {
   ensure_adjoint<T>(ctx, F, A, built);
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = F.No;
   ctx->g4.alloc(sizeof(T) * (size_t)N * 4 * CHUNK_GRAD);
   for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
     const int c = std::min(CHUNK_GRAD, nd - d0);
@@ -974,7 +999,7 @@ static void apply_adj_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int nd
     // transposed tree: targets are the No oversampled points, sources the N nodes
     launch_fmm<T>(A.dt, FMM_ADJ, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
                   N, st);
-    launch_adj_combine<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
+    launch_adj_combine<T>(c, ctx->NP, ctx->n_p, F.n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
                           dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
                           dptr<int64_t>(ctx->cblk), dptr<T>(F.vals4), dptr<T>(ctx->g4), sbar + (int64_t)d0 * N, st);
   }
@@ -992,7 +1017,7 @@ static void apply_S_xbar_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int
                            T* xbar, hipStream_t st) {
   ensure_ws(ctx, F, CHUNK_GRAD);
   ensure_adjoint<T>(ctx, F, A, built);
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = F.No;
   if (!F.rm2_none.p) {
     upload(F.rm2_none, std::vector<T>((size_t)No, std::numeric_limits<T>::min()));
     A.fmm4.alloc(sizeof(T) * (size_t)No * 4 * CHUNK_GRAD);
@@ -1004,7 +1029,7 @@ static void apply_S_xbar_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int
     const int c = std::min(CHUNK_GRAD, nd - d0);
     const T* sd = sigma + (int64_t)d0 * N;
     const T* gd = gbar + (int64_t)d0 * N;
-    launch_strengths<T>(sd, c, N, ctx->NP, ctx->n_p, ctx->n_o, dptr<T>(F.P), dptr<T>(F.wo), dptr<int>(F.src_pos), No,
+    launch_strengths<T>(sd, c, N, ctx->NP, ctx->n_p, F.n_o, dptr<T>(F.P), dptr<T>(F.wo), dptr<int>(F.src_pos), No,
                         dptr<T>(F.str), st);
     launch_fmm<T>(Fu, FMM_GRAD, c, dptr<T>(F.str), dptr<T>(F.M), dptr<T>(F.Lc), dptr<T>(F.D), dptr<T>(F.fmm), N, No,
                   st);
@@ -1012,7 +1037,7 @@ static void apply_S_xbar_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, int
     launch_scatter_perm<T>(c, N, gd, dptr<int>(A.src_pos), dptr<T>(A.str), st);
     launch_fmm<T>(A.dt, FMM_GRAD, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm4), No,
                   N, st);
-    launch_xbar_S<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.str), dptr<int>(F.src_pos),
+    launch_xbar_S<T>(c, ctx->NP, ctx->n_p, F.n_o, N, No, dptr<T>(F.P), dptr<T>(F.str), dptr<int>(F.src_pos),
                      dptr<T>(F.fmm), dptr<int>(F.tgt_pos), gd, dptr<T>(A.fmm4), dptr<int>(A.tgt_pos), xbar, st);
   }
 }
@@ -1207,7 +1232,7 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
                         const T* v, T* out, hipStream_t st) {
   ensure_ws(ctx, F, CHUNK_GRAD);  // allocates ctx->partial (column sums below)
   ensure_adjoint<T>(ctx, F, A, built);
-  const int64_t N = ctx->N, No = ctx->No;
+  const int64_t N = ctx->N, No = F.No;
   if (!zbuilt) {
     DBuf wt, z1;
     wt.alloc(sizeof(T) * N);
@@ -1233,7 +1258,7 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
     launch_adj3_str1<T>(c, N, vd, dptr<T>(F.H), dptr<int>(A.src_pos), dptr<T>(A.str), g2, st);
     launch_fmm<T>(A.dt, FMM_ADJ3, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
                   N, st);
-    launch_adj3_comb1<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
+    launch_adj3_comb1<T>(c, ctx->NP, ctx->n_p, F.n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
                          dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
                          dptr<int64_t>(ctx->cblk), dptr<T>(F.vals3), g2, a, b, st);
     launch_seg_dot<T>(c, ctx->n_surf, N, dptr<int64_t>(ctx->node_off), vd, nullptr, dptr<double>(ctx->inv_area),
@@ -1241,7 +1266,7 @@ static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& 
     launch_adj3_str2<T>(c, N, a, b, dptr<T>(F.nrm), dptr<int>(A.src_pos), dptr<T>(A.str), g2, st);
     launch_fmm<T>(A.dt, FMM_ADJ, c, dptr<T>(A.str), dptr<T>(A.M), dptr<T>(A.Lc), dptr<T>(A.D), dptr<T>(A.fmm), No,
                   N, st);
-    launch_adj3_comb2<T>(c, ctx->NP, ctx->n_p, ctx->n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
+    launch_adj3_comb2<T>(c, ctx->NP, ctx->n_p, F.n_o, N, No, dptr<T>(F.P), dptr<T>(F.wo), dptr<T>(A.fmm),
                          dptr<int>(A.tgt_pos), dptr<int64_t>(ctx->cptr), dptr<int>(ctx->crow),
                          dptr<int64_t>(ctx->cblk), dptr<T>(F.vals3), g2, vd, dptr<T>(zb),
                          dptr<double>(ctx->a3t_scal), ctx->n_surf, dptr<int>(ctx->node_surf), out + (int64_t)d0 * N,
@@ -1676,13 +1701,24 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
   out.v3_64.alloc(sizeof(double) * ne * 3);
   out.v4_32.alloc(sizeof(float) * ne * 4);
   out.v3_32.alloc(sizeof(float) * ne * 3);
+  // FP64 values from the primary far rule
   FarRuleArgs fr;
   fr.X = sq.X; fr.nrm = sq.nrm; fr.s = dptr<double>(ds); fr.nu = dptr<double>(dnu); fr.wo = dptr<double>(dwo);
-  fr.rm2 = dptr<float>(drm2); fr.P = dptr<double>(dP);
+  fr.rm2 = nullptr; fr.P = dptr<double>(dP);
   fr.brow = dptr<int64_t>(dbrow); fr.patch = dptr<int32_t>(dnp); fr.A = sq.A;
   fr.v4_64 = dptr<double>(out.v4_64); fr.v3_64 = dptr<double>(out.v3_64);
-  fr.v4_32 = dptr<float>(out.v4_32); fr.v3_32 = dptr<float>(out.v3_32);
+  fr.v4_32 = nullptr; fr.v3_32 = nullptr;
   fr.nb = nb; fr.n_p = n_p; fr.n_o = S.n_o;
+  HIPTRY(launch_far_rule(fr, nullptr));
+  // FP32 values from the FP32 far rule, without the points its near-field
+  // kernel skips
+  DBuf ds32, dnu32, dwo32, dP32;
+  upload(ds32, S.o32.s); upload(dnu32, S.o32.nu); upload(dwo32, S.o32.wo); upload(dP32, S.o32.re->P);
+  fr.s = dptr<double>(ds32); fr.nu = dptr<double>(dnu32); fr.wo = dptr<double>(dwo32); fr.P = dptr<double>(dP32);
+  fr.rm2 = dptr<float>(drm2);
+  fr.v4_64 = nullptr; fr.v3_64 = nullptr;
+  fr.v4_32 = dptr<float>(out.v4_32); fr.v3_32 = dptr<float>(out.v3_32);
+  fr.n_o = S.o32.n_o;
   HIPTRY(launch_far_rule(fr, nullptr));
   HIPTRY(hipDeviceSynchronize());
 }
@@ -1702,6 +1738,8 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   if (opts) ctx->opts = *opts; else default_opts(&ctx->opts);
   lb_opts& o = ctx->opts;
   if (o.over_q <= 0) o.over_q = order + 6;
+  if (o.over_q32 <= 0) o.over_q32 = std::max(order + 2, 6);
+  if (o.over_q > 40 || o.over_q32 > 40) fail(LB_EINVAL, "over_q / over_q32 must be <= 40");
   if (o.eta_near <= 1.0) fail(LB_EINVAL, "eta_near must be > 1");
   if (o.p_f32 < 2 || o.p_f32 > 31 || o.p_f64 < 2 || o.p_f64 > 31) fail(LB_EINVAL, "expansion order out of range 2..31");
   if (o.max_iter < 1) fail(LB_EINVAL, "max_iter must be >= 1");
@@ -1712,8 +1750,10 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   ctx->k = order;
   ctx->n_surf = n_surf;
   ctx->re.reset(new RefElem(order, o.over_q));
+  ctx->re32.reset(new RefElem(order, o.over_q32));
   Surface& S = ctx->S;
   S.build(*ctx->re, n_patches, X, Xu, Xv, o.eta_near);
+  S.build_over(*ctx->re32, S.o32);
   S.surf_of_patch.resize(n_patches);
   for (int q = 0; q < n_surf; ++q)
     for (int pt = ctx->surf_patch[q]; pt < ctx->surf_patch[q + 1]; ++pt) S.surf_of_patch[pt] = q;
@@ -1760,10 +1800,10 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
     // of a target are left to the corrections (such a patch is always in
     // Near(target), since |x - c_l| < (1 + (eta-1)) R_l)
     const double kMaskFrac = 0.5;
-    std::vector<float> rm2(S.No);
+    std::vector<float> rm2(S.o32.No);
     double rmax = 0;
-    for (int64_t m = 0; m < S.No; ++m) {
-      double rm = kMaskFrac * (o.eta_near - 1.0) * S.R[m / S.n_o];
+    for (int64_t m = 0; m < S.o32.No; ++m) {
+      double rm = kMaskFrac * (o.eta_near - 1.0) * S.R[m / S.o32.n_o];
       rm2[m] = (float)(rm * rm);
       rmax = std::max(rmax, rm);
     }
@@ -1772,11 +1812,11 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
     if (dev_quad) {
       corrections_device(S, *ctx->re, qo, rm2, dc);
     } else {
-      std::vector<float> tx32(3 * S.N), sx32(3 * S.No);
+      std::vector<float> tx32(3 * S.N), sx32(3 * S.o32.No);
       for (int64_t i = 0; i < 3 * S.N; ++i) tx32[i] = (float)S.X[i];
-      for (int64_t i = 0; i < 3 * S.No; ++i) sx32[i] = (float)S.s[i];
+      for (int64_t i = 0; i < 3 * S.o32.No; ++i) sx32[i] = (float)S.o32.s[i];
       std::vector<double> B32;
-      far_rule_blocks(S, rm2, tx32, sx32, true, B32);
+      far_rule_blocks(S, rm2, tx32, sx32, true, B32, &S.o32);
       C32.resize(A.size());
       for (size_t i = 0; i < A.size(); ++i) C32[i] = A[i] - B32[i];
     }
@@ -1839,6 +1879,8 @@ lb_status lb_get_sizes(const lb_ctx* ctx, lb_sizes* s) {
   s->N = ctx->N;
   s->n_o = ctx->n_o;
   s->N_o = ctx->No;
+  s->n_o32 = ctx->S.o32.n_o;
+  s->N_o32 = ctx->S.o32.No;
   s->nnz_blocks = ctx->S.near_ptr.empty() ? 0 : ctx->S.near_ptr.back();
   s->fmm_levels = 0;
   if (!ctx->host_only)

@@ -359,7 +359,9 @@ hipError_t launch_self_quad(const SelfQuadArgs& q, hipStream_t st);
 // C = A - B of every block (eq. nys-lcq) in the packed layouts of the
 // combine kernels, for FP64 (B over every oversampled point of the patch)
 // and FP32 (B without the points that the float32 near-field kernel skips:
-// float r^2 below rm2 of the point).
+// float r^2 below rm2 of the point).  Either pair of outputs may be null
+// (the FP32 values then need no rm2), so that the two precisions can use
+// far rules of their own (two launches).
 struct FarRuleArgs {
   const double* X = nullptr;    // [N][3]
   const double* nrm = nullptr;  // [N][3]

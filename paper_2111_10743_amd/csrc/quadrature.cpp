@@ -259,11 +259,14 @@ void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A
 
 void far_rule_blocks(const Surface& S, const std::vector<float>& rm2_f32,
                      const std::vector<float>& tx32, const std::vector<float>& sx32,
-                     bool fp32_mask, std::vector<double>& B) {
-  const int n_p = S.n_p, n_o = S.n_o;
+                     bool fp32_mask, std::vector<double>& B, const OverRule* over) {
+  const int n_p = S.n_p, n_o = over ? over->n_o : S.n_o;
   const int64_t nb = S.near_ptr[S.N];
   B.assign((size_t)nb * n_p * 6, 0.0);
-  const std::vector<double>& P = S.re->P;
+  const std::vector<double>& P = over ? over->re->P : S.re->P;
+  const std::vector<double>& Ss = over ? over->s : S.s;
+  const std::vector<double>& Snu = over ? over->nu : S.nu;
+  const std::vector<double>& Swo = over ? over->wo : S.wo;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < S.N; ++i) {
     const double* x = &S.X[3 * i];
@@ -282,8 +285,8 @@ void far_rule_blocks(const Surface& S, const std::vector<float>& rm2_f32,
           if (r2 < rm2_f32[sm]) continue;
         }
         double kv[6];
-        kernel6(x, n, &S.s[3 * sm], &S.nu[3 * sm], kv);
-        const double wm = S.wo[sm];
+        kernel6(x, n, &Ss[3 * sm], &Snu[3 * sm], kv);
+        const double wm = Swo[sm];
         for (int t = 0; t < 6; ++t) kv[t] *= wm;
         const double* Pm = &P[(size_t)m * n_p];
         for (int k = 0; k < n_p; ++k)

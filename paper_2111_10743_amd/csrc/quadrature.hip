@@ -450,7 +450,7 @@ __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
       // the float32 near-field kernel's test, in its arithmetic
       const float dx = __fsub_rn(tx, (float)y0), dy = __fsub_rn(ty, (float)y1), dz = __fsub_rn(tz, (float)y2);
       const float fr2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
-      masked = fr2 < q.rm2[sm];
+      masked = q.rm2 ? fr2 < q.rm2[sm] : false;
     }
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
@@ -486,13 +486,13 @@ __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
       const float c32 = (float)(a - b32[j]);
       const int64_t e = b * n_p + k;
       if (t < 4) {
-        q.v4_64[4 * e + t] = c64;
-        q.v4_32[4 * e + t] = c32;
+        if (q.v4_64) q.v4_64[4 * e + t] = c64;
+        if (q.v4_32) q.v4_32[4 * e + t] = c32;
       }
       if (t == 0 || t >= 4) {
         const int u = t == 0 ? 0 : t - 3;
-        q.v3_64[3 * e + u] = c64;
-        q.v3_32[3 * e + u] = c32;
+        if (q.v3_64) q.v3_64[3 * e + u] = c64;
+        if (q.v3_32) q.v3_32[3 * e + u] = c32;
       }
     }
   }

@@ -57,6 +57,45 @@ void Surface::dchart(int p, double u, double v, double* K, double* du, double* d
   dv[0] = v0; dv[1] = v1; dv[2] = v2;
 }
 
+void Surface::build_over(const RefElem& reo, OverRule& out) const {
+  out.re = &reo;
+  out.n_o = reo.n_o;
+  out.No = (int64_t)NP * reo.n_o;
+  out.s.assign(3 * out.No, 0.0);
+  out.nu.assign(3 * out.No, 0.0);
+  out.wo.assign(out.No, 0.0);
+  int bad = -1;
+#pragma omp parallel for schedule(static)
+  for (int p = 0; p < NP; ++p) {
+    const int64_t o = (int64_t)p * n_p, oo = (int64_t)p * reo.n_o;
+    for (int m = 0; m < reo.n_o; ++m) {
+      double xs[3] = {0, 0, 0}, su[3] = {0, 0, 0}, sv[3] = {0, 0, 0};
+      for (int b = 0; b < n_p; ++b) {
+        const double pw = reo.P[m * n_p + b];
+        for (int d = 0; d < 3; ++d) {
+          xs[d] += pw * X[3 * (o + b) + d];
+          su[d] += pw * Xu[3 * (o + b) + d];
+          sv[d] += pw * Xv[3 * (o + b) + d];
+        }
+      }
+      double c[3];
+      cross3(su, sv, c);
+      double j = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+      if (!(j > 0.0)) {
+#pragma omp critical
+        bad = p;
+        j = 1.0;
+      }
+      for (int d = 0; d < 3; ++d) {
+        out.s[3 * (oo + m) + d] = xs[d];
+        out.nu[3 * (oo + m) + d] = c[d] / j;
+      }
+      out.wo[oo + m] = j * reo.over_w[m];
+    }
+  }
+  if (bad >= 0) fail(LB_EGEOM, "degenerate patch %d (zero Jacobian)", bad);
+}
+
 void Surface::build(const RefElem& re_, int NP_, const double* X_, const double* Xu_,
                     const double* Xv_, double eta_) {
   re = &re_;

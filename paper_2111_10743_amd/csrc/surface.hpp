@@ -18,6 +18,16 @@ struct QuadOpts {
   int max_depth = 16;
 };
 
+// An oversampled far rule on every patch (Section 4: the q x q conical
+// Gauss points of the reference element mapped by the interpolated chart):
+// positions, unit normals and weights, patch-major.
+struct OverRule {
+  const RefElem* re = nullptr;  // the reference element holding P and the rule
+  int n_o = 0;
+  int64_t No = 0;
+  std::vector<double> s, nu, wo;  // [No][3], [No][3], [No]
+};
+
 struct Surface {
   const RefElem* re = nullptr;
   int NP = 0, n_p = 0, n_o = 0;
@@ -32,8 +42,10 @@ struct Surface {
   // modal coefficients of the derivatives of the interpolated X (the
   // polynomials dXu, dXv of degree k - 1): [NP][n_p][3]
   std::vector<double> cDu, cDv;
-  // oversampled far rule
+  // oversampled far rule (the primary one: FP64 path, patch radii)
   std::vector<double> s, nu, wo;          // [No][3], [No][3], [No]
+  // the FP32 path's own far rule (build_over)
+  OverRule o32;
   // patches
   std::vector<double> cen, R;             // [NP][3], [NP]
   double eta = 2.0;
@@ -49,6 +61,9 @@ struct Surface {
   // Chart at param (u, v) of patch p: position, interpolated X_u, X_v and the
   // basis values K (modal), n_p of them.
   void chart(int p, double u, double v, double* K, double* x, double* xu, double* xv) const;
+  // A second far rule (for instance a coarser one for the FP32 path) from
+  // the same chart samples; the primary rule above sets the patch radii.
+  void build_over(const RefElem& reo, OverRule& out) const;
   // Derivatives of the interpolated X (not the interpolated X_u, X_v) at
   // param (u, v) of patch p; K is basis scratch of n_p values.
   void dchart(int p, double u, double v, double* K, double* du, double* dv) const;
@@ -68,8 +83,10 @@ void near_leaf_rule(int q, std::vector<double>& ru, std::vector<double>& rw);
 // oversampled sources whose float32 squared distance to the target is below
 // the float32 mask radius squared of the source (the FP32 near-field kernel
 // skips exactly these pairs) are left out.
+// `over` (nullable): the far rule to use instead of the surface's primary one
+// (rm2_f32 and sx32 then index its points).
 void far_rule_blocks(const Surface& S, const std::vector<float>& rm2_f32,
                      const std::vector<float>& tx32, const std::vector<float>& sx32,
-                     bool fp32_mask, std::vector<double>& B);
+                     bool fp32_mask, std::vector<double>& B, const OverRule* over = nullptr);
 
 }  // namespace lb

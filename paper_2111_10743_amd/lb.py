@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("eta_near", ctypes.c_double), ("over_q", ctypes.c_int), ("p_f32", ctypes.c_int),
                 ("p_f64", ctypes.c_int), ("leaf_src", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("flags", ctypes.c_int), ("self_n", ctypes.c_int), ("near_q", ctypes.c_int),
-                ("near_adm", ctypes.c_double), ("m2l_trunc32", ctypes.c_double), ("m2l_trunc64", ctypes.c_double)]
+                ("near_adm", ctypes.c_double), ("m2l_trunc32", ctypes.c_double), ("m2l_trunc64", ctypes.c_double),
+                ("over_q32", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -58,7 +59,7 @@ class Sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_patches", "n_p", "N", "n_o", "N_o", "nnz_blocks",
                                                "fmm_levels", "fmm_leaves", "p_f32", "p_f64",
                                                "p2p_pairs32", "m2l_pairs32", "p2p_pairs64", "m2l_pairs64",
-                                               "n_surf", "m2l_flops32", "m2l_flops64")]
+                                               "n_surf", "m2l_flops32", "m2l_flops64", "n_o32", "N_o32")]
 
 
 class TreeInfo(ctypes.Structure):
@@ -242,11 +243,16 @@ class Surface:
             _check(lib().lb_setup_batch(ctypes.byref(self._ctx), len(pps),
                                         pps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), order, _dp(X), _dp(Xu),
                                         _dp(Xv), ctypes.byref(o), stream))
+        sz = self.sizes
+        self.N = sz["N"]
+        self.n_surf = sz["n_surf"]
+
+    @property
+    def sizes(self):
+        """lb_get_sizes (queried on each access: tuning rebuilds the trees)."""
         s = Sizes()
         _check(lib().lb_get_sizes(self._ctx, ctypes.byref(s)))
-        self.sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
-        self.N = s.N
-        self.n_surf = s.n_surf
+        return {f: getattr(s, f) for f, _ in Sizes._fields_}
 
     def close(self):
         if self._ctx:
@@ -277,9 +283,10 @@ class Surface:
 
     def tree(self, prec=32, transposed=False, surf=0, counts=None):
         """The FMM octree of one surface (see lb_get_tree in include/lb.h) as
-        numpy arrays; counts = (nodes, oversampled points) of that surface
-        (default: the whole context, right for one surface)."""
-        nn, no = counts if counts is not None else (self.N, self.sizes["N_o"])
+        numpy arrays; counts = (nodes, oversampled points of that precision's
+        far rule) of that surface (default: the whole context, right for one
+        surface)."""
+        nn, no = counts if counts is not None else (self.N, self.sizes["N_o32" if prec == 32 else "N_o"])
         nt, ns = (no, nn) if transposed else (nn, no)
         return _tree_arrays(lambda *a: lib().lb_get_tree(self._ctx, prec, int(transposed), surf, *a), nt, ns)
 

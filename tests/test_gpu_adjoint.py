@@ -237,13 +237,22 @@ def test_autograd_solve_fd(torch_dev):
 @pytest.mark.parametrize("prec", [64, 32])
 def test_c1_position_vjp_vs_oracle(torch_dev, c1_oracle, direct, prec):
     """Kernel-position derivative of S (lb_apply_S_adj_X) against the
-    oracle's, two densities summed.  FP32 sums every pair without the near
+    oracle's, two densities summed.  The derivative moves the far rule's
+    points with the nodes, unmasked, so it is that of each precision's own
+    rule: the FP32 path's (max(k+2, 6) = 6 points per direction) is compared
+    with the oracle on that rule.  FP32 sums every pair without the near
     mask, so terms up to 1/r^2 of the closest node/point pairs enter the
-    FP32 sums: 1e-5 relative L2."""
+    FP32 sums (the coarser FP32 rule has pairs closer than the FP64 one):
+    1e-4 relative L2 (measured 2e-5)."""
     torch = torch_dev
     import paper_2111_10743_amd as P
     o = c1_oracle
     g = o.g
+    if prec == 32:
+        from oracle.geometry import Geometry
+        from oracle.ops import Oracle
+        o = Oracle(Geometry(g.Xp, g.Xup, g.Xvp, 4, q=6))
+        g = o.g
     note(f"c1 position vjp direct={direct} prec={prec} setup")
     s = P.Surface(g.Xp, g.Xup, g.Xvp, 4, direct=direct)
     dt = torch.float64 if prec == 64 else torch.float32
@@ -255,7 +264,7 @@ def test_c1_position_vjp_vs_oracle(torch_dev, c1_oracle, direct, prec):
     ref = o.position_vjp_S(sig, gb)
     e = rel_l2(xb.double().cpu().numpy(), ref)
     note(f"c1 position vjp error {e:.2e}")
-    assert e < (1e-9 if prec == 64 else 1e-5)
+    assert e < (1e-9 if prec == 64 else 1e-4)
     s.close()
 
 
@@ -263,14 +272,16 @@ def test_c1_position_vjp_vs_oracle(torch_dev, c1_oracle, direct, prec):
 def test_fmm_position_vjp_sampled(torch_dev, prec):
     """Several FMM levels (sphere, 1280 order-4 patches, N = 19,200): the
     position derivative on the nodes of 24 sampled patches against the
-    oracle's, which sums over every node and oversampled point."""
+    oracle's, which sums over every node and oversampled point of the
+    precision's far rule (FP32: 6 x 6 points per patch; unmasked FP32 sums,
+    1e-4 relative L2, measured 6e-5)."""
     torch = torch_dev
     import paper_2111_10743_amd as P
     from oracle.geometry import Geometry
     from oracle.ops import Oracle
     from oracle.refelem import nodes
     X, Xu, Xv = I.sphere_patches(3, nodes(4))
-    g = Geometry(X, Xu, Xv, 4)
+    g = Geometry(X, Xu, Xv, 4, q=None if prec == 64 else 6)
     note(f"fmm position vjp prec={prec} setup")
     s = P.Surface(X, Xu, Xv, 4)
     note(f"fmm position vjp sizes {s.sizes}")
@@ -288,7 +299,7 @@ def test_fmm_position_vjp_sampled(torch_dev, prec):
     rows = (pts[:, None] * g.n_p + np.arange(g.n_p)[None, :]).reshape(-1)
     e = rel_l2(xb.double().cpu().numpy()[rows], ref)
     note(f"fmm position vjp prec={prec} error {e:.2e}")
-    assert e < (1e-9 if prec == 64 else 1e-5)
+    assert e < (1e-9 if prec == 64 else 1e-4)
     s.close()
 
 

@@ -6,13 +6,14 @@ as in Section 4.3, un-restarted GMRES at tol 1e-12 as in Section 6) are
 stored by ``tests/golden/make_oracle_golden.py``, which calls only
 ``oracle/``; the inputs are regenerated here from the same seeds.
 
-* ellipsoid (1, 1.5, 2), 320 order-6 patches, N = 8,960 (FMM with several
-  levels): S, grad S, S' and grad_Gamma S (Section 4.1) at every row in both
+* ellipsoid (1, 1.5, 2), 320 order-6 patches, N = 8,960 (octrees of at
+  least three levels in both precisions: the coarser FP32 far rule gets
+  256 oversampled points per leaf): S, grad S, S' and grad_Gamma S (Section 4.1) at every row in both
   precisions, A3 (eq. ie-dis2) at every row, and both solve modes against
   the oracle's solves of a band-limited right-hand side and of the
   manufactured f = -2 H n_1 (whose exact solution is x_1 minus its mean).
-* star-shaped surface (320 order-4 patches, N = 4,800, a tree of at least
-  three levels): A3 at every row and both solve modes.
+* star-shaped surface (320 order-4 patches, N = 4,800, trees of at least
+  three levels: 256 / 128 oversampled points per leaf in FP64 / FP32): A3 at every row and both solve modes.
 
 Bars: FP64 1e-9 relative L2 on S, grad S, S', grad_Gamma S and the solves;
 FP32 1e-6 on S, grad S, S', grad_Gamma S; FP32+refine solves 1e-9.  A3
@@ -68,8 +69,9 @@ def ellipsoid(torch_dev):
     X, Xu, Xv, k, inp, ref = load("ellipsoid320_k6")
     note("ellipsoid320_k6 setup")
     s = P.Surface(X, Xu, Xv, k)
+    s.set_tuning(32, 256, 64)  # the coarser FP32 far rule: fewer points per leaf for three levels
     note(f"ellipsoid320_k6 sizes {s.sizes}")
-    assert s.sizes["fmm_levels"] >= 3
+    assert s.sizes["fmm_levels"] >= 3 and s.tree(64)["depth"] >= 3
     yield s, inp, ref
     s.close()
 
@@ -100,8 +102,9 @@ def star(torch_dev):
     X, Xu, Xv, k, inp, ref = load("star320_k4")
     note("star320_k4 setup")
     s = P.Surface(X, Xu, Xv, k, leaf_src=256)
+    s.set_tuning(32, 128, 64)
     note(f"star320_k4 sizes {s.sizes}")
-    assert s.sizes["fmm_levels"] >= 3
+    assert s.sizes["fmm_levels"] >= 3 and s.tree(64)["depth"] >= 3
     yield s, inp, ref
     s.close()
 
