@@ -37,32 +37,46 @@ PEAK_HBM_GBS = 8000.0
 CPU_POOL_MAX = 16               # worker processes of the CPU baseline (the host share of one GPU)
 
 
+WORKLOADS = {
+    # name: (surface, order, size parameters)
+    "ellipsoid5120": ("ellipsoid", 6, 4),
+    "ellipsoid1280": ("ellipsoid", 6, 3),
+    "sphere80": ("sphere", 4, 1),
+    "torus561k": ("torus", 6, (60, 167)),    # R = 2, r = 0.7: 20,040 patches, N = 561,120
+    "torus1M": ("torus", 6, (90, 200)),      # 36,000 patches, N = 1,008,000
+}
+
+
 def workload(name, host_nodes=False):
     """Charts, density and description of a workload; host_nodes takes the
     reference nodes from the oracle's node construction (equal bit for bit
     to the library's) so that the CPU-only baseline never loads the library."""
     import lbinputs as I
-    if name == "ellipsoid5120":
-        k, nsub, axes = 6, 4, (1.0, 1.5, 2.0)
-    elif name == "ellipsoid1280":
-        k, nsub, axes = 6, 3, (1.0, 1.5, 2.0)
-    elif name == "sphere80":
-        k, nsub, axes = 4, 1, (1.0, 1.0, 1.0)
-    else:
-        raise SystemExit(f"unknown workload {name}")
+    if name not in WORKLOADS:
+        raise SystemExit(f"unknown workload {name}; one of {sorted(WORKLOADS)}")
+    kind, k, size = WORKLOADS[name]
     if host_nodes:
         from oracle.refelem import nodes
         uv = nodes(k)
     else:
         import paper_2111_10743_amd as P
         uv, _ = P.ref_nodes(k)
-    X, Xu, Xv = I.ellipsoid_patches(nsub, uv, axes)
-    xi = I.sphere_preimage(X.reshape(-1, 3), axes)
-    coef = I.random_sh_coeffs(8, seed=1, decay=2.0)
-    f = I.sh_series(coef, xi)
-    desc = {"workload": f"{name}: ellipsoid axes {axes}, {X.shape[0]} order-{k} patches, N={X.shape[0] * uv.shape[0]}",
-            "patches": int(X.shape[0]), "order": k, "N": int(X.shape[0] * uv.shape[0]),
-            "density": "band-limited SH series l<=8, seed 1"}
+    if kind == "torus":
+        R, r = 2.0, 0.7
+        X, Xu, Xv = I.torus_patches(R, r, size[0], size[1], uv)
+        th, ph = I.torus_angles(X.reshape(-1, 3), R)
+        f = I.trig_series(th, ph, seed=3)
+        dens = "random trigonometric series |a|,|b| <= 6 in (theta, phi), coefficients N(0,1)/(1+a^2+b^2), seed 3"
+        surf = f"torus R={R}, r={r}, {size[0]}x{size[1]} cells split in two"
+    else:
+        axes = (1.0, 1.5, 2.0) if kind == "ellipsoid" else (1.0, 1.0, 1.0)
+        X, Xu, Xv = I.ellipsoid_patches(size, uv, axes)
+        xi = I.sphere_preimage(X.reshape(-1, 3), axes)
+        f = I.sh_series(I.random_sh_coeffs(8, seed=1, decay=2.0), xi)
+        dens = "band-limited SH series l<=8, seed 1"
+        surf = f"ellipsoid axes {axes}"
+    desc = {"workload": f"{name}: {surf}, {X.shape[0]} order-{k} patches, N={X.shape[0] * uv.shape[0]}",
+            "patches": int(X.shape[0]), "order": k, "N": int(X.shape[0] * uv.shape[0]), "density": dens}
     return X, Xu, Xv, k, f, desc
 
 

@@ -80,7 +80,9 @@ typedef struct {
                        (default k+6)                                                   */
   int p_f32;        /* FMM expansion order of the FP32 path                   (default 14) */
   int p_f64;        /* FMM expansion order of the FP64 path                   (default 28) */
-  int leaf_src;     /* target mean number of sources per FMM leaf box         (default 1024)*/
+  int leaf_src;     /* target mean number of sources per FMM leaf box of the FP64 tree
+                       (default 1024); the FP32 tree starts from leaf_src n_o32 / n_o,
+                       the same boxes for its coarser far rule                        */
   int max_iter;     /* GMRES iteration cap per (inner) solve                  (default 100)*/
   int flags;        /* LB_STRICT_MEAN | LB_HOST_ONLY | LB_DIRECT | LB_NO_P2M_TABLES |
                        LB_HOST_OCTREE | LB_NO_GRAPH | LB_NO_OVERLAP | LB_HOST_QUAD     */
@@ -163,6 +165,28 @@ lb_status lb_setup(lb_ctx **ctx, int n_patches, int order, const double *X,
 lb_status lb_setup_batch(lb_ctx **ctx, int n_surf, const int32_t *patches_per_surf, int order,
                          const double *X, const double *Xu, const double *Xv,
                          const lb_opts *opts, void *stream);
+
+/* Save a context's setup to the file `path` (the paper generates the
+ * quadrature corrections once per geometry and reuses them: across the
+ * iterations of a solve and across the two solves of a Hodge decomposition,
+ * harmonic-vector-field section and Section 6): the chart samples, options,
+ * near lists, the corrections of both precisions (eq. nys-lcq2) and the
+ * tuning of each precision (lb_autotune / lb_set_tuning), with a checksum.
+ * Host side (synchronizes the device); the file is in the native byte order.
+ * Errors: LB_EINVAL (null argument, LB_HOST_ONLY context, file not
+ * writable), LB_EHIP. */
+lb_status lb_export_setup(const lb_ctx *ctx, const char *path);
+
+/* Create a context from a file written by lb_export_setup, on the current
+ * device, without generating the corrections: the geometry and near lists
+ * are rebuilt from the saved charts and checked against the saved lists,
+ * the saved corrections are uploaded, the octrees and translation operators
+ * rebuilt with the saved tuning.  Applies and solves of the new context
+ * equal those of the saved one bit for bit.  lb_solve_info.t_setup reports
+ * the import time.  Errors: LB_EINVAL (missing, truncated, corrupt or
+ * incompatible file: magic, version, byte order, option layout, checksum,
+ * near lists), LB_ENOMEM, LB_EHIP. */
+lb_status lb_import_setup(lb_ctx **ctx, const char *path, void *stream);
 
 /* Sizes of the discretization held by ctx. */
 lb_status lb_get_sizes(const lb_ctx *ctx, lb_sizes *out);

@@ -295,6 +295,27 @@ def legendre_field(x, seed, deg, L):
     return V
 
 
+def torus_angles(X, R):
+    """(theta, phi) of points X (n, 3) on the torus of torus_patches."""
+    X = np.asarray(X, dtype=float)
+    ph = np.arctan2(X[:, 1], X[:, 0])
+    th = np.arctan2(X[:, 2], np.hypot(X[:, 0], X[:, 1]) - R)
+    return th, ph
+
+
+def trig_series(theta, phi, seed, amax=6):
+    """sum over |a|, |b| <= amax of c cos(a theta + b phi) + d sin(a theta + b phi),
+    c, d ~ N(0, 1) / (1 + a^2 + b^2) (seeded): a random smooth periodic field."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros_like(np.asarray(theta, dtype=float))
+    for a in range(-amax, amax + 1):
+        for b in range(-amax, amax + 1):
+            c, d = rng.standard_normal(2) / (1.0 + a * a + b * b)
+            t = a * theta + b * phi
+            out += c * np.cos(t) + d * np.sin(t)
+    return out
+
+
 def torus_frame(X, R, r):
     """Unit tangents e_phi, e_theta and rho = R + r cos(theta) of the torus of
     torus_patches at the points X (n, 3)."""

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <limits>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -1590,6 +1591,7 @@ static ApplyWs<T> scratch_ws(lb_ctx* ctx, Prec<T>& P, int nd) {
 }
 }  // namespace lb
 
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1724,8 +1726,10 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
 }
 
 // Setup of n_surf surfaces (surface q: pps[q] patches, in order).
+// given (nullable): corrections taken over instead of generated (an
+// imported setup), already on the device in the packed layouts.
 static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, const double* X, const double* Xu,
-                       const double* Xv, const lb_opts* opts) {
+                       const double* Xv, const lb_opts* opts, DevCorrections* given = nullptr) {
   if (!X || !Xu || !Xv || !pps) fail(LB_EINVAL, "null argument");
   if (n_surf < 1) fail(LB_EINVAL, "n_surf must be >= 1");
   ctx->surf_patch.assign(n_surf + 1, 0);
@@ -1781,8 +1785,8 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   qo.near_adm = o.near_adm;
   // the device rules: at most 3 max_depth + 1 triangles on the near rule's
   // stack, at most 256 (node, kernel) outputs per block
-  const bool dev_quad = !ctx->host_only && !(o.flags & LB_HOST_QUAD) && 3 * qo.max_depth + 1 <= 72 &&
-                        6 * S.n_p <= 256;
+  const bool dev_quad = given || (!ctx->host_only && !(o.flags & LB_HOST_QUAD) && 3 * qo.max_depth + 1 <= 72 &&
+                                  6 * S.n_p <= 256);
   std::vector<double> A, B;
   if (!dev_quad) {
     near_integrals(S, qo, A);
@@ -1809,7 +1813,12 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
     }
     std::vector<double> C32;
     DevCorrections dc;
-    if (dev_quad) {
+    if (given) {
+      std::swap(dc.v4_64.p, given->v4_64.p); std::swap(dc.v4_64.bytes, given->v4_64.bytes);
+      std::swap(dc.v3_64.p, given->v3_64.p); std::swap(dc.v3_64.bytes, given->v3_64.bytes);
+      std::swap(dc.v4_32.p, given->v4_32.p); std::swap(dc.v4_32.bytes, given->v4_32.bytes);
+      std::swap(dc.v3_32.p, given->v3_32.p); std::swap(dc.v3_32.bytes, given->v3_32.bytes);
+    } else if (dev_quad) {
       corrections_device(S, *ctx->re, qo, rm2, dc);
     } else {
       std::vector<float> tx32(3 * S.N), sx32(3 * S.o32.No);
@@ -1829,7 +1838,10 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
     upload(ctx->node_surf, nsurf_of);
     upload(ctx->inv_area, inv);
     const bool direct = (o.flags & LB_DIRECT) != 0;
-    build_prec<float>(ctx, ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), o.leaf_src, direct, nullptr,
+    // the FP32 rule has fewer points per patch: the same leaf boxes as the
+    // FP64 tree hold proportionally fewer of them
+    const int leaf_src32 = std::max(16, (int)((int64_t)o.leaf_src * S.o32.n_o / S.n_o));
+    build_prec<float>(ctx, ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), leaf_src32, direct, nullptr,
                       dev_quad ? &dc.v4_32 : nullptr, dev_quad ? &dc.v3_32 : nullptr);
     C32.clear(); C32.shrink_to_fit();
     ctx->rm2f = std::move(rm2);
@@ -1840,6 +1852,176 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   }
 }
 }  // namespace lb
+
+}  // extern "C" (templates below)
+
+namespace lb {
+// ---------------------------------------------------------------------------
+// Saved setups.  The corrections dominate the setup (the paper generates them
+// once and reuses them for every solve on the geometry, and across the two
+// solves of a Hodge decomposition); a saved setup holds the chart samples,
+// the options, the near lists, the packed corrections of both precisions and
+// the tuning of each precision.  Loading rebuilds the geometry and the near
+// lists (checked against the saved ones), takes the corrections over instead
+// of generating them, and rebuilds the octrees and translation operators.
+// Layout (native byte order): magic "LBSETUP", version, byte-order word,
+// sizeof(lb_opts), n_surf, order, opts, patches per surface, N, nnz blocks,
+// n_p, six tuning words per precision (FP32, FP64), X, Xu, Xv, near_ptr,
+// near_patch, FP64 values k=4 and k=3, FP32 values k=4 and k=3, and an
+// FNV-1a checksum of everything before it.
+// ---------------------------------------------------------------------------
+static const char kSetupMagic[8] = {'L', 'B', 'S', 'E', 'T', 'U', 'P', 0};
+constexpr uint32_t kSetupVersion = 1;
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  }
+};
+
+struct FileW {
+  FILE* f = nullptr;
+  Fnv sum;
+  explicit FileW(const char* path) : f(std::fopen(path, "wb")) {
+    if (!f) fail(LB_EINVAL, "cannot open %s for writing", path);
+  }
+  ~FileW() { if (f) std::fclose(f); }
+  void put(const void* p, size_t n) {
+    if (n && std::fwrite(p, 1, n, f) != n) fail(LB_EINVAL, "write failed");
+    sum.add(p, n);
+  }
+  template <typename T> void put(const std::vector<T>& v) { put(v.data(), sizeof(T) * v.size()); }
+  template <typename T> void val(const T& x) { put(&x, sizeof(T)); }
+};
+
+struct FileR {
+  FILE* f = nullptr;
+  Fnv sum;
+  explicit FileR(const char* path) : f(std::fopen(path, "rb")) {
+    if (!f) fail(LB_EINVAL, "cannot open %s", path);
+  }
+  ~FileR() { if (f) std::fclose(f); }
+  void get(void* p, size_t n) {
+    if (n && std::fread(p, 1, n, f) != n) fail(LB_EINVAL, "saved setup is truncated");
+    sum.add(p, n);
+  }
+  template <typename T> void get(std::vector<T>& v, size_t n) {
+    v.resize(n);
+    get(v.data(), sizeof(T) * n);
+  }
+  template <typename T> T val() { T x; get(&x, sizeof(T)); return x; }
+};
+
+template <typename T>
+static void tuning_words(const Prec<T>& P, int32_t* w) {
+  w[0] = P.build_leaf_src; w[1] = P.leaf_fmax; w[2] = P.leaf_split;
+  w[3] = P.fork_late; w[4] = P.near_grid; w[5] = P.corr_early;
+}
+
+template <typename T>
+static std::vector<T> device_copy(const DBuf& b, size_t n) {
+  std::vector<T> h(n);
+  if (n) HIPTRY(hipMemcpy(h.data(), b.p, sizeof(T) * n, hipMemcpyDeviceToHost));
+  return h;
+}
+
+static void export_setup(const lb_ctx* ctx, const char* path) {
+  if (ctx->host_only) fail(LB_EINVAL, "a LB_HOST_ONLY context holds no device corrections to save");
+  const Surface& S = ctx->S;
+  const int64_t nnzb = S.near_ptr[S.N];
+  const size_t ne = (size_t)nnzb * S.n_p;
+  HIPTRY(hipDeviceSynchronize());
+  FileW w(path);
+  w.put(kSetupMagic, 8);
+  w.val<uint32_t>(kSetupVersion);
+  w.val<uint32_t>(0x01020304u);
+  w.val<uint32_t>((uint32_t)sizeof(lb_opts));
+  w.val<int32_t>(ctx->n_surf);
+  w.val<int32_t>(ctx->k);
+  w.put(&ctx->opts, sizeof(lb_opts));
+  for (int q = 0; q < ctx->n_surf; ++q) w.val<int32_t>(ctx->surf_patch[q + 1] - ctx->surf_patch[q]);
+  w.val<int64_t>(S.N);
+  w.val<int64_t>(nnzb);
+  w.val<int32_t>(S.n_p);
+  int32_t tw[12];
+  tuning_words(ctx->f32, tw);
+  tuning_words(ctx->f64, tw + 6);
+  w.put(tw, sizeof(tw));
+  w.put(S.X); w.put(S.Xu); w.put(S.Xv);
+  w.put(S.near_ptr); w.put(S.near_patch);
+  w.put(device_copy<double>(ctx->f64.vals4, ne * 4));
+  w.put(device_copy<double>(ctx->f64.vals3, ne * 3));
+  w.put(device_copy<float>(ctx->f32.vals4, ne * 4));
+  w.put(device_copy<float>(ctx->f32.vals3, ne * 3));
+  const uint64_t h = w.sum.h;
+  w.val<uint64_t>(h);
+}
+
+template <typename T>
+static void apply_tuning_words(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, const int32_t* w) {
+  lb_tune_info c{};
+  c.leaf_src = w[0]; c.leaf_fmax = w[1]; c.leaf_split = w[2];
+  c.fork_late = w[3]; c.near_grid = w[4]; c.corr_early = w[5];
+  if (P.direct) c.leaf_src = P.build_leaf_src;
+  if (c.leaf_src < 16 || c.leaf_fmax < 1 || c.leaf_fmax > 64 || (c.leaf_fmax & (c.leaf_fmax - 1)) ||
+      c.leaf_split < 0 || c.leaf_split > 3 || c.near_grid < 0)
+    fail(LB_EINVAL, "saved setup holds an invalid tuning");
+  set_tuning_t<T>(ctx, P, adj_built, z_built, c);
+}
+
+static void import_setup(lb_ctx* ctx, const char* path) {
+  FileR r(path);
+  char magic[8];
+  r.get(magic, 8);
+  if (std::memcmp(magic, kSetupMagic, 8) != 0) fail(LB_EINVAL, "%s is not a saved setup", path);
+  if (r.val<uint32_t>() != kSetupVersion) fail(LB_EINVAL, "saved setup version differs");
+  if (r.val<uint32_t>() != 0x01020304u) fail(LB_EINVAL, "saved setup has another byte order");
+  if (r.val<uint32_t>() != (uint32_t)sizeof(lb_opts)) fail(LB_EINVAL, "saved setup options differ in size");
+  const int32_t n_surf = r.val<int32_t>();
+  const int32_t order = r.val<int32_t>();
+  if (n_surf < 1 || n_surf > (1 << 24) || order < 1 || order > 7) fail(LB_EINVAL, "saved setup header is corrupt");
+  lb_opts opts;
+  r.get(&opts, sizeof(lb_opts));
+  std::vector<int32_t> pps;
+  r.get(pps, (size_t)n_surf);
+  int64_t NP = 0;
+  for (int32_t c : pps) {
+    if (c < 1) fail(LB_EINVAL, "saved setup header is corrupt");
+    NP += c;
+  }
+  const int64_t N = r.val<int64_t>(), nnzb = r.val<int64_t>();
+  const int32_t n_p = r.val<int32_t>();
+  if (n_p != (order + 1) * (order + 2) / 2 || N != NP * n_p || nnzb < N || nnzb > N * NP)
+    fail(LB_EINVAL, "saved setup sizes are inconsistent");
+  int32_t tw[12];
+  r.get(tw, sizeof(tw));
+  std::vector<double> X, Xu, Xv;
+  r.get(X, 3 * (size_t)N); r.get(Xu, 3 * (size_t)N); r.get(Xv, 3 * (size_t)N);
+  std::vector<int64_t> nptr;
+  std::vector<int32_t> npat;
+  r.get(nptr, (size_t)N + 1);
+  r.get(npat, (size_t)nnzb);
+  const size_t ne = (size_t)nnzb * n_p;
+  std::vector<double> v4d, v3d;
+  std::vector<float> v4f, v3f;
+  r.get(v4d, ne * 4); r.get(v3d, ne * 3); r.get(v4f, ne * 4); r.get(v3f, ne * 3);
+  const uint64_t h = r.sum.h;
+  if (r.val<uint64_t>() != h) fail(LB_EINVAL, "saved setup checksum mismatch (corrupt file)");
+  if (opts.flags & LB_HOST_ONLY) fail(LB_EINVAL, "saved setup asks for a host-only context");
+  DevCorrections dc;
+  upload(dc.v4_64, v4d); upload(dc.v3_64, v3d); upload(dc.v4_32, v4f); upload(dc.v3_32, v3f);
+  v4d.clear(); v3d.clear(); v4f.clear(); v3f.clear();
+  setup_impl(ctx, n_surf, pps.data(), order, X.data(), Xu.data(), Xv.data(), &opts, &dc);
+  if (ctx->S.near_ptr != nptr || ctx->S.near_patch != npat)
+    fail(LB_EINVAL, "the near lists rebuilt from the saved charts differ from the saved ones");
+  apply_tuning_words<float>(ctx, ctx->f32, ctx->adj_built32, ctx->z_built32, tw);
+  apply_tuning_words<double>(ctx, ctx->f64, ctx->adj_built64, ctx->z_built64, tw + 6);
+}
+}  // namespace lb
+
+extern "C" {
 
 lb_status lb_setup(lb_ctx** out, int n_patches, int order, const double* X, const double* Xu, const double* Xv,
                    const lb_opts* opts, void* stream) {
@@ -1866,6 +2048,26 @@ lb_status lb_setup_batch(lb_ctx** out, int n_surf, const int32_t* patches_per_su
   const double t0 = wall_seconds();
   auto ctx = std::make_unique<lb_ctx>();
   setup_impl(ctx.get(), n_surf, patches_per_surf, order, X, Xu, Xv, opts);
+  ctx->t_setup = wall_seconds() - t0;
+  *out = ctx.release();
+  API_END
+}
+
+lb_status lb_export_setup(const lb_ctx* ctx, const char* path) {
+  API_BEGIN
+  if (!ctx || !path) fail(LB_EINVAL, "null argument");
+  export_setup(ctx, path);
+  API_END
+}
+
+lb_status lb_import_setup(lb_ctx** out, const char* path, void* stream) {
+  API_BEGIN
+  (void)stream;
+  if (!out || !path) fail(LB_EINVAL, "null argument");
+  *out = nullptr;
+  const double t0 = wall_seconds();
+  auto ctx = std::make_unique<lb_ctx>();
+  import_setup(ctx.get(), path);
   ctx->t_setup = wall_seconds() - t0;
   *out = ctx.release();
   API_END

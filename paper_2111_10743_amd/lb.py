@@ -38,7 +38,7 @@ EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj",
             "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_apply_A1", "lb_set_tuning", "lb_destroy",
-            "lb_last_error", "lb_apply_gradS_noalloc")
+            "lb_last_error", "lb_apply_gradS_noalloc", "lb_export_setup", "lb_import_setup")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -105,6 +105,8 @@ def lib():
         L.lb_setup_batch.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ctypes.c_int32), ip, dp, dp, dp,
                                      ctypes.POINTER(Opts), vp]
         L.lb_get_sizes.argtypes = [vp, ctypes.POINTER(Sizes)]
+        L.lb_export_setup.argtypes = [vp, ctypes.c_char_p]
+        L.lb_import_setup.argtypes = [ctypes.POINTER(vp), ctypes.c_char_p, vp]
         L.lb_get_geometry.argtypes = [vp, dp, dp, dp]
         L.lb_get_corrections.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp]
         L.lb_get_tree.argtypes = [vp, ip, ip, ip, ctypes.POINTER(TreeInfo)] + [vp] * 9
@@ -209,6 +211,15 @@ class Surface:
                  host_octree=False, patches_per_surf=None, graphs=True, overlap=True, host_quad=False, **kw):
         """One surface, or with patches_per_surf several independent surfaces
         (their patches one after the other in X, Xu, Xv; lb_setup_batch)."""
+        if X is None:  # Surface.load: the context comes from a saved setup (opts = its path)
+            self.order = order
+            self.host_only = False
+            self._ctx = ctypes.c_void_p()
+            _check(lib().lb_import_setup(ctypes.byref(self._ctx), os.fsencode(opts), _stream()))
+            sz = self.sizes
+            self.N = sz["N"]
+            self.n_surf = sz["n_surf"]
+            return
         X = np.ascontiguousarray(X, dtype=np.float64)
         Xu = np.ascontiguousarray(Xu, dtype=np.float64)
         Xv = np.ascontiguousarray(Xv, dtype=np.float64)
@@ -253,6 +264,16 @@ class Surface:
         s = Sizes()
         _check(lib().lb_get_sizes(self._ctx, ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in Sizes._fields_}
+
+    def save(self, path):
+        """lb_export_setup: write this context's setup (corrections, tuning) to path."""
+        _check(lib().lb_export_setup(self._ctx, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, order=None):
+        """lb_import_setup: a context from a saved setup, without generating
+        the corrections."""
+        return cls(None, None, None, order, opts=path)
 
     def close(self):
         if self._ctx:

@@ -111,3 +111,22 @@ def test_host_only_rejects_device_entry_points():
     assert L.lb_set_tuning(s._ctx, 32, ctypes.byref(cfg)) == lb.LB_EINVAL
     ptr, patch, vals = s.corrections()
     assert ptr[-1] == len(patch) and np.isfinite(vals).all() and np.abs(vals).max() > 0
+
+
+def test_saved_setup_errors_on_host(tmp_path):
+    """lb_export_setup refuses a host-only context and lb_import_setup a file
+    that is not a saved setup, before any device call."""
+    import ctypes
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    import lbinputs as I
+    s = P.Surface(*I.sphere_patches(0, nodes(2)), 2, host_only=True)
+    with pytest.raises(P.LBError) as e:
+        s.save(str(tmp_path / "x.lbsetup"))
+    assert e.value.code == P.LB_EINVAL and "LB_HOST_ONLY" in str(e.value)
+    bad = tmp_path / "bad.lbsetup"
+    bad.write_bytes(b"not a setup at all")
+    ctx = ctypes.c_void_p()
+    code = P.lib().lb_import_setup(ctypes.byref(ctx), str(bad).encode(), None)
+    assert code == P.LB_EINVAL and not ctx
+    s.close()
