@@ -155,6 +155,56 @@ def measured_traffic(kernel_key):
     return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"]))
 
 
+def c3_run(P, torch, s, X, N, steps):
+    """The torus right-hand sides batched as 16 densities: the two Hodge
+    right-hand sides of one tangential field F = -n x (n x V) (V with tensor
+    Legendre components of degree 5 on x / 2L, L = 2.7, seed 3; div F and
+    -div(n x F) by the surface calculus) and 14 random trigonometric series
+    (seeds 4..17).  Times the FP32 gradient apply of all 16 in one FMM
+    traversal (value in Mpts/s x nd), A3 of all 16 and the batched
+    FP32+refine and FP64 solves at tol 1e-9."""
+    import lbinputs as I
+    x = X.reshape(-1, 3)
+    w, nrm, _ = s.geometry()
+    V = I.legendre_field(x, seed=3, deg=5, L=2.7)
+    F = torch.tensor(-(V - nrm * (nrm * V).sum(1, keepdims=True)), device="cuda")
+    th, ph = I.torus_angles(x, 2.0)
+    rhs = [s.surface_div(F), -s.surface_div(F, cross_n=True)]
+    rhs += [torch.tensor(I.trig_series(th, ph, seed=sd), device="cuda") for sd in range(4, 18)]
+    f = torch.stack(rhs).contiguous()
+    nd = f.shape[0]
+    f32 = f.float().contiguous()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    s.apply_gradS(f32)
+    ms_g = timed(lambda: s.apply_gradS(f32), steps)
+    s.apply_A3(f32)
+    ms_a3 = timed(lambda: s.apply_A3(f32), max(2, steps // 4))
+    out = {"nd": nd, "gradS_fp32_ms": ms_g, "gradS_fp32_value": N * nd / (ms_g * 1e-3) / 1e6,
+           "value_unit": "Mpts/s x nd", "A3_fp32_ms": ms_a3}
+    for name, mode in (("fp64", P.LB_SOLVE_FP64), ("fp32_refine", P.LB_SOLVE_FP32_REFINE)):
+        s.solve(f, tol=1e-9, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, info, code = s.solve(f, tol=1e-9, mode=mode)
+        torch.cuda.synchronize()
+        out[f"solve_{name}"] = {"s": time.perf_counter() - t0, "status": code,
+                                "iters": [i["iters"] for i in info], "max_rel_resid": max(i["rel_resid"] for i in info)}
+        print(f"[bench] c3 solve {name} {out[f'solve_{name}']}", file=sys.stderr, flush=True)
+    print(f"[bench] c3 {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +214,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and FP32+refine solves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default octree depth and leaf shape")
+    ap.add_argument("--tuning", default=None,
+                    help="apply this configuration (JSON as in config.tuning of an earlier run) instead of "
+                         "running the autotuner, e.g. to profile the launches a tuned run timed")
     ap.add_argument("--no-hodge", action="store_true", help="skip the twisted-torus Hodge decomposition")
     ap.add_argument("--cpu-rows", type=int, default=24, help="oracle rows per host core in the cpu baseline")
     ap.add_argument("--cpu-only", action="store_true",
@@ -190,7 +243,14 @@ def main():
     t_setup = time.perf_counter() - t0
     print(f"[bench] setup {t_setup:.1f} s sizes {s.sizes}", file=sys.stderr, flush=True)
     tuning = None
-    if not args.no_tune:  # untimed: picks the octree depth and leaf-kernel shape of each precision
+    if args.tuning:
+        tuning = json.loads(args.tuning)
+        for prec in (32, 64):
+            t = tuning[f"fp{prec}"]
+            s.set_tuning(prec, t["leaf_src"], t["leaf_fmax"], t["leaf_split"], t["fork_late"], t["near_grid"],
+                         t["corr_early"])
+        print(f"[bench] tuning applied {tuning}", file=sys.stderr, flush=True)
+    elif not args.no_tune:  # untimed: picks the octree depth and leaf-kernel shape of each precision
         tuning = {}
         for prec in (32, 64):
             t = s.autotune(prec, 1)
@@ -301,6 +361,8 @@ def main():
         "operator_apply_ms": t_mv,
         "roofline": roof,
     }
+    if args.workload.startswith("torus") and not args.no_solve:
+        out["rhs16"] = c3_run(P, torch, s, X, N, args.steps)
     if not args.no_solve:
         fz = torch.tensor(f, dtype=torch.float64, device="cuda")
         res = {}

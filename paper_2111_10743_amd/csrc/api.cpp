@@ -57,8 +57,15 @@ template <typename T> static inline T* dptr(const DBuf& b) { return reinterpret_
 
 struct PlanBuf {
   GemmPlan pl;
-  DBuf grp_mat, grp_beg, pair_src, boxes, box_scale, tptr, tpairs, grp_lo, pair_lo, work[9];
+  DBuf grp_mat, grp_beg, pair_src, boxes, box_scale, tptr, tpairs, grp_lo, pair_lo, work[GEMM_NE_MAX + 1];
 };
+
+// Densities per FMM traversal: FP32 carries more expansions per traversal
+// (wider M2L GEMMs, fewer traversals for many right-hand sides); the FP64
+// column scratch of M2L would grow past what the N ~ 1M problems can hold.
+template <typename T> constexpr int nemax() { return sizeof(T) == 4 ? GEMM_NE_MAX : 8; }
+template <typename T> constexpr int chunk_fwd() { return sizeof(T) == 4 ? 16 : 8; }  // S, grad S
+template <typename T> constexpr int chunk_a3() { return nemax<T>() / 3; }           // A3 (3 expansions)
 
 template <typename T, class A>
 static void upload(DBuf& d, const std::vector<T, A>& h);
@@ -68,9 +75,10 @@ static void upload(DBuf& d, const std::vector<T, A>& h);
 // the plan accumulates).
 struct Triple { int mat, tgt, src; };
 // mat_lo (nullable: all L): active size of each matrix id's translation.
+// ne_max: work lists for 1..ne_max expansions per box.
 static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<int>& boxes,
                          const std::vector<double>& scale, bool scaled, bool accumulate, int nbox_total, int L,
-                         const std::vector<int>& mat_lo = {}, bool ksplit = false) {
+                         int ne_max, const std::vector<int>& mat_lo = {}, bool ksplit = false) {
   std::stable_sort(tr.begin(), tr.end(), [](const Triple& a, const Triple& b) {
     return a.mat != b.mat ? a.mat < b.mat : a.tgt < b.tgt;
   });
@@ -124,7 +132,8 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
       pl.nslice = (L + kl - 1) / kl;
     }
   }
-  for (int ne = 1; ne <= 8; ++ne) {
+  pl.ne_max = ne_max;
+  for (int ne = 1; ne <= ne_max; ++ne) {
     std::vector<int> w;
     for (int g2 = 0; g2 < pl.ngrp; ++g2) {
       const int lo = glo.empty() ? L : glo[g2];
@@ -666,7 +675,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         const double l = lo.empty() ? P.L : lo[q.mat];
         P.m2l_flops += 2.0 * l * l;
       }
-      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb, P.L, lo));
+      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb, P.L, nemax<T>(), lo));
     }
     P.m2m_pb.clear();
     P.l2l_pb.clear();
@@ -688,7 +697,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
           if (ch >= 0 && F.has_src[ch]) trp.push_back({c, g, ch});
         }
       }
-      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb, P.L, {}, true));
+      maxcols = std::max(maxcols, build_plan(*P.m2m_pb[l], trp, boxes, {}, false, false, nb, P.L, nemax<T>(), {}, true));
       P.m2m_pl[l] = P.m2m_pb[l]->pl;
     }
     for (int l = 3; l <= F.depth; ++l) {  // L2L into level l from level l-1
@@ -704,10 +713,10 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         boxes.push_back(g);
         trp.push_back({oct, g, pg});
       }
-      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb, P.L, {}, true));
+      maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb, P.L, nemax<T>(), {}, true));
       P.l2l_pl[l] = P.l2l_pb[l]->pl;
     }
-    P.Y.alloc(sizeof(T) * maxcols * 8 * (size_t)P.L);
+    P.Y.alloc(sizeof(T) * maxcols * nemax<T>() * (size_t)P.L);
   }
   // device tree descriptor
   DevTree<T>& D = P.dt;
@@ -775,6 +784,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
 
 template <typename T>
 static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
+  chunk = std::max(chunk, chunk_fwd<T>());
   if (P.ws_rhs >= chunk) return;
   const int64_t N = ctx->N, No = P.No;
   const int nb = P.dt.nbox;
@@ -840,8 +850,8 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
   // the side stream (ahead of the near field, which launch_fmm forks there
   // and joins back), and a light final step adds the far sums
   const bool early = P.corr_early && P.dt.side && P.dt.depth >= 2 && !tm;
-  for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
-    const int c = std::min(CHUNK_GRAD, nd - d0);
+  for (int d0 = 0; d0 < nd; d0 += chunk_fwd<T>()) {
+    const int c = std::min(chunk_fwd<T>(), nd - d0);
     if (early) {
       HIPTRY(hipEventRecord(P.dt.fork_ev, st));
       HIPTRY(hipStreamWaitEvent(P.dt.side, P.dt.fork_ev, 0));
@@ -868,13 +878,13 @@ static void apply_gradS_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* po
   }
 }
 
-// S alone (potential-only FMM), eight densities per traversal
+// S alone (potential-only FMM), chunk_fwd densities per traversal
 template <typename T>
 static void apply_S_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, hipStream_t st) {
   ensure_ws(ctx, P, CHUNK_GRAD);
   const int64_t N = ctx->N, No = P.No;
-  for (int d0 = 0; d0 < nd; d0 += CHUNK_GRAD) {
-    const int c = std::min(CHUNK_GRAD, nd - d0);
+  for (int d0 = 0; d0 < nd; d0 += chunk_fwd<T>()) {
+    const int c = std::min(chunk_fwd<T>(), nd - d0);
     launch_strengths<T>(sigma + (int64_t)d0 * N, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo),
                         dptr<int>(P.src_pos), No, dptr<T>(P.str), st);
     launch_fmm<T>(P.dt, FMM_POT, c, dptr<T>(P.str), dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No,
@@ -884,17 +894,16 @@ static void apply_S_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* sigma, T* pot, h
   }
 }
 
-// A3 (Section 4.3) for nd densities, two per traversal: the second FMM
+// A3 (Section 4.3) for nd densities, chunk_a3 per traversal: the second FMM
 // carries three expansions per density (charges mu1, mu2 and dipole mu2 nu).
-constexpr int CHUNK_A3 = 2;
 
 template <typename T>
 static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
   ensure_ws(ctx, P, CHUNK_GRAD);
   const int64_t N = ctx->N, No = P.No;
   T* mu = dptr<T>(P.mu);  // [c][mu1; mu2]
-  for (int d0 = 0; d0 < nd; d0 += CHUNK_A3) {
-    const int c = std::min(CHUNK_A3, nd - d0);
+  for (int d0 = 0; d0 < nd; d0 += chunk_a3<T>()) {
+    const int c = std::min(chunk_a3<T>(), nd - d0);
     const T* td = tau + (int64_t)d0 * N;
     launch_strengths<T>(td, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
                         dptr<T>(P.str), st);
@@ -1573,7 +1582,7 @@ namespace lb {
 template <typename T>
 static ApplyWs<T> scratch_ws(lb_ctx* ctx, Prec<T>& P, int nd) {
   size_t cnt[6];
-  ws_counts<T>(ctx, P, std::min(nd, CHUNK_GRAD), cnt);
+  ws_counts<T>(ctx, P, std::min(nd, chunk_fwd<T>()), cnt);
   size_t off[7] = {0};
   for (int i = 0; i < 6; ++i) off[i + 1] = off[i] + (sizeof(T) * cnt[i] + 255) / 256 * 256;
   if (off[6] > NOALLOC_SCRATCH_BYTES)

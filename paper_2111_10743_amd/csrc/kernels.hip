@@ -1266,7 +1266,8 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
   if (!tm) tm = &dummy;
   const int p = t.p, L = t.L, Lc_ = (p + 1) * (p + 2) / 2;
   const int ne = nrhs * fmm_nexp(mode);
-  if (ne > 8) fail(LB_EINVAL, "launch_fmm called with %d expansions (max 8)", ne);
+  if (t.depth >= 2 && ne > t.m2l_plan->ne_max)
+    fail(LB_EINVAL, "launch_fmm called with %d expansions (at most %d)", ne, t.m2l_plan->ne_max);
   // With a side stream, the near-field sums (which need only the strengths)
   // run there while this stream does P2M (unless fork_late), M2M, M2L and
   // L2L; the L2P kernel then adds the far field.  Timed applies stay serial.

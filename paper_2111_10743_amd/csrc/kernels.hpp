@@ -44,6 +44,11 @@ constexpr int GEMM_TILE_ROWS = 128, GEMM_TILE_COLS = 64;
 // turn, each XCD with its own L2.
 constexpr int GEMM_NXCD = 8;
 
+// Most expansions one FMM traversal may carry (FP32; the FP64 plans stop at
+// 8): sixteen densities of a gradient apply, eight of the second A3 pass
+// (three expansions each).
+constexpr int GEMM_NE_MAX = 24;
+
 struct GemmPlan {
   int ngrp = 0, npair = 0, nbox = 0;
   const int *grp_mat = nullptr, *grp_beg = nullptr;  // [ngrp], [ngrp+1] (triple index)
@@ -55,10 +60,11 @@ struct GemmPlan {
   const int* boxes = nullptr;                         // [nbox] target boxes
   const double* box_scale = nullptr;                  // [nbox] factor of each target box (scaled plans)
   const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
-  // per density count ne (1..8): work items (group, first column, first
-  // row, first k), ordered group -> row tile -> column tile -> k slice
-  const int* work[9] = {nullptr};
-  int nwork[9] = {0};
+  // per expansion count ne (1..ne_max): work items (group, first column,
+  // first row, first k), ordered group -> row tile -> column tile -> k slice
+  const int* work[GEMM_NE_MAX + 1] = {nullptr};
+  int nwork[GEMM_NE_MAX + 1] = {0};
+  int ne_max = 0;
   // k split: slices of kslice coefficients (0: the whole sum in one block);
   // slice s of column c goes to Y[s][c], and the column reduction adds the
   // nslice slices
@@ -238,7 +244,7 @@ struct PhaseTimer {
   void mark(int i, hipStream_t st) { if (on) (void)hipEventRecord(ev[i], st); }
 };
 
-// nrhs * fmm_nexp(mode) <= 8.  D: scratch [n_leaf_work][nrhs][nexp*3*p^2 + 9*(p-1)^2]
+// nrhs * fmm_nexp(mode) <= the plans' ne_max.  D: scratch [n_leaf_work][nrhs][nexp*3*p^2 + 9*(p-1)^2]
 template <typename T>
 void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
                 int64_t N, int64_t No, hipStream_t st, PhaseTimer* tm = nullptr);
