@@ -44,6 +44,9 @@ WORKLOADS = {
     "sphere80": ("sphere", 4, 1),
     "torus561k": ("torus", 6, (60, 167)),    # R = 2, r = 0.7: 20,040 patches, N = 561,120
     "torus1M": ("torus", 6, (90, 200)),      # 36,000 patches, N = 1,008,000
+    # 64 star-shaped surfaces, faces split n_s x n_s, n_s ~ U{3..9} (seed 99):
+    # 180 .. 1,620 order-5 patches each, N = 1,060,920 in all
+    "stars64": ("stars", 5, 64),
 }
 
 
@@ -61,7 +64,19 @@ def workload(name, host_nodes=False):
     else:
         import paper_2111_10743_amd as P
         uv, _ = P.ref_nodes(k)
-    if kind == "torus":
+    pps = None
+    if kind == "stars":
+        ns = np.random.default_rng(99).integers(3, 10, size)
+        surfs = [I.star_patches(int(n), uv, I.star_coeffs(4 + q)) for q, n in enumerate(ns)]
+        X, Xu, Xv = (np.concatenate([sf[c] for sf in surfs]) for c in range(3))
+        pps = [int(sf[0].shape[0]) for sf in surfs]
+        x = X.reshape(-1, 3)
+        f = I.sh_series(I.random_sh_coeffs(6, seed=1, decay=2.0), x / np.linalg.norm(x, axis=1, keepdims=True))
+        dens = ("band-limited SH series l<=6 of the direction x/|x| (coefficients N(0,1)(l+1)^-2, seed 1) on "
+                "every surface")
+        surf = (f"{size} star-shaped surfaces r = 1 + 0.25 sum_(l<=4) a_lm Y_lm, a_lm ~ U(-1,1)/(l+1) "
+                f"(seed 4+s), faces split n_s x n_s, n_s ~ U{{3..9}} (seed 99): {min(pps)}..{max(pps)} patches each")
+    elif kind == "torus":
         R, r = 2.0, 0.7
         X, Xu, Xv = I.torus_patches(R, r, size[0], size[1], uv)
         th, ph = I.torus_angles(X.reshape(-1, 3), R)
@@ -77,7 +92,9 @@ def workload(name, host_nodes=False):
         surf = f"ellipsoid axes {axes}"
     desc = {"workload": f"{name}: {surf}, {X.shape[0]} order-{k} patches, N={X.shape[0] * uv.shape[0]}",
             "patches": int(X.shape[0]), "order": k, "N": int(X.shape[0] * uv.shape[0]), "density": dens}
-    return X, Xu, Xv, k, f, desc
+    if pps is not None:
+        desc["surfaces"] = len(pps)
+    return X, Xu, Xv, k, f, desc, pps
 
 
 _ORC = None
@@ -90,37 +107,58 @@ def _orc_layer(args):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(X, Xu, Xv, k, f, nrows):
-    """The FP64 oracle's apply (far sum over all oversampled sources + near
-    corrections, correction generation excluded) on sampled target rows:
-    `nrows` rows on one thread, then `nrows` rows per core on every host core
-    this process may use (one process per core, BLAS single-threaded)."""
+def cpu_baseline(X, Xu, Xv, k, f, nrows, pps=None):
+    """The FP64 oracle's apply (far sum over all oversampled sources of the
+    target's surface + near corrections, correction generation excluded) on
+    sampled target rows: `nrows` rows on one thread, then `nrows` rows per
+    core on every host core this process may use (one process per core, BLAS
+    single-threaded).  With several surfaces (pps: patches per surface) core
+    c takes its rows from surface c * n_surf / cores."""
     global _ORC
     from multiprocessing import get_context
     from threadpoolctl import threadpool_limits
     from oracle.geometry import Geometry
     from oracle.ops import Oracle
     cores = min(len(os.sched_getaffinity(0)), CPU_POOL_MAX)
+    npp = X.shape[1]
+    bounds = np.cumsum([0] + (pps if pps else [X.shape[0]]))
+    nsurf = len(bounds) - 1
+
+    def surface(q):
+        a, z = bounds[q], bounds[q + 1]
+        g = Geometry(X[a:z], Xu[a:z], Xv[a:z], k)
+        return g, f[a * npp:z * npp]
+
     with threadpool_limits(limits=1):
-        g = Geometry(X, Xu, Xv, k)
+        g, fq = surface(0)
         rows = np.linspace(0, g.N - 1, nrows).astype(np.int64)
         o = Oracle(g, rows, dense_limit=0)
         t0 = time.perf_counter()
-        o.layer(f)
+        o.layer(fq)
         dt1 = time.perf_counter() - t0
-        allrows = np.array_split(np.linspace(0, g.N - 1, nrows * cores).astype(np.int64), cores)
-        _ORC = [Oracle(g, r, dense_limit=0) for r in allrows]   # corrections (untimed)
+        _ORC, jobs, srcs = [], [], []
+        for c in range(cores):
+            q = c * nsurf // cores
+            g, fq = surface(q)
+            lo, hi = (c * g.N // cores, (c + 1) * g.N // cores) if nsurf == 1 else (0, g.N)
+            r = np.linspace(lo, hi - 1, nrows).astype(np.int64)
+            _ORC.append(Oracle(g, r, dense_limit=0))   # corrections (untimed)
+            jobs.append((c, fq))
+            srcs.append(g.No)
     with get_context("fork").Pool(cores) as pool:
         t0 = time.perf_counter()
-        per = pool.map(_orc_layer, [(c, f) for c in range(cores)])
+        per = pool.map(_orc_layer, jobs)
         dtn = time.perf_counter() - t0
         pool.close()
         pool.join()
     _ORC = None
+    where = (f"of {g.N}" if nsurf == 1 else
+             f"from surfaces {sorted(set(c * nsurf // cores for c in range(cores)))} of {nsurf}")
     return {"value": nrows * cores / dtn / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nrows} target rows per core ({nrows * cores} of {g.N}) on {cores} cores, one process "
-                      f"each: direct far sum over all {g.No} oversampled sources + near corrections (correction "
-                      f"generation excluded), {dtn:.2f} s wall (slowest core {max(per):.2f} s)",
+            "sample": f"{nrows} target rows per core ({nrows * cores} {where}) on {cores} cores, one process "
+                      f"each: direct far sum over all {min(srcs)}..{max(srcs)} oversampled sources of the "
+                      f"row's surface + near corrections (correction generation excluded), {dtn:.2f} s wall "
+                      f"(slowest core {max(per):.2f} s)",
             "single_core": {"value": nrows / dt1 / 1e6, "unit": "Mpts/s", "cores": 1,
                             "sample": f"{nrows} target rows, {dt1:.2f} s"},
             "host_cores": cores}
@@ -226,8 +264,8 @@ def main():
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.cpu_only:
-        X, Xu, Xv, k, f, _ = workload(args.workload, host_nodes=True)
-        print(json.dumps(cpu_baseline(X, Xu, Xv, k, f, args.cpu_rows)), flush=True)
+        X, Xu, Xv, k, f, _, pps = workload(args.workload, host_nodes=True)
+        print(json.dumps(cpu_baseline(X, Xu, Xv, k, f, args.cpu_rows, pps)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU runs are not part "
@@ -237,9 +275,9 @@ def main():
     import paper_2111_10743_amd as P
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    X, Xu, Xv, k, f, desc = workload(args.workload)
+    X, Xu, Xv, k, f, desc, pps = workload(args.workload)
     t0 = time.perf_counter()
-    s = P.Surface(X, Xu, Xv, k)
+    s = P.Surface(X, Xu, Xv, k, patches_per_surf=pps)
     t_setup = time.perf_counter() - t0
     print(f"[bench] setup {t_setup:.1f} s sizes {s.sizes}", file=sys.stderr, flush=True)
     tuning = None
@@ -375,13 +413,21 @@ def main():
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             us[name] = u
-            res[name] = {"s": dt, "iters": info[0]["iters"], "outer_steps": info[0]["outer_steps"],
-                         "rel_resid": info[0]["rel_resid"], "status": code}
+            its = [i["iters"] for i in info]
+            res[name] = {"s": dt, "iters": its[0] if len(its) == 1 else [min(its), max(its)],
+                         "outer_steps": max(i["outer_steps"] for i in info),
+                         "rel_resid": max(i["rel_resid"] for i in info), "status": code, "systems": len(info)}
             print(f"[bench] solve {name} {res[name]}", file=sys.stderr, flush=True)
         w, _, _ = s.geometry()
         w = torch.tensor(w, device="cuda")
         d = us["fp32_refine"] - us["fp64"]
         res["fp32_refine_vs_fp64_rel_l2"] = float(torch.sqrt((w * d * d).sum() / (w * us["fp64"] ** 2).sum()))
+        if pps:  # the worst surface
+            npp = X.shape[1]
+            cut = np.cumsum([0] + pps) * npp
+            res["fp32_refine_vs_fp64_worst_surface"] = max(
+                float(torch.sqrt((w[a:z] * d[a:z] ** 2).sum() / (w[a:z] * us["fp64"][a:z] ** 2).sum()))
+                for a, z in zip(cut[:-1], cut[1:]))
         out["solve"] = res
     s.close()
     if not args.no_hodge:

@@ -52,6 +52,17 @@ struct DBuf {
     if (e != hipSuccess) fail(LB_ENOMEM, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
     bytes = b;
   }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // exactly b bytes (frees a larger buffer)
+  void alloc_exact(size_t b) {
+    if (b == 0) b = 16;
+    if (p && b != bytes) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    alloc(b);
+  }
 };
 template <typename T> static inline T* dptr(const DBuf& b) { return reinterpret_cast<T*>(b.p); }
 
@@ -66,6 +77,8 @@ struct PlanBuf {
 template <typename T> constexpr int nemax() { return sizeof(T) == 4 ? GEMM_NE_MAX : 8; }
 template <typename T> constexpr int chunk_fwd() { return sizeof(T) == 4 ? 16 : 8; }  // S, grad S
 template <typename T> constexpr int chunk_a3() { return nemax<T>() / 3; }           // A3 (3 expansions)
+// largest column scratch of the M2L plan (split into parts beyond it)
+constexpr size_t M2L_Y_BUDGET = (size_t)4 << 30;
 
 template <typename T, class A>
 static void upload(DBuf& d, const std::vector<T, A>& h);
@@ -204,9 +217,8 @@ struct Prec {
   DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
   DBuf m2m, l2l, m2l, dgrad, dhess;
   // batched translation plans (M2L over all levels; M2M, L2L per level)
-  std::unique_ptr<PlanBuf> m2l_pb;
-  std::vector<std::unique_ptr<PlanBuf>> m2m_pb, l2l_pb;
-  std::vector<GemmPlan> m2m_pl, l2l_pl;
+  std::vector<std::unique_ptr<PlanBuf>> m2l_pb, m2m_pb, l2l_pb;
+  std::vector<GemmPlan> m2l_pl, m2m_pl, l2l_pl;
   DBuf Y;
   DBuf p2m_H, p2m_D;
   // work
@@ -666,7 +678,6 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         scale.push_back(F.box_scale[g]);
         for (int v = F.vlist_ptr[g]; v < F.vlist_ptr[g + 1]; ++v) trp.push_back({F.vlist_off[v], g, F.vlist_src[v]});
       }
-      P.m2l_pb.reset(new PlanBuf());
       const std::vector<int> lo = m2l_orders(p, sizeof(T) == 4 ? ctx->opts.m2l_trunc32 : ctx->opts.m2l_trunc64);
       // algorithmic M2L work per density: a pair at offset o multiplies its
       // leading lo[o] coefficients by the leading lo[o] x lo[o] block
@@ -675,7 +686,35 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
         const double l = lo.empty() ? P.L : lo[q.mat];
         P.m2l_flops += 2.0 * l * l;
       }
-      maxcols = std::max(maxcols, build_plan(*P.m2l_pb, trp, boxes, scale, true, false, nb, P.L, nemax<T>(), lo));
+      // parts of at most cap pairs (in (offset, target) order), so that the
+      // column scratch of the deep trees of the N ~ 1M surfaces stays within
+      // M2L_Y_BUDGET; the first part writes every target box, the others add
+      std::stable_sort(trp.begin(), trp.end(), [](const Triple& a, const Triple& b) {
+        return a.mat != b.mat ? a.mat < b.mat : a.tgt < b.tgt;
+      });
+      const size_t cap = std::max<size_t>(4096, M2L_Y_BUDGET / (sizeof(T) * (size_t)nemax<T>() * P.L));
+      const size_t nparts = std::max<size_t>(1, (trp.size() + cap - 1) / cap);
+      P.m2l_pb.clear();
+      P.m2l_pl.clear();
+      for (size_t q = 0; q < nparts; ++q) {
+        const size_t b0 = trp.size() * q / nparts, b1 = trp.size() * (q + 1) / nparts;
+        std::vector<Triple> part(trp.begin() + b0, trp.begin() + b1);
+        std::vector<int> pboxes;
+        std::vector<double> pscale;
+        if (q == 0) {
+          pboxes = boxes;
+          pscale = scale;
+        } else {
+          std::vector<char> has(nb, 0);
+          for (const Triple& t3 : part) has[t3.tgt] = 1;
+          for (size_t b = 0; b < boxes.size(); ++b)
+            if (has[boxes[b]]) { pboxes.push_back(boxes[b]); pscale.push_back(scale[b]); }
+        }
+        P.m2l_pb.emplace_back(new PlanBuf());
+        maxcols = std::max(maxcols, build_plan(*P.m2l_pb.back(), part, pboxes, pscale, true, q > 0, nb, P.L,
+                                               nemax<T>(), lo));
+        P.m2l_pl.push_back(P.m2l_pb.back()->pl);
+      }
     }
     P.m2m_pb.clear();
     P.l2l_pb.clear();
@@ -716,7 +755,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
       maxcols = std::max(maxcols, build_plan(*P.l2l_pb[l], trp, boxes, {}, false, true, nb, P.L, nemax<T>(), {}, true));
       P.l2l_pl[l] = P.l2l_pb[l]->pl;
     }
-    P.Y.alloc(sizeof(T) * maxcols * nemax<T>() * (size_t)P.L);
+    P.Y.alloc_exact(sizeof(T) * maxcols * nemax<T>() * (size_t)P.L);
   }
   // device tree descriptor
   DevTree<T>& D = P.dt;
@@ -745,7 +784,8 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   const Prec<T>& TRs = adj ? *fwd : P;  // owner of the translation operators
   D.m2m = dptr<T>(TRs.m2m); D.l2l = dptr<T>(TRs.l2l); D.m2l = dptr<T>(TRs.m2l);
   D.dgradT = dptr<T>(TRs.dgrad); D.dhessT = dptr<T>(TRs.dhess);
-  D.m2l_plan = F.depth >= 2 ? &P.m2l_pb->pl : nullptr;
+  D.m2l_plan = F.depth >= 2 ? P.m2l_pl.data() : nullptr;
+  D.m2l_parts = F.depth >= 2 ? (int)P.m2l_pl.size() : 0;
   D.m2m_plan = F.depth >= 2 ? P.m2m_pl.data() : nullptr;
   D.l2l_plan = F.depth >= 2 ? P.l2l_pl.data() : nullptr;
   D.Y = P.Y.p;
@@ -782,29 +822,6 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   }
 }
 
-template <typename T>
-static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
-  chunk = std::max(chunk, chunk_fwd<T>());
-  if (P.ws_rhs >= chunk) return;
-  const int64_t N = ctx->N, No = P.No;
-  const int nb = P.dt.nbox;
-  const int L = P.L, p = P.p;
-  P.str.alloc(sizeof(T) * (size_t)No * 2 * chunk);
-  P.M.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
-  P.Lc.alloc(sizeof(T) * (size_t)nb * 3 * chunk * L);
-  P.D.alloc(sizeof(T) * (size_t)std::max(P.dt.n_leaf_work, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1)));
-  P.fmm.alloc(sizeof(T) * (size_t)N * 4 * chunk);
-  P.corr.alloc(sizeof(T) * (size_t)N * 4 * chunk);
-  P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
-  P.y2.alloc(sizeof(T) * (size_t)N * chunk);
-  ctx->seg_scal.alloc(sizeof(double) * (size_t)chunk * ctx->n_surf + 8);
-  P.ws_rhs = chunk;
-  // per-block partial sums: the A3 combine (4 per row block) and the GMRES
-  // dot products (256 blocks per basis vector)
-  ctx->partial.alloc(sizeof(double) * std::max<size_t>((size_t)4 * ((N + 3) / 4) + 64,
-                                                       (size_t)256 * (ctx->opts.max_iter + 2)));
-}
-
 constexpr int CHUNK_GRAD = 8;
 
 // Per-call workspace of the gradient apply for `chunk` densities per
@@ -815,16 +832,47 @@ struct ApplyWs {
   T *str = nullptr, *M = nullptr, *Lc = nullptr, *D = nullptr, *fmm = nullptr, *corr = nullptr;
 };
 
-// element counts of the ApplyWs buffers (the sizes ensure_ws allocates)
+// element counts of the ApplyWs buffers for traversals of at most `chunk`
+// densities (gradient or potential applies: one expansion per density; A3:
+// three per density for at most chunk_a3 densities)
 template <typename T>
 static void ws_counts(const lb_ctx* ctx, const Prec<T>& P, int chunk, size_t cnt[6]) {
-  const int p = P.p;
+  const int c3 = std::min(chunk, chunk_a3<T>());
+  const size_t ne = (size_t)std::max(chunk, 3 * c3);
+  const int64_t dpd = std::max({(int64_t)chunk * leaf_d_stride<T>(FMM_GRAD, P.p),
+                                (int64_t)chunk * leaf_d_stride<T>(FMM_POT, P.p),
+                                (int64_t)c3 * leaf_d_stride<T>(FMM_A3B, P.p)});
   cnt[0] = (size_t)P.No * 2 * chunk;
-  cnt[1] = (size_t)P.dt.nbox * 3 * chunk * P.L;
+  cnt[1] = (size_t)P.dt.nbox * ne * P.L;
   cnt[2] = cnt[1];
-  cnt[3] = (size_t)std::max(P.dt.n_leaf_work, 1) * chunk * (3 * 3 * p * p + 9 * (p - 1) * (p - 1));
+  cnt[3] = (size_t)std::max(P.dt.n_leaf_work, 1) * (size_t)dpd;
   cnt[4] = (size_t)ctx->N * 4 * chunk;
   cnt[5] = (size_t)ctx->N * 4 * chunk;
+}
+
+template <typename T>
+static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
+  chunk = std::max(chunk, chunk_fwd<T>());
+  if (P.ws_rhs >= chunk) return;
+  const int64_t N = ctx->N;
+  size_t cnt[6];
+  ws_counts<T>(ctx, P, chunk, cnt);
+  // exact sizes: a rebuild with a shallower tree gives back what a deeper
+  // one took
+  P.str.alloc_exact(sizeof(T) * cnt[0]);
+  P.M.alloc_exact(sizeof(T) * cnt[1]);
+  P.Lc.alloc_exact(sizeof(T) * cnt[2]);
+  P.D.alloc_exact(sizeof(T) * std::max<size_t>(cnt[3], 1));
+  P.fmm.alloc_exact(sizeof(T) * cnt[4]);
+  P.corr.alloc_exact(sizeof(T) * cnt[5]);
+  P.mu.alloc(sizeof(T) * (size_t)N * 2 * chunk);
+  P.y2.alloc(sizeof(T) * (size_t)N * chunk);
+  ctx->seg_scal.alloc(sizeof(double) * (size_t)chunk * ctx->n_surf + 8);
+  P.ws_rhs = chunk;
+  // per-block partial sums: the A3 combine (4 per row block) and the GMRES
+  // dot products (256 blocks per basis vector)
+  ctx->partial.alloc(sizeof(double) * std::max<size_t>((size_t)4 * ((N + 3) / 4) + 64,
+                                                       (size_t)256 * (ctx->opts.max_iter + 2)));
 }
 
 template <typename T>
@@ -1063,6 +1111,8 @@ template <typename T>
 static void rebuild_trees(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built, int leaf_src) {
   HIPTRY(hipDeviceSynchronize());
   ctx->reset_graphs();
+  // the old trees' workspaces go first (a deep candidate's are large)
+  for (DBuf* b : {&P.str, &P.M, &P.Lc, &P.D, &P.fmm, &P.corr, &P.Y}) b->release();
   const bool fp32 = sizeof(T) == 4;
   build_prec<T>(ctx, P, P.p, std::vector<double>(), fp32 ? ctx->rm2f : std::vector<float>(), P.min_leaf_side,
                 leaf_src, P.direct);

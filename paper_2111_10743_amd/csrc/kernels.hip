@@ -1198,6 +1198,20 @@ void k_leaf(DevTree<T> t, int nrhs, const T* __restrict__ str, int64_t No, const
   }
 }
 
+// Values per (work item, density) the leaf kernels of `mode` read and write
+// in the workspace D: zero when every part keeps its expansions in LDS (the
+// choices of launch_leaf below, taken for the part that also stages sources).
+template <typename T>
+int64_t leaf_d_stride(int mode, int p) {
+  const size_t chunk = sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
+  if (chunk + leaf_exp_bytes<T>(mode, p) <= 40 * 1024) return 0;
+  const size_t stat = sizeof(T) * RECTAB_N + 512;
+  if (mode == FMM_A3B && leaf_far_split_bytes<T>(LEAF_FAR1, p) + stat <= 64 * 1024 &&
+      leaf_far_split_bytes<T>(LEAF_FAR2, p) + stat <= 64 * 1024)
+    return 0;
+  return (int64_t)fmm_nexp(mode) * 3 * p * p + 9 * (int64_t)(p - 1) * (p - 1);
+}
+
 template <typename T>
 static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const T* str, const T* Lc, T* D, T* out,
                         int64_t N, int64_t No, hipStream_t st) {
@@ -1305,7 +1319,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     T* Y = (T*)t.Y;
     for (int l = t.depth - 1; l >= 2; --l) run_plan<T>(t.m2m_plan[l], t.m2m, L, ne, M, Y, M, st);
     tm->mark(PH_M2L, st);
-    run_plan<T>(*t.m2l_plan, t.m2l, L, ne, M, Y, Lc, st);
+    for (int q = 0; q < t.m2l_parts; ++q) run_plan<T>(t.m2l_plan[q], t.m2l, L, ne, M, Y, Lc, st);
     tm->mark(PH_L2L, st);
     for (int l = 3; l <= t.depth; ++l) run_plan<T>(t.l2l_plan[l], t.l2l, L, ne, Lc, Y, Lc, st);
   } else {
@@ -2489,6 +2503,7 @@ void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, 
                                       const T*, const T*, int64_t, const T*, const int*, const T*, const double*, \
                                       int, const int64_t*, const int*, const double*, T*, T*, double*, hipStream_t);                                     \
   template void launch_p2m_tables<T>(const DevTree<T>&, T*, T*, hipStream_t);                                  \
+  template int64_t leaf_d_stride<T>(int, int);                                                                  \
   template void launch_combine_pot<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*, const T*, \
                                       const int*, T*, hipStream_t);                                             \
   template void launch_adj_strengths<T>(int, int64_t, const T*, const T*, const T*, const T*, const T*,          \

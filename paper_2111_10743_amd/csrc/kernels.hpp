@@ -100,9 +100,10 @@ struct DevTree {
   const T *m2m, *l2l, *m2l;  // transposed [..][in][out]
   const T *dgradT, *dhessT;  // transposed [t][in][out]
   const GemmPlan* m2l_plan;   // host structs with device pointers (nullable):
-  const GemmPlan* m2m_plan;   //   M2L over all levels; M2M and L2L indexed by level (all trees)
-  const GemmPlan* l2l_plan;
-  void* Y;                    // column scratch [max columns * 8][L]
+  const GemmPlan* m2m_plan;   //   M2L over all levels in m2l_parts parts run in turn (the
+  const GemmPlan* l2l_plan;   //   first writes, the others add); M2M and L2L indexed by level
+  int m2l_parts;
+  void* Y;                    // column scratch [max columns of one plan * ne_max][L]
   const T *p2m_H, *p2m_D;     // per-source P2M tables [No][L] in tree order (nullable)
   int leaf_fmax;              // most lanes per target in the leaf kernel (power of two, 1..64)
   // host handles (nullable side): a non-blocking stream for the near-field
@@ -233,6 +234,10 @@ void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, 
 // in tree order; see k_p2m_build
 template <typename T>
 void launch_p2m_tables(const DevTree<T>& t, T* H, T* Dp, hipStream_t st);
+// values per (leaf work item, density) of the workspace D that the leaf
+// kernels of `mode` use at expansion order p (0: none)
+template <typename T>
+int64_t leaf_d_stride(int mode, int p);
 
 // full FMM (or direct sums when depth < 2): str [nrhs*nstr][No] -> out [nrhs*nout][N]
 // Optional phase timer: events recorded on the launch stream at the phase
