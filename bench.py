@@ -45,7 +45,7 @@ WORKLOADS = {
     "torus561k": ("torus", 6, (60, 167)),    # R = 2, r = 0.7: 20,040 patches, N = 561,120
     "torus1M": ("torus", 6, (90, 200)),      # 36,000 patches, N = 1,008,000
     # 64 star-shaped surfaces, faces split n_s x n_s, n_s ~ U{3..9} (seed 99):
-    # 180 .. 1,620 order-5 patches each, N = 1,060,920 in all
+    # 180 .. 1,620 order-5 patches each, 52,960 in all (N = 1,112,160)
     "stars64": ("stars", 5, 64),
 }
 
