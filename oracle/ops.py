@@ -11,6 +11,11 @@
   mu = grad_Gamma S tau, div S[mu] = sum_l d_l S[mu_l] (each Cartesian
   component of mu a density of the single layer, its x_l derivative taken),
   applied right to left.
+* Section 4.2 / eq. (ie-dis1): A2[tau] = -tau/4 + D[D tau]
+  - S[(S''+D') tau + 2 H S' tau] + S W S tau, applied right to left: mu1 = D tau,
+  mu2 = -(S''+D') tau - 2 H S' tau + W(S tau), A2 tau = -tau/4 + S mu2 + D mu1
+  (the double layer D of Section 3 with the source normal: grad_y G . nu).
+  Its right-hand side is S[f] and the solution u = S sigma (eq. ie-dis1).
 * Section 4.3 / eq. (ie-dis2): A3[tau] = -tau/4 + S'[S' tau]
   - (S''+D')[S tau] - 2 H S'[S tau] + W S[S tau], applied right to left, with
   W[phi] = sum_j w_j phi_j / sum_j w_j (the averaging operator of Section 3).
@@ -22,14 +27,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
 import numpy as np
 
-from .quad import Corrections, FOUR_PI
+from .quad import Corrections, FOUR_PI, NK
 
 
 def direct(x, n, s, nu, c, chunk=None):
     """Direct sums over all sources for targets x (T,3) with normals n (T,3).
 
-    c: strengths (No,) or (nd, No).  Returns pot (nd,T), grad (nd,T,3) and
-    sdd (nd,T) = sum c n.gradgrad G.(n - nu); every term includes 1/(4 pi).
+    c: strengths (No,) or (nd, No).  Returns pot (nd,T), grad (nd,T,3),
+    sdd (nd,T) = sum c n.gradgrad G.(n - nu) and dbl (nd,T) = sum c grad_y G . nu
+    (the double layer); every term includes 1/(4 pi).
     """
     c = np.atleast_2d(c)
     nd = c.shape[0]
@@ -37,6 +43,7 @@ def direct(x, n, s, nu, c, chunk=None):
     pot = np.zeros((nd, T))
     grad = np.zeros((nd, T, 3))
     sdd = np.zeros((nd, T))
+    dbl = np.zeros((nd, T))
     if chunk is None:
         chunk = max(1, int(4e6 // max(1, s.shape[0])))
     for t0 in range(0, T, chunk):
@@ -56,7 +63,9 @@ def direct(x, n, s, nu, c, chunk=None):
         pot[:, t0:t0 + chunk] = c @ G.T
         grad[:, t0:t0 + chunk, :] = np.einsum('dm,tmc->dtc', c, Gd)
         sdd[:, t0:t0 + chunk] = c @ H.T
-    return pot, grad, sdd
+        Dk = (nu[None, :, :] * d).sum(-1) * inv_r3 / FOUR_PI
+        dbl[:, t0:t0 + chunk] = c @ Dk.T
+    return pot, grad, sdd, dbl
 
 
 class Oracle:
@@ -81,11 +90,12 @@ class Oracle:
             n = geom.n[t][:, None, :]
             m = n - geom.nu[None, :, :]
             ndt = (n * d).sum(-1)
-            K = np.empty((6,) + r2.shape)
+            K = np.empty((NK,) + r2.shape)
             K[0] = inv_r / FOUR_PI
             K[1:4] = np.moveaxis(-d * (inv_r3 / FOUR_PI)[..., None], -1, 0)
             K[4] = -ndt * inv_r3 / FOUR_PI
             K[5] = (3.0 * ndt * (m * d).sum(-1) * inv_r3 / r2 - (n * m).sum(-1) * inv_r3) / FOUR_PI
+            K[6] = (geom.nu[None, :, :] * d).sum(-1) * inv_r3 / FOUR_PI
             self._K = K
 
     # -- pieces ---------------------------------------------------------
@@ -96,9 +106,9 @@ class Oracle:
         return g.wo * tt
 
     def layer(self, tau):
-        """All six discrete kernels applied to tau at the target rows: (T, 6).
+        """All seven discrete kernels applied to tau at the target rows: (T, 7).
 
-        Columns: S, dS/dx1, dS/dx2, dS/dx3, S', S''+D'.
+        Columns: S, dS/dx1, dS/dx2, dS/dx3, S', S''+D', D.
         """
         g = self.g
         t = self.targets
@@ -106,16 +116,17 @@ class Oracle:
         if self._K is not None:
             out = (self._K @ c).T
         else:
-            pot, grad, sdd = direct(g.x[t], g.n[t], g.s, g.nu, c)
-            out = np.empty((len(t), 6))
+            pot, grad, sdd, dbl = direct(g.x[t], g.n[t], g.s, g.nu, c)
+            out = np.empty((len(t), NK))
             out[:, 0] = pot[0]
             out[:, 1:4] = grad[0]
             out[:, 4] = (grad[0] * g.n[t]).sum(-1)
             out[:, 5] = sdd[0]
+            out[:, 6] = dbl[0]
         return out + self.corr.apply(g, tau)
 
     def operator_matrices(self):
-        """Dense matrices (6, rows, N) of the six discrete kernels (small N only)."""
+        """Dense matrices (7, rows, N) of the seven discrete kernels (small N only)."""
         g = self.g
         assert self._K is not None
         Pfull = np.zeros((g.No, g.N))
@@ -192,9 +203,9 @@ class Oracle:
         zn = np.zeros((len(nodes), 3))
         zo = np.zeros((len(over), 3))
         # grad phi at the nodes (far sum over every oversampled point)
-        _, gphi, _ = direct(g.x[nodes], zn, g.s, np.zeros_like(g.s), c)
+        _, gphi, _, _ = direct(g.x[nodes], zn, g.s, np.zeros_like(g.s), c)
         # grad psi at the oversampled points (charges gbar on every node)
-        _, gpsi, _ = direct(g.s[over], zo, g.x, np.zeros_like(g.x), gb)
+        _, gpsi, _, _ = direct(g.s[over], zo, g.x, np.zeros_like(g.x), gb)
         out = (gb[:, nodes, None] * gphi).sum(0)
         sbar = (c[:, over, None] * gpsi).sum(0).reshape(len(pts), g.n_o, 3)
         out += np.einsum('mk,pmc->pkc', g.re.P, sbar).reshape(-1, 3)
@@ -210,6 +221,16 @@ class Oracle:
         SS = S @ S
         return (-0.25 * np.eye(g.N) + Sp @ Sp - K @ S - 2.0 * g.H[:, None] * (Sp @ S)
                 + np.outer(np.ones(g.N), g.w @ SS) / g.w.sum())
+
+    def A2_matrix(self):
+        """Dense A2 of Section 4.2 from the operator matrices (all rows, small N):
+        -I/4 + D D - S ((S''+D') + 2 diag(H) S') + (1/area) S 1 w^T S."""
+        g = self.g
+        if getattr(self, "_M", None) is None:
+            self._M = self.operator_matrices()
+        S, Sp, K, D = self._M[0], self._M[4], self._M[5], self._M[6]
+        return (-0.25 * np.eye(g.N) + D @ D - S @ (K + 2.0 * g.H[:, None] * Sp)
+                + np.outer(S @ np.ones(g.N), g.w @ S) / g.w.sum())
 
     def A1_matrix(self):
         """Dense A1 of Section 4.1 from the operator matrices (all rows, small N):
@@ -263,6 +284,23 @@ class Oracle:
         Lb = self.layer(mu2)
         return (-0.25 * tau + La[:, 4] - Lb[:, 5] - 2.0 * g.H * Lb[:, 4]
                 + self.W(Lb[:, 0]))
+
+    def A2(self, tau):
+        """Section 4.2; needs all rows (targets == all nodes)."""
+        g = self.g
+        assert len(self.targets) == g.N
+        L1 = self.layer(tau)
+        mu1 = L1[:, 6]                                              # D tau
+        mu2 = -L1[:, 5] - 2.0 * g.H * L1[:, 4] + self.W(L1[:, 0])   # -(S''+D'+2HS') tau + W S tau
+        return -0.25 * tau + self.layer(mu2)[:, 0] + self.layer(mu1)[:, 6]
+
+    def solve_A2(self, f, tol=1e-12, max_iter=100):
+        """u = S sigma with A2 sigma = S[f - mean] (eq. ie-dis1), plus info."""
+        f = np.asarray(f, dtype=float)
+        fz = f - self.W(f)
+        sigma, info = gmres(self.A2, self.apply_S(fz), tol=tol, max_iter=max_iter)
+        info["sigma"] = sigma
+        return self.apply_S(sigma), info
 
     def solve(self, f, tol=1e-12, max_iter=100):
         """u solving Delta_Gamma u = f (mean-projected f), plus info dict."""

@@ -26,6 +26,9 @@ third-party package that is not reproduced; this module computes A with
   as exclusion set: its 1/s part is subtracted and integrated analytically
   (Guiggiani-Gigante singularity subtraction), which adds f_{-1} ln|B| with
   B the chart's tangent along the ray.
+  The double layer D has the same 1/s^2 term as S' with the opposite sign
+  (non-zero on the interpolated chart only through the interpolation error),
+  and takes the same subtraction.
 * other near patches: level-by-level 4-way subdivision of T0 with a conical
   Gauss rule on each leaf; a leaf is accepted once its distance to the target
   is at least ``adm`` times its diameter.
@@ -35,6 +38,9 @@ Kernels (x target with normal n, y source with normal nu, d = x - y, r = |d|):
   G_l  : d/dx_l of 1/(4 pi r) = -d_l/(4 pi r^3)            (l = 1, 2, 3)
   S'   : n . grad_x G
   SDD  : n . grad grad G . (n - nu)   (S'' + D', Section 3)
+  D    : grad_y G . nu = (nu . d)/(4 pi r^3)   (the double layer, Section 3;
+         weakly singular on a smooth surface, nu . d = O(r^2), so its
+         on-surface principal value is the improper integral)
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
 import numpy as np
@@ -42,12 +48,12 @@ import numpy as np
 from .refelem import basis, gauss01, conical_rule
 
 FOUR_PI = 4.0 * np.pi
-NK = 6  # S, Gx, Gy, Gz, S', SDD
-KNAMES = ("S", "Gx", "Gy", "Gz", "Sp", "SDD")
+NK = 7  # S, Gx, Gy, Gz, S', SDD, D
+KNAMES = ("S", "Gx", "Gy", "Gz", "Sp", "SDD", "D")
 
 
 def kernels(x, n, y, nu):
-    """Pointwise kernel values, shape (..., 5): S, Gx, Gy, Gz, SDD."""
+    """Pointwise kernel values, shape (..., 6): S, Gx, Gy, Gz, SDD, D."""
     return kernels_d(x - y, n, nu)
 
 
@@ -57,7 +63,7 @@ def kernels_d(d, n, nu):
     r = np.sqrt(r2)
     inv_r = 1.0 / r
     inv_r3 = inv_r / r2
-    out = np.empty(d.shape[:-1] + (5,))
+    out = np.empty(d.shape[:-1] + (6,))
     out[..., 0] = inv_r / FOUR_PI
     out[..., 1:4] = -d * inv_r3[..., None] / FOUR_PI
     m = n - nu
@@ -65,6 +71,7 @@ def kernels_d(d, n, nu):
     md = (m * d).sum(-1)
     nm = (n * m).sum(-1)
     out[..., 4] = (3.0 * nd * md * inv_r3 / r2 - nm * inv_r3) / FOUR_PI
+    out[..., 5] = (nu * d).sum(-1) * inv_r3 / FOUR_PI
     return out
 
 
@@ -77,12 +84,14 @@ def _chart(geom, patch, uv):
     return L, X, Xu, Xv
 
 
-def _full6(vals5, n):
-    """Expand (…,5) kernel values to (…,6) with S' = n . G."""
-    out = np.empty(vals5.shape[:-1] + (6,))
-    out[..., 0:4] = vals5[..., 0:4]
-    out[..., 4] = (vals5[..., 1:4] * n).sum(-1)
-    out[..., 5] = vals5[..., 4]
+def _full(vals, n):
+    """Expand (…,6) kernel values to the NK columns S, Gx, Gy, Gz, S', SDD, D
+    with S' = n . G."""
+    out = np.empty(vals.shape[:-1] + (NK,))
+    out[..., 0:4] = vals[..., 0:4]
+    out[..., 4] = (vals[..., 1:4] * n).sum(-1)
+    out[..., 5] = vals[..., 4]
+    out[..., 6] = vals[..., 5]
     return out
 
 
@@ -90,7 +99,7 @@ def _full6(vals5, n):
 # self patch: Duffy + sinh + principal-value subtraction
 # ----------------------------------------------------------------------
 def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
-    """A^K_{i, p(i), k} for the given target nodes: array (T, n_p, 6).
+    """A^K_{i, p(i), k} for the given target nodes: array (T, n_p, NK).
 
     ns Gauss points along the ray; the sinh-graded edge variable is split into
     ceil(length / panel) equal panels of nt Gauss points each.
@@ -102,7 +111,7 @@ def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
     tg, tw = gauss01(nt)
     mg, mw = gauss01((geom.k + 1) // 2)      # exact for the degree k - 1 of X'
     verts = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
-    out = np.zeros((len(targets), n_p, 6))
+    out = np.zeros((len(targets), n_p, NK))
     for ti, i in enumerate(targets):
         pch = geom.patch_of[i]
         a = geom.local_of[i]
@@ -112,7 +121,7 @@ def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
         Ji = geom.J[i]
         dXu = geom.dXu[pch, a]
         dXv = geom.dXv[pch, a]
-        acc = np.zeros((n_p, 6))
+        acc = np.zeros((n_p, NK))
         # metric of the interpolated chart at the node: the edge coordinate is
         # graded with sinh in the metric arclength, so that |X(y) - x_i| is
         # exactly s * h cosh(t) for an affine chart
@@ -149,9 +158,9 @@ def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
             Xd = (np.einsum('tsmb,bc->tsmc', Lm, geom.dXu[pch]) * dvec[:, None, None, 0:1]
                   + np.einsum('tsmb,bc->tsmc', Lm, geom.dXv[pch]) * dvec[:, None, None, 1:2])
             d = -(sg[None, :, None] * np.einsum('m,tsmc->tsc', mw, Xd)).reshape(-1, 3)
-            kv = _full6(kernels_d(d, ni[None, :], nu), ni[None, :])             # (nt*ns, 6)
+            kv = _full(kernels_d(d, ni[None, :], nu), ni[None, :])              # (nt*ns, NK)
             wgt = (jac_t[:, None] * sg[None, :] * wtau[:, None] * sw[None, :]).reshape(-1)
-            f = kv * (J * wgt)[:, None]                                     # (M, 6)
+            f = kv * (J * wgt)[:, None]                                     # (M, NK)
             acc += L.T @ f
             # principal-value subtraction for the gradient kernels (cols 1..4)
             B = dvec[:, 0:1] * dXu[None, :] + dvec[:, 1:2] * dXv[None, :]     # (nt,3)
@@ -162,6 +171,9 @@ def self_integrals(geom, targets, ns=16, nt=12, panel=2.0):
             sub = (sw / sg).sum()
             corr = (wtau[:, None] * fm1_full * (np.log(Bn)[:, None] - sub)).sum(0)
             acc[a, 1:5] += corr
+            # D has the 1/s^2 part of S' with the opposite sign (nu . d = -n . d
+            # to first order along the ray): the same principal value
+            acc[a, 6] -= corr[3]
         out[ti] = acc
     return out
 
@@ -175,7 +187,7 @@ def near_integrals(geom, tgt, pch, qa=8, adm=2.0, max_depth=16):
     pch = np.asarray(pch)
     M = len(tgt)
     n_p = geom.n_p
-    out = np.zeros((M, n_p, 6))
+    out = np.zeros((M, n_p, NK))
     ru, rw = conical_rule(qa)
     tri = np.array([[[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]])
     pair = np.arange(M)
@@ -214,10 +226,10 @@ def near_integrals(geom, tgt, pch, qa=8, adm=2.0, max_depth=16):
                 J = np.linalg.norm(cr, axis=-1)
                 nu = cr / J[:, None]
                 tt = np.repeat(tgt[apc], nq)
-                kv = _full6(kernels(geom.x[tt], geom.n[tt], X, nu), geom.n[tt])
+                kv = _full(kernels(geom.x[tt], geom.n[tt], X, nu), geom.n[tt])
                 wq = (area2[sl][:, None] * rw[None, :]).reshape(-1) * J
-                f = kv * wq[:, None]                                    # (m,6)
-                contrib = np.einsum('mb,mk->mbk', L, f).reshape(len(apc), nq, n_p, 6).sum(1)
+                f = kv * wq[:, None]                                    # (m, NK)
+                contrib = np.einsum('mb,mk->mbk', L, f).reshape(len(apc), nq, n_p, NK).sum(1)
                 np.add.at(out, apc, contrib)
         rej = ~acc
         if not rej.any():
@@ -238,12 +250,12 @@ def near_integrals(geom, tgt, pch, qa=8, adm=2.0, max_depth=16):
 
 
 def far_rule(geom, tgt, pch):
-    """B^K_{i,l,k}: the oversampled rule restricted to patch l, (M, n_p, 6)."""
+    """B^K_{i,l,k}: the oversampled rule restricted to patch l, (M, n_p, NK)."""
     tgt = np.asarray(tgt)
     pch = np.asarray(pch)
     n_o = geom.n_o
     P = geom.re.P
-    out = np.empty((len(tgt), geom.n_p, 6))
+    out = np.empty((len(tgt), geom.n_p, NK))
     CH = 2048
     for c0 in range(0, len(tgt), CH):
         t = tgt[c0:c0 + CH]
@@ -251,7 +263,7 @@ def far_rule(geom, tgt, pch):
         idx = p[:, None] * n_o + np.arange(n_o)[None, :]
         y = geom.s[idx]
         nu = geom.nu[idx]
-        kv = _full6(kernels(geom.x[t][:, None, :], geom.n[t][:, None, :], y, nu), geom.n[t][:, None, :])
+        kv = _full(kernels(geom.x[t][:, None, :], geom.n[t][:, None, :], y, nu), geom.n[t][:, None, :])
         kv = kv * geom.wo[idx][..., None]
         out[c0:c0 + CH] = np.einsum('mok,ob->mbk', kv, P)
     return out
@@ -281,7 +293,7 @@ class Corrections:
         self.rows = rows
 
     def apply(self, geom, tau):
-        """Near-correction part sum_l sum_k C_{i,lk} tau_lk for each row, (T, 6)."""
+        """Near-correction part sum_l sum_k C_{i,lk} tau_lk for each row, (T, NK)."""
         tau_p = np.asarray(tau).reshape(geom.NP, geom.n_p)
         contrib = np.einsum('jbk,jb->jk', self.C, tau_p[self.patch])
         out = np.zeros((len(self.targets), NK))

@@ -1,9 +1,12 @@
 """The stored oracle outputs (tests/golden/oracle_*.npz, written by
-make_oracle_golden.py) are the oracle's: the six layer columns on sampled
+make_oracle_golden.py) are the oracle's: the seven layer columns on sampled
 rows of the ellipsoid recomputed here by a row-restricted oracle with its own
 corrections (the same arithmetic per row), and the stored solutions are mean
 zero in the smooth weights (Lemma 1) and their count of GMRES iterations is
-in the range the paper's Table 3 reports for A3 (a handful)."""
+in the range the paper's Table 3 reports for A3 (a handful).  The ellipsoid's
+solves by A2 (Section 4.2) return x_1 minus its mean for f = -2 H n_1 (the
+manufactured phi = x_1) to the discretization error and agree with the
+solves by A3 to it (the two formulations share the continuum solution)."""
 import os
 import sys
 
@@ -35,3 +38,16 @@ def test_golden_solutions_mean_zero():
         for u in ref["u"]:
             assert abs((g.w * u).sum()) < 1e-4 * np.sqrt((g.w * u * u).sum() * g.w.sum())
         assert np.all((ref["iters"] >= 3) & (ref["iters"] <= 15))
+
+
+def test_golden_A2_solves():
+    X, Xu, Xv, k = G.surface("ellipsoid320_k6")
+    g = Geometry(X, Xu, Xv, k)
+    ref = np.load(os.path.join(HERE, "golden", "oracle_ellipsoid320_k6.npz"))
+    x1 = g.x[:, 0] - (g.w * g.x[:, 0]).sum() / g.w.sum()
+    rel = lambda a, b: np.sqrt((g.w * (a - b) ** 2).sum() / (g.w * b * b).sum())
+    assert rel(ref["u_A2"][1], x1) < 2e-5
+    assert rel(ref["u"][1], x1) < 2e-5
+    for a2, a3 in zip(ref["u_A2"], ref["u"]):
+        assert rel(a2, a3) < 2e-5
+    assert np.all((ref["iters_A2"] >= 3) & (ref["iters_A2"] <= 20))

@@ -105,8 +105,9 @@ def _flat():
 @pytest.mark.parametrize("name", ["flat", "sphere", "ellipsoid"])
 def test_self_rule_converged(name):
     """Default self rule (16 x 12) against 24 x 20 on sampled targets, column
-    by column (S, dS/dx1..3, S', S''+D'), relative to each column's largest
-    entry; on the flat triangle S' and S''+D' vanish and are held absolutely."""
+    by column (S, dS/dx1..3, S', S''+D', D), relative to each column's
+    largest entry; on the flat triangle S', S''+D' and D vanish and are held
+    absolutely."""
     if name == "flat":
         g = _flat()
     else:
@@ -125,6 +126,7 @@ def test_self_rule_converged(name):
     else:
         assert d[4] < 2e-10 * sc[4]
         assert d[5] < 3e-9 * sc[5]
+        assert d[6] < 2e-10 * sc[6]
 
 
 @pytest.mark.parametrize("name", ["sphere", "ellipsoid"])
@@ -140,4 +142,4 @@ def test_self_rule_translation_invariant(name):
     sc = np.abs(a).max(axis=(0, 1))
     d = np.abs(a - b).max(axis=(0, 1)) / sc
     print(name, " ".join(f"{x:.1e}" for x in d))
-    assert np.all(d[:5] < 2e-11) and d[5] < 1e-10
+    assert np.all(d[:5] < 2e-11) and d[5] < 1e-10 and d[6] < 2e-11
