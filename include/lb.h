@@ -197,9 +197,10 @@ lb_status lb_get_geometry(const lb_ctx *ctx, double *w, double *normals, double 
 
 /* Host copy of the FP64 near corrections C = A - B (eq. nys-lcq2) in block
  * CSR form: row_ptr [N+1] (int64), patch [nnz_blocks] (int32) and
- * vals [nnz_blocks][n_p][6] for the kernels S, dS/dx1, dS/dx2, dS/dx3, S',
- * S''+D' (all including the 1/(4 pi) of the Green's function).  Works on a
- * LB_HOST_ONLY context.  Any output may be NULL. */
+ * vals [nnz_blocks][n_p][7] for the kernels S, dS/dx1, dS/dx2, dS/dx3, S',
+ * S''+D' and the double layer D = grad_y G . nu (Section 3), all including
+ * the 1/(4 pi) of the Green's function.  Works on a LB_HOST_ONLY context.
+ * Any output may be NULL. */
 lb_status lb_get_corrections(const lb_ctx *ctx, int64_t *row_ptr, int32_t *patch,
                              double *vals);
 
@@ -418,6 +419,18 @@ lb_status lb_solve_adj(lb_ctx *ctx, int nrhs, const double *ubar, double *fbar, 
  * computed on first use).  tau, out: device [nd][N] in the precision `prec`
  * (32 or 64).  Stream-ordered.  Errors as lb_apply_S. */
 lb_status lb_apply_A1(lb_ctx *ctx, int nd, int prec, const void *tau, void *out, void *stream);
+
+/* A2 (Section 4.2, eq. ie-dis1): A2[tau] = -tau/4 + D D tau
+ * - S (S'' + D' + 2 H S') tau + S W S tau, the second-kind discretization of
+ * S (Delta + W) S with the double layer D = grad_y G . nu (Section 3), applied
+ * right to left: mu1 = D tau and mu2 = -(S''+D'+2HS') tau + W S tau from one
+ * charge + dipole FMM (S, S', S''+D' of tau) and one dipole FMM (D tau), then
+ * A2 tau = -tau/4 + S mu2 + D mu1 from one charge + dipole potential FMM, each
+ * with its near corrections (the D column of lb_get_corrections included).
+ * tau, out: device [nd][N] in the precision `prec` (32 or 64).  A2's
+ * right-hand side is S[f] and its solution u = S sigma (eq. ie-dis1).
+ * Stream-ordered.  Errors as lb_apply_S. */
+lb_status lb_apply_A2(lb_ctx *ctx, int nd, int prec, const void *tau, void *out, void *stream);
 
 /* Surface gradient of node values (Section 2): on each patch the order-k
  * interpolant of psi differentiated along the chart, with the metric of the

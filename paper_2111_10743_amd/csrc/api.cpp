@@ -214,7 +214,7 @@ struct Prec {
   DBuf tgt_beg, tgt_end, src_beg, src_end, ulist_ptr, ulist, vlist_ptr, vlist_src, vlist_off;
   DBuf parent, child, child_src, leaf_tgt, leaf_src, lev_src, lev_src_ptr, lev_tgt, lev_tgt_ptr;
   DBuf leaf_box, leaf_lvl, leaf_h;
-  DBuf tgt_pos, src_pos, P, wo, vals4, vals3, nrm, H;
+  DBuf tgt_pos, src_pos, P, wo, vals4, vals3, valsD, nrm, H;
   DBuf m2m, l2l, m2l, dgrad, dhess;
   // batched translation plans (M2L over all levels; M2M, L2L per level)
   std::vector<std::unique_ptr<PlanBuf>> m2l_pb, m2m_pb, l2l_pb;
@@ -223,6 +223,7 @@ struct Prec {
   DBuf p2m_H, p2m_D;
   // work
   DBuf str, M, Lc, D, fmm, mu, y2, tmp_in, tmp_out;
+  DBuf a2s;  // A2: strengths of tau, then of mu1 and mu2 [2][chunk_a3][No]
   int ws_rhs = 0;
   // position derivative: mask radii that exclude only coincident points
   // (forward tree) and gradient outputs at the targets (transposed tree)
@@ -258,7 +259,7 @@ struct lb_ctx {
   std::unique_ptr<RefElem> re;    // order k, the FP64 far rule (q = over_q)
   std::unique_ptr<RefElem> re32;  // order k, the FP32 far rule (q = over_q32)
   Surface S;
-  std::vector<double> C64;  // [nnzb][n_p][6]
+  std::vector<double> C64;  // [nnzb][n_p][NKER]
   bool host_only = false;
   int device = 0;
   Prec<float> f32;
@@ -343,16 +344,19 @@ static void transpose_blocks(const V& src, int nblk, int rows, int cols, big_vec
         dst[(size_t)b * rows * cols + (size_t)c * rows + r] = (T)src[(size_t)b * rows * cols + (size_t)r * cols + c];
 }
 
-// pack [nnzb][n_p][6] corrections into the gradS (k=4: S, Gx, Gy, Gz) and
-// A3 (k=3: S, S', S''+D') layouts
+// pack [nnzb][n_p][NKER] corrections into the gradS (k=4: S, Gx, Gy, Gz),
+// A3 (k=3: S, S', S''+D') and double-layer (k=1: D) layouts
 template <typename T>
-static void pack_vals(const std::vector<double>& C, int64_t nnz, std::vector<T>& v4, std::vector<T>& v3) {
+static void pack_vals(const std::vector<double>& C, int64_t nnz, std::vector<T>& v4, std::vector<T>& v3,
+                      std::vector<T>& vD) {
   v4.resize((size_t)nnz * 4);
   v3.resize((size_t)nnz * 3);
+  vD.resize((size_t)nnz);
   for (int64_t e = 0; e < nnz; ++e) {
-    const double* c = &C[(size_t)e * 6];
+    const double* c = &C[(size_t)e * NKER];
     v4[4 * e] = (T)c[0]; v4[4 * e + 1] = (T)c[1]; v4[4 * e + 2] = (T)c[2]; v4[4 * e + 3] = (T)c[3];
     v3[3 * e] = (T)c[0]; v3[3 * e + 1] = (T)c[4]; v3[3 * e + 2] = (T)c[5];
+    vD[e] = (T)c[6];
   }
 }
 
@@ -528,7 +532,7 @@ static OverView over_view(const lb_ctx* ctx) {
 template <typename T>
 static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>& C, const std::vector<float>& rm2f,
                        double min_leaf_side, int leaf_src, bool direct, const Prec<T>* fwd = nullptr,
-                       DBuf* dev_v4 = nullptr, DBuf* dev_v3 = nullptr) {
+                       DBuf* dev_v4 = nullptr, DBuf* dev_v3 = nullptr, DBuf* dev_vD = nullptr) {
   const Surface& S = ctx->S;
   const bool adj = fwd != nullptr;
   const OverView ov = over_view<T>(ctx);
@@ -637,7 +641,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
   upload(P.tgt_pos, tp); upload(P.src_pos, sp);
   // node data and corrections do not depend on the tree: a rebuild (empty C)
   // keeps them where they are
-  // (dev_v4, dev_v3: corrections already on the device in the packed
+  // (dev_v4, dev_v3, dev_vD: corrections already on the device in the packed
   // layouts, taken over)
   if (!adj && (!C.empty() || dev_v4)) {
     upload_as<T>(P.P, *ov.P);
@@ -647,11 +651,13 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
     if (dev_v4) {
       std::swap(P.vals4.p, dev_v4->p); std::swap(P.vals4.bytes, dev_v4->bytes);
       std::swap(P.vals3.p, dev_v3->p); std::swap(P.vals3.bytes, dev_v3->bytes);
+      std::swap(P.valsD.p, dev_vD->p); std::swap(P.valsD.bytes, dev_vD->bytes);
     } else {
-      std::vector<T> v4, v3;
-      pack_vals(C, (int64_t)C.size() / 6, v4, v3);
+      std::vector<T> v4, v3, vD;
+      pack_vals(C, (int64_t)C.size() / NKER, v4, v3, vD);
       upload(P.vals4, v4);
       upload(P.vals3, v3);
+      upload(P.valsD, vD);
     }
   }
   // translations (level independent: built once)
@@ -841,7 +847,8 @@ static void ws_counts(const lb_ctx* ctx, const Prec<T>& P, int chunk, size_t cnt
   const size_t ne = (size_t)std::max(chunk, 3 * c3);
   const int64_t dpd = std::max({(int64_t)chunk * leaf_d_stride<T>(FMM_GRAD, P.p),
                                 (int64_t)chunk * leaf_d_stride<T>(FMM_POT, P.p),
-                                (int64_t)c3 * leaf_d_stride<T>(FMM_A3B, P.p)});
+                                (int64_t)c3 * leaf_d_stride<T>(FMM_A3B, P.p),
+                                (int64_t)c3 * leaf_d_stride<T>(FMM_ADJ, P.p)});
   cnt[0] = (size_t)P.No * 2 * chunk;
   cnt[1] = (size_t)P.dt.nbox * ne * P.L;
   cnt[2] = cnt[1];
@@ -859,7 +866,8 @@ static void ensure_ws(lb_ctx* ctx, Prec<T>& P, int chunk) {
   ws_counts<T>(ctx, P, chunk, cnt);
   // exact sizes: a rebuild with a shallower tree gives back what a deeper
   // one took
-  P.str.alloc_exact(sizeof(T) * cnt[0]);
+  // (the A2 apply keeps two strength layouts, 2 + 4 values per density)
+  P.str.alloc_exact(sizeof(T) * std::max(cnt[0], (size_t)P.No * 6 * std::min(chunk, chunk_a3<T>())));
   P.M.alloc_exact(sizeof(T) * cnt[1]);
   P.Lc.alloc_exact(sizeof(T) * cnt[2]);
   P.D.alloc_exact(sizeof(T) * std::max<size_t>(cnt[3], 1));
@@ -966,6 +974,54 @@ static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hi
                           ctx->n_surf, dptr<int64_t>(ctx->node_off), dptr<int>(ctx->node_surf),
                           dptr<double>(ctx->inv_area), out + (int64_t)d0 * N, dptr<T>(P.y2),
                           dptr<double>(ctx->seg_scal), st);
+  }
+}
+
+// A2 (Section 4.2, eq. ie-dis1) for nd densities, chunk_a3 per traversal:
+// the first pass is the A3 second pass's FMM (charges 0 and tau, dipole
+// tau nu: S, S', S''+D' of tau) plus a dipole-potential FMM (D tau); then
+// mu1 = D tau, mu2 = -(S''+D'+2HS') tau + W S tau, and one FMM of the
+// charge mu2 and dipole mu1 nu gives A2 tau = -tau/4 + S mu2 + D mu1 (the
+// D^2 term of eq. ie-dis1 is D mu1 with a plus sign).
+template <typename T>
+static void apply_A2_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
+  ensure_ws(ctx, P, CHUNK_GRAD);
+  const int64_t N = ctx->N, No = P.No;
+  const int cmax = chunk_a3<T>();
+  if ((size_t)6 * cmax * No > P.str.bytes / sizeof(T) || (size_t)2 * cmax * N > P.mu.bytes / sizeof(T))
+    fail(LB_EINVAL, "A2 workspace too small");
+  P.a2s.alloc(sizeof(T) * (size_t)No * 2 * cmax);
+  T* c1 = dptr<T>(P.a2s);
+  T* c2 = c1 + (size_t)cmax * No;
+  T* s3 = dptr<T>(P.str);                  // [c][2][No]
+  T* sd = s3 + (size_t)2 * cmax * No;      // [c][4][No]
+  T* mu1 = dptr<T>(P.mu);
+  T* mu2 = mu1 + (size_t)cmax * N;
+  T* fd = dptr<T>(P.corr);
+  for (int d0 = 0; d0 < nd; d0 += cmax) {
+    const int c = std::min(cmax, nd - d0);
+    const T* td = tau + (int64_t)d0 * N;
+    launch_strengths<T>(td, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+                        c1, st);
+    launch_a2_str1<T>(c, No, c1, dptr<T>(P.snx), dptr<T>(P.sny), dptr<T>(P.snz), s3, sd, st);
+    launch_fmm<T>(P.dt, FMM_A3B, c, s3, dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), dptr<T>(P.fmm), N, No, st);
+    launch_fmm<T>(P.dt, FMM_ADJ, c, sd, dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), fd, N, No, st);
+    launch_combine_a2a<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3),
+                          dptr<T>(P.valsD), td, dptr<T>(P.fmm), fd, dptr<int>(P.tgt_pos), dptr<T>(P.H), mu1, mu2,
+                          dptr<T>(P.y2), st);
+    // W S tau (the average over each surface) onto mu2
+    launch_seg_dot<T>(c, ctx->n_surf, N, dptr<int64_t>(ctx->node_off), dptr<T>(P.y2), dptr<double>(ctx->w),
+                      dptr<double>(ctx->inv_area), dptr<double>(ctx->seg_scal), st);
+    launch_seg_axpy<T>(c, ctx->n_surf, N, dptr<int>(ctx->node_surf), mu2, 1.0, nullptr,
+                       dptr<double>(ctx->seg_scal), mu2, st);
+    launch_strengths<T>(mu1, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+                        c1, st);
+    launch_strengths<T>(mu2, c, N, ctx->NP, ctx->n_p, P.n_o, dptr<T>(P.P), dptr<T>(P.wo), dptr<int>(P.src_pos), No,
+                        c2, st);
+    launch_a2_str2<T>(c, No, c1, c2, dptr<T>(P.snx), dptr<T>(P.sny), dptr<T>(P.snz), sd, st);
+    launch_fmm<T>(P.dt, FMM_ADJ, c, sd, dptr<T>(P.M), dptr<T>(P.Lc), dptr<T>(P.D), fd, N, No, st);
+    launch_combine_a2b<T>(c, N, ctx->n_p, dptr<int64_t>(ctx->row_ptr), dptr<int>(ctx->patch), dptr<T>(P.vals3),
+                          dptr<T>(P.valsD), td, mu1, mu2, fd, dptr<int>(P.tgt_pos), out + (int64_t)d0 * N, st);
   }
 }
 
@@ -1697,10 +1753,10 @@ lb_status lb_ref_nodes(int order, double* uv, double* w_ref) {
 namespace lb {
 // Corrections C = A - B of every (target, near patch) block on the device
 // (self rule, adaptive near rule, far rule with and without the FP32 mask),
-// left in the packed layouts of the combine kernels: v4 (S, Gx, Gy, Gz) and
-// v3 (S, S', S''+D') per (block, node), FP64 and FP32.
+// left in the packed layouts of the combine kernels: v4 (S, Gx, Gy, Gz), v3
+// (S, S', S''+D') and vD (D) per (block, node), FP64 and FP32.
 struct DevCorrections {
-  DBuf v4_64, v3_64, v4_32, v3_32;
+  DBuf v4_64, v3_64, vD_64, v4_32, v3_32, vD_32;
 };
 
 static void corrections_device(const Surface& S, const RefElem& re, const QuadOpts& qo, const std::vector<float>& rm2,
@@ -1736,7 +1792,7 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
   upload(drow, row); upload(dblk, blk); upload(dpat, pat); upload(dsblk, sblk); upload(dbrow, brow);
   upload(dnp, S.near_patch);
   upload(ds, S.s); upload(dnu, S.nu); upload(dwo, S.wo); upload(drm2, rm2); upload(dP, re.P);
-  dA.alloc(sizeof(double) * (size_t)nb * n_p * 6);
+  dA.alloc(sizeof(double) * (size_t)nb * n_p * NKER);
   SelfQuadArgs sq;
   sq.X = dptr<double>(dX); sq.nrm = dptr<double>(dn); sq.dXu = dptr<double>(ddXu); sq.dXv = dptr<double>(ddXv);
   sq.J = dptr<double>(dJ);
@@ -1760,15 +1816,17 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
   const size_t ne = (size_t)nb * n_p;
   out.v4_64.alloc(sizeof(double) * ne * 4);
   out.v3_64.alloc(sizeof(double) * ne * 3);
+  out.vD_64.alloc(sizeof(double) * ne);
   out.v4_32.alloc(sizeof(float) * ne * 4);
   out.v3_32.alloc(sizeof(float) * ne * 3);
+  out.vD_32.alloc(sizeof(float) * ne);
   // FP64 values from the primary far rule
   FarRuleArgs fr;
   fr.X = sq.X; fr.nrm = sq.nrm; fr.s = dptr<double>(ds); fr.nu = dptr<double>(dnu); fr.wo = dptr<double>(dwo);
   fr.rm2 = nullptr; fr.P = dptr<double>(dP);
   fr.brow = dptr<int64_t>(dbrow); fr.patch = dptr<int32_t>(dnp); fr.A = sq.A;
-  fr.v4_64 = dptr<double>(out.v4_64); fr.v3_64 = dptr<double>(out.v3_64);
-  fr.v4_32 = nullptr; fr.v3_32 = nullptr;
+  fr.v4_64 = dptr<double>(out.v4_64); fr.v3_64 = dptr<double>(out.v3_64); fr.vD_64 = dptr<double>(out.vD_64);
+  fr.v4_32 = nullptr; fr.v3_32 = nullptr; fr.vD_32 = nullptr;
   fr.nb = nb; fr.n_p = n_p; fr.n_o = S.n_o;
   HIPTRY(launch_far_rule(fr, nullptr));
   // FP32 values from the FP32 far rule, without the points its near-field
@@ -1777,8 +1835,8 @@ static void corrections_device(const Surface& S, const RefElem& re, const QuadOp
   upload(ds32, S.o32.s); upload(dnu32, S.o32.nu); upload(dwo32, S.o32.wo); upload(dP32, S.o32.re->P);
   fr.s = dptr<double>(ds32); fr.nu = dptr<double>(dnu32); fr.wo = dptr<double>(dwo32); fr.P = dptr<double>(dP32);
   fr.rm2 = dptr<float>(drm2);
-  fr.v4_64 = nullptr; fr.v3_64 = nullptr;
-  fr.v4_32 = dptr<float>(out.v4_32); fr.v3_32 = dptr<float>(out.v3_32);
+  fr.v4_64 = nullptr; fr.v3_64 = nullptr; fr.vD_64 = nullptr;
+  fr.v4_32 = dptr<float>(out.v4_32); fr.v3_32 = dptr<float>(out.v3_32); fr.vD_32 = dptr<float>(out.vD_32);
   fr.n_o = S.o32.n_o;
   HIPTRY(launch_far_rule(fr, nullptr));
   HIPTRY(hipDeviceSynchronize());
@@ -1845,7 +1903,7 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
   // the device rules: at most 3 max_depth + 1 triangles on the near rule's
   // stack, at most 256 (node, kernel) outputs per block
   const bool dev_quad = given || (!ctx->host_only && !(o.flags & LB_HOST_QUAD) && 3 * qo.max_depth + 1 <= 72 &&
-                                  6 * S.n_p <= 256);
+                                  NKER * S.n_p <= 256);
   std::vector<double> A, B;
   if (!dev_quad) {
     near_integrals(S, qo, A);
@@ -1877,6 +1935,8 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
       std::swap(dc.v3_64.p, given->v3_64.p); std::swap(dc.v3_64.bytes, given->v3_64.bytes);
       std::swap(dc.v4_32.p, given->v4_32.p); std::swap(dc.v4_32.bytes, given->v4_32.bytes);
       std::swap(dc.v3_32.p, given->v3_32.p); std::swap(dc.v3_32.bytes, given->v3_32.bytes);
+      std::swap(dc.vD_64.p, given->vD_64.p); std::swap(dc.vD_64.bytes, given->vD_64.bytes);
+      std::swap(dc.vD_32.p, given->vD_32.p); std::swap(dc.vD_32.bytes, given->vD_32.bytes);
     } else if (dev_quad) {
       corrections_device(S, *ctx->re, qo, rm2, dc);
     } else {
@@ -1901,12 +1961,12 @@ static void setup_impl(lb_ctx* ctx, int n_surf, const int32_t* pps, int order, c
     // FP64 tree hold proportionally fewer of them
     const int leaf_src32 = std::max(16, (int)((int64_t)o.leaf_src * S.o32.n_o / S.n_o));
     build_prec<float>(ctx, ctx->f32, o.p_f32, C32, rm2, rmax * (1.0 + 1e-6), leaf_src32, direct, nullptr,
-                      dev_quad ? &dc.v4_32 : nullptr, dev_quad ? &dc.v3_32 : nullptr);
+                      dev_quad ? &dc.v4_32 : nullptr, dev_quad ? &dc.v3_32 : nullptr, dev_quad ? &dc.vD_32 : nullptr);
     C32.clear(); C32.shrink_to_fit();
     ctx->rm2f = std::move(rm2);
     // the float positions used by the mask test must be exactly the ones on the device
     build_prec<double>(ctx, ctx->f64, o.p_f64, ctx->C64, std::vector<float>(), 0.0, o.leaf_src, direct, nullptr,
-                       dev_quad ? &dc.v4_64 : nullptr, dev_quad ? &dc.v3_64 : nullptr);
+                       dev_quad ? &dc.v4_64 : nullptr, dev_quad ? &dc.v3_64 : nullptr, dev_quad ? &dc.vD_64 : nullptr);
     HIPTRY(hipDeviceSynchronize());
   }
 }
@@ -1930,7 +1990,7 @@ namespace lb {
 // FNV-1a checksum of everything before it.
 // ---------------------------------------------------------------------------
 static const char kSetupMagic[8] = {'L', 'B', 'S', 'E', 'T', 'U', 'P', 0};
-constexpr uint32_t kSetupVersion = 1;
+constexpr uint32_t kSetupVersion = 2;  // 2: the double-layer corrections
 
 struct Fnv {
   uint64_t h = 1469598103934665603ull;
@@ -2014,6 +2074,8 @@ static void export_setup(const lb_ctx* ctx, const char* path) {
   w.put(device_copy<double>(ctx->f64.vals3, ne * 3));
   w.put(device_copy<float>(ctx->f32.vals4, ne * 4));
   w.put(device_copy<float>(ctx->f32.vals3, ne * 3));
+  w.put(device_copy<double>(ctx->f64.valsD, ne));
+  w.put(device_copy<float>(ctx->f32.valsD, ne));
   const uint64_t h = w.sum.h;
   w.val<uint64_t>(h);
 }
@@ -2063,15 +2125,17 @@ static void import_setup(lb_ctx* ctx, const char* path) {
   r.get(nptr, (size_t)N + 1);
   r.get(npat, (size_t)nnzb);
   const size_t ne = (size_t)nnzb * n_p;
-  std::vector<double> v4d, v3d;
-  std::vector<float> v4f, v3f;
+  std::vector<double> v4d, v3d, vDd;
+  std::vector<float> v4f, v3f, vDf;
   r.get(v4d, ne * 4); r.get(v3d, ne * 3); r.get(v4f, ne * 4); r.get(v3f, ne * 3);
+  r.get(vDd, ne); r.get(vDf, ne);
   const uint64_t h = r.sum.h;
   if (r.val<uint64_t>() != h) fail(LB_EINVAL, "saved setup checksum mismatch (corrupt file)");
   if (opts.flags & LB_HOST_ONLY) fail(LB_EINVAL, "saved setup asks for a host-only context");
   DevCorrections dc;
   upload(dc.v4_64, v4d); upload(dc.v3_64, v3d); upload(dc.v4_32, v4f); upload(dc.v3_32, v3f);
-  v4d.clear(); v3d.clear(); v4f.clear(); v3f.clear();
+  upload(dc.vD_64, vDd); upload(dc.vD_32, vDf);
+  v4d.clear(); v3d.clear(); v4f.clear(); v3f.clear(); vDd.clear(); vDf.clear();
   setup_impl(ctx, n_surf, pps.data(), order, X.data(), Xu.data(), Xv.data(), &opts, &dc);
   if (ctx->S.near_ptr != nptr || ctx->S.near_patch != npat)
     fail(LB_EINVAL, "the near lists rebuilt from the saved charts differ from the saved ones");
@@ -2193,13 +2257,15 @@ lb_status lb_get_corrections(const lb_ctx* ctx, int64_t* row_ptr, int32_t* patch
   } else if (vals) {
     // generated on the device: unpack the FP64 combine layouts
     const size_t ne = (size_t)S.near_ptr[S.N] * S.n_p;
-    std::vector<double> v4(ne * 4), v3(ne * 3);
+    std::vector<double> v4(ne * 4), v3(ne * 3), vD(ne);
     HIPTRY(hipMemcpy(v4.data(), ctx->f64.vals4.p, sizeof(double) * v4.size(), hipMemcpyDeviceToHost));
     HIPTRY(hipMemcpy(v3.data(), ctx->f64.vals3.p, sizeof(double) * v3.size(), hipMemcpyDeviceToHost));
+    HIPTRY(hipMemcpy(vD.data(), ctx->f64.valsD.p, sizeof(double) * vD.size(), hipMemcpyDeviceToHost));
     for (size_t e = 0; e < ne; ++e) {
-      for (int t = 0; t < 4; ++t) vals[6 * e + t] = v4[4 * e + t];
-      vals[6 * e + 4] = v3[3 * e + 1];
-      vals[6 * e + 5] = v3[3 * e + 2];
+      for (int t = 0; t < 4; ++t) vals[NKER * e + t] = v4[4 * e + t];
+      vals[NKER * e + 4] = v3[3 * e + 1];
+      vals[NKER * e + 5] = v3[3 * e + 2];
+      vals[NKER * e + 6] = vD[e];
     }
   }
   API_END
@@ -2260,6 +2326,19 @@ lb_status lb_apply_A1(lb_ctx* ctx, int nd, int prec, const void* tau, void* out,
     apply_A1_t<float>(ctx, ctx->f32, ctx->a1_phi0_32, nd, (const float*)tau, (float*)out, st);
   else
     apply_A1_t<double>(ctx, ctx->f64, ctx->a1_phi0_64, nd, (const double*)tau, (double*)out, st);
+  HIPTRY(hipGetLastError());
+  API_END
+}
+
+lb_status lb_apply_A2(lb_ctx* ctx, int nd, int prec, const void* tau, void* out, void* stream) {
+  API_BEGIN
+  check_apply(ctx, nd, prec);
+  if (!tau || !out) fail(LB_EINVAL, "null tau or out");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == LB_PREC_FP32)
+    apply_A2_t<float>(ctx, ctx->f32, nd, (const float*)tau, (float*)out, st);
+  else
+    apply_A2_t<double>(ctx, ctx->f64, nd, (const double*)tau, (double*)out, st);
   HIPTRY(hipGetLastError());
   API_END
 }

@@ -919,7 +919,10 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   typedef typename Vec4<T>::type T4;
   T4* rec1 = reinterpret_cast<T4*>(tile);
   T4* rec2 = rec1 + LEAF_CH;                                                   // A3B only
-  constexpr bool TMASK = MODE == FMM_ADJ || MODE == FMM_ADJ3;  // the mask radius is the target's
+  // the mask radius is the target's in the transposed-tree modes (FMM_ADJ
+  // with target radii, FMM_ADJ3), else the source's; TMASK sizes the records
+  constexpr bool TMASK = MODE == FMM_ADJ || MODE == FMM_ADJ3;
+  const bool tmask = MODE == FMM_ADJ3 || (MODE == FMM_ADJ && t.trm2 != nullptr);
   T* trm_ = reinterpret_cast<T*>(rec1 + (MODE == FMM_A3B || TMASK ? 2 : 1) * LEAF_CH);
   __shared__ int upref[28];
   const int u0 = t.ulist_ptr[b], nU = t.ulist_ptr[b + 1] - u0;
@@ -939,7 +942,7 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     const bool act = i < tend;
     T X = 0, Y = 0, Z = 0, NX = 0, NY = 0, NZ = 0, TR = 0;
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
-    if (TMASK && act) TR = t.trm2[i];
+    if (tmask && act) TR = t.trm2[i];
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     // ---- far field: local expansions at xi = (x - c)/h, orders m = f mod F ----
     if (far && act) {
@@ -1056,7 +1059,7 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
         r1.z = t.sz[s];
         r1.w = str[(int64_t)(rhs * nstr) * No + s];
         rec1[j] = r1;
-        if (!TMASK) trm_[j] = t.rm2[s];
+        if (!tmask) trm_[j] = t.rm2[s];
         if (MODE == FMM_A3B || MODE == FMM_ADJ3) {
           T4 r2;
           r2.x = t.snx[s];
@@ -1081,8 +1084,8 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
         // one (target, source jj) pair
         auto pair = [&](int jj) __attribute__((always_inline)) {
             const T4 r1 = rec1[jj];
-            // the mask radius of the pair: the source's, or the target's in FMM_ADJ
-            const T rm = TMASK ? TR : trm_[jj];
+            // the mask radius of the pair: the source's, or the target's on the transposed tree
+            const T rm = tmask ? TR : trm_[jj];
             const T dx = X - r1.x;
             const T dy = Y - r1.y;
             const T dz = Z - r1.z;
@@ -1298,8 +1301,7 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     int ts = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (2 * Lc_));
     ts = ts < 1 ? 1 : (ts > P2M_TSMAX ? P2M_TSMAX : ts);
     size_t sm = sizeof(T) * (2 * ts * Lc_ + 5 * ts);
-    if (t.p2m_H && (mode == FMM_ADJ || mode == FMM_ADJ3))
-      fail(LB_EINVAL, "P2M tables are not built for the transposed tree");
+    if (t.p2m_H && mode == FMM_ADJ3) fail(LB_EINVAL, "P2M tables are not built for the transposed tree");
     if (mode == FMM_ADJ3) {
       int ts3 = (int)((48 * 1024 / sizeof(T) - RECTAB_N - 5 * P2M_TSMAX) / (4 * Lc_));
       ts3 = ts3 < 1 ? 1 : (ts3 > P2M_TSMAX ? P2M_TSMAX : ts3);
@@ -1308,10 +1310,10 @@ void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* 
     } else if (t.p2m_H && mode == FMM_A3B)
       hipLaunchKernelGGL((k_p2m_tab<T, true>), dim3(t.n_leaf_src, nrhs), dim3(64 * P2M_W), 0, st, t, nrhs, str, No,
                          t.p2m_H, t.p2m_D, M);
-    else if (t.p2m_H)
+    else if (t.p2m_H && mode != FMM_ADJ)
       hipLaunchKernelGGL((k_p2m_tab<T, false>), dim3(t.n_leaf_src, nrhs), dim3(64 * P2M_W), 0, st, t, nrhs, str, No,
                          t.p2m_H, t.p2m_D, M);
-    else
+    else  // (FMM_ADJ on the forward tree: arbitrary dipole vectors, harmonics on the fly)
       hipLaunchKernelGGL(k_p2m<T>, dim3(t.n_leaf_src, nrhs), dim3(256), sm, st, t, mode, nrhs, str, No, M, ts);
     KCHECK();
     if (ovl && t.fork_late) fork();
@@ -1695,6 +1697,181 @@ void launch_combine_a3b(int nd, int64_t N, int n_p, const int64_t* row_ptr, cons
   // W S[S tau] per surface: scal[d][q] = sum_{i in q} w_i y2_i / area_q
   launch_seg_dot<T>(nd, nsurf, N, node_off, y2buf, w, inv_area, scal, st);
   launch_seg_axpy<T>(nd, nsurf, N, node_surf, out, 1.0, nullptr, scal, out, st);
+}
+
+// ---------------------------------------------------------------------------
+// A2 (Section 4.2): strengths in the layouts of the two FMM calls, and the
+// corrections fused with the combination steps
+// ---------------------------------------------------------------------------
+// pass 1: from c [nd][No] (w^over P tau, tree order) the FMM_A3B strengths
+// (charges 0 and c; its dipole c nu is formed from the tree's normals)
+// [nd][2][No] and the FMM_ADJ strengths (no charge, dipole vector c nu)
+// [nd][4][No]
+template <typename T>
+__global__ void k_a2_str1(int nd, int64_t No, const T* __restrict__ c, const T* __restrict__ nx,
+                          const T* __restrict__ ny, const T* __restrict__ nz, T* __restrict__ s3, T* __restrict__ sd) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= No) return;
+  const T a = nx[m], b = ny[m], e = nz[m];
+  for (int d = 0; d < nd; ++d) {
+    const T v = c[(int64_t)d * No + m];
+    s3[(int64_t)(2 * d) * No + m] = 0;
+    s3[(int64_t)(2 * d + 1) * No + m] = v;
+    sd[(int64_t)(4 * d) * No + m] = 0;
+    sd[(int64_t)(4 * d + 1) * No + m] = v * a;
+    sd[(int64_t)(4 * d + 2) * No + m] = v * b;
+    sd[(int64_t)(4 * d + 3) * No + m] = v * e;
+  }
+}
+
+// pass 2: charge c2 and dipole vector c1 nu, [nd][4][No], from c1 and c2
+// [nd][No] (c1 = w^over P mu1, c2 = w^over P mu2)
+template <typename T>
+__global__ void k_a2_str2(int nd, int64_t No, const T* __restrict__ c1, const T* __restrict__ c2,
+                          const T* __restrict__ nx, const T* __restrict__ ny, const T* __restrict__ nz,
+                          T* __restrict__ sd) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= No) return;
+  const T a = nx[m], b = ny[m], e = nz[m];
+  for (int d = 0; d < nd; ++d) {
+    const T v1 = c1[(int64_t)d * No + m], v2 = c2[(int64_t)d * No + m];
+    sd[(int64_t)(4 * d) * No + m] = v2;
+    sd[(int64_t)(4 * d + 1) * No + m] = v1 * a;
+    sd[(int64_t)(4 * d + 2) * No + m] = v1 * b;
+    sd[(int64_t)(4 * d + 3) * No + m] = v1 * e;
+  }
+}
+
+template <typename T>
+void launch_a2_str1(int nd, int64_t No, const T* c, const T* nx, const T* ny, const T* nz, T* s3, T* sd,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_a2_str1<T>, dim3((unsigned)((No + 255) / 256)), dim3(256), 0, st, nd, No, c, nx, ny, nz, s3,
+                     sd);
+  KCHECK();
+}
+
+template <typename T>
+void launch_a2_str2(int nd, int64_t No, const T* c1, const T* c2, const T* nx, const T* ny, const T* nz, T* sd,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_a2_str2<T>, dim3((unsigned)((No + 255) / 256)), dim3(256), 0, st, nd, No, c1, c2, nx, ny, nz,
+                     sd);
+  KCHECK();
+}
+
+// A2 step 1, one wave per row: S tau, S' tau, (S''+D') tau from the FMM_A3B
+// outputs f3 [nd][4][N] (expansion 2 = charge tau, expansion 3 = dipole
+// tau nu) and D tau from the FMM_ADJ output fd [nd][N], plus the
+// corrections (vals3: S, S', S''+D'; valsD: D);
+// mu1 = D tau, mu2 = -(S''+D') tau - 2 H S' tau, y = S tau (the W S tau
+// term is added to mu2 per surface afterwards)
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void k_combine_a2a(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+                                                     const int* __restrict__ patch, const T* __restrict__ vals3,
+                                                     const T* __restrict__ valsD, const T* __restrict__ tau,
+                                                     const T* __restrict__ f3, const T* __restrict__ fd,
+                                                     const int* __restrict__ tgt_pos, const T* __restrict__ H,
+                                                     T* mu1, T* mu2, T* y) {
+  __shared__ int pat_s[4][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wv;
+  if (row >= N) return;
+  T aS[ND], aP[ND], aK[ND], aD[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) { aS[d] = aP[d] = aK[d] = aD[d] = 0; }
+  row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[wv], [&](int64_t e, int64_t col, bool on) {
+    const T* c = vals3 + e * 3;
+    const T cS = c[0], cP = c[1], cK = c[2], cD = valsD[e];
+    const T m = on ? (T)1 : (T)0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const T x = tau[(int64_t)d * N + col] * m;
+      aS[d] += cS * x;
+      aP[d] += cP * x;
+      aK[d] += cK * x;
+      aD[d] += cD * x;
+    }
+  });
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    aS[d] = wave_sum(aS[d]); aP[d] = wave_sum(aP[d]); aK[d] = wave_sum(aK[d]); aD[d] = wave_sum(aD[d]);
+  }
+  if (lane == 0) {
+    const int tp = tgt_pos[row];
+    const T s = (T)INV4PI_D;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const T* f = f3 + (int64_t)d * 4 * N;
+      const T vS = f[N + tp] * s + aS[d];
+      const T vP = f[2 * N + tp] * s + aP[d];
+      const T vK = f[3 * N + tp] * s + aK[d];
+      const T vD = fd[(int64_t)d * N + tp] * s + aD[d];
+      mu1[(int64_t)d * N + row] = vD;
+      mu2[(int64_t)d * N + row] = -vK - (T)2 * H[row] * vP;
+      y[(int64_t)d * N + row] = vS;
+    }
+  }
+}
+
+// A2 step 2: out = -tau/4 + S mu2 + D mu1 (D mu1 = D D tau) from the FMM_ADJ
+// output fb [nd][N] (charge mu2, dipole vector mu1 nu) and the corrections
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void k_combine_a2b(int64_t N, int n_p, const int64_t* __restrict__ row_ptr,
+                                                     const int* __restrict__ patch, const T* __restrict__ vals3,
+                                                     const T* __restrict__ valsD, const T* __restrict__ tau,
+                                                     const T* __restrict__ mu1, const T* __restrict__ mu2,
+                                                     const T* __restrict__ fb, const int* __restrict__ tgt_pos,
+                                                     T* out) {
+  __shared__ int pat_s[4][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wv;
+  if (row >= N) return;
+  T a[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) a[d] = 0;
+  row_blocks(row_ptr[row], row_ptr[row + 1], n_p, lane, patch, pat_s[wv], [&](int64_t e, int64_t col, bool on) {
+    const T cS = vals3[e * 3], cD = valsD[e];
+    const T m = on ? (T)1 : (T)0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      a[d] += (cS * mu2[(int64_t)d * N + col] + cD * mu1[(int64_t)d * N + col]) * m;
+  });
+#pragma unroll
+  for (int d = 0; d < ND; ++d) a[d] = wave_sum(a[d]);
+  if (lane == 0) {
+    const int tp = tgt_pos[row];
+    const T s = (T)INV4PI_D;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      out[(int64_t)d * N + row] = -(T)0.25 * tau[(int64_t)d * N + row] + fb[(int64_t)d * N + tp] * s + a[d];
+  }
+}
+
+template <typename T>
+void launch_combine_a2a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,
+                        const T* valsD, const T* tau, const T* f3, const T* fd, const int* tgt_pos, const T* H,
+                        T* mu1, T* mu2, T* y, hipStream_t st) {
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    ND_DISPATCH(k_combine_a2a, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3, valsD,
+                tau + (int64_t)d0 * N, f3 + (int64_t)d0 * 4 * N, fd + (int64_t)d0 * N, tgt_pos, H,
+                mu1 + (int64_t)d0 * N, mu2 + (int64_t)d0 * N, y + (int64_t)d0 * N)
+    KCHECK();
+  }
+}
+
+template <typename T>
+void launch_combine_a2b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,
+                        const T* valsD, const T* tau, const T* mu1, const T* mu2, const T* fb, const int* tgt_pos,
+                        T* out, hipStream_t st) {
+  for (int d0 = 0; d0 < nd; d0 += NDMAX) {
+    int ndc = nd - d0 < NDMAX ? nd - d0 : NDMAX;
+    ND_DISPATCH(k_combine_a2b, ndc, dim3((N + 3) / 4), dim3(256), 0, st, N, n_p, row_ptr, patch, vals3, valsD,
+                tau + (int64_t)d0 * N, mu1 + (int64_t)d0 * N, mu2 + (int64_t)d0 * N, fb + (int64_t)d0 * N, tgt_pos,
+                out + (int64_t)d0 * N)
+    KCHECK();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2504,6 +2681,14 @@ void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, 
                                       int, const int64_t*, const int*, const double*, T*, T*, double*, hipStream_t);                                     \
   template void launch_p2m_tables<T>(const DevTree<T>&, T*, T*, hipStream_t);                                  \
   template int64_t leaf_d_stride<T>(int, int);                                                                  \
+  template void launch_a2_str1<T>(int, int64_t, const T*, const T*, const T*, const T*, T*, T*, hipStream_t);  \
+  template void launch_a2_str2<T>(int, int64_t, const T*, const T*, const T*, const T*, const T*, T*,          \
+                                  hipStream_t);                                                                \
+  template void launch_combine_a2a<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,        \
+                                      const T*, const T*, const T*, const int*, const T*, T*, T*, T*,           \
+                                      hipStream_t);                                                            \
+  template void launch_combine_a2b<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*,        \
+                                      const T*, const T*, const T*, const T*, const int*, T*, hipStream_t);     \
   template void launch_combine_pot<T>(int, int64_t, int, const int64_t*, const int*, const T*, const T*, const T*, \
                                       const int*, T*, hipStream_t);                                             \
   template void launch_adj_strengths<T>(int, int64_t, const T*, const T*, const T*, const T*, const T*,          \

@@ -3,6 +3,8 @@
 #include <cstdint>
 #include <hip/hip_runtime.h>
 
+#include "nker.hpp"
+
 namespace lb {
 
 // FMM output sets at the targets (tree order), per right-hand side:
@@ -12,7 +14,8 @@ namespace lb {
 //             (expansions per rhs: charge mu1, charge mu2, dipole mu2 * nu)
 //   FMM_ADJ : psi = sum_j q_j / r + d_j . (x - y_j) / r^3 (sources with a
 //             charge q_j and a dipole vector d_j: strengths q, dx, dy, dz;
-//             the mask radius belongs to the target, see DevTree::trm2)
+//             the mask radius belongs to the target on the transposed tree,
+//             see DevTree::trm2, and to the source on the forward tree)
 //   FMM_ADJ3: the far part of the first step of the transposed A3, at
 //             targets x with normal nu from sources y_j with normal n_j and
 //             strengths v_j, w_j (d = x - y_j, m = n_j - nu):
@@ -234,6 +237,30 @@ void launch_seg_axpy(int nd, int nsurf, int64_t N, const int* surf, const T* x, 
 // in tree order; see k_p2m_build
 template <typename T>
 void launch_p2m_tables(const DevTree<T>& t, T* H, T* Dp, hipStream_t st);
+// A2 (Section 4.2).  Strengths of the first pass from c = w^over P tau
+// [nd][No] (tree order): s3 [nd][2][No] for FMM_A3B (charges 0 and c) and sd
+// [nd][4][No] for FMM_ADJ (dipole vector c nu, nu the tree's source normals)
+template <typename T>
+void launch_a2_str1(int nd, int64_t No, const T* c, const T* nx, const T* ny, const T* nz, T* s3, T* sd,
+                    hipStream_t st);
+// second pass: sd [nd][4][No] = (c2, c1 nu) from c1, c2 [nd][No]
+template <typename T>
+void launch_a2_str2(int nd, int64_t No, const T* c1, const T* c2, const T* nx, const T* ny, const T* nz, T* sd,
+                    hipStream_t st);
+// mu1 = D tau, mu2 = -(S''+D') tau - 2 H S' tau and y = S tau [nd][N] from the
+// FMM_A3B output f3 [nd][4][N], the FMM_ADJ output fd [nd][N] and the
+// corrections vals3 (S, S', S''+D'), valsD (D)
+template <typename T>
+void launch_combine_a2a(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,
+                        const T* valsD, const T* tau, const T* f3, const T* fd, const int* tgt_pos, const T* H,
+                        T* mu1, T* mu2, T* y, hipStream_t st);
+// out = -tau/4 + S mu2 + D mu1 from the FMM_ADJ output fb [nd][N] (charge
+// mu2, dipole vector mu1 nu) and the corrections
+template <typename T>
+void launch_combine_a2b(int nd, int64_t N, int n_p, const int64_t* row_ptr, const int* patch, const T* vals3,
+                        const T* valsD, const T* tau, const T* mu1, const T* mu2, const T* fb, const int* tgt_pos,
+                        T* out, hipStream_t st);
+
 // values per (leaf work item, density) of the workspace D that the leaf
 // kernels of `mode` use at expansion order p (0: none)
 template <typename T>
@@ -383,11 +410,13 @@ struct FarRuleArgs {
   const double* P = nullptr;    // [n_o][n_p]
   const int64_t* brow = nullptr;  // [nb] target of each block
   const int32_t* patch = nullptr; // [nb]
-  const double* A = nullptr;    // [nb][n_p][6]
-  double* v4_64 = nullptr;      // [nb * n_p][4]
-  double* v3_64 = nullptr;      // [nb * n_p][3]
+  const double* A = nullptr;    // [nb][n_p][NKER]
+  double* v4_64 = nullptr;      // [nb * n_p][4]: S, Gx, Gy, Gz
+  double* v3_64 = nullptr;      // [nb * n_p][3]: S, S', S''+D'
+  double* vD_64 = nullptr;      // [nb * n_p]: D
   float* v4_32 = nullptr;
   float* v3_32 = nullptr;
+  float* vD_32 = nullptr;
   int64_t nb = 0;
   int n_p = 0, n_o = 0;
 };

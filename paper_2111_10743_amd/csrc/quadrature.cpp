@@ -17,6 +17,9 @@
 //    integral from the ball radius to 1 is added analytically; the ln(eps)
 //    parts cancel over the full angle, leaving f_{-1} ln|B| with B the tangent
 //    of the interpolated chart along the ray (Guiggiani-Gigante subtraction).
+//    The double layer D takes the same subtraction as S' with the opposite
+//    sign (its 1/s part is non-zero only through the chart's interpolation
+//    error).
 //    The displacement from the node to a point s e of a ray is formed without
 //    cancellation: the interpolated chart is a polynomial of degree k, so
 //    X(u0 + s e) - X(u0) = s int_0^1 X'(u0 + t s e) e dt exactly with
@@ -38,8 +41,9 @@ namespace lb {
 
 static const double INV4PI = 0.25 / M_PI;
 
-// S, Gx, Gy, Gz, S', S''+D' at target x (normal n) from source y (normal nu).
-static inline void kernel6_d(const double* d, const double* n, const double* nu, double* k) {
+// S, Gx, Gy, Gz, S', S''+D', D at target x (normal n) from source y (normal
+// nu); D = grad_y G . nu, the double layer (Section 3).
+static inline void kernel7_d(const double* d, const double* n, const double* nu, double* k) {
   const double d0 = d[0], d1 = d[1], d2 = d[2];
   double r2 = d0 * d0 + d1 * d1 + d2 * d2;
   double ir = 1.0 / std::sqrt(r2);
@@ -55,14 +59,15 @@ static inline void kernel6_d(const double* d, const double* n, const double* nu,
   double md = m0 * d0 + m1 * d1 + m2 * d2;
   double nm = n[0] * m0 + n[1] * m1 + n[2] * m2;
   k[5] = (3.0 * nd * md * ir5 - nm * ir3) * INV4PI;
+  k[6] = (nu[0] * d0 + nu[1] * d1 + nu[2] * d2) * ir3 * INV4PI;
 }
 
-static inline void kernel6(const double* x, const double* n, const double* y, const double* nu, double* k) {
+static inline void kernel7(const double* x, const double* n, const double* y, const double* nu, double* k) {
   const double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
-  kernel6_d(d, n, nu, k);
+  kernel7_d(d, n, nu, k);
 }
 
-// Accumulate weight * kernel(x, chart(p, u, v)) * psi_c(u, v) into mom[c][6];
+// Accumulate weight * kernel(x, chart(p, u, v)) * psi_c(u, v) into mom[c][NKER];
 // dsp (nullable) is the displacement x - chart(p, u, v) when the caller has
 // formed it without cancellation (self rule).
 static inline void accum_point(const Surface& S, int p, double u, double v, double wgt,
@@ -76,24 +81,24 @@ static inline void accum_point(const Surface& S, int p, double u, double v, doub
   c[2] = yu[0] * yv[1] - yu[1] * yv[0];
   double J = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
   double nu[3] = {c[0] / J, c[1] / J, c[2] / J};
-  double kv[6];
-  kernel6_d(dsp ? dsp : dxy, n, nu, kv);
+  double kv[NKER];
+  kernel7_d(dsp ? dsp : dxy, n, nu, kv);
   double f = wgt * J;
-  for (int t = 0; t < 6; ++t) kv[t] *= f;
+  for (int t = 0; t < NKER; ++t) kv[t] *= f;
   for (int m = 0; m < S.n_p; ++m)
-    for (int t = 0; t < 6; ++t) mom[6 * m + t] += K[m] * kv[t];
+    for (int t = 0; t < NKER; ++t) mom[NKER * m + t] += K[m] * kv[t];
   if (kv_out)
-    for (int t = 0; t < 6; ++t) kv_out[t] = kv[t];
+    for (int t = 0; t < NKER; ++t) kv_out[t] = kv[t];
 }
 
 // moments -> Lagrange values: out[b][t] = sum_c Vinv[c][b] mom[c][t]
 static void moments_to_nodal(const Surface& S, const double* mom, double* out) {
   const int n_p = S.n_p;
   for (int b = 0; b < n_p; ++b)
-    for (int t = 0; t < 6; ++t) {
+    for (int t = 0; t < NKER; ++t) {
       double acc = 0;
-      for (int c = 0; c < n_p; ++c) acc += S.re->Vinv[c * n_p + b] * mom[6 * c + t];
-      out[6 * b + t] = acc;
+      for (int c = 0; c < n_p; ++c) acc += S.re->Vinv[c * n_p + b] * mom[NKER * c + t];
+      out[NKER * b + t] = acc;
     }
 }
 
@@ -115,8 +120,8 @@ static void self_integral(const Surface& S, int64_t i, const QuadOpts& qo,
   std::vector<double> mg, mw;
   gauss_legendre01((S.re->k + 1) / 2, mg, mw);
   const int nm = (int)mg.size();
-  double mom[6 * 64];
-  std::memset(mom, 0, sizeof(double) * 6 * n_p);
+  double mom[NKER * 64];
+  std::memset(mom, 0, sizeof(double) * NKER * n_p);
   double pv[4] = {0, 0, 0, 0};
   double sub = 0;
   for (int js = 0; js < ns; ++js) sub += gw[js] / g[js];
@@ -170,7 +175,10 @@ static void self_integral(const Surface& S, int64_t i, const QuadOpts& qo,
       }
   }
   moments_to_nodal(S, mom, out);
-  for (int t = 0; t < 4; ++t) out[6 * a + 1 + t] += pv[t];
+  for (int t = 0; t < 4; ++t) out[NKER * a + 1 + t] += pv[t];
+  // D has the 1/s^2 part of S' with the opposite sign (nu . d = -n . d to
+  // first order along the ray): the same principal value
+  out[NKER * a + 6] -= pv[3];
 }
 
 static void near_integral(const Surface& S, int64_t i, int p, const QuadOpts& qo,
@@ -179,8 +187,8 @@ static void near_integral(const Surface& S, int64_t i, int p, const QuadOpts& qo
   const int n_p = S.n_p;
   const double* x = &S.X[3 * i];
   const double* n = &S.nrm[3 * i];
-  double mom[6 * 64];
-  std::memset(mom, 0, sizeof(double) * 6 * n_p);
+  double mom[NKER * 64];
+  std::memset(mom, 0, sizeof(double) * NKER * n_p);
   struct Tri { double v[6]; int depth; };
   Tri stack[4 * 20 + 8];
   int top = 0;
@@ -237,7 +245,7 @@ void near_leaf_rule(int q, std::vector<double>& ru, std::vector<double>& rw) {
 void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A, bool self_only) {
   const int n_p = S.n_p;
   const int64_t nb = S.near_ptr[S.N];
-  if (!self_only) A.assign((size_t)nb * n_p * 6, 0.0);
+  if (!self_only) A.assign((size_t)nb * n_p * NKER, 0.0);
   std::vector<double> g, gw, tg, tw;
   gauss_legendre01(qo.self_n, g, gw);
   gauss_legendre01(qo.self_nt, tg, tw);
@@ -247,7 +255,7 @@ void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A
   for (int64_t i = 0; i < S.N; ++i) {
     const int self = (int)(i / n_p);
     for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b) {
-      double* out = &A[(size_t)b * n_p * 6];
+      double* out = &A[(size_t)b * n_p * NKER];
       int p = S.near_patch[b];
       if (p == self)
         self_integral(S, i, qo, g, gw, tg, tw, out);
@@ -262,7 +270,7 @@ void far_rule_blocks(const Surface& S, const std::vector<float>& rm2_f32,
                      bool fp32_mask, std::vector<double>& B, const OverRule* over) {
   const int n_p = S.n_p, n_o = over ? over->n_o : S.n_o;
   const int64_t nb = S.near_ptr[S.N];
-  B.assign((size_t)nb * n_p * 6, 0.0);
+  B.assign((size_t)nb * n_p * NKER, 0.0);
   const std::vector<double>& P = over ? over->re->P : S.re->P;
   const std::vector<double>& Ss = over ? over->s : S.s;
   const std::vector<double>& Snu = over ? over->nu : S.nu;
@@ -272,7 +280,7 @@ void far_rule_blocks(const Surface& S, const std::vector<float>& rm2_f32,
     const double* x = &S.X[3 * i];
     const double* n = &S.nrm[3 * i];
     for (int64_t b = S.near_ptr[i]; b < S.near_ptr[i + 1]; ++b) {
-      double* out = &B[(size_t)b * n_p * 6];
+      double* out = &B[(size_t)b * n_p * NKER];
       const int64_t p = S.near_patch[b];
       for (int m = 0; m < n_o; ++m) {
         const int64_t sm = p * n_o + m;
@@ -284,13 +292,13 @@ void far_rule_blocks(const Surface& S, const std::vector<float>& rm2_f32,
           float r2 = std::fmaf(dz, dz, std::fmaf(dy, dy, dx * dx));
           if (r2 < rm2_f32[sm]) continue;
         }
-        double kv[6];
-        kernel6(x, n, &Ss[3 * sm], &Snu[3 * sm], kv);
+        double kv[NKER];
+        kernel7(x, n, &Ss[3 * sm], &Snu[3 * sm], kv);
         const double wm = Swo[sm];
-        for (int t = 0; t < 6; ++t) kv[t] *= wm;
+        for (int t = 0; t < NKER; ++t) kv[t] *= wm;
         const double* Pm = &P[(size_t)m * n_p];
         for (int k = 0; k < n_p; ++k)
-          for (int t = 0; t < 6; ++t) out[6 * k + t] += Pm[k] * kv[t];
+          for (int t = 0; t < NKER; ++t) out[NKER * k + t] += Pm[k] * kv[t];
       }
     }
   }

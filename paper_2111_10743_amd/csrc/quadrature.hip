@@ -25,9 +25,10 @@
 //
 // One wavefront per (target, patch) pair (per target for the self rule).
 // The quadrature points are taken 64 at a time, one per lane: the lane
-// evaluates the modal basis, the chart and the six kernels and stages the
+// evaluates the modal basis, the chart and the NKER kernels and stages the
 // basis values and weighted kernel values in LDS; lane l then owns the
-// moments (c, t) = (o / 6, o % 6) for o = l, l + 64, l + 128, l + 192.  The
+// moments (c, t) = (o / NKER, o % NKER) for o = l, l + 64, l + 128, l + 192
+// (NKER n_p <= 256 up to order 7).  The
 // subdivision stack of the near rule is wave-uniform and lives in LDS.  The
 // order is a template parameter so that a point's n_p basis values stay in
 // registers.
@@ -49,8 +50,8 @@ struct QuadLds {
   double sc[3][NPP * 3];  // modal coefficients of X, X_u, X_v of the patch
   double sj[3][NJ];       // Jacobi recurrence tables of the modal basis
   double sK[64][NPP + 1]; // basis values of the staged points
-  double sKV[64][6];      // weighted kernel values of the staged points
-  double sM[6 * NPP];
+  double sKV[64][NKER];   // weighted kernel values of the staged points
+  double sM[NKER * NPP];
 };
 
 // modal basis psi_c(u, v), c = n (n + 1) / 2 + i (total degree n, index i):
@@ -120,7 +121,7 @@ __device__ inline void quad_batch(QuadLds<KO>& L, int lane, bool active, double 
                                   double* acc, const double* dsp = nullptr) {
   constexpr int NPP = QuadLds<KO>::NPP;
   double K[NPP];
-  double kv[6] = {0, 0, 0, 0, 0, 0};
+  double kv[NKER] = {0, 0, 0, 0, 0, 0, 0};
   if (active) {
     nq_basis<KO>(L.sj[0], L.sj[1], L.sj[2], u, v, K);
     double y[3] = {0, 0, 0}, yu[3] = {0, 0, 0}, yv[3] = {0, 0, 0};
@@ -153,9 +154,10 @@ __device__ inline void quad_batch(QuadLds<KO>& L, int lane, bool active, double 
     const double md = m0 * d0 + m1 * d1 + m2 * d2;
     const double nm = n0 * m0 + n1 * m1 + n2 * m2;
     kv[5] = (3.0 * nd * md * ir5 - nm * ir3) * NQ_INV4PI;
+    kv[6] = (nu0 * d0 + nu1 * d1 + nu2 * d2) * ir3 * NQ_INV4PI;  // D
     const double f = wgt * J;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) kv[t] *= f;
+    for (int t = 0; t < NKER; ++t) kv[t] *= f;
   } else {
 #pragma unroll
     for (int m = 0; m < NPP; ++m) K[m] = 0.0;
@@ -163,13 +165,13 @@ __device__ inline void quad_batch(QuadLds<KO>& L, int lane, bool active, double 
 #pragma unroll
   for (int m = 0; m < NPP; ++m) L.sK[lane][m] = K[m];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) L.sKV[lane][t] = kv[t];
+  for (int t = 0; t < NKER; ++t) L.sKV[lane][t] = kv[t];
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int o = lane + 64 * j;
-    if (o < 6 * NPP) {
-      const int c = o / 6, t = o % 6;
+    if (o < NKER * NPP) {
+      const int c = o / NKER, t = o % NKER;
       double s = 0;
       for (int l = 0; l < 64; ++l) s += L.sK[l][c] * L.sKV[l][t];
       acc[j] += s;
@@ -180,7 +182,8 @@ __device__ inline void quad_batch(QuadLds<KO>& L, int lane, bool active, double 
 
 // modal moments -> Lagrange-basis values of one block:
 // out[b][t] = sum_c Vinv[c][b] mom[c][t], plus pv[t - 1] for b = pv_b and
-// t = 1..4 when pv (in LDS, written before the call) is non-null
+// t = 1..4, and -pv[3] for t = 6 (D: the 1/s part of S' with the opposite
+// sign), when pv (in LDS, written before the call) is non-null
 template <int KO>
 __device__ inline void moments_out(QuadLds<KO>& L, int lane, const double* acc, const double* Vinv, double* out,
                                    const double* pv = nullptr, int pv_b = -1) {
@@ -188,15 +191,16 @@ __device__ inline void moments_out(QuadLds<KO>& L, int lane, const double* acc, 
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int o = lane + 64 * j;
-    if (o < 6 * NPP) L.sM[o] = acc[j];
+    if (o < NKER * NPP) L.sM[o] = acc[j];
   }
   __syncthreads();
-  for (int o = lane; o < 6 * NPP; o += 64) {
-    const int b = o / 6, t = o % 6;
+  for (int o = lane; o < NKER * NPP; o += 64) {
+    const int b = o / NKER, t = o % NKER;
     double s = 0;
 #pragma unroll
-    for (int c = 0; c < NPP; ++c) s += Vinv[c * NPP + b] * L.sM[6 * c + t];
+    for (int c = 0; c < NPP; ++c) s += Vinv[c * NPP + b] * L.sM[NKER * c + t];
     if (pv && b == pv_b && t >= 1 && t <= 4) s += pv[t - 1];
+    if (pv && b == pv_b && t == 6) s -= pv[3];
     out[o] = s;
   }
 }
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(64) void k_near_quad(NearQuadArgs q) {
       __syncthreads();
     }
   }
-  moments_out<KO>(L, lane, acc, q.Vinv, q.A + q.blk[w] * 6 * QuadLds<KO>::NPP);
+  moments_out<KO>(L, lane, acc, q.Vinv, q.A + q.blk[w] * NKER * QuadLds<KO>::NPP);
 }
 
 template <int KO>
@@ -403,14 +407,15 @@ __global__ __launch_bounds__(64) void k_self_quad(SelfQuadArgs q) {
     spvs[lane] = s;
   }
   // (moments_out's barrier orders spvs before its use)
-  moments_out<KO>(L, lane, acc, q.Vinv, q.A + blk * 6 * NPP, spvs, a);
+  moments_out<KO>(L, lane, acc, q.Vinv, q.A + blk * NKER * NPP, spvs, a);
 }
 
 // C = A - B for one block per wavefront, B and B32 accumulated over the
 // oversampled points of the patch 64 at a time; written in the packed
-// layouts of the combine kernels (k = 4: S, Gx, Gy, Gz; k = 3: S, S', S''+D').
+// layouts of the combine kernels (k = 4: S, Gx, Gy, Gz; k = 3: S, S', S''+D';
+// k = 1: D).
 __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
-  __shared__ double skv[64][12];  // kernel x weight of the staged points: FP64 rule, FP32-masked rule
+  __shared__ double skv[64][2 * NKER];  // kernel x weight of the staged points: FP64 rule, FP32-masked rule
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
   if (b >= q.nb) return;
@@ -423,7 +428,7 @@ __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
   double b64[4] = {0, 0, 0, 0}, b32[4] = {0, 0, 0, 0};
   for (int m0 = 0; m0 < n_o; m0 += 64) {
     const int m = m0 + lane;
-    double kv[6] = {0, 0, 0, 0, 0, 0};
+    double kv[NKER] = {0, 0, 0, 0, 0, 0, 0};
     bool masked = true;
     if (m < n_o) {
       const int64_t sm = p * n_o + m;
@@ -444,31 +449,32 @@ __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
       const double md = m0v * d0 + m1v * d1 + m2v * d2;
       const double nm = n0 * m0v + n1 * m1v + n2 * m2v;
       kv[5] = (3.0 * nd * md * ir5 - nm * ir3) * NQ_INV4PI;
+      kv[6] = (nu0 * d0 + nu1 * d1 + nu2 * d2) * ir3 * NQ_INV4PI;
       const double wm = q.wo[sm];
 #pragma unroll
-      for (int t = 0; t < 6; ++t) kv[t] *= wm;
+      for (int t = 0; t < NKER; ++t) kv[t] *= wm;
       // the float32 near-field kernel's test, in its arithmetic
       const float dx = __fsub_rn(tx, (float)y0), dy = __fsub_rn(ty, (float)y1), dz = __fsub_rn(tz, (float)y2);
       const float fr2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
       masked = q.rm2 ? fr2 < q.rm2[sm] : false;
     }
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
+    for (int t = 0; t < NKER; ++t) {
       skv[lane][t] = kv[t];
-      skv[lane][6 + t] = masked ? 0.0 : kv[t];
+      skv[lane][NKER + t] = masked ? 0.0 : kv[t];
     }
     __syncthreads();
     const int lim = min(64, n_o - m0);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int o = lane + 64 * j;
-      if (o < 6 * n_p) {
-        const int k = o / 6, t = o % 6;
+      if (o < NKER * n_p) {
+        const int k = o / NKER, t = o % NKER;
         double s64 = 0, s32 = 0;
         for (int l = 0; l < lim; ++l) {
           const double P = q.P[(int64_t)(m0 + l) * n_p + k];
           s64 += P * skv[l][t];
-          s32 += P * skv[l][6 + t];
+          s32 += P * skv[l][NKER + t];
         }
         b64[j] += s64;
         b32[j] += s32;
@@ -479,9 +485,9 @@ __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int o = lane + 64 * j;
-    if (o < 6 * n_p) {
-      const int k = o / 6, t = o % 6;
-      const double a = q.A[b * 6 * n_p + o];
+    if (o < NKER * n_p) {
+      const int k = o / NKER, t = o % NKER;
+      const double a = q.A[b * NKER * n_p + o];
       const double c64 = a - b64[j];
       const float c32 = (float)(a - b32[j]);
       const int64_t e = b * n_p + k;
@@ -489,10 +495,14 @@ __global__ __launch_bounds__(64) void k_far_rule(FarRuleArgs q) {
         if (q.v4_64) q.v4_64[4 * e + t] = c64;
         if (q.v4_32) q.v4_32[4 * e + t] = c32;
       }
-      if (t == 0 || t >= 4) {
+      if (t == 0 || t == 4 || t == 5) {
         const int u = t == 0 ? 0 : t - 3;
         if (q.v3_64) q.v3_64[3 * e + u] = c64;
         if (q.v3_32) q.v3_32[3 * e + u] = c32;
+      }
+      if (t == 6) {
+        if (q.vD_64) q.vD_64[e] = c64;
+        if (q.vD_32) q.vD_32[e] = c32;
       }
     }
   }
@@ -537,7 +547,7 @@ hipError_t launch_self_quad(const SelfQuadArgs& q, hipStream_t st) {
 
 hipError_t launch_far_rule(const FarRuleArgs& q, hipStream_t st) {
   if (q.nb <= 0) return hipSuccess;
-  if (q.nb > 0x7fffffff || q.n_p < 1 || 6 * q.n_p > 256 || q.n_o < 1) return hipErrorInvalidValue;
+  if (q.nb > 0x7fffffff || q.n_p < 1 || NKER * q.n_p > 256 || q.n_o < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_far_rule, dim3((unsigned)q.nb), dim3(64), 0, st, q);
   return hipGetLastError();
 }

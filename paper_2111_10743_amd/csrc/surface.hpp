@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "nker.hpp"
 #include "refelem.hpp"
 
 namespace lb {
@@ -70,8 +71,8 @@ struct Surface {
 };
 
 // Accurate near integrals A (eq. nys-lcq2) for every (target, near patch)
-// block: vals [nnz_blocks][n_p][6], kernels S, Gx, Gy, Gz, S', S''+D'.
-// With self_only, A must already hold nnz_blocks * n_p * 6 values and only
+// block: vals [nnz_blocks][n_p][NKER], kernels S, Gx, Gy, Gz, S', S''+D', D.
+// With self_only, A must already hold nnz_blocks * n_p * NKER values and only
 // the blocks of each target's own patch are written.
 void near_integrals(const Surface& S, const QuadOpts& qo, std::vector<double>& A, bool self_only = false);
 

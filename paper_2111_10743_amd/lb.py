@@ -38,7 +38,7 @@ EXPORTED = ("lb_default_opts", "lb_ref_nodes", "lb_setup", "lb_setup_batch", "lb
             "lb_get_corrections", "lb_get_tree", "lb_tree_build", "lb_tree_get", "lb_tree_destroy", "lb_apply_S", "lb_apply_gradS", "lb_apply_gradS_adj", "lb_apply_S_adj", "lb_apply_S_adj_X", "lb_autotune",
             "lb_apply_gradS_timed", "lb_apply_A3", "lb_apply_A3_adj", "lb_solve", "lb_solve_adj",
             "lb_surface_grad", "lb_surface_div", "lb_hodge", "lb_apply_A1", "lb_set_tuning", "lb_destroy",
-            "lb_last_error", "lb_apply_gradS_noalloc", "lb_export_setup", "lb_import_setup")
+            "lb_last_error", "lb_apply_gradS_noalloc", "lb_export_setup", "lb_import_setup", "lb_apply_A2")
 PHASES = ("strengths", "p2m", "m2m", "m2l", "l2l", "leaf", "combine")
 
 
@@ -127,6 +127,7 @@ def lib():
         L.lb_solve_adj.argtypes = [vp, ip, vp, vp, ctypes.c_double, ip, ctypes.POINTER(SolveInfo), vp]
         L.lb_apply_A3_adj.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_apply_A1.argtypes = [vp, ip, ip, vp, vp, vp]
+        L.lb_apply_A2.argtypes = [vp, ip, ip, vp, vp, vp]
         L.lb_set_tuning.argtypes = [vp, ip, ctypes.POINTER(TuneInfo)]
         L.lb_surface_grad.argtypes = [vp, ip, vp, vp, vp]
         L.lb_surface_div.argtypes = [vp, ip, vp, ip, vp, vp]
@@ -297,7 +298,7 @@ class Surface:
         nb = self.sizes["nnz_blocks"]
         ptr = np.zeros(self.N + 1, dtype=np.int64)
         patch = np.zeros(nb, dtype=np.int32)
-        vals = np.zeros((nb, self.sizes["n_p"], 6))
+        vals = np.zeros((nb, self.sizes["n_p"], 7))
         _check(lib().lb_get_corrections(self._ctx, ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                         patch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(vals)))
         return ptr, patch, vals
@@ -446,6 +447,15 @@ class Surface:
         nd = self._nd(tau)
         res = out if out is not None else torch.empty_like(tau)
         _check(lib().lb_apply_A1(self._ctx, nd, self._prec(tau), _ptr(tau), _ptr(res), _stream()))
+        return res
+
+    def apply_A2(self, tau, out=None):
+        """lb_apply_A2: -tau/4 + D D tau - S (S''+D'+2HS') tau + S W S tau
+        (Section 4.2, eq. ie-dis1)."""
+        import torch
+        nd = self._nd(tau)
+        res = out if out is not None else torch.empty_like(tau)
+        _check(lib().lb_apply_A2(self._ctx, nd, self._prec(tau), _ptr(tau), _ptr(res), _stream()))
         return res
 
     def apply_A3_adj(self, v, out=None):

@@ -5,13 +5,16 @@ second-kindness section with the library's operators.
   20 order-4 patches, N = 300): FP64 <= 1e-9, FP32 <= 2e-5 (two gradient
   applies in sequence, the second on tangential components of the first).
 * A batch of densities equals the densities applied one at a time.
-* Dense A1 and A3 assembled from the library's FP64 applies (the paper uses
-  dense matrices to keep FMM errors out; the FP64 FMM's 1e-11 are far below
-  the singular values in question) on the sphere with order-4 patches, N = 1200 and 4800 (the paper: 1920 and
-  7680): the smallest singular value of A1 falls under refinement while
-  A3's stays put, and GMRES (tol 1e-14, at most 100 iterations; data:
-  random degree <= 4 harmonics with U(-0.5, 0.5) coefficients) converges on
-  A3 in a handful of iterations and stalls at the cap on A1.
+* Dense A1, A2 and A3 assembled from the library's FP64 applies (the paper
+  uses dense matrices to keep FMM errors out; the FP64 FMM's 1e-11 are far
+  below the singular values in question) on the sphere with order-4
+  patches, N = 1200 and 4800 (the paper: 1920 and 7680): the smallest
+  singular value of A1 falls under refinement while those of A2 (the
+  second-kind discretization of the same operator, eq. ie-dis1) and A3 stay
+  put, and GMRES (tol 1e-14, at most 100 iterations; data: random degree <= 4
+  harmonics with U(-0.5, 0.5) coefficients; right-hand side S f for A1 and
+  A2, f for A3) converges on A2 and A3 in a handful of iterations and stalls
+  at the cap on A1.
 """
 import sys
 
@@ -84,25 +87,32 @@ def test_numerical_second_kindness(torch_dev):
         X, Xu, Xv = I.sphere_patches(nsub, nodes(4))
         s = P.Surface(X, Xu, Xv, 4)
         N = s.N
-        note(f"second kindness N={N}: dense A1, A3")
+        note(f"second kindness N={N}: dense A1, A2, A3")
         A1 = _dense(torch, s.apply_A1, N)
+        A2 = _dense(torch, s.apply_A2, N)
         A3 = _dense(torch, s.apply_A3, N)
         Sm = _dense(torch, s.apply_S, N)
         s1 = torch.linalg.svdvals(A1).cpu().numpy()
+        s2 = torch.linalg.svdvals(A2).cpu().numpy()
         s3 = torch.linalg.svdvals(A3).cpu().numpy()
         x = X.reshape(-1, 3)
         w = s.geometry()[0]
         rng = np.random.default_rng(3)
         f = sum(rng.uniform(-0.5, 0.5) * I.real_sph_harm(l, m, x) for l in range(1, 5) for m in range(-l, l + 1))
         f = f - (w * f).sum() / w.sum()
-        A1h, A3h, Sh = A1.cpu().numpy(), A3.cpu().numpy(), Sm.cpu().numpy()
+        A1h, A2h, A3h, Sh = A1.cpu().numpy(), A2.cpu().numpy(), A3.cpu().numpy(), Sm.cpu().numpy()
         _, i1 = gmres(lambda v: A1h @ v, Sh @ f, tol=1e-14, max_iter=100)
+        _, i2 = gmres(lambda v: A2h @ v, Sh @ f, tol=1e-14, max_iter=100)
         _, i3 = gmres(lambda v: A3h @ v, f, tol=1e-14, max_iter=100)
         note(f"second kindness N={N}: A1 sigma max {s1[0]:.3f} min {s1[-1]:.2e}; A3 sigma max {s3[0]:.3f} "
              f"min {s3[-1]:.3f}; GMRES A1 {i1['iters']} its (resid {i1['rel_resid']:.1e}), "
-             f"A3 {i3['iters']} its (resid {i3['rel_resid']:.1e})")
-        res.append((s1[-1], s3[-1], i1["iters"], i3["iters"]))
+             f"A3 {i3['iters']} its (resid {i3['rel_resid']:.1e}); A2 sigma max {s2[0]:.3f} min {s2[-1]:.3f}, "
+             f"GMRES {i2['iters']} its (resid {i2['rel_resid']:.1e})")
+        res.append((s1[-1], s3[-1], i1["iters"], i3["iters"], s2[-1], i2["iters"]))
         s.close()
-    (a0, b0, n10, n30), (a1, b1, n11, n31) = res
+    (a0, b0, n10, n30, c0, n20), (a1, b1, n11, n31, c1, n21) = res
     assert a1 < a0 / 2 and abs(b1 - b0) < 0.05 * b0 and a1 < 1e-2 * b1
     assert n30 <= 12 and n31 <= 12 and n10 == 100 and n11 == 100
+    # A2, mathematically equal to A1, is second kind: sigma_min does not
+    # fall under refinement and GMRES takes a handful of iterations
+    assert abs(c1 - c0) < 0.05 * c0 and a1 < 1e-2 * c1 and n20 <= 12 and n21 <= 12

@@ -9,11 +9,12 @@ stored by ``tests/golden/make_oracle_golden.py``, which calls only
 * ellipsoid (1, 1.5, 2), 320 order-6 patches, N = 8,960 (octrees of at
   least three levels in both precisions: the coarser FP32 far rule gets
   256 oversampled points per leaf): S, grad S, S' and grad_Gamma S (Section 4.1) at every row in both
-  precisions, A3 (eq. ie-dis2) at every row, and both solve modes against
+  precisions, A3 (eq. ie-dis2) and A2 (eq. ie-dis1) at every row, and both solve modes against
   the oracle's solves of a band-limited right-hand side and of the
   manufactured f = -2 H n_1 (whose exact solution is x_1 minus its mean).
 * star-shaped surface (320 order-4 patches, N = 4,800, trees of at least
-  three levels: 256 / 128 oversampled points per leaf in FP64 / FP32): A3 at every row and both solve modes.
+  three levels: 256 / 128 oversampled points per leaf in FP64 / FP32): A3 and A2 at every row and both solve
+  modes.
 
 Bars: FP64 1e-9 relative L2 on S, grad S, S', grad_Gamma S and the solves;
 FP32 1e-6 on S, grad S, S', grad_Gamma S; FP32+refine solves 1e-9.  A3
@@ -147,6 +148,19 @@ def test_A3_every_row(torch_dev, request, name, prec):
     note(f"{name} A3 prec={prec}")
     out = s.apply_A3(torch.tensor(inp["tau"], dtype=dt, device="cuda")).double().cpu().numpy()
     check(f"{name} prec {prec} A3", out, ref["A3"], A3_BARS[(name, prec)])
+
+
+@pytest.mark.parametrize("name,prec", list(A3_BARS))
+def test_A2_every_row(torch_dev, request, name, prec):
+    """A2 (Section 4.2, eq. ie-dis1) against the oracle's: the same first-pass
+    FMM as A3's second pass (its Hessian truncation bounds the error), a
+    dipole FMM for D and a charge + dipole potential FMM; the same bars."""
+    torch = torch_dev
+    s, inp, ref = request.getfixturevalue(name)
+    dt = torch.float64 if prec == 64 else torch.float32
+    note(f"{name} A2 prec={prec}")
+    out = s.apply_A2(torch.tensor(inp["tau"], dtype=dt, device="cuda")).double().cpu().numpy()
+    check(f"{name} prec {prec} A2", out, ref["A2"], A3_BARS[(name, prec)])
 
 
 @pytest.mark.parametrize("mode", [0, 1])
