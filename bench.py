@@ -338,9 +338,9 @@ def main():
         for key, v in t.items():
             ph64[key] = ph64.get(key, 0.0) + v / 2
     print(f"[bench] fp64 apply {ms64:.3f} ms phases {ph64}", file=sys.stderr, flush=True)
-    # operator applies per GMRES iteration (t_mv): A3 and the non-second-kind A1
+    # operator applies per GMRES iteration (t_mv): A3, A2 and the non-second-kind A1
     t_mv = {}
-    for name, fn in (("A3", s.apply_A3), ("A1", s.apply_A1)):
+    for name, fn in (("A3", s.apply_A3), ("A2", s.apply_A2), ("A1", s.apply_A1)):
         for tag, xx in (("fp32", x32), ("fp64", x64)):
             fn(xx)
             t_mv[f"{name}_{tag}_ms"] = timed(lambda: fn(xx), st64)
