@@ -256,6 +256,8 @@ def main():
                     help="apply this configuration (JSON as in config.tuning of an earlier run) instead of "
                          "running the autotuner, e.g. to profile the launches a tuned run timed")
     ap.add_argument("--no-hodge", action="store_true", help="skip the twisted-torus Hodge decomposition")
+    ap.add_argument("--no-tmv", action="store_true",
+                    help="skip the per-iteration operator timings (A3, A2, A1), e.g. for counter runs of the gradient apply")
     ap.add_argument("--cpu-rows", type=int, default=24, help="oracle rows per host core in the cpu baseline")
     ap.add_argument("--cpu-only", action="store_true",
                     help="print the CPU baseline of the workload as JSON and exit (no GPU use); the full run "
@@ -340,7 +342,7 @@ def main():
     print(f"[bench] fp64 apply {ms64:.3f} ms phases {ph64}", file=sys.stderr, flush=True)
     # operator applies per GMRES iteration (t_mv): A3, A2 and the non-second-kind A1
     t_mv = {}
-    for name, fn in (("A3", s.apply_A3), ("A2", s.apply_A2), ("A1", s.apply_A1)):
+    for name, fn in () if args.no_tmv else (("A3", s.apply_A3), ("A2", s.apply_A2), ("A1", s.apply_A1)):
         for tag, xx in (("fp32", x32), ("fp64", x64)):
             fn(xx)
             t_mv[f"{name}_{tag}_ms"] = timed(lambda: fn(xx), st64)
@@ -417,6 +419,17 @@ def main():
             res[name] = {"s": dt, "iters": its[0] if len(its) == 1 else [min(its), max(its)],
                          "outer_steps": max(i["outer_steps"] for i in info),
                          "rel_resid": max(i["rel_resid"] for i in info), "status": code, "systems": len(info)}
+            print(f"[bench] solve {name} {res[name]}", file=sys.stderr, flush=True)
+        # the A2 formulation (eq. ie-dis1) on the same right-hand side
+        for name, mode in (("a2_fp64", P.LB_SOLVE_FP64), ("a2_fp32_refine", P.LB_SOLVE_FP32_REFINE)):
+            s.solve(fz, tol=1e-9, mode=mode | P.LB_SOLVE_A2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, info, code = s.solve(fz, tol=1e-9, mode=mode | P.LB_SOLVE_A2)
+            torch.cuda.synchronize()
+            its = [i["iters"] for i in info]
+            res[name] = {"s": time.perf_counter() - t0, "iters": its[0] if len(its) == 1 else [min(its), max(its)],
+                         "status": code}
             print(f"[bench] solve {name} {res[name]}", file=sys.stderr, flush=True)
         w, _, _ = s.geometry()
         w = torch.tensor(w, device="cuda")

@@ -55,6 +55,7 @@ typedef int lb_status;
 /* lb_solve modes */
 #define LB_SOLVE_FP64        0   /* FP64 FMM, FP64 corrections, FP64 GMRES */
 #define LB_SOLVE_FP32_REFINE 1   /* FP32 inner GMRES operator, FP64 residual refinement */
+#define LB_SOLVE_A2          4   /* or-ed into either mode: the A2 formulation (eq. ie-dis1) */
 
 /* lb_opts.flags */
 #define LB_STRICT_MEAN 1   /* lb_solve rejects f with |mean| > 1e-12 ||f|| */
@@ -395,7 +396,9 @@ lb_status lb_apply_A3_adj(lb_ctx *ctx, int nd, int prec, const void *v, void *ou
 /* Solve Delta_Gamma u = f for the mean-zero u (Lemma 1), through
  * A3 sigma = f - mean(f) and u = S[S[sigma]] (eq. ie-dis2, Section 6 GMRES:
  * x0 = 0, no restart, relative Euclidean residual < tol, at most
- * opts.max_iter iterations per inner solve).  f, u: device double [nrhs][N].
+ * opts.max_iter iterations per inner solve); with LB_SOLVE_A2 or-ed into
+ * `mode`, through A2 sigma = S[f - mean(f)] and u = S[sigma] (eq. ie-dis1),
+ * the residual relative to S[f - mean(f)].  f, u: device double [nrhs][N].
  * info: host [nrhs * n_surf], nullable.  Synchronizes `stream`.  Returns LB_ENOCONV
  * if some right-hand side did not reach tol (its best iterate is written),
  * LB_ENOTMEANZERO in strict-mean mode. */

@@ -303,8 +303,11 @@ struct lb_ctx {
   // GMRES iteration graphs (A3 and A3^T, FP64 and FP32) and the FP64
   // residual applies of the solves
   lb::OpGraph gI64, gI32, gIT64, gIT32, gR64, gRT64;
+  lb::OpGraph gI64a2, gI32a2, gR64a2;  // the same for the A2 solves
+  DBuf a2b;                             // A2 solves: the right-hand side S f
   void reset_graphs() {
     gI64.reset(); gI32.reset(); gIT64.reset(); gIT32.reset(); gR64.reset(); gRT64.reset();
+    gI64a2.reset(); gI32a2.reset(); gR64a2.reset();
   }
   ~lb_ctx() {
     reset_graphs();
@@ -984,13 +987,19 @@ static void apply_A3_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hi
 // charge mu2 and dipole mu1 nu gives A2 tau = -tau/4 + S mu2 + D mu1 (the
 // D^2 term of eq. ie-dis1 is D mu1 with a plus sign).
 template <typename T>
-static void apply_A2_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
+static void a2_ws(lb_ctx* ctx, Prec<T>& P) {
   ensure_ws(ctx, P, CHUNK_GRAD);
+  const int cmax = chunk_a3<T>();
+  if ((size_t)6 * cmax * P.No > P.str.bytes / sizeof(T) || (size_t)2 * cmax * ctx->N > P.mu.bytes / sizeof(T))
+    fail(LB_EINVAL, "A2 workspace too small");
+  P.a2s.alloc(sizeof(T) * (size_t)P.No * 2 * cmax);
+}
+
+template <typename T>
+static void apply_A2_t(lb_ctx* ctx, Prec<T>& P, int nd, const T* tau, T* out, hipStream_t st) {
+  a2_ws<T>(ctx, P);
   const int64_t N = ctx->N, No = P.No;
   const int cmax = chunk_a3<T>();
-  if ((size_t)6 * cmax * No > P.str.bytes / sizeof(T) || (size_t)2 * cmax * N > P.mu.bytes / sizeof(T))
-    fail(LB_EINVAL, "A2 workspace too small");
-  P.a2s.alloc(sizeof(T) * (size_t)No * 2 * cmax);
   T* c1 = dptr<T>(P.a2s);
   T* c2 = c1 + (size_t)cmax * No;
   T* s3 = dptr<T>(P.str);                  // [c][2][No]
@@ -2583,12 +2592,20 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   check_apply(ctx, nrhs, LB_PREC_FP64);
   if (!f || !u) fail(LB_EINVAL, "null f or u");
   if (!(tol > 0)) fail(LB_EINVAL, "tol must be > 0");
+  // formulation: A3 (eq. ie-dis2, u = S S sigma) or, with LB_SOLVE_A2, A2
+  // (eq. ie-dis1: A2 sigma = S f, u = S sigma)
+  const bool a2 = (mode & LB_SOLVE_A2) != 0;
+  mode &= ~LB_SOLVE_A2;
   if (mode != LB_SOLVE_FP64 && mode != LB_SOLVE_FP32_REFINE) fail(LB_EINVAL, "unknown mode");
   hipStream_t st = (hipStream_t)stream;
   const int64_t N = ctx->N;
   const int nsf = ctx->n_surf;
   ensure_ws(ctx, ctx->f64, CHUNK_GRAD);
   ensure_ws(ctx, ctx->f32, CHUNK_GRAD);
+  if (a2) {
+    a2_ws<double>(ctx, ctx->f64);
+    a2_ws<float>(ctx, ctx->f32);
+  }
   const size_t nN = (size_t)nrhs * N;
   ctx->r.alloc(sizeof(double) * nN);
   ctx->sig.alloc(sizeof(double) * nN);
@@ -2602,13 +2619,19 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
   double* ut = dptr<double>(ctx->utmp);
   double* dcorr = ut + nN;
   auto A64 = [&](const double* v, double* w, int na, hipStream_t s2) {
-    apply_A3_t<double>(ctx, ctx->f64, na, v, w, s2);
+    if (a2)
+      apply_A2_t<double>(ctx, ctx->f64, na, v, w, s2);
+    else
+      apply_A3_t<double>(ctx, ctx->f64, na, v, w, s2);
   };
   auto A32 = [&](const double* v, double* w, int na, hipStream_t s2) {
     float* vi = dptr<float>(ctx->f32.tmp_in);
     float* vo = dptr<float>(ctx->f32.tmp_out);
     launch_convert<double, float>(v, vi, (int64_t)na * N, s2);
-    apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, s2);
+    if (a2)
+      apply_A2_t<float>(ctx, ctx->f32, na, vi, vo, s2);
+    else
+      apply_A3_t<float>(ctx, ctx->f32, na, vi, vo, s2);
     launch_convert<float, double>(vo, w, (int64_t)na * N, s2);
   };
   // mean projection per surface (Lemma 1): fz = f - (sum_q w f / area_q) on surface q
@@ -2637,11 +2660,25 @@ lb_status lb_solve(lb_ctx* ctx, int nrhs, const double* f, double* u, double tol
     }
   std::vector<double> rel;
   std::vector<int> iters, outer;
-  solve_system(ctx, nrhs, sy, A64, A32, ctx->gI64, ctx->gI32, ctx->gR64, fz, fnorm, sig, r, ut, dcorr, tol, mode, rel,
-               iters, outer, st);
-  // u = S[S[sigma]] in FP64
-  apply_S_t<double>(ctx, ctx->f64, nrhs, sig, ut, st);
-  apply_S_t<double>(ctx, ctx->f64, nrhs, ut, u, st);
+  if (a2) {
+    // the right-hand side S f of eq. ie-dis1, its norms for the residual test
+    ctx->a2b.alloc(sizeof(double) * nN);
+    double* b = dptr<double>(ctx->a2b);
+    apply_S_t<double>(ctx, ctx->f64, nrhs, fz, b, st);
+    std::vector<double> bnorm = system_norms(ctx, sy, b, st);
+    for (size_t a = 0; a < bnorm.size(); ++a)
+      if (fnorm[a] == 0.0) bnorm[a] = 0.0;
+    solve_system(ctx, nrhs, sy, A64, A32, ctx->gI64a2, ctx->gI32a2, ctx->gR64a2, b, bnorm, sig, r, ut, dcorr, tol,
+                 mode, rel, iters, outer, st);
+    // u = S[sigma] in FP64
+    apply_S_t<double>(ctx, ctx->f64, nrhs, sig, u, st);
+  } else {
+    solve_system(ctx, nrhs, sy, A64, A32, ctx->gI64, ctx->gI32, ctx->gR64, fz, fnorm, sig, r, ut, dcorr, tol, mode,
+                 rel, iters, outer, st);
+    // u = S[S[sigma]] in FP64
+    apply_S_t<double>(ctx, ctx->f64, nrhs, sig, ut, st);
+    apply_S_t<double>(ctx, ctx->f64, nrhs, ut, u, st);
+  }
   HIPTRY(hipStreamSynchronize(st));
   const double t_solve = wall_seconds() - t_start;
   lb_status ret = LB_OK;

@@ -25,6 +25,7 @@ LB_PREC_FP32 = 32
 LB_PREC_FP64 = 64
 LB_SOLVE_FP64 = 0
 LB_SOLVE_FP32_REFINE = 1
+LB_SOLVE_A2 = 4  # or-ed into a mode: the A2 formulation (eq. ie-dis1)
 LB_STRICT_MEAN = 1
 LB_HOST_ONLY = 2
 LB_DIRECT = 4

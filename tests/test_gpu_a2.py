@@ -6,7 +6,8 @@ to 1e-5; the eigen-relation A2 Y_l = -l(l+1)/(2l+1)^2 Y_l that A2 shares with
 A1 and A3 (S (Delta + W) S on the sphere) to the discretization error; a
 batch of densities equals the densities applied one at a time; and the A2
 solve of the library's operator (u = S sigma with A2 sigma = S f, by GMRES
-in NumPy over the FP64 apply) returns u = -f/6 for f = x z."""
+in NumPy over the FP64 apply) returns u = -f/6 for f = x z, and lb_solve with
+LB_SOLVE_A2 (device GMRES, both modes) returns the same solution."""
 import numpy as np
 import pytest
 
@@ -89,3 +90,10 @@ def test_A2_eigen_batch_and_solve(torch_dev, sphere_ctx):
     u = fmm.apply_S(torch.tensor(sig, device="cuda")).cpu().numpy()
     note(f"A2 solve: {info['iters']} iterations, u vs -f/6 {rel_l2(u, -f / 6.0, w):.2e}")
     assert info["iters"] <= 12 and rel_l2(u, -f / 6.0, w) < 1e-3
+    # the library's A2 solve (LB_SOLVE_A2) in both modes: the same solution
+    import paper_2111_10743_amd as P
+    for mode in (P.LB_SOLVE_FP64, P.LB_SOLVE_FP32_REFINE):
+        ul, info_l, code = fmm.solve(torch.tensor(f, device="cuda"), tol=1e-12, mode=mode | P.LB_SOLVE_A2)
+        ul = ul.cpu().numpy()
+        note(f"lb_solve A2 mode {mode}: {info_l[0]['iters']} iterations, against the NumPy GMRES {rel_l2(ul, u, w):.2e}")
+        assert code == 0 and rel_l2(ul, u, w) < 1e-9

@@ -164,6 +164,23 @@ def test_A2_every_row(torch_dev, request, name, prec):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_solve_A2_vs_oracle(torch_dev, ellipsoid, mode):
+    """The A2 solve (eq. ie-dis1: A2 sigma = S f, u = S sigma; LB_SOLVE_A2)
+    against the oracle's A2 solves of the two ellipsoid right-hand sides."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    s, inp, ref = ellipsoid
+    g = ref["geom"]
+    F = np.stack([inp["f1"], -2.0 * g.H * g.n[:, 0]])
+    u, info, code = s.solve(torch.tensor(F, device="cuda"), tol=1e-12, mode=mode | P.LB_SOLVE_A2)
+    note(f"ellipsoid A2 solve mode={mode} iterations {[i['iters'] for i in info]} oracle {ref['iters_A2']}")
+    assert code == 0
+    u = u.cpu().numpy()
+    for r in range(2):
+        check(f"ellipsoid A2 mode {mode} rhs {r} u", u[r], ref["u_A2"][r], 1e-9, g.w)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("name", ["ellipsoid", "star"])
 def test_solve_vs_oracle(torch_dev, request, name, mode):
     torch = torch_dev
