@@ -47,6 +47,9 @@ WORKLOADS = {
     # 64 star-shaped surfaces, faces split n_s x n_s, n_s ~ U{3..9} (seed 99):
     # 180 .. 1,620 order-5 patches each, 52,960 in all (N = 1,112,160)
     "stars64": ("stars", 5, 64),
+    # the genus-2 surface of lbinputs.genus2 meshed at edge 0.07: ~34,600
+    # order-6 patches, N ~ 970,000 (meshing takes minutes on the host)
+    "genus2_1M": ("genus2", 6, 0.07),
 }
 
 
@@ -65,7 +68,16 @@ def workload(name, host_nodes=False):
         import paper_2111_10743_amd as P
         uv, _ = P.ref_nodes(k)
     pps = None
-    if kind == "stars":
+    if kind == "genus2":
+        from lbinputs import genus2 as G2
+        S2 = G2.FusedTori()
+        V, T = G2.mesh(S2, size)
+        X, Xu, Xv = G2.patches(S2, V, T, uv)
+        f = I.legendre_field(X.reshape(-1, 3), seed=5, deg=5, L=2.6)[:, 0]
+        dens = "first component of a tensor-Legendre field of degree 5 on x / 5.2 (seed 5)"
+        surf = (f"genus-2 surface (smoothed union of two solid tori R = 1, r = 0.4, centres +-1.1), "
+                f"mesh edge {size}, Euler characteristic {G2.euler_characteristic(T)}")
+    elif kind == "stars":
         ns = np.random.default_rng(99).integers(3, 10, size)
         surfs = [I.star_patches(int(n), uv, I.star_coeffs(4 + q)) for q, n in enumerate(ns)]
         X, Xu, Xv = (np.concatenate([sf[c] for sf in surfs]) for c in range(3))

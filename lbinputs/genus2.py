@@ -49,7 +49,10 @@ class FusedTori:
         return (1.0 - t1 / q)[..., None] * g1 + (1.0 - t2 / q)[..., None] * g2
 
     def bounds(self):
-        R, r, d = self.R, self.r, self.d
+        # F < 0 reaches beyond the tori where both T_i < c / sqrt(2) (the
+        # blend), i.e. at most to the tube radius sqrt(r^2 + c / sqrt(2))
+        R, d = self.R, self.d
+        r = np.sqrt(self.r ** 2 + self.c / np.sqrt(2.0))
         return np.array([-d - R - r, -R - r, -r]), np.array([d + R + r, R + r, r])
 
     def project(self, p, iters=60):
