@@ -7,7 +7,10 @@ solid tori (a smoothed minimum of T1 and T2: F is close to T1 away from the
 second torus), and c rounds off the crease where the two tubes meet (over a
 width of order c / (2 r)).  With the rings a little more than a diameter
 apart (d slightly above R) the tubes overlap in one lens, and the union has
-genus 2.
+genus 2.  Seeded bumps displace the surface along its normal by about
+amp * a_b * exp(-|x - c_b|^2 / (2 width^2)), a_b ~ U(-1, 1), centres c_b on
+the surface: F - 0.8 sum_b amp a_b exp(...) (0.8 ~ |grad F| = 2 r on the
+tubes).
 
 Meshing (synthetic input generation, no part of the method): marching
 tetrahedra on the six-tetrahedra split of a cubic grid, vertices moved onto
@@ -27,8 +30,27 @@ _TETS = np.array([[0, 1, 3, 7], [0, 3, 2, 7], [0, 2, 6, 7], [0, 6, 4, 7], [0, 4,
 
 
 class FusedTori:
-    def __init__(self, R=1.0, r=0.4, d=1.1, c=0.3):
+    def __init__(self, R=1.0, r=0.4, d=1.1, c=0.3, bumps=8, amp=0.05, width=0.25, seed=5):
         self.R, self.r, self.d, self.c = R, r, d, c
+        self.amp, self.width = amp, width
+        self.bc = np.zeros((0, 3))
+        self.ba = np.zeros(0)
+        if bumps:
+            rng = np.random.default_rng(seed)
+            lo, hi = self.bounds()
+            p = lo + (hi - lo) * rng.uniform(size=(bumps, 3))
+            a = rng.uniform(-1.0, 1.0, bumps)
+            self.bc = self.project(p)  # centres on the surface without bumps
+            self.ba = a
+
+    def _bump(self, x):
+        if len(self.ba) == 0:
+            return 0.0, 0.0
+        # |x - c|^2 = |x|^2 + |c|^2 - 2 x.c (a product with the few centres)
+        d2 = (x * x).sum(-1)[..., None] + (self.bc * self.bc).sum(-1) - 2.0 * (x @ self.bc.T)
+        e = np.exp(-np.maximum(d2, 0.0) / (2.0 * self.width ** 2)) * (0.8 * self.amp * self.ba)
+        es = e.sum(-1)
+        return es, -(es[..., None] * x - e @ self.bc) / self.width ** 2
 
     def _torus(self, x, a):
         rho = np.sqrt((x[..., 0] - a) ** 2 + x[..., 1] ** 2)
@@ -40,19 +62,21 @@ class FusedTori:
     def F(self, x):
         t1, _ = self._torus(x, -self.d)
         t2, _ = self._torus(x, self.d)
-        return t1 + t2 - np.sqrt(t1 * t1 + t2 * t2 + self.c * self.c)
+        b, _ = self._bump(x)
+        return t1 + t2 - np.sqrt(t1 * t1 + t2 * t2 + self.c * self.c) - b
 
     def grad(self, x):
         t1, g1 = self._torus(x, -self.d)
         t2, g2 = self._torus(x, self.d)
         q = np.sqrt(t1 * t1 + t2 * t2 + self.c * self.c)
-        return (1.0 - t1 / q)[..., None] * g1 + (1.0 - t2 / q)[..., None] * g2
+        _, gb = self._bump(x)
+        return (1.0 - t1 / q)[..., None] * g1 + (1.0 - t2 / q)[..., None] * g2 - gb
 
     def bounds(self):
         # F < 0 reaches beyond the tori where both T_i < c / sqrt(2) (the
         # blend), i.e. at most to the tube radius sqrt(r^2 + c / sqrt(2))
         R, d = self.R, self.d
-        r = np.sqrt(self.r ** 2 + self.c / np.sqrt(2.0))
+        r = np.sqrt(self.r ** 2 + self.c / np.sqrt(2.0)) + 2.0 * self.amp
         return np.array([-d - R - r, -R - r, -r]), np.array([d + R + r, R + r, r])
 
     def project(self, p, iters=60):
@@ -155,6 +179,11 @@ def _collapse(S, V, T, lmin):
     cand = cand[L[cand] < lmin]
     if len(cand) == 0:
         return V, T, 0
+    # midpoints of the candidate edges on the surface, in one call (an edge
+    # is collapsed only while both its ends are untouched in this pass, so
+    # its midpoint stays the one computed here)
+    mids = S.project(0.5 * (V[E[cand, 0]] + V[E[cand, 1]]))
+    mid_of = {int(e): mids[i] for i, e in enumerate(cand)}
     vt = [[] for _ in range(len(V))]
     for t, (a, b, c) in enumerate(T):
         vt[a].append(t); vt[b].append(t); vt[c].append(t)
@@ -174,7 +203,7 @@ def _collapse(S, V, T, lmin):
         shared = [t for t in ta if b in T[t]]
         if len(shared) != 2 or len(na & nb) != 2:
             continue                                   # link condition
-        m = S.project(0.5 * (V[a] + V[b])[None])[0]
+        m = mid_of[int(e)]
         ok = True
         for t in set(ta) | set(tb):
             if t in shared:

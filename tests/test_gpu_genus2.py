@@ -1,9 +1,10 @@
 """The 2g count on a genus-2 surface (Section 5: the harmonic vector fields
 of a closed surface of genus g form a 2g-dimensional space).
 
-The surface is the smoothed union of two overlapping solid tori
-(lbinputs.genus2: marching tetrahedra, mesh improvement, charts projected
-onto the implicit surface), 6,720 order-6 patches, N = 188,160.  The Hodge
+The surface is the smoothed union of two overlapping solid tori with eight
+seeded normal bumps (lbinputs.genus2: marching tetrahedra, mesh improvement,
+charts projected onto the implicit surface), 6,686 order-6 patches,
+N = 187,208.  The Hodge
 split of 2g + 2 = 6 random tangential fields (tensor-Legendre components of
 degree ceil((2g)^(1/3)) + 3 = 5 on x / 2L, the paper's recipe) by lb_hodge
 (two batched FP32 + refinement Laplace-Beltrami solves per field): their

@@ -14,7 +14,7 @@ from oracle.refelem import nodes
 def test_genus2_generator():
     S = G2.FusedTori()
     res = []
-    for h in (0.22, 0.16):
+    for h in (0.26, 0.2):
         V, T = G2.mesh(S, h)
         assert G2.euler_characteristic(T) == -2
         amin, ratio = G2.quality(V, T)
