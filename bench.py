@@ -72,7 +72,12 @@ def workload(name, host_nodes=False):
         from lbinputs import genus2 as G2
         S2 = G2.FusedTori()
         V, T = G2.mesh(S2, size)
-        X, Xu, Xv = G2.patches(S2, V, T, uv)
+        print(f"[bench] genus-2 mesh: {len(T)} triangles", file=sys.stderr, flush=True)
+        parts = []
+        for c0 in range(0, len(T), 4096):  # charts in chunks, with progress lines
+            parts.append(G2.patches(S2, V, T[c0:c0 + 4096], uv))
+            print(f"[bench] genus-2 charts {min(c0 + 4096, len(T))} / {len(T)}", file=sys.stderr, flush=True)
+        X, Xu, Xv = (np.concatenate([q[c] for q in parts]) for c in range(3))
         f = I.legendre_field(X.reshape(-1, 3), seed=5, deg=5, L=2.6)[:, 0]
         dens = "first component of a tensor-Legendre field of degree 5 on x / 5.2 (seed 5)"
         surf = (f"genus-2 surface (smoothed union of two solid tori R = 1, r = 0.4, centres +-1.1), "
