@@ -78,7 +78,7 @@ template <typename T> constexpr int nemax() { return sizeof(T) == 4 ? GEMM_NE_MA
 template <typename T> constexpr int chunk_fwd() { return sizeof(T) == 4 ? 16 : 8; }  // S, grad S
 template <typename T> constexpr int chunk_a3() { return nemax<T>() / 3; }           // A3 (3 expansions)
 // largest column scratch of the M2L plan (split into parts beyond it)
-constexpr size_t M2L_Y_BUDGET = (size_t)4 << 30;
+constexpr size_t M2L_Y_BUDGET = (size_t)8 << 30;
 
 template <typename T, class A>
 static void upload(DBuf& d, const std::vector<T, A>& h);
@@ -147,6 +147,9 @@ static size_t build_plan(PlanBuf& pb, std::vector<Triple> tr, const std::vector<
   }
   pl.ne_max = ne_max;
   for (int ne = 1; ne <= ne_max; ++ne) {
+    // the expansion counts of the applies: up to chunk_fwd densities of one
+    // expansion, and three expansions per density (A3's second pass, A2)
+    if (ne > 16 && ne % 3 != 0) continue;
     std::vector<int> w;
     for (int g2 = 0; g2 < pl.ngrp; ++g2) {
       const int lo = glo.empty() ? L : glo[g2];

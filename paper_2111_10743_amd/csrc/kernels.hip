@@ -699,6 +699,7 @@ __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxe
 template <typename T>
 static void run_plan(const GemmPlan& pl, const T* TT, int L, int ne, const T* X, T* Y, T* out, hipStream_t st) {
   if (pl.nbox == 0) return;
+  if (pl.npair > 0 && !pl.work[ne]) fail(LB_EINVAL, "translation plan has no work list for %d expansions", ne);
   const int64_t ystride = (int64_t)pl.npair * ne * L;  // one k slice of Y
   if (pl.nwork[ne] > 0) {
     dim3 grid(pl.nwork[ne]);

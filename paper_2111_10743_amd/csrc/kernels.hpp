@@ -50,7 +50,7 @@ constexpr int GEMM_NXCD = 8;
 // Most expansions one FMM traversal may carry (FP32; the FP64 plans stop at
 // 8): sixteen densities of a gradient apply, eight of the second A3 pass
 // (three expansions each).
-constexpr int GEMM_NE_MAX = 24;
+constexpr int GEMM_NE_MAX = 48;
 
 struct GemmPlan {
   int ngrp = 0, npair = 0, nbox = 0;
@@ -63,8 +63,9 @@ struct GemmPlan {
   const int* boxes = nullptr;                         // [nbox] target boxes
   const double* box_scale = nullptr;                  // [nbox] factor of each target box (scaled plans)
   const int *tptr = nullptr, *tpairs = nullptr;       // [nbox+1], [npair]
-  // per expansion count ne (1..ne_max): work items (group, first column,
-  // first row, first k), ordered group -> row tile -> column tile -> k slice
+  // per expansion count ne (1..ne_max; built for the counts the applies use,
+  // null for the others): work items (group, first column, first row, first
+  // k), ordered group -> row tile -> column tile -> k slice
   const int* work[GEMM_NE_MAX + 1] = {nullptr};
   int nwork[GEMM_NE_MAX + 1] = {0};
   int ne_max = 0;
