@@ -772,13 +772,18 @@ __device__ void derive3(const T* src, int pin, T* dx, T* dy, T* dz) {
 #endif
 constexpr int LEAF_BS = LB_LEAF_BS;            // threads per block
 constexpr int LEAF_CH = LB_LEAF_CH;            // sources per LDS chunk
+// the far-field values of a pass (4 per target slot) pass through the
+// source chunk area, the smallest of which holds 5 values per source
+static_assert(5 * LEAF_CH >= 4 * LEAF_BS, "source chunk area too small for the far-field values");
 
 // Each target of a leaf gets F = min(leaf_fmax, 256 / targets) threads (a
-// power of two, at most one wave; leaf_fmax is set by the autotuner):
-// thread (slot, f) works for target slot `slot` of the current pass,
-// the far field over the harmonic orders m = f (mod F), the near field over
-// the source indices j = f (mod F) of each LDS chunk; the F partial sums of
-// a target (contiguous lanes) are then added by shuffles.
+// power of two, at most one wave; leaf_fmax is set by the autotuner) for
+// the near field: thread (slot, f) sums the source indices j = f (mod F) of
+// each LDS chunk for target slot `slot` of the current pass, and the F
+// partial sums of a target (contiguous lanes) are then added by shuffles.
+// The far field (L2P) takes one thread per target instead: split over F
+// lanes of one wave by harmonic order, its terms would run one after the
+// other with 1/F of the lanes active.
 // LDS bytes of the L2P expansions of one block, rounded up to 16: the local
 // expansions (nexp L), the gradient expansions the mode evaluates (3 p^2
 // per expansion: all three in A3B, the first in GRAD and ADJ3) and, in A3B
@@ -938,6 +943,129 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   }
   __syncthreads();
   const int utot = FARONLY ? 0 : upref[nU];
+  // ---- far field: the local expansions at xi = (x - c)/h, one thread per
+  // target, so that every lane of a wave runs the same (n, m) term: the
+  // recurrence coefficients and expansion reads are wave-uniform and no
+  // lane idles in a divergent branch ----
+  auto far_target = [&](int i, T& o0, T& o1, T& o2, T& o3) __attribute__((always_inline)) {
+    const T X = t.tx[i], Y = t.ty[i], Z = t.tz[i];
+    T NX = 0, NY = 0, NZ = 0;
+    if (MODE == FMM_A3B || MODE == FMM_ADJ3) { NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
+    const T x = (X - cx) * ih, y = (Y - cy) * ih, z = (Z - cz) * ih;
+    const T r2 = x * x + y * y + z * z;
+    T pot = 0, pot2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
+    T mre = 1, mim = 0;
+    for (int m = 0; m <= p; ++m) {
+      if (m > 0) {
+        const T fm = rt.sect[m];
+        T nr = fm * (x * mre - y * mim);
+        T ni = fm * (x * mim + y * mre);
+        mre = nr; mim = ni;
+      }
+      T are = 0, aim = 0, bre = mre, bim = mim;  // R_{n-1}, R_n with n = m
+      for (int n = m; n <= p; ++n) {
+        if (n > m) {
+          T cre, cim;
+          if (n == m + 1) {
+            T c1 = z * rt.up[m];
+            cre = c1 * bre; cim = c1 * bim;
+          } else {
+            const int cc = cidx(n - 1, m);
+            const T f1 = rt.a[cc] * z, f2 = rt.b[cc] * r2;
+            cre = f1 * bre - f2 * are;
+            cim = f1 * bim - f2 * aim;
+          }
+          are = bre; aim = bim; bre = cre; bim = cim;
+        }
+        T rre, rim;
+        int ire, iim;
+        if (m == 0) { rre = bre; rim = 0; ire = n * n; iim = -1; }
+        else { rre = 2 * bre; rim = -2 * bim; ire = n * n + 2 * m - 1; iim = n * n + 2 * m; }
+#define ACC(dst, base, idxre, idxim) dst += (base)[idxre] * rre + ((idxim) >= 0 ? (base)[idxim] * rim : (T)0)
+        if (MODE == FMM_POT || MODE == FMM_ADJ) {
+          ACC(pot, sL, ire, iim);
+        } else if (MODE == FMM_ADJ3) {
+          ACC(pot, sL, ire, iim);
+          ACC(pot2, sL + L, ire, iim);
+          if (n < p) {
+            ACC(g1[0], sG, ire, iim);
+            ACC(g1[1], sG + Lg, ire, iim);
+            ACC(g1[2], sG + 2 * Lg, ire, iim);
+          }
+        } else if (MODE == FMM_GRAD) {
+          ACC(pot, sL, ire, iim);
+          if (n < p) {
+            ACC(g1[0], sG, ire, iim);
+            ACC(g1[1], sG + Lg, ire, iim);
+            ACC(g1[2], sG + 2 * Lg, ire, iim);
+          }
+        } else {
+          if (PART != LEAF_FAR2) {
+            ACC(pot, xP, ire, iim);  // phi_2
+            if (n < p) {
+              ACC(g1[0], xG1, ire, iim);
+              ACC(g1[1], xG1 + Lg, ire, iim);
+              ACC(g1[2], xG1 + 2 * Lg, ire, iim);
+              ACC(g2[0], xG2, ire, iim);
+              ACC(g2[1], xG2 + Lg, ire, iim);
+              ACC(g2[2], xG2 + 2 * Lg, ire, iim);
+            }
+          }
+          if (PART != LEAF_FAR1) {
+            if (n < p) {
+              ACC(g3[0], xG3, ire, iim);
+              ACC(g3[1], xG3 + Lg, ire, iim);
+              ACC(g3[2], xG3 + 2 * Lg, ire, iim);
+            }
+            if (n < p - 1) {
+#pragma unroll
+              for (int q = 0; q < 6; ++q) ACC(hs[q], xH + q * Lh, ire, iim);
+            }
+          }
+        }
+#undef ACC
+      }
+    }
+    if (MODE == FMM_POT || MODE == FMM_ADJ) {
+      o0 = pot;
+    } else if (MODE == FMM_ADJ3) {
+      o0 = pot;
+      o1 = pot2 + (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
+    } else if (MODE == FMM_GRAD) {
+      o0 = pot; o1 = g1[0] * ih; o2 = g1[1] * ih; o3 = g1[2] * ih;
+    } else {
+      o0 = (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
+      o1 = pot;
+      o2 = (NX * g2[0] + NY * g2[1] + NZ * g2[2]) * ih;
+      T nhn = NX * NX * hs[0] + 2 * NX * NY * hs[1] + 2 * NX * NZ * hs[2] + NY * NY * hs[3] +
+              2 * NY * NZ * hs[4] + NZ * NZ * hs[5];
+      o3 = nhn * ih * ih + (NX * g3[0] + NY * g3[1] + NZ * g3[2]) * ih;
+    }
+  };
+  if (FARONLY) {
+    if (far) {
+      for (int i = tbeg + (int)threadIdx.x; i < tend; i += blockDim.x) {
+        T o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+        far_target(i, o0, o1, o2, o3);
+        const int64_t base = (int64_t)rhs * nout * N;
+        if (PART == LEAF_FAR1) {
+          out[base + i] += o0;
+          out[base + N + i] += o1;
+          out[base + 2 * N + i] += o2;
+        } else if (PART == LEAF_FAR2) {
+          out[base + 3 * N + i] += o3;
+        } else {  // after the near-field kernel (stream ordered)
+          out[base + i] += o0;
+          if (nout > 1) out[base + N + i] += o1;
+          if (nout > 2) {
+            out[base + 2 * N + i] += o2;
+            out[base + 3 * N + i] += o3;
+          }
+        }
+      }
+    }
+    return;
+  }
   for (int i0 = tbeg; i0 < tend; i0 += TPB) {
     const int i = i0 + slot;
     const bool act = i < tend;
@@ -945,101 +1073,24 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     if (act) { X = t.tx[i]; Y = t.ty[i]; Z = t.tz[i]; NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
     if (tmask && act) TR = t.trm2[i];
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    // ---- far field: local expansions at xi = (x - c)/h, orders m = f mod F ----
-    if (far && act) {
-      const T x = (X - cx) * ih, y = (Y - cy) * ih, z = (Z - cz) * ih;
-      const T r2 = x * x + y * y + z * z;
-      T pot = 0, pot2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
-      T mre = 1, mim = 0;
-      // orders m go to the F lanes back and forth (f, 2F-1-f, 2F+f, ...) so
-      // that the triangular n loops are balanced across the lanes
-      for (int m = 0, mq = 0, mr = 0; m <= p; ++m, mr = (mr + 1 == F ? 0 : mr + 1), mq += (mr == 0 && m > 0)) {
-        if (m > 0) {
-          const T fm = rt.sect[m];
-          T nr = fm * (x * mre - y * mim);
-          T ni = fm * (x * mim + y * mre);
-          mre = nr; mim = ni;
-        }
-        if ((mq & 1 ? F - 1 - mr : mr) != f) continue;
-        T are = 0, aim = 0, bre = mre, bim = mim;  // R_{n-1}, R_n with n = m
-        for (int n = m; n <= p; ++n) {
-          if (n > m) {
-            T cre, cim;
-            if (n == m + 1) {
-              T c1 = z * rt.up[m];
-              cre = c1 * bre; cim = c1 * bim;
-            } else {
-              const int cc = cidx(n - 1, m);
-              const T f1 = rt.a[cc] * z, f2 = rt.b[cc] * r2;
-              cre = f1 * bre - f2 * are;
-              cim = f1 * bim - f2 * aim;
-            }
-            are = bre; aim = bim; bre = cre; bim = cim;
-          }
-          T rre, rim;
-          int ire, iim;
-          if (m == 0) { rre = bre; rim = 0; ire = n * n; iim = -1; }
-          else { rre = 2 * bre; rim = -2 * bim; ire = n * n + 2 * m - 1; iim = n * n + 2 * m; }
-#define ACC(dst, base, idxre, idxim) dst += (base)[idxre] * rre + ((idxim) >= 0 ? (base)[idxim] * rim : (T)0)
-          if (MODE == FMM_POT || MODE == FMM_ADJ) {
-            ACC(pot, sL, ire, iim);
-          } else if (MODE == FMM_ADJ3) {
-            ACC(pot, sL, ire, iim);
-            ACC(pot2, sL + L, ire, iim);
-            if (n < p) {
-              ACC(g1[0], sG, ire, iim);
-              ACC(g1[1], sG + Lg, ire, iim);
-              ACC(g1[2], sG + 2 * Lg, ire, iim);
-            }
-          } else if (MODE == FMM_GRAD) {
-            ACC(pot, sL, ire, iim);
-            if (n < p) {
-              ACC(g1[0], sG, ire, iim);
-              ACC(g1[1], sG + Lg, ire, iim);
-              ACC(g1[2], sG + 2 * Lg, ire, iim);
-            }
-          } else {
-            if (PART != LEAF_FAR2) {
-              ACC(pot, xP, ire, iim);  // phi_2
-              if (n < p) {
-                ACC(g1[0], xG1, ire, iim);
-                ACC(g1[1], xG1 + Lg, ire, iim);
-                ACC(g1[2], xG1 + 2 * Lg, ire, iim);
-                ACC(g2[0], xG2, ire, iim);
-                ACC(g2[1], xG2 + Lg, ire, iim);
-                ACC(g2[2], xG2 + 2 * Lg, ire, iim);
-              }
-            }
-            if (PART != LEAF_FAR1) {
-              if (n < p) {
-                ACC(g3[0], xG3, ire, iim);
-                ACC(g3[1], xG3 + Lg, ire, iim);
-                ACC(g3[2], xG3 + 2 * Lg, ire, iim);
-              }
-              if (n < p - 1) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) ACC(hs[q], xH + q * Lh, ire, iim);
-              }
-            }
-          }
-#undef ACC
-        }
+    if (far) {
+      // the far field of the pass's targets, one per thread, through the
+      // source chunk area (free until the near field restages it) to the
+      // first lane of each target
+      T* fb = tile;
+      const int nf = min(TPB, tend - i0);
+      __syncthreads();  // the previous pass may still read its last chunk
+      if ((int)threadIdx.x < nf) {
+        T o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+        far_target(i0 + threadIdx.x, o0, o1, o2, o3);
+        fb[4 * threadIdx.x] = o0;
+        fb[4 * threadIdx.x + 1] = o1;
+        fb[4 * threadIdx.x + 2] = o2;
+        fb[4 * threadIdx.x + 3] = o3;
       }
-      if (MODE == FMM_POT || MODE == FMM_ADJ) {
-        a0 = pot;
-      } else if (MODE == FMM_ADJ3) {
-        a0 = pot;
-        a1 = pot2 + (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
-      } else if (MODE == FMM_GRAD) {
-        a0 = pot; a1 = g1[0] * ih; a2 = g1[1] * ih; a3 = g1[2] * ih;
-      } else {
-        a0 = (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
-        a1 = pot;
-        a2 = (NX * g2[0] + NY * g2[1] + NZ * g2[2]) * ih;
-        T nhn = NX * NX * hs[0] + 2 * NX * NY * hs[1] + 2 * NX * NZ * hs[2] + NY * NY * hs[3] +
-                2 * NY * NZ * hs[4] + NZ * NZ * hs[5];
-        a3 = nhn * ih * ih + (NX * g3[0] + NY * g3[1] + NZ * g3[2]) * ih;
-      }
+      __syncthreads();
+      if (act && f == 0) { a0 = fb[4 * slot]; a1 = fb[4 * slot + 1]; a2 = fb[4 * slot + 2]; a3 = fb[4 * slot + 3]; }
+      __syncthreads();  // before the near field restages the area
     }
     // ---- near field: U-list direct sums.  The U-list sources are gathered
     // into LDS in chunks of LEAF_CH (several neighbour boxes per chunk);
@@ -1159,26 +1210,11 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     }
     if (act && f == 0) {
       const int64_t base = (int64_t)rhs * nout * N;
-      if (PART == LEAF_FAR1) {
-        out[base + i] += (T)a0;
-        out[base + N + i] += (T)a1;
-        out[base + 2 * N + i] += (T)a2;
-      } else if (PART == LEAF_FAR2) {
-        out[base + 3 * N + i] += (T)a3;
-      } else if (PART == LEAF_FAR) {  // after the near-field kernel (stream ordered)
-        out[base + i] += (T)a0;
-        if (nout > 1) out[base + N + i] += (T)a1;
-        if (nout > 2) {
-          out[base + 2 * N + i] += (T)a2;
-          out[base + 3 * N + i] += (T)a3;
-        }
-      } else {
-        out[base + i] = (T)a0;
-        if (nout > 1) out[base + N + i] = (T)a1;
-        if (nout > 2) {
-          out[base + 2 * N + i] = (T)a2;
-          out[base + 3 * N + i] = (T)a3;
-        }
+      out[base + i] = (T)a0;
+      if (nout > 1) out[base + N + i] = (T)a1;
+      if (nout > 2) {
+        out[base + 2 * N + i] = (T)a2;
+        out[base + 3 * N + i] = (T)a3;
       }
     }
   }
