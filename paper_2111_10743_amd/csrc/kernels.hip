@@ -680,19 +680,57 @@ __global__ __launch_bounds__(256) void k_col_reduce(const int* __restrict__ boxe
                                                     const int* __restrict__ pair_lo, int nslice, int64_t ystride,
                                                     int ne, int L, int accumulate, const T* __restrict__ Y,
                                                     T* __restrict__ out) {
+  // the box's triples and their orders are staged in LDS, so that the
+  // column reads of several triples are in flight at once (a chain of
+  // dependent index loads per triple would leave the kernel latency bound);
+  // the sum keeps the triple order, so results do not depend on the staging
+  constexpr int QC = 256;
+  __shared__ int sp[QC];
+  __shared__ int slo[QC];
   const int g = boxes[blockIdx.x];
   const T f = box_scale ? (T)box_scale[blockIdx.x] : (T)1;
   const int pb = tptr[blockIdx.x], pe = tptr[blockIdx.x + 1];
-  for (int i = threadIdx.x; i < ne * L; i += blockDim.x) {
-    const int e = i / L, r = i - e * L;
+  for (int i0 = 0; i0 < ne * L; i0 += blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const bool act = i < ne * L;
+    const int e = act ? i / L : 0, r = act ? i - e * L : 0;
     T a = 0;
-    for (int q = pb; q < pe; ++q) {
-      const int pq = tpairs[q];
-      if (!pair_lo || r < pair_lo[pq])
-        for (int sl = 0; sl < nslice; ++sl) a += Y[sl * ystride + ((int64_t)pq * ne + e) * L + r];
+    for (int q0 = pb; q0 < pe; q0 += QC) {
+      const int nq = min(QC, pe - q0);
+      __syncthreads();
+      for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+        const int pq = tpairs[q0 + j];
+        sp[j] = pq;
+        slo[j] = pair_lo ? pair_lo[pq] : L;
+      }
+      __syncthreads();
+      if (!act) continue;
+      const T* Ye = Y + (int64_t)e * L + r;
+      const int64_t cs = (int64_t)ne * L;  // column stride of a triple
+      if (nslice == 1) {
+        int q = 0;
+        for (; q + 8 <= nq; q += 8) {
+          T v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const T y = Ye[sp[q + j] * cs];  // rows past a triple's order hold no value: read, then dropped
+            v[j] = r < slo[q + j] ? y : (T)0;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) a += v[j];
+        }
+        for (; q < nq; ++q)
+          if (r < slo[q]) a += Ye[sp[q] * cs];
+      } else {
+        for (int q = 0; q < nq; ++q)
+          if (r < slo[q])
+            for (int sl = 0; sl < nslice; ++sl) a += Ye[sl * ystride + sp[q] * cs];
+      }
     }
-    const int64_t o = ((int64_t)g * ne + e) * L + r;
-    out[o] = accumulate ? out[o] + a * f : a * f;
+    if (act) {
+      const int64_t o = ((int64_t)g * ne + e) * L + r;
+      out[o] = accumulate ? out[o] + a * f : a * f;
+    }
   }
 }
 
