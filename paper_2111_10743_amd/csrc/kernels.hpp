@@ -48,8 +48,8 @@ constexpr int GEMM_TILE_ROWS = 128, GEMM_TILE_COLS = 64;
 constexpr int GEMM_NXCD = 8;
 
 // Most expansions one FMM traversal may carry (FP32; the FP64 plans stop at
-// 8): sixteen densities of a gradient apply, eight of the second A3 pass
-// (three expansions each).
+// 8): sixteen densities of a gradient apply or of the second A3 pass (three
+// expansions each).
 constexpr int GEMM_NE_MAX = 48;
 
 struct GemmPlan {

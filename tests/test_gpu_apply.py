@@ -331,6 +331,34 @@ def test_overlap_matches_serial(torch_dev):
     b.close()
 
 
+def test_leaf_work_shapes(torch_dev):
+    """The leaf kernel's work items: leaves cut into 1..3 blocks
+    (leaf_split 1..3) at 16 and 64 most lanes per target, against one block
+    per leaf: the same near-field sums in another order, so the gradient
+    apply and A3 agree to rounding (the far field is evaluated one thread
+    per target in every shape)."""
+    torch = torch_dev
+    import paper_2111_10743_amd as P
+    from oracle.refelem import nodes
+    X, Xu, Xv = I.ellipsoid_patches(3, nodes(4), (1.0, 1.5, 2.0))
+    s = P.Surface(X, Xu, Xv, 4)
+    x = np.random.default_rng(89).standard_normal((2, s.N))
+    for prec, dt, tol in ((32, torch.float32, 3e-6), (64, torch.float64, 1e-13)):
+        xs = torch.tensor(x, dtype=dt, device="cuda")
+        for ls in (256, 1024):
+            s.set_tuning(prec, ls, 64, 0)
+            g0, a0 = s.apply_gradS(xs), s.apply_A3(xs)
+            for fm in (16, 64):
+                for sp in (1, 2, 3):
+                    s.set_tuning(prec, ls, fm, sp)
+                    g1, a1 = s.apply_gradS(xs), s.apply_A3(xs)
+                    errs = [rel_l2(g1[k].double().cpu().numpy(), g0[k].double().cpu().numpy()) for k in g0]
+                    errs.append(rel_l2(a1.double().cpu().numpy(), a0.double().cpu().numpy()))
+                    note(f"leaf shape prec={prec} leaf_src={ls} fmax={fm} split={sp}: max rel diff {max(errs):.2e}")
+                    assert max(errs) < tol
+    s.close()
+
+
 def test_overlap_schedules_bit_identical(torch_dev):
     """lb_set_tuning with every schedule of the overlapped apply (near-field
     kernel forked after the strengths or after P2M; one block per work item
