@@ -577,8 +577,12 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
   constexpr int KC = GmKc<T>::v;
   constexpr int NA = KC * GM_RB * 16 / 256;  // A values per thread per chunk
   constexpr int NB = KC * GM_COLS / 256;     // B values per thread per chunk
-  __shared__ T As[KC][GM_RB * 16];
-  __shared__ T Bs[GM_COLS][KC + 1];  // column-major, padded against bank conflicts
+  // FP64: two LDS buffers and one barrier per k chunk (measured: FP64 M2L
+  // 2.85 -> 2.51 ms at 143k nodes); FP32 keeps one buffer (its three
+  // blocks per CU: the second buffer costs it 0.200 -> 0.205 ms)
+  constexpr int NBUF = sizeof(T) == 8 ? 2 : 1;
+  __shared__ T As[NBUF][KC][GM_RB * 16];
+  __shared__ T Bs[NBUF][GM_COLS][KC + 1];  // column-major, padded against bank conflicts
   __shared__ int srcrow[GM_COLS];
   // XCD-aware order: block b runs on XCD b % 8; each XCD takes a contiguous
   // range of the work list, so the column tiles that share a slab of a
@@ -635,29 +639,52 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const T* __restrict__ TT, 
   typename Mfma<T>::acc acc[GM_RB];
 #pragma unroll
   for (int rb = 0; rb < GM_RB; ++rb) acc[rb] = (typename Mfma<T>::acc){0, 0, 0, 0};
-  load(kb);
-  for (int k0 = kb; k0 < ke; k0 += KC) {
-    __syncthreads();
+  auto store = [&](int bf) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int i = threadIdx.x + 256 * u;
-      As[i / (GM_RB * 16)][i % (GM_RB * 16)] = ra[u];
+      As[bf][i / (GM_RB * 16)][i % (GM_RB * 16)] = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int i = threadIdx.x + 256 * u;
-      Bs[i / KC][i % KC] = rb_[u];
+      Bs[bf][i / KC][i % KC] = rb_[u];
     }
-    __syncthreads();
-    if (k0 + KC < ke) load(k0 + KC);
+  };
+  auto compute = [&](int bf) {
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      const T b = Bs[wv * 16 + (lane & 15)][kk + (lane >> 4)];
+      const T b = Bs[bf][wv * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
       for (int rb = 0; rb < GM_RB; ++rb) {
-        const T a = As[kk + (lane >> 4)][rb * 16 + (lane & 15)];
+        const T a = As[bf][kk + (lane >> 4)][rb * 16 + (lane & 15)];
         acc[rb] = Mfma<T>::op(a, b, acc[rb]);
       }
+    }
+  };
+  load(kb);
+  if constexpr (NBUF == 2) {
+    // chunk i+1 goes into registers while the matrix cores work on chunk i
+    // from one buffer, then into the other buffer (read last in chunk i-1,
+    // which every wave finished before the previous barrier)
+    store(0);
+    __syncthreads();
+    int bf = 0;
+    for (int k0 = kb; k0 < ke; k0 += KC) {
+      const bool more = k0 + KC < ke;
+      if (more) load(k0 + KC);
+      compute(bf);
+      if (more) store(bf ^ 1);
+      __syncthreads();
+      bf ^= 1;
+    }
+  } else {
+    for (int k0 = kb; k0 < ke; k0 += KC) {
+      __syncthreads();
+      store(0);
+      __syncthreads();
+      if (k0 + KC < ke) load(k0 + KC);
+      compute(0);
     }
   }
   const int c = c0 + wv * 16 + (lane & 15);
