@@ -851,16 +851,28 @@ static_assert(5 * LEAF_CH >= 4 * LEAF_BS, "source chunk area too small for the f
 // other with 1/F of the lanes active.
 // LDS bytes of the L2P expansions of one block, rounded up to 16: the local
 // expansions (nexp L), the gradient expansions the mode evaluates (3 p^2
-// per expansion: all three in A3B, the first in GRAD and ADJ3) and, in A3B
-// only, the Hessian expansions (6 (p-1)^2 and 3 (p-1)^2 scratch).
+// per expansion: all three in A3B, the first in GRAD and ADJ3), in A3B
+// the Hessian expansions (6 (p-1)^2 and 3 (p-1)^2 scratch), and in GRAD the
+// four expansions interleaved per coefficient (4 L, aligned to 16 bytes).
 template <typename T>
 __host__ __device__ inline size_t leaf_exp_bytes(int mode, int p) {
   const size_t L = (size_t)(p + 1) * (p + 1), Lg = (size_t)p * p, Lh = (size_t)(p - 1) * (p - 1);
   const size_t nexp = fmm_nexp(mode);
   size_t n = nexp * L;
   if (mode == FMM_GRAD || mode == FMM_ADJ3) n += 3 * Lg;
+  if (mode == FMM_GRAD) n += 4 * L + 8;
   if (mode == FMM_A3B) n += nexp * 3 * Lg + 9 * Lh;
   return (sizeof(T) * n + 15) / 16 * 16;
+}
+
+// Values of one (work item, density) slice of the leaf workspace D when the
+// expansions do not fit in LDS: the gradient expansions (nexp 3 p^2), the
+// Hessian and its scratch (9 (p-1)^2), and in GRAD the interleaved
+// coefficients (4 L, at a multiple of 4 values so that they stay aligned).
+__host__ __device__ inline int64_t leaf_d_vals(int mode, int p) {
+  const int64_t L = (int64_t)(p + 1) * (p + 1), Lg = (int64_t)p * p, Lh = (int64_t)(p - 1) * (p - 1);
+  const int64_t base = (int64_t)fmm_nexp(mode) * 3 * Lg + 9 * Lh;
+  return mode == FMM_GRAD ? (base + 3) / 4 * 4 + 4 * L : base;
 }
 
 // PART: LEAF_BOTH (far and near, outputs written), LEAF_NEAR (near-field
@@ -908,7 +920,7 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   constexpr int REC = MODE == FMM_A3B || MODE == FMM_ADJ || MODE == FMM_ADJ3 ? 9 : 5;  // T values per source record
   T* tile = reinterpret_cast<T*>(smraw);  // (x, y, z, q1) [, (nx, ny, nz, q2)], rm2
   const T* gL = Lc + ((int64_t)g * nrhs * nexp + rhs * nexp) * L;
-  const int64_t dstride = (int64_t)nexp * 3 * Lg + 9 * Lh;
+  const int64_t dstride = leaf_d_vals(MODE, p);
   T* sL;
   T* sG;
   if (EXP_LDS) {
@@ -919,6 +931,13 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     sG = D + ((int64_t)widx * nrhs + rhs) * dstride;
   }
   T* sH = sG + nexp * 3 * Lg;
+  typedef typename Vec4<T>::type T4;
+  // GRAD: the interleaved coefficients after the gradient expansions, in
+  // LDS at the next multiple of sizeof(T4), else at the end of the D slice
+  // (slices start at multiples of 4 values)
+  T4* sZ = EXP_LDS ? reinterpret_cast<T4*>(smraw) +
+                         ((size_t)(sG + 3 * Lg - tile) * sizeof(T) + sizeof(T4) - 1) / sizeof(T4)
+                   : reinterpret_cast<T4*>(sG + (nexp * 3 * Lg + 9 * Lh + 3) / 4 * 4);
   // A3B: the expansion values the L2P sums read (expansion 1, gradients of
   // 0, 1, 2, Hessian of 1); the split passes keep theirs in LDS
   const T* xP = sL + L;
@@ -968,6 +987,24 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
       for (int e = 0; e < nexp; ++e)
         derive3(sL + e * L, p, sG + (e * 3 + 0) * Lg, sG + (e * 3 + 1) * Lg, sG + (e * 3 + 2) * Lg);
     }
+    if (MODE == FMM_GRAD) {
+      // (phi, d/dx, d/dy, d/dz) of each real coefficient side by side, the
+      // factors of the real-part evaluation folded in (2 Re and -2 Im for
+      // m > 0), the gradients zero for n = p: one 4-vector read per part
+      __syncthreads();
+      for (int c = threadIdx.x; c < L; c += blockDim.x) {
+        int n = 0;
+        while ((n + 1) * (n + 1) <= c) ++n;
+        const int r = c - n * n;  // 0: m = 0; odd: Re of m = (r+1)/2; even > 0: Im
+        const T f = r == 0 ? (T)1 : ((r & 1) ? (T)2 : (T)-2);
+        T4 z;
+        z.x = f * sL[c];
+        z.y = n < p ? f * sG[c] : (T)0;
+        z.z = n < p ? f * sG[Lg + c] : (T)0;
+        z.w = n < p ? f * sG[2 * Lg + c] : (T)0;
+        sZ[c] = z;
+      }
+    }
     if (MODE == FMM_ADJ3) derive3(sL, p, sG, sG + Lg, sG + 2 * Lg);  // gradient of expansion 1
     if (MODE == FMM_A3B) {
       // second derivatives of expansion 1 from its gradient expansions; the
@@ -987,7 +1024,6 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   const T ih = (T)1 / h;
   const T cx = t.bcx[g], cy = t.bcy[g], cz = t.bcz[g];
   // source records in LDS: (x, y, z, q1), (nx, ny, nz, q2) and rm2
-  typedef typename Vec4<T>::type T4;
   T4* rec1 = reinterpret_cast<T4*>(tile);
   T4* rec2 = rec1 + LEAF_CH;                                                   // A3B only
   // the mask radius is the target's in the transposed-tree modes (FMM_ADJ
@@ -1018,6 +1054,52 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     if (MODE == FMM_A3B || MODE == FMM_ADJ3) { NX = t.tnx[i]; NY = t.tny[i]; NZ = t.tnz[i]; }
     const T x = (X - cx) * ih, y = (Y - cy) * ih, z = (Z - cz) * ih;
     const T r2 = x * x + y * y + z * z;
+    if constexpr (MODE == FMM_GRAD) {
+      // the interleaved, prefactored coefficients: column m = 0 (real
+      // harmonics), then m >= 1 (real and imaginary parts)
+      T pot = 0, gx = 0, gy = 0, gz = 0;
+      T mre = 1, mim = 0;
+      {
+        T are = 0, bre = 1;
+        for (int n = 0; n <= p; ++n) {
+          if (n == 1) {
+            are = bre; bre = z * rt.up[0] * bre;
+          } else if (n > 1) {
+            const int cc = cidx(n - 1, 0);
+            const T c = rt.a[cc] * z * bre - rt.b[cc] * r2 * are;
+            are = bre; bre = c;
+          }
+          const T4 v = sZ[n * n];
+          pot += v.x * bre; gx += v.y * bre; gy += v.z * bre; gz += v.w * bre;
+        }
+      }
+      for (int m = 1; m <= p; ++m) {
+        const T fm = rt.sect[m];
+        const T nr = fm * (x * mre - y * mim);
+        const T ni = fm * (x * mim + y * mre);
+        mre = nr; mim = ni;
+        T are = 0, aim = 0, bre = mre, bim = mim;  // R_{n-1}, R_n with n = m
+        for (int n = m; n <= p; ++n) {
+          if (n == m + 1) {
+            const T c1 = z * rt.up[m];
+            are = bre; aim = bim; bre = c1 * bre; bim = c1 * bim;
+          } else if (n > m + 1) {
+            const int cc = cidx(n - 1, m);
+            const T f1 = rt.a[cc] * z, f2 = rt.b[cc] * r2;
+            const T cre = f1 * bre - f2 * are;
+            const T cim = f1 * bim - f2 * aim;
+            are = bre; aim = bim; bre = cre; bim = cim;
+          }
+          const T4 vr = sZ[n * n + 2 * m - 1], vi = sZ[n * n + 2 * m];
+          pot += vr.x * bre + vi.x * bim;
+          gx += vr.y * bre + vi.y * bim;
+          gy += vr.z * bre + vi.z * bim;
+          gz += vr.w * bre + vi.w * bim;
+        }
+      }
+      o0 = pot; o1 = gx * ih; o2 = gy * ih; o3 = gz * ih;
+      return;
+    }
     T pot = 0, pot2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
     T mre = 1, mim = 0;
     for (int m = 0; m <= p; ++m) {
@@ -1314,7 +1396,7 @@ int64_t leaf_d_stride(int mode, int p) {
   if (mode == FMM_A3B && leaf_far_split_bytes<T>(LEAF_FAR1, p) + stat <= 64 * 1024 &&
       leaf_far_split_bytes<T>(LEAF_FAR2, p) + stat <= 64 * 1024)
     return 0;
-  return (int64_t)fmm_nexp(mode) * 3 * p * p + 9 * (int64_t)(p - 1) * (p - 1);
+  return leaf_d_vals(mode, p);
 }
 
 template <typename T>

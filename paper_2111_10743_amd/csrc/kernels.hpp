@@ -277,7 +277,7 @@ struct PhaseTimer {
   void mark(int i, hipStream_t st) { if (on) (void)hipEventRecord(ev[i], st); }
 };
 
-// nrhs * fmm_nexp(mode) <= the plans' ne_max.  D: scratch [n_leaf_work][nrhs][nexp*3*p^2 + 9*(p-1)^2]
+// nrhs * fmm_nexp(mode) <= the plans' ne_max.  D: scratch [n_leaf_work][nrhs][leaf_d_stride(mode, p)]
 template <typename T>
 void launch_fmm(const DevTree<T>& t, int mode, int nrhs, const T* str, T* M, T* Lc, T* D, T* out,
                 int64_t N, int64_t No, hipStream_t st, PhaseTimer* tm = nullptr);
