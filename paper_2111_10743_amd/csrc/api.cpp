@@ -835,6 +835,7 @@ static void build_prec(lb_ctx* ctx, Prec<T>& P, int p, const std::vector<double>
 }
 
 constexpr int CHUNK_GRAD = 8;
+constexpr int CHUNK_A3T = 4;  // densities per transposed A3 traversal (two expansions each)
 
 // Per-call workspace of the gradient apply for `chunk` densities per
 // traversal: strengths, multipole and local expansions, derived leaf
@@ -1105,7 +1106,11 @@ static void ensure_adjoint(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built) {
   A.str.alloc(sizeof(T) * (size_t)ctx->N * 4 * c);
   A.M.alloc(sizeof(T) * (size_t)nb * c * L);
   A.Lc.alloc(sizeof(T) * (size_t)nb * c * L);
-  A.D.alloc(sizeof(T) * (size_t)std::max(A.dt.n_leaf_work, 1) * c * (3 * p * p + 9 * (p - 1) * (p - 1)));
+  // leaf workspace of the transposed traversals: FMM_ADJ with up to
+  // CHUNK_GRAD densities, FMM_ADJ3 with up to CHUNK_A3T
+  const int64_t dpd = std::max({(int64_t)c * leaf_d_stride<T>(FMM_ADJ, p),
+                                (int64_t)CHUNK_A3T * leaf_d_stride<T>(FMM_ADJ3, p), (int64_t)1});
+  A.D.alloc(sizeof(T) * (size_t)std::max(A.dt.n_leaf_work, 1) * (size_t)dpd);
   A.fmm.alloc(sizeof(T) * (size_t)F.No * c);
   HIPTRY(hipDeviceSynchronize());
   built = true;
@@ -1353,7 +1358,6 @@ static void set_tuning_t(lb_ctx* ctx, Prec<T>& P, bool& adj_built, bool& z_built
 // in two transposed FMMs: step 1 (FMM_ADJ3) a = S'^T v and
 // b = (S''+D')^T v + S'^T (2 H v); step 2 (FMM_ADJ) S'^T a - S^T b.
 // ---------------------------------------------------------------------------
-constexpr int CHUNK_A3T = 4;
 
 template <typename T>
 static void apply_A3T_t(lb_ctx* ctx, Prec<T>& F, Prec<T>& A, bool& built, DBuf& zb, bool& zbuilt, int nd,

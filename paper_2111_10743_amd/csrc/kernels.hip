@@ -2805,17 +2805,35 @@ void launch_gm_finish(const GmresDev& gm, const double* V, double* X, hipStream_
 // ---- per-surface reductions: surface q owns rows [off[q], off[q+1]) ----
 // out[d][q] = scale[q] * sum_{i in q} x[d][i] (w ? w[i] : 1), one block per
 // (surface, density), fixed summation order
+constexpr int SEG_BS = 1024;  // threads per (surface, density) block of the segment sums
 template <typename T>
-__global__ void k_seg_dot(int nsurf, int64_t N, const int64_t* __restrict__ off, const T* __restrict__ x,
-                          const double* __restrict__ w, const double* __restrict__ scale, double* __restrict__ out) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(SEG_BS) void k_seg_dot(int nsurf, int64_t N, const int64_t* __restrict__ off,
+                                                    const T* __restrict__ x, const double* __restrict__ w,
+                                                    const double* __restrict__ scale, double* __restrict__ out) {
+  // one wide block per (surface, density): eight independent partial sums
+  // per thread keep eight loads of x (and w) in flight, so that a surface
+  // of ~1e5 nodes is not a chain of dependent load latencies; the order of
+  // the sums is fixed, so results are reproducible
+  __shared__ double red[SEG_BS];
   const int q = blockIdx.x, d = blockIdx.y;
   const T* xd = x + (int64_t)d * N;
-  double acc = 0;
-  for (int64_t i = off[q] + threadIdx.x; i < off[q + 1]; i += 256) acc += (double)xd[i] * (w ? w[i] : 1.0);
-  red[threadIdx.x] = acc;
+  const int64_t b = off[q], e = off[q + 1];
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t i = b + threadIdx.x;
+  if (w) {
+    for (; i + 7 * SEG_BS < e; i += 8 * SEG_BS)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += (double)xd[i + u * SEG_BS] * w[i + u * SEG_BS];
+    for (; i < e; i += SEG_BS) a[0] += (double)xd[i] * w[i];
+  } else {
+    for (; i + 7 * SEG_BS < e; i += 8 * SEG_BS)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += (double)xd[i + u * SEG_BS];
+    for (; i < e; i += SEG_BS) a[0] += (double)xd[i];
+  }
+  red[threadIdx.x] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = SEG_BS / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
@@ -2836,7 +2854,7 @@ __global__ void k_seg_axpy(int nd, int nsurf, int64_t N, const int* __restrict__
 template <typename T>
 void launch_seg_dot(int nd, int nsurf, int64_t N, const int64_t* off, const T* x, const double* w,
                     const double* scale, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_seg_dot<T>, dim3(nsurf, nd), dim3(256), 0, st, nsurf, N, off, x, w, scale, out);
+  hipLaunchKernelGGL(k_seg_dot<T>, dim3(nsurf, nd), dim3(SEG_BS), 0, st, nsurf, N, off, x, w, scale, out);
   KCHECK();
 }
 template <typename T>
