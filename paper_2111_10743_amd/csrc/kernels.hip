@@ -865,6 +865,13 @@ __host__ __device__ inline size_t leaf_exp_bytes(int mode, int p) {
   return (sizeof(T) * n + 15) / 16 * 16;
 }
 
+// LDS bytes of the interleaved coefficients of the A3B far-only part (16
+// values per real coefficient, aligned to 16 bytes), beyond leaf_exp_bytes.
+template <typename T>
+__host__ __device__ inline size_t leaf_z16_bytes(int p) {
+  return sizeof(T) * ((size_t)16 * (p + 1) * (p + 1) + 8);
+}
+
 // Values of one (work item, density) slice of the leaf workspace D when the
 // expansions do not fit in LDS: the gradient expansions (nexp 3 p^2), the
 // Hessian and its scratch (9 (p-1)^2), and in GRAD the interleaved
@@ -938,6 +945,11 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
   T4* sZ = EXP_LDS ? reinterpret_cast<T4*>(smraw) +
                          ((size_t)(sG + 3 * Lg - tile) * sizeof(T) + sizeof(T4) - 1) / sizeof(T4)
                    : reinterpret_cast<T4*>(sG + (nexp * 3 * Lg + 9 * Lh + 3) / 4 * 4);
+  // A3B far-only part with the expansions in LDS: the 16 values of each
+  // coefficient (expansion 1, the gradients of expansions 0, 1, 2 and the
+  // Hessian of expansion 1) side by side after the Hessian scratch
+  constexpr bool Z16 = MODE == FMM_A3B && PART == LEAF_FAR && EXP_LDS;
+  T4* sZ16 = reinterpret_cast<T4*>(smraw) + ((size_t)(sH + 9 * Lh - tile) * sizeof(T) + sizeof(T4) - 1) / sizeof(T4);
   // A3B: the expansion values the L2P sums read (expansion 1, gradients of
   // 0, 1, 2, Hessian of 1); the split passes keep theirs in LDS
   const T* xP = sL + L;
@@ -1017,6 +1029,23 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
       derive3(gx, p - 1, sH, sH + Lh, sH + 2 * Lh);          // xx, xy, xz
       derive3(gy, p - 1, tmp, sH + 3 * Lh, sH + 4 * Lh);     // (yx), yy, yz
       derive3(gz, p - 1, tmp + Lh, tmp + 2 * Lh, sH + 5 * Lh);  // (zx), (zy), zz
+    }
+    if (Z16) {
+      __syncthreads();
+      for (int c = threadIdx.x; c < L; c += blockDim.x) {
+        int n = 0;
+        while ((n + 1) * (n + 1) <= c) ++n;
+        const int r = c - n * n;
+        const T f = r == 0 ? (T)1 : ((r & 1) ? (T)2 : (T)-2);
+        const T fg = n < p ? f : (T)0, fh = n < p - 1 ? f : (T)0;
+        const int cg = n < p ? c : 0, ch = n < p - 1 ? c : 0;  // clamped: the factor is zero there
+        T4 z0, z1, z2, z3;
+        z0.x = f * xP[c];         z0.y = fg * xG1[cg];          z0.z = fg * xG1[Lg + cg];     z0.w = fg * xG1[2 * Lg + cg];
+        z1.x = fg * xG2[cg];      z1.y = fg * xG2[Lg + cg];     z1.z = fg * xG2[2 * Lg + cg]; z1.w = fg * xG3[cg];
+        z2.x = fg * xG3[Lg + cg]; z2.y = fg * xG3[2 * Lg + cg]; z2.z = fh * xH[ch];           z2.w = fh * xH[Lh + ch];
+        z3.x = fh * xH[2 * Lh + ch]; z3.y = fh * xH[3 * Lh + ch]; z3.z = fh * xH[4 * Lh + ch]; z3.w = fh * xH[5 * Lh + ch];
+        sZ16[4 * c] = z0; sZ16[4 * c + 1] = z1; sZ16[4 * c + 2] = z2; sZ16[4 * c + 3] = z3;
+      }
     }
     __syncthreads();
   }
@@ -1098,6 +1127,68 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
         }
       }
       o0 = pot; o1 = gx * ih; o2 = gy * ih; o3 = gz * ih;
+      return;
+    }
+    if constexpr (Z16) {
+      // the 16 interleaved, prefactored values per coefficient: column m = 0,
+      // then m >= 1
+      T acc[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[k] = 0;
+      auto add = [&](const T4* zc, T br, T bi, const T4* zs) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T4 u = zc[q];
+          if (zs) {
+            const T4 v = zs[q];
+            acc[4 * q] += u.x * br + v.x * bi; acc[4 * q + 1] += u.y * br + v.y * bi;
+            acc[4 * q + 2] += u.z * br + v.z * bi; acc[4 * q + 3] += u.w * br + v.w * bi;
+          } else {
+            acc[4 * q] += u.x * br; acc[4 * q + 1] += u.y * br; acc[4 * q + 2] += u.z * br; acc[4 * q + 3] += u.w * br;
+          }
+        }
+      };
+      T mre = 1, mim = 0;
+      {
+        T are = 0, bre = 1;
+        for (int n = 0; n <= p; ++n) {
+          if (n == 1) {
+            are = bre; bre = z * rt.up[0] * bre;
+          } else if (n > 1) {
+            const int cc = cidx(n - 1, 0);
+            const T c = rt.a[cc] * z * bre - rt.b[cc] * r2 * are;
+            are = bre; bre = c;
+          }
+          add(sZ16 + 4 * (n * n), bre, (T)0, nullptr);
+        }
+      }
+      for (int m = 1; m <= p; ++m) {
+        const T fm = rt.sect[m];
+        const T nr = fm * (x * mre - y * mim);
+        const T ni = fm * (x * mim + y * mre);
+        mre = nr; mim = ni;
+        T are = 0, aim = 0, bre = mre, bim = mim;
+        for (int n = m; n <= p; ++n) {
+          if (n == m + 1) {
+            const T c1 = z * rt.up[m];
+            are = bre; aim = bim; bre = c1 * bre; bim = c1 * bim;
+          } else if (n > m + 1) {
+            const int cc = cidx(n - 1, m);
+            const T f1 = rt.a[cc] * z, f2 = rt.b[cc] * r2;
+            const T cre = f1 * bre - f2 * are;
+            const T cim = f1 * bim - f2 * aim;
+            are = bre; aim = bim; bre = cre; bim = cim;
+          }
+          add(sZ16 + 4 * (n * n + 2 * m - 1), bre, bim, sZ16 + 4 * (n * n + 2 * m));
+        }
+      }
+      // acc: pot, g1 (3), g2 (3), g3 (3), Hessian xx xy xz yy yz zz
+      o0 = (NX * acc[1] + NY * acc[2] + NZ * acc[3]) * ih;
+      o1 = acc[0];
+      o2 = (NX * acc[4] + NY * acc[5] + NZ * acc[6]) * ih;
+      const T nhn = NX * NX * acc[10] + 2 * NX * NY * acc[11] + 2 * NX * NZ * acc[12] + NY * NY * acc[13] +
+                    2 * NY * NZ * acc[14] + NZ * NZ * acc[15];
+      o3 = nhn * ih * ih + (NX * acc[7] + NY * acc[8] + NZ * acc[9]) * ih;
       return;
     }
     T pot = 0, pot2 = 0, g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0}, g3[3] = {0, 0, 0}, hs[6] = {0, 0, 0, 0, 0, 0};
@@ -1410,7 +1501,8 @@ static void launch_leaf(const DevTree<T>& t, int mode, int part, int nrhs, const
   // e.g. 1.42 ms -> 1.74 ms for the FP64 gradient kernel at 45 KiB)
   const size_t chunk = part == LEAF_FAR ? 0
                        : sizeof(T) * (mode == FMM_A3B || mode == FMM_ADJ || mode == FMM_ADJ3 ? 9 : 5) * LEAF_CH;
-  const size_t exps = part == LEAF_NEAR ? 0 : leaf_exp_bytes<T>(mode, p);
+  const size_t exps = part == LEAF_NEAR ? 0
+                      : leaf_exp_bytes<T>(mode, p) + (part == LEAF_FAR && mode == FMM_A3B ? leaf_z16_bytes<T>(p) : 0);
   const bool lds = chunk + exps <= 40 * 1024;
   const size_t sml = lds ? chunk + exps : chunk;
   (void)L; (void)nexp;
