@@ -1230,14 +1230,7 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
             ACC(g1[1], sG + Lg, ire, iim);
             ACC(g1[2], sG + 2 * Lg, ire, iim);
           }
-        } else if (MODE == FMM_GRAD) {
-          ACC(pot, sL, ire, iim);
-          if (n < p) {
-            ACC(g1[0], sG, ire, iim);
-            ACC(g1[1], sG + Lg, ire, iim);
-            ACC(g1[2], sG + 2 * Lg, ire, iim);
-          }
-        } else {
+        } else {  // A3B (GRAD returned above)
           if (PART != LEAF_FAR2) {
             ACC(pot, xP, ire, iim);  // phi_2
             if (n < p) {
@@ -1269,8 +1262,6 @@ __device__ __forceinline__ void leaf_item(const DevTree<T>& t, int nrhs, const T
     } else if (MODE == FMM_ADJ3) {
       o0 = pot;
       o1 = pot2 + (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
-    } else if (MODE == FMM_GRAD) {
-      o0 = pot; o1 = g1[0] * ih; o2 = g1[1] * ih; o3 = g1[2] * ih;
     } else {
       o0 = (NX * g1[0] + NY * g1[1] + NZ * g1[2]) * ih;
       o1 = pot;
